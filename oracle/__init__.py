@@ -1,0 +1,211 @@
+"""ctypes binding of the CPU FP64 oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  It shares no code with the HIP
+library (``paper_2308_09400_amd``) and the product path never calls it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+INACTIVE, PT, PE, PP, EE, DEGENERATE = 0, 1, 2, 3, 4, 7
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("dhat", ctypes.c_double),
+        ("kappa", ctypes.c_double),
+        ("dthr_ratio", ctypes.c_double),
+        ("epsx_ratio", ctypes.c_double),
+        ("filter", ctypes.c_int),
+        ("mollify", ctypes.c_int),
+        ("eq12", ctypes.c_int),
+    ]
+
+
+def params(dhat=1e-3, kappa=1e4, dthr_ratio=0.1, epsx_ratio=1e-3, filter=True, mollify=True, eq12=False):
+    return Params(dhat, kappa, dthr_ratio, epsx_ratio, int(filter), int(mollify), int(eq12))
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C, OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fno-fast-math", "-shared", "-fPIC", "-o", tmp,
+                               os.path.join(_HERE, "gipc_oracle.c"), "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, d, i32, i64 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int64
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.orc_barrier.argtypes = [d, d, ctypes.c_int, dp, dp, dp]
+        L.orc_barrier.restype = None
+        L.orc_mollifier.argtypes = [d, d, dp, dp, dp]
+        L.orc_mollifier.restype = None
+        L.orc_jacobi_eig.argtypes = [ctypes.c_int, vp, vp, vp]
+        L.orc_jacobi_eig.restype = ctypes.c_int
+        L.orc_pair_local.argtypes = [vp, vp, vp, ctypes.POINTER(Params), dp, vp, vp,
+                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), dp,
+                                     vp, vp, vp, ctypes.POINTER(ctypes.c_int)]
+        L.orc_pair_local.restype = ctypes.c_int
+        L.orc_stencil.argtypes = [vp, vp]
+        L.orc_stencil.restype = ctypes.c_int
+        L.orc_eval.argtypes = [i32, vp, vp, i64, vp, ctypes.POINTER(Params), ctypes.c_int, dp, vp, vp, vp, vp, vp, vp]
+        L.orc_eval.restype = i64
+        L.orc_assemble.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp, i64]
+        L.orc_assemble.restype = i64
+        L.orc_spmv.argtypes = [i32, i64, vp, vp, vp, vp, vp]
+        L.orc_spmv.restype = None
+        L.orc_pcg.argtypes = [i32, i64, vp, vp, vp, vp, vp, d, ctypes.c_int, dp]
+        L.orc_pcg.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def barrier(g, dhat=1e-3, eq12=False):
+    """(b, db/dg, d2b/dg2) of Eq. 24 (or Eq. 12)."""
+    b, db, d2b = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    lib().orc_barrier(float(g), float(dhat), int(eq12), ctypes.byref(b), ctypes.byref(db), ctypes.byref(d2b))
+    return b.value, db.value, d2b.value
+
+
+def mollifier(c, epsx):
+    e, de, d2e = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    lib().orc_mollifier(float(c), float(epsx), ctypes.byref(e), ctypes.byref(de), ctypes.byref(d2e))
+    return e.value, de.value, d2e.value
+
+
+def jacobi_eig(A):
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    lam = np.zeros(n)
+    vec = np.zeros((n, n))
+    lib().orc_jacobi_eig(n, A.ctypes.data, lam.ctypes.data, vec.ctypes.data)
+    return lam, vec
+
+
+def stencil(tuple4):
+    t = np.ascontiguousarray(tuple4, dtype=np.int32)
+    vid = np.zeros(4, dtype=np.int32)
+    nv = lib().orc_stencil(t.ctypes.data, vid.ctypes.data)
+    return nv, vid
+
+
+def pair_local(tuple4, xs, xr=None, prm=None, debug=False):
+    """One pair.  ``xs``/``xr``: stencil positions ``[4][3]`` (unused rows ignored).
+
+    Returns a dict with E, grad (12,), hess (12, 12), subtype, mollified, d2
+    and, with ``debug``, the inner Hessian before/after projection, vec(db/dJ)
+    and the Jacobian dimension m.
+    """
+    prm = prm or params()
+    t = np.ascontiguousarray(tuple4, dtype=np.int32)
+    xs = np.zeros((4, 3)) + 0.0 if xs is None else np.ascontiguousarray(np.asarray(xs, np.float64).reshape(-1, 3))
+    if xs.shape[0] < 4:
+        xs = np.vstack([xs, np.zeros((4 - xs.shape[0], 3))])
+    xr_a = None
+    if xr is not None:
+        xr_a = np.ascontiguousarray(np.asarray(xr, np.float64).reshape(-1, 3))
+        if xr_a.shape[0] < 4:
+            xr_a = np.vstack([xr_a, np.zeros((4 - xr_a.shape[0], 3))])
+    E = ctypes.c_double()
+    g = np.zeros(12)
+    H = np.zeros(144)
+    st, mo, m = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    d2 = ctypes.c_double()
+    iH = np.zeros(81) if debug else None
+    iHp = np.zeros(81) if debug else None
+    bJ = np.zeros(9) if debug else None
+    rc = lib().orc_pair_local(t.ctypes.data, xs.ctypes.data, _ptr(xr_a), ctypes.byref(prm), ctypes.byref(E),
+                              g.ctypes.data, H.ctypes.data, ctypes.byref(st), ctypes.byref(mo), ctypes.byref(d2),
+                              _ptr(iH), _ptr(iHp), _ptr(bJ), ctypes.byref(m))
+    if rc < 0:
+        raise ValueError("malformed tuple")
+    out = dict(E=E.value, grad=g, hess=H.reshape(12, 12), subtype=st.value, mollified=bool(mo.value), d2=d2.value)
+    if debug:
+        M = m.value * m.value
+        out.update(m=m.value, innerH=iH[:M * M].reshape(M, M), innerHp=iHp[:M * M].reshape(M, M), dbdJ=bJ[:M])
+    return out
+
+
+def eval_scene(x, tuples, prm=None, x_rest=None, nthreads=0, per_pair=False):
+    """Energy and gradient of a whole pair list (plus per-pair data on request)."""
+    prm = prm or params()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    t = np.ascontiguousarray(tuples, dtype=np.int32).reshape(-1, 4)
+    xr = None if x_rest is None else np.ascontiguousarray(x_rest, dtype=np.float64)
+    V, P = x.shape[0], t.shape[0]
+    grad = np.zeros((V, 3))
+    E = ctypes.c_double()
+    pE = np.zeros(P) if per_pair else None
+    pG = np.zeros((P, 12)) if per_pair else None
+    pH = np.zeros((P, 144)) if per_pair else None
+    st = np.zeros(P, np.int32)
+    mo = np.zeros(P, np.int32)
+    ndeg = lib().orc_eval(V, x.ctypes.data, _ptr(xr), P, t.ctypes.data, ctypes.byref(prm), int(nthreads),
+                          ctypes.byref(E), grad.ctypes.data, _ptr(pE), _ptr(pG), _ptr(pH),
+                          st.ctypes.data, mo.ctypes.data)
+    if ndeg < 0:
+        raise ValueError("malformed tuple or vertex index out of range")
+    out = dict(E=E.value, grad=grad, subtype=st, mollified=mo.astype(bool), n_degenerate=int(ndeg))
+    if per_pair:
+        out.update(pairE=pE, pairG=pG, pairH=pH.reshape(P, 12, 12))
+    return out
+
+
+def assemble(V, tuples, pairH, diag=None):
+    """Sorted block list (rows, cols, vals[nb,3,3]) of diag(d) I + sum_k S_k^T H_k S_k."""
+    t = np.ascontiguousarray(tuples, dtype=np.int32).reshape(-1, 4)
+    H = np.ascontiguousarray(pairH, dtype=np.float64).reshape(-1, 144)
+    dg = None if diag is None else np.ascontiguousarray(diag, dtype=np.float64)
+    L = lib()
+    nb = L.orc_assemble(V, t.shape[0], t.ctypes.data, H.ctypes.data, _ptr(dg), None, None, None, 0)
+    if nb < 0:
+        raise ValueError("malformed tuple")
+    rows = np.zeros(nb, np.int32)
+    cols = np.zeros(nb, np.int32)
+    vals = np.zeros((nb, 9))
+    L.orc_assemble(V, t.shape[0], t.ctypes.data, H.ctypes.data, _ptr(dg), rows.ctypes.data, cols.ctypes.data,
+                   vals.ctypes.data, nb)
+    return rows, cols, vals.reshape(nb, 3, 3)
+
+
+def spmv(V, rows, cols, vals, x):
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+    y = np.zeros(3 * V)
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    lib().orc_spmv(V, rows.shape[0], rows.ctypes.data, cols.ctypes.data, vals.ctypes.data, x.ctypes.data, y.ctypes.data)
+    return y
+
+
+def pcg(V, rows, cols, vals, b, x0=None, rtol=1e-6, maxit=1000):
+    b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
+    x = np.zeros(3 * V) if x0 is None else np.ascontiguousarray(x0, dtype=np.float64).reshape(-1).copy()
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    rr = ctypes.c_double()
+    it = lib().orc_pcg(V, rows.shape[0], rows.ctypes.data, cols.ctypes.data, vals.ctypes.data, b.ctypes.data,
+                       x.ctypes.data, float(rtol), int(maxit), ctypes.byref(rr))
+    return x, it, rr.value

@@ -1,0 +1,102 @@
+/*
+ * CPU FP64 oracle for the GIPC barrier hot path -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow reference of what the path computes (Huang et al., "GIPC: Fast
+ * and stable Gauss-Newton optimization of IPC barrier energy").  It shares no
+ * code with the HIP library.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load it.
+ *
+ * Contact tuples use the paper's sign encoding (Sec. 6.2, "Data structures"):
+ *   [a0, a1, b0, b1]          edge-edge candidate (a1 may be -(v+1): same)
+ *   [-(p+1), t0, t1, t2]      point-triangle candidate
+ *   [-(p+1), e0, e1, -1]      point-edge
+ *   [-(p+1), q, -1, -1]       point-point
+ *   [-(p+1), -(o+1), e0, -(e1+1)]    point-edge cut from a nearly parallel
+ *                                     edge pair (o: p's edge partner)
+ *   [-(p+1), -(o+1), -(q+1), -(r+1)] point-point cut from a nearly parallel
+ *                                     edge pair (o, r: edge partners)
+ * Candidates (the first two kinds) are classified by the constrained minimum
+ * of Eq. 4 / Eq. 5; the typed kinds use their own distance directly.
+ */
+#ifndef GIPC_ORACLE_H
+#define GIPC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    double dhat;        /* computational accuracy target */
+    double kappa;       /* barrier stiffness */
+    double dthr_ratio;  /* filter threshold d_thr / dhat (Eq. 23), 0.1 */
+    double epsx_ratio;  /* mollifier tolerance factor (Eq. 25), 1e-3 */
+    int filter;         /* apply Eq. 23 */
+    int mollify;        /* apply Eq. 25-36 to edge-edge families */
+    int eq12;           /* use the non-stiffened barrier Eq. 12 instead of Eq. 24 */
+} orc_params;
+
+/* sub-type codes reported per pair */
+enum { ORC_INACTIVE = 0, ORC_PT = 1, ORC_PE = 2, ORC_PP = 3, ORC_EE = 4, ORC_DEGENERATE = 7 };
+
+/* barrier b(g) and its first two derivatives in g (Eq. 24, or Eq. 12) */
+void orc_barrier(double g, double dhat, int eq12, double* b, double* db, double* d2b);
+/* mollifier e(c) and derivatives (Eq. 25) */
+void orc_mollifier(double c, double epsx, double* e, double* de, double* d2e);
+
+/* Cyclic Jacobi eigen-decomposition of a symmetric n x n row-major matrix.
+ * lam[n] receives eigenvalues, vec (n x n row-major) eigenvectors in columns. */
+int orc_jacobi_eig(int n, const double* A, double* lam, double* vec);
+
+/*
+ * One contact pair.  xs / xr hold the stencil's current / rest positions as
+ * [4][3] (unused rows ignored).  Outputs: energy, gradient [12] and proxy
+ * Hessian [12][12] over the stencil's 4 vertex slots (slots the tuple does
+ * not use stay zero), the sub-type, whether the mollifier applied and d^2.
+ * Optional debug outputs (nullable): the inner Hessian in vec(J) space
+ * before projection [9*9], its projection [9*9], vec(db/dJ) [9] and m.
+ */
+int orc_pair_local(const int32_t tuple[4], const double* xs, const double* xr, const orc_params* prm,
+                   double* E, double* grad12, double* hess144, int* subtype, int* mollified, double* dist2,
+                   double* innerH, double* innerHp, double* dbdJ, int* m_out);
+
+/* Stencil of a tuple: returns the vertex count (2..4, or -1 if malformed);
+ * vid[4] receives decoded vertex ids in slot order (-1 unused). */
+int orc_stencil(const int32_t tuple[4], int32_t vid[4]);
+
+/*
+ * Whole scene.  x, x_rest: [V][3] (x_rest nullable -> x).  Writes the total
+ * energy and grad[3V] (overwritten).  Per-pair outputs are optional.
+ * Returns the number of degenerate pairs, or -1 on a malformed tuple / index
+ * out of range.
+ */
+int64_t orc_eval(int32_t V, const double* x, const double* x_rest, int64_t P, const int32_t* tuples,
+                 const orc_params* prm, int nthreads, double* energy, double* grad,
+                 double* pairE, double* pairG, double* pairH, int32_t* subtype, int32_t* mollified);
+
+/*
+ * Assemble A = diag(d_v I3) + sum_k S_k^T H_k S_k as a sorted, duplicate-free
+ * list of 3x3 blocks (row-major values).  Every stencil block of every pair
+ * is listed (zero or not) and every vertex gets a diagonal block.  Returns
+ * the block count; with rows == NULL only counts.  diag nullable (0).
+ */
+int64_t orc_assemble(int32_t V, int64_t P, const int32_t* tuples, const double* pairH, const double* diag,
+                     int32_t* rows, int32_t* cols, double* vals, int64_t cap);
+
+/* y = A x for a block list produced by orc_assemble. */
+void orc_spmv(int32_t V, int64_t nb, const int32_t* rows, const int32_t* cols, const double* vals,
+              const double* x, double* y);
+
+/*
+ * Block-Jacobi preconditioned CG on A x = b (textbook PCG) with the 3x3
+ * diagonal blocks of A as preconditioner.  x holds x0 on entry.  Stops when
+ * ||r||_2 <= rtol ||b||_2 or after maxit iterations.  Returns iterations;
+ * *relres receives ||r||/||b||.
+ */
+int orc_pcg(int32_t V, int64_t nb, const int32_t* rows, const int32_t* cols, const double* vals,
+            const double* b, double* x, double rtol, int maxit, double* relres);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
