@@ -1,0 +1,216 @@
+/*
+ * gipc.h -- C ABI of the MI355X (gfx950) implementation of the GIPC barrier
+ * hot path (Huang, Chitalu, Lin, Komura: "GIPC: Fast and stable Gauss-Newton
+ * optimization of IPC barrier energy").
+ *
+ * Per contact pair the library evaluates the rewritten barrier energy
+ * (Eq. 24, optionally mollified by Eq. 25-29 for edge-edge pairs), its
+ * gradient (Eq. 13-14, Eq. 30) and its analytically projected Gauss-Newton
+ * proxy Hessian (Eq. 18-23 and Eq. 32-36), assembles the local Hessians
+ * into a 3x3 block-sparse (BSR) matrix, and solves with it by block-Jacobi
+ * preconditioned conjugate gradients (Sec. 6.2).
+ *
+ * Conventions for every entry point:
+ *  - Pointers documented as "device" are HIP device pointers; the caller
+ *    owns them.  Buffers the library needs internally live in the context.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued on it and the call returns; outputs are valid once
+ *    the stream has completed, unless a function states that it
+ *    synchronises.
+ *  - Functions return gipc_status and never throw or exit.  On an error the
+ *    context keeps a message (gipc_ctx_last_error).
+ *  - A context is bound to the device that was current at creation and must
+ *    not be used from two host threads at once.
+ */
+#ifndef GIPC_H
+#define GIPC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GIPC_OK = 0,
+    GIPC_ERR_INVALID_ARG = -1,   /* NULL pointer, negative size, bad flag */
+    GIPC_ERR_INDEX = -2,         /* malformed tuple, vertex id out of range, repeated vertex */
+    GIPC_ERR_DEGENERATE = -3,    /* reported by gipc_get_info: pairs with d = 0 or non-finite d */
+    GIPC_ERR_HIP = -4,           /* a HIP runtime call failed */
+    GIPC_ERR_WORKSPACE = -5,     /* allocation failed or a documented capacity limit was exceeded */
+    GIPC_ERR_BREAKDOWN = -6,     /* PCG: p^T A p <= 0 (A not positive definite) */
+    GIPC_ERR_STATE = -7,         /* call order violated (e.g. eval before build) */
+    GIPC_WARN_NOT_CONVERGED = 1  /* PCG stopped at maxit above the tolerance */
+} gipc_status;
+
+/* parameter flags */
+#define GIPC_FLAG_FILTER 0x1u        /* eigenvalue filter of Eq. 23 */
+#define GIPC_FLAG_MOLLIFY 0x2u       /* nearly-parallel edge-edge mollifier, Eq. 25-36 */
+#define GIPC_FLAG_BARRIER_EQ12 0x4u  /* non-stiffened barrier Eq. 12 instead of Eq. 24 (test mode) */
+#define GIPC_FLAGS_DEFAULT (GIPC_FLAG_FILTER | GIPC_FLAG_MOLLIFY)
+
+typedef struct {
+    double dhat;        /* computational accuracy target (Eq. 6, Eq. 9) */
+    double kappa;       /* barrier stiffness multiplying every pair's energy */
+    double dthr_ratio;  /* d_thr / dhat of the filter, Eq. 23 (paper: 0.1) */
+    double epsx_ratio;  /* eps_x = epsx_ratio |x12-x11|^2 |x22-x21|^2 at rest, Eq. 25 (paper: 1e-3) */
+    uint32_t flags;     /* GIPC_FLAG_* */
+} gipc_params;
+
+/* Vertex positions (the x of Eq. 1).  Both arrays: device, float64 [V][3]
+ * (AoS, 24 bytes per vertex).  x_rest (the reference positions of Eq. 25)
+ * may be NULL, meaning x. */
+typedef struct {
+    int32_t V;
+    const double* x;
+    const double* x_rest;
+} gipc_mesh;
+
+/* Contact tuples of vertex ids with the type in the signs (Sec. 6.2,
+ * "Data structures"); device, int32 [P][4]:
+ *   [a0, a1, b0, b1]        edge-edge pair (a1 may carry the nearly-parallel
+ *                           flag -(a1+1); the mollifier is decided anyway)
+ *   [-(p+1), t0, t1, t2]    point-triangle pair
+ *   [-(p+1), e0, e1, -1]    point-edge pair
+ *   [-(p+1), q, -1, -1]     point-point pair
+ * Every pair's distance is the constrained minimum over its primitives
+ * (Eq. 4 / Eq. 5); the library reduces it to its sub-type itself. */
+typedef struct {
+    int64_t P;
+    const int32_t* tuples;
+} gipc_pairs;
+
+enum { GIPC_F64 = 0, GIPC_F32 = 1 };
+
+/* Block-sparse matrix with 3x3 blocks.  row_ptr: device int32 [nbrows+1];
+ * col_idx: device int32 [nnzb], columns ascending within a row, every row
+ * holding its diagonal block; val: device, component-major [9][nnzb]
+ * (component 3a+b of block s at val[(3a+b)*nnzb + s]) of float64 (GIPC_F64)
+ * or float32 (GIPC_F32).  Vectors multiplied with it are [nbrows][3] of the
+ * same dtype. */
+typedef struct {
+    int32_t nbrows;
+    int64_t nnzb;
+    const int32_t* row_ptr;
+    const int32_t* col_idx;
+    void* val;
+    int32_t dtype;
+} gipc_bsr;
+
+/* Counts of the last gipc_pairs_build (host struct). */
+typedef struct {
+    int64_t n_candidates;   /* tuples given */
+    int64_t n_active;       /* pairs closer than dhat after classification */
+    int64_t n_by_type[8];   /* active pairs by sub-type: [1] PT, [2] PE, [3] PP, [4] EE,
+                               [5] EE, [6] PE, [7] PP cut from mollified edge-edge pairs */
+    int64_t n_degenerate;   /* pairs at distance 0 or with non-finite positions (skipped) */
+    int64_t first_degenerate; /* tuple index of the first one, -1 if none */
+    int64_t nnzb;           /* blocks of the assembled matrix */
+    int64_t n_contrib;      /* local-block contributions gathered by the assembly */
+    int32_t max_row_pairs;  /* largest number of pairs touching one vertex */
+} gipc_info;
+
+typedef struct gipc_ctx gipc_ctx;
+
+/* Status name ("GIPC_OK", ...). */
+const char* gipc_status_string(int status);
+
+/* Create a context on the current HIP device.  Allocates only a few small
+ * buffers; larger ones grow on demand.  *out is NULL on failure. */
+gipc_status gipc_ctx_create(gipc_ctx** out);
+/* Free every buffer the context holds (synchronises its device).  NULL ok. */
+void gipc_ctx_destroy(gipc_ctx* ctx);
+/* Message of the last error on this context ("" if none). */
+const char* gipc_ctx_last_error(const gipc_ctx* ctx);
+
+/*
+ * Stage a pair list and build the block pattern (Sec. 6.2 "Data
+ * structures"; matrix decomposition of supplement Sec. 6).
+ * Classifies every tuple at positions mesh->x by the active constraints of
+ * Eq. 4 / Eq. 5, drops pairs at distance >= dhat, sorts the active ones by
+ * sub-type (the four type buffers of supplement Sec. 6) and builds the BSR
+ * pattern of diag + sum_k S_k^T H_k S_k over the vertices each pair's
+ * distance depends on (all four for mollified edge-edge pairs).
+ * Synchronises `stream` (three times) to size the pattern; `info` (host,
+ * nullable) receives the counts.  Errors: INVALID_ARG, INDEX (no state is
+ * kept), WORKSPACE (a vertex touched by more than 2048 active pairs), HIP.
+ */
+gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pairs* pairs,
+                             const gipc_params* params, void* stream, gipc_info* info);
+
+/* Counts of the last successful build (host copy, no synchronisation). */
+gipc_status gipc_get_info(const gipc_ctx* ctx, gipc_info* info);
+
+/* Pattern of the last build: fills nbrows, nnzb, row_ptr, col_idx (device
+ * pointers owned by the context, valid until the next build); leaves val
+ * and dtype untouched. */
+gipc_status gipc_bsr_pattern(const gipc_ctx* ctx, gipc_bsr* A);
+
+/*
+ * Barrier energy and gradient of the staged pairs at mesh->x (Eq. 24 / 29,
+ * Eq. 13-14 / 30): *energy (device, 1 double) = kappa * sum_k e_k b_k;
+ * grad (device, double [V][3], overwritten).  Also stores each pair's
+ * compact proxy-Hessian factors (Eq. 18-23, 32-36) in the context for
+ * gipc_assemble_bsr.  Deterministic (no floating-point atomics).
+ * Errors: INVALID_ARG, STATE (no build, or V differs from the build).
+ */
+gipc_status gipc_barrier_eval(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params,
+                              double* energy, double* grad, void* stream);
+
+/*
+ * Assemble the proxy Hessians of the last gipc_barrier_eval plus
+ * diag(d_v) (x) I3 into A->val (device, [9][nnzb] of A->dtype; FP32 values
+ * are rounded once from FP64 sums).  A->row_ptr / col_idx / nnzb / nbrows
+ * must be the context's pattern (gipc_bsr_pattern).  diag: device double
+ * [V] (e.g. mass / dt^2), nullable = 0.  Errors: INVALID_ARG, STATE.
+ */
+gipc_status gipc_assemble_bsr(gipc_ctx* ctx, const double* diag, const gipc_bsr* A, void* stream);
+
+/* gipc_barrier_eval followed by gipc_assemble_bsr, with the gradient and
+ * the diagonal blocks produced by one kernel. */
+gipc_status gipc_eval_assemble(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params,
+                               double* energy, double* grad, const double* diag, const gipc_bsr* A,
+                               void* stream);
+
+/* y = A x (device vectors of A's dtype, [nbrows][3]); any BSR in the layout
+ * above.  Deterministic.  Errors: INVALID_ARG. */
+gipc_status gipc_bsr_spmv(const gipc_bsr* A, const void* x, void* y, void* stream);
+
+/*
+ * Solve A x = b by conjugate gradients preconditioned with the inverses of
+ * A's 3x3 diagonal blocks (Sec. 6.2; Saad Alg. 9.1).  b, x: device double
+ * [nbrows][3]; x holds x0 on entry and the result on return.  A must be
+ * FP64 (GIPC_F64).  Stops when ||r||_2 <= rtol ||b||_2 (checked every
+ * iteration on the device; the host polls every 16 iterations) or after
+ * maxit iterations; rtol = 0 runs exactly maxit iterations.  Synchronises
+ * `stream`; *iters and *relres (host, nullable) receive the iterations run
+ * and ||r||/||b||.  Returns OK, WARN_NOT_CONVERGED (rtol > 0 not reached),
+ * BREAKDOWN, INVALID_ARG or HIP.
+ */
+gipc_status gipc_pcg(gipc_ctx* ctx, const gipc_bsr* A, const double* b, double* x, double rtol, int32_t maxit,
+                     int32_t* iters, double* relres, void* stream);
+
+/*
+ * Inspection of the staged pairs of the last build and the factors of the
+ * last eval, expanded per pair (for tests and tooling).  Device buffers sized
+ * for info.n_active pairs, each nullable:
+ *   src [Pa] int32        tuple index each staged pair came from
+ *   type [Pa] int32       sub-type code as in gipc_info.n_by_type
+ *   vid [Pa][4] int32     vertex ids of the staged stencil (-1 unused)
+ *   energy [Pa] double    kappa e b of the pair, evaluated at mesh->x
+ *   grad [Pa][12] double  local gradient over the 4 stencil slots  (needs an eval)
+ *   hess [Pa][144] double local proxy Hessian, 12x12 row-major      (needs an eval)
+ * Errors: INVALID_ARG, STATE.
+ */
+gipc_status gipc_pair_inspect(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params, int32_t* src,
+                              int32_t* type, int32_t* vid, double* energy, double* grad, double* hess,
+                              void* stream);
+
+/* Plain device-to-device copy of `bytes` bytes with the library's own
+ * streaming kernel (bandwidth reference for roofline fractions). */
+gipc_status gipc_copy(const void* src, void* dst, int64_t bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GIPC_H */

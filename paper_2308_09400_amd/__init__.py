@@ -1,0 +1,314 @@
+"""Python binding of libgipc (the GIPC barrier hot path on MI355X / gfx950).
+
+Argument marshalling only: every step runs in the HIP kernels of
+``libgipc.so``.  Tensors are torch tensors on the current HIP device and the
+work goes on ``torch.cuda.current_stream()`` unless a stream is given.  The
+names follow the C ABI in ``include/gipc.h`` without the ``gipc_`` prefix.
+There is no CPU fallback: if the library cannot be loaded every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgipc.so")
+
+OK, ERR_INVALID_ARG, ERR_INDEX, ERR_DEGENERATE, ERR_HIP, ERR_WORKSPACE, ERR_BREAKDOWN, ERR_STATE = 0, -1, -2, -3, -4, -5, -6, -7
+WARN_NOT_CONVERGED = 1
+FLAG_FILTER, FLAG_MOLLIFY, FLAG_BARRIER_EQ12 = 0x1, 0x2, 0x4
+FLAGS_DEFAULT = FLAG_FILTER | FLAG_MOLLIFY
+F64, F32 = 0, 1
+SUBTYPES = {1: "PT", 2: "PE", 3: "PP", 4: "EE", 5: "EE_moll", 6: "PE_moll", 7: "PP_moll"}
+
+EXPORTS = [
+    "gipc_status_string", "gipc_ctx_create", "gipc_ctx_destroy", "gipc_ctx_last_error", "gipc_pairs_build",
+    "gipc_get_info", "gipc_bsr_pattern", "gipc_barrier_eval", "gipc_assemble_bsr", "gipc_eval_assemble",
+    "gipc_bsr_spmv", "gipc_pcg", "gipc_pair_inspect", "gipc_copy",
+]
+
+
+class GipcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(msg)
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("dhat", ctypes.c_double), ("kappa", ctypes.c_double), ("dthr_ratio", ctypes.c_double),
+                ("epsx_ratio", ctypes.c_double), ("flags", ctypes.c_uint32)]
+
+
+class Mesh(ctypes.Structure):
+    _fields_ = [("V", ctypes.c_int32), ("x", ctypes.c_void_p), ("x_rest", ctypes.c_void_p)]
+
+
+class Pairs(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int64), ("tuples", ctypes.c_void_p)]
+
+
+class Bsr(ctypes.Structure):
+    _fields_ = [("nbrows", ctypes.c_int32), ("nnzb", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p), ("dtype", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n_candidates", ctypes.c_int64), ("n_active", ctypes.c_int64), ("n_by_type", ctypes.c_int64 * 8),
+                ("n_degenerate", ctypes.c_int64), ("first_degenerate", ctypes.c_int64), ("nnzb", ctypes.c_int64),
+                ("n_contrib", ctypes.c_int64), ("max_row_pairs", ctypes.c_int32)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "n_by_type"}
+        d["n_by_type"] = {SUBTYPES[t]: int(self.n_by_type[t]) for t in range(1, 8)}
+        return d
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libgipc.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing; build it with `python -m paper_2308_09400_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        st = ctypes.c_int
+        sig = {
+            "gipc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+            "gipc_ctx_create": (st, [ctypes.POINTER(vp)]),
+            "gipc_ctx_destroy": (None, [vp]),
+            "gipc_ctx_last_error": (ctypes.c_char_p, [vp]),
+            "gipc_pairs_build": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Pairs), ctypes.POINTER(Params), vp,
+                                      ctypes.POINTER(Info)]),
+            "gipc_get_info": (st, [vp, ctypes.POINTER(Info)]),
+            "gipc_bsr_pattern": (st, [vp, ctypes.POINTER(Bsr)]),
+            "gipc_barrier_eval": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), vp, vp, vp]),
+            "gipc_assemble_bsr": (st, [vp, vp, ctypes.POINTER(Bsr), vp]),
+            "gipc_eval_assemble": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), vp, vp, vp,
+                                        ctypes.POINTER(Bsr), vp]),
+            "gipc_bsr_spmv": (st, [ctypes.POINTER(Bsr), vp, vp, vp]),
+            "gipc_pcg": (st, [vp, ctypes.POINTER(Bsr), vp, vp, d, i32, ctypes.POINTER(i32), ctypes.POINTER(d), vp]),
+            "gipc_pair_inspect": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), vp, vp, vp, vp, vp, vp, vp]),
+            "gipc_copy": (st, [vp, vp, i64, vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(s: int) -> str:
+    return lib().gipc_status_string(int(s)).decode()
+
+
+def params(dhat=1e-3, kappa=1e4, dthr_ratio=0.1, epsx_ratio=1e-3, flags=FLAGS_DEFAULT) -> Params:
+    return Params(float(dhat), float(kappa), float(dthr_ratio), float(epsx_ratio), int(flags))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need(t, dtype, shape_last=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_last is not None and (t.dim() < 1 or t.shape[-1] != shape_last):
+        raise ValueError(f"{name} must have last dimension {shape_last}")
+
+
+class Context:
+    """Owns a gipc_ctx (device workspace, staged pairs, pattern, factors)."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        s = lib().gipc_ctx_create(ctypes.byref(h))
+        if s != OK:
+            raise GipcError(s, f"gipc_ctx_create: {status_string(s)}")
+        self.h = h
+        self.V = 0
+        self.info = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().gipc_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, s, what):
+        if s < 0:
+            msg = lib().gipc_ctx_last_error(self.h).decode()
+            raise GipcError(s, f"{what}: {status_string(s)}: {msg}")
+        return s
+
+    @staticmethod
+    def _mesh(x, x_rest):
+        _need(x, torch.float64, 3, "x")
+        if x_rest is not None:
+            _need(x_rest, torch.float64, 3, "x_rest")
+            if x_rest.shape != x.shape:
+                raise ValueError("x_rest must match x")
+        return Mesh(int(x.shape[0]), x.data_ptr(), None if x_rest is None else x_rest.data_ptr())
+
+
+def pairs_build(ctx: Context, x, tuples, prm: Params, x_rest=None, stream=None) -> dict:
+    """Stage the tuples at positions x and build the BSR pattern (synchronises)."""
+    _need(tuples, torch.int32, 4, "tuples")
+    mesh = Context._mesh(x, x_rest)
+    pairs = Pairs(int(tuples.shape[0]), tuples.data_ptr())
+    info = Info()
+    ctx._check(lib().gipc_pairs_build(ctx.h, ctypes.byref(mesh), ctypes.byref(pairs), ctypes.byref(prm),
+                                      _stream(stream), ctypes.byref(info)), "gipc_pairs_build")
+    ctx.V = int(x.shape[0])
+    ctx.info = info.as_dict()
+    return ctx.info
+
+
+def bsr_pattern(ctx: Context) -> Bsr:
+    A = Bsr()
+    ctx._check(lib().gipc_bsr_pattern(ctx.h, ctypes.byref(A)), "gipc_bsr_pattern")
+    return A
+
+
+def barrier_eval(ctx: Context, x, prm: Params, x_rest=None, energy=None, grad=None, stream=None):
+    """Energy (device scalar tensor) and gradient [V][3] of the staged pairs."""
+    mesh = Context._mesh(x, x_rest)
+    energy = torch.empty((), dtype=torch.float64, device=x.device) if energy is None else energy
+    grad = torch.empty_like(x) if grad is None else grad
+    ctx._check(lib().gipc_barrier_eval(ctx.h, ctypes.byref(mesh), ctypes.byref(prm), _ptr(energy), _ptr(grad),
+                                       _stream(stream)), "gipc_barrier_eval")
+    return energy, grad
+
+
+class BsrMatrix:
+    """A BSR matrix on the context's pattern with caller-owned values [9][nnzb]."""
+
+    def __init__(self, ctx: Context, dtype=F64, device=None):
+        self.ctx = ctx
+        self.desc = bsr_pattern(ctx)
+        self.dtype = dtype
+        tdt = torch.float64 if dtype == F64 else torch.float32
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.val = torch.empty((9, max(int(self.desc.nnzb), 1)), dtype=tdt, device=dev)
+        self.desc.val = self.val.data_ptr()
+        self.desc.dtype = dtype
+
+    @property
+    def nnzb(self):
+        return int(self.desc.nnzb)
+
+    @property
+    def nbrows(self):
+        return int(self.desc.nbrows)
+
+    def row_ptr(self):
+        return _wrap_i32(self.desc.row_ptr, self.nbrows + 1, self.val.device)
+
+    def col_idx(self):
+        return _wrap_i32(self.desc.col_idx, self.nnzb, self.val.device)
+
+    def to_scipy(self):
+        """Host scipy.sparse.bsr_matrix copy (test helper)."""
+        import numpy as np
+        import scipy.sparse as sps
+        rp = self.row_ptr().cpu().numpy()
+        ci = self.col_idx().cpu().numpy()
+        v = self.val[:, :self.nnzb].double().cpu().numpy().T.reshape(-1, 3, 3)
+        return sps.bsr_matrix((v, ci, rp), shape=(3 * self.nbrows, 3 * self.nbrows))
+
+
+def _wrap_i32(ptr, n, device):
+    """Copy n int32 from a library-owned device pointer into a new tensor."""
+    out = torch.empty(max(n, 0), dtype=torch.int32, device=device)
+    if n > 0:
+        s = lib().gipc_copy(ctypes.c_void_p(ptr), ctypes.c_void_p(out.data_ptr()), 4 * n, _stream(None))
+        if s != OK:
+            raise GipcError(s, "gipc_copy failed")
+    return out
+
+
+def assemble_bsr(ctx: Context, A: BsrMatrix, diag=None, stream=None):
+    if diag is not None:
+        _need(diag, torch.float64, None, "diag")
+    ctx._check(lib().gipc_assemble_bsr(ctx.h, _ptr(diag), ctypes.byref(A.desc), _stream(stream)), "gipc_assemble_bsr")
+    return A
+
+
+def eval_assemble(ctx: Context, x, prm: Params, A: BsrMatrix, diag=None, x_rest=None, energy=None, grad=None,
+                  stream=None):
+    mesh = Context._mesh(x, x_rest)
+    if diag is not None:
+        _need(diag, torch.float64, None, "diag")
+    energy = torch.empty((), dtype=torch.float64, device=x.device) if energy is None else energy
+    grad = torch.empty_like(x) if grad is None else grad
+    ctx._check(lib().gipc_eval_assemble(ctx.h, ctypes.byref(mesh), ctypes.byref(prm), _ptr(energy), _ptr(grad),
+                                        _ptr(diag), ctypes.byref(A.desc), _stream(stream)), "gipc_eval_assemble")
+    return energy, grad
+
+
+def bsr_spmv(A: BsrMatrix, x, y=None, stream=None):
+    tdt = torch.float64 if A.dtype == F64 else torch.float32
+    _need(x, tdt, 3, "x")
+    y = torch.empty_like(x) if y is None else y
+    s = lib().gipc_bsr_spmv(ctypes.byref(A.desc), _ptr(x), _ptr(y), _stream(stream))
+    if s != OK:
+        raise GipcError(s, f"gipc_bsr_spmv: {status_string(s)}")
+    return y
+
+
+def pcg(ctx: Context, A: BsrMatrix, b, x=None, rtol=1e-6, maxit=1000, stream=None):
+    """Block-Jacobi PCG (synchronises).  Returns (x, iterations, relres, status)."""
+    _need(b, torch.float64, 3, "b")
+    x = torch.zeros_like(b) if x is None else x
+    it = ctypes.c_int32()
+    rr = ctypes.c_double()
+    s = lib().gipc_pcg(ctx.h, ctypes.byref(A.desc), _ptr(b), _ptr(x), float(rtol), int(maxit), ctypes.byref(it),
+                       ctypes.byref(rr), _stream(stream))
+    ctx._check(s, "gipc_pcg")
+    return x, int(it.value), float(rr.value), int(s)
+
+
+def pair_inspect(ctx: Context, x=None, prm: Params | None = None, x_rest=None, want=("src", "type", "vid"),
+                 stream=None):
+    """Per staged pair: src, type, vid, energy, grad [12], hess [12,12] (device tensors)."""
+    n = int(ctx.info["n_active"]) if ctx.info else 0
+    dev = torch.device("cuda", torch.cuda.current_device())
+    out = {}
+    alloc = {"src": ((n,), torch.int32), "type": ((n,), torch.int32), "vid": ((n, 4), torch.int32),
+             "energy": ((n,), torch.float64), "grad": ((n, 12), torch.float64), "hess": ((n, 12, 12), torch.float64)}
+    for k in want:
+        shp, dt = alloc[k]
+        out[k] = torch.empty(shp, dtype=dt, device=dev)
+    mesh = Context._mesh(x, x_rest) if x is not None else None
+    ctx._check(lib().gipc_pair_inspect(ctx.h, ctypes.byref(mesh) if mesh else None,
+                                       ctypes.byref(prm) if prm else None,
+                                       *[_ptr(out.get(k)) for k in ("src", "type", "vid", "energy", "grad", "hess")],
+                                       _stream(stream)), "gipc_pair_inspect")
+    return out
+
+
+def copy(src, dst, nbytes=None, stream=None):
+    nbytes = src.numel() * src.element_size() if nbytes is None else nbytes
+    s = lib().gipc_copy(_ptr(src), _ptr(dst), int(nbytes), _stream(stream))
+    if s != OK:
+        raise GipcError(s, "gipc_copy failed")
+    return dst

@@ -1,0 +1,460 @@
+// C ABI of libgipc: argument checks, context state, buffer management and
+// the launch sequences.  Every compute step runs in the kernels of the
+// other translation units.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.hpp"
+
+using namespace gipc;
+
+namespace gipc {
+
+hipError_t ensure(DevBuf& b, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (bytes <= b.bytes) return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+        if (e != hipSuccess) return e;
+    }
+    size_t cap = bytes + bytes / 4;
+    cap = (cap + 255) & ~size_t(255);
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, cap);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return e;
+    }
+    b.p = p;
+    b.bytes = cap;
+    return hipSuccess;
+}
+
+void release(DevBuf& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+}  // namespace gipc
+
+namespace {
+
+// counters layout (int64 slots of ctx->counters)
+enum {
+    C_NBAD = 0, C_FIRST_BAD = 1, C_NDEG = 2, C_FIRST_DEG = 3, C_ACTIVE = 4, C_OFF = 5,  // 5..13: type offsets
+    C_INC = 16, C_K = 17, C_NNZB = 18, C_MAXDEG = 19, C_NSLOTS = 24
+};
+
+gipc_status fail(gipc_ctx* ctx, gipc_status st, const char* fmt, ...) {
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return st;
+}
+
+gipc_status hip_fail(gipc_ctx* ctx, hipError_t e, const char* what) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(ctx, GIPC_ERR_WORKSPACE, "%s: out of device memory (%s)", what, hipGetErrorString(e));
+    return fail(ctx, GIPC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define CK(call, what)                                 \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+    } while (0)
+
+gipc_status check_device(gipc_ctx* ctx) {
+    int d = -1;
+    if (hipGetDevice(&d) != hipSuccess) return fail(ctx, GIPC_ERR_HIP, "hipGetDevice failed");
+    if (d != ctx->device)
+        return fail(ctx, GIPC_ERR_INVALID_ARG, "context belongs to device %d but device %d is current", ctx->device, d);
+    return GIPC_OK;
+}
+
+gipc_status to_dev_params(gipc_ctx* ctx, const gipc_params* p, DevParams& o) {
+    if (!p) return fail(ctx, GIPC_ERR_INVALID_ARG, "params is NULL");
+    if (!(p->dhat > 0.0) || !std::isfinite(p->dhat)) return fail(ctx, GIPC_ERR_INVALID_ARG, "dhat must be > 0");
+    if (!(p->kappa >= 0.0) || !std::isfinite(p->kappa)) return fail(ctx, GIPC_ERR_INVALID_ARG, "kappa must be >= 0");
+    if (!(p->dthr_ratio >= 0.0) || !(p->dthr_ratio < 1.0))
+        return fail(ctx, GIPC_ERR_INVALID_ARG, "dthr_ratio must be in [0, 1)");
+    if (!(p->epsx_ratio >= 0.0) || !std::isfinite(p->epsx_ratio))
+        return fail(ctx, GIPC_ERR_INVALID_ARG, "epsx_ratio must be >= 0");
+    if (p->flags & ~(GIPC_FLAG_FILTER | GIPC_FLAG_MOLLIFY | GIPC_FLAG_BARRIER_EQ12))
+        return fail(ctx, GIPC_ERR_INVALID_ARG, "unknown flag bits 0x%x", p->flags);
+    o.dhat = p->dhat;
+    o.kappa = p->kappa;
+    o.dthr_ratio = p->dthr_ratio;
+    o.epsx_ratio = p->epsx_ratio;
+    o.filter = (p->flags & GIPC_FLAG_FILTER) ? 1 : 0;
+    o.mollify = (p->flags & GIPC_FLAG_MOLLIFY) ? 1 : 0;
+    o.eq12 = (p->flags & GIPC_FLAG_BARRIER_EQ12) ? 1 : 0;
+    return GIPC_OK;
+}
+
+gipc_status check_mesh(gipc_ctx* ctx, const gipc_mesh* m) {
+    if (!m) return fail(ctx, GIPC_ERR_INVALID_ARG, "mesh is NULL");
+    if (m->V < 0) return fail(ctx, GIPC_ERR_INVALID_ARG, "V < 0");
+    if (m->V > 0 && !m->x) return fail(ctx, GIPC_ERR_INVALID_ARG, "mesh->x is NULL");
+    return GIPC_OK;
+}
+
+hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+gipc_status read_counters(gipc_ctx* ctx, int64_t* host, int first, int n, hipStream_t s) {
+    CK(hipMemcpyAsync(host + first, as<int64_t>(ctx->counters) + first, sizeof(int64_t) * n, hipMemcpyDeviceToHost,
+                      s),
+       "copy counters");
+    CK(hipStreamSynchronize(s), "stream synchronize");
+    return GIPC_OK;
+}
+
+bool same_pattern(const gipc_ctx* ctx, const gipc_bsr* A) {
+    return A->nbrows == ctx->V && A->nnzb == ctx->nnzb && A->row_ptr == ctx->row_ptr.p &&
+           A->col_idx == ctx->col_idx.p;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gipc_status_string(int st) {
+    switch (st) {
+        case GIPC_OK: return "GIPC_OK";
+        case GIPC_ERR_INVALID_ARG: return "GIPC_ERR_INVALID_ARG";
+        case GIPC_ERR_INDEX: return "GIPC_ERR_INDEX";
+        case GIPC_ERR_DEGENERATE: return "GIPC_ERR_DEGENERATE";
+        case GIPC_ERR_HIP: return "GIPC_ERR_HIP";
+        case GIPC_ERR_WORKSPACE: return "GIPC_ERR_WORKSPACE";
+        case GIPC_ERR_BREAKDOWN: return "GIPC_ERR_BREAKDOWN";
+        case GIPC_ERR_STATE: return "GIPC_ERR_STATE";
+        case GIPC_WARN_NOT_CONVERGED: return "GIPC_WARN_NOT_CONVERGED";
+        default: return "GIPC_UNKNOWN_STATUS";
+    }
+}
+
+gipc_status gipc_ctx_create(gipc_ctx** out) {
+    if (!out) return GIPC_ERR_INVALID_ARG;
+    *out = nullptr;
+    gipc_ctx* ctx = new (std::nothrow) gipc_ctx();
+    if (!ctx) return GIPC_ERR_WORKSPACE;
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        delete ctx;
+        return GIPC_ERR_HIP;
+    }
+    if (ensure(ctx->counters, sizeof(int64_t) * C_NSLOTS) != hipSuccess) {
+        delete ctx;
+        return GIPC_ERR_WORKSPACE;
+    }
+    *out = ctx;
+    return GIPC_OK;
+}
+
+void gipc_ctx_destroy(gipc_ctx* ctx) {
+    if (!ctx) return;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(ctx->device);
+    DevBuf* bufs[] = {&ctx->cand_ft, &ctx->cand_vid, &ctx->bcount, &ctx->boff, &ctx->counters, &ctx->st_vid,
+                      &ctx->st_src, &ctx->deg, &ctx->kcount, &ctx->fill, &ctx->inc_ptr, &ctx->kptr, &ctx->inc,
+                      &ctx->contrib, &ctx->kcol, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
+                      &ctx->slot_row, &ctx->diag_slot, &ctx->maxbuf, &ctx->rec_main, &ctx->rec_extra, &ctx->e_part,
+                      &ctx->r, &ctx->z, &ctx->p, &ctx->q, &ctx->minv, &ctx->part, &ctx->scal, &ctx->scan_tmp,
+                      &ctx->scan_tmp2};
+    for (DevBuf* b : bufs) release(*b);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    delete ctx;
+}
+
+const char* gipc_ctx_last_error(const gipc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pairs* pairs,
+                             const gipc_params* params, void* stream, gipc_info* info) {
+    if (!ctx) return GIPC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    gipc_status st;
+    if ((st = check_device(ctx)) != GIPC_OK) return st;
+    if ((st = check_mesh(ctx, mesh)) != GIPC_OK) return st;
+    if (!pairs) return fail(ctx, GIPC_ERR_INVALID_ARG, "pairs is NULL");
+    if (pairs->P < 0 || pairs->P >= (int64_t(1) << 31))
+        return fail(ctx, GIPC_ERR_INVALID_ARG, "P must be in [0, 2^31)");
+    if (pairs->P > 0 && !pairs->tuples) return fail(ctx, GIPC_ERR_INVALID_ARG, "pairs->tuples is NULL");
+    DevParams pm;
+    if ((st = to_dev_params(ctx, params, pm)) != GIPC_OK) return st;
+
+    hipStream_t s = S(stream);
+    const int64_t P = pairs->P;
+    const int32_t V = mesh->V;
+    const double* xr = mesh->x_rest ? mesh->x_rest : mesh->x;
+    ctx->built = false;
+    ctx->evaluated = false;
+
+    // ---- staging
+    const int64_t nb = (P + kBlock - 1) / kBlock;
+    CK(ensure(ctx->cand_ft, (size_t)P), "alloc staging");
+    CK(ensure(ctx->cand_vid, sizeof(int4) * (size_t)P), "alloc staging");
+    CK(ensure(ctx->bcount, sizeof(int32_t) * 8 * (size_t)(nb > 0 ? nb : 1)), "alloc staging");
+    CK(ensure(ctx->boff, sizeof(int64_t) * (8 * (size_t)nb + 1)), "alloc staging");
+    CK(ensure(ctx->st_vid, sizeof(int4) * (size_t)P), "alloc staged pairs");
+    CK(ensure(ctx->st_src, sizeof(int32_t) * (size_t)P), "alloc staged pairs");
+    int64_t* cnt = as<int64_t>(ctx->counters);
+    CK(hipMemsetAsync(cnt, 0, sizeof(int64_t) * C_NSLOTS, s), "clear counters");
+    CK(hipMemsetAsync(cnt + C_FIRST_BAD, 0xff, sizeof(int64_t), s), "clear counters");
+    CK(hipMemsetAsync(cnt + C_FIRST_DEG, 0xff, sizeof(int64_t), s), "clear counters");
+    if (P > 0) {
+        CK(launch_stage_classify(pairs->tuples, P, V, mesh->x, xr, pm, as<uint8_t>(ctx->cand_ft),
+                                 as<int4>(ctx->cand_vid), as<int32_t>(ctx->bcount), cnt, s),
+           "stage classify");
+        CK((exclusive_scan<int32_t, int64_t>(as<int32_t>(ctx->bcount), 8 * nb, as<int64_t>(ctx->boff), ctx, s,
+                                             cnt + C_ACTIVE)),
+           "stage scan");
+        CK(launch_stage_scatter(as<uint8_t>(ctx->cand_ft), as<int4>(ctx->cand_vid), P, as<int64_t>(ctx->boff),
+                                as<int4>(ctx->st_vid), as<int32_t>(ctx->st_src), s),
+           "stage scatter");
+        CK(launch_stage_offsets(as<int64_t>(ctx->boff), nb, cnt + C_OFF, s), "stage offsets");
+    }
+    int64_t hc[C_NSLOTS] = {0};
+    if ((st = read_counters(ctx, hc, 0, 14, s)) != GIPC_OK) return st;
+    if (hc[C_NBAD] > 0)
+        return fail(ctx, GIPC_ERR_INDEX, "%lld malformed tuple(s) or vertex id(s) out of [0, %d); first at %lld",
+                    (long long)hc[C_NBAD], V, (long long)hc[C_FIRST_BAD]);
+    TypeRanges tr;
+    for (int t = 0; t < 9; ++t) tr.off[t] = P > 0 ? hc[C_OFF + t] : 0;
+    tr.off[0] = 0;
+    const int64_t Ps = tr.off[8];
+    if (Ps >= (int64_t(1) << 28)) return fail(ctx, GIPC_ERR_WORKSPACE, "more than 2^28 active pairs (%lld)", (long long)Ps);
+
+    // ---- symbolic
+    const size_t Vs = (size_t)(V > 0 ? V : 1);
+    CK(ensure(ctx->deg, sizeof(int32_t) * Vs), "alloc pattern");
+    CK(ensure(ctx->kcount, sizeof(int32_t) * Vs), "alloc pattern");
+    CK(ensure(ctx->fill, sizeof(int32_t) * Vs), "alloc pattern");
+    CK(ensure(ctx->inc_ptr, sizeof(int64_t) * (Vs + 1)), "alloc pattern");
+    CK(ensure(ctx->kptr, sizeof(int64_t) * (Vs + 1)), "alloc pattern");
+    CK(ensure(ctx->ncols, sizeof(int32_t) * Vs), "alloc pattern");
+    CK(ensure(ctx->row_ptr, sizeof(int32_t) * (Vs + 1)), "alloc pattern");
+    CK(ensure(ctx->diag_slot, sizeof(int32_t) * Vs), "alloc pattern");
+    CK(hipMemsetAsync(ctx->deg.p, 0, sizeof(int32_t) * Vs, s), "clear pattern");
+    CK(hipMemsetAsync(ctx->kcount.p, 0, sizeof(int32_t) * Vs, s), "clear pattern");
+    CK(hipMemsetAsync(ctx->fill.p, 0, sizeof(int32_t) * Vs, s), "clear pattern");
+    CK(launch_sym_count(as<int4>(ctx->st_vid), tr, as<int32_t>(ctx->deg), as<int32_t>(ctx->kcount), s), "count");
+    CK(reduce_max_i32(as<int32_t>(ctx->deg), V, reinterpret_cast<int32_t*>(cnt + C_MAXDEG), s), "max degree");
+    CK((exclusive_scan<int32_t, int64_t>(as<int32_t>(ctx->deg), V, as<int64_t>(ctx->inc_ptr), ctx, s, cnt + C_INC)),
+       "incidence scan");
+    CK((exclusive_scan<int32_t, int64_t>(as<int32_t>(ctx->kcount), V, as<int64_t>(ctx->kptr), ctx, s, cnt + C_K)),
+       "contribution scan");
+    if ((st = read_counters(ctx, hc, C_INC, 4, s)) != GIPC_OK) return st;
+    const int32_t max_deg = (int32_t)(hc[C_MAXDEG] & 0xffffffff);
+    if (max_deg > kMaxRowPairs)
+        return fail(ctx, GIPC_ERR_WORKSPACE, "a vertex is touched by %d active pairs (limit %d)", max_deg,
+                    kMaxRowPairs);
+    const int64_t ninc = hc[C_INC], K = hc[C_K];
+    CK(ensure(ctx->inc, sizeof(uint32_t) * (size_t)ninc), "alloc incidences");
+    CK(ensure(ctx->contrib, sizeof(uint32_t) * (size_t)K), "alloc contributions");
+    CK(ensure(ctx->kcol, sizeof(int32_t) * (size_t)K), "alloc contributions");
+    CK(launch_sym_scatter(as<int4>(ctx->st_vid), tr, as<int64_t>(ctx->inc_ptr), as<int32_t>(ctx->fill),
+                          as<uint32_t>(ctx->inc), s),
+       "incidence scatter");
+    CK(launch_sym_rowsort(V, max_deg, as<int64_t>(ctx->inc_ptr), as<uint32_t>(ctx->inc), as<int4>(ctx->st_vid), tr,
+                          as<int64_t>(ctx->kptr), as<uint32_t>(ctx->contrib), as<int32_t>(ctx->kcol),
+                          as<int32_t>(ctx->ncols), s),
+       "row sort");
+    CK((exclusive_scan<int32_t, int32_t>(as<int32_t>(ctx->ncols), V, as<int32_t>(ctx->row_ptr), ctx, s,
+                                         cnt + C_NNZB)),
+       "row scan");
+    if ((st = read_counters(ctx, hc, C_NNZB, 1, s)) != GIPC_OK) return st;
+    const int64_t nnzb = hc[C_NNZB];
+    if (nnzb >= (int64_t(1) << 31)) return fail(ctx, GIPC_ERR_WORKSPACE, "more than 2^31 blocks");
+    CK(ensure(ctx->col_idx, sizeof(int32_t) * (size_t)nnzb), "alloc pattern");
+    CK(ensure(ctx->slot_row, sizeof(int32_t) * (size_t)nnzb), "alloc pattern");
+    CK(ensure(ctx->cptr, sizeof(int64_t) * (size_t)(nnzb + 1)), "alloc pattern");
+    CK(launch_sym_fill(V, as<int64_t>(ctx->kptr), as<int32_t>(ctx->kcol), as<int32_t>(ctx->row_ptr),
+                       as<int32_t>(ctx->col_idx), as<int64_t>(ctx->cptr), as<int32_t>(ctx->slot_row),
+                       as<int32_t>(ctx->diag_slot), nnzb, s),
+       "pattern fill");
+
+    ctx->ranges = tr;
+    ctx->Ps = Ps;
+    ctx->V = V;
+    ctx->nnzb = nnzb;
+    ctx->K = K;
+    ctx->max_deg = max_deg;
+    gipc_info& in = ctx->info;
+    memset(&in, 0, sizeof(in));
+    in.n_candidates = P;
+    in.n_active = Ps;
+    for (int t = 1; t < 8; ++t) in.n_by_type[t] = tr.off[t + 1] - tr.off[t];
+    in.n_degenerate = hc[C_NDEG];
+    in.first_degenerate = hc[C_NDEG] > 0 ? hc[C_FIRST_DEG] : -1;
+    in.nnzb = nnzb;
+    in.n_contrib = K;
+    in.max_row_pairs = max_deg;
+    if (info) *info = in;
+    ctx->built = true;
+    return GIPC_OK;
+}
+
+gipc_status gipc_get_info(const gipc_ctx* ctx, gipc_info* info) {
+    if (!ctx || !info) return GIPC_ERR_INVALID_ARG;
+    if (!ctx->built) return GIPC_ERR_STATE;
+    *info = ctx->info;
+    return GIPC_OK;
+}
+
+gipc_status gipc_bsr_pattern(const gipc_ctx* ctx, gipc_bsr* A) {
+    if (!ctx || !A) return GIPC_ERR_INVALID_ARG;
+    if (!ctx->built) return GIPC_ERR_STATE;
+    A->nbrows = ctx->V;
+    A->nnzb = ctx->nnzb;
+    A->row_ptr = static_cast<const int32_t*>(ctx->row_ptr.p);
+    A->col_idx = static_cast<const int32_t*>(ctx->col_idx.p);
+    return GIPC_OK;
+}
+
+static gipc_status eval_impl(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params, double* energy,
+                             double* grad, const double* diag, const gipc_bsr* A, bool assemble, void* stream) {
+    if (!ctx) return GIPC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    gipc_status st;
+    if ((st = check_device(ctx)) != GIPC_OK) return st;
+    if ((st = check_mesh(ctx, mesh)) != GIPC_OK) return st;
+    DevParams pm;
+    if ((st = to_dev_params(ctx, params, pm)) != GIPC_OK) return st;
+    if (!energy || (!grad && mesh->V > 0)) return fail(ctx, GIPC_ERR_INVALID_ARG, "energy or grad is NULL");
+    if (!ctx->built) return fail(ctx, GIPC_ERR_STATE, "gipc_pairs_build has not succeeded");
+    if (mesh->V != ctx->V) return fail(ctx, GIPC_ERR_STATE, "V = %d differs from the build (%d)", mesh->V, ctx->V);
+    if (assemble) {
+        if (!A || !A->val) return fail(ctx, GIPC_ERR_INVALID_ARG, "A or A->val is NULL");
+        if (A->dtype != GIPC_F64 && A->dtype != GIPC_F32) return fail(ctx, GIPC_ERR_INVALID_ARG, "bad dtype");
+        if (!same_pattern(ctx, A)) return fail(ctx, GIPC_ERR_STATE, "A is not the pattern of the last build");
+    }
+    hipStream_t s = S(stream);
+    const double* xr = mesh->x_rest ? mesh->x_rest : mesh->x;
+    const TypeRanges& tr = ctx->ranges;
+    const int64_t Ps = ctx->Ps, Pm = tr.off[8] - tr.off[FT_EEM];
+    const int64_t nparts = eval_num_parts(Ps);
+    CK(ensure(ctx->rec_main, sizeof(double) * 8 * (size_t)Ps), "alloc factors");
+    CK(ensure(ctx->rec_extra, sizeof(double) * 9 * (size_t)Pm), "alloc factors");
+    CK(ensure(ctx->e_part, sizeof(double) * (size_t)(nparts > 0 ? nparts : 1)), "alloc factors");
+    CK(launch_eval(as<int4>(ctx->st_vid), tr, mesh->x, xr, pm, as<double>(ctx->rec_main), as<double>(ctx->rec_extra),
+                   as<double>(ctx->e_part), s),
+       "pair eval");
+    CK(launch_energy_final(as<double>(ctx->e_part), nparts, energy, s), "energy");
+    const int64_t m0 = tr.off[FT_EEM];
+    CK(launch_rows_diag(assemble ? 3 : 1, ctx->V, as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr),
+                        as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra), m0, diag,
+                        grad, assemble ? A->val : nullptr, assemble ? A->dtype : 0, ctx->nnzb, s),
+       "gradient");
+    if (assemble)
+        CK(launch_offdiag(ctx->nnzb, as<int32_t>(ctx->slot_row), as<int32_t>(ctx->col_idx), as<int64_t>(ctx->cptr),
+                          as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra), m0,
+                          A->val, A->dtype, s),
+           "off-diagonal blocks");
+    ctx->evaluated = true;
+    return GIPC_OK;
+}
+
+gipc_status gipc_barrier_eval(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params, double* energy,
+                              double* grad, void* stream) {
+    return eval_impl(ctx, mesh, params, energy, grad, nullptr, nullptr, false, stream);
+}
+
+gipc_status gipc_eval_assemble(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params, double* energy,
+                               double* grad, const double* diag, const gipc_bsr* A, void* stream) {
+    return eval_impl(ctx, mesh, params, energy, grad, diag, A, true, stream);
+}
+
+gipc_status gipc_assemble_bsr(gipc_ctx* ctx, const double* diag, const gipc_bsr* A, void* stream) {
+    if (!ctx) return GIPC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    gipc_status st;
+    if ((st = check_device(ctx)) != GIPC_OK) return st;
+    if (!A || !A->val) return fail(ctx, GIPC_ERR_INVALID_ARG, "A or A->val is NULL");
+    if (A->dtype != GIPC_F64 && A->dtype != GIPC_F32) return fail(ctx, GIPC_ERR_INVALID_ARG, "bad dtype");
+    if (!ctx->built || !ctx->evaluated) return fail(ctx, GIPC_ERR_STATE, "build and eval must precede assembly");
+    if (!same_pattern(ctx, A)) return fail(ctx, GIPC_ERR_STATE, "A is not the pattern of the last build");
+    hipStream_t s = S(stream);
+    const int64_t m0 = ctx->ranges.off[FT_EEM];
+    CK(launch_rows_diag(2, ctx->V, as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr), as<uint32_t>(ctx->contrib),
+                        as<double>(ctx->rec_main), as<double>(ctx->rec_extra), m0, diag, nullptr, A->val, A->dtype,
+                        ctx->nnzb, s),
+       "diagonal blocks");
+    CK(launch_offdiag(ctx->nnzb, as<int32_t>(ctx->slot_row), as<int32_t>(ctx->col_idx), as<int64_t>(ctx->cptr),
+                      as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra), m0, A->val,
+                      A->dtype, s),
+       "off-diagonal blocks");
+    return GIPC_OK;
+}
+
+gipc_status gipc_bsr_spmv(const gipc_bsr* A, const void* x, void* y, void* stream) {
+    if (!A || A->nbrows < 0 || A->nnzb < 0) return GIPC_ERR_INVALID_ARG;
+    if (A->dtype != GIPC_F64 && A->dtype != GIPC_F32) return GIPC_ERR_INVALID_ARG;
+    if (A->nbrows > 0 && (!A->row_ptr || !x || !y)) return GIPC_ERR_INVALID_ARG;
+    if (A->nnzb > 0 && (!A->col_idx || !A->val)) return GIPC_ERR_INVALID_ARG;
+    if (launch_spmv(*A, x, y, S(stream)) != hipSuccess) return GIPC_ERR_HIP;
+    return GIPC_OK;
+}
+
+gipc_status gipc_pcg(gipc_ctx* ctx, const gipc_bsr* A, const double* b, double* x, double rtol, int32_t maxit,
+                     int32_t* iters, double* relres, void* stream) {
+    if (!ctx) return GIPC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    gipc_status st;
+    if ((st = check_device(ctx)) != GIPC_OK) return st;
+    if (!A || A->nbrows < 0 || A->nnzb < 0) return fail(ctx, GIPC_ERR_INVALID_ARG, "bad matrix");
+    if (A->dtype != GIPC_F64) return fail(ctx, GIPC_ERR_INVALID_ARG, "gipc_pcg needs an FP64 matrix");
+    if (A->nbrows > 0 && (!A->row_ptr || !A->col_idx || !A->val || !b || !x))
+        return fail(ctx, GIPC_ERR_INVALID_ARG, "NULL matrix or vector");
+    if (!(rtol >= 0.0) || maxit < 0) return fail(ctx, GIPC_ERR_INVALID_ARG, "rtol must be >= 0 and maxit >= 0");
+    int32_t it = 0;
+    double rr = 0.0;
+    int brk = 0;
+    if (A->nbrows > 0) CK(pcg_run(ctx, *A, b, x, rtol, maxit, &it, &rr, &brk, S(stream)), "pcg");
+    if (iters) *iters = it;
+    if (relres) *relres = rr;
+    if (brk) return fail(ctx, GIPC_ERR_BREAKDOWN, "p^T A p <= 0 at iteration %d", it);
+    if (rtol > 0.0 && rr > rtol) return GIPC_WARN_NOT_CONVERGED;
+    return GIPC_OK;
+}
+
+gipc_status gipc_pair_inspect(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params, int32_t* src,
+                              int32_t* type, int32_t* vid, double* energy, double* grad, double* hess,
+                              void* stream) {
+    if (!ctx) return GIPC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    gipc_status st;
+    if ((st = check_device(ctx)) != GIPC_OK) return st;
+    if (!ctx->built) return fail(ctx, GIPC_ERR_STATE, "no build");
+    if ((grad || hess) && !ctx->evaluated) return fail(ctx, GIPC_ERR_STATE, "grad / hess need an eval");
+    DevParams pm{};
+    const double *x = nullptr, *xr = nullptr;
+    if (energy) {
+        if ((st = check_mesh(ctx, mesh)) != GIPC_OK) return st;
+        if ((st = to_dev_params(ctx, params, pm)) != GIPC_OK) return st;
+        if (mesh->V != ctx->V) return fail(ctx, GIPC_ERR_STATE, "V differs from the build");
+        x = mesh->x;
+        xr = mesh->x_rest ? mesh->x_rest : mesh->x;
+    }
+    CK(launch_pair_inspect(as<int4>(ctx->st_vid), as<int32_t>(ctx->st_src), ctx->ranges, as<double>(ctx->rec_main),
+                           as<double>(ctx->rec_extra), x, xr, pm, src, type, vid, energy, grad, hess, S(stream)),
+       "pair inspect");
+    return GIPC_OK;
+}
+
+gipc_status gipc_copy(const void* src, void* dst, int64_t bytes, void* stream) {
+    if (bytes < 0 || (bytes > 0 && (!src || !dst))) return GIPC_ERR_INVALID_ARG;
+    if (launch_copy(src, dst, bytes, S(stream)) != hipSuccess) return GIPC_ERR_HIP;
+    return GIPC_OK;
+}
+
+}  // extern "C"

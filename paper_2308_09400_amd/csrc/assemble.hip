@@ -1,0 +1,204 @@
+// Numeric assembly by gathering (no floating-point atomics): every BSR block
+// sums its own contribution list, in the order fixed by the symbolic phase.
+//   block(v_i, v_j) += P22 g_i g_j^T + P12 (s_i g_j^T + g_i s_j^T) + P11 s_i s_j^T
+// with g_i = c_i w~ (slot i of grad f) and s_i = (-u, u, -v, v)_i (slot i of
+// grad sqrt(c), mollified pairs only).  The gradient of vertex r gathers
+// a2 g_i + a1 s_i over the contributions of its diagonal block, which are
+// exactly its incidences (i = j).
+#include "internal.hpp"
+
+namespace gipc {
+namespace {
+
+struct Slots {
+    d3 g;       // c_i w~
+    d3 s;       // grad sqrt(c) slot i
+};
+
+__device__ __forceinline__ double coef(const double* m, int i) {
+    return i < 3 ? m[i] : -(m[0] + m[1] + m[2]);
+}
+
+__device__ __forceinline__ d3 sq_slot(const double* x, int i) {
+    // (-u, u, -v, v)
+    double sg = (i & 1) ? 1.0 : -1.0;
+    return i < 2 ? mk(sg * x[0], sg * x[1], sg * x[2]) : mk(sg * x[3], sg * x[4], sg * x[5]);
+}
+
+__device__ __forceinline__ void add_outer(double* B, double s, d3 a, d3 b) {
+    B[0] += s * a.x * b.x; B[1] += s * a.x * b.y; B[2] += s * a.x * b.z;
+    B[3] += s * a.y * b.x; B[4] += s * a.y * b.y; B[5] += s * a.y * b.z;
+    B[6] += s * a.z * b.x; B[7] += s * a.z * b.y; B[8] += s * a.z * b.z;
+}
+
+// one local block (i, j) of pair k added to B
+__device__ __forceinline__ void add_block(double* B, const double* __restrict__ rec_main,
+                                          const double* __restrict__ rec_extra, int64_t m0, uint32_t k, int i, int j) {
+    const double* m = rec_main + 8 * (int64_t)k;
+    d3 wt = mk(m[3], m[4], m[5]);
+    d3 gi = coef(m, i) * wt, gj = coef(m, j) * wt;
+    add_outer(B, m[6], gi, gj);
+    if ((int64_t)k >= m0) {
+        const double* x = rec_extra + 9 * ((int64_t)k - m0);
+        d3 si = sq_slot(x, i), sj = sq_slot(x, j);
+        add_outer(B, x[6], si, sj);
+        add_outer(B, x[7], si, gj);
+        add_outer(B, x[7], gi, sj);
+    }
+}
+
+__device__ __forceinline__ void store_block(void* val, int dtype, int64_t nnzb, int64_t s, const double* B) {
+    if (dtype == GIPC_F64) {
+        double* v = static_cast<double*>(val);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) v[c * nnzb + s] = B[c];
+    } else {
+        float* v = static_cast<float*>(val);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) v[c * nnzb + s] = (float)B[c];
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_rows_diag(int mode, int32_t V, const int32_t* __restrict__ diag_slot,
+                                                      const int64_t* __restrict__ cptr,
+                                                      const uint32_t* __restrict__ contrib,
+                                                      const double* __restrict__ rec_main,
+                                                      const double* __restrict__ rec_extra, int64_t m0,
+                                                      const double* __restrict__ diag, double* __restrict__ grad,
+                                                      void* val, int dtype, int64_t nnzb) {
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r >= V) return;
+    const int32_t s = diag_slot[r];
+    const int64_t t0 = cptr[s], t1 = cptr[s + 1];
+    double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    d3 g = mk(0, 0, 0);
+    for (int64_t t = t0; t < t1; ++t) {
+        uint32_t code = contrib[t];
+        uint32_t k = code >> 4;
+        int i = (int)((code >> 2) & 3u);
+        if (mode & 1) {
+            const double* m = rec_main + 8 * (int64_t)k;
+            d3 gi = coef(m, i) * mk(m[3], m[4], m[5]);
+            g = g + m[7] * gi;
+            if ((int64_t)k >= m0) {
+                const double* x = rec_extra + 9 * ((int64_t)k - m0);
+                g = g + x[8] * sq_slot(x, i);
+            }
+        }
+        if (mode & 2) add_block(B, rec_main, rec_extra, m0, k, i, i);
+    }
+    if (mode & 1) {
+        grad[3 * r + 0] = g.x;
+        grad[3 * r + 1] = g.y;
+        grad[3 * r + 2] = g.z;
+    }
+    if (mode & 2) {
+        double dv = diag ? diag[r] : 0.0;
+        B[0] += dv; B[4] += dv; B[8] += dv;
+        store_block(val, dtype, nnzb, s, B);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_offdiag(int64_t nnzb, const int32_t* __restrict__ slot_row,
+                                                    const int32_t* __restrict__ col_idx,
+                                                    const int64_t* __restrict__ cptr,
+                                                    const uint32_t* __restrict__ contrib,
+                                                    const double* __restrict__ rec_main,
+                                                    const double* __restrict__ rec_extra, int64_t m0, void* val,
+                                                    int dtype) {
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= nnzb) return;
+    if (col_idx[s] == slot_row[s]) return;  // diagonal blocks: k_rows_diag
+    double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int64_t t0 = cptr[s], t1 = cptr[s + 1];
+    for (int64_t t = t0; t < t1; ++t) {
+        uint32_t code = contrib[t];
+        add_block(B, rec_main, rec_extra, m0, code >> 4, (int)((code >> 2) & 3u), (int)(code & 3u));
+    }
+    store_block(val, dtype, nnzb, s, B);
+}
+
+// Expanded per-pair view of the staged list and the stored factors.
+__global__ void __launch_bounds__(kBlock) k_pair_inspect(const int4* __restrict__ st_vid,
+                                                         const int32_t* __restrict__ st_src, TypeRanges tr,
+                                                         const double* __restrict__ rec_main,
+                                                         const double* __restrict__ rec_extra,
+                                                         const double* __restrict__ X, const double* __restrict__ XR,
+                                                         DevParams pm, int32_t* src, int32_t* type, int32_t* vid,
+                                                         double* energy, double* grad, double* hess) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= tr.off[8]) return;
+    const int ft = type_of(k, tr);
+    const int4 v4 = st_vid[k];
+    const int64_t m0 = tr.off[FT_EEM];
+    if (src) src[k] = st_src[k];
+    if (type) type[k] = ft;
+    if (vid) {
+        vid[4 * k + 0] = v4.x; vid[4 * k + 1] = v4.y; vid[4 * k + 2] = v4.z; vid[4 * k + 3] = v4.w;
+    }
+    if (energy) {
+        const int v[4] = {v4.x, v4.y, v4.z, v4.w};
+        PairFactors o;
+        eval_typed(ft, v, X, XR, pm, o);
+        energy[k] = o.E;
+    }
+    const int nv = ft_nverts(ft);
+    if (grad) {
+        const double* m = rec_main + 8 * k;
+        for (int i = 0; i < 4; ++i) {
+            d3 g = mk(0, 0, 0);
+            if (i < nv) {
+                g = m[7] * (coef(m, i) * mk(m[3], m[4], m[5]));
+                if (k >= m0) {
+                    const double* x = rec_extra + 9 * (k - m0);
+                    g = g + x[8] * sq_slot(x, i);
+                }
+            }
+            grad[12 * k + 3 * i + 0] = g.x;
+            grad[12 * k + 3 * i + 1] = g.y;
+            grad[12 * k + 3 * i + 2] = g.z;
+        }
+    }
+    if (hess) {
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                if (i < nv && j < nv) add_block(B, rec_main, rec_extra, m0, (uint32_t)k, i, j);
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) hess[144 * k + (3 * i + a) * 12 + 3 * j + b] = B[3 * a + b];
+            }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_rows_diag(int mode, int32_t V, const int32_t* diag_slot, const int64_t* cptr,
+                            const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t m0,
+                            const double* diag, double* grad, void* val, int dtype, int64_t nnzb, hipStream_t s) {
+    if (V == 0) return hipSuccess;
+    k_rows_diag<<<(unsigned)((V + kBlock - 1) / kBlock), kBlock, 0, s>>>(mode, V, diag_slot, cptr, contrib, rec_main,
+                                                                        rec_extra, m0, diag, grad, val, dtype, nnzb);
+    return hipGetLastError();
+}
+
+hipError_t launch_offdiag(int64_t nnzb, const int32_t* slot_row, const int32_t* col_idx, const int64_t* cptr,
+                          const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t m0,
+                          void* val, int dtype, hipStream_t s) {
+    if (nnzb == 0) return hipSuccess;
+    k_offdiag<<<(unsigned)((nnzb + kBlock - 1) / kBlock), kBlock, 0, s>>>(nnzb, slot_row, col_idx, cptr, contrib,
+                                                                         rec_main, rec_extra, m0, val, dtype);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_inspect(const int4* st_vid, const int32_t* st_src, TypeRanges tr, const double* rec_main,
+                               const double* rec_extra, const double* x, const double* xr, const DevParams& pm,
+                               int32_t* src, int32_t* type, int32_t* vid, double* energy, double* grad,
+                               double* hess, hipStream_t s) {
+    int64_t nb = (tr.off[8] + kBlock - 1) / kBlock;
+    if (nb == 0) return hipSuccess;
+    k_pair_inspect<<<(unsigned)nb, kBlock, 0, s>>>(st_vid, st_src, tr, rec_main, rec_extra, x, xr, pm, src, type, vid,
+                                                  energy, grad, hess);
+    return hipGetLastError();
+}
+
+}  // namespace gipc

@@ -1,0 +1,150 @@
+// Host-side internals shared by the translation units of libgipc: the
+// context, device buffers and the kernel launchers each .hip file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/gipc.h"
+#include "device_math.hpp"
+
+namespace gipc {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 waves of 64)
+constexpr int kScanItems = 8;        // elements per thread in the scans
+constexpr int kMaxRowPairs = 2048;   // pairs touching one vertex (LDS sort capacity, 64 KiB)
+
+// Grow-only device buffer.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+hipError_t ensure(DevBuf& b, size_t bytes);
+void release(DevBuf& b);
+
+template <typename T>
+inline T* as(DevBuf& b) { return static_cast<T*>(b.p); }
+
+// Ranges of staged pairs per sub-type: pairs of type t occupy [off[t], off[t+1]).
+struct TypeRanges {
+    int64_t off[9];
+};
+
+__device__ __forceinline__ int type_of(int64_t k, const TypeRanges& tr) {
+    int t = 1;
+    while (t < 7 && k >= tr.off[t + 1]) ++t;
+    return t;
+}
+
+__device__ __forceinline__ int vslot(const int4& v, int j) {
+    return j == 0 ? v.x : (j == 1 ? v.y : (j == 2 ? v.z : v.w));
+}
+
+// wave64 sum by a fixed butterfly, then the block's waves in order: the
+// result does not depend on scheduling
+__device__ __forceinline__ double block_sum(double v, double* lds /*[kBlock/64]*/) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kBlock / 64; ++w) s += lds[w];
+    __syncthreads();
+    return s;  // valid in thread 0
+}
+
+struct PcgScalars {  // device-resident scalars of the PCG loop
+    double rz, pq, rr, bb, alpha, beta, rtol2;
+    int iters, done, breakdown, maxit;
+};
+
+}  // namespace gipc
+
+struct gipc_ctx {
+    int device = 0;
+    std::string err;
+
+    // staging (per candidate)
+    gipc::DevBuf cand_ft, cand_vid, bcount, boff, counters;
+    // staged pairs, sorted by sub-type
+    gipc::DevBuf st_vid, st_src;
+    gipc::TypeRanges ranges{};
+    int64_t Ps = 0;
+    int32_t V = 0;
+    // symbolic
+    gipc::DevBuf deg, kcount, fill, inc_ptr, kptr, inc, contrib, kcol, ncols, row_ptr, col_idx, cptr, slot_row,
+        diag_slot, maxbuf;
+    int64_t nnzb = 0, K = 0;
+    int32_t max_deg = 0;
+    // factors of the last eval
+    gipc::DevBuf rec_main, rec_extra, e_part;
+    // PCG workspace
+    gipc::DevBuf r, z, p, q, minv, part, scal;
+    // scan scratch
+    gipc::DevBuf scan_tmp, scan_tmp2;
+
+    gipc_info info{};
+    bool built = false;
+    bool evaluated = false;
+};
+
+namespace gipc {
+
+// ---- scan.hip
+// out[i] = sum_{j<i} in[j] for i <= n (out has n+1 entries); *total_dev
+// (device int64, nullable) receives the sum without narrowing.
+// TIn: int32/int64, TOut: int32/int64.
+template <typename TIn, typename TOut>
+hipError_t exclusive_scan(const TIn* in, int64_t n, TOut* out, gipc_ctx* ctx, hipStream_t s,
+                          int64_t* total_dev = nullptr);
+hipError_t reduce_max_i32(const int32_t* in, int64_t n, int32_t* out_dev, hipStream_t s);
+
+// ---- stage.hip
+hipError_t launch_stage_classify(const int32_t* tuples, int64_t P, int32_t V, const double* x, const double* xr,
+                                 const DevParams& pm, uint8_t* ft, int4* vid, int32_t* bcount, int64_t* counters,
+                                 hipStream_t s);
+hipError_t launch_stage_scatter(const uint8_t* ft, const int4* vid, int64_t P, const int64_t* boff, int4* st_vid,
+                                int32_t* st_src, hipStream_t s);
+hipError_t launch_stage_offsets(const int64_t* boff, int64_t nb, int64_t* out, hipStream_t s);
+
+// ---- symbolic.hip
+hipError_t launch_sym_count(const int4* st_vid, TypeRanges tr, int32_t* deg, int32_t* kcount, hipStream_t s);
+hipError_t launch_sym_scatter(const int4* st_vid, TypeRanges tr, const int64_t* inc_ptr, int32_t* fill,
+                              uint32_t* inc, hipStream_t s);
+hipError_t launch_sym_rowsort(int32_t V, int32_t max_deg, const int64_t* inc_ptr, const uint32_t* inc,
+                              const int4* st_vid, TypeRanges tr, const int64_t* kptr, uint32_t* contrib,
+                              int32_t* kcol, int32_t* ncols, hipStream_t s);
+hipError_t launch_sym_fill(int32_t V, const int64_t* kptr, const int32_t* kcol, const int32_t* row_ptr,
+                           int32_t* col_idx, int64_t* cptr, int32_t* slot_row, int32_t* diag_slot, int64_t nnzb,
+                           hipStream_t s);
+
+// ---- eval.hip
+hipError_t launch_eval(const int4* st_vid, TypeRanges tr, const double* x, const double* xr, const DevParams& pm,
+                       double* rec_main, double* rec_extra, double* e_part, hipStream_t s);
+hipError_t launch_energy_final(const double* e_part, int64_t nparts, double* energy, hipStream_t s);
+int64_t eval_num_parts(int64_t Ps);
+
+// ---- assemble.hip
+// mode bit 1: gradient, bit 2: diagonal block values
+hipError_t launch_rows_diag(int mode, int32_t V, const int32_t* diag_slot, const int64_t* cptr,
+                            const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t m0,
+                            const double* diag, double* grad, void* val, int dtype, int64_t nnzb, hipStream_t s);
+hipError_t launch_offdiag(int64_t nnzb, const int32_t* slot_row, const int32_t* col_idx, const int64_t* cptr,
+                          const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t m0,
+                          void* val, int dtype, hipStream_t s);
+hipError_t launch_pair_inspect(const int4* st_vid, const int32_t* st_src, TypeRanges tr, const double* rec_main,
+                               const double* rec_extra, const double* x, const double* xr, const DevParams& pm,
+                               int32_t* src, int32_t* type, int32_t* vid, double* energy, double* grad,
+                               double* hess, hipStream_t s);
+
+// ---- solve.hip
+hipError_t launch_spmv(const gipc_bsr& A, const void* x, void* y, hipStream_t s);
+hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
+hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x, double rtol, int32_t maxit,
+                   int32_t* iters, double* relres, int* breakdown, hipStream_t s);
+
+}  // namespace gipc

@@ -1,0 +1,308 @@
+// BSR SpMV, block-Jacobi preconditioned CG and a plain copy kernel.
+//
+// SpMV: G = 8 lanes per block row; each lane walks every 8th block of the
+// row (component-major values, so the 8 lanes of a row read 8 consecutive
+// doubles of each component), gathers x[col] (24 bytes, mostly cache hits),
+// and the 8 partial 3-vectors are combined by a fixed xor-butterfly inside
+// the lane group.  Deterministic.
+//
+// PCG (Saad Alg. 9.1 with the inverse 3x3 diagonal blocks as
+// preconditioner, the paper's simple block preconditioner of Sec. 6.2):
+// every scalar (alpha, beta, residual norms, the stopping test) lives in
+// device memory, so an iteration is five kernel launches without host
+// round trips; the host polls the "done" flag every 16 iterations.
+#include "internal.hpp"
+
+namespace gipc {
+namespace {
+
+constexpr int kG = 8;  // lanes per block row
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_spmv(int32_t nrows, const int32_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ ci, const T* __restrict__ val,
+                                                 int64_t nnzb, const T* __restrict__ x, T* __restrict__ y,
+                                                 const T* __restrict__ dotv, double* __restrict__ part,
+                                                 const PcgScalars* __restrict__ sc) {
+    if (sc && sc->done) return;
+    __shared__ double lds[kBlock / 64];
+    const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t row = gt / kG;
+    const int lg = threadIdx.x % kG;
+    T a0 = 0, a1 = 0, a2 = 0;
+    if (row < nrows) {
+        const int32_t e = rp[row + 1];
+        for (int32_t s = rp[row] + lg; s < e; s += kG) {
+            const int64_t c = ci[s];
+            const T x0 = x[3 * c], x1 = x[3 * c + 1], x2 = x[3 * c + 2];
+            a0 += val[s] * x0 + val[nnzb + s] * x1 + val[2 * nnzb + s] * x2;
+            a1 += val[3 * nnzb + s] * x0 + val[4 * nnzb + s] * x1 + val[5 * nnzb + s] * x2;
+            a2 += val[6 * nnzb + s] * x0 + val[7 * nnzb + s] * x1 + val[8 * nnzb + s] * x2;
+        }
+    }
+#pragma unroll
+    for (int o = kG / 2; o > 0; o >>= 1) {
+        a0 += __shfl_xor(a0, o, kG);
+        a1 += __shfl_xor(a1, o, kG);
+        a2 += __shfl_xor(a2, o, kG);
+    }
+    double d = 0.0;
+    if (row < nrows && lg == 0) {
+        y[3 * row] = a0;
+        y[3 * row + 1] = a1;
+        y[3 * row + 2] = a2;
+        if (dotv) d = (double)dotv[3 * row] * a0 + (double)dotv[3 * row + 1] * a1 + (double)dotv[3 * row + 2] * a2;
+    }
+    if (part) {
+        d = block_sum(d, lds);
+        if (threadIdx.x == 0) part[blockIdx.x] = d;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        dst[i] = src[i];
+}
+
+__global__ void k_copy1(const uint8_t* __restrict__ src, uint8_t* __restrict__ dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------- PCG
+
+// inverse of each row's diagonal block (cofactors); identity if singular
+__global__ void __launch_bounds__(kBlock) k_bj_inverse(int32_t V, const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ ci, const double* __restrict__ val,
+                                                       int64_t nnzb, double* __restrict__ minv) {
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r >= V) return;
+    double A[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int32_t s = rp[r]; s < rp[r + 1]; ++s)
+        if (ci[s] == r) {
+            for (int c = 0; c < 9; ++c) A[c] = val[c * nnzb + s];
+            break;
+        }
+    double c00 = A[4] * A[8] - A[5] * A[7], c01 = A[5] * A[6] - A[3] * A[8], c02 = A[3] * A[7] - A[4] * A[6];
+    double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+    double* M = minv + 9 * r;
+    if (!(fabs(det) > 0.0) || !isfinite(det)) {
+        for (int c = 0; c < 9; ++c) M[c] = (c % 4 == 0) ? 1.0 : 0.0;
+        return;
+    }
+    double id = 1.0 / det;
+    M[0] = c00 * id; M[1] = (A[2] * A[7] - A[1] * A[8]) * id; M[2] = (A[1] * A[5] - A[2] * A[4]) * id;
+    M[3] = c01 * id; M[4] = (A[0] * A[8] - A[2] * A[6]) * id; M[5] = (A[2] * A[3] - A[0] * A[5]) * id;
+    M[6] = c02 * id; M[7] = (A[1] * A[6] - A[0] * A[7]) * id; M[8] = (A[0] * A[4] - A[1] * A[3]) * id;
+}
+
+__device__ __forceinline__ d3 apply3(const double* M, d3 v) {
+    return mk(M[0] * v.x + M[1] * v.y + M[2] * v.z, M[3] * v.x + M[4] * v.y + M[5] * v.z,
+              M[6] * v.x + M[7] * v.y + M[8] * v.z);
+}
+
+__device__ __forceinline__ d3 ldv(const double* a, int64_t r) { return mk(a[3 * r], a[3 * r + 1], a[3 * r + 2]); }
+__device__ __forceinline__ void stv(double* a, int64_t r, d3 v) {
+    a[3 * r] = v.x; a[3 * r + 1] = v.y; a[3 * r + 2] = v.z;
+}
+
+// r = b - q; z = M^-1 r; p = z; partial (r.z, r.r, b.b)
+__global__ void __launch_bounds__(kBlock) k_init(int32_t V, const double* __restrict__ b, const double* __restrict__ q,
+                                                 const double* __restrict__ minv, double* __restrict__ r,
+                                                 double* __restrict__ z, double* __restrict__ p,
+                                                 double* __restrict__ part) {
+    __shared__ double lds[kBlock / 64];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double rz = 0, rr = 0, bb = 0;
+    if (i < V) {
+        d3 bv = ldv(b, i), rv = bv - ldv(q, i);
+        d3 zv = apply3(minv + 9 * i, rv);
+        stv(r, i, rv); stv(z, i, zv); stv(p, i, zv);
+        rz = dot(rv, zv); rr = dot(rv, rv); bb = dot(bv, bv);
+    }
+    rz = block_sum(rz, lds);
+    rr = block_sum(rr, lds);
+    bb = block_sum(bb, lds);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = rz;
+        part[gridDim.x + blockIdx.x] = rr;
+        part[2 * gridDim.x + blockIdx.x] = bb;
+    }
+}
+
+__device__ __forceinline__ double sum_parts(const double* part, int64_t n, double* lds) {
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) s += part[i];
+    return block_sum(s, lds);
+}
+
+__global__ void __launch_bounds__(kBlock) k_init_finish(const double* __restrict__ part, int64_t nb, PcgScalars* sc,
+                                                        double rtol2, int maxit) {
+    __shared__ double lds[kBlock / 64];
+    double rz = sum_parts(part, nb, lds), rr = sum_parts(part + nb, nb, lds), bb = sum_parts(part + 2 * nb, nb, lds);
+    if (threadIdx.x == 0) {
+        sc->rz = rz; sc->rr = rr; sc->bb = bb; sc->rtol2 = rtol2;
+        sc->pq = 0; sc->alpha = 0; sc->beta = 0;
+        sc->iters = 0; sc->breakdown = 0; sc->maxit = maxit;
+        sc->done = (rr <= rtol2 * bb) || maxit <= 0;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_alpha(const double* __restrict__ part, int64_t nb, PcgScalars* sc) {
+    if (sc->done) return;
+    __shared__ double lds[kBlock / 64];
+    double pq = sum_parts(part, nb, lds);
+    if (threadIdx.x == 0) {
+        sc->pq = pq;
+        if (!(pq > 0.0)) {
+            sc->breakdown = 1;
+            sc->done = 1;
+        } else {
+            sc->alpha = sc->rz / pq;
+        }
+    }
+}
+
+// x += alpha p; r -= alpha q; z = M^-1 r; partial (r.z, r.r)
+__global__ void __launch_bounds__(kBlock) k_update(int32_t V, double* __restrict__ x, double* __restrict__ r,
+                                                   double* __restrict__ z, const double* __restrict__ p,
+                                                   const double* __restrict__ q, const double* __restrict__ minv,
+                                                   const PcgScalars* __restrict__ sc, double* __restrict__ part) {
+    if (sc->done) return;
+    __shared__ double lds[kBlock / 64];
+    const double al = sc->alpha;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double rz = 0, rr = 0;
+    if (i < V) {
+        d3 pv = ldv(p, i);
+        stv(x, i, ldv(x, i) + al * pv);
+        d3 rv = ldv(r, i) - al * ldv(q, i);
+        d3 zv = apply3(minv + 9 * i, rv);
+        stv(r, i, rv); stv(z, i, zv);
+        rz = dot(rv, zv); rr = dot(rv, rv);
+    }
+    rz = block_sum(rz, lds);
+    rr = block_sum(rr, lds);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = rz;
+        part[gridDim.x + blockIdx.x] = rr;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_beta(const double* __restrict__ part, int64_t nb, PcgScalars* sc) {
+    if (sc->done) return;
+    __shared__ double lds[kBlock / 64];
+    double rz = sum_parts(part, nb, lds), rr = sum_parts(part + nb, nb, lds);
+    if (threadIdx.x == 0) {
+        sc->beta = rz / sc->rz;
+        sc->rz = rz;
+        sc->rr = rr;
+        sc->iters += 1;
+        sc->done = (rr <= sc->rtol2 * sc->bb) || sc->iters >= sc->maxit;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_pupdate(int64_t n, const double* __restrict__ z, double* __restrict__ p,
+                                                    const PcgScalars* __restrict__ sc) {
+    if (sc->done) return;
+    const double be = sc->beta;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = z[i] + be * p[i];
+}
+
+}  // namespace
+
+hipError_t launch_spmv(const gipc_bsr& A, const void* x, void* y, hipStream_t s) {
+    if (A.nbrows == 0) return hipSuccess;
+    const int64_t threads = (int64_t)A.nbrows * kG;
+    const unsigned nb = (unsigned)((threads + kBlock - 1) / kBlock);
+    if (A.dtype == GIPC_F64)
+        k_spmv<double><<<nb, kBlock, 0, s>>>(A.nbrows, A.row_ptr, A.col_idx, static_cast<const double*>(A.val), A.nnzb,
+                                             static_cast<const double*>(x), static_cast<double*>(y), nullptr, nullptr,
+                                             nullptr);
+    else
+        k_spmv<float><<<nb, kBlock, 0, s>>>(A.nbrows, A.row_ptr, A.col_idx, static_cast<const float*>(A.val), A.nnzb,
+                                            static_cast<const float*>(x), static_cast<float*>(y), nullptr, nullptr,
+                                            nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s) {
+    if (bytes <= 0) return hipSuccess;
+    const bool aligned = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0;
+    int64_t n16 = aligned ? bytes / 16 : 0;
+    if (n16 > 0) {
+        int64_t blocks = (n16 + kBlock - 1) / kBlock;
+        if (blocks > 65536) blocks = 65536;
+        k_copy16<<<(unsigned)blocks, kBlock, 0, s>>>(static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
+    }
+    int64_t rest = bytes - 16 * n16;
+    if (rest > 0) {
+        int64_t blocks = (rest + kBlock - 1) / kBlock;
+        if (blocks > 65536) blocks = 65536;
+        k_copy1<<<(unsigned)blocks, kBlock, 0, s>>>(static_cast<const uint8_t*>(src) + 16 * n16,
+                                                    static_cast<uint8_t*>(dst) + 16 * n16, rest);
+    }
+    return hipGetLastError();
+}
+
+hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x, double rtol, int32_t maxit,
+                   int32_t* iters, double* relres, int* breakdown, hipStream_t s) {
+    const int32_t V = A.nbrows;
+    const int64_t n3 = 3 * (int64_t)V;
+    const int64_t nbv = (V + kBlock - 1) / kBlock;               // row-parallel kernels
+    const int64_t nbs = ((int64_t)V * kG + kBlock - 1) / kBlock;  // SpMV kernel
+    hipError_t e;
+#define GIPC_TRY(x)                         \
+    do {                                    \
+        if ((e = (x)) != hipSuccess) return e; \
+    } while (0)
+    GIPC_TRY(ensure(ctx->r, sizeof(double) * n3));
+    GIPC_TRY(ensure(ctx->z, sizeof(double) * n3));
+    GIPC_TRY(ensure(ctx->p, sizeof(double) * n3));
+    GIPC_TRY(ensure(ctx->q, sizeof(double) * n3));
+    GIPC_TRY(ensure(ctx->minv, sizeof(double) * 9 * (size_t)V));
+    GIPC_TRY(ensure(ctx->part, sizeof(double) * 3 * (size_t)(nbv > nbs ? nbv : nbs)));
+    GIPC_TRY(ensure(ctx->scal, sizeof(PcgScalars)));
+    double *r = as<double>(ctx->r), *z = as<double>(ctx->z), *p = as<double>(ctx->p), *q = as<double>(ctx->q);
+    double *minv = as<double>(ctx->minv), *part = as<double>(ctx->part);
+    PcgScalars* sc = as<PcgScalars>(ctx->scal);
+    const double* val = static_cast<const double*>(A.val);
+
+    k_bj_inverse<<<(unsigned)nbv, kBlock, 0, s>>>(V, A.row_ptr, A.col_idx, val, A.nnzb, minv);
+    k_spmv<double><<<(unsigned)nbs, kBlock, 0, s>>>(V, A.row_ptr, A.col_idx, val, A.nnzb, x, q, nullptr, nullptr,
+                                                    nullptr);
+    k_init<<<(unsigned)nbv, kBlock, 0, s>>>(V, b, q, minv, r, z, p, part);
+    k_init_finish<<<1, kBlock, 0, s>>>(part, nbv, sc, rtol * rtol, maxit);
+    GIPC_TRY(hipGetLastError());
+
+    PcgScalars hs{};
+    const int32_t chunk = rtol > 0.0 ? 16 : (maxit > 0 ? maxit : 1);
+    int32_t launched = 0;
+    while (launched < maxit) {
+        int32_t m = maxit - launched < chunk ? maxit - launched : chunk;
+        for (int32_t it = 0; it < m; ++it) {
+            k_spmv<double><<<(unsigned)nbs, kBlock, 0, s>>>(V, A.row_ptr, A.col_idx, val, A.nnzb, p, q, p, part, sc);
+            k_alpha<<<1, kBlock, 0, s>>>(part, nbs, sc);
+            k_update<<<(unsigned)nbv, kBlock, 0, s>>>(V, x, r, z, p, q, minv, sc, part);
+            k_beta<<<1, kBlock, 0, s>>>(part, nbv, sc);
+            k_pupdate<<<(unsigned)((n3 + kBlock - 1) / kBlock), kBlock, 0, s>>>(n3, z, p, sc);
+        }
+        GIPC_TRY(hipGetLastError());
+        launched += m;
+        GIPC_TRY(hipMemcpyAsync(&hs, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
+        GIPC_TRY(hipStreamSynchronize(s));
+        if (hs.done) break;
+    }
+    if (maxit <= 0) {
+        GIPC_TRY(hipMemcpyAsync(&hs, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
+        GIPC_TRY(hipStreamSynchronize(s));
+    }
+#undef GIPC_TRY
+    if (iters) *iters = hs.iters;
+    if (relres) *relres = hs.bb > 0.0 ? sqrt(hs.rr / hs.bb) : 0.0;
+    if (breakdown) *breakdown = hs.breakdown;
+    return hipSuccess;
+}
+
+}  // namespace gipc

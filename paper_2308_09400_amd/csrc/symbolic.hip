@@ -1,0 +1,209 @@
+// Symbolic assembly: the block pattern of diag + sum_k S_k^T H_k S_k (the
+// matrix decomposition of supplement Sec. 6 read in reverse: every local
+// block (i, j) of pair k lands in global block (v_i, v_j)).
+//
+//  1. incidence counts per vertex (integer atomics: counts are exact);
+//  2. exclusive scans -> per-vertex incidence and contribution offsets;
+//  3. incidence scatter (order inside a vertex is irrelevant: step 4 sorts);
+//  4. per block row, one workgroup builds the keys (column, k, i, j) of all
+//     local blocks landing in that row and sorts them in LDS (bitonic); the
+//     sorted codes are the row's contribution lists, grouped by column;
+//  5. scan of the per-row column counts -> row_ptr;
+//  6. per row, the column boundaries give col_idx and the start of each
+//     block's contribution list.
+// A contribution code is k << 4 | i << 2 | j (staged pair k, local block i, j).
+#include "internal.hpp"
+
+namespace gipc {
+namespace {
+
+__global__ void __launch_bounds__(kBlock) k_sym_count(const int4* __restrict__ st_vid, TypeRanges tr,
+                                                      int32_t* __restrict__ deg, int32_t* __restrict__ kcount) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= tr.off[8]) return;
+    const int nv = ft_nverts(type_of(k, tr));
+    const int4 v = st_vid[k];
+    for (int i = 0; i < nv; ++i) {
+        int vi = vslot(v, i);
+        atomicAdd(&deg[vi], 1);
+        atomicAdd(&kcount[vi], nv);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_sym_scatter(const int4* __restrict__ st_vid, TypeRanges tr,
+                                                        const int64_t* __restrict__ inc_ptr,
+                                                        int32_t* __restrict__ fill, uint32_t* __restrict__ inc) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= tr.off[8]) return;
+    const int nv = ft_nverts(type_of(k, tr));
+    const int4 v = st_vid[k];
+    for (int i = 0; i < nv; ++i) {
+        int vi = vslot(v, i);
+        int64_t pos = inc_ptr[vi] + atomicAdd(&fill[vi], 1);
+        inc[pos] = ((uint32_t)k << 2) | (uint32_t)i;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_sym_rowsort(const int64_t* __restrict__ inc_ptr,
+                                                        const uint32_t* __restrict__ inc,
+                                                        const int4* __restrict__ st_vid, TypeRanges tr,
+                                                        const int64_t* __restrict__ kptr,
+                                                        uint32_t* __restrict__ contrib, int32_t* __restrict__ kcol,
+                                                        int32_t* __restrict__ ncols) {
+    extern __shared__ unsigned long long keys[];
+    __shared__ int32_t cnt;
+    const int r = blockIdx.x;
+    const int64_t start = inc_ptr[r];
+    const int n = (int)(inc_ptr[r + 1] - start);
+    if (n == 0) {
+        if (threadIdx.x == 0) ncols[r] = 1;  // the diagonal block alone
+        return;
+    }
+    unsigned N = 1;
+    while (N < 4u * (unsigned)n) N <<= 1;
+    for (unsigned t = threadIdx.x; t < N; t += kBlock) keys[t] = ~0ull;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < n; t += kBlock) {
+        uint32_t code = inc[start + t];
+        uint32_t k = code >> 2, i = code & 3u;
+        int nv = ft_nverts(type_of(k, tr));
+        int4 v = st_vid[k];
+        for (int j = 0; j < nv; ++j)
+            keys[4 * t + j] = ((unsigned long long)(uint32_t)vslot(v, j) << 32) | (unsigned long long)((k << 4) | (i << 2) | (uint32_t)j);
+    }
+    __syncthreads();
+    // bitonic sort, ascending
+    for (unsigned kk = 2; kk <= N; kk <<= 1) {
+        for (unsigned j = kk >> 1; j > 0; j >>= 1) {
+            for (unsigned t = threadIdx.x; t < N / 2; t += kBlock) {
+                unsigned i = (t / j) * (2 * j) + (t % j), l = i + j;
+                unsigned long long a = keys[i], b = keys[l];
+                bool up = (i & kk) == 0;
+                if ((a > b) == up) {
+                    keys[i] = b;
+                    keys[l] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const int64_t base = kptr[r];
+    const int K = (int)(kptr[r + 1] - base);
+    int c = 0;
+    for (int t = threadIdx.x; t < K; t += kBlock) {
+        unsigned long long key = keys[t];
+        int col = (int)(key >> 32);
+        contrib[base + t] = (uint32_t)key;
+        kcol[base + t] = col;
+        if (t == 0 || (int)(keys[t - 1] >> 32) != col) ++c;
+    }
+    atomicAdd(&cnt, c);
+    __syncthreads();
+    if (threadIdx.x == 0) ncols[r] = cnt;
+}
+
+__device__ __forceinline__ int block_exscan_i32(int v, int* lds, int& total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int n = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += n;
+    }
+    if (lane == 63) lds[wid] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            int t = lds[w];
+            lds[w] = s;
+            s += t;
+        }
+        lds[kBlock / 64] = s;
+    }
+    __syncthreads();
+    int ex = lds[wid] + inc - v;
+    total = lds[kBlock / 64];
+    __syncthreads();
+    return ex;
+}
+
+__global__ void __launch_bounds__(kBlock) k_sym_fill(int32_t V, const int64_t* __restrict__ kptr,
+                                                     const int32_t* __restrict__ kcol,
+                                                     const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_idx,
+                                                     int64_t* __restrict__ cptr, int32_t* __restrict__ slot_row,
+                                                     int32_t* __restrict__ diag_slot, int64_t nnzb) {
+    __shared__ int lds[kBlock / 64 + 1];
+    const int r = blockIdx.x;
+    const int64_t base = kptr[r];
+    const int K = (int)(kptr[r + 1] - base);
+    const int rp = row_ptr[r];
+    if (threadIdx.x == 0 && r == V - 1) cptr[nnzb] = kptr[V];
+    if (K == 0) {
+        if (threadIdx.x == 0) {
+            col_idx[rp] = r;
+            cptr[rp] = base;
+            slot_row[rp] = r;
+            diag_slot[r] = rp;
+        }
+        return;
+    }
+    int carry = 0;
+    for (int c0 = 0; c0 < K; c0 += kBlock) {
+        const int t = c0 + threadIdx.x;
+        int flag = 0, col = -1;
+        if (t < K) {
+            col = kcol[base + t];
+            flag = (t == 0) || (kcol[base + t - 1] != col);
+        }
+        int tot;
+        int ex = block_exscan_i32(flag, lds, tot) + carry;
+        if (flag) {
+            int s = rp + ex;
+            col_idx[s] = col;
+            cptr[s] = base + t;
+            slot_row[s] = r;
+            if (col == r) diag_slot[r] = s;
+        }
+        carry += tot;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_sym_count(const int4* st_vid, TypeRanges tr, int32_t* deg, int32_t* kcount, hipStream_t s) {
+    int64_t nb = (tr.off[8] + kBlock - 1) / kBlock;
+    if (nb == 0) return hipSuccess;
+    k_sym_count<<<(unsigned)nb, kBlock, 0, s>>>(st_vid, tr, deg, kcount);
+    return hipGetLastError();
+}
+
+hipError_t launch_sym_scatter(const int4* st_vid, TypeRanges tr, const int64_t* inc_ptr, int32_t* fill,
+                              uint32_t* inc, hipStream_t s) {
+    int64_t nb = (tr.off[8] + kBlock - 1) / kBlock;
+    if (nb == 0) return hipSuccess;
+    k_sym_scatter<<<(unsigned)nb, kBlock, 0, s>>>(st_vid, tr, inc_ptr, fill, inc);
+    return hipGetLastError();
+}
+
+hipError_t launch_sym_rowsort(int32_t V, int32_t max_deg, const int64_t* inc_ptr, const uint32_t* inc,
+                              const int4* st_vid, TypeRanges tr, const int64_t* kptr, uint32_t* contrib,
+                              int32_t* kcol, int32_t* ncols, hipStream_t s) {
+    if (V == 0) return hipSuccess;
+    unsigned N = 64;
+    while (N < 4u * (unsigned)max_deg) N <<= 1;
+    size_t lds = sizeof(unsigned long long) * N;
+    k_sym_rowsort<<<(unsigned)V, kBlock, lds, s>>>(inc_ptr, inc, st_vid, tr, kptr, contrib, kcol, ncols);
+    return hipGetLastError();
+}
+
+hipError_t launch_sym_fill(int32_t V, const int64_t* kptr, const int32_t* kcol, const int32_t* row_ptr,
+                           int32_t* col_idx, int64_t* cptr, int32_t* slot_row, int32_t* diag_slot, int64_t nnzb,
+                           hipStream_t s) {
+    if (V == 0) return hipSuccess;
+    k_sym_fill<<<(unsigned)V, kBlock, 0, s>>>(V, kptr, kcol, row_ptr, col_idx, cptr, slot_row, diag_slot, nnzb);
+    return hipGetLastError();
+}
+
+}  // namespace gipc
