@@ -67,6 +67,8 @@ def lib():
                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), dp,
                                      vp, vp, vp, ctypes.POINTER(ctypes.c_int)]
         L.orc_pair_local.restype = ctypes.c_int
+        L.orc_num_threads.argtypes = []
+        L.orc_num_threads.restype = ctypes.c_int
         L.orc_stencil.argtypes = [vp, vp]
         L.orc_stencil.restype = ctypes.c_int
         L.orc_eval.argtypes = [i32, vp, vp, i64, vp, ctypes.POINTER(Params), ctypes.c_int, dp, vp, vp, vp, vp, vp, vp]
@@ -79,6 +81,10 @@ def lib():
         L.orc_pcg.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def barrier(g, dhat=1e-3, eq12=False):

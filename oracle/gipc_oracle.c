@@ -262,6 +262,14 @@ static int decode(const int32_t t[4], int32_t vid[4], int* kind) {
     return -1;
 }
 
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 int orc_stencil(const int32_t tuple[4], int32_t vid[4]) {
     int kind;
     return decode(tuple, vid, &kind);

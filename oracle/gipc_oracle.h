@@ -7,16 +7,13 @@
  * baseline leg of the benchmark may load it.
  *
  * Contact tuples use the paper's sign encoding (Sec. 6.2, "Data structures"):
- *   [a0, a1, b0, b1]          edge-edge candidate (a1 may be -(v+1): same)
- *   [-(p+1), t0, t1, t2]      point-triangle candidate
- *   [-(p+1), e0, e1, -1]      point-edge
- *   [-(p+1), q, -1, -1]       point-point
- *   [-(p+1), -(o+1), e0, -(e1+1)]    point-edge cut from a nearly parallel
- *                                     edge pair (o: p's edge partner)
- *   [-(p+1), -(o+1), -(q+1), -(r+1)] point-point cut from a nearly parallel
- *                                     edge pair (o, r: edge partners)
- * Candidates (the first two kinds) are classified by the constrained minimum
- * of Eq. 4 / Eq. 5; the typed kinds use their own distance directly.
+ *   [a0, a1, b0, b1]          edge-edge pair (a1 may be -(v+1): same pair)
+ *   [-(p+1), t0, t1, t2]      point-triangle pair
+ *   [-(p+1), e0, e1, -1]      point-edge pair
+ *   [-(p+1), q, -1, -1]       point-point pair
+ * Every pair's distance is the constrained minimum over its primitives
+ * (Eq. 4 / Eq. 5, point-edge as the segment sub-problem of Eq. 4).  The
+ * mollifier applies to the edge-edge kind.  Other sign patterns are rejected.
  */
 #ifndef GIPC_ORACLE_H
 #define GIPC_ORACLE_H
@@ -59,6 +56,9 @@ int orc_jacobi_eig(int n, const double* A, double* lam, double* vec);
 int orc_pair_local(const int32_t tuple[4], const double* xs, const double* xr, const orc_params* prm,
                    double* E, double* grad12, double* hess144, int* subtype, int* mollified, double* dist2,
                    double* innerH, double* innerHp, double* dbdJ, int* m_out);
+
+/* Number of OpenMP threads the scene-level functions use. */
+int orc_num_threads(void);
 
 /* Stencil of a tuple: returns the vertex count (2..4, or -1 if malformed);
  * vid[4] receives decoded vertex ids in slot order (-1 unused). */

@@ -198,10 +198,25 @@ __device__ __forceinline__ void barrier(double g, double dhat, int eq12, double&
 
 // Projection of the symmetric 2x2 [[A, B], [B, C]] onto its non-negative
 // eigenspace (spectral projector; no eigenvector division, stable at ties).
+// The entries of the mollified block differ by many orders of magnitude
+// (sqrt(c) and f scale J_22 and J_33 very differently), and the small
+// eigenvalue is the one that dominates after the change of basis, so both
+// eigenvalues are formed without cancellation: the larger-magnitude root as
+// m +- disc, the other as det / root, with det = AC - B^2 by Kahan's
+// fused difference of products.
 __device__ __forceinline__ void psd2(double A, double B, double C, double& P11, double& P12, double& P22) {
     double h = 0.5 * (A - C), m = 0.5 * (A + C);
     double disc = sqrt(h * h + B * B);
-    double mup = m + disc, mum = m - disc;
+    double bb = B * B;
+    double det = fma(A, C, -bb) + fma(-B, B, bb);
+    double mup, mum;
+    if (m >= 0.0) {
+        mup = m + disc;
+        mum = mup > 0.0 ? det / mup : m - disc;
+    } else {
+        mum = m - disc;
+        mup = det / mum;
+    }
     if (mum >= 0.0) {
         P11 = A; P12 = B; P22 = C;
         return;
