@@ -183,6 +183,23 @@ def main():
             "traffic": None,
         },
     }
+    # achievable bandwidth of a plain streaming copy with the library's own
+    # kernel (reference for the roofline fraction; also the calibration
+    # kernel for the HBM byte counters)
+    nbytes = 2 << 30
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    gp.copy(src, dst)
+    ce = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    for i in range(5):
+        ce[i].record(stream)
+        gp.copy(src, dst)
+    ce[5].record(stream)
+    torch.cuda.synchronize()
+    copy_ms = np.mean([ce[i].elapsed_time(ce[i + 1]) for i in range(5)])
+    out["copy_gbs"] = float(2 * nbytes / (copy_ms * 1e-3) / 1e9)
+    out["roofline"]["frac_of_copy"] = float(spmv_gbs / out["copy_gbs"])
+    del src, dst
     ctx.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_sample)
