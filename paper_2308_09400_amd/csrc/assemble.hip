@@ -10,11 +10,6 @@
 namespace gipc {
 namespace {
 
-struct Slots {
-    d3 g;       // c_i w~
-    d3 s;       // grad sqrt(c) slot i
-};
-
 __device__ __forceinline__ double coef(const double* m, int i) {
     return i < 3 ? m[i] : -(m[0] + m[1] + m[2]);
 }
@@ -59,6 +54,11 @@ __device__ __forceinline__ void store_block(void* val, int dtype, int64_t nnzb, 
     }
 }
 
+// kRowLanes lanes per block row: each lane sums every kRowLanes-th
+// contribution of the row's diagonal list, then a fixed xor butterfly
+// combines the lanes (same order on every run).
+constexpr int kRowLanes = 16;
+
 __global__ void __launch_bounds__(kBlock) k_rows_diag(int mode, int32_t V, const int32_t* __restrict__ diag_slot,
                                                       const int64_t* __restrict__ cptr,
                                                       const uint32_t* __restrict__ contrib,
@@ -66,27 +66,40 @@ __global__ void __launch_bounds__(kBlock) k_rows_diag(int mode, int32_t V, const
                                                       const double* __restrict__ rec_extra, int64_t m0,
                                                       const double* __restrict__ diag, double* __restrict__ grad,
                                                       void* val, int dtype, int64_t nnzb) {
-    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (r >= V) return;
-    const int32_t s = diag_slot[r];
-    const int64_t t0 = cptr[s], t1 = cptr[s + 1];
+    const int64_t r = (int64_t)blockIdx.x * (kBlock / kRowLanes) + threadIdx.x / kRowLanes;
+    const int lg = threadIdx.x % kRowLanes;
+    const bool valid = r < V;
     double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     d3 g = mk(0, 0, 0);
-    for (int64_t t = t0; t < t1; ++t) {
-        uint32_t code = contrib[t];
-        uint32_t k = code >> 4;
-        int i = (int)((code >> 2) & 3u);
-        if (mode & 1) {
-            const double* m = rec_main + 8 * (int64_t)k;
-            d3 gi = coef(m, i) * mk(m[3], m[4], m[5]);
-            g = g + m[7] * gi;
-            if ((int64_t)k >= m0) {
-                const double* x = rec_extra + 9 * ((int64_t)k - m0);
-                g = g + x[8] * sq_slot(x, i);
+    int32_t s = 0;
+    if (valid) {
+        s = diag_slot[r];
+        const int64_t t0 = cptr[s], t1 = cptr[s + 1];
+        for (int64_t t = t0 + lg; t < t1; t += kRowLanes) {
+            uint32_t code = contrib[t];
+            uint32_t k = code >> 4;
+            int i = (int)((code >> 2) & 3u);
+            if (mode & 1) {
+                const double* m = rec_main + 8 * (int64_t)k;
+                d3 gi = coef(m, i) * mk(m[3], m[4], m[5]);
+                g = g + m[7] * gi;
+                if ((int64_t)k >= m0) {
+                    const double* x = rec_extra + 9 * ((int64_t)k - m0);
+                    g = g + x[8] * sq_slot(x, i);
+                }
             }
+            if (mode & 2) add_block(B, rec_main, rec_extra, m0, k, i, i);
         }
-        if (mode & 2) add_block(B, rec_main, rec_extra, m0, k, i, i);
     }
+#pragma unroll
+    for (int o = kRowLanes / 2; o > 0; o >>= 1) {
+        g.x += __shfl_xor(g.x, o, kRowLanes);
+        g.y += __shfl_xor(g.y, o, kRowLanes);
+        g.z += __shfl_xor(g.z, o, kRowLanes);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) B[c] += __shfl_xor(B[c], o, kRowLanes);
+    }
+    if (!valid || lg != 0) return;
     if (mode & 1) {
         grad[3 * r + 0] = g.x;
         grad[3 * r + 1] = g.y;
@@ -176,8 +189,9 @@ hipError_t launch_rows_diag(int mode, int32_t V, const int32_t* diag_slot, const
                             const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t m0,
                             const double* diag, double* grad, void* val, int dtype, int64_t nnzb, hipStream_t s) {
     if (V == 0) return hipSuccess;
-    k_rows_diag<<<(unsigned)((V + kBlock - 1) / kBlock), kBlock, 0, s>>>(mode, V, diag_slot, cptr, contrib, rec_main,
-                                                                        rec_extra, m0, diag, grad, val, dtype, nnzb);
+    const int64_t nb = ((int64_t)V * kRowLanes + kBlock - 1) / kBlock;
+    k_rows_diag<<<(unsigned)nb, kBlock, 0, s>>>(mode, V, diag_slot, cptr, contrib, rec_main, rec_extra, m0, diag, grad,
+                                                val, dtype, nnzb);
     return hipGetLastError();
 }
 
@@ -185,8 +199,9 @@ hipError_t launch_offdiag(int64_t nnzb, const int32_t* slot_row, const int32_t* 
                           const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t m0,
                           void* val, int dtype, hipStream_t s) {
     if (nnzb == 0) return hipSuccess;
-    k_offdiag<<<(unsigned)((nnzb + kBlock - 1) / kBlock), kBlock, 0, s>>>(nnzb, slot_row, col_idx, cptr, contrib,
-                                                                         rec_main, rec_extra, m0, val, dtype);
+    const int64_t nb = (nnzb + kBlock - 1) / kBlock;
+    k_offdiag<<<(unsigned)nb, kBlock, 0, s>>>(nnzb, slot_row, col_idx, cptr, contrib, rec_main, rec_extra, m0, val,
+                                              dtype);
     return hipGetLastError();
 }
 

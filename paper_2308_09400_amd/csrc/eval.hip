@@ -43,8 +43,15 @@ __global__ void __launch_bounds__(kBlock) k_eval(const int4* __restrict__ st_vid
 __global__ void __launch_bounds__(kBlock) k_energy_final(const double* __restrict__ e_part, int64_t n,
                                                          double* __restrict__ energy) {
     __shared__ double lds[kBlock / 64];
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) s += e_part[i];
+    // 8 independent accumulators per lane keep loads in flight; fixed order
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t i = threadIdx.x;
+    for (; i + 7 * kBlock < n; i += 8 * kBlock) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] += e_part[i + u * kBlock];
+    }
+    for (int u = 0; i < n; i += kBlock, ++u) a[u & 7] += e_part[i];
+    double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     s = block_sum(s, lds);
     if (threadIdx.x == 0) *energy = s;
 }

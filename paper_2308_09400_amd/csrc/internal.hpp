@@ -60,6 +60,7 @@ __device__ __forceinline__ double block_sum(double v, double* lds /*[kBlock/64]*
 struct PcgScalars {  // device-resident scalars of the PCG loop
     double rz, pq, rr, bb, alpha, beta, rtol2;
     int iters, done, breakdown, maxit;
+    unsigned int ticket;  // arrivals of the current reduction (last block resets it)
 };
 
 }  // namespace gipc

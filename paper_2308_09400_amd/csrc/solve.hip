@@ -10,7 +10,8 @@
 // preconditioner, the paper's simple block preconditioner of Sec. 6.2):
 // every scalar (alpha, beta, residual norms, the stopping test) lives in
 // device memory, so an iteration is five kernel launches without host
-// round trips; the host polls the "done" flag every 16 iterations.
+// round trips; the host polls the "done" flag every 16 iterations (once
+// when rtol = 0).
 #include "internal.hpp"
 
 namespace gipc {
@@ -21,13 +22,8 @@ constexpr int kG = 8;  // lanes per block row
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_spmv(int32_t nrows, const int32_t* __restrict__ rp,
                                                  const int32_t* __restrict__ ci, const T* __restrict__ val,
-                                                 int64_t nnzb, const T* __restrict__ x, T* __restrict__ y,
-                                                 const T* __restrict__ dotv, double* __restrict__ part,
-                                                 const PcgScalars* __restrict__ sc) {
-    if (sc && sc->done) return;
-    __shared__ double lds[kBlock / 64];
-    const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t row = gt / kG;
+                                                 int64_t nnzb, const T* __restrict__ x, T* __restrict__ y) {
+    const int64_t row = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kG;
     const int lg = threadIdx.x % kG;
     T a0 = 0, a1 = 0, a2 = 0;
     if (row < nrows) {
@@ -46,22 +42,25 @@ __global__ void __launch_bounds__(kBlock) k_spmv(int32_t nrows, const int32_t* _
         a1 += __shfl_xor(a1, o, kG);
         a2 += __shfl_xor(a2, o, kG);
     }
-    double d = 0.0;
     if (row < nrows && lg == 0) {
         y[3 * row] = a0;
         y[3 * row + 1] = a1;
         y[3 * row + 2] = a2;
-        if (dotv) d = (double)dotv[3 * row] * a0 + (double)dotv[3 * row + 1] * a1 + (double)dotv[3 * row + 2] * a2;
-    }
-    if (part) {
-        d = block_sum(d, lds);
-        if (threadIdx.x == 0) part[blockIdx.x] = d;
     }
 }
 
+// streaming copy, 4 independent 16-byte loads in flight per lane
 __global__ void __launch_bounds__(kBlock) k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-        dst[i] = src[i];
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n; i += stride) dst[i] = src[i];
 }
 
 __global__ void k_copy1(const uint8_t* __restrict__ src, uint8_t* __restrict__ dst, int64_t n) {
@@ -70,6 +69,27 @@ __global__ void k_copy1(const uint8_t* __restrict__ src, uint8_t* __restrict__ d
 }
 
 // ---------------------------------------------------------------- PCG
+//
+// Per iteration: q = A p with per-workgroup partials of p.q; one workgroup
+// sums them in index order and forms alpha; the vector update writes
+// partials of r.z and r.r; one workgroup forms beta and the stopping test;
+// p = z + beta p.  Every kernel reads the device "done" flag first, so the
+// host can enqueue many iterations at once.  Sums are in a fixed order and
+// therefore bit-reproducible.
+
+// sum of part[0..n) by one workgroup: 8 independent accumulators per lane
+// (loads in flight), then a fixed combination and the block butterfly
+__device__ __forceinline__ double sum_parts(const double* __restrict__ part, int64_t n, double* lds) {
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t i = threadIdx.x;
+    for (; i + 7 * kBlock < n; i += 8 * kBlock) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] += part[i + u * kBlock];
+    }
+    for (int u = 0; i < n; i += kBlock, ++u) a[u & 7] += part[i];
+    double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    return block_sum(s, lds);
+}
 
 // inverse of each row's diagonal block (cofactors); identity if singular
 __global__ void __launch_bounds__(kBlock) k_bj_inverse(int32_t V, const int32_t* __restrict__ rp,
@@ -106,49 +126,43 @@ __device__ __forceinline__ void stv(double* a, int64_t r, d3 v) {
     a[3 * r] = v.x; a[3 * r + 1] = v.y; a[3 * r + 2] = v.z;
 }
 
-// r = b - q; z = M^-1 r; p = z; partial (r.z, r.r, b.b)
-__global__ void __launch_bounds__(kBlock) k_init(int32_t V, const double* __restrict__ b, const double* __restrict__ q,
-                                                 const double* __restrict__ minv, double* __restrict__ r,
-                                                 double* __restrict__ z, double* __restrict__ p,
-                                                 double* __restrict__ part) {
+// q = A p (kG lanes per row) and one partial of p.q per workgroup
+__global__ void __launch_bounds__(kBlock) k_pcg_spmv(int32_t nrows, const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ ci, const double* __restrict__ val,
+                                                     int64_t nnzb, const double* __restrict__ p,
+                                                     double* __restrict__ q, double* __restrict__ part,
+                                                     const PcgScalars* __restrict__ sc) {
+    if (sc->done) return;
     __shared__ double lds[kBlock / 64];
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    double rz = 0, rr = 0, bb = 0;
-    if (i < V) {
-        d3 bv = ldv(b, i), rv = bv - ldv(q, i);
-        d3 zv = apply3(minv + 9 * i, rv);
-        stv(r, i, rv); stv(z, i, zv); stv(p, i, zv);
-        rz = dot(rv, zv); rr = dot(rv, rv); bb = dot(bv, bv);
+    const int64_t row = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kG;
+    const int lg = threadIdx.x % kG;
+    double a0 = 0, a1 = 0, a2 = 0;
+    if (row < nrows) {
+        const int32_t e = rp[row + 1];
+        for (int32_t s = rp[row] + lg; s < e; s += kG) {
+            const int64_t c = ci[s];
+            const double x0 = p[3 * c], x1 = p[3 * c + 1], x2 = p[3 * c + 2];
+            a0 += val[s] * x0 + val[nnzb + s] * x1 + val[2 * nnzb + s] * x2;
+            a1 += val[3 * nnzb + s] * x0 + val[4 * nnzb + s] * x1 + val[5 * nnzb + s] * x2;
+            a2 += val[6 * nnzb + s] * x0 + val[7 * nnzb + s] * x1 + val[8 * nnzb + s] * x2;
+        }
     }
-    rz = block_sum(rz, lds);
-    rr = block_sum(rr, lds);
-    bb = block_sum(bb, lds);
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = rz;
-        part[gridDim.x + blockIdx.x] = rr;
-        part[2 * gridDim.x + blockIdx.x] = bb;
+#pragma unroll
+    for (int o = kG / 2; o > 0; o >>= 1) {
+        a0 += __shfl_xor(a0, o, kG);
+        a1 += __shfl_xor(a1, o, kG);
+        a2 += __shfl_xor(a2, o, kG);
     }
+    double d = 0.0;
+    if (row < nrows && lg == 0) {
+        stv(q, row, mk(a0, a1, a2));
+        d = p[3 * row] * a0 + p[3 * row + 1] * a1 + p[3 * row + 2] * a2;
+    }
+    d = block_sum(d, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = d;
 }
 
-__device__ __forceinline__ double sum_parts(const double* part, int64_t n, double* lds) {
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) s += part[i];
-    return block_sum(s, lds);
-}
-
-__global__ void __launch_bounds__(kBlock) k_init_finish(const double* __restrict__ part, int64_t nb, PcgScalars* sc,
-                                                        double rtol2, int maxit) {
-    __shared__ double lds[kBlock / 64];
-    double rz = sum_parts(part, nb, lds), rr = sum_parts(part + nb, nb, lds), bb = sum_parts(part + 2 * nb, nb, lds);
-    if (threadIdx.x == 0) {
-        sc->rz = rz; sc->rr = rr; sc->bb = bb; sc->rtol2 = rtol2;
-        sc->pq = 0; sc->alpha = 0; sc->beta = 0;
-        sc->iters = 0; sc->breakdown = 0; sc->maxit = maxit;
-        sc->done = (rr <= rtol2 * bb) || maxit <= 0;
-    }
-}
-
-__global__ void __launch_bounds__(kBlock) k_alpha(const double* __restrict__ part, int64_t nb, PcgScalars* sc) {
+__global__ void __launch_bounds__(kBlock) k_pcg_alpha(const double* __restrict__ part, int64_t nb, PcgScalars* sc) {
     if (sc->done) return;
     __shared__ double lds[kBlock / 64];
     double pq = sum_parts(part, nb, lds);
@@ -163,42 +177,64 @@ __global__ void __launch_bounds__(kBlock) k_alpha(const double* __restrict__ par
     }
 }
 
-// x += alpha p; r -= alpha q; z = M^-1 r; partial (r.z, r.r)
-__global__ void __launch_bounds__(kBlock) k_update(int32_t V, double* __restrict__ x, double* __restrict__ r,
-                                                   double* __restrict__ z, const double* __restrict__ p,
-                                                   const double* __restrict__ q, const double* __restrict__ minv,
-                                                   const PcgScalars* __restrict__ sc, double* __restrict__ part) {
-    if (sc->done) return;
+// first: r = b - q, z = M^-1 r, p = z, partials (r.z, r.r, b.b);
+// otherwise: x += alpha p, r -= alpha q, z = M^-1 r, partials (r.z, r.r)
+__global__ void __launch_bounds__(kBlock) k_pcg_update(int first, int32_t V, const double* __restrict__ b,
+                                                       double* __restrict__ x, double* __restrict__ r,
+                                                       double* __restrict__ z, double* __restrict__ p,
+                                                       const double* __restrict__ q, const double* __restrict__ minv,
+                                                       double* __restrict__ part, const PcgScalars* __restrict__ sc) {
+    if (!first && sc->done) return;
     __shared__ double lds[kBlock / 64];
-    const double al = sc->alpha;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    double rz = 0, rr = 0;
+    const double al = first ? 0.0 : sc->alpha;
+    double rz = 0, rr = 0, bb = 0;
     if (i < V) {
-        d3 pv = ldv(p, i);
-        stv(x, i, ldv(x, i) + al * pv);
-        d3 rv = ldv(r, i) - al * ldv(q, i);
+        d3 rv;
+        if (first) {
+            d3 bv = ldv(b, i);
+            rv = bv - ldv(q, i);
+            bb = dot(bv, bv);
+        } else {
+            stv(x, i, ldv(x, i) + al * ldv(p, i));
+            rv = ldv(r, i) - al * ldv(q, i);
+        }
         d3 zv = apply3(minv + 9 * i, rv);
-        stv(r, i, rv); stv(z, i, zv);
-        rz = dot(rv, zv); rr = dot(rv, rv);
+        stv(r, i, rv);
+        stv(z, i, zv);
+        if (first) stv(p, i, zv);
+        rz = dot(rv, zv);
+        rr = dot(rv, rv);
     }
     rz = block_sum(rz, lds);
     rr = block_sum(rr, lds);
+    if (first) bb = block_sum(bb, lds);
     if (threadIdx.x == 0) {
         part[blockIdx.x] = rz;
         part[gridDim.x + blockIdx.x] = rr;
+        part[2 * gridDim.x + blockIdx.x] = bb;
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_beta(const double* __restrict__ part, int64_t nb, PcgScalars* sc) {
-    if (sc->done) return;
+// first: initial scalars; otherwise beta, the new r.z and the stopping test
+__global__ void __launch_bounds__(kBlock) k_pcg_beta(int first, const double* __restrict__ part, int64_t nb,
+                                                     PcgScalars* sc, double rtol2, int maxit) {
+    if (!first && sc->done) return;
     __shared__ double lds[kBlock / 64];
-    double rz = sum_parts(part, nb, lds), rr = sum_parts(part + nb, nb, lds);
-    if (threadIdx.x == 0) {
-        sc->beta = rz / sc->rz;
-        sc->rz = rz;
-        sc->rr = rr;
+    const double RZ = sum_parts(part, nb, lds), RR = sum_parts(part + nb, nb, lds);
+    const double BB = first ? sum_parts(part + 2 * nb, nb, lds) : 0.0;
+    if (threadIdx.x != 0) return;
+    if (first) {
+        sc->rz = RZ; sc->rr = RR; sc->bb = BB; sc->rtol2 = rtol2;
+        sc->pq = 0; sc->alpha = 0; sc->beta = 0;
+        sc->iters = 0; sc->breakdown = 0; sc->maxit = maxit;
+        sc->done = (RR <= rtol2 * BB) || maxit <= 0;
+    } else {
+        sc->beta = RZ / sc->rz;
+        sc->rz = RZ;
+        sc->rr = RR;
         sc->iters += 1;
-        sc->done = (rr <= sc->rtol2 * sc->bb) || sc->iters >= sc->maxit;
+        sc->done = (RR <= sc->rtol2 * sc->bb) || sc->iters >= sc->maxit;
     }
 }
 
@@ -218,12 +254,10 @@ hipError_t launch_spmv(const gipc_bsr& A, const void* x, void* y, hipStream_t s)
     const unsigned nb = (unsigned)((threads + kBlock - 1) / kBlock);
     if (A.dtype == GIPC_F64)
         k_spmv<double><<<nb, kBlock, 0, s>>>(A.nbrows, A.row_ptr, A.col_idx, static_cast<const double*>(A.val), A.nnzb,
-                                             static_cast<const double*>(x), static_cast<double*>(y), nullptr, nullptr,
-                                             nullptr);
+                                             static_cast<const double*>(x), static_cast<double*>(y));
     else
         k_spmv<float><<<nb, kBlock, 0, s>>>(A.nbrows, A.row_ptr, A.col_idx, static_cast<const float*>(A.val), A.nnzb,
-                                            static_cast<const float*>(x), static_cast<float*>(y), nullptr, nullptr,
-                                            nullptr);
+                                            static_cast<const float*>(x), static_cast<float*>(y));
     return hipGetLastError();
 }
 
@@ -253,8 +287,8 @@ hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x,
     const int64_t nbv = (V + kBlock - 1) / kBlock;               // row-parallel kernels
     const int64_t nbs = ((int64_t)V * kG + kBlock - 1) / kBlock;  // SpMV kernel
     hipError_t e;
-#define GIPC_TRY(x)                         \
-    do {                                    \
+#define GIPC_TRY(x)                            \
+    do {                                       \
         if ((e = (x)) != hipSuccess) return e; \
     } while (0)
     GIPC_TRY(ensure(ctx->r, sizeof(double) * n3));
@@ -270,10 +304,9 @@ hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x,
     const double* val = static_cast<const double*>(A.val);
 
     k_bj_inverse<<<(unsigned)nbv, kBlock, 0, s>>>(V, A.row_ptr, A.col_idx, val, A.nnzb, minv);
-    k_spmv<double><<<(unsigned)nbs, kBlock, 0, s>>>(V, A.row_ptr, A.col_idx, val, A.nnzb, x, q, nullptr, nullptr,
-                                                    nullptr);
-    k_init<<<(unsigned)nbv, kBlock, 0, s>>>(V, b, q, minv, r, z, p, part);
-    k_init_finish<<<1, kBlock, 0, s>>>(part, nbv, sc, rtol * rtol, maxit);
+    GIPC_TRY(launch_spmv(A, x, q, s));
+    k_pcg_update<<<(unsigned)nbv, kBlock, 0, s>>>(1, V, b, x, r, z, p, q, minv, part, sc);
+    k_pcg_beta<<<1, kBlock, 0, s>>>(1, part, nbv, sc, rtol * rtol, maxit);
     GIPC_TRY(hipGetLastError());
 
     PcgScalars hs{};
@@ -282,10 +315,10 @@ hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x,
     while (launched < maxit) {
         int32_t m = maxit - launched < chunk ? maxit - launched : chunk;
         for (int32_t it = 0; it < m; ++it) {
-            k_spmv<double><<<(unsigned)nbs, kBlock, 0, s>>>(V, A.row_ptr, A.col_idx, val, A.nnzb, p, q, p, part, sc);
-            k_alpha<<<1, kBlock, 0, s>>>(part, nbs, sc);
-            k_update<<<(unsigned)nbv, kBlock, 0, s>>>(V, x, r, z, p, q, minv, sc, part);
-            k_beta<<<1, kBlock, 0, s>>>(part, nbv, sc);
+            k_pcg_spmv<<<(unsigned)nbs, kBlock, 0, s>>>(V, A.row_ptr, A.col_idx, val, A.nnzb, p, q, part, sc);
+            k_pcg_alpha<<<1, kBlock, 0, s>>>(part, nbs, sc);
+            k_pcg_update<<<(unsigned)nbv, kBlock, 0, s>>>(0, V, b, x, r, z, p, q, minv, part, sc);
+            k_pcg_beta<<<1, kBlock, 0, s>>>(0, part, nbv, sc, 0.0, 0);
             k_pupdate<<<(unsigned)((n3 + kBlock - 1) / kBlock), kBlock, 0, s>>>(n3, z, p, sc);
         }
         GIPC_TRY(hipGetLastError());

@@ -17,16 +17,47 @@
 namespace gipc {
 namespace {
 
+// Runs of equal keys in consecutive lanes share one atomic: the run head
+// (found with a wave ballot) adds the run length, and the members take
+// consecutive positions after the head's old value.  Staged pairs are sorted
+// by type and then by their first vertex, so slot-0 runs are long.
+struct WaveRun {
+    int head;  // lane of this lane's run head
+    int len;   // run length (valid in the head lane)
+};
+
+__device__ __forceinline__ WaveRun wave_run(int key, int key2, bool valid) {
+    const int lane = threadIdx.x & 63;
+    const int prev = __shfl_up(key, 1, 64);
+    const int prev2 = __shfl_up(key2, 1, 64);
+    const int prev_ok = __shfl_up((int)valid, 1, 64);
+    const bool head = valid && (lane == 0 || !prev_ok || prev != key || prev2 != key2);
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    WaveRun w;
+    w.head = 63 - __clzll(heads & le);
+    // a run ends at the next head or at the first invalid lane
+    const unsigned long long stop = (heads | ~__ballot(valid)) & ~le;
+    w.len = (stop ? __ffsll((long long)stop) - 1 : 64) - lane;
+    return w;
+}
+
 __global__ void __launch_bounds__(kBlock) k_sym_count(const int4* __restrict__ st_vid, TypeRanges tr,
                                                       int32_t* __restrict__ deg, int32_t* __restrict__ kcount) {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= tr.off[8]) return;
-    const int nv = ft_nverts(type_of(k, tr));
-    const int4 v = st_vid[k];
-    for (int i = 0; i < nv; ++i) {
-        int vi = vslot(v, i);
-        atomicAdd(&deg[vi], 1);
-        atomicAdd(&kcount[vi], nv);
+    const bool in = k < tr.off[8];
+    const int nv = in ? ft_nverts(type_of(k, tr)) : 0;
+    const int4 v = in ? st_vid[k] : make_int4(-1, -1, -1, -1);
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int vi = vslot(v, i);
+        const bool valid = i < nv;
+        WaveRun w = wave_run(valid ? vi : -1, nv, valid);
+        if (valid && w.head == lane) {
+            atomicAdd(&deg[vi], w.len);
+            atomicAdd(&kcount[vi], w.len * nv);
+        }
     }
 }
 
@@ -34,13 +65,19 @@ __global__ void __launch_bounds__(kBlock) k_sym_scatter(const int4* __restrict__
                                                         const int64_t* __restrict__ inc_ptr,
                                                         int32_t* __restrict__ fill, uint32_t* __restrict__ inc) {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= tr.off[8]) return;
-    const int nv = ft_nverts(type_of(k, tr));
-    const int4 v = st_vid[k];
-    for (int i = 0; i < nv; ++i) {
-        int vi = vslot(v, i);
-        int64_t pos = inc_ptr[vi] + atomicAdd(&fill[vi], 1);
-        inc[pos] = ((uint32_t)k << 2) | (uint32_t)i;
+    const bool in = k < tr.off[8];
+    const int nv = in ? ft_nverts(type_of(k, tr)) : 0;
+    const int4 v = in ? st_vid[k] : make_int4(-1, -1, -1, -1);
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int vi = vslot(v, i);
+        const bool valid = i < nv;
+        WaveRun w = wave_run(valid ? vi : -1, 0, valid);
+        int base = 0;
+        if (valid && w.head == lane) base = atomicAdd(&fill[vi], w.len);
+        base = __shfl(base, valid ? w.head : lane, 64);
+        if (valid) inc[inc_ptr[vi] + base + (lane - w.head)] = ((uint32_t)k << 2) | (uint32_t)i;
     }
 }
 
