@@ -50,6 +50,21 @@ static void cross3(const double* a, const double* b, double* o) {
     o[1] = a[2] * b[0] - a[0] * b[2];
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
+/* p*q - r*s within 1.5 ulp of the exact value (Kahan's difference of
+ * products: fma recovers the rounding error of r*s).  Used for the cross
+ * product that defines the parallelness c of Eq. 25: for edges parallel up to
+ * the rounding of their coordinates, the plain formula returns cancellation
+ * noise, and the direction of a x b sets grad sqrt(c) (Eq. 28-29). */
+static double diff_prod(double p, double q, double r, double s) {
+    double w = r * s;
+    double err = fma(-r, s, w);
+    return fma(p, q, -w) + err;
+}
+static void cross3_acc(const double* a, const double* b, double* o) {
+    o[0] = diff_prod(a[1], b[2], a[2], b[1]);
+    o[1] = diff_prod(a[2], b[0], a[0], b[2]);
+    o[2] = diff_prod(a[0], b[1], a[1], b[0]);
+}
 
 /* ---------------------------------------------------------------- scalars */
 
@@ -338,7 +353,7 @@ int orc_pair_local(const int32_t tuple[4], const double* xs, const double* xr, c
     memset(gsc, 0, sizeof(gsc));
     if (kind == K_EE && prm->mollify) {
         double a[3], b[3], n[3], ar[3], br[3];
-        sub3(X[1], X[0], a); sub3(X[3], X[2], b); cross3(a, b, n);
+        sub3(X[1], X[0], a); sub3(X[3], X[2], b); cross3_acc(a, b, n);
         cpar = dot3(n, n);
         const double* R = xr ? xr : xs;
         sub3(R + 3, R + 0, ar); sub3(R + 9, R + 6, br);

@@ -312,3 +312,40 @@ def copy(src, dst, nbytes=None, stream=None):
     if s != OK:
         raise GipcError(s, "gipc_copy failed")
     return dst
+
+
+class BarrierEnergy(torch.autograd.Function):
+    """Total barrier energy kappa * sum_k e_k b_k of the pairs staged in ``gctx``
+    as a differentiable function of the positions (Eq. 3, 24, 29).
+
+    ``forward`` runs the pair-evaluation and gradient kernels
+    (``gipc_barrier_eval``) and keeps the gradient; ``backward`` returns
+    ``grad_output * gradient`` -- no autograd graph is built through the
+    kernels.  The pairs must have been staged with ``pairs_build`` (their
+    sub-types stay fixed while x moves, as inside one Newton iteration).
+    """
+
+    @staticmethod
+    def forward(ctx, x, gctx, prm, x_rest=None):
+        E, g = barrier_eval(gctx, x.detach().contiguous(), prm, x_rest=x_rest)
+        ctx.save_for_backward(g)
+        return E
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g,) = ctx.saved_tensors
+        return grad_out * g, None, None, None
+
+
+def barrier_energy(x, gctx: Context, prm: Params, x_rest=None):
+    """Differentiable total barrier energy (see BarrierEnergy)."""
+    return BarrierEnergy.apply(x, gctx, prm, x_rest)
+
+
+def hvp(gctx: Context, x, prm: Params, v, x_rest=None, A: BsrMatrix | None = None):
+    """Product of the assembled proxy Hessian (Eq. 18-23, 32-36; no mass term)
+    at positions x with a direction v [V][3]: eval + BSR assembly + BSR SpMV.
+    Returns (Hv, A); pass A back in to reuse its value buffer."""
+    A = BsrMatrix(gctx) if A is None else A
+    eval_assemble(gctx, x, prm, A, diag=None, x_rest=x_rest)
+    return bsr_spmv(A, v.contiguous()), A

@@ -169,7 +169,7 @@ void gipc_ctx_destroy(gipc_ctx* ctx) {
                       &ctx->st_src, &ctx->deg, &ctx->kcount, &ctx->fill, &ctx->inc_ptr, &ctx->kptr, &ctx->inc,
                       &ctx->contrib, &ctx->kcol, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
                       &ctx->slot_row, &ctx->diag_slot, &ctx->maxbuf, &ctx->rec_main, &ctx->rec_extra, &ctx->e_part,
-                      &ctx->r, &ctx->z, &ctx->p, &ctx->q, &ctx->minv, &ctx->part, &ctx->scal, &ctx->scan_tmp,
+                      &ctx->r, &ctx->z, &ctx->p, &ctx->q, &ctx->p32, &ctx->minv, &ctx->part, &ctx->scal, &ctx->scan_tmp,
                       &ctx->scan_tmp2};
     for (DevBuf* b : bufs) release(*b);
     if (prev >= 0) (void)hipSetDevice(prev);
@@ -412,7 +412,7 @@ gipc_status gipc_pcg(gipc_ctx* ctx, const gipc_bsr* A, const double* b, double* 
     gipc_status st;
     if ((st = check_device(ctx)) != GIPC_OK) return st;
     if (!A || A->nbrows < 0 || A->nnzb < 0) return fail(ctx, GIPC_ERR_INVALID_ARG, "bad matrix");
-    if (A->dtype != GIPC_F64) return fail(ctx, GIPC_ERR_INVALID_ARG, "gipc_pcg needs an FP64 matrix");
+    if (A->dtype != GIPC_F64 && A->dtype != GIPC_F32) return fail(ctx, GIPC_ERR_INVALID_ARG, "bad dtype");
     if (A->nbrows > 0 && (!A->row_ptr || !A->col_idx || !A->val || !b || !x))
         return fail(ctx, GIPC_ERR_INVALID_ARG, "NULL matrix or vector");
     if (!(rtol >= 0.0) || maxit < 0) return fail(ctx, GIPC_ERR_INVALID_ARG, "rtol must be >= 0 and maxit >= 0");

@@ -58,6 +58,19 @@ __device__ __forceinline__ double dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y
 __device__ __forceinline__ d3 cross(d3 a, d3 b) {
     return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
+// p*q - r*s within 1.5 ulp of the exact value (Kahan's difference of
+// products; the fma recovers the rounding error of r*s).  The parallelness
+// c of Eq. 25 uses it: for edges that are parallel up to the rounding of
+// their coordinates the plain cross product is cancellation noise, and its
+// direction sets grad sqrt(c), so n must be a function of the input alone.
+__device__ __forceinline__ double diff_prod(double p, double q, double r, double s) {
+    double w = __dmul_rn(r, s);
+    double err = fma(-r, s, w);
+    return __dadd_rn(fma(p, q, -w), err);
+}
+__device__ __forceinline__ d3 cross_acc(d3 a, d3 b) {
+    return mk(diff_prod(a.y, b.z, a.z, b.y), diff_prod(a.z, b.x, a.x, b.z), diff_prod(a.x, b.y, a.y, b.x));
+}
 __device__ __forceinline__ d3 ld3(const double* __restrict__ X, int v) {
     const double* q = X + 3ll * v;
     return mk(q[0], q[1], q[2]);
@@ -311,7 +324,7 @@ __device__ inline void eval_typed(int ft, const int* v, const double* __restrict
     double e = 1.0, de = 0.0, d2e = 0.0, cpar = 0.0, sc = 0.0;
     if (ft >= FT_EEM && pm.mollify) {
         d3 A = ld3(X, v[1]) - ld3(X, v[0]), B = ld3(X, v[3]) - ld3(X, v[2]);
-        d3 n = cross(A, B);
+        d3 n = cross_acc(A, B);
         cpar = dot(n, n);
         double ex = eps_x(XR, v[0], v[1], v[2], v[3], pm.epsx_ratio);
         if (cpar < ex) {

@@ -60,7 +60,6 @@ __device__ __forceinline__ double block_sum(double v, double* lds /*[kBlock/64]*
 struct PcgScalars {  // device-resident scalars of the PCG loop
     double rz, pq, rr, bb, alpha, beta, rtol2;
     int iters, done, breakdown, maxit;
-    unsigned int ticket;  // arrivals of the current reduction (last block resets it)
 };
 
 }  // namespace gipc
@@ -84,7 +83,7 @@ struct gipc_ctx {
     // factors of the last eval
     gipc::DevBuf rec_main, rec_extra, e_part;
     // PCG workspace
-    gipc::DevBuf r, z, p, q, minv, part, scal;
+    gipc::DevBuf r, z, p, q, p32, minv, part, scal;
     // scan scratch
     gipc::DevBuf scan_tmp, scan_tmp2;
 

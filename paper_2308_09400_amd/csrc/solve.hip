@@ -91,16 +91,17 @@ __device__ __forceinline__ double sum_parts(const double* __restrict__ part, int
     return block_sum(s, lds);
 }
 
-// inverse of each row's diagonal block (cofactors); identity if singular
+// inverse of each row's diagonal block (cofactors, FP64); identity if singular
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_bj_inverse(int32_t V, const int32_t* __restrict__ rp,
-                                                       const int32_t* __restrict__ ci, const double* __restrict__ val,
+                                                       const int32_t* __restrict__ ci, const T* __restrict__ val,
                                                        int64_t nnzb, double* __restrict__ minv) {
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (r >= V) return;
     double A[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int32_t s = rp[r]; s < rp[r + 1]; ++s)
         if (ci[s] == r) {
-            for (int c = 0; c < 9; ++c) A[c] = val[c * nnzb + s];
+            for (int c = 0; c < 9; ++c) A[c] = (double)val[c * nnzb + s];
             break;
         }
     double c00 = A[4] * A[8] - A[5] * A[7], c01 = A[5] * A[6] - A[3] * A[8], c02 = A[3] * A[7] - A[4] * A[6];
@@ -126,22 +127,25 @@ __device__ __forceinline__ void stv(double* a, int64_t r, d3 v) {
     a[3 * r] = v.x; a[3 * r + 1] = v.y; a[3 * r + 2] = v.z;
 }
 
-// q = A p (kG lanes per row) and one partial of p.q per workgroup
+// q = A p (kG lanes per row) and one partial of p.q per workgroup.  T is
+// the matrix type: for FP32 matrices the product runs in FP32 on the FP32
+// copy pm of p and is widened to FP64 when stored; the dot is FP64.
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_pcg_spmv(int32_t nrows, const int32_t* __restrict__ rp,
-                                                     const int32_t* __restrict__ ci, const double* __restrict__ val,
-                                                     int64_t nnzb, const double* __restrict__ p,
-                                                     double* __restrict__ q, double* __restrict__ part,
-                                                     const PcgScalars* __restrict__ sc) {
+                                                     const int32_t* __restrict__ ci, const T* __restrict__ val,
+                                                     int64_t nnzb, const T* __restrict__ pm,
+                                                     const double* __restrict__ p, double* __restrict__ q,
+                                                     double* __restrict__ part, const PcgScalars* __restrict__ sc) {
     if (sc->done) return;
     __shared__ double lds[kBlock / 64];
     const int64_t row = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kG;
     const int lg = threadIdx.x % kG;
-    double a0 = 0, a1 = 0, a2 = 0;
+    T a0 = 0, a1 = 0, a2 = 0;
     if (row < nrows) {
         const int32_t e = rp[row + 1];
         for (int32_t s = rp[row] + lg; s < e; s += kG) {
             const int64_t c = ci[s];
-            const double x0 = p[3 * c], x1 = p[3 * c + 1], x2 = p[3 * c + 2];
+            const T x0 = pm[3 * c], x1 = pm[3 * c + 1], x2 = pm[3 * c + 2];
             a0 += val[s] * x0 + val[nnzb + s] * x1 + val[2 * nnzb + s] * x2;
             a1 += val[3 * nnzb + s] * x0 + val[4 * nnzb + s] * x1 + val[5 * nnzb + s] * x2;
             a2 += val[6 * nnzb + s] * x0 + val[7 * nnzb + s] * x1 + val[8 * nnzb + s] * x2;
@@ -155,8 +159,9 @@ __global__ void __launch_bounds__(kBlock) k_pcg_spmv(int32_t nrows, const int32_
     }
     double d = 0.0;
     if (row < nrows && lg == 0) {
-        stv(q, row, mk(a0, a1, a2));
-        d = p[3 * row] * a0 + p[3 * row + 1] * a1 + p[3 * row + 2] * a2;
+        const d3 qv = mk((double)a0, (double)a1, (double)a2);
+        stv(q, row, qv);
+        d = dot(ldv(p, row), qv);
     }
     d = block_sum(d, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = d;
@@ -238,12 +243,19 @@ __global__ void __launch_bounds__(kBlock) k_pcg_beta(int first, const double* __
     }
 }
 
+// p = z + beta p (beta = 0 and z = p on the first call: plain copy), and
+// the FP32 copy of p when the matrix is FP32
 __global__ void __launch_bounds__(kBlock) k_pupdate(int64_t n, const double* __restrict__ z, double* __restrict__ p,
-                                                    const PcgScalars* __restrict__ sc) {
-    if (sc->done) return;
-    const double be = sc->beta;
+                                                    float* __restrict__ p32, const PcgScalars* __restrict__ sc,
+                                                    int first) {
+    if (!first && sc->done) return;
+    const double be = first ? 0.0 : sc->beta;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) p[i] = z[i] + be * p[i];
+    if (i < n) {
+        const double v = first ? p[i] : z[i] + be * p[i];
+        p[i] = v;
+        if (p32) p32[i] = (float)v;
+    }
 }
 
 }  // namespace
@@ -298,15 +310,30 @@ hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x,
     GIPC_TRY(ensure(ctx->minv, sizeof(double) * 9 * (size_t)V));
     GIPC_TRY(ensure(ctx->part, sizeof(double) * 3 * (size_t)(nbv > nbs ? nbv : nbs)));
     GIPC_TRY(ensure(ctx->scal, sizeof(PcgScalars)));
+    const bool f32 = A.dtype == GIPC_F32;
+    if (f32) GIPC_TRY(ensure(ctx->p32, sizeof(float) * n3));
     double *r = as<double>(ctx->r), *z = as<double>(ctx->z), *p = as<double>(ctx->p), *q = as<double>(ctx->q);
     double *minv = as<double>(ctx->minv), *part = as<double>(ctx->part);
+    float* p32 = f32 ? as<float>(ctx->p32) : nullptr;
     PcgScalars* sc = as<PcgScalars>(ctx->scal);
-    const double* val = static_cast<const double*>(A.val);
+    const unsigned nbn = (unsigned)((n3 + kBlock - 1) / kBlock);
 
-    k_bj_inverse<<<(unsigned)nbv, kBlock, 0, s>>>(V, A.row_ptr, A.col_idx, val, A.nnzb, minv);
-    GIPC_TRY(launch_spmv(A, x, q, s));
+    GIPC_TRY(hipMemsetAsync(sc, 0, sizeof(PcgScalars), s));
+    // r = b - A x0 (for FP32 matrices through an FP32 copy of x0)
+    if (f32) {
+        k_bj_inverse<float><<<(unsigned)nbv, kBlock, 0, s>>>(V, A.row_ptr, A.col_idx,
+                                                             static_cast<const float*>(A.val), A.nnzb, minv);
+        k_pupdate<<<nbn, kBlock, 0, s>>>(n3, nullptr, x, p32, sc, 1);  // FP32 copy of x0 in p32
+        k_pcg_spmv<float><<<(unsigned)nbs, kBlock, 0, s>>>(V, A.row_ptr, A.col_idx, static_cast<const float*>(A.val),
+                                                           A.nnzb, p32, x, q, part, sc);
+    } else {
+        k_bj_inverse<double><<<(unsigned)nbv, kBlock, 0, s>>>(V, A.row_ptr, A.col_idx,
+                                                              static_cast<const double*>(A.val), A.nnzb, minv);
+        GIPC_TRY(launch_spmv(A, x, q, s));
+    }
     k_pcg_update<<<(unsigned)nbv, kBlock, 0, s>>>(1, V, b, x, r, z, p, q, minv, part, sc);
     k_pcg_beta<<<1, kBlock, 0, s>>>(1, part, nbv, sc, rtol * rtol, maxit);
+    if (f32) k_pupdate<<<nbn, kBlock, 0, s>>>(n3, z, p, p32, sc, 1);  // FP32 copy of p0
     GIPC_TRY(hipGetLastError());
 
     PcgScalars hs{};
@@ -315,11 +342,16 @@ hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x,
     while (launched < maxit) {
         int32_t m = maxit - launched < chunk ? maxit - launched : chunk;
         for (int32_t it = 0; it < m; ++it) {
-            k_pcg_spmv<<<(unsigned)nbs, kBlock, 0, s>>>(V, A.row_ptr, A.col_idx, val, A.nnzb, p, q, part, sc);
+            if (f32)
+                k_pcg_spmv<float><<<(unsigned)nbs, kBlock, 0, s>>>(
+                    V, A.row_ptr, A.col_idx, static_cast<const float*>(A.val), A.nnzb, p32, p, q, part, sc);
+            else
+                k_pcg_spmv<double><<<(unsigned)nbs, kBlock, 0, s>>>(
+                    V, A.row_ptr, A.col_idx, static_cast<const double*>(A.val), A.nnzb, p, p, q, part, sc);
             k_pcg_alpha<<<1, kBlock, 0, s>>>(part, nbs, sc);
             k_pcg_update<<<(unsigned)nbv, kBlock, 0, s>>>(0, V, b, x, r, z, p, q, minv, part, sc);
             k_pcg_beta<<<1, kBlock, 0, s>>>(0, part, nbv, sc, 0.0, 0);
-            k_pupdate<<<(unsigned)((n3 + kBlock - 1) / kBlock), kBlock, 0, s>>>(n3, z, p, sc);
+            k_pupdate<<<nbn, kBlock, 0, s>>>(n3, z, p, p32, sc, 0);
         }
         GIPC_TRY(hipGetLastError());
         launched += m;

@@ -212,3 +212,59 @@ def subsample(scene: Scene, n_pairs: int, seed: int = 0) -> np.ndarray:
         return scene.tuples.copy()
     idx = np.sort(rng.choice(scene.P, size=n_pairs, replace=False))
     return scene.tuples[idx].copy()
+
+
+def cube_surface_topology(n: int):
+    """Boundary triangles and edges of an ``n x n x n`` vertex grid (vertex
+    (i, j, k) -> index (i*n + j)*n + k); each boundary quad is split along a
+    diagonal.  Interior vertices stay in the vertex set (they touch no
+    boundary primitive)."""
+    idx = np.arange(n ** 3).reshape(n, n, n)
+    tris = []
+    for axis in range(3):
+        for side in (0, n - 1):
+            face = np.take(idx, side, axis=axis)           # n x n grid of that face
+            a = face[:-1, :-1].ravel(); b = face[:-1, 1:].ravel()
+            c = face[1:, 1:].ravel(); d = face[1:, :-1].ravel()
+            tris.append(np.stack([a, b, c], 1))
+            tris.append(np.stack([a, c, d], 1))
+    tris = np.concatenate(tris).astype(np.int32)
+    e = np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [2, 0]]])
+    e = np.sort(e, axis=1)
+    edges = np.unique(e, axis=0).astype(np.int32)
+    return tris, edges
+
+
+def cube_lattice(m: int = 6, n: int = 10, dhat: float = 1e-3, kappa: float = 1e4, seed: int = 3,
+                 gap_lo: float = 0.1, gap_hi: float = 0.9, with_pairs: bool = True) -> Scene:
+    """An ``m x m x m`` lattice of unit cubes with ``n^3`` vertices each (spacing
+    1/(n-1)).  The gap across each lattice plane (m-1 planes per axis) is drawn
+    uniformly from ``(gap_lo, gap_hi) * dhat``, so facing faces are parallel and
+    aligned.  ``x_rest`` = x (the gaps are part of the rest configuration)."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.uniform(gap_lo, gap_hi, size=(3, m - 1)) * dhat
+    offs = np.zeros((3, m))
+    for ax in range(3):
+        offs[ax, 1:] = np.arange(1, m) * 1.0 + np.cumsum(gaps[ax])
+    u = np.linspace(0.0, 1.0, n)
+    gx, gy, gz = np.meshgrid(u, u, u, indexing="ij")
+    local = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], 1)
+    tris1, edges1 = cube_surface_topology(n)
+    nv = n ** 3
+    xs, tris, edges, vobj = [], [], [], []
+    c = 0
+    for i in range(m):
+        for j in range(m):
+            for k in range(m):
+                xs.append(local + np.array([offs[0, i], offs[1, j], offs[2, k]]))
+                tris.append(tris1 + c * nv)
+                edges.append(edges1 + c * nv)
+                vobj.append(np.full(nv, c, dtype=np.int32))
+                c += 1
+    x = np.concatenate(xs)
+    tris = np.concatenate(tris).astype(np.int32)
+    edges = np.concatenate(edges).astype(np.int32)
+    vobj = np.concatenate(vobj)
+    tuples = broadphase(x, vobj, tris, edges, dhat) if with_pairs else np.zeros((0, 4), np.int32)
+    return Scene(f"cube_lattice_{m}x{n}", x, x.copy(), tris, edges, vobj, dhat, kappa, tuples,
+                 meta=dict(m=m, n=n, seed=seed, gaps=gaps))

@@ -194,6 +194,26 @@ def test_mollified_pair_with_scale_separated_inner_block(gp):
     gpu["ctx"].close()
 
 
+def test_rounding_level_parallel_edges(gp):
+    # Facing diagonals of a cube lattice: |a x b| = 4.9e-32 for the rounded
+    # coordinates while the plain product formula gives 0.  The mollifier
+    # term along grad sqrt(c) carries the whole proxy Hessian, so both sides
+    # must take c from the input alone.
+    x = np.array([[1.7779462971114925, 1.0, 1.1118521306832763],
+                  [1.8890574082226037, 1.0, 1.2229632417943872],
+                  [1.8890574082226037, 1.000289448405277, 1.2229632417943872],
+                  [2.000168519333715, 1.000289448405277, 1.3340743529054984]])
+    t = np.array([[0, 1, 2, 3], [1, 0, 3, 2]], np.int32)
+    pg, po = _prm_pair(gp, 1e-3, 1e4)
+    gpu = run_gpu(gp, x, x, t, pg, np.full(4, 10.0))
+    ref = run_oracle(x, x, t, po, np.full(4, 10.0))
+    assert ref["mollified"].all() and (gpu["pairs"]["type"] == 7).all()
+    assert np.abs(ref["pairH"]).max() > 0
+    compare_scene(gpu, ref, 4)
+    compare_pairs(gpu, ref, t, x, x)
+    gpu["ctx"].close()
+
+
 def test_typed_point_edge_and_point_point_tuples(gp):
     rng = np.random.default_rng(11)
     V = 40
@@ -296,6 +316,28 @@ def test_fp32_blocks_and_spmv(gp):
     y64 = gp.bsr_spmv(g64["A"], xv).cpu().numpy()
     y32 = gp.bsr_spmv(g32["A"], xv.float()).double().cpu().numpy()
     assert np.abs(y32 - y64).max() <= 1e-5 * np.abs(y64).max()
+    g64["ctx"].close(); g32["ctx"].close()
+
+
+def test_fp32_pcg_against_fp64(gp):
+    # FP32 blocks and FP32 SpMV; FP64 vectors, dots and preconditioner
+    s = scenes.two_sheets(n=16, seed=1)
+    pg, _ = _prm_pair(gp, s.dhat, s.kappa)
+    diag = np.full(s.V, 10.0)
+    g64 = run_gpu(gp, s.x, s.x_rest, s.tuples, pg, diag, dtype=gp.F64, inspect=False)
+    g32 = run_gpu(gp, s.x, s.x_rest, s.tuples, pg, diag, dtype=gp.F32, inspect=False)
+    b = torch.tensor(-g64["grad"], device="cuda")
+    x64, it64, rr64, st64 = gp.pcg(g64["ctx"], g64["A"], b, rtol=1e-6, maxit=1000)
+    x32, it32, rr32, st32 = gp.pcg(g32["ctx"], g32["A"], b, rtol=1e-6, maxit=1000)
+    assert st64 == st32 == gp.OK and rr32 <= 1e-6
+    assert abs(it32 - it64) <= 2
+    # residual of the FP32 solution measured with the FP64 matrix
+    r = b - gp.bsr_spmv(g64["A"], x32)
+    assert float(torch.linalg.norm(r) / torch.linalg.norm(b)) <= 1e-5
+    assert float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64)) <= 1e-4
+    # fixed iteration count with rtol = 0 on an FP32 matrix
+    _, it, _, st = gp.pcg(g32["ctx"], g32["A"], b, rtol=0.0, maxit=7)
+    assert it == 7 and st == gp.OK
     g64["ctx"].close(); g32["ctx"].close()
 
 

@@ -284,3 +284,36 @@ def test_exactly_parallel_edges_contribute_nothing():
     X = np.array([[0, 0, 0], [1, 0, 0], [0.2, 0, 0.4], [1.3, 0, 0.4]], float)
     out = oracle.pair_local(np.array([0, 1, 2, 3], np.int32), X, X, prm())
     assert out["mollified"] and out["E"] == 0 and not out["grad"].any() and not out["hess"].any()
+
+
+def test_rounding_level_parallel_edges_follow_exact_cross_product():
+    # Two facing diagonals of a cube lattice (m = 2, n = 10, seed 3): parallel
+    # in exact arithmetic before the vertex coordinates were rounded.  The
+    # rounded input is not quite parallel: |a x b| is 4.9e-32, while the
+    # plain product formula returns exactly 0 here.  The parallelness c of
+    # Eq. 25 is a function of the input coordinates, so c > 0, and the proxy
+    # Hessian is the rank-1 mollifier term along grad c (the distance term is
+    # scaled by e(c) ~ 1e-57).  grad c is taken exactly: sympy's derivative of
+    # |(x1 - x0) x (x3 - x2)|^2 evaluated in rationals.
+    from fractions import Fraction
+    X = np.array([[1.7779462971114925, 1.0, 1.1118521306832763],
+                  [1.8890574082226037, 1.0, 1.2229632417943872],
+                  [1.8890574082226037, 1.000289448405277, 1.2229632417943872],
+                  [2.000168519333715, 1.000289448405277, 1.3340743529054984]])
+    xs = sp.Matrix(4, 3, lambda i, j: sp.Symbol(f"x{i}{j}"))
+    a = xs[1, :] - xs[0, :]
+    b = xs[3, :] - xs[2, :]
+    n = a.cross(b)
+    c = n.dot(n)
+    subs = {xs[i, j]: sp.Rational(Fraction(float(X[i, j]))) for i in range(4) for j in range(3)}
+    c_exact = c.subs(subs)
+    assert c_exact > 0
+    grad = [sp.diff(c, xs[i, j]).subs(subs) for i in range(4) for j in range(3)]
+    top = max(abs(gk) for gk in grad)
+    gdir = np.array([float(gk / top) for gk in grad])
+    gdir /= np.linalg.norm(gdir)
+    out = oracle.pair_local(np.array([0, 1, 2, 3], np.int32), X, X, oracle.params(dhat=1e-3, kappa=1.0))
+    assert out["mollified"] and out["subtype"] == oracle.PP
+    lam, Q = np.linalg.eigh(out["hess"])
+    assert lam[-1] > 0 and np.abs(lam[:-1]).max() <= 1e-12 * lam[-1]
+    assert abs(abs(Q[:, -1] @ gdir) - 1.0) <= 1e-12
