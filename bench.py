@@ -13,6 +13,12 @@ One step = the whole hot path on the resident candidate list:
 `value` is candidate pairs per second through stage + build + eval/assembly
 (the metric's scope); the SpMV and PCG are timed in the same step and
 reported alongside.  Prints one JSON line.
+
+--workload sheets40 is the precision mode at four times the size: 40 sheets
+(seed 5), FP32 Hessian blocks and FP32 SpMV, PCG to ||r|| / ||b|| <= 1e-6
+inside the step; after the timed steps the FP64 path runs once on the same
+pattern for the comparison (block error, iterations, PCG time, solution
+difference).
 """
 from __future__ import annotations
 
@@ -37,7 +43,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["sheets10", "sheets2"], default="sheets10")
+    ap.add_argument("--workload", choices=["sheets10", "sheets40", "sheets2"], default="sheets10")
     ap.add_argument("--pcg-iters", type=int, default=100)
     ap.add_argument("--cpu-sample", type=int, default=5_000_000, help="candidates in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
@@ -50,6 +56,10 @@ def make_scene(name):
         s = scenes.stacked_sheets(n_sheets=10, n=256, seed=2)
         desc = ("10 stacked 256x256 sheets, spacing 0.6 dhat, jitter +-0.3 dhat, 1 sheared sheet, dhat=1e-3, "
                 "kappa=1e4, m/dt^2=10, AABB candidates within dhat")
+    elif name == "sheets40":
+        s = scenes.stacked_sheets(n_sheets=40, n=256, seed=5)
+        desc = ("40 stacked 256x256 sheets, spacing 0.6 dhat, jitter +-0.3 dhat, 1 sheared sheet, dhat=1e-3, "
+                "kappa=1e4, m/dt^2=10, AABB candidates within dhat; FP32 blocks and SpMV, PCG to 1e-6")
     else:
         s = scenes.two_sheets(n=16, seed=1)
         s.diag = np.full(s.V, 10.0)
@@ -70,6 +80,31 @@ def cpu_baseline(s, n_sample):
     return {"value": len(sub) / dt, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"{len(sub)} candidates drawn (seed 7) from the same list; oracle eval with per-pair "
                       f"Hessians (OpenMP) + assembly (serial sort); {dt:.1f} s"}
+
+
+def precision_compare(gp, ctx, x, xr, prm, diag, last, stream):
+    """The FP64 path once on the same pattern: block error of the FP32
+    matrix, PCG iterations and time at the same tolerance, solution gap."""
+    import torch
+    _, _, A32, d32, b = last
+    A64 = gp.BsrMatrix(ctx, dtype=gp.F64)
+    gp.eval_assemble(ctx, x, prm, A64, diag=diag, x_rest=xr)
+    n = A64.nnzb
+    fro = float(torch.linalg.norm(A32.val[:, :n].double() - A64.val[:, :n]) / torch.linalg.norm(A64.val[:, :n]))
+    out = {"block_rel_fro": fro}
+    for name, A in (("f64", A64), ("f32", A32)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        d, it, rr, st = gp.pcg(ctx, A, b, rtol=1e-6, maxit=20000)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[f"pcg_{name}"] = {"iters": it, "relres": rr, "ms": e0.elapsed_time(e1), "status": st}
+        out[f"x_{name}"] = d
+    x64, x32 = out.pop("x_f64"), out.pop("x_f32")
+    out["x_rel_diff"] = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
+    out["fp32_true_relres"] = float(torch.linalg.norm(b - gp.bsr_spmv(A64, x32)) / torch.linalg.norm(b))
+    del A64
+    return out
 
 
 def main():
@@ -95,24 +130,28 @@ def main():
     diag = torch.tensor(s.diag, device=dev)
     ctx = gp.Context()
     stream = torch.cuda.current_stream()
+    mixed = args.workload == "sheets40"
+    dt = gp.F32 if mixed else gp.F64
+    rtol, maxit = (1e-6, 20000) if mixed else (0.0, args.pcg_iters)
 
     def step(rec):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
         ev[0].record(stream)
         info = gp.pairs_build(ctx, x, tup, prm, x_rest=xr)
         ev[1].record(stream)
-        A = gp.BsrMatrix(ctx)
+        A = gp.BsrMatrix(ctx, dtype=dt)
         E, g = gp.eval_assemble(ctx, x, prm, A, diag=diag, x_rest=xr)
+        gv = g.float() if mixed else g
         ev[2].record(stream)
-        y = gp.bsr_spmv(A, g)
+        y = gp.bsr_spmv(A, gv)
         ev[3].record(stream)
         b = -g
         ev[4].record(stream)
-        d, it, rr, st = gp.pcg(ctx, A, b, rtol=0.0, maxit=args.pcg_iters)
+        d, it, rr, st = gp.pcg(ctx, A, b, rtol=rtol, maxit=maxit)
         ev[5].record(stream)
         if rec is not None:
-            rec.append((ev, info, it, A.nnzb))
-        return E, y
+            rec.append((ev, info, it, A.nnzb, rr))
+        return E, y, A, d, b
 
     for _ in range(args.warmup):
         step(None)
@@ -120,7 +159,7 @@ def main():
     recs = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step(recs)
+        last = step(recs)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     print(f"[bench] {args.steps} steps in {wall:.3f} s", file=sys.stderr, flush=True)
@@ -134,13 +173,14 @@ def main():
     V = s.V
     path_ms = build_ms + evas_ms
     value = s.P / (np.median(path_ms) * 1e-3)
-    # algorithmic bytes of one BSR SpMV (FP64 values): blocks (72 B values +
-    # 4 B column), row pointers, x read once, y written once
-    spmv_bytes = nnzb * (72 + 4) + 4 * (V + 1) + 24 * V + 24 * V
+    # algorithmic bytes of one BSR SpMV: blocks (9 values + 4 B column), row
+    # pointers, x read once, y written once
+    sv = 4 if mixed else 8
+    spmv_bytes = nnzb * (9 * sv + 4) + 4 * (V + 1) + 3 * sv * V + 3 * sv * V
     spmv_gbs = spmv_bytes / (np.mean(spmv_ms) * 1e-3) / 1e9
     # algorithmic bytes of stage + build + eval/assembly (metric scope):
     # tuples 16 B, positions + rest read once, gradient written, BSR written
-    path_bytes = 16 * s.P + 48 * V + 24 * V + nnzb * (72 + 4) + 4 * (V + 1) + 8 * V
+    path_bytes = 16 * s.P + 48 * V + 24 * V + nnzb * (9 * sv + 4) + 4 * (V + 1) + 8 * V
     out = {
         "metric": "contact pairs/s (energy+grad+proxy Hessian+BSR assembly); BSR SpMV GB/s vs roofline",
         "value": float(value),
@@ -152,7 +192,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64 geometry, f32 blocks and SpMV" if mixed else "f64",
         "data": "synthetic",
         "config": {
             "workload": desc,
@@ -162,6 +202,7 @@ def main():
             "active_by_type": info["n_by_type"],
             "nnzb": int(nnzb),
             "pcg_iters": int(iters),
+            "pcg_rtol": rtol,
         },
         "breakdown_ms": {
             "stage_build": float(np.median(build_ms)),
@@ -174,7 +215,7 @@ def main():
         "path_gbs": float(path_bytes / (np.median(path_ms) * 1e-3) / 1e9),
         "spmv_gbs": float(spmv_gbs),
         "roofline": {
-            "kernel": "k_spmv<double> (BSR SpMV)",
+            "kernel": "k_spmv<float> (BSR SpMV)" if mixed else "k_spmv<double> (BSR SpMV)",
             "bound": "hbm",
             "achieved": float(spmv_gbs),
             "peak": HBM_PEAK_GBS,
@@ -200,6 +241,8 @@ def main():
     out["copy_gbs"] = float(2 * nbytes / (copy_ms * 1e-3) / 1e9)
     out["roofline"]["frac_of_copy"] = float(spmv_gbs / out["copy_gbs"])
     del src, dst
+    if mixed:
+        out["precision"] = precision_compare(gp, ctx, x, xr, prm, diag, last, stream)
     ctx.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_sample)

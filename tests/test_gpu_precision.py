@@ -1,0 +1,113 @@
+"""Precision mode at scale: 40 stacked 256 x 256 sheets (seed 5, one sheared
+sheet; V = 2,621,440, about 234M AABB candidates within dhat).
+
+FP64 positions, classification, distances and mollifier; each Hessian block
+is reduced in FP64 registers and rounded once to FP32; the SpMV reads FP32
+blocks and accumulates in FP32; PCG vectors, dot products and the block
+Jacobi preconditioner stay FP64.
+
+* FP32 against FP64 blocks of the same pattern: relative Frobenius error of
+  the whole matrix <= 1e-5, and of every block <= 2^-24 (one rounding to
+  nearest per entry);
+* FP32 blocks against the oracle on sampled rows: <= 1e-5 of the row's
+  largest entry;
+* PCG to ||r|| / ||b|| <= 1e-6 on both matrices: both converge, within a few
+  per cent of each other in iterations, and the FP32 solution has a
+  residual <= 1e-5 ||b|| under the FP64 matrix.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import scenes  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def c5():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2308_09400_amd as gp
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    s = scenes.stacked_sheets(n_sheets=40, n=256, seed=5)
+    prm = gp.params(dhat=s.dhat, kappa=s.kappa)
+    X = torch.tensor(s.x, device=dev)
+    XR = torch.tensor(s.x_rest, device=dev)
+    T = torch.tensor(s.tuples, device=dev)
+    D = torch.tensor(s.diag, device=dev)
+    ctx = gp.Context()
+    info = gp.pairs_build(ctx, X, T, prm, x_rest=XR)
+    del T
+    A64 = gp.BsrMatrix(ctx, dtype=gp.F64)
+    E64, g64 = gp.eval_assemble(ctx, X, prm, A64, diag=D, x_rest=XR)
+    A32 = gp.BsrMatrix(ctx, dtype=gp.F32)
+    E32, g32 = gp.eval_assemble(ctx, X, prm, A32, diag=D, x_rest=XR)
+    yield dict(gp=gp, s=s, prm=prm, X=X, XR=XR, ctx=ctx, info=info, A64=A64, A32=A32, E64=E64, E32=E32,
+               g64=g64, g32=g32)
+    ctx.close()
+
+
+def test_precision_mode_keeps_fp64_energy_and_gradient(c5):
+    # only the blocks change precision
+    assert c5["E64"].item() == c5["E32"].item()
+    assert torch.equal(c5["g64"], c5["g32"])
+    assert c5["info"]["n_active"] > 50_000_000
+
+
+def test_fp32_blocks_against_fp64_blocks(c5):
+    A64, A32 = c5["A64"], c5["A32"]
+    n = A64.nnzb
+    v64 = A64.val[:, :n]
+    diff = A32.val[:, :n].double() - v64
+    fro = float(torch.linalg.norm(diff) / torch.linalg.norm(v64))
+    assert fro <= 1e-5
+    assert fro <= 2.0 ** -24
+    bn = torch.linalg.norm(v64, dim=0)
+    dn = torch.linalg.norm(diff, dim=0)
+    big = bn > 1e-30 * float(bn.max())
+    assert float((dn[big] / bn[big]).max()) <= 2.0 ** -24 * (1 + 1e-12)
+
+
+def test_fp32_blocks_against_oracle_on_sampled_rows(c5):
+    s, A = c5["s"], c5["A32"]
+    rng = np.random.default_rng(15)
+    rows = rng.choice(s.V, 24, replace=False)
+    mark = np.zeros(s.V, bool)
+    mark[rows] = True
+    t = s.tuples
+    sub = t[mark[np.where(t < 0, -t - 1, t)].any(1)]
+    po = oracle.params(dhat=s.dhat, kappa=s.kappa)
+    r = oracle.eval_scene(s.x, sub, po, x_rest=s.x_rest, per_pair=True)
+    orows, ocols, ovals = oracle.assemble(s.V, sub, r["pairH"], s.diag)
+    rp = A.row_ptr().cpu().numpy()
+    ci_all = A.col_idx()
+    for row in rows:
+        lo, hi = int(rp[row]), int(rp[row + 1])
+        ci = ci_all[lo:hi].cpu().numpy()
+        vals = A.val[:, lo:hi].double().cpu().numpy().T.reshape(-1, 3, 3)
+        g = {int(c): B for c, B in zip(ci, vals)}
+        sel = orows == row
+        o = {int(c): B for c, B in zip(ocols[sel], ovals[sel])}
+        hs = max(np.abs(B).max() for B in o.values())
+        for c in set(g) | set(o):
+            assert np.abs(g.get(c, 0.0) - o.get(c, 0.0)).max() <= 1e-5 * hs, (row, c)
+
+
+def test_pcg_fp32_against_fp64_to_1e6(c5):
+    gp, ctx = c5["gp"], c5["ctx"]
+    b = -c5["g64"]
+    x64, it64, rr64, st64 = gp.pcg(ctx, c5["A64"], b, rtol=1e-6, maxit=20000)
+    x32, it32, rr32, st32 = gp.pcg(ctx, c5["A32"], b, rtol=1e-6, maxit=20000)
+    assert st64 == gp.OK and st32 == gp.OK and rr64 <= 1e-6 and rr32 <= 1e-6
+    assert abs(it32 - it64) <= max(3, 0.05 * it64), (it32, it64)
+    nb = torch.linalg.norm(b)
+    r32 = float(torch.linalg.norm(b - gp.bsr_spmv(c5["A64"], x32)) / nb)
+    r64 = float(torch.linalg.norm(b - gp.bsr_spmv(c5["A64"], x64)) / nb)
+    assert r64 <= 2e-6 and r32 <= 1e-5, (r64, r32)
+    xd = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
+    print(f"[precision] iters fp64 {it64} fp32 {it32}; true residual fp64 {r64:.3e} fp32 {r32:.3e}; "
+          f"|x32 - x64| / |x64| = {xd:.3e}")
