@@ -34,7 +34,8 @@ extern "C" {
 typedef enum {
     GIPC_OK = 0,
     GIPC_ERR_INVALID_ARG = -1,   /* NULL pointer, negative size, bad flag */
-    GIPC_ERR_INDEX = -2,         /* malformed tuple, vertex id out of range, repeated vertex */
+    GIPC_ERR_INDEX = -2,         /* malformed tuple, vertex id out of range, repeated vertex,
+                                    tuple spanning two scenes of a batch */
     GIPC_ERR_DEGENERATE = -3,    /* reported by gipc_get_info: pairs with d = 0 or non-finite d */
     GIPC_ERR_HIP = -4,           /* a HIP runtime call failed */
     GIPC_ERR_WORKSPACE = -5,     /* allocation failed or a documented capacity limit was exceeded */
@@ -49,12 +50,31 @@ typedef enum {
 #define GIPC_FLAG_BARRIER_EQ12 0x4u  /* non-stiffened barrier Eq. 12 instead of Eq. 24 (test mode) */
 #define GIPC_FLAGS_DEFAULT (GIPC_FLAG_FILTER | GIPC_FLAG_MOLLIFY)
 
+/* A batch of independent scenes concatenated into one mesh and one tuple
+ * list (an extension: the paper evaluates one scene at a time).  Scene s
+ * owns the vertices [vert_off[s], vert_off[s+1]); every tuple's vertices
+ * must lie in one scene.  Device arrays:
+ *   vert_off  int32 [S+1]  non-decreasing, vert_off[0] = 0, vert_off[S] = V
+ *   dhat      double [S]   > 0, the scene's dhat (replaces params->dhat)
+ *   kappa     double [S]   >= 0, the scene's kappa (replaces params->kappa)
+ * gipc_pairs_build reads and checks all three (INVALID_ARG) and keeps the
+ * scene of every vertex; later calls on that build must pass a batch with
+ * the same S and the same dhat and kappa values (they are read again on
+ * the device, not re-checked). */
+typedef struct {
+    int32_t S;
+    const int32_t* vert_off;
+    const double* dhat;
+    const double* kappa;
+} gipc_batch;
+
 typedef struct {
     double dhat;        /* computational accuracy target (Eq. 6, Eq. 9) */
     double kappa;       /* barrier stiffness multiplying every pair's energy */
     double dthr_ratio;  /* d_thr / dhat of the filter, Eq. 23 (paper: 0.1) */
     double epsx_ratio;  /* eps_x = epsx_ratio |x12-x11|^2 |x22-x21|^2 at rest, Eq. 25 (paper: 1e-3) */
     uint32_t flags;     /* GIPC_FLAG_* */
+    const gipc_batch* batch;  /* host struct, NULL for one scene (dhat, kappa above) */
 } gipc_params;
 
 /* Vertex positions (the x of Eq. 1).  Both arrays: device, float64 [V][3]
@@ -131,9 +151,11 @@ const char* gipc_ctx_last_error(const gipc_ctx* ctx);
  * sub-type (the four type buffers of supplement Sec. 6) and builds the BSR
  * pattern of diag + sum_k S_k^T H_k S_k over the vertices each pair's
  * distance depends on (all four for mollified edge-edge pairs).
- * Synchronises `stream` (three times) to size the pattern; `info` (host,
- * nullable) receives the counts.  Errors: INVALID_ARG, INDEX (no state is
- * kept), WORKSPACE (a vertex touched by more than 2048 active pairs), HIP.
+ * With params->batch, each tuple is tested against its own scene's dhat.
+ * Synchronises `stream` (three times, four with a batch) to size the
+ * pattern; `info` (host, nullable) receives the counts.  Errors:
+ * INVALID_ARG, INDEX (no state is kept), WORKSPACE (a vertex touched by
+ * more than 2048 active pairs), HIP.
  */
 gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pairs* pairs,
                              const gipc_params* params, void* stream, gipc_info* info);
@@ -148,11 +170,14 @@ gipc_status gipc_bsr_pattern(const gipc_ctx* ctx, gipc_bsr* A);
 
 /*
  * Barrier energy and gradient of the staged pairs at mesh->x (Eq. 24 / 29,
- * Eq. 13-14 / 30): *energy (device, 1 double) = kappa * sum_k e_k b_k;
- * grad (device, double [V][3], overwritten).  Also stores each pair's
- * compact proxy-Hessian factors (Eq. 18-23, 32-36) in the context for
- * gipc_assemble_bsr.  Deterministic (no floating-point atomics).
- * Errors: INVALID_ARG, STATE (no build, or V differs from the build).
+ * Eq. 13-14 / 30): energy (device, double [S], S = 1 without a batch)
+ * receives kappa_s * sum_{k in scene s} e_k b_k per scene; grad (device,
+ * double [V][3], overwritten).  Also stores each pair's compact
+ * proxy-Hessian factors (Eq. 18-23, 32-36) in the context for
+ * gipc_assemble_bsr.  Deterministic for a given gipc_tune (no
+ * floating-point atomics; sums in fixed orders).
+ * Errors: INVALID_ARG, STATE (no build, V or the batch differs from the
+ * build).
  */
 gipc_status gipc_barrier_eval(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params,
                               double* energy, double* grad, void* stream);
@@ -179,8 +204,11 @@ gipc_status gipc_bsr_spmv(const gipc_bsr* A, const void* x, void* y, void* strea
 /*
  * Solve A x = b by conjugate gradients preconditioned with the inverses of
  * A's 3x3 diagonal blocks (Sec. 6.2; Saad Alg. 9.1).  b, x: device double
- * [nbrows][3]; x holds x0 on entry and the result on return.  A must be
- * FP64 (GIPC_F64).  Stops when ||r||_2 <= rtol ||b||_2 (checked every
+ * [nbrows][3]; x holds x0 on entry and the result on return.  A may be FP64
+ * or FP32; with FP32 blocks the product A p reads an FP32 copy of p and
+ * accumulates in FP32, while vectors, dot products and the preconditioner
+ * (inverted in FP64 from the FP32 blocks) stay FP64.  A batch is solved as
+ * one block-diagonal system.  Stops when ||r||_2 <= rtol ||b||_2 (checked every
  * iteration on the device; the host polls every 16 iterations) or after
  * maxit iterations; rtol = 0 runs exactly maxit iterations.  Synchronises
  * `stream`; *iters and *relres (host, nullable) receive the iterations run
@@ -209,6 +237,56 @@ gipc_status gipc_pair_inspect(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_p
 /* Plain device-to-device copy of `bytes` bytes with the library's own
  * streaming kernel (bandwidth reference for roofline fractions). */
 gipc_status gipc_copy(const void* src, void* dst, int64_t bytes, void* stream);
+
+/*
+ * Launch shapes of the evaluation and assembly kernels (per context).
+ *   eval_waves     wavefronts per workgroup of the pair evaluation: 1, 2, 4, 8
+ *   row_lanes      lanes per block row of the gradient / diagonal-block
+ *                  gather: 4, 8, 16, 32 (changes the summation order of
+ *                  those sums, hence their last bits)
+ *   offdiag_waves  wavefronts per workgroup of the off-diagonal blocks: 1, 2, 4, 8
+ * Default {4, 16, 4}.  Set: INVALID_ARG for other values.
+ */
+typedef struct {
+    int32_t eval_waves;
+    int32_t row_lanes;
+    int32_t offdiag_waves;
+} gipc_tune;
+
+gipc_status gipc_get_tune(const gipc_ctx* ctx, gipc_tune* tune);
+gipc_status gipc_set_tune(gipc_ctx* ctx, const gipc_tune* tune);
+
+/*
+ * Autotuner: with the arguments of gipc_eval_assemble on the current build,
+ * time every eval_waves, row_lanes and offdiag_waves choice (each kernel
+ * alone, `reps` launches after one warm-up, HIP events on `stream`), keep
+ * the fastest of each in the context and in *best (host, nullable).  The
+ * outputs hold the result of the last timed launch of each kernel, which
+ * equals a gipc_eval_assemble with the chosen shapes only up to summation
+ * order: call gipc_eval_assemble afterwards.  Synchronises.  Errors as
+ * gipc_eval_assemble, INVALID_ARG for reps < 1.
+ */
+gipc_status gipc_autotune(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params, double* energy,
+                          double* grad, const double* diag, const gipc_bsr* A, int32_t reps, gipc_tune* best,
+                          void* stream);
+
+/*
+ * The launch sequence of gipc_eval_assemble (pair evaluation, gradient and
+ * diagonal blocks, off-diagonal blocks, per-scene energies) captured once
+ * into a HIP graph for the given argument pointers; replays read whatever
+ * those buffers hold then (e.g. positions updated in place) and run no
+ * allocation, memset or synchronisation.  Capture uses a private stream and
+ * sizes the context's buffers first (it may allocate).  A graph stays valid
+ * until the next gipc_pairs_build on its context, or until
+ * the context is destroyed (launch returns STATE after a rebuild).
+ * Errors: as gipc_eval_assemble; HIP if capture or instantiation fails.
+ */
+typedef struct gipc_graph gipc_graph;
+
+gipc_status gipc_graph_create(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params, double* energy,
+                              double* grad, const double* diag, const gipc_bsr* A, gipc_graph** out);
+gipc_status gipc_graph_launch(gipc_graph* graph, void* stream);
+void gipc_graph_destroy(gipc_graph* graph);
 
 #ifdef __cplusplus
 }

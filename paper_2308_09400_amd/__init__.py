@@ -26,7 +26,8 @@ SUBTYPES = {1: "PT", 2: "PE", 3: "PP", 4: "EE", 5: "EE_moll", 6: "PE_moll", 7: "
 EXPORTS = [
     "gipc_status_string", "gipc_ctx_create", "gipc_ctx_destroy", "gipc_ctx_last_error", "gipc_pairs_build",
     "gipc_get_info", "gipc_bsr_pattern", "gipc_barrier_eval", "gipc_assemble_bsr", "gipc_eval_assemble",
-    "gipc_bsr_spmv", "gipc_pcg", "gipc_pair_inspect", "gipc_copy",
+    "gipc_bsr_spmv", "gipc_pcg", "gipc_pair_inspect", "gipc_copy", "gipc_get_tune", "gipc_set_tune",
+    "gipc_autotune", "gipc_graph_create", "gipc_graph_launch", "gipc_graph_destroy",
 ]
 
 
@@ -36,9 +37,21 @@ class GipcError(RuntimeError):
         self.status = status
 
 
+class BatchC(ctypes.Structure):
+    _fields_ = [("S", ctypes.c_int32), ("vert_off", ctypes.c_void_p), ("dhat", ctypes.c_void_p),
+                ("kappa", ctypes.c_void_p)]
+
+
 class Params(ctypes.Structure):
     _fields_ = [("dhat", ctypes.c_double), ("kappa", ctypes.c_double), ("dthr_ratio", ctypes.c_double),
-                ("epsx_ratio", ctypes.c_double), ("flags", ctypes.c_uint32)]
+                ("epsx_ratio", ctypes.c_double), ("flags", ctypes.c_uint32), ("batch", ctypes.POINTER(BatchC))]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("eval_waves", ctypes.c_int32), ("row_lanes", ctypes.c_int32), ("offdiag_waves", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 class Mesh(ctypes.Structure):
@@ -94,6 +107,14 @@ def lib():
             "gipc_pcg": (st, [vp, ctypes.POINTER(Bsr), vp, vp, d, i32, ctypes.POINTER(i32), ctypes.POINTER(d), vp]),
             "gipc_pair_inspect": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), vp, vp, vp, vp, vp, vp, vp]),
             "gipc_copy": (st, [vp, vp, i64, vp]),
+            "gipc_get_tune": (st, [vp, ctypes.POINTER(Tune)]),
+            "gipc_set_tune": (st, [vp, ctypes.POINTER(Tune)]),
+            "gipc_autotune": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), vp, vp, vp, ctypes.POINTER(Bsr),
+                                   i32, ctypes.POINTER(Tune), vp]),
+            "gipc_graph_create": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), vp, vp, vp,
+                                       ctypes.POINTER(Bsr), ctypes.POINTER(vp)]),
+            "gipc_graph_launch": (st, [vp, vp]),
+            "gipc_graph_destroy": (None, [vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -107,8 +128,43 @@ def status_string(s: int) -> str:
     return lib().gipc_status_string(int(s)).decode()
 
 
-def params(dhat=1e-3, kappa=1e4, dthr_ratio=0.1, epsx_ratio=1e-3, flags=FLAGS_DEFAULT) -> Params:
-    return Params(float(dhat), float(kappa), float(dthr_ratio), float(epsx_ratio), int(flags))
+class Batch:
+    """Independent scenes concatenated into one mesh: scene s owns the
+    vertices [vert_off[s], vert_off[s+1]) and has its own dhat and kappa
+    (device tensors int32 [S+1], float64 [S], float64 [S])."""
+
+    def __init__(self, vert_off, dhat, kappa, device=None):
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.vert_off = torch.as_tensor(vert_off, dtype=torch.int32).to(dev).contiguous()
+        self.dhat = torch.as_tensor(dhat, dtype=torch.float64).to(dev).contiguous()
+        self.kappa = torch.as_tensor(kappa, dtype=torch.float64).to(dev).contiguous()
+        self.S = int(self.dhat.numel())
+        if self.vert_off.numel() != self.S + 1 or self.kappa.numel() != self.S:
+            raise ValueError("vert_off must have S+1 entries, dhat and kappa S")
+        self.c = BatchC(self.S, self.vert_off.data_ptr(), self.dhat.data_ptr(), self.kappa.data_ptr())
+        self._scene_of_vertex = None
+
+    def scene_of_vertex(self):
+        """int64 [V] scene id of every vertex (for the autograd backward)."""
+        if self._scene_of_vertex is None:
+            counts = (self.vert_off[1:] - self.vert_off[:-1]).long()
+            self._scene_of_vertex = torch.repeat_interleave(
+                torch.arange(self.S, device=self.vert_off.device), counts)
+        return self._scene_of_vertex
+
+
+def params(dhat=1e-3, kappa=1e4, dthr_ratio=0.1, epsx_ratio=1e-3, flags=FLAGS_DEFAULT, batch: Batch | None = None
+           ) -> Params:
+    """Parameters; with ``batch`` its per-scene dhat and kappa replace dhat and kappa."""
+    p = Params(float(dhat), float(kappa), float(dthr_ratio), float(epsx_ratio), int(flags),
+               ctypes.pointer(batch.c) if batch is not None else None)
+    p._batch = batch  # keeps the batch's tensors alive with the struct
+    return p
+
+
+def _energy_out(prm: Params, device):
+    b = getattr(prm, "_batch", None)
+    return torch.empty((b.S,) if b is not None else (), dtype=torch.float64, device=device)
 
 
 def _ptr(t):
@@ -192,7 +248,7 @@ def bsr_pattern(ctx: Context) -> Bsr:
 def barrier_eval(ctx: Context, x, prm: Params, x_rest=None, energy=None, grad=None, stream=None):
     """Energy (device scalar tensor) and gradient [V][3] of the staged pairs."""
     mesh = Context._mesh(x, x_rest)
-    energy = torch.empty((), dtype=torch.float64, device=x.device) if energy is None else energy
+    energy = _energy_out(prm, x.device) if energy is None else energy
     grad = torch.empty_like(x) if grad is None else grad
     ctx._check(lib().gipc_barrier_eval(ctx.h, ctypes.byref(mesh), ctypes.byref(prm), _ptr(energy), _ptr(grad),
                                        _stream(stream)), "gipc_barrier_eval")
@@ -258,7 +314,7 @@ def eval_assemble(ctx: Context, x, prm: Params, A: BsrMatrix, diag=None, x_rest=
     mesh = Context._mesh(x, x_rest)
     if diag is not None:
         _need(diag, torch.float64, None, "diag")
-    energy = torch.empty((), dtype=torch.float64, device=x.device) if energy is None else energy
+    energy = _energy_out(prm, x.device) if energy is None else energy
     grad = torch.empty_like(x) if grad is None else grad
     ctx._check(lib().gipc_eval_assemble(ctx.h, ctypes.byref(mesh), ctypes.byref(prm), _ptr(energy), _ptr(grad),
                                         _ptr(diag), ctypes.byref(A.desc), _stream(stream)), "gipc_eval_assemble")
@@ -316,7 +372,8 @@ def copy(src, dst, nbytes=None, stream=None):
 
 class BarrierEnergy(torch.autograd.Function):
     """Total barrier energy kappa * sum_k e_k b_k of the pairs staged in ``gctx``
-    as a differentiable function of the positions (Eq. 3, 24, 29).
+    as a differentiable function of the positions (Eq. 3, 24, 29); with a
+    batch, the vector of per-scene energies.
 
     ``forward`` runs the pair-evaluation and gradient kernels
     (``gipc_barrier_eval``) and keeps the gradient; ``backward`` returns
@@ -329,11 +386,14 @@ class BarrierEnergy(torch.autograd.Function):
     def forward(ctx, x, gctx, prm, x_rest=None):
         E, g = barrier_eval(gctx, x.detach().contiguous(), prm, x_rest=x_rest)
         ctx.save_for_backward(g)
+        ctx.batch = getattr(prm, "_batch", None)
         return E
 
     @staticmethod
     def backward(ctx, grad_out):
         (g,) = ctx.saved_tensors
+        if ctx.batch is not None:  # per-scene energies: each vertex takes its scene's weight
+            return grad_out[ctx.batch.scene_of_vertex()].unsqueeze(1) * g, None, None, None
         return grad_out * g, None, None, None
 
 
@@ -349,3 +409,90 @@ def hvp(gctx: Context, x, prm: Params, v, x_rest=None, A: BsrMatrix | None = Non
     A = BsrMatrix(gctx) if A is None else A
     eval_assemble(gctx, x, prm, A, diag=None, x_rest=x_rest)
     return bsr_spmv(A, v.contiguous()), A
+
+
+def get_tune(ctx: Context) -> dict:
+    t = Tune()
+    ctx._check(lib().gipc_get_tune(ctx.h, ctypes.byref(t)), "gipc_get_tune")
+    return t.as_dict()
+
+
+def set_tune(ctx: Context, eval_waves=4, row_lanes=16, offdiag_waves=4):
+    t = Tune(int(eval_waves), int(row_lanes), int(offdiag_waves))
+    ctx._check(lib().gipc_set_tune(ctx.h, ctypes.byref(t)), "gipc_set_tune")
+
+
+def autotune(ctx: Context, x, prm: Params, A: BsrMatrix, diag=None, x_rest=None, reps=5, cache=None, key=None,
+             stream=None) -> dict:
+    """Pick the fastest launch shapes of the eval / row / off-diagonal kernels
+    for the current build (``gipc_autotune``, synchronises).  With ``cache``
+    (a JSON file path) and ``key`` (a string naming the workload), a stored
+    choice for (device, key) is applied instead of timing, and a new one is
+    stored."""
+    import json
+    dkey = None
+    if cache is not None and key is not None:
+        dkey = f"{torch.cuda.get_device_name(x.device)}|{key}"
+        try:
+            with open(cache) as f:
+                table = json.load(f)
+        except (OSError, ValueError):
+            table = {}
+        if dkey in table:
+            set_tune(ctx, **table[dkey])
+            return dict(table[dkey])
+    mesh = Context._mesh(x, x_rest)
+    if diag is not None:
+        _need(diag, torch.float64, None, "diag")
+    energy = _energy_out(prm, x.device)
+    grad = torch.empty_like(x)
+    t = Tune()
+    ctx._check(lib().gipc_autotune(ctx.h, ctypes.byref(mesh), ctypes.byref(prm), _ptr(energy), _ptr(grad),
+                                   _ptr(diag), ctypes.byref(A.desc), int(reps), ctypes.byref(t), _stream(stream)),
+               "gipc_autotune")
+    best = t.as_dict()
+    if dkey is not None:
+        try:
+            with open(cache) as f:
+                table = json.load(f)
+        except (OSError, ValueError):
+            table = {}
+        table[dkey] = best
+        with open(cache, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+    return best
+
+
+class Graph:
+    """``gipc_eval_assemble`` for fixed buffers, captured once into a HIP graph
+    (``gipc_graph_create``); ``launch()`` replays it.  Write new positions
+    into ``x`` in place between launches; ``energy`` and ``grad`` are the
+    output tensors the graph writes."""
+
+    def __init__(self, ctx: Context, x, prm: Params, A: BsrMatrix, diag=None, x_rest=None):
+        mesh = Context._mesh(x, x_rest)
+        if diag is not None:
+            _need(diag, torch.float64, None, "diag")
+        self.ctx, self.x, self.x_rest, self.prm, self.A, self.diag = ctx, x, x_rest, prm, A, diag
+        self.energy = _energy_out(prm, x.device)
+        self.grad = torch.empty_like(x)
+        h = ctypes.c_void_p()
+        ctx._check(lib().gipc_graph_create(ctx.h, ctypes.byref(mesh), ctypes.byref(prm), _ptr(self.energy),
+                                           _ptr(self.grad), _ptr(diag), ctypes.byref(A.desc), ctypes.byref(h)),
+                   "gipc_graph_create")
+        self.h = h
+
+    def launch(self, stream=None):
+        self.ctx._check(lib().gipc_graph_launch(self.h, _stream(stream)), "gipc_graph_launch")
+        return self.energy, self.grad
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().gipc_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,10 +1,12 @@
 // C ABI of libgipc: argument checks, context state, buffer management and
 // the launch sequences.  Every compute step runs in the kernels of the
 // other translation units.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -47,7 +49,7 @@ namespace {
 // counters layout (int64 slots of ctx->counters)
 enum {
     C_NBAD = 0, C_FIRST_BAD = 1, C_NDEG = 2, C_FIRST_DEG = 3, C_ACTIVE = 4, C_OFF = 5,  // 5..13: type offsets
-    C_INC = 16, C_K = 17, C_NNZB = 18, C_MAXDEG = 19, C_NSLOTS = 24
+    C_INC = 16, C_K = 17, C_NNZB = 18, C_MAXDEG = 19, C_NSPAN = 20, C_FIRST_SPAN = 21, C_NSLOTS = 24
 };
 
 gipc_status fail(gipc_ctx* ctx, gipc_status st, const char* fmt, ...) {
@@ -99,6 +101,29 @@ gipc_status to_dev_params(gipc_ctx* ctx, const gipc_params* p, DevParams& o) {
     o.filter = (p->flags & GIPC_FLAG_FILTER) ? 1 : 0;
     o.mollify = (p->flags & GIPC_FLAG_MOLLIFY) ? 1 : 0;
     o.eq12 = (p->flags & GIPC_FLAG_BARRIER_EQ12) ? 1 : 0;
+    o.vscene = nullptr;
+    o.dhat_s = nullptr;
+    o.kappa_s = nullptr;
+    if (p->batch) {
+        const gipc_batch* b = p->batch;
+        if (b->S < 1) return fail(ctx, GIPC_ERR_INVALID_ARG, "batch->S must be >= 1");
+        if (!b->vert_off || !b->dhat || !b->kappa)
+            return fail(ctx, GIPC_ERR_INVALID_ARG, "batch->vert_off, dhat and kappa must be device arrays");
+        o.dhat_s = b->dhat;
+        o.kappa_s = b->kappa;
+    }
+    return GIPC_OK;
+}
+
+// the batch of a call after the build: same presence and S as the build's
+gipc_status bind_batch(gipc_ctx* ctx, const gipc_params* p, DevParams& pm) {
+    const bool has = p->batch != nullptr;
+    if (has != ctx->batched) return fail(ctx, GIPC_ERR_STATE, "the batch must be given iff the build had one");
+    if (has) {
+        if (p->batch->S != ctx->S)
+            return fail(ctx, GIPC_ERR_STATE, "batch->S = %d differs from the build (%d)", p->batch->S, ctx->S);
+        pm.vscene = static_cast<const int32_t*>(ctx->vscene.p);
+    }
     return GIPC_OK;
 }
 
@@ -168,7 +193,8 @@ void gipc_ctx_destroy(gipc_ctx* ctx) {
     DevBuf* bufs[] = {&ctx->cand_ft, &ctx->cand_vid, &ctx->bcount, &ctx->boff, &ctx->counters, &ctx->st_vid,
                       &ctx->st_src, &ctx->deg, &ctx->kcount, &ctx->fill, &ctx->inc_ptr, &ctx->kptr, &ctx->inc,
                       &ctx->contrib, &ctx->kcol, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
-                      &ctx->slot_row, &ctx->diag_slot, &ctx->maxbuf, &ctx->rec_main, &ctx->rec_extra, &ctx->e_part,
+                      &ctx->slot_row, &ctx->diag_slot, &ctx->maxbuf, &ctx->rec_main, &ctx->rec_extra, &ctx->ev,
+                      &ctx->epart, &ctx->vscene, &ctx->pieces, &ctx->poff,
                       &ctx->r, &ctx->z, &ctx->p, &ctx->q, &ctx->p32, &ctx->minv, &ctx->part, &ctx->scal, &ctx->scan_tmp,
                       &ctx->scan_tmp2};
     for (DevBuf* b : bufs) release(*b);
@@ -198,6 +224,57 @@ gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
     const double* xr = mesh->x_rest ? mesh->x_rest : mesh->x;
     ctx->built = false;
     ctx->evaluated = false;
+    ++ctx->build_gen;
+
+    // ---- scenes: vertex ranges, energy pieces, scene of every vertex
+    const gipc_batch* batch = params->batch;
+    const int32_t Sc = batch ? batch->S : 1;
+    std::vector<int32_t> voff(Sc + 1);
+    if (batch) {
+        std::vector<double> dh(Sc), ka(Sc);
+        CK(hipMemcpyAsync(voff.data(), batch->vert_off, sizeof(int32_t) * (Sc + 1), hipMemcpyDeviceToHost, s),
+           "copy batch");
+        CK(hipMemcpyAsync(dh.data(), batch->dhat, sizeof(double) * Sc, hipMemcpyDeviceToHost, s), "copy batch");
+        CK(hipMemcpyAsync(ka.data(), batch->kappa, sizeof(double) * Sc, hipMemcpyDeviceToHost, s), "copy batch");
+        CK(hipStreamSynchronize(s), "stream synchronize");
+        if (voff[0] != 0 || voff[Sc] != V)
+            return fail(ctx, GIPC_ERR_INVALID_ARG, "batch->vert_off must start at 0 and end at V = %d", V);
+        for (int32_t k = 0; k < Sc; ++k) {
+            if (voff[k + 1] < voff[k])
+                return fail(ctx, GIPC_ERR_INVALID_ARG, "batch->vert_off decreases at scene %d", k);
+            if (!(dh[k] > 0.0) || !std::isfinite(dh[k]))
+                return fail(ctx, GIPC_ERR_INVALID_ARG, "batch->dhat[%d] must be > 0", k);
+            if (!(ka[k] >= 0.0) || !std::isfinite(ka[k]))
+                return fail(ctx, GIPC_ERR_INVALID_ARG, "batch->kappa[%d] must be >= 0", k);
+        }
+    } else {
+        voff[0] = 0;
+        voff[1] = V;
+    }
+    std::vector<int2> pcs;
+    std::vector<int32_t> po(Sc + 1);
+    for (int32_t k = 0; k < Sc; ++k) {
+        po[k] = (int32_t)pcs.size();
+        for (int64_t v = voff[k]; v < voff[k + 1]; v += kEnergyPiece)
+            pcs.push_back(make_int2((int)v, (int)std::min<int64_t>(v + kEnergyPiece, voff[k + 1])));
+    }
+    po[Sc] = (int32_t)pcs.size();
+    CK(ensure(ctx->pieces, sizeof(int2) * pcs.size()), "alloc energy pieces");
+    CK(ensure(ctx->poff, sizeof(int32_t) * po.size()), "alloc energy pieces");
+    if (!pcs.empty())
+        CK(hipMemcpyAsync(ctx->pieces.p, pcs.data(), sizeof(int2) * pcs.size(), hipMemcpyHostToDevice, s),
+           "upload energy pieces");
+    CK(hipMemcpyAsync(ctx->poff.p, po.data(), sizeof(int32_t) * po.size(), hipMemcpyHostToDevice, s),
+       "upload energy pieces");
+    if (batch) {
+        CK(ensure(ctx->vscene, sizeof(int32_t) * (size_t)(V > 0 ? V : 1)), "alloc vertex scenes");
+        CK(launch_vertex_scene(batch->vert_off, Sc, V, as<int32_t>(ctx->vscene), s), "vertex scenes");
+        pm.vscene = as<int32_t>(ctx->vscene);
+    }
+    CK(hipStreamSynchronize(s), "stream synchronize");  // the host tables above go out of scope
+    ctx->S = Sc;
+    ctx->batched = batch != nullptr;
+    ctx->npieces = (int32_t)pcs.size();
 
     // ---- staging
     const int64_t nb = (P + kBlock - 1) / kBlock;
@@ -224,10 +301,13 @@ gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
         CK(launch_stage_offsets(as<int64_t>(ctx->boff), nb, cnt + C_OFF, s), "stage offsets");
     }
     int64_t hc[C_NSLOTS] = {0};
-    if ((st = read_counters(ctx, hc, 0, 14, s)) != GIPC_OK) return st;
+    if ((st = read_counters(ctx, hc, 0, C_NSLOTS, s)) != GIPC_OK) return st;
     if (hc[C_NBAD] > 0)
         return fail(ctx, GIPC_ERR_INDEX, "%lld malformed tuple(s) or vertex id(s) out of [0, %d); first at %lld",
                     (long long)hc[C_NBAD], V, (long long)hc[C_FIRST_BAD]);
+    if (hc[C_NSPAN] > 0)
+        return fail(ctx, GIPC_ERR_INDEX, "%lld tuple(s) with vertices in two scenes; first at %lld",
+                    (long long)hc[C_NSPAN], (long long)hc[C_FIRST_SPAN]);
     TypeRanges tr;
     for (int t = 0; t < 9; ++t) tr.off[t] = P > 0 ? hc[C_OFF + t] : 0;
     tr.off[0] = 0;
@@ -321,45 +401,81 @@ gipc_status gipc_bsr_pattern(const gipc_ctx* ctx, gipc_bsr* A) {
     return GIPC_OK;
 }
 
-static gipc_status eval_impl(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params, double* energy,
-                             double* grad, const double* diag, const gipc_bsr* A, bool assemble, void* stream) {
-    if (!ctx) return GIPC_ERR_INVALID_ARG;
-    ctx->err.clear();
+// ---------------------------------------------------------------- eval
+
+namespace {
+
+// argument checks shared by the eval entry points; fills pm
+gipc_status eval_check(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params, double* energy,
+                       double* grad, const gipc_bsr* A, bool assemble, DevParams& pm) {
     gipc_status st;
     if ((st = check_device(ctx)) != GIPC_OK) return st;
     if ((st = check_mesh(ctx, mesh)) != GIPC_OK) return st;
-    DevParams pm;
     if ((st = to_dev_params(ctx, params, pm)) != GIPC_OK) return st;
     if (!energy || (!grad && mesh->V > 0)) return fail(ctx, GIPC_ERR_INVALID_ARG, "energy or grad is NULL");
     if (!ctx->built) return fail(ctx, GIPC_ERR_STATE, "gipc_pairs_build has not succeeded");
     if (mesh->V != ctx->V) return fail(ctx, GIPC_ERR_STATE, "V = %d differs from the build (%d)", mesh->V, ctx->V);
+    if ((st = bind_batch(ctx, params, pm)) != GIPC_OK) return st;
     if (assemble) {
         if (!A || !A->val) return fail(ctx, GIPC_ERR_INVALID_ARG, "A or A->val is NULL");
         if (A->dtype != GIPC_F64 && A->dtype != GIPC_F32) return fail(ctx, GIPC_ERR_INVALID_ARG, "bad dtype");
         if (!same_pattern(ctx, A)) return fail(ctx, GIPC_ERR_STATE, "A is not the pattern of the last build");
     }
-    hipStream_t s = S(stream);
-    const double* xr = mesh->x_rest ? mesh->x_rest : mesh->x;
+    return GIPC_OK;
+}
+
+// size the factor and energy buffers for the current build
+gipc_status eval_prepare(gipc_ctx* ctx) {
     const TypeRanges& tr = ctx->ranges;
     const int64_t Ps = ctx->Ps, Pm = tr.off[8] - tr.off[FT_EEM];
-    const int64_t nparts = eval_num_parts(Ps);
     CK(ensure(ctx->rec_main, sizeof(double) * 8 * (size_t)Ps), "alloc factors");
     CK(ensure(ctx->rec_extra, sizeof(double) * 9 * (size_t)Pm), "alloc factors");
-    CK(ensure(ctx->e_part, sizeof(double) * (size_t)(nparts > 0 ? nparts : 1)), "alloc factors");
-    CK(launch_eval(as<int4>(ctx->st_vid), tr, mesh->x, xr, pm, as<double>(ctx->rec_main), as<double>(ctx->rec_extra),
-                   as<double>(ctx->e_part), s),
-       "pair eval");
-    CK(launch_energy_final(as<double>(ctx->e_part), nparts, energy, s), "energy");
-    const int64_t m0 = tr.off[FT_EEM];
-    CK(launch_rows_diag(assemble ? 3 : 1, ctx->V, as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr),
-                        as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra), m0, diag,
-                        grad, assemble ? A->val : nullptr, assemble ? A->dtype : 0, ctx->nnzb, s),
-       "gradient");
-    if (assemble)
-        CK(launch_offdiag(ctx->nnzb, as<int32_t>(ctx->slot_row), as<int32_t>(ctx->col_idx), as<int64_t>(ctx->cptr),
-                          as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra), m0,
-                          A->val, A->dtype, s),
-           "off-diagonal blocks");
+    CK(ensure(ctx->ev, sizeof(double) * (size_t)(ctx->V > 0 ? ctx->V : 1)), "alloc energy shares");
+    CK(ensure(ctx->epart, sizeof(double) * (size_t)(ctx->npieces > 0 ? ctx->npieces : 1)), "alloc energy pieces");
+    return GIPC_OK;
+}
+
+// the launch sequence: no allocation, memset or synchronisation (graph-safe)
+hipError_t eval_enqueue(gipc_ctx* ctx, const DevParams& pm, const gipc_mesh* mesh, double* energy, double* grad,
+                        const double* diag, const gipc_bsr* A, bool assemble, const gipc_tune& t, hipStream_t s) {
+    const double* xr = mesh->x_rest ? mesh->x_rest : mesh->x;
+    const TypeRanges& tr = ctx->ranges;
+    const int64_t m0 = tr.off[FT_EEM], e0 = tr.off[FT_EE];
+    hipError_t e = launch_eval(as<int4>(ctx->st_vid), tr, mesh->x, xr, pm, as<double>(ctx->rec_main),
+                               as<double>(ctx->rec_extra), t.eval_waves, s);
+    if (e != hipSuccess) return e;
+    e = launch_rows_diag(assemble ? 3 : 1, ctx->V, as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr),
+                         as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra), e0, m0,
+                         diag, grad, as<double>(ctx->ev), assemble ? A->val : nullptr, assemble ? A->dtype : 0,
+                         ctx->nnzb, t.row_lanes, s);
+    if (e != hipSuccess) return e;
+    if (assemble) {
+        e = launch_offdiag(ctx->nnzb, as<int32_t>(ctx->slot_row), as<int32_t>(ctx->col_idx), as<int64_t>(ctx->cptr),
+                           as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra), e0, m0,
+                           A->val, A->dtype, t.offdiag_waves, s);
+        if (e != hipSuccess) return e;
+    }
+    return launch_energy(as<double>(ctx->ev), as<int2>(ctx->pieces), ctx->npieces, as<int32_t>(ctx->poff), ctx->S,
+                         as<double>(ctx->epart), energy, s);
+}
+
+bool tune_ok(const gipc_tune& t) {
+    auto w = [](int v) { return v == 1 || v == 2 || v == 4 || v == 8; };
+    return w(t.eval_waves) && w(t.offdiag_waves) &&
+           (t.row_lanes == 4 || t.row_lanes == 8 || t.row_lanes == 16 || t.row_lanes == 32);
+}
+
+}  // namespace
+
+static gipc_status eval_impl(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params, double* energy,
+                             double* grad, const double* diag, const gipc_bsr* A, bool assemble, void* stream) {
+    if (!ctx) return GIPC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    gipc_status st;
+    DevParams pm;
+    if ((st = eval_check(ctx, mesh, params, energy, grad, A, assemble, pm)) != GIPC_OK) return st;
+    if ((st = eval_prepare(ctx)) != GIPC_OK) return st;
+    CK(eval_enqueue(ctx, pm, mesh, energy, grad, diag, A, assemble, ctx->tune, S(stream)), "eval");
     ctx->evaluated = true;
     return GIPC_OK;
 }
@@ -384,14 +500,14 @@ gipc_status gipc_assemble_bsr(gipc_ctx* ctx, const double* diag, const gipc_bsr*
     if (!ctx->built || !ctx->evaluated) return fail(ctx, GIPC_ERR_STATE, "build and eval must precede assembly");
     if (!same_pattern(ctx, A)) return fail(ctx, GIPC_ERR_STATE, "A is not the pattern of the last build");
     hipStream_t s = S(stream);
-    const int64_t m0 = ctx->ranges.off[FT_EEM];
+    const int64_t m0 = ctx->ranges.off[FT_EEM], e0 = ctx->ranges.off[FT_EE];
     CK(launch_rows_diag(2, ctx->V, as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr), as<uint32_t>(ctx->contrib),
-                        as<double>(ctx->rec_main), as<double>(ctx->rec_extra), m0, diag, nullptr, A->val, A->dtype,
-                        ctx->nnzb, s),
+                        as<double>(ctx->rec_main), as<double>(ctx->rec_extra), e0, m0, diag, nullptr, nullptr, A->val,
+                        A->dtype, ctx->nnzb, ctx->tune.row_lanes, s),
        "diagonal blocks");
     CK(launch_offdiag(ctx->nnzb, as<int32_t>(ctx->slot_row), as<int32_t>(ctx->col_idx), as<int64_t>(ctx->cptr),
-                      as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra), m0, A->val,
-                      A->dtype, s),
+                      as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra), e0, m0,
+                      A->val, A->dtype, ctx->tune.offdiag_waves, s),
        "off-diagonal blocks");
     return GIPC_OK;
 }
@@ -442,6 +558,7 @@ gipc_status gipc_pair_inspect(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_p
         if ((st = check_mesh(ctx, mesh)) != GIPC_OK) return st;
         if ((st = to_dev_params(ctx, params, pm)) != GIPC_OK) return st;
         if (mesh->V != ctx->V) return fail(ctx, GIPC_ERR_STATE, "V differs from the build");
+        if ((st = bind_batch(ctx, params, pm)) != GIPC_OK) return st;
         x = mesh->x;
         xr = mesh->x_rest ? mesh->x_rest : mesh->x;
     }
@@ -455,6 +572,166 @@ gipc_status gipc_copy(const void* src, void* dst, int64_t bytes, void* stream) {
     if (bytes < 0 || (bytes > 0 && (!src || !dst))) return GIPC_ERR_INVALID_ARG;
     if (launch_copy(src, dst, bytes, S(stream)) != hipSuccess) return GIPC_ERR_HIP;
     return GIPC_OK;
+}
+
+// ---------------------------------------------------------------- tuning
+
+gipc_status gipc_get_tune(const gipc_ctx* ctx, gipc_tune* tune) {
+    if (!ctx || !tune) return GIPC_ERR_INVALID_ARG;
+    *tune = ctx->tune;
+    return GIPC_OK;
+}
+
+gipc_status gipc_set_tune(gipc_ctx* ctx, const gipc_tune* tune) {
+    if (!ctx || !tune) return GIPC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (!tune_ok(*tune))
+        return fail(ctx, GIPC_ERR_INVALID_ARG, "unsupported launch shape {%d, %d, %d}", tune->eval_waves,
+                    tune->row_lanes, tune->offdiag_waves);
+    ctx->tune = *tune;
+    return GIPC_OK;
+}
+
+gipc_status gipc_autotune(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params, double* energy,
+                          double* grad, const double* diag, const gipc_bsr* A, int32_t reps, gipc_tune* best,
+                          void* stream) {
+    if (!ctx) return GIPC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (reps < 1) return fail(ctx, GIPC_ERR_INVALID_ARG, "reps must be >= 1");
+    gipc_status st;
+    DevParams pm;
+    if ((st = eval_check(ctx, mesh, params, energy, grad, A, true, pm)) != GIPC_OK) return st;
+    if ((st = eval_prepare(ctx)) != GIPC_OK) return st;
+    hipStream_t s = S(stream);
+    const double* xr = mesh->x_rest ? mesh->x_rest : mesh->x;
+    const TypeRanges& tr = ctx->ranges;
+    const int64_t m0 = tr.off[FT_EEM], e0 = tr.off[FT_EE];
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    CK(hipEventCreate(&ev0), "event");
+    if (hipEventCreate(&ev1) != hipSuccess) {
+        (void)hipEventDestroy(ev0);
+        return fail(ctx, GIPC_ERR_HIP, "event");
+    }
+    hipError_t err = hipSuccess;
+    // one warm-up launch, then `reps` timed launches of the same kernel
+    auto time_it = [&](auto launch) -> float {
+        float ms = INFINITY;
+        if (err != hipSuccess) return ms;
+        if ((err = launch()) != hipSuccess) return ms;
+        if ((err = hipEventRecord(ev0, s)) != hipSuccess) return ms;
+        for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch();
+        if (err == hipSuccess) err = hipEventRecord(ev1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(ev1);
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, ev0, ev1);
+        return ms;
+    };
+    gipc_tune t = ctx->tune;
+    const int waves[4] = {1, 2, 4, 8}, lanes[4] = {4, 8, 16, 32};
+    float bt = INFINITY;
+    for (int w : waves) {
+        float ms = time_it([&] {
+            return launch_eval(as<int4>(ctx->st_vid), tr, mesh->x, xr, pm, as<double>(ctx->rec_main),
+                               as<double>(ctx->rec_extra), w, s);
+        });
+        if (ms < bt) { bt = ms; t.eval_waves = w; }
+    }
+    bt = INFINITY;
+    for (int l : lanes) {
+        float ms = time_it([&] {
+            return launch_rows_diag(3, ctx->V, as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr),
+                                    as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra),
+                                    e0, m0, diag, grad, as<double>(ctx->ev), A->val, A->dtype, ctx->nnzb, l, s);
+        });
+        if (ms < bt) { bt = ms; t.row_lanes = l; }
+    }
+    bt = INFINITY;
+    for (int w : waves) {
+        float ms = time_it([&] {
+            return launch_offdiag(ctx->nnzb, as<int32_t>(ctx->slot_row), as<int32_t>(ctx->col_idx),
+                                  as<int64_t>(ctx->cptr), as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main),
+                                  as<double>(ctx->rec_extra), e0, m0, A->val, A->dtype, w, s);
+        });
+        if (ms < bt) { bt = ms; t.offdiag_waves = w; }
+    }
+    if (err == hipSuccess)
+        err = launch_energy(as<double>(ctx->ev), as<int2>(ctx->pieces), ctx->npieces, as<int32_t>(ctx->poff),
+                            ctx->S, as<double>(ctx->epart), energy, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    if (err != hipSuccess) return hip_fail(ctx, err, "autotune");
+    ctx->tune = t;
+    ctx->evaluated = true;
+    if (best) *best = t;
+    return GIPC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- graphs
+
+struct gipc_graph {
+    gipc_ctx* ctx = nullptr;
+    uint64_t gen = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+gipc_status gipc_graph_create(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params, double* energy,
+                              double* grad, const double* diag, const gipc_bsr* A, gipc_graph** out) {
+    if (!ctx || !out) return GIPC_ERR_INVALID_ARG;
+    *out = nullptr;
+    ctx->err.clear();
+    gipc_status st;
+    DevParams pm;
+    if ((st = eval_check(ctx, mesh, params, energy, grad, A, true, pm)) != GIPC_OK) return st;
+    if ((st = eval_prepare(ctx)) != GIPC_OK) return st;
+    gipc_graph* g = new (std::nothrow) gipc_graph();
+    if (!g) return fail(ctx, GIPC_ERR_WORKSPACE, "graph handle");
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) {
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t le = eval_enqueue(ctx, pm, mesh, energy, grad, diag, A, true, ctx->tune, cs);
+            e = hipStreamEndCapture(cs, &g->graph);
+            if (le != hipSuccess) e = le;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        (void)hipStreamDestroy(cs);
+    }
+    if (e != hipSuccess) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        delete g;
+        return hip_fail(ctx, e, "graph capture");
+    }
+    g->ctx = ctx;
+    g->gen = ctx->build_gen;
+    *out = g;
+    return GIPC_OK;
+}
+
+gipc_status gipc_graph_launch(gipc_graph* g, void* stream) {
+    if (!g || !g->ctx) return GIPC_ERR_INVALID_ARG;
+    gipc_ctx* ctx = g->ctx;
+    ctx->err.clear();
+    gipc_status st;
+    if ((st = check_device(ctx)) != GIPC_OK) return st;
+    if (g->gen != ctx->build_gen || !ctx->built)
+        return fail(ctx, GIPC_ERR_STATE, "the graph was captured before the last gipc_pairs_build");
+    CK(hipGraphLaunch(g->exec, S(stream)), "graph launch");
+    ctx->evaluated = true;
+    return GIPC_OK;
+}
+
+void gipc_graph_destroy(gipc_graph* g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
 }
 
 }  // extern "C"

@@ -4,15 +4,12 @@
 // with g_i = c_i w~ (slot i of grad f) and s_i = (-u, u, -v, v)_i (slot i of
 // grad sqrt(c), mollified pairs only).  The gradient of vertex r gathers
 // a2 g_i + a1 s_i over the contributions of its diagonal block, which are
-// exactly its incidences (i = j).
+// exactly its incidences (i = j); the same pass sums the energies of the
+// pairs whose slot 0 is r.
 #include "internal.hpp"
 
 namespace gipc {
 namespace {
-
-__device__ __forceinline__ double coef(const double* m, int i) {
-    return i < 3 ? m[i] : -(m[0] + m[1] + m[2]);
-}
 
 __device__ __forceinline__ d3 sq_slot(const double* x, int i) {
     // (-u, u, -v, v)
@@ -26,13 +23,16 @@ __device__ __forceinline__ void add_outer(double* B, double s, d3 a, d3 b) {
     B[6] += s * a.z * b.x; B[7] += s * a.z * b.y; B[8] += s * a.z * b.z;
 }
 
-// one local block (i, j) of pair k added to B
+// one local block (i, j) of pair k added to B; pairs from e0 on are of the
+// edge-edge family, from m0 on mollified
 __device__ __forceinline__ void add_block(double* B, const double* __restrict__ rec_main,
-                                          const double* __restrict__ rec_extra, int64_t m0, uint32_t k, int i, int j) {
+                                          const double* __restrict__ rec_extra, int64_t e0, int64_t m0, uint32_t k,
+                                          int i, int j) {
     const double* m = rec_main + 8 * (int64_t)k;
-    d3 wt = mk(m[3], m[4], m[5]);
-    d3 gi = coef(m, i) * wt, gj = coef(m, j) * wt;
-    add_outer(B, m[6], gi, gj);
+    const bool ee = (int64_t)k >= e0;
+    d3 wt = mk(m[R_W], m[R_W + 1], m[R_W + 2]);
+    d3 gi = rec_coef(m, i, ee) * wt, gj = rec_coef(m, j, ee) * wt;
+    add_outer(B, m[R_P22], gi, gj);
     if ((int64_t)k >= m0) {
         const double* x = rec_extra + 9 * ((int64_t)k - m0);
         d3 si = sq_slot(x, i), sj = sq_slot(x, j);
@@ -54,56 +54,59 @@ __device__ __forceinline__ void store_block(void* val, int dtype, int64_t nnzb, 
     }
 }
 
-// kRowLanes lanes per block row: each lane sums every kRowLanes-th
-// contribution of the row's diagonal list, then a fixed xor butterfly
-// combines the lanes (same order on every run).
-constexpr int kRowLanes = 16;
-
+// LANES lanes per block row: each lane sums every LANES-th contribution of
+// the row's diagonal list, then a fixed xor butterfly combines the lanes
+// (same order on every run for a given LANES).
+template <int LANES>
 __global__ void __launch_bounds__(kBlock) k_rows_diag(int mode, int32_t V, const int32_t* __restrict__ diag_slot,
                                                       const int64_t* __restrict__ cptr,
                                                       const uint32_t* __restrict__ contrib,
                                                       const double* __restrict__ rec_main,
-                                                      const double* __restrict__ rec_extra, int64_t m0,
+                                                      const double* __restrict__ rec_extra, int64_t e0, int64_t m0,
                                                       const double* __restrict__ diag, double* __restrict__ grad,
-                                                      void* val, int dtype, int64_t nnzb) {
-    const int64_t r = (int64_t)blockIdx.x * (kBlock / kRowLanes) + threadIdx.x / kRowLanes;
-    const int lg = threadIdx.x % kRowLanes;
+                                                      double* __restrict__ ev, void* val, int dtype, int64_t nnzb) {
+    const int64_t r = (int64_t)blockIdx.x * (kBlock / LANES) + threadIdx.x / LANES;
+    const int lg = threadIdx.x % LANES;
     const bool valid = r < V;
     double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     d3 g = mk(0, 0, 0);
+    double e = 0.0;
     int32_t s = 0;
     if (valid) {
         s = diag_slot[r];
         const int64_t t0 = cptr[s], t1 = cptr[s + 1];
-        for (int64_t t = t0 + lg; t < t1; t += kRowLanes) {
+        for (int64_t t = t0 + lg; t < t1; t += LANES) {
             uint32_t code = contrib[t];
             uint32_t k = code >> 4;
             int i = (int)((code >> 2) & 3u);
             if (mode & 1) {
                 const double* m = rec_main + 8 * (int64_t)k;
-                d3 gi = coef(m, i) * mk(m[3], m[4], m[5]);
-                g = g + m[7] * gi;
+                d3 gi = rec_coef(m, i, (int64_t)k >= e0) * mk(m[R_W], m[R_W + 1], m[R_W + 2]);
+                g = g + m[R_A2] * gi;
+                if (i == 0) e += m[R_E];
                 if ((int64_t)k >= m0) {
                     const double* x = rec_extra + 9 * ((int64_t)k - m0);
                     g = g + x[8] * sq_slot(x, i);
                 }
             }
-            if (mode & 2) add_block(B, rec_main, rec_extra, m0, k, i, i);
+            if (mode & 2) add_block(B, rec_main, rec_extra, e0, m0, k, i, i);
         }
     }
 #pragma unroll
-    for (int o = kRowLanes / 2; o > 0; o >>= 1) {
-        g.x += __shfl_xor(g.x, o, kRowLanes);
-        g.y += __shfl_xor(g.y, o, kRowLanes);
-        g.z += __shfl_xor(g.z, o, kRowLanes);
+    for (int o = LANES / 2; o > 0; o >>= 1) {
+        g.x += __shfl_xor(g.x, o, LANES);
+        g.y += __shfl_xor(g.y, o, LANES);
+        g.z += __shfl_xor(g.z, o, LANES);
+        e += __shfl_xor(e, o, LANES);
 #pragma unroll
-        for (int c = 0; c < 9; ++c) B[c] += __shfl_xor(B[c], o, kRowLanes);
+        for (int c = 0; c < 9; ++c) B[c] += __shfl_xor(B[c], o, LANES);
     }
     if (!valid || lg != 0) return;
     if (mode & 1) {
         grad[3 * r + 0] = g.x;
         grad[3 * r + 1] = g.y;
         grad[3 * r + 2] = g.z;
+        ev[r] = e;
     }
     if (mode & 2) {
         double dv = diag ? diag[r] : 0.0;
@@ -112,21 +115,22 @@ __global__ void __launch_bounds__(kBlock) k_rows_diag(int mode, int32_t V, const
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_offdiag(int64_t nnzb, const int32_t* __restrict__ slot_row,
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_offdiag(int64_t nnzb, const int32_t* __restrict__ slot_row,
                                                     const int32_t* __restrict__ col_idx,
                                                     const int64_t* __restrict__ cptr,
                                                     const uint32_t* __restrict__ contrib,
                                                     const double* __restrict__ rec_main,
-                                                    const double* __restrict__ rec_extra, int64_t m0, void* val,
-                                                    int dtype) {
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+                                                    const double* __restrict__ rec_extra, int64_t e0, int64_t m0,
+                                                    void* val, int dtype) {
+    const int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (s >= nnzb) return;
     if (col_idx[s] == slot_row[s]) return;  // diagonal blocks: k_rows_diag
     double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t t0 = cptr[s], t1 = cptr[s + 1];
     for (int64_t t = t0; t < t1; ++t) {
         uint32_t code = contrib[t];
-        add_block(B, rec_main, rec_extra, m0, code >> 4, (int)((code >> 2) & 3u), (int)(code & 3u));
+        add_block(B, rec_main, rec_extra, e0, m0, code >> 4, (int)((code >> 2) & 3u), (int)(code & 3u));
     }
     store_block(val, dtype, nnzb, s, B);
 }
@@ -143,7 +147,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_inspect(const int4* __restrict_
     if (k >= tr.off[8]) return;
     const int ft = type_of(k, tr);
     const int4 v4 = st_vid[k];
-    const int64_t m0 = tr.off[FT_EEM];
+    const int64_t m0 = tr.off[FT_EEM], e0 = tr.off[FT_EE];
     if (src) src[k] = st_src[k];
     if (type) type[k] = ft;
     if (vid) {
@@ -161,7 +165,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_inspect(const int4* __restrict_
         for (int i = 0; i < 4; ++i) {
             d3 g = mk(0, 0, 0);
             if (i < nv) {
-                g = m[7] * (coef(m, i) * mk(m[3], m[4], m[5]));
+                g = m[R_A2] * (rec_coef(m, i, k >= e0) * mk(m[R_W], m[R_W + 1], m[R_W + 2]));
                 if (k >= m0) {
                     const double* x = rec_extra + 9 * (k - m0);
                     g = g + x[8] * sq_slot(x, i);
@@ -176,7 +180,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_inspect(const int4* __restrict_
         for (int i = 0; i < 4; ++i)
             for (int j = 0; j < 4; ++j) {
                 double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-                if (i < nv && j < nv) add_block(B, rec_main, rec_extra, m0, (uint32_t)k, i, j);
+                if (i < nv && j < nv) add_block(B, rec_main, rec_extra, e0, m0, (uint32_t)k, i, j);
                 for (int a = 0; a < 3; ++a)
                     for (int b = 0; b < 3; ++b) hess[144 * k + (3 * i + a) * 12 + 3 * j + b] = B[3 * a + b];
             }
@@ -185,24 +189,61 @@ __global__ void __launch_bounds__(kBlock) k_pair_inspect(const int4* __restrict_
 
 }  // namespace
 
-hipError_t launch_rows_diag(int mode, int32_t V, const int32_t* diag_slot, const int64_t* cptr,
-                            const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t m0,
-                            const double* diag, double* grad, void* val, int dtype, int64_t nnzb, hipStream_t s) {
-    if (V == 0) return hipSuccess;
-    const int64_t nb = ((int64_t)V * kRowLanes + kBlock - 1) / kBlock;
-    k_rows_diag<<<(unsigned)nb, kBlock, 0, s>>>(mode, V, diag_slot, cptr, contrib, rec_main, rec_extra, m0, diag, grad,
-                                                val, dtype, nnzb);
+namespace {
+template <int LANES>
+hipError_t rows_launch(int mode, int32_t V, const int32_t* diag_slot, const int64_t* cptr, const uint32_t* contrib,
+                       const double* rec_main, const double* rec_extra, int64_t e0, int64_t m0, const double* diag,
+                       double* grad, double* ev, void* val, int dtype, int64_t nnzb, hipStream_t s) {
+    const int64_t nb = ((int64_t)V * LANES + kBlock - 1) / kBlock;
+    k_rows_diag<LANES><<<(unsigned)nb, kBlock, 0, s>>>(mode, V, diag_slot, cptr, contrib, rec_main, rec_extra, e0, m0,
+                                                       diag, grad, ev, val, dtype, nnzb);
     return hipGetLastError();
 }
+}  // namespace
+
+hipError_t launch_rows_diag(int mode, int32_t V, const int32_t* diag_slot, const int64_t* cptr,
+                            const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t e0,
+                            int64_t m0, const double* diag, double* grad, double* ev, void* val, int dtype,
+                            int64_t nnzb, int lanes, hipStream_t s) {
+    if (V == 0) return hipSuccess;
+    switch (lanes) {
+        case 4: return rows_launch<4>(mode, V, diag_slot, cptr, contrib, rec_main, rec_extra, e0, m0, diag, grad, ev,
+                                      val, dtype, nnzb, s);
+        case 8: return rows_launch<8>(mode, V, diag_slot, cptr, contrib, rec_main, rec_extra, e0, m0, diag, grad, ev,
+                                      val, dtype, nnzb, s);
+        case 32: return rows_launch<32>(mode, V, diag_slot, cptr, contrib, rec_main, rec_extra, e0, m0, diag, grad, ev,
+                                        val, dtype, nnzb, s);
+        default: return rows_launch<16>(mode, V, diag_slot, cptr, contrib, rec_main, rec_extra, e0, m0, diag, grad,
+                                        ev, val, dtype, nnzb, s);
+    }
+}
+
+namespace {
+template <int BLOCK>
+hipError_t offdiag_launch(int64_t nnzb, const int32_t* slot_row, const int32_t* col_idx, const int64_t* cptr,
+                          const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t e0,
+                          int64_t m0, void* val, int dtype, hipStream_t s) {
+    const int64_t nb = (nnzb + BLOCK - 1) / BLOCK;
+    k_offdiag<BLOCK><<<(unsigned)nb, BLOCK, 0, s>>>(nnzb, slot_row, col_idx, cptr, contrib, rec_main, rec_extra, e0,
+                                                    m0, val, dtype);
+    return hipGetLastError();
+}
+}  // namespace
 
 hipError_t launch_offdiag(int64_t nnzb, const int32_t* slot_row, const int32_t* col_idx, const int64_t* cptr,
-                          const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t m0,
-                          void* val, int dtype, hipStream_t s) {
+                          const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t e0,
+                          int64_t m0, void* val, int dtype, int waves, hipStream_t s) {
     if (nnzb == 0) return hipSuccess;
-    const int64_t nb = (nnzb + kBlock - 1) / kBlock;
-    k_offdiag<<<(unsigned)nb, kBlock, 0, s>>>(nnzb, slot_row, col_idx, cptr, contrib, rec_main, rec_extra, m0, val,
-                                              dtype);
-    return hipGetLastError();
+    switch (waves) {
+        case 1: return offdiag_launch<64>(nnzb, slot_row, col_idx, cptr, contrib, rec_main, rec_extra, e0, m0, val,
+                                          dtype, s);
+        case 2: return offdiag_launch<128>(nnzb, slot_row, col_idx, cptr, contrib, rec_main, rec_extra, e0, m0, val,
+                                           dtype, s);
+        case 8: return offdiag_launch<512>(nnzb, slot_row, col_idx, cptr, contrib, rec_main, rec_extra, e0, m0, val,
+                                           dtype, s);
+        default: return offdiag_launch<256>(nnzb, slot_row, col_idx, cptr, contrib, rec_main, rec_extra, e0, m0, val,
+                                            dtype, s);
+    }
 }
 
 hipError_t launch_pair_inspect(const int4* st_vid, const int32_t* st_src, TypeRanges tr, const double* rec_main,

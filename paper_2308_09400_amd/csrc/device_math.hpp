@@ -79,7 +79,25 @@ __device__ __forceinline__ d3 ld3(const double* __restrict__ X, int v) {
 struct DevParams {
     double dhat, kappa, dthr_ratio, epsx_ratio;
     int filter, mollify, eq12;
+    // batches of independent scenes: scene id per vertex and the scenes'
+    // dhat and kappa (all NULL for a single scene, which uses dhat, kappa)
+    const int32_t* vscene;
+    const double* dhat_s;
+    const double* kappa_s;
 };
+
+// dhat and kappa of the scene that owns vertex v (every vertex of a staged
+// pair belongs to the same scene)
+__device__ __forceinline__ void scene_params(const DevParams& pm, int v, double& dhat, double& kappa) {
+    if (pm.vscene) {
+        const int s = pm.vscene[v];
+        dhat = pm.dhat_s[s];
+        kappa = pm.kappa_s[s];
+    } else {
+        dhat = pm.dhat;
+        kappa = pm.kappa;
+    }
+}
 
 // point P against segment AB: squared distance, clamped parameter
 __device__ __forceinline__ double seg_dist2(d3 P, d3 A, d3 B, double& al) {
@@ -263,6 +281,22 @@ struct PairFactors {
     double P11, P12, a1;
 };
 
+// Stored main record of an evaluated pair, 8 doubles (64 B):
+//   [c1, c2, w~x, w~y, w~z, P22, a2, E]
+// c0 and c3 follow from the family of the sub-type: the point-first kinds
+// (PT, PE, PP) have c0 = 1 and c0 + c1 + c2 + c3 = 0; the edge-edge kinds
+// (EE, EEM, PEM, PPM) have c0 + c1 = 1 and c2 + c3 = -1.  The staged order
+// puts the edge-edge family last, from the first EE pair on.
+// Extra record of a mollified pair, 9 doubles: [u, v, P11, P12, a1].
+enum RecIdx { R_C1 = 0, R_C2 = 1, R_W = 2, R_P22 = 5, R_A2 = 6, R_E = 7 };
+
+__device__ __forceinline__ double rec_coef(const double* m, int i, bool ee_family) {
+    if (i == 1) return m[R_C1];
+    if (i == 2) return m[R_C2];
+    if (ee_family) return i == 0 ? 1.0 - m[R_C1] : -1.0 - m[R_C2];
+    return i == 0 ? 1.0 : -((1.0 + m[R_C1]) + m[R_C2]);
+}
+
 __device__ inline void eval_typed(int ft, const int* v, const double* __restrict__ X, const double* __restrict__ XR,
                                   const DevParams& pm, PairFactors& o) {
     o.E = 0.0;
@@ -312,7 +346,8 @@ __device__ inline void eval_typed(int ft, const int* v, const double* __restrict
         c0 = 1.0 - g1; c1 = g1; c2 = -(1.0 - g2); c3 = -g2;
     }
 
-    const double dhat = pm.dhat, kappa = pm.kappa;
+    double dhat, kappa;
+    scene_params(pm, v[0], dhat, kappa);
     double d2 = dot(w, w);
     if (!(d2 > 0.0) || !(d2 < dhat * dhat)) return;  // inactive or degenerate: no contribution
     double d = sqrt(d2), f = d / dhat, g = d2 / (dhat * dhat);

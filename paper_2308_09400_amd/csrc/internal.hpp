@@ -15,6 +15,7 @@ namespace gipc {
 constexpr int kBlock = 256;          // threads per workgroup (4 waves of 64)
 constexpr int kScanItems = 8;        // elements per thread in the scans
 constexpr int kMaxRowPairs = 2048;   // pairs touching one vertex (LDS sort capacity, 64 KiB)
+constexpr int kEnergyPiece = 8192;   // vertices per energy piece
 
 // Grow-only device buffer.
 struct DevBuf {
@@ -80,8 +81,16 @@ struct gipc_ctx {
         diag_slot, maxbuf;
     int64_t nnzb = 0, K = 0;
     int32_t max_deg = 0;
-    // factors of the last eval
-    gipc::DevBuf rec_main, rec_extra, e_part;
+    // scenes of the build: scene id per vertex (batches only), energy pieces
+    // (vertex ranges of at most kEnergyPiece inside one scene) and the
+    // scenes' piece offsets
+    gipc::DevBuf vscene, pieces, poff;
+    int32_t S = 1, npieces = 0;
+    bool batched = false;
+    // factors of the last eval; per-vertex energy shares and piece sums
+    gipc::DevBuf rec_main, rec_extra, ev, epart;
+    // launch shapes (gipc_tune)
+    gipc_tune tune{4, 16, 4};
     // PCG workspace
     gipc::DevBuf r, z, p, q, p32, minv, part, scal;
     // scan scratch
@@ -90,6 +99,7 @@ struct gipc_ctx {
     gipc_info info{};
     bool built = false;
     bool evaluated = false;
+    uint64_t build_gen = 0;  // bumped by every gipc_pairs_build (graphs check it)
 };
 
 namespace gipc {
@@ -104,6 +114,7 @@ hipError_t exclusive_scan(const TIn* in, int64_t n, TOut* out, gipc_ctx* ctx, hi
 hipError_t reduce_max_i32(const int32_t* in, int64_t n, int32_t* out_dev, hipStream_t s);
 
 // ---- stage.hip
+hipError_t launch_vertex_scene(const int32_t* vert_off, int32_t S, int32_t V, int32_t* vscene, hipStream_t s);
 hipError_t launch_stage_classify(const int32_t* tuples, int64_t P, int32_t V, const double* x, const double* xr,
                                  const DevParams& pm, uint8_t* ft, int4* vid, int32_t* bcount, int64_t* counters,
                                  hipStream_t s);
@@ -123,19 +134,24 @@ hipError_t launch_sym_fill(int32_t V, const int64_t* kptr, const int32_t* kcol, 
                            hipStream_t s);
 
 // ---- eval.hip
+// waves: workgroup size in wavefronts (1, 2, 4 or 8)
 hipError_t launch_eval(const int4* st_vid, TypeRanges tr, const double* x, const double* xr, const DevParams& pm,
-                       double* rec_main, double* rec_extra, double* e_part, hipStream_t s);
-hipError_t launch_energy_final(const double* e_part, int64_t nparts, double* energy, hipStream_t s);
-int64_t eval_num_parts(int64_t Ps);
+                       double* rec_main, double* rec_extra, int waves, hipStream_t s);
+// per-scene energies from the per-vertex shares: pieces, then scenes
+hipError_t launch_energy(const double* ev, const int2* pieces, int32_t npieces, const int32_t* poff, int32_t S,
+                         double* part, double* energy, hipStream_t s);
 
 // ---- assemble.hip
-// mode bit 1: gradient, bit 2: diagonal block values
+// mode bit 1: gradient and per-vertex energy shares, bit 2: diagonal block
+// values; lanes per row: 4, 8, 16 or 32
 hipError_t launch_rows_diag(int mode, int32_t V, const int32_t* diag_slot, const int64_t* cptr,
-                            const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t m0,
-                            const double* diag, double* grad, void* val, int dtype, int64_t nnzb, hipStream_t s);
+                            const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t e0,
+                            int64_t m0, const double* diag, double* grad, double* ev, void* val, int dtype,
+                            int64_t nnzb, int lanes, hipStream_t s);
+// waves: workgroup size in wavefronts (1, 2, 4 or 8)
 hipError_t launch_offdiag(int64_t nnzb, const int32_t* slot_row, const int32_t* col_idx, const int64_t* cptr,
-                          const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t m0,
-                          void* val, int dtype, hipStream_t s);
+                          const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t e0,
+                          int64_t m0, void* val, int dtype, int waves, hipStream_t s);
 hipError_t launch_pair_inspect(const int4* st_vid, const int32_t* st_src, TypeRanges tr, const double* rec_main,
                                const double* rec_extra, const double* x, const double* xr, const DevParams& pm,
                                int32_t* src, int32_t* type, int32_t* vid, double* energy, double* grad,

@@ -10,8 +10,9 @@
 namespace gipc {
 namespace {
 
-// counters[0] malformed tuples, [1] first malformed index,
-// counters[2] degenerate pairs, [3] first degenerate index
+// counters (relative to the pointer the kernel gets): [0] malformed tuples,
+// [1] first malformed index, [2] degenerate pairs, [3] first degenerate
+// index, [20] tuples whose vertices lie in different scenes, [21] the first
 __device__ __forceinline__ void flag_index(unsigned long long* cnt, unsigned long long* first, int64_t p) {
     atomicAdd(cnt, 1ull);
     atomicMin(first, (unsigned long long)p);
@@ -50,8 +51,15 @@ __global__ void __launch_bounds__(kBlock) k_stage_classify(const int4* __restric
             ok = v[k] >= 0 && v[k] < V;
             for (int l = 0; l < k && ok; ++l) ok = v[l] != v[k];
         }
+        bool same_scene = true;
+        if (ok && pm.vscene) {
+            const int s0 = pm.vscene[v[0]];
+            for (int k = 1; k < nv; ++k) same_scene = same_scene && pm.vscene[v[k]] == s0;
+        }
         if (!ok) {
             flag_index(&counters[0], &counters[1], p);
+        } else if (!same_scene) {
+            flag_index(&counters[20], &counters[21], p);
         } else {
             double d2;
             Staged s;
@@ -63,9 +71,11 @@ __global__ void __launch_bounds__(kBlock) k_stage_classify(const int4* __restric
                 d2 = dot(w, w);
                 s = Staged{FT_PP, {v[0], v[1], -1, -1}};
             }
+            double dhat, kappa;
+            scene_params(pm, v[0], dhat, kappa);
             if (!(d2 > 0.0) || !(d2 < INFINITY)) {
                 flag_index(&counters[2], &counters[3], p);
-            } else if (d2 < pm.dhat * pm.dhat) {
+            } else if (d2 < dhat * dhat) {
                 ft = s.ft;
                 vo = make_int4(s.v[0], s.v[1], s.v[2], s.v[3]);
             }
@@ -145,6 +155,29 @@ __global__ void k_stage_offsets(const int64_t* __restrict__ boff, int64_t nb, in
 
 hipError_t launch_stage_offsets(const int64_t* boff, int64_t nb, int64_t* out, hipStream_t s) {
     k_stage_offsets<<<1, 64, 0, s>>>(boff, nb, out);
+    return hipGetLastError();
+}
+
+namespace {
+// scene of every vertex: the last s with vert_off[s] <= v (vert_off is
+// non-decreasing with vert_off[0] = 0 and vert_off[S] = V, checked on the host)
+__global__ void __launch_bounds__(kBlock) k_vertex_scene(const int32_t* __restrict__ vert_off, int32_t S, int32_t V,
+                                                         int32_t* __restrict__ vscene) {
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= V) return;
+    int lo = 0, hi = S - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (vert_off[mid] <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    vscene[v] = lo;
+}
+}  // namespace
+
+hipError_t launch_vertex_scene(const int32_t* vert_off, int32_t S, int32_t V, int32_t* vscene, hipStream_t s) {
+    if (V == 0) return hipSuccess;
+    k_vertex_scene<<<(unsigned)((V + kBlock - 1) / kBlock), kBlock, 0, s>>>(vert_off, S, V, vscene);
     return hipGetLastError();
 }
 }  // namespace gipc

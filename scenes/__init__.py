@@ -268,3 +268,78 @@ def cube_lattice(m: int = 6, n: int = 10, dhat: float = 1e-3, kappa: float = 1e4
     tuples = broadphase(x, vobj, tris, edges, dhat) if with_pairs else np.zeros((0, 4), np.int32)
     return Scene(f"cube_lattice_{m}x{n}", x, x.copy(), tris, edges, vobj, dhat, kappa, tuples,
                  meta=dict(m=m, n=n, seed=seed, gaps=gaps))
+
+
+@dataclass
+class BatchScene:
+    """Independent scenes concatenated into one vertex array and one tuple
+    list: scene s owns vertices ``[vert_off[s], vert_off[s+1])`` and tuples
+    ``[pair_off[s], pair_off[s+1])``, with its own dhat and kappa."""
+
+    name: str
+    x: np.ndarray
+    x_rest: np.ndarray
+    tuples: np.ndarray
+    vert_off: np.ndarray
+    pair_off: np.ndarray
+    dhat: np.ndarray
+    kappa: np.ndarray
+    scenes: list
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def V(self) -> int:
+        return int(self.x.shape[0])
+
+    @property
+    def P(self) -> int:
+        return int(self.tuples.shape[0])
+
+    @property
+    def S(self) -> int:
+        return len(self.scenes)
+
+
+def offset_tuples(tuples: np.ndarray, off: int) -> np.ndarray:
+    """Shift the vertex ids of sign-encoded tuples by ``off``: columns 0 and 1
+    hold ids or -(id+1), columns 2 and 3 ids or -1 (unused)."""
+    t = np.asarray(tuples, dtype=np.int64).copy()
+    for c in (0, 1):
+        t[:, c] = np.where(t[:, c] >= 0, t[:, c] + off, t[:, c] - off)
+    for c in (2, 3):
+        t[:, c] = np.where(t[:, c] >= 0, t[:, c] + off, t[:, c])
+    return t.astype(np.int32)
+
+
+def concat_scenes(scenes: list, name: str = "batch") -> BatchScene:
+    """Concatenate scenes (each with its own dhat and kappa) into one batch."""
+    vo, po = [0], [0]
+    xs, xr, ts = [], [], []
+    for sc in scenes:
+        ts.append(offset_tuples(sc.tuples, vo[-1]))
+        xs.append(sc.x)
+        xr.append(sc.x_rest)
+        vo.append(vo[-1] + sc.V)
+        po.append(po[-1] + sc.P)
+    tuples = np.concatenate(ts) if ts else np.zeros((0, 4), np.int32)
+    return BatchScene(name, np.concatenate(xs), np.concatenate(xr), np.ascontiguousarray(tuples),
+                      np.array(vo, np.int32), np.array(po, np.int64),
+                      np.array([sc.dhat for sc in scenes]), np.array([sc.kappa for sc in scenes]), list(scenes))
+
+
+def batch_two_sheets(S: int = 64, r_lo: int = 32, r_hi: int = 256, dhat_lo: float = 1e-4, dhat_hi: float = 1e-2,
+                     kappa: float = 1e4, seed_base: int = 1000) -> BatchScene:
+    """``S`` two-sheet scenes (the recipe of ``two_sheets``): scene s draws,
+    from seed ``seed_base + s``, its resolution r uniform in ``r_lo..r_hi``
+    vertices per side and dhat log-uniform in ``[dhat_lo, dhat_hi]``; the
+    upper sheet sits at 0.5 dhat with +-0.2 dhat jitter."""
+    scenes = []
+    for s in range(S):
+        rng = np.random.default_rng(seed_base + s)
+        r = int(rng.integers(r_lo, r_hi + 1))
+        dhat = float(10.0 ** rng.uniform(np.log10(dhat_lo), np.log10(dhat_hi)))
+        scenes.append(two_sheets(n=r, dhat=dhat, kappa=kappa, seed=seed_base + s))
+    b = concat_scenes(scenes, name=f"batch_two_sheets_{S}")
+    b.meta = dict(S=S, r_lo=r_lo, r_hi=r_hi, dhat_lo=dhat_lo, dhat_hi=dhat_hi, seed_base=seed_base,
+                  r=[sc.meta["n"] for sc in scenes])
+    return b
