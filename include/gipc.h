@@ -48,6 +48,7 @@ typedef enum {
 #define GIPC_FLAG_FILTER 0x1u        /* eigenvalue filter of Eq. 23 */
 #define GIPC_FLAG_MOLLIFY 0x2u       /* nearly-parallel edge-edge mollifier, Eq. 25-36 */
 #define GIPC_FLAG_BARRIER_EQ12 0x4u  /* non-stiffened barrier Eq. 12 instead of Eq. 24 (test mode) */
+#define GIPC_FLAG_NO_MERGE 0x8u      /* gipc_pairs_build: keep duplicate reduced constraints apart */
 #define GIPC_FLAGS_DEFAULT (GIPC_FLAG_FILTER | GIPC_FLAG_MOLLIFY)
 
 /* A batch of independent scenes concatenated into one mesh and one tuple
@@ -123,6 +124,8 @@ typedef struct {
     int64_t n_active;       /* pairs closer than dhat after classification */
     int64_t n_by_type[8];   /* active pairs by sub-type: [1] PT, [2] PE, [3] PP, [4] EE,
                                [5] EE, [6] PE, [7] PP cut from mollified edge-edge pairs */
+    int64_t n_staged;       /* staged pairs after merging duplicate PE / PP constraints */
+    int64_t n_staged_by_type[8]; /* staged pairs by sub-type (as n_by_type) */
     int64_t n_degenerate;   /* pairs at distance 0 or with non-finite positions (skipped) */
     int64_t first_degenerate; /* tuple index of the first one, -1 if none */
     int64_t nnzb;           /* blocks of the assembled matrix */
@@ -152,6 +155,11 @@ const char* gipc_ctx_last_error(const gipc_ctx* ctx);
  * pattern of diag + sum_k S_k^T H_k S_k over the vertices each pair's
  * distance depends on (all four for mollified edge-edge pairs).
  * With params->batch, each tuple is tested against its own scene's dhat.
+ * Active point-edge and point-point constraints with the same vertices
+ * (the point and the unordered edge, or the unordered vertex pair) are
+ * merged into one staged pair with an integer multiplicity that scales its
+ * energy, gradient and Hessian: the sum of Eq. 3 over the candidates is
+ * unchanged (up to rounding order).  GIPC_FLAG_NO_MERGE keeps them apart.
  * Synchronises `stream` (three times, four with a batch) to size the
  * pattern; `info` (host, nullable) receives the counts.  Errors:
  * INVALID_ARG, INDEX (no state is kept), WORKSPACE (a vertex touched by
@@ -221,18 +229,20 @@ gipc_status gipc_pcg(gipc_ctx* ctx, const gipc_bsr* A, const double* b, double* 
 /*
  * Inspection of the staged pairs of the last build and the factors of the
  * last eval, expanded per pair (for tests and tooling).  Device buffers sized
- * for info.n_active pairs, each nullable:
- *   src [Pa] int32        tuple index each staged pair came from
+ * for info.n_staged pairs, each nullable:
+ *   src [Pa] int32        tuple index each staged pair came from (the first
+ *                         tuple of a merged group)
  *   type [Pa] int32       sub-type code as in gipc_info.n_by_type
  *   vid [Pa][4] int32     vertex ids of the staged stencil (-1 unused)
- *   energy [Pa] double    kappa e b of the pair, evaluated at mesh->x
- *   grad [Pa][12] double  local gradient over the 4 stencil slots  (needs an eval)
- *   hess [Pa][144] double local proxy Hessian, 12x12 row-major      (needs an eval)
+ *   mult [Pa] int32       number of candidate tuples the staged pair stands for
+ *   energy [Pa] double    mult * kappa e b of the pair, evaluated at mesh->x
+ *   grad [Pa][12] double  local gradient over the 4 stencil slots, times mult  (needs an eval)
+ *   hess [Pa][144] double local proxy Hessian, 12x12 row-major, times mult (needs an eval)
  * Errors: INVALID_ARG, STATE.
  */
 gipc_status gipc_pair_inspect(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params, int32_t* src,
-                              int32_t* type, int32_t* vid, double* energy, double* grad, double* hess,
-                              void* stream);
+                              int32_t* type, int32_t* vid, int32_t* mult, double* energy, double* grad,
+                              double* hess, void* stream);
 
 /* Plain device-to-device copy of `bytes` bytes with the library's own
  * streaming kernel (bandwidth reference for roofline fractions). */

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libgipc.so")
 
 OK, ERR_INVALID_ARG, ERR_INDEX, ERR_DEGENERATE, ERR_HIP, ERR_WORKSPACE, ERR_BREAKDOWN, ERR_STATE = 0, -1, -2, -3, -4, -5, -6, -7
 WARN_NOT_CONVERGED = 1
-FLAG_FILTER, FLAG_MOLLIFY, FLAG_BARRIER_EQ12 = 0x1, 0x2, 0x4
+FLAG_FILTER, FLAG_MOLLIFY, FLAG_BARRIER_EQ12, FLAG_NO_MERGE = 0x1, 0x2, 0x4, 0x8
 FLAGS_DEFAULT = FLAG_FILTER | FLAG_MOLLIFY
 F64, F32 = 0, 1
 SUBTYPES = {1: "PT", 2: "PE", 3: "PP", 4: "EE", 5: "EE_moll", 6: "PE_moll", 7: "PP_moll"}
@@ -69,12 +69,14 @@ class Bsr(ctypes.Structure):
 
 class Info(ctypes.Structure):
     _fields_ = [("n_candidates", ctypes.c_int64), ("n_active", ctypes.c_int64), ("n_by_type", ctypes.c_int64 * 8),
+                ("n_staged", ctypes.c_int64), ("n_staged_by_type", ctypes.c_int64 * 8),
                 ("n_degenerate", ctypes.c_int64), ("first_degenerate", ctypes.c_int64), ("nnzb", ctypes.c_int64),
                 ("n_contrib", ctypes.c_int64), ("max_row_pairs", ctypes.c_int32)]
 
     def as_dict(self):
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "n_by_type"}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("n_by_type", "n_staged_by_type")}
         d["n_by_type"] = {SUBTYPES[t]: int(self.n_by_type[t]) for t in range(1, 8)}
+        d["n_staged_by_type"] = {SUBTYPES[t]: int(self.n_staged_by_type[t]) for t in range(1, 8)}
         return d
 
 
@@ -105,7 +107,8 @@ def lib():
                                         ctypes.POINTER(Bsr), vp]),
             "gipc_bsr_spmv": (st, [ctypes.POINTER(Bsr), vp, vp, vp]),
             "gipc_pcg": (st, [vp, ctypes.POINTER(Bsr), vp, vp, d, i32, ctypes.POINTER(i32), ctypes.POINTER(d), vp]),
-            "gipc_pair_inspect": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), vp, vp, vp, vp, vp, vp, vp]),
+            "gipc_pair_inspect": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), vp, vp, vp, vp, vp, vp, vp,
+                                       vp]),
             "gipc_copy": (st, [vp, vp, i64, vp]),
             "gipc_get_tune": (st, [vp, ctypes.POINTER(Tune)]),
             "gipc_set_tune": (st, [vp, ctypes.POINTER(Tune)]),
@@ -345,11 +348,13 @@ def pcg(ctx: Context, A: BsrMatrix, b, x=None, rtol=1e-6, maxit=1000, stream=Non
 
 def pair_inspect(ctx: Context, x=None, prm: Params | None = None, x_rest=None, want=("src", "type", "vid"),
                  stream=None):
-    """Per staged pair: src, type, vid, energy, grad [12], hess [12,12] (device tensors)."""
-    n = int(ctx.info["n_active"]) if ctx.info else 0
+    """Per staged pair: src, type, vid, mult, energy, grad [12], hess [12,12]
+    (device tensors; energy, grad and hess include the multiplicity)."""
+    n = int(ctx.info["n_staged"]) if ctx.info else 0
     dev = torch.device("cuda", torch.cuda.current_device())
     out = {}
     alloc = {"src": ((n,), torch.int32), "type": ((n,), torch.int32), "vid": ((n, 4), torch.int32),
+             "mult": ((n,), torch.int32),
              "energy": ((n,), torch.float64), "grad": ((n, 12), torch.float64), "hess": ((n, 12, 12), torch.float64)}
     for k in want:
         shp, dt = alloc[k]
@@ -357,7 +362,8 @@ def pair_inspect(ctx: Context, x=None, prm: Params | None = None, x_rest=None, w
     mesh = Context._mesh(x, x_rest) if x is not None else None
     ctx._check(lib().gipc_pair_inspect(ctx.h, ctypes.byref(mesh) if mesh else None,
                                        ctypes.byref(prm) if prm else None,
-                                       *[_ptr(out.get(k)) for k in ("src", "type", "vid", "energy", "grad", "hess")],
+                                       *[_ptr(out.get(k)) for k in ("src", "type", "vid", "mult", "energy", "grad",
+                                                                    "hess")],
                                        _stream(stream)), "gipc_pair_inspect")
     return out
 

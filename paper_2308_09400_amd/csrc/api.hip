@@ -49,7 +49,9 @@ namespace {
 // counters layout (int64 slots of ctx->counters)
 enum {
     C_NBAD = 0, C_FIRST_BAD = 1, C_NDEG = 2, C_FIRST_DEG = 3, C_ACTIVE = 4, C_OFF = 5,  // 5..13: type offsets
-    C_INC = 16, C_K = 17, C_NNZB = 18, C_MAXDEG = 19, C_NSPAN = 20, C_FIRST_SPAN = 21, C_NSLOTS = 24
+    C_INC = 16, C_K = 17, C_NNZB = 18, C_MAXDEG = 19, C_NSPAN = 20, C_FIRST_SPAN = 21,
+    C_MOFF = 24,  // 24..32: merged type offsets
+    C_NSLOTS = 40
 };
 
 gipc_status fail(gipc_ctx* ctx, gipc_status st, const char* fmt, ...) {
@@ -92,7 +94,7 @@ gipc_status to_dev_params(gipc_ctx* ctx, const gipc_params* p, DevParams& o) {
         return fail(ctx, GIPC_ERR_INVALID_ARG, "dthr_ratio must be in [0, 1)");
     if (!(p->epsx_ratio >= 0.0) || !std::isfinite(p->epsx_ratio))
         return fail(ctx, GIPC_ERR_INVALID_ARG, "epsx_ratio must be >= 0");
-    if (p->flags & ~(GIPC_FLAG_FILTER | GIPC_FLAG_MOLLIFY | GIPC_FLAG_BARRIER_EQ12))
+    if (p->flags & ~(GIPC_FLAG_FILTER | GIPC_FLAG_MOLLIFY | GIPC_FLAG_BARRIER_EQ12 | GIPC_FLAG_NO_MERGE))
         return fail(ctx, GIPC_ERR_INVALID_ARG, "unknown flag bits 0x%x", p->flags);
     o.dhat = p->dhat;
     o.kappa = p->kappa;
@@ -191,7 +193,8 @@ void gipc_ctx_destroy(gipc_ctx* ctx) {
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(ctx->device);
     DevBuf* bufs[] = {&ctx->cand_ft, &ctx->cand_vid, &ctx->bcount, &ctx->boff, &ctx->counters, &ctx->st_vid,
-                      &ctx->st_src, &ctx->deg, &ctx->kcount, &ctx->fill, &ctx->inc_ptr, &ctx->kptr, &ctx->inc,
+                      &ctx->st_src, &ctx->mult, &ctx->mkeys, &ctx->mrep, &ctx->mrep_of, &ctx->mcount,
+                      &ctx->mflag, &ctx->mpos, &ctx->st_vid2, &ctx->st_src2, &ctx->deg, &ctx->kcount, &ctx->fill, &ctx->inc_ptr, &ctx->kptr, &ctx->inc,
                       &ctx->contrib, &ctx->kcol, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
                       &ctx->slot_row, &ctx->diag_slot, &ctx->maxbuf, &ctx->rec_main, &ctx->rec_extra, &ctx->ev,
                       &ctx->epart, &ctx->vscene, &ctx->pieces, &ctx->poff,
@@ -311,8 +314,17 @@ gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
     TypeRanges tr;
     for (int t = 0; t < 9; ++t) tr.off[t] = P > 0 ? hc[C_OFF + t] : 0;
     tr.off[0] = 0;
+    const TypeRanges raw = tr;
+    ctx->merged = false;
+    if (tr.off[8] > 0 && !(params->flags & GIPC_FLAG_NO_MERGE)) {
+        ctx->ranges = tr;
+        CK(merge_duplicates(ctx, s, cnt + C_MOFF), "merge duplicates");
+        if ((st = read_counters(ctx, hc, C_MOFF, 9, s)) != GIPC_OK) return st;
+        for (int t = 0; t < 9; ++t) tr.off[t] = hc[C_MOFF + t];
+        ctx->merged = true;
+    }
     const int64_t Ps = tr.off[8];
-    if (Ps >= (int64_t(1) << 28)) return fail(ctx, GIPC_ERR_WORKSPACE, "more than 2^28 active pairs (%lld)", (long long)Ps);
+    if (Ps >= (int64_t(1) << 28)) return fail(ctx, GIPC_ERR_WORKSPACE, "more than 2^28 staged pairs (%lld)", (long long)Ps);
 
     // ---- symbolic
     const size_t Vs = (size_t)(V > 0 ? V : 1);
@@ -372,8 +384,10 @@ gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
     gipc_info& in = ctx->info;
     memset(&in, 0, sizeof(in));
     in.n_candidates = P;
-    in.n_active = Ps;
-    for (int t = 1; t < 8; ++t) in.n_by_type[t] = tr.off[t + 1] - tr.off[t];
+    in.n_active = raw.off[8];
+    for (int t = 1; t < 8; ++t) in.n_by_type[t] = raw.off[t + 1] - raw.off[t];
+    in.n_staged = Ps;
+    for (int t = 1; t < 8; ++t) in.n_staged_by_type[t] = tr.off[t + 1] - tr.off[t];
     in.n_degenerate = hc[C_NDEG];
     in.first_degenerate = hc[C_NDEG] > 0 ? hc[C_FIRST_DEG] : -1;
     in.nnzb = nnzb;
@@ -441,7 +455,8 @@ hipError_t eval_enqueue(gipc_ctx* ctx, const DevParams& pm, const gipc_mesh* mes
     const double* xr = mesh->x_rest ? mesh->x_rest : mesh->x;
     const TypeRanges& tr = ctx->ranges;
     const int64_t m0 = tr.off[FT_EEM], e0 = tr.off[FT_EE];
-    hipError_t e = launch_eval(as<int4>(ctx->st_vid), tr, mesh->x, xr, pm, as<double>(ctx->rec_main),
+    const int32_t* mult = ctx->merged ? as<int32_t>(ctx->mult) : nullptr;
+    hipError_t e = launch_eval(as<int4>(ctx->st_vid), mult, tr, mesh->x, xr, pm, as<double>(ctx->rec_main),
                                as<double>(ctx->rec_extra), t.eval_waves, s);
     if (e != hipSuccess) return e;
     e = launch_rows_diag(assemble ? 3 : 1, ctx->V, as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr),
@@ -544,8 +559,8 @@ gipc_status gipc_pcg(gipc_ctx* ctx, const gipc_bsr* A, const double* b, double* 
 }
 
 gipc_status gipc_pair_inspect(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params, int32_t* src,
-                              int32_t* type, int32_t* vid, double* energy, double* grad, double* hess,
-                              void* stream) {
+                              int32_t* type, int32_t* vid, int32_t* mult, double* energy, double* grad,
+                              double* hess, void* stream) {
     if (!ctx) return GIPC_ERR_INVALID_ARG;
     ctx->err.clear();
     gipc_status st;
@@ -562,8 +577,10 @@ gipc_status gipc_pair_inspect(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_p
         x = mesh->x;
         xr = mesh->x_rest ? mesh->x_rest : mesh->x;
     }
-    CK(launch_pair_inspect(as<int4>(ctx->st_vid), as<int32_t>(ctx->st_src), ctx->ranges, as<double>(ctx->rec_main),
-                           as<double>(ctx->rec_extra), x, xr, pm, src, type, vid, energy, grad, hess, S(stream)),
+    CK(launch_pair_inspect(as<int4>(ctx->st_vid), as<int32_t>(ctx->st_src),
+                           ctx->merged ? as<int32_t>(ctx->mult) : nullptr, ctx->ranges, as<double>(ctx->rec_main),
+                           as<double>(ctx->rec_extra), x, xr, pm, src, type, vid, mult, energy, grad, hess,
+                           S(stream)),
        "pair inspect");
     return GIPC_OK;
 }
@@ -630,8 +647,8 @@ gipc_status gipc_autotune(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_param
     float bt = INFINITY;
     for (int w : waves) {
         float ms = time_it([&] {
-            return launch_eval(as<int4>(ctx->st_vid), tr, mesh->x, xr, pm, as<double>(ctx->rec_main),
-                               as<double>(ctx->rec_extra), w, s);
+            return launch_eval(as<int4>(ctx->st_vid), ctx->merged ? as<int32_t>(ctx->mult) : nullptr, tr, mesh->x,
+                               xr, pm, as<double>(ctx->rec_main), as<double>(ctx->rec_extra), w, s);
         });
         if (ms < bt) { bt = ms; t.eval_waves = w; }
     }

@@ -137,19 +137,23 @@ __global__ void __launch_bounds__(BLOCK) k_offdiag(int64_t nnzb, const int32_t* 
 
 // Expanded per-pair view of the staged list and the stored factors.
 __global__ void __launch_bounds__(kBlock) k_pair_inspect(const int4* __restrict__ st_vid,
-                                                         const int32_t* __restrict__ st_src, TypeRanges tr,
+                                                         const int32_t* __restrict__ st_src,
+                                                         const int32_t* __restrict__ smult, TypeRanges tr,
                                                          const double* __restrict__ rec_main,
                                                          const double* __restrict__ rec_extra,
                                                          const double* __restrict__ X, const double* __restrict__ XR,
                                                          DevParams pm, int32_t* src, int32_t* type, int32_t* vid,
-                                                         double* energy, double* grad, double* hess) {
+                                                         int32_t* mult, double* energy, double* grad,
+                                                         double* hess) {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= tr.off[8]) return;
     const int ft = type_of(k, tr);
     const int4 v4 = st_vid[k];
     const int64_t m0 = tr.off[FT_EEM], e0 = tr.off[FT_EE];
+    const int32_t w = smult ? smult[k] : 1;
     if (src) src[k] = st_src[k];
     if (type) type[k] = ft;
+    if (mult) mult[k] = w;
     if (vid) {
         vid[4 * k + 0] = v4.x; vid[4 * k + 1] = v4.y; vid[4 * k + 2] = v4.z; vid[4 * k + 3] = v4.w;
     }
@@ -157,7 +161,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_inspect(const int4* __restrict_
         const int v[4] = {v4.x, v4.y, v4.z, v4.w};
         PairFactors o;
         eval_typed(ft, v, X, XR, pm, o);
-        energy[k] = o.E;
+        energy[k] = (double)w * o.E;
     }
     const int nv = ft_nverts(ft);
     if (grad) {
@@ -246,14 +250,14 @@ hipError_t launch_offdiag(int64_t nnzb, const int32_t* slot_row, const int32_t* 
     }
 }
 
-hipError_t launch_pair_inspect(const int4* st_vid, const int32_t* st_src, TypeRanges tr, const double* rec_main,
-                               const double* rec_extra, const double* x, const double* xr, const DevParams& pm,
-                               int32_t* src, int32_t* type, int32_t* vid, double* energy, double* grad,
-                               double* hess, hipStream_t s) {
+hipError_t launch_pair_inspect(const int4* st_vid, const int32_t* st_src, const int32_t* smult, TypeRanges tr,
+                               const double* rec_main, const double* rec_extra, const double* x, const double* xr,
+                               const DevParams& pm, int32_t* src, int32_t* type, int32_t* vid, int32_t* mult,
+                               double* energy, double* grad, double* hess, hipStream_t s) {
     int64_t nb = (tr.off[8] + kBlock - 1) / kBlock;
     if (nb == 0) return hipSuccess;
-    k_pair_inspect<<<(unsigned)nb, kBlock, 0, s>>>(st_vid, st_src, tr, rec_main, rec_extra, x, xr, pm, src, type, vid,
-                                                  energy, grad, hess);
+    k_pair_inspect<<<(unsigned)nb, kBlock, 0, s>>>(st_vid, st_src, smult, tr, rec_main, rec_extra, x, xr, pm, src,
+                                                  type, vid, mult, energy, grad, hess);
     return hipGetLastError();
 }
 

@@ -11,28 +11,31 @@
 namespace gipc {
 namespace {
 
+// a merged pair stands for `mult` identical constraints: its energy, its
+// gradient factors and its Hessian factors are scaled by that count
 template <int BLOCK>
-__global__ void __launch_bounds__(BLOCK) k_eval(const int4* __restrict__ st_vid, TypeRanges tr,
-                                                const double* __restrict__ X, const double* __restrict__ XR,
-                                                DevParams pm, double* __restrict__ rec_main,
-                                                double* __restrict__ rec_extra) {
+__global__ void __launch_bounds__(BLOCK) k_eval(const int4* __restrict__ st_vid, const int32_t* __restrict__ mult,
+                                                TypeRanges tr, const double* __restrict__ X,
+                                                const double* __restrict__ XR, DevParams pm,
+                                                double* __restrict__ rec_main, double* __restrict__ rec_extra) {
     const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (k >= tr.off[8]) return;
     const int ft = type_of(k, tr);
     const int4 v4 = st_vid[k];
     const int v[4] = {v4.x, v4.y, v4.z, v4.w};
+    const double w = mult ? (double)mult[k] : 1.0;
     PairFactors o;
     eval_typed(ft, v, X, XR, pm, o);
     double2* m = reinterpret_cast<double2*>(rec_main + 8 * k);
     m[0] = make_double2(o.c[1], o.c[2]);
     m[1] = make_double2(o.wt.x, o.wt.y);
-    m[2] = make_double2(o.wt.z, o.P22);
-    m[3] = make_double2(o.a2, o.E);
+    m[2] = make_double2(o.wt.z, w * o.P22);
+    m[3] = make_double2(w * o.a2, w * o.E);
     if (ft >= FT_EEM) {
         double* x = rec_extra + 9 * (k - tr.off[FT_EEM]);
         x[0] = o.u.x; x[1] = o.u.y; x[2] = o.u.z;
         x[3] = o.v.x; x[4] = o.v.y; x[5] = o.v.z;
-        x[6] = o.P11; x[7] = o.P12; x[8] = o.a1;
+        x[6] = w * o.P11; x[7] = w * o.P12; x[8] = w * o.a1;
     }
 }
 
@@ -65,23 +68,23 @@ __global__ void __launch_bounds__(kBlock) k_energy_scenes(const double* __restri
 }
 
 template <int BLOCK>
-hipError_t eval_launch(const int4* st_vid, TypeRanges tr, const double* x, const double* xr, const DevParams& pm,
-                       double* rec_main, double* rec_extra, hipStream_t s) {
+hipError_t eval_launch(const int4* st_vid, const int32_t* mult, TypeRanges tr, const double* x, const double* xr,
+                       const DevParams& pm, double* rec_main, double* rec_extra, hipStream_t s) {
     const int64_t nb = (tr.off[8] + BLOCK - 1) / BLOCK;
-    k_eval<BLOCK><<<(unsigned)nb, BLOCK, 0, s>>>(st_vid, tr, x, xr, pm, rec_main, rec_extra);
+    k_eval<BLOCK><<<(unsigned)nb, BLOCK, 0, s>>>(st_vid, mult, tr, x, xr, pm, rec_main, rec_extra);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_eval(const int4* st_vid, TypeRanges tr, const double* x, const double* xr, const DevParams& pm,
-                       double* rec_main, double* rec_extra, int waves, hipStream_t s) {
+hipError_t launch_eval(const int4* st_vid, const int32_t* mult, TypeRanges tr, const double* x, const double* xr,
+                       const DevParams& pm, double* rec_main, double* rec_extra, int waves, hipStream_t s) {
     if (tr.off[8] == 0) return hipSuccess;
     switch (waves) {
-        case 1: return eval_launch<64>(st_vid, tr, x, xr, pm, rec_main, rec_extra, s);
-        case 2: return eval_launch<128>(st_vid, tr, x, xr, pm, rec_main, rec_extra, s);
-        case 8: return eval_launch<512>(st_vid, tr, x, xr, pm, rec_main, rec_extra, s);
-        default: return eval_launch<256>(st_vid, tr, x, xr, pm, rec_main, rec_extra, s);
+        case 1: return eval_launch<64>(st_vid, mult, tr, x, xr, pm, rec_main, rec_extra, s);
+        case 2: return eval_launch<128>(st_vid, mult, tr, x, xr, pm, rec_main, rec_extra, s);
+        case 8: return eval_launch<512>(st_vid, mult, tr, x, xr, pm, rec_main, rec_extra, s);
+        default: return eval_launch<256>(st_vid, mult, tr, x, xr, pm, rec_main, rec_extra, s);
     }
 }
 

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <utility>
 
 #include "../../include/gipc.h"
 #include "device_math.hpp"
@@ -71,8 +72,12 @@ struct gipc_ctx {
 
     // staging (per candidate)
     gipc::DevBuf cand_ft, cand_vid, bcount, boff, counters;
-    // staged pairs, sorted by sub-type
-    gipc::DevBuf st_vid, st_src;
+    // staged pairs, sorted by sub-type; mult = multiplicity of merged
+    // duplicates (valid when merged)
+    gipc::DevBuf st_vid, st_src, mult;
+    bool merged = false;
+    // merge scratch
+    gipc::DevBuf mkeys, mrep, mrep_of, mcount, mflag, mpos, st_vid2, st_src2;
     gipc::TypeRanges ranges{};
     int64_t Ps = 0;
     int32_t V = 0;
@@ -122,6 +127,12 @@ hipError_t launch_stage_scatter(const uint8_t* ft, const int4* vid, int64_t P, c
                                 int32_t* st_src, hipStream_t s);
 hipError_t launch_stage_offsets(const int64_t* boff, int64_t nb, int64_t* out, hipStream_t s);
 
+// ---- merge.hip
+// merge duplicate PE / PP constraints of ctx->ranges into one staged pair
+// with a multiplicity (ctx->mult); swaps the staged arrays and writes the
+// merged type offsets (9 int64) to new_off_dev
+hipError_t merge_duplicates(gipc_ctx* ctx, hipStream_t s, int64_t* new_off_dev);
+
 // ---- symbolic.hip
 hipError_t launch_sym_count(const int4* st_vid, TypeRanges tr, int32_t* deg, int32_t* kcount, hipStream_t s);
 hipError_t launch_sym_scatter(const int4* st_vid, TypeRanges tr, const int64_t* inc_ptr, int32_t* fill,
@@ -135,8 +146,9 @@ hipError_t launch_sym_fill(int32_t V, const int64_t* kptr, const int32_t* kcol, 
 
 // ---- eval.hip
 // waves: workgroup size in wavefronts (1, 2, 4 or 8)
-hipError_t launch_eval(const int4* st_vid, TypeRanges tr, const double* x, const double* xr, const DevParams& pm,
-                       double* rec_main, double* rec_extra, int waves, hipStream_t s);
+// mult: multiplicity per staged pair, nullable (all 1)
+hipError_t launch_eval(const int4* st_vid, const int32_t* mult, TypeRanges tr, const double* x, const double* xr,
+                       const DevParams& pm, double* rec_main, double* rec_extra, int waves, hipStream_t s);
 // per-scene energies from the per-vertex shares: pieces, then scenes
 hipError_t launch_energy(const double* ev, const int2* pieces, int32_t npieces, const int32_t* poff, int32_t S,
                          double* part, double* energy, hipStream_t s);
@@ -152,10 +164,10 @@ hipError_t launch_rows_diag(int mode, int32_t V, const int32_t* diag_slot, const
 hipError_t launch_offdiag(int64_t nnzb, const int32_t* slot_row, const int32_t* col_idx, const int64_t* cptr,
                           const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t e0,
                           int64_t m0, void* val, int dtype, int waves, hipStream_t s);
-hipError_t launch_pair_inspect(const int4* st_vid, const int32_t* st_src, TypeRanges tr, const double* rec_main,
-                               const double* rec_extra, const double* x, const double* xr, const DevParams& pm,
-                               int32_t* src, int32_t* type, int32_t* vid, double* energy, double* grad,
-                               double* hess, hipStream_t s);
+hipError_t launch_pair_inspect(const int4* st_vid, const int32_t* st_src, const int32_t* smult, TypeRanges tr,
+                               const double* rec_main, const double* rec_extra, const double* x, const double* xr,
+                               const DevParams& pm, int32_t* src, int32_t* type, int32_t* vid, int32_t* mult,
+                               double* energy, double* grad, double* hess, hipStream_t s);
 
 // ---- solve.hip
 hipError_t launch_spmv(const gipc_bsr& A, const void* x, void* y, hipStream_t s);

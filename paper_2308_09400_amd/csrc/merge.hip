@@ -1,0 +1,168 @@
+// Merging of duplicate constraints after staging.  On aligned grids many
+// candidate tuples reduce to the same point-edge or point-point constraint
+// (a point over a shared edge or vertex is found through every triangle and
+// edge pair around it).  The energy of Eq. 3 sums each candidate with its
+// own constrained distance, so identical reduced constraints can be
+// evaluated once and weighted by their count: that is exact.
+//
+// Duplicates are found with an open-addressing hash table on a 64-bit
+// fingerprint of the canonical key (PP: the unordered vertex pair; PE: the
+// point and the unordered edge).  The representative of a key is the
+// smallest staged index carrying it (atomicMin), and a pair merges into it
+// only if its full key equals the representative's, so a fingerprint
+// collision can only leave duplicates unmerged, never merge different
+// constraints.  Counts are integer atomics and the compaction keeps the
+// staged order, so the result is deterministic.
+#include "internal.hpp"
+
+namespace gipc {
+namespace {
+
+// splitmix64 finalizer (Steele, Lea, Flood, "Fast splittable pseudorandom
+// number generators", 2014)
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+struct Key {
+    int a, b, c;
+};
+
+__device__ __forceinline__ Key canon(bool pp, int4 v) {
+    if (pp) return Key{min(v.x, v.y), max(v.x, v.y), -1};
+    return Key{v.x, min(v.y, v.z), max(v.y, v.z)};
+}
+
+__device__ __forceinline__ unsigned long long fingerprint(const Key& k) {
+    uint64_t x = ((uint64_t)(uint32_t)k.a << 32) | (uint32_t)k.b;
+    uint64_t f = mix64(x ^ mix64((uint64_t)(uint32_t)k.c + 0x9e3779b97f4a7c15ull));
+    return f ? f : 1ull;  // 0 marks an empty slot
+}
+
+// pairs [k0, k1) are PE then PP from pp0 on
+__global__ void __launch_bounds__(kBlock) k_merge_insert(const int4* __restrict__ st_vid, int64_t k0, int64_t k1,
+                                                         int64_t pp0, unsigned long long* __restrict__ keys,
+                                                         int32_t* __restrict__ rep, uint64_t mask) {
+    const int64_t k = k0 + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= k1) return;
+    const unsigned long long f = fingerprint(canon(k >= pp0, st_vid[k]));
+    uint64_t h = f & mask;
+    // the table has at least twice as many slots as keys: an empty slot exists
+    for (;;) {
+        const unsigned long long prev = atomicCAS(&keys[h], 0ull, f);
+        if (prev == 0ull || prev == f) {
+            atomicMin(&rep[h], (int32_t)k);
+            return;
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_merge_resolve(const int4* __restrict__ st_vid, int64_t k0, int64_t k1,
+                                                          int64_t pp0, const unsigned long long* __restrict__ keys,
+                                                          const int32_t* __restrict__ rep, uint64_t mask,
+                                                          int32_t* __restrict__ rep_of, int32_t* __restrict__ mult) {
+    const int64_t k = k0 + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= k1) return;
+    const bool pp = k >= pp0;
+    const Key me = canon(pp, st_vid[k]);
+    const unsigned long long f = fingerprint(me);
+    uint64_t h = f & mask;
+    while (keys[h] != f) h = (h + 1) & mask;  // inserted by this pair
+    const int32_t r = rep[h];
+    const bool rpp = r >= pp0;
+    const Key o = canon(rpp, st_vid[r]);
+    const int32_t my = (rpp == pp && o.a == me.a && o.b == me.b && o.c == me.c) ? r : (int32_t)k;
+    rep_of[k - k0] = my;
+    atomicAdd(&mult[my - k0], 1);
+}
+
+__global__ void __launch_bounds__(kBlock) k_merge_flags(int64_t Ps, int64_t k0, int64_t k1,
+                                                        const int32_t* __restrict__ rep_of,
+                                                        int32_t* __restrict__ flag) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= Ps) return;
+    flag[k] = (k < k0 || k >= k1) ? 1 : (rep_of[k - k0] == (int32_t)k ? 1 : 0);
+}
+
+__global__ void __launch_bounds__(kBlock) k_merge_scatter(int64_t Ps, int64_t k0, int64_t k1,
+                                                          const int32_t* __restrict__ flag,
+                                                          const int64_t* __restrict__ pos,
+                                                          const int4* __restrict__ st_vid,
+                                                          const int32_t* __restrict__ st_src,
+                                                          const int32_t* __restrict__ mult_in,
+                                                          int4* __restrict__ vid_out, int32_t* __restrict__ src_out,
+                                                          int32_t* __restrict__ mult_out) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= Ps || !flag[k]) return;
+    const int64_t n = pos[k];
+    vid_out[n] = st_vid[k];
+    src_out[n] = st_src[k];
+    mult_out[n] = (k >= k0 && k < k1) ? mult_in[k - k0] : 1;
+}
+
+// merged type offsets: out[t] = pos[off[t]]
+__global__ void k_merge_offsets(const int64_t* __restrict__ pos, TypeRanges tr, int64_t* __restrict__ out) {
+    const int t = threadIdx.x;
+    if (t < 9) out[t] = pos[tr.off[t]];
+}
+
+unsigned grid(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+hipError_t merge_duplicates(gipc_ctx* ctx, hipStream_t s, int64_t* new_off_dev) {
+    const TypeRanges& tr = ctx->ranges;
+    const int64_t Ps = tr.off[8], k0 = tr.off[FT_PE], pp0 = tr.off[FT_PP], k1 = tr.off[FT_PP + 1];
+    const int64_t n = k1 - k0;
+    uint64_t H = 1024;
+    while (H < 2 * (uint64_t)n) H <<= 1;
+    hipError_t e;
+#define TRY(x)                          \
+    do {                                \
+        if ((e = (x)) != hipSuccess) return e; \
+    } while (0)
+    TRY(ensure(ctx->mkeys, sizeof(unsigned long long) * H));
+    TRY(ensure(ctx->mrep, sizeof(int32_t) * H));
+    TRY(ensure(ctx->mrep_of, sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
+    TRY(ensure(ctx->mcount, sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
+    TRY(ensure(ctx->mflag, sizeof(int32_t) * (size_t)(Ps > 0 ? Ps : 1)));
+    TRY(ensure(ctx->mpos, sizeof(int64_t) * (size_t)(Ps + 1)));
+    TRY(ensure(ctx->st_vid2, sizeof(int4) * (size_t)(Ps > 0 ? Ps : 1)));
+    TRY(ensure(ctx->st_src2, sizeof(int32_t) * (size_t)(Ps > 0 ? Ps : 1)));
+    TRY(ensure(ctx->mult, sizeof(int32_t) * (size_t)(Ps > 0 ? Ps : 1)));
+    if (n > 0) {
+        TRY(hipMemsetAsync(ctx->mkeys.p, 0, sizeof(unsigned long long) * H, s));
+        TRY(hipMemsetAsync(ctx->mrep.p, 0x7f, sizeof(int32_t) * H, s));
+        TRY(hipMemsetAsync(ctx->mcount.p, 0, sizeof(int32_t) * n, s));
+        k_merge_insert<<<grid(n), kBlock, 0, s>>>(as<int4>(ctx->st_vid), k0, k1, pp0,
+                                                  as<unsigned long long>(ctx->mkeys), as<int32_t>(ctx->mrep), H - 1);
+        TRY(hipGetLastError());
+        k_merge_resolve<<<grid(n), kBlock, 0, s>>>(as<int4>(ctx->st_vid), k0, k1, pp0,
+                                                   as<unsigned long long>(ctx->mkeys), as<int32_t>(ctx->mrep), H - 1,
+                                                   as<int32_t>(ctx->mrep_of), as<int32_t>(ctx->mcount));
+        TRY(hipGetLastError());
+    }
+    if (Ps > 0) {
+        k_merge_flags<<<grid(Ps), kBlock, 0, s>>>(Ps, k0, k1, as<int32_t>(ctx->mrep_of), as<int32_t>(ctx->mflag));
+        TRY(hipGetLastError());
+    }
+    TRY((exclusive_scan<int32_t, int64_t>(as<int32_t>(ctx->mflag), Ps, as<int64_t>(ctx->mpos), ctx, s)));
+    if (Ps > 0) {
+        k_merge_scatter<<<grid(Ps), kBlock, 0, s>>>(Ps, k0, k1, as<int32_t>(ctx->mflag), as<int64_t>(ctx->mpos),
+                                                    as<int4>(ctx->st_vid), as<int32_t>(ctx->st_src),
+                                                    as<int32_t>(ctx->mcount), as<int4>(ctx->st_vid2),
+                                                    as<int32_t>(ctx->st_src2), as<int32_t>(ctx->mult));
+        TRY(hipGetLastError());
+    }
+    k_merge_offsets<<<1, 64, 0, s>>>(as<int64_t>(ctx->mpos), tr, new_off_dev);
+    TRY(hipGetLastError());
+#undef TRY
+    std::swap(ctx->st_vid, ctx->st_vid2);
+    std::swap(ctx->st_src, ctx->st_src2);
+    return hipSuccess;
+}
+
+}  // namespace gipc

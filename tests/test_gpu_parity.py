@@ -48,7 +48,7 @@ def run_gpu(gp, x, xr, tuples, prm, diag=None, dtype=0, inspect=True):
     E, g = gp.eval_assemble(ctx, X, prm, A, diag=D, x_rest=XR)
     out = dict(ctx=ctx, info=info, A=A, E=E.item(), grad=g.cpu().numpy(), X=X, XR=XR)
     if inspect:
-        pi = gp.pair_inspect(ctx, X, prm, x_rest=XR, want=("src", "type", "vid", "energy", "grad", "hess"))
+        pi = gp.pair_inspect(ctx, X, prm, x_rest=XR, want=("src", "type", "vid", "mult", "energy", "grad", "hess"))
         out["pairs"] = {k: v.cpu().numpy() for k, v in pi.items()}
     return out
 
@@ -85,39 +85,52 @@ def compare_scene(gpu, ref, V, tol=TOL):
     assert worst <= tol * hs, worst / hs
 
 
-def compare_pairs(gpu, ref, tuples, x, xr, tol=TOL):
-    """Per staged pair: energy, local gradient and Hessian, keyed by vertex id."""
+def compare_pairs(gpu, ref, tuples, x, xr, tol=TOL, whole_list=True):
+    """Per staged pair: energy, local gradient and Hessian, keyed by vertex id.
+    A staged pair of multiplicity m stands for m candidates with the same
+    reduced constraint: it is compared with m times the oracle's values for
+    its first tuple, and over a whole list the multiplicities add up to the
+    oracle's active candidates."""
     pr = gpu["pairs"]
     src, typ, vid = pr["src"], pr["type"], pr["vid"]
+    mult = pr["mult"] if "mult" in pr else np.ones(len(src), np.int32)
     st = ref["subtype"]
     active_o = set(np.nonzero((st > 0) & (st != oracle.DEGENERATE))[0].tolist())
     active_g = set(src.tolist())
     assert len(active_g) == len(src)                      # each tuple staged at most once
+    assert (mult >= 1).all()
     Emax = np.abs(ref["pairE"]).max() if len(ref["pairE"]) else 0.0
-    for p in active_o ^ active_g:                          # boundary cases only (d within rounding of dhat)
-        assert abs(ref["pairE"][p]) <= 1e-12 * max(Emax, 1e-300)
+
+    def boundary(p):                                       # d within rounding of dhat
+        return abs(ref["pairE"][p]) <= 1e-12 * max(Emax, 1e-300)
+    for p in active_g - active_o:
+        assert boundary(p)
+    if whole_list:
+        nb = sum(1 for p in active_o if boundary(p))
+        assert abs(int(mult.sum()) - len(active_o)) <= nb
     gmax = np.abs(ref["pairG"]).max()
     hmax = np.abs(ref["pairH"]).max()
     for k in range(len(src)):
         p = int(src[k])
+        m = float(mult[k])
         nv, ov = oracle.stencil(tuples[p])
-        og = {int(ov[i]): ref["pairG"][p][3 * i:3 * i + 3] for i in range(nv)}
+        og = {int(ov[i]): m * ref["pairG"][p][3 * i:3 * i + 3] for i in range(nv)}
         gg = {int(vid[k][i]): pr["grad"][k][3 * i:3 * i + 3] for i in range(4) if vid[k][i] >= 0}
-        sc_e = max(abs(ref["pairE"][p]), 1e-6 * Emax)
-        assert abs(pr["energy"][k] - ref["pairE"][p]) <= tol * sc_e + 1e-300
-        sc_g = max(np.abs(ref["pairG"][p]).max(), 1e-6 * gmax)
+        sc_e = m * max(abs(ref["pairE"][p]), 1e-6 * Emax)
+        assert abs(pr["energy"][k] - m * ref["pairE"][p]) <= tol * sc_e + 1e-300
+        sc_g = m * max(np.abs(ref["pairG"][p]).max(), 1e-6 * gmax)
         for v in set(og) | set(gg):
             assert np.abs(gg.get(v, 0.0) - og.get(v, 0.0)).max() <= tol * sc_g + 1e-300, (k, p, v)
         oh = {}
         for i in range(nv):
             for j in range(nv):
-                oh[(int(ov[i]), int(ov[j]))] = ref["pairH"][p][3 * i:3 * i + 3, 3 * j:3 * j + 3]
+                oh[(int(ov[i]), int(ov[j]))] = m * ref["pairH"][p][3 * i:3 * i + 3, 3 * j:3 * j + 3]
         gh = {}
         for i in range(4):
             for j in range(4):
                 if vid[k][i] >= 0 and vid[k][j] >= 0:
                     gh[(int(vid[k][i]), int(vid[k][j]))] = pr["hess"][k][3 * i:3 * i + 3, 3 * j:3 * j + 3]
-        sc_h = max(np.abs(ref["pairH"][p]).max(), 1e-6 * hmax)
+        sc_h = m * max(np.abs(ref["pairH"][p]).max(), 1e-6 * hmax)
         for key in set(oh) | set(gh):
             assert np.abs(gh.get(key, 0.0) - oh.get(key, 0.0)).max() <= tol * sc_h + 1e-300, (k, p, key)
         # mollified kinds <-> oracle's mollifier decision (exact, away from c = eps_x)
@@ -151,9 +164,36 @@ def test_two_sheet_scene(gp, opts):
     info = gpu["info"]
     assert info["n_candidates"] == s.P and info["n_degenerate"] == 0
     assert sum(info["n_by_type"].values()) == info["n_active"]
+    assert sum(info["n_staged_by_type"].values()) == info["n_staged"] < info["n_active"]
     if opts.get("mollify", True):
         assert info["n_by_type"]["EE_moll"] + info["n_by_type"]["PE_moll"] + info["n_by_type"]["PP_moll"] > 0
     gpu["ctx"].close()
+
+
+@pytest.mark.parametrize("which", ["two_sheets", "tiny"])
+def test_merged_duplicates_equal_the_unmerged_list(gp, which):
+    # reading of Eq. 3: the candidate list equals its merged list of reduced
+    # constraints weighted by integer multiplicities
+    s = scenes.two_sheets(n=16, seed=1) if which == "two_sheets" else _tiny_scene(4)
+    pm, po = _prm_pair(gp, s.dhat, s.kappa)
+    pn = gp.params(dhat=s.dhat, kappa=s.kappa, flags=gp.FLAGS_DEFAULT | gp.FLAG_NO_MERGE)
+    diag = np.full(s.V, 10.0)
+    a = run_gpu(gp, s.x, s.x_rest, s.tuples, pm, diag)
+    b = run_gpu(gp, s.x, s.x_rest, s.tuples, pn, diag)
+    assert b["info"]["n_staged"] == b["info"]["n_active"] == a["info"]["n_active"]
+    assert a["info"]["n_staged"] < a["info"]["n_active"]
+    assert int(a["pairs"]["mult"].sum()) == a["info"]["n_active"] and (b["pairs"]["mult"] == 1).all()
+    assert a["E"] == pytest.approx(b["E"], rel=1e-13)
+    assert np.abs(a["grad"] - b["grad"]).max() <= 1e-13 * np.abs(b["grad"]).max()
+    ga, _, _ = blocks_of(a["A"])
+    gb, _, _ = blocks_of(b["A"])
+    assert ga.keys() == gb.keys()
+    hs = max(np.abs(B).max() for B in gb.values())
+    assert max(np.abs(ga[k] - gb[k]).max() for k in gb) <= 1e-13 * hs
+    ref = run_oracle(s.x, s.x_rest, s.tuples, po, diag)
+    compare_scene(b, ref, s.V)
+    compare_pairs(b, ref, s.tuples, s.x, s.x_rest)
+    a["ctx"].close(); b["ctx"].close()
 
 
 @pytest.mark.parametrize("seed", [3, 4, 5])
@@ -455,7 +495,8 @@ def test_full_scale_sampled_rows(big, gp):
 
 def test_full_scale_sampled_pairs(big, gp):
     s, pg, po, gpu = big
-    pi = gp.pair_inspect(gpu["ctx"], gpu["X"], pg, x_rest=gpu["XR"], want=("src", "type", "vid", "energy", "grad", "hess"))
+    pi = gp.pair_inspect(gpu["ctx"], gpu["X"], pg, x_rest=gpu["XR"],
+                         want=("src", "type", "vid", "mult", "energy", "grad", "hess"))
     n = pi["src"].shape[0]
     rng = np.random.default_rng(9)
     pick = np.sort(rng.choice(n, min(n, 4000), replace=False))
@@ -464,4 +505,4 @@ def test_full_scale_sampled_pairs(big, gp):
     src = pairs["src"]
     ref = oracle.eval_scene(s.x, s.tuples[src], po, x_rest=s.x_rest, per_pair=True)
     pairs["src"] = np.arange(len(src))
-    compare_pairs(dict(pairs=pairs), ref, s.tuples[src], s.x, s.x_rest)
+    compare_pairs(dict(pairs=pairs), ref, s.tuples[src], s.x, s.x_rest, whole_list=False)
