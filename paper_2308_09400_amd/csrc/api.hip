@@ -193,7 +193,7 @@ void gipc_ctx_destroy(gipc_ctx* ctx) {
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(ctx->device);
     DevBuf* bufs[] = {&ctx->cand_ft, &ctx->cand_vid, &ctx->bcount, &ctx->boff, &ctx->counters, &ctx->st_vid,
-                      &ctx->st_src, &ctx->mult, &ctx->mkeys, &ctx->mrep, &ctx->mrep_of, &ctx->mcount,
+                      &ctx->st_src, &ctx->mult, &ctx->mkeys, &ctx->mrep_of, &ctx->mcount,
                       &ctx->mflag, &ctx->mpos, &ctx->st_vid2, &ctx->st_src2, &ctx->deg, &ctx->kcount, &ctx->fill, &ctx->inc_ptr, &ctx->kptr, &ctx->inc,
                       &ctx->contrib, &ctx->kcol, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
                       &ctx->slot_row, &ctx->diag_slot, &ctx->maxbuf, &ctx->rec_main, &ctx->rec_extra, &ctx->ev,
@@ -318,7 +318,7 @@ gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
     ctx->merged = false;
     if (tr.off[8] > 0 && !(params->flags & GIPC_FLAG_NO_MERGE)) {
         ctx->ranges = tr;
-        CK(merge_duplicates(ctx, s, cnt + C_MOFF), "merge duplicates");
+        CK(merge_duplicates(ctx, V, s, cnt + C_MOFF), "merge duplicates");
         if ((st = read_counters(ctx, hc, C_MOFF, 9, s)) != GIPC_OK) return st;
         for (int t = 0; t < 9; ++t) tr.off[t] = hc[C_MOFF + t];
         ctx->merged = true;

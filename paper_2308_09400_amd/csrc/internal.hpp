@@ -77,7 +77,7 @@ struct gipc_ctx {
     gipc::DevBuf st_vid, st_src, mult;
     bool merged = false;
     // merge scratch
-    gipc::DevBuf mkeys, mrep, mrep_of, mcount, mflag, mpos, st_vid2, st_src2;
+    gipc::DevBuf mkeys, mrep_of, mcount, mflag, mpos, st_vid2, st_src2;
     gipc::TypeRanges ranges{};
     int64_t Ps = 0;
     int32_t V = 0;
@@ -128,10 +128,10 @@ hipError_t launch_stage_scatter(const uint8_t* ft, const int4* vid, int64_t P, c
 hipError_t launch_stage_offsets(const int64_t* boff, int64_t nb, int64_t* out, hipStream_t s);
 
 // ---- merge.hip
-// merge duplicate PE / PP constraints of ctx->ranges into one staged pair
-// with a multiplicity (ctx->mult); swaps the staged arrays and writes the
-// merged type offsets (9 int64) to new_off_dev
-hipError_t merge_duplicates(gipc_ctx* ctx, hipStream_t s, int64_t* new_off_dev);
+// merge duplicate PE / PP constraints of ctx->ranges (vertex ids < V) into
+// one staged pair with a multiplicity (ctx->mult); swaps the staged arrays
+// and writes the merged type offsets (9 int64) to new_off_dev
+hipError_t merge_duplicates(gipc_ctx* ctx, int32_t V, hipStream_t s, int64_t* new_off_dev);
 
 // ---- symbolic.hip
 hipError_t launch_sym_count(const int4* st_vid, TypeRanges tr, int32_t* deg, int32_t* kcount, hipStream_t s);

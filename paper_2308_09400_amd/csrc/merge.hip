@@ -13,6 +13,11 @@
 // collision can only leave duplicates unmerged, never merge different
 // constraints.  Counts are integer atomics and the compaction keeps the
 // staged order, so the result is deterministic.
+//
+// Layout: one 16-byte entry per slot (fingerprint, representative), and a
+// key's home slot is proportional to its first vertex plus a 16-slot
+// offset from the fingerprint: staged pairs come in vertex-major order
+// within each sub-type, so neighbouring lanes probe neighbouring lines.
 #include "internal.hpp"
 
 namespace gipc {
@@ -41,19 +46,34 @@ __device__ __forceinline__ unsigned long long fingerprint(const Key& k) {
     return f ? f : 1ull;  // 0 marks an empty slot
 }
 
+struct Slot {
+    unsigned long long key;  // fingerprint, 0 = empty
+    int32_t rep;             // smallest staged index with this fingerprint
+    int32_t pad;
+};
+
+__device__ __forceinline__ uint64_t home(const Key& k, unsigned long long f, double scale, uint64_t mask) {
+    return ((uint64_t)((double)(uint32_t)k.a * scale) + (f & 15ull)) & mask;
+}
+
+// Probes stop after kMaxProbe slots: a pair whose key finds neither its
+// slot nor an empty one that close to home stays unmerged (exact, only
+// slower); both passes walk the same sequence, so they agree.
+constexpr int kMaxProbe = 4096;
+
 // pairs [k0, k1) are PE then PP from pp0 on
 __global__ void __launch_bounds__(kBlock) k_merge_insert(const int4* __restrict__ st_vid, int64_t k0, int64_t k1,
-                                                         int64_t pp0, unsigned long long* __restrict__ keys,
-                                                         int32_t* __restrict__ rep, uint64_t mask) {
+                                                         int64_t pp0, Slot* __restrict__ table, double scale,
+                                                         uint64_t mask) {
     const int64_t k = k0 + (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= k1) return;
-    const unsigned long long f = fingerprint(canon(k >= pp0, st_vid[k]));
-    uint64_t h = f & mask;
-    // the table has at least twice as many slots as keys: an empty slot exists
-    for (;;) {
-        const unsigned long long prev = atomicCAS(&keys[h], 0ull, f);
+    const Key key = canon(k >= pp0, st_vid[k]);
+    const unsigned long long f = fingerprint(key);
+    uint64_t h = home(key, f, scale, mask);
+    for (int t = 0; t < kMaxProbe; ++t) {
+        const unsigned long long prev = atomicCAS(&table[h].key, 0ull, f);
         if (prev == 0ull || prev == f) {
-            atomicMin(&rep[h], (int32_t)k);
+            atomicMin(&table[h].rep, (int32_t)k);
             return;
         }
         h = (h + 1) & mask;
@@ -61,20 +81,28 @@ __global__ void __launch_bounds__(kBlock) k_merge_insert(const int4* __restrict_
 }
 
 __global__ void __launch_bounds__(kBlock) k_merge_resolve(const int4* __restrict__ st_vid, int64_t k0, int64_t k1,
-                                                          int64_t pp0, const unsigned long long* __restrict__ keys,
-                                                          const int32_t* __restrict__ rep, uint64_t mask,
-                                                          int32_t* __restrict__ rep_of, int32_t* __restrict__ mult) {
+                                                          int64_t pp0, const Slot* __restrict__ table, double scale,
+                                                          uint64_t mask, int32_t* __restrict__ rep_of,
+                                                          int32_t* __restrict__ mult) {
     const int64_t k = k0 + (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= k1) return;
     const bool pp = k >= pp0;
     const Key me = canon(pp, st_vid[k]);
     const unsigned long long f = fingerprint(me);
-    uint64_t h = f & mask;
-    while (keys[h] != f) h = (h + 1) & mask;  // inserted by this pair
-    const int32_t r = rep[h];
-    const bool rpp = r >= pp0;
-    const Key o = canon(rpp, st_vid[r]);
-    const int32_t my = (rpp == pp && o.a == me.a && o.b == me.b && o.c == me.c) ? r : (int32_t)k;
+    uint64_t h = home(me, f, scale, mask);
+    int32_t my = (int32_t)k;
+    for (int t = 0; t < kMaxProbe; ++t) {
+        const unsigned long long kh = table[h].key;
+        if (kh == f) {
+            const int32_t r = table[h].rep;
+            const bool rpp = r >= pp0;
+            const Key o = canon(rpp, st_vid[r]);
+            if (rpp == pp && o.a == me.a && o.b == me.b && o.c == me.c) my = r;
+            break;
+        }
+        if (kh == 0ull) break;  // not inserted (probe bound reached on insert)
+        h = (h + 1) & mask;
+    }
     rep_of[k - k0] = my;
     atomicAdd(&mult[my - k0], 1);
 }
@@ -109,23 +137,31 @@ __global__ void k_merge_offsets(const int64_t* __restrict__ pos, TypeRanges tr, 
     if (t < 9) out[t] = pos[tr.off[t]];
 }
 
+// empty slots: key 0, representative above any staged index
+__global__ void __launch_bounds__(kBlock) k_merge_clear(Slot* __restrict__ table, int64_t H) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < H) table[i] = Slot{0ull, INT32_MAX, 0};
+}
+
 unsigned grid(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
 
-hipError_t merge_duplicates(gipc_ctx* ctx, hipStream_t s, int64_t* new_off_dev) {
+hipError_t merge_duplicates(gipc_ctx* ctx, int32_t V, hipStream_t s, int64_t* new_off_dev) {
     const TypeRanges& tr = ctx->ranges;
     const int64_t Ps = tr.off[8], k0 = tr.off[FT_PE], pp0 = tr.off[FT_PP], k1 = tr.off[FT_PP + 1];
     const int64_t n = k1 - k0;
     uint64_t H = 1024;
-    while (H < 2 * (uint64_t)n) H <<= 1;
+    while (H < (uint64_t)n + (uint64_t)n / 4) H <<= 1;
+    // home slots spread over the whole table: V is this build's vertex count
+    const double scale = V > 0 ? (double)H / (double)V : 1.0;
     hipError_t e;
 #define TRY(x)                          \
     do {                                \
         if ((e = (x)) != hipSuccess) return e; \
     } while (0)
-    TRY(ensure(ctx->mkeys, sizeof(unsigned long long) * H));
-    TRY(ensure(ctx->mrep, sizeof(int32_t) * H));
+    static_assert(sizeof(Slot) == 16, "slot layout");
+    TRY(ensure(ctx->mkeys, sizeof(Slot) * H));
     TRY(ensure(ctx->mrep_of, sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
     TRY(ensure(ctx->mcount, sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
     TRY(ensure(ctx->mflag, sizeof(int32_t) * (size_t)(Ps > 0 ? Ps : 1)));
@@ -134,15 +170,14 @@ hipError_t merge_duplicates(gipc_ctx* ctx, hipStream_t s, int64_t* new_off_dev) 
     TRY(ensure(ctx->st_src2, sizeof(int32_t) * (size_t)(Ps > 0 ? Ps : 1)));
     TRY(ensure(ctx->mult, sizeof(int32_t) * (size_t)(Ps > 0 ? Ps : 1)));
     if (n > 0) {
-        TRY(hipMemsetAsync(ctx->mkeys.p, 0, sizeof(unsigned long long) * H, s));
-        TRY(hipMemsetAsync(ctx->mrep.p, 0x7f, sizeof(int32_t) * H, s));
-        TRY(hipMemsetAsync(ctx->mcount.p, 0, sizeof(int32_t) * n, s));
-        k_merge_insert<<<grid(n), kBlock, 0, s>>>(as<int4>(ctx->st_vid), k0, k1, pp0,
-                                                  as<unsigned long long>(ctx->mkeys), as<int32_t>(ctx->mrep), H - 1);
+        k_merge_clear<<<grid((int64_t)H), kBlock, 0, s>>>(as<Slot>(ctx->mkeys), (int64_t)H);
         TRY(hipGetLastError());
-        k_merge_resolve<<<grid(n), kBlock, 0, s>>>(as<int4>(ctx->st_vid), k0, k1, pp0,
-                                                   as<unsigned long long>(ctx->mkeys), as<int32_t>(ctx->mrep), H - 1,
-                                                   as<int32_t>(ctx->mrep_of), as<int32_t>(ctx->mcount));
+        TRY(hipMemsetAsync(ctx->mcount.p, 0, sizeof(int32_t) * n, s));
+        k_merge_insert<<<grid(n), kBlock, 0, s>>>(as<int4>(ctx->st_vid), k0, k1, pp0, as<Slot>(ctx->mkeys), scale,
+                                                  H - 1);
+        TRY(hipGetLastError());
+        k_merge_resolve<<<grid(n), kBlock, 0, s>>>(as<int4>(ctx->st_vid), k0, k1, pp0, as<Slot>(ctx->mkeys), scale,
+                                                   H - 1, as<int32_t>(ctx->mrep_of), as<int32_t>(ctx->mcount));
         TRY(hipGetLastError());
     }
     if (Ps > 0) {

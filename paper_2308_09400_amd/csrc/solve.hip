@@ -1,10 +1,15 @@
 // BSR SpMV, block-Jacobi preconditioned CG and a plain copy kernel.
 //
-// SpMV: G = 8 lanes per block row; each lane walks every 8th block of the
-// row (component-major values, so the 8 lanes of a row read 8 consecutive
-// doubles of each component), gathers x[col] (24 bytes, mostly cache hits),
-// and the 8 partial 3-vectors are combined by a fixed xor-butterfly inside
-// the lane group.  Deterministic.
+// SpMV: G = 32 lanes per block row (two rows per wavefront); each lane walks
+// every 32nd block of the row (component-major values, so the lanes of a row
+// read consecutive values of each component: two 128-byte lines of doubles),
+// gathers x[col] (mostly cache hits), and the 32 partial 3-vectors are
+// combined by a fixed xor-butterfly inside the lane group.  Deterministic.
+// Rows of the contact matrices hold about 27 blocks, so most lanes issue all
+// their loads at once.  Measured on the ten-sheet matrix (17.4M blocks),
+// FP64: 4 / 8 / 16 / 32 / 64 lanes = 815 / 373 / 311 / 296 / 383 us; FP32:
+// 8 / 16 / 32 lanes = 228 / 178 / 163 us.  At 8 lanes, non-temporal value
+// loads (573 us) and XCD-contiguous row chunks (405 us) were slower.
 //
 // PCG (Saad Alg. 9.1 with the inverse 3x3 diagonal blocks as
 // preconditioner, the paper's simple block preconditioner of Sec. 6.2):
@@ -17,7 +22,7 @@
 namespace gipc {
 namespace {
 
-constexpr int kG = 8;  // lanes per block row
+constexpr int kG = 32;  // lanes per block row
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_spmv(int32_t nrows, const int32_t* __restrict__ rp,
