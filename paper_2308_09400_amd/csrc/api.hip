@@ -49,7 +49,7 @@ namespace {
 // counters layout (int64 slots of ctx->counters)
 enum {
     C_NBAD = 0, C_FIRST_BAD = 1, C_NDEG = 2, C_FIRST_DEG = 3, C_ACTIVE = 4, C_OFF = 5,  // 5..13: type offsets
-    C_INC = 16, C_K = 17, C_NNZB = 18, C_MAXDEG = 19, C_NSPAN = 20, C_FIRST_SPAN = 21,
+    C_INC = 16, C_K = 17, C_NNZB = 18, C_MAXDEG = 19, C_NSPAN = 20, C_FIRST_SPAN = 21, C_NBIG = 22,
     C_MOFF = 24,  // 24..32: merged type offsets
     C_NSLOTS = 40
 };
@@ -196,7 +196,7 @@ void gipc_ctx_destroy(gipc_ctx* ctx) {
                       &ctx->st_src, &ctx->mult, &ctx->mkeys, &ctx->mrep_of, &ctx->mcount,
                       &ctx->mflag, &ctx->mpos, &ctx->st_vid2, &ctx->st_src2, &ctx->deg, &ctx->kcount, &ctx->fill, &ctx->inc_ptr, &ctx->kptr, &ctx->inc,
                       &ctx->contrib, &ctx->kcol, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
-                      &ctx->slot_row, &ctx->diag_slot, &ctx->maxbuf, &ctx->rec_main, &ctx->rec_extra, &ctx->ev,
+                      &ctx->slot_row, &ctx->diag_slot, &ctx->maxbuf, &ctx->bigrows, &ctx->rec_main, &ctx->rec_extra, &ctx->ev,
                       &ctx->epart, &ctx->vscene, &ctx->pieces, &ctx->poff,
                       &ctx->r, &ctx->z, &ctx->p, &ctx->q, &ctx->p32, &ctx->minv, &ctx->part, &ctx->scal, &ctx->scan_tmp,
                       &ctx->scan_tmp2};
@@ -357,9 +357,10 @@ gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
     CK(launch_sym_scatter(as<int4>(ctx->st_vid), tr, as<int64_t>(ctx->inc_ptr), as<int32_t>(ctx->fill),
                           as<uint32_t>(ctx->inc), s),
        "incidence scatter");
+    CK(ensure(ctx->bigrows, sizeof(int32_t) * Vs), "alloc pattern");
     CK(launch_sym_rowsort(V, max_deg, as<int64_t>(ctx->inc_ptr), as<uint32_t>(ctx->inc), as<int4>(ctx->st_vid), tr,
                           as<int64_t>(ctx->kptr), as<uint32_t>(ctx->contrib), as<int32_t>(ctx->kcol),
-                          as<int32_t>(ctx->ncols), s),
+                          as<int32_t>(ctx->ncols), as<int32_t>(ctx->bigrows), cnt + C_NBIG, s),
        "row sort");
     CK((exclusive_scan<int32_t, int32_t>(as<int32_t>(ctx->ncols), V, as<int32_t>(ctx->row_ptr), ctx, s,
                                          cnt + C_NNZB)),

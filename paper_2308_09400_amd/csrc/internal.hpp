@@ -46,17 +46,22 @@ __device__ __forceinline__ int vslot(const int4& v, int j) {
 }
 
 // wave64 sum by a fixed butterfly, then the block's waves in order: the
-// result does not depend on scheduling
-__device__ __forceinline__ double block_sum(double v, double* lds /*[kBlock/64]*/) {
+// result does not depend on scheduling.  NT = threads of the workgroup.
+template <int NT>
+__device__ __forceinline__ double block_sum_n(double v, double* lds /*[NT/64]*/) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
     __syncthreads();
     double s = 0.0;
     if (threadIdx.x == 0)
-        for (int w = 0; w < kBlock / 64; ++w) s += lds[w];
+        for (int w = 0; w < NT / 64; ++w) s += lds[w];
     __syncthreads();
     return s;  // valid in thread 0
+}
+
+__device__ __forceinline__ double block_sum(double v, double* lds /*[kBlock/64]*/) {
+    return block_sum_n<kBlock>(v, lds);
 }
 
 struct PcgScalars {  // device-resident scalars of the PCG loop
@@ -83,7 +88,7 @@ struct gipc_ctx {
     int32_t V = 0;
     // symbolic
     gipc::DevBuf deg, kcount, fill, inc_ptr, kptr, inc, contrib, kcol, ncols, row_ptr, col_idx, cptr, slot_row,
-        diag_slot, maxbuf;
+        diag_slot, maxbuf, bigrows;
     int64_t nnzb = 0, K = 0;
     int32_t max_deg = 0;
     // scenes of the build: scene id per vertex (batches only), energy pieces
@@ -137,9 +142,11 @@ hipError_t merge_duplicates(gipc_ctx* ctx, int32_t V, hipStream_t s, int64_t* ne
 hipError_t launch_sym_count(const int4* st_vid, TypeRanges tr, int32_t* deg, int32_t* kcount, hipStream_t s);
 hipError_t launch_sym_scatter(const int4* st_vid, TypeRanges tr, const int64_t* inc_ptr, int32_t* fill,
                               uint32_t* inc, hipStream_t s);
+// big: int32 [V] scratch for the rows sorted by whole workgroups, nbig: a
+// device counter that must be zero on entry
 hipError_t launch_sym_rowsort(int32_t V, int32_t max_deg, const int64_t* inc_ptr, const uint32_t* inc,
                               const int4* st_vid, TypeRanges tr, const int64_t* kptr, uint32_t* contrib,
-                              int32_t* kcol, int32_t* ncols, hipStream_t s);
+                              int32_t* kcol, int32_t* ncols, int32_t* big, int64_t* nbig, hipStream_t s);
 hipError_t launch_sym_fill(int32_t V, const int64_t* kptr, const int32_t* kcol, const int32_t* row_ptr,
                            int32_t* col_idx, int64_t* cptr, int32_t* slot_row, int32_t* diag_slot, int64_t nnzb,
                            hipStream_t s);

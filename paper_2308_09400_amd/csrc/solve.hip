@@ -82,18 +82,22 @@ __global__ void k_copy1(const uint8_t* __restrict__ src, uint8_t* __restrict__ d
 // host can enqueue many iterations at once.  Sums are in a fixed order and
 // therefore bit-reproducible.
 
-// sum of part[0..n) by one workgroup: 8 independent accumulators per lane
-// (loads in flight), then a fixed combination and the block butterfly
+// the single-workgroup reductions of the PCG scalars use 1024 threads
+constexpr int kRed = 1024;
+
+// sum of part[0..n) by one workgroup of kRed threads: 8 independent
+// accumulators per lane (loads in flight), then a fixed combination and the
+// block butterfly
 __device__ __forceinline__ double sum_parts(const double* __restrict__ part, int64_t n, double* lds) {
     double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int64_t i = threadIdx.x;
-    for (; i + 7 * kBlock < n; i += 8 * kBlock) {
+    for (; i + 7 * kRed < n; i += 8 * kRed) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] += part[i + u * kBlock];
+        for (int u = 0; u < 8; ++u) a[u] += part[i + u * kRed];
     }
-    for (int u = 0; i < n; i += kBlock, ++u) a[u & 7] += part[i];
+    for (int u = 0; i < n; i += kRed, ++u) a[u & 7] += part[i];
     double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-    return block_sum(s, lds);
+    return block_sum_n<kRed>(s, lds);
 }
 
 // inverse of each row's diagonal block (cofactors, FP64); identity if singular
@@ -172,9 +176,9 @@ __global__ void __launch_bounds__(kBlock) k_pcg_spmv(int32_t nrows, const int32_
     if (threadIdx.x == 0) part[blockIdx.x] = d;
 }
 
-__global__ void __launch_bounds__(kBlock) k_pcg_alpha(const double* __restrict__ part, int64_t nb, PcgScalars* sc) {
+__global__ void __launch_bounds__(kRed) k_pcg_alpha(const double* __restrict__ part, int64_t nb, PcgScalars* sc) {
     if (sc->done) return;
-    __shared__ double lds[kBlock / 64];
+    __shared__ double lds[kRed / 64];
     double pq = sum_parts(part, nb, lds);
     if (threadIdx.x == 0) {
         sc->pq = pq;
@@ -227,10 +231,10 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(int first, int32_t V, con
 }
 
 // first: initial scalars; otherwise beta, the new r.z and the stopping test
-__global__ void __launch_bounds__(kBlock) k_pcg_beta(int first, const double* __restrict__ part, int64_t nb,
+__global__ void __launch_bounds__(kRed) k_pcg_beta(int first, const double* __restrict__ part, int64_t nb,
                                                      PcgScalars* sc, double rtol2, int maxit) {
     if (!first && sc->done) return;
-    __shared__ double lds[kBlock / 64];
+    __shared__ double lds[kRed / 64];
     const double RZ = sum_parts(part, nb, lds), RR = sum_parts(part + nb, nb, lds);
     const double BB = first ? sum_parts(part + 2 * nb, nb, lds) : 0.0;
     if (threadIdx.x != 0) return;
@@ -337,7 +341,7 @@ hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x,
         GIPC_TRY(launch_spmv(A, x, q, s));
     }
     k_pcg_update<<<(unsigned)nbv, kBlock, 0, s>>>(1, V, b, x, r, z, p, q, minv, part, sc);
-    k_pcg_beta<<<1, kBlock, 0, s>>>(1, part, nbv, sc, rtol * rtol, maxit);
+    k_pcg_beta<<<1, kRed, 0, s>>>(1, part, nbv, sc, rtol * rtol, maxit);
     if (f32) k_pupdate<<<nbn, kBlock, 0, s>>>(n3, z, p, p32, sc, 1);  // FP32 copy of p0
     GIPC_TRY(hipGetLastError());
 
@@ -353,9 +357,9 @@ hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x,
             else
                 k_pcg_spmv<double><<<(unsigned)nbs, kBlock, 0, s>>>(
                     V, A.row_ptr, A.col_idx, static_cast<const double*>(A.val), A.nnzb, p, p, q, part, sc);
-            k_pcg_alpha<<<1, kBlock, 0, s>>>(part, nbs, sc);
+            k_pcg_alpha<<<1, kRed, 0, s>>>(part, nbs, sc);
             k_pcg_update<<<(unsigned)nbv, kBlock, 0, s>>>(0, V, b, x, r, z, p, q, minv, part, sc);
-            k_pcg_beta<<<1, kBlock, 0, s>>>(0, part, nbv, sc, 0.0, 0);
+            k_pcg_beta<<<1, kRed, 0, s>>>(0, part, nbv, sc, 0.0, 0);
             k_pupdate<<<nbn, kBlock, 0, s>>>(n3, z, p, p32, sc, 0);
         }
         GIPC_TRY(hipGetLastError());

@@ -5,9 +5,12 @@
 //  1. incidence counts per vertex (integer atomics: counts are exact);
 //  2. exclusive scans -> per-vertex incidence and contribution offsets;
 //  3. incidence scatter (order inside a vertex is irrelevant: step 4 sorts);
-//  4. per block row, one workgroup builds the keys (column, k, i, j) of all
-//     local blocks landing in that row and sorts them in LDS (bitonic); the
-//     sorted codes are the row's contribution lists, grouped by column;
+//  4. per block row, the keys (column, k, i, j) of all local blocks landing
+//     in that row are sorted: one wavefront per row with the keys in
+//     registers (bitonic network over cross-lane shuffles) for rows of up to
+//     128 incidences, one workgroup per row with the keys in LDS for the
+//     rest; the sorted codes are the row's contribution lists, grouped by
+//     column;
 //  5. scan of the per-row column counts -> row_ptr;
 //  6. per row, the column boundaries give col_idx and the start of each
 //     block's contribution list.
@@ -81,21 +84,19 @@ __global__ void __launch_bounds__(kBlock) k_sym_scatter(const int4* __restrict__
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_sym_rowsort(const int64_t* __restrict__ inc_ptr,
-                                                        const uint32_t* __restrict__ inc,
-                                                        const int4* __restrict__ st_vid, TypeRanges tr,
-                                                        const int64_t* __restrict__ kptr,
-                                                        uint32_t* __restrict__ contrib, int32_t* __restrict__ kcol,
-                                                        int32_t* __restrict__ ncols) {
+constexpr int kWaveM = 8;                    // keys per lane in the wavefront sort
+constexpr int kWaveN = 64 * kWaveM;          // 512 keys per row
+constexpr int kWaveIncidences = kWaveN / 4;  // 128 incidences of 4 key slots
+
+// sort of one row's keys in LDS by a whole workgroup (rows with more than
+// kWaveIncidences incidences)
+__device__ void rowsort_lds(int r, const int64_t* __restrict__ inc_ptr, const uint32_t* __restrict__ inc,
+                            const int4* __restrict__ st_vid, const TypeRanges& tr, const int64_t* __restrict__ kptr,
+                            uint32_t* __restrict__ contrib, int32_t* __restrict__ kcol, int32_t* __restrict__ ncols) {
     extern __shared__ unsigned long long keys[];
     __shared__ int32_t cnt;
-    const int r = blockIdx.x;
     const int64_t start = inc_ptr[r];
     const int n = (int)(inc_ptr[r + 1] - start);
-    if (n == 0) {
-        if (threadIdx.x == 0) ncols[r] = 1;  // the diagonal block alone
-        return;
-    }
     unsigned N = 1;
     while (N < 4u * (unsigned)n) N <<= 1;
     for (unsigned t = threadIdx.x; t < N; t += kBlock) keys[t] = ~0ull;
@@ -138,6 +139,130 @@ __global__ void __launch_bounds__(kBlock) k_sym_rowsort(const int64_t* __restric
     atomicAdd(&cnt, c);
     __syncthreads();
     if (threadIdx.x == 0) ncols[r] = cnt;
+}
+
+__device__ __forceinline__ unsigned long long shfl_xor64(unsigned long long v, int m) {
+    const int lo = __shfl_xor((int)(uint32_t)v, m, 64), hi = __shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+    return ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+__device__ __forceinline__ unsigned long long shfl_up64(unsigned long long v, int d) {
+    const int lo = __shfl_up((int)(uint32_t)v, d, 64), hi = __shfl_up((int)(uint32_t)(v >> 32), d, 64);
+    return ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// one wavefront per row: lane l holds the key slots 8l .. 8l+7 (incidences
+// 2l and 2l+1, four slots each, unused slots ~0); a bitonic network over the
+// first Neff = pow2 >= 4n slots sorts the row, exchanging across lanes with
+// shuffles for distances >= 8 and inside the lane below.  Rows with more
+// incidences are appended to `big` for the workgroup sort.
+__global__ void __launch_bounds__(kBlock) k_sym_rowsort_wave(int32_t V, const int64_t* __restrict__ inc_ptr,
+                                                             const uint32_t* __restrict__ inc,
+                                                             const int4* __restrict__ st_vid, TypeRanges tr,
+                                                             const int64_t* __restrict__ kptr,
+                                                             uint32_t* __restrict__ contrib,
+                                                             int32_t* __restrict__ kcol, int32_t* __restrict__ ncols,
+                                                             int32_t* __restrict__ big,
+                                                             unsigned long long* __restrict__ nbig) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (r >= V) return;  // the whole wavefront
+    const int64_t start = inc_ptr[r];
+    const int n = (int)(inc_ptr[r + 1] - start);
+    if (n == 0) {
+        if (lane == 0) ncols[r] = 1;  // the diagonal block alone
+        return;
+    }
+    if (n > kWaveIncidences) {
+        if (lane == 0) big[atomicAdd(nbig, 1ull)] = (int32_t)r;
+        return;
+    }
+    unsigned long long key[kWaveM];
+#pragma unroll
+    for (int q = 0; q < kWaveM; ++q) key[q] = ~0ull;
+#pragma unroll
+    for (int h = 0; h < kWaveM / 4; ++h) {
+        const int t = (kWaveM / 4) * lane + h;
+        if (t < n) {
+            const uint32_t code = inc[start + t];
+            const uint32_t k = code >> 2, i = code & 3u;
+            const int nv = ft_nverts(type_of(k, tr));
+            const int4 v = st_vid[k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (j < nv)
+                    key[4 * h + j] = ((unsigned long long)(uint32_t)vslot(v, j) << 32) |
+                                     (unsigned long long)((k << 4) | (i << 2) | (uint32_t)j);
+        }
+    }
+    unsigned Neff = kWaveM;
+    while (Neff < 4u * (unsigned)n) Neff <<= 1;
+#pragma unroll
+    for (int kk = 2; kk <= kWaveN; kk <<= 1) {
+        if ((unsigned)kk > Neff) break;  // uniform in the wavefront
+#pragma unroll
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            if (j >= kWaveM) {
+#pragma unroll
+                for (int q = 0; q < kWaveM; ++q) {
+                    const int e = kWaveM * lane + q;
+                    const unsigned long long o = shfl_xor64(key[q], j / kWaveM);
+                    const bool up = (e & kk) == 0, lower = (e & j) == 0;
+                    const unsigned long long mn = key[q] < o ? key[q] : o, mx = key[q] < o ? o : key[q];
+                    key[q] = (lower == up) ? mn : mx;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < kWaveM; ++q) {
+                    if ((q & j) == 0) {
+                        const int l = q | j;
+                        const int e = kWaveM * lane + q;
+                        const bool up = (e & kk) == 0;
+                        const unsigned long long a = key[q], b = key[l];
+                        if ((a > b) == up) {
+                            key[q] = b;
+                            key[l] = a;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    const int64_t base = kptr[r];
+    const int K = (int)(kptr[r + 1] - base);
+    const unsigned long long prev_last = shfl_up64(key[kWaveM - 1], 1);
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < kWaveM; ++q) {
+        const int e = kWaveM * lane + q;
+        if (e < K) {
+            const int col = (int)(key[q] >> 32);
+            contrib[base + e] = (uint32_t)key[q];
+            kcol[base + e] = col;
+            const unsigned long long pk = q == 0 ? prev_last : key[q > 0 ? q - 1 : 0];
+            if (e == 0 || (int)(pk >> 32) != col) ++c;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if (lane == 0) ncols[r] = c;
+}
+
+// one workgroup per listed row (grid-stride over the list of rows the
+// wavefront kernel left: more than kWaveIncidences incidences)
+__global__ void __launch_bounds__(kBlock) k_sym_rowsort(const int32_t* __restrict__ rows,
+                                                        const unsigned long long* __restrict__ nrows,
+                                                        const int64_t* __restrict__ inc_ptr,
+                                                        const uint32_t* __restrict__ inc,
+                                                        const int4* __restrict__ st_vid, TypeRanges tr,
+                                                        const int64_t* __restrict__ kptr,
+                                                        uint32_t* __restrict__ contrib, int32_t* __restrict__ kcol,
+                                                        int32_t* __restrict__ ncols) {
+    const int64_t nr = (int64_t)*nrows;
+    for (int64_t idx = blockIdx.x; idx < nr; idx += gridDim.x) {
+        rowsort_lds(rows[idx], inc_ptr, inc, st_vid, tr, kptr, contrib, kcol, ncols);
+        __syncthreads();
+    }
 }
 
 __device__ __forceinline__ int block_exscan_i32(int v, int* lds, int& total) {
@@ -226,12 +351,18 @@ hipError_t launch_sym_scatter(const int4* st_vid, TypeRanges tr, const int64_t* 
 
 hipError_t launch_sym_rowsort(int32_t V, int32_t max_deg, const int64_t* inc_ptr, const uint32_t* inc,
                               const int4* st_vid, TypeRanges tr, const int64_t* kptr, uint32_t* contrib,
-                              int32_t* kcol, int32_t* ncols, hipStream_t s) {
+                              int32_t* kcol, int32_t* ncols, int32_t* big, int64_t* nbig, hipStream_t s) {
     if (V == 0) return hipSuccess;
+    unsigned long long* nb = reinterpret_cast<unsigned long long*>(nbig);
+    const unsigned blocks = (unsigned)(((int64_t)V + kBlock / 64 - 1) / (kBlock / 64));
+    k_sym_rowsort_wave<<<blocks, kBlock, 0, s>>>(V, inc_ptr, inc, st_vid, tr, kptr, contrib, kcol, ncols, big, nb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || max_deg <= kWaveIncidences) return e;
     unsigned N = 64;
     while (N < 4u * (unsigned)max_deg) N <<= 1;
-    size_t lds = sizeof(unsigned long long) * N;
-    k_sym_rowsort<<<(unsigned)V, kBlock, lds, s>>>(inc_ptr, inc, st_vid, tr, kptr, contrib, kcol, ncols);
+    const size_t lds = sizeof(unsigned long long) * N;
+    const unsigned grid = (unsigned)(V < 2048 ? V : 2048);
+    k_sym_rowsort<<<grid, kBlock, lds, s>>>(big, nb, inc_ptr, inc, st_vid, tr, kptr, contrib, kcol, ncols);
     return hipGetLastError();
 }
 
