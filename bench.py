@@ -43,6 +43,13 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, vendor figure
 FP64_VECTOR_TFLOPS = 78.6    # MI355X FP64 vector peak
 
+# HBM bytes per launch of the roofline kernel on the default workload, from
+# two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the counts of a
+# 2 GiB copy with the library's copy kernel (bytes = 2.0 x FETCH_SIZE +
+# 1.0 x WRITE_SIZE), as summarised in profiles/sheets10_path.md.  Valid only
+# for the kernel source those runs measured: reset to None when it changes.
+MEASURED_TRAFFIC = {"k_spmv<double>": 1.575e9}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -73,19 +80,20 @@ def make_scene(name):
     return s, desc
 
 
-def cpu_baseline(s, n_sample):
+def cpu_baseline(s, n_sample, nthreads=0):
     """The oracle as it stands (eval with per-pair Hessians + assembly) on a seeded sample."""
     import oracle
     import scenes
     sub = scenes.subsample(s, n_sample, seed=7)
     prm = oracle.params(dhat=s.dhat, kappa=s.kappa)
     t0 = time.perf_counter()
-    r = oracle.eval_scene(s.x, sub, prm, x_rest=s.x_rest, per_pair=True)
+    r = oracle.eval_scene(s.x, sub, prm, x_rest=s.x_rest, nthreads=nthreads, per_pair=True)
     oracle.assemble(s.V, sub, r["pairH"], s.diag)
     dt = time.perf_counter() - t0
-    return {"value": len(sub) / dt, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+    cores = nthreads if nthreads > 0 else oracle.num_threads()
+    return {"value": len(sub) / dt, "unit": "pairs/s", "cores": cores, "kind": "oracle",
             "sample": f"{len(sub)} candidates drawn (seed 7) from the same list; oracle eval with per-pair "
-                      f"Hessians (OpenMP) + assembly (serial sort); {dt:.1f} s"}
+                      f"Hessians ({cores} thread(s)) + assembly (serial sort); {dt:.1f} s"}
 
 
 def precision_compare(gp, ctx, x, xr, prm, diag, last, stream):
@@ -361,7 +369,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": float(spmv_gbs / HBM_PEAK_GBS),
-            "traffic": None,
+            "traffic": None if (mixed or args.workload != "sheets10") else MEASURED_TRAFFIC.get("k_spmv<double>"),
         },
     }
     # achievable bandwidth of a plain streaming copy with the library's own
@@ -386,6 +394,7 @@ def main():
     ctx.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_sample)
+        out["cpu_baseline_1thread"] = cpu_baseline(s, max(args.cpu_sample // 20, 1000), nthreads=1)
     print(json.dumps(out))
 
 

@@ -196,7 +196,7 @@ void gipc_ctx_destroy(gipc_ctx* ctx) {
                       &ctx->st_src, &ctx->mult, &ctx->mkeys, &ctx->mrep_of, &ctx->mcount,
                       &ctx->mflag, &ctx->mpos, &ctx->st_vid2, &ctx->st_src2, &ctx->deg, &ctx->kcount, &ctx->fill, &ctx->inc_ptr, &ctx->kptr, &ctx->inc,
                       &ctx->contrib, &ctx->kcol, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
-                      &ctx->slot_row, &ctx->diag_slot, &ctx->maxbuf, &ctx->bigrows, &ctx->rec_main, &ctx->rec_extra, &ctx->ev,
+                      &ctx->slot_row, &ctx->diag_slot, &ctx->maxbuf, &ctx->bigrows, &ctx->tslot, &ctx->incv, &ctx->rec_main, &ctx->rec_extra, &ctx->ev,
                       &ctx->epart, &ctx->vscene, &ctx->pieces, &ctx->poff,
                       &ctx->r, &ctx->z, &ctx->p, &ctx->q, &ctx->p32, &ctx->minv, &ctx->part, &ctx->scal, &ctx->scan_tmp,
                       &ctx->scan_tmp2};
@@ -352,13 +352,14 @@ gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
                     kMaxRowPairs);
     const int64_t ninc = hc[C_INC], K = hc[C_K];
     CK(ensure(ctx->inc, sizeof(uint32_t) * (size_t)ninc), "alloc incidences");
+    CK(ensure(ctx->incv, sizeof(int4) * (size_t)(ninc > 0 ? ninc : 1)), "alloc incidences");
     CK(ensure(ctx->contrib, sizeof(uint32_t) * (size_t)K), "alloc contributions");
     CK(ensure(ctx->kcol, sizeof(int32_t) * (size_t)K), "alloc contributions");
     CK(launch_sym_scatter(as<int4>(ctx->st_vid), tr, as<int64_t>(ctx->inc_ptr), as<int32_t>(ctx->fill),
-                          as<uint32_t>(ctx->inc), s),
+                          as<uint32_t>(ctx->inc), as<int4>(ctx->incv), s),
        "incidence scatter");
     CK(ensure(ctx->bigrows, sizeof(int32_t) * Vs), "alloc pattern");
-    CK(launch_sym_rowsort(V, max_deg, as<int64_t>(ctx->inc_ptr), as<uint32_t>(ctx->inc), as<int4>(ctx->st_vid), tr,
+    CK(launch_sym_rowsort(V, max_deg, as<int64_t>(ctx->inc_ptr), as<uint32_t>(ctx->inc), as<int4>(ctx->incv), tr,
                           as<int64_t>(ctx->kptr), as<uint32_t>(ctx->contrib), as<int32_t>(ctx->kcol),
                           as<int32_t>(ctx->ncols), as<int32_t>(ctx->bigrows), cnt + C_NBIG, s),
        "row sort");
@@ -375,6 +376,10 @@ gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
                        as<int32_t>(ctx->col_idx), as<int64_t>(ctx->cptr), as<int32_t>(ctx->slot_row),
                        as<int32_t>(ctx->diag_slot), nnzb, s),
        "pattern fill");
+    CK(ensure(ctx->tslot, sizeof(int32_t) * (size_t)(nnzb > 0 ? nnzb : 1)), "alloc pattern");
+    CK(launch_sym_transpose(nnzb, as<int32_t>(ctx->slot_row), as<int32_t>(ctx->col_idx), as<int32_t>(ctx->row_ptr),
+                            as<int32_t>(ctx->tslot), s),
+       "pattern transpose");
 
     ctx->ranges = tr;
     ctx->Ps = Ps;
@@ -466,7 +471,7 @@ hipError_t eval_enqueue(gipc_ctx* ctx, const DevParams& pm, const gipc_mesh* mes
                          ctx->nnzb, t.row_lanes, s);
     if (e != hipSuccess) return e;
     if (assemble) {
-        e = launch_offdiag(ctx->nnzb, as<int32_t>(ctx->slot_row), as<int32_t>(ctx->col_idx), as<int64_t>(ctx->cptr),
+        e = launch_offdiag(ctx->nnzb, as<int32_t>(ctx->slot_row), as<int32_t>(ctx->col_idx), as<int32_t>(ctx->tslot), as<int64_t>(ctx->cptr),
                            as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra), e0, m0,
                            A->val, A->dtype, t.offdiag_waves, s);
         if (e != hipSuccess) return e;
@@ -521,7 +526,7 @@ gipc_status gipc_assemble_bsr(gipc_ctx* ctx, const double* diag, const gipc_bsr*
                         as<double>(ctx->rec_main), as<double>(ctx->rec_extra), e0, m0, diag, nullptr, nullptr, A->val,
                         A->dtype, ctx->nnzb, ctx->tune.row_lanes, s),
        "diagonal blocks");
-    CK(launch_offdiag(ctx->nnzb, as<int32_t>(ctx->slot_row), as<int32_t>(ctx->col_idx), as<int64_t>(ctx->cptr),
+    CK(launch_offdiag(ctx->nnzb, as<int32_t>(ctx->slot_row), as<int32_t>(ctx->col_idx), as<int32_t>(ctx->tslot), as<int64_t>(ctx->cptr),
                       as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra), e0, m0,
                       A->val, A->dtype, ctx->tune.offdiag_waves, s),
        "off-diagonal blocks");
@@ -665,7 +670,7 @@ gipc_status gipc_autotune(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_param
     bt = INFINITY;
     for (int w : waves) {
         float ms = time_it([&] {
-            return launch_offdiag(ctx->nnzb, as<int32_t>(ctx->slot_row), as<int32_t>(ctx->col_idx),
+            return launch_offdiag(ctx->nnzb, as<int32_t>(ctx->slot_row), as<int32_t>(ctx->col_idx), as<int32_t>(ctx->tslot),
                                   as<int64_t>(ctx->cptr), as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main),
                                   as<double>(ctx->rec_extra), e0, m0, A->val, A->dtype, w, s);
         });

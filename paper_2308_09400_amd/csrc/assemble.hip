@@ -42,15 +42,17 @@ __device__ __forceinline__ void add_block(double* B, const double* __restrict__ 
     }
 }
 
-__device__ __forceinline__ void store_block(void* val, int dtype, int64_t nnzb, int64_t s, const double* B) {
+// store B (tr = false) or its transpose (tr = true) into block slot s
+__device__ __forceinline__ void store_block(void* val, int dtype, int64_t nnzb, int64_t s, const double* B,
+                                            bool tr = false) {
     if (dtype == GIPC_F64) {
         double* v = static_cast<double*>(val);
 #pragma unroll
-        for (int c = 0; c < 9; ++c) v[c * nnzb + s] = B[c];
+        for (int c = 0; c < 9; ++c) v[c * nnzb + s] = B[tr ? 3 * (c % 3) + c / 3 : c];
     } else {
         float* v = static_cast<float*>(val);
 #pragma unroll
-        for (int c = 0; c < 9; ++c) v[c * nnzb + s] = (float)B[c];
+        for (int c = 0; c < 9; ++c) v[c * nnzb + s] = (float)B[tr ? 3 * (c % 3) + c / 3 : c];
     }
 }
 
@@ -111,13 +113,20 @@ __global__ void __launch_bounds__(kBlock) k_rows_diag(int mode, int32_t V, const
     if (mode & 2) {
         double dv = diag ? diag[r] : 0.0;
         B[0] += dv; B[4] += dv; B[8] += dv;
+        // symmetric up to rounding: keep the upper triangle on both sides
+        B[3] = B[1]; B[6] = B[2]; B[7] = B[5];
         store_block(val, dtype, nnzb, s, B);
     }
 }
 
+// one lane per block above the diagonal: its contribution list summed in
+// order, stored, and stored transposed in the mirrored slot (the (c, r)
+// list holds the same pairs with i and j swapped, so its sum is the
+// transpose up to rounding; storing the transpose makes A exactly symmetric)
 template <int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_offdiag(int64_t nnzb, const int32_t* __restrict__ slot_row,
                                                     const int32_t* __restrict__ col_idx,
+                                                    const int32_t* __restrict__ tslot,
                                                     const int64_t* __restrict__ cptr,
                                                     const uint32_t* __restrict__ contrib,
                                                     const double* __restrict__ rec_main,
@@ -125,7 +134,8 @@ __global__ void __launch_bounds__(BLOCK) k_offdiag(int64_t nnzb, const int32_t* 
                                                     void* val, int dtype) {
     const int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (s >= nnzb) return;
-    if (col_idx[s] == slot_row[s]) return;  // diagonal blocks: k_rows_diag
+    const int32_t t = tslot[s];
+    if (t == -1) return;  // diagonal (k_rows_diag) and lower blocks (written as transposes)
     double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t t0 = cptr[s], t1 = cptr[s + 1];
     for (int64_t t = t0; t < t1; ++t) {
@@ -133,6 +143,7 @@ __global__ void __launch_bounds__(BLOCK) k_offdiag(int64_t nnzb, const int32_t* 
         add_block(B, rec_main, rec_extra, e0, m0, code >> 4, (int)((code >> 2) & 3u), (int)(code & 3u));
     }
     store_block(val, dtype, nnzb, s, B);
+    if (t >= 0) store_block(val, dtype, nnzb, t, B, true);
 }
 
 // Expanded per-pair view of the staged list and the stored factors.
@@ -224,29 +235,30 @@ hipError_t launch_rows_diag(int mode, int32_t V, const int32_t* diag_slot, const
 
 namespace {
 template <int BLOCK>
-hipError_t offdiag_launch(int64_t nnzb, const int32_t* slot_row, const int32_t* col_idx, const int64_t* cptr,
-                          const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t e0,
-                          int64_t m0, void* val, int dtype, hipStream_t s) {
+hipError_t offdiag_launch(int64_t nnzb, const int32_t* slot_row, const int32_t* col_idx, const int32_t* tslot,
+                          const int64_t* cptr, const uint32_t* contrib, const double* rec_main,
+                          const double* rec_extra, int64_t e0, int64_t m0, void* val, int dtype, hipStream_t s) {
     const int64_t nb = (nnzb + BLOCK - 1) / BLOCK;
-    k_offdiag<BLOCK><<<(unsigned)nb, BLOCK, 0, s>>>(nnzb, slot_row, col_idx, cptr, contrib, rec_main, rec_extra, e0,
-                                                    m0, val, dtype);
+    k_offdiag<BLOCK><<<(unsigned)nb, BLOCK, 0, s>>>(nnzb, slot_row, col_idx, tslot, cptr, contrib, rec_main,
+                                                    rec_extra, e0, m0, val, dtype);
     return hipGetLastError();
 }
 }  // namespace
 
-hipError_t launch_offdiag(int64_t nnzb, const int32_t* slot_row, const int32_t* col_idx, const int64_t* cptr,
-                          const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t e0,
-                          int64_t m0, void* val, int dtype, int waves, hipStream_t s) {
+hipError_t launch_offdiag(int64_t nnzb, const int32_t* slot_row, const int32_t* col_idx, const int32_t* tslot,
+                          const int64_t* cptr, const uint32_t* contrib, const double* rec_main,
+                          const double* rec_extra, int64_t e0, int64_t m0, void* val, int dtype, int waves,
+                          hipStream_t s) {
     if (nnzb == 0) return hipSuccess;
     switch (waves) {
-        case 1: return offdiag_launch<64>(nnzb, slot_row, col_idx, cptr, contrib, rec_main, rec_extra, e0, m0, val,
-                                          dtype, s);
-        case 2: return offdiag_launch<128>(nnzb, slot_row, col_idx, cptr, contrib, rec_main, rec_extra, e0, m0, val,
-                                           dtype, s);
-        case 8: return offdiag_launch<512>(nnzb, slot_row, col_idx, cptr, contrib, rec_main, rec_extra, e0, m0, val,
-                                           dtype, s);
-        default: return offdiag_launch<256>(nnzb, slot_row, col_idx, cptr, contrib, rec_main, rec_extra, e0, m0, val,
-                                            dtype, s);
+        case 1: return offdiag_launch<64>(nnzb, slot_row, col_idx, tslot, cptr, contrib, rec_main, rec_extra, e0, m0,
+                                          val, dtype, s);
+        case 2: return offdiag_launch<128>(nnzb, slot_row, col_idx, tslot, cptr, contrib, rec_main, rec_extra, e0,
+                                           m0, val, dtype, s);
+        case 8: return offdiag_launch<512>(nnzb, slot_row, col_idx, tslot, cptr, contrib, rec_main, rec_extra, e0,
+                                           m0, val, dtype, s);
+        default: return offdiag_launch<256>(nnzb, slot_row, col_idx, tslot, cptr, contrib, rec_main, rec_extra, e0,
+                                            m0, val, dtype, s);
     }
 }
 

@@ -88,7 +88,7 @@ struct gipc_ctx {
     int32_t V = 0;
     // symbolic
     gipc::DevBuf deg, kcount, fill, inc_ptr, kptr, inc, contrib, kcol, ncols, row_ptr, col_idx, cptr, slot_row,
-        diag_slot, maxbuf, bigrows;
+        diag_slot, maxbuf, bigrows, tslot, incv;
     int64_t nnzb = 0, K = 0;
     int32_t max_deg = 0;
     // scenes of the build: scene id per vertex (batches only), energy pieces
@@ -140,16 +140,20 @@ hipError_t merge_duplicates(gipc_ctx* ctx, int32_t V, hipStream_t s, int64_t* ne
 
 // ---- symbolic.hip
 hipError_t launch_sym_count(const int4* st_vid, TypeRanges tr, int32_t* deg, int32_t* kcount, hipStream_t s);
+// inc: incidence codes k << 2 | i; incv: the incidence's pair stencil
 hipError_t launch_sym_scatter(const int4* st_vid, TypeRanges tr, const int64_t* inc_ptr, int32_t* fill,
-                              uint32_t* inc, hipStream_t s);
+                              uint32_t* inc, int4* incv, hipStream_t s);
 // big: int32 [V] scratch for the rows sorted by whole workgroups, nbig: a
 // device counter that must be zero on entry
 hipError_t launch_sym_rowsort(int32_t V, int32_t max_deg, const int64_t* inc_ptr, const uint32_t* inc,
-                              const int4* st_vid, TypeRanges tr, const int64_t* kptr, uint32_t* contrib,
+                              const int4* incv, TypeRanges tr, const int64_t* kptr, uint32_t* contrib,
                               int32_t* kcol, int32_t* ncols, int32_t* big, int64_t* nbig, hipStream_t s);
 hipError_t launch_sym_fill(int32_t V, const int64_t* kptr, const int32_t* kcol, const int32_t* row_ptr,
                            int32_t* col_idx, int64_t* cptr, int32_t* slot_row, int32_t* diag_slot, int64_t nnzb,
                            hipStream_t s);
+// tslot[s] = slot of (c, r) for every block s = (r, c) with c > r, else -1
+hipError_t launch_sym_transpose(int64_t nnzb, const int32_t* slot_row, const int32_t* col_idx,
+                                const int32_t* row_ptr, int32_t* tslot, hipStream_t s);
 
 // ---- eval.hip
 // waves: workgroup size in wavefronts (1, 2, 4 or 8)
@@ -167,10 +171,12 @@ hipError_t launch_rows_diag(int mode, int32_t V, const int32_t* diag_slot, const
                             const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t e0,
                             int64_t m0, const double* diag, double* grad, double* ev, void* val, int dtype,
                             int64_t nnzb, int lanes, hipStream_t s);
-// waves: workgroup size in wavefronts (1, 2, 4 or 8)
-hipError_t launch_offdiag(int64_t nnzb, const int32_t* slot_row, const int32_t* col_idx, const int64_t* cptr,
-                          const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t e0,
-                          int64_t m0, void* val, int dtype, int waves, hipStream_t s);
+// blocks above the diagonal are summed once and stored with their
+// transpose at tslot; waves: workgroup size in wavefronts (1, 2, 4 or 8)
+hipError_t launch_offdiag(int64_t nnzb, const int32_t* slot_row, const int32_t* col_idx, const int32_t* tslot,
+                          const int64_t* cptr, const uint32_t* contrib, const double* rec_main,
+                          const double* rec_extra, int64_t e0, int64_t m0, void* val, int dtype, int waves,
+                          hipStream_t s);
 hipError_t launch_pair_inspect(const int4* st_vid, const int32_t* st_src, const int32_t* smult, TypeRanges tr,
                                const double* rec_main, const double* rec_extra, const double* x, const double* xr,
                                const DevParams& pm, int32_t* src, int32_t* type, int32_t* vid, int32_t* mult,

@@ -136,18 +136,24 @@ __device__ __forceinline__ void stv(double* a, int64_t r, d3 v) {
     a[3 * r] = v.x; a[3 * r + 1] = v.y; a[3 * r + 2] = v.z;
 }
 
-// q = A p (kG lanes per row) and one partial of p.q per workgroup.  T is
-// the matrix type: for FP32 matrices the product runs in FP32 on the FP32
-// copy pm of p and is widened to FP64 when stored; the dot is FP64.
+// q = A p (kG lanes per row) and one partial of p.q per workgroup of
+// kPcgBlock threads (32 rows), so the single-workgroup sum that forms alpha
+// reads few partials.  (A fixed grid walking row groups with a stride gave
+// fewer partials still but a slower product.)  T is the matrix type: for
+// FP32 matrices the product runs in FP32 on the FP32 copy pm of p and is
+// widened to FP64 when stored; the dot is FP64.
+constexpr int kPcgBlock = 1024;
+
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_pcg_spmv(int32_t nrows, const int32_t* __restrict__ rp,
-                                                     const int32_t* __restrict__ ci, const T* __restrict__ val,
-                                                     int64_t nnzb, const T* __restrict__ pm,
-                                                     const double* __restrict__ p, double* __restrict__ q,
-                                                     double* __restrict__ part, const PcgScalars* __restrict__ sc) {
+__global__ void __launch_bounds__(kPcgBlock) k_pcg_spmv(int32_t nrows, const int32_t* __restrict__ rp,
+                                                        const int32_t* __restrict__ ci, const T* __restrict__ val,
+                                                        int64_t nnzb, const T* __restrict__ pm,
+                                                        const double* __restrict__ p, double* __restrict__ q,
+                                                        double* __restrict__ part,
+                                                        const PcgScalars* __restrict__ sc) {
     if (sc->done) return;
-    __shared__ double lds[kBlock / 64];
-    const int64_t row = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kG;
+    __shared__ double lds[kPcgBlock / 64];
+    const int64_t row = ((int64_t)blockIdx.x * kPcgBlock + threadIdx.x) / kG;
     const int lg = threadIdx.x % kG;
     T a0 = 0, a1 = 0, a2 = 0;
     if (row < nrows) {
@@ -172,7 +178,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_spmv(int32_t nrows, const int32_
         stv(q, row, qv);
         d = dot(ldv(p, row), qv);
     }
-    d = block_sum(d, lds);
+    d = block_sum_n<kPcgBlock>(d, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = d;
 }
 
@@ -306,7 +312,7 @@ hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x,
     const int32_t V = A.nbrows;
     const int64_t n3 = 3 * (int64_t)V;
     const int64_t nbv = (V + kBlock - 1) / kBlock;               // row-parallel kernels
-    const int64_t nbs = ((int64_t)V * kG + kBlock - 1) / kBlock;  // SpMV kernel
+    const int64_t nbs = ((int64_t)V * kG + kPcgBlock - 1) / kPcgBlock;  // SpMV kernel
     hipError_t e;
 #define GIPC_TRY(x)                            \
     do {                                       \
@@ -333,7 +339,7 @@ hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x,
         k_bj_inverse<float><<<(unsigned)nbv, kBlock, 0, s>>>(V, A.row_ptr, A.col_idx,
                                                              static_cast<const float*>(A.val), A.nnzb, minv);
         k_pupdate<<<nbn, kBlock, 0, s>>>(n3, nullptr, x, p32, sc, 1);  // FP32 copy of x0 in p32
-        k_pcg_spmv<float><<<(unsigned)nbs, kBlock, 0, s>>>(V, A.row_ptr, A.col_idx, static_cast<const float*>(A.val),
+        k_pcg_spmv<float><<<(unsigned)nbs, kPcgBlock, 0, s>>>(V, A.row_ptr, A.col_idx, static_cast<const float*>(A.val),
                                                            A.nnzb, p32, x, q, part, sc);
     } else {
         k_bj_inverse<double><<<(unsigned)nbv, kBlock, 0, s>>>(V, A.row_ptr, A.col_idx,
@@ -352,10 +358,10 @@ hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x,
         int32_t m = maxit - launched < chunk ? maxit - launched : chunk;
         for (int32_t it = 0; it < m; ++it) {
             if (f32)
-                k_pcg_spmv<float><<<(unsigned)nbs, kBlock, 0, s>>>(
+                k_pcg_spmv<float><<<(unsigned)nbs, kPcgBlock, 0, s>>>(
                     V, A.row_ptr, A.col_idx, static_cast<const float*>(A.val), A.nnzb, p32, p, q, part, sc);
             else
-                k_pcg_spmv<double><<<(unsigned)nbs, kBlock, 0, s>>>(
+                k_pcg_spmv<double><<<(unsigned)nbs, kPcgBlock, 0, s>>>(
                     V, A.row_ptr, A.col_idx, static_cast<const double*>(A.val), A.nnzb, p, p, q, part, sc);
             k_pcg_alpha<<<1, kRed, 0, s>>>(part, nbs, sc);
             k_pcg_update<<<(unsigned)nbv, kBlock, 0, s>>>(0, V, b, x, r, z, p, q, minv, part, sc);

@@ -64,9 +64,12 @@ __global__ void __launch_bounds__(kBlock) k_sym_count(const int4* __restrict__ s
     }
 }
 
+// every incidence also carries its pair's stencil (incv), so the row sort
+// streams contiguous records instead of gathering the staged list
 __global__ void __launch_bounds__(kBlock) k_sym_scatter(const int4* __restrict__ st_vid, TypeRanges tr,
                                                         const int64_t* __restrict__ inc_ptr,
-                                                        int32_t* __restrict__ fill, uint32_t* __restrict__ inc) {
+                                                        int32_t* __restrict__ fill, uint32_t* __restrict__ inc,
+                                                        int4* __restrict__ incv) {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool in = k < tr.off[8];
     const int nv = in ? ft_nverts(type_of(k, tr)) : 0;
@@ -80,7 +83,11 @@ __global__ void __launch_bounds__(kBlock) k_sym_scatter(const int4* __restrict__
         int base = 0;
         if (valid && w.head == lane) base = atomicAdd(&fill[vi], w.len);
         base = __shfl(base, valid ? w.head : lane, 64);
-        if (valid) inc[inc_ptr[vi] + base + (lane - w.head)] = ((uint32_t)k << 2) | (uint32_t)i;
+        if (valid) {
+            const int64_t at = inc_ptr[vi] + base + (lane - w.head);
+            inc[at] = ((uint32_t)k << 2) | (uint32_t)i;
+            incv[at] = v;
+        }
     }
 }
 
@@ -91,7 +98,7 @@ constexpr int kWaveIncidences = kWaveN / 4;  // 128 incidences of 4 key slots
 // sort of one row's keys in LDS by a whole workgroup (rows with more than
 // kWaveIncidences incidences)
 __device__ void rowsort_lds(int r, const int64_t* __restrict__ inc_ptr, const uint32_t* __restrict__ inc,
-                            const int4* __restrict__ st_vid, const TypeRanges& tr, const int64_t* __restrict__ kptr,
+                            const int4* __restrict__ incv, const TypeRanges& tr, const int64_t* __restrict__ kptr,
                             uint32_t* __restrict__ contrib, int32_t* __restrict__ kcol, int32_t* __restrict__ ncols) {
     extern __shared__ unsigned long long keys[];
     __shared__ int32_t cnt;
@@ -106,7 +113,7 @@ __device__ void rowsort_lds(int r, const int64_t* __restrict__ inc_ptr, const ui
         uint32_t code = inc[start + t];
         uint32_t k = code >> 2, i = code & 3u;
         int nv = ft_nverts(type_of(k, tr));
-        int4 v = st_vid[k];
+        int4 v = incv[start + t];
         for (int j = 0; j < nv; ++j)
             keys[4 * t + j] = ((unsigned long long)(uint32_t)vslot(v, j) << 32) | (unsigned long long)((k << 4) | (i << 2) | (uint32_t)j);
     }
@@ -158,7 +165,7 @@ __device__ __forceinline__ unsigned long long shfl_up64(unsigned long long v, in
 // incidences are appended to `big` for the workgroup sort.
 __global__ void __launch_bounds__(kBlock) k_sym_rowsort_wave(int32_t V, const int64_t* __restrict__ inc_ptr,
                                                              const uint32_t* __restrict__ inc,
-                                                             const int4* __restrict__ st_vid, TypeRanges tr,
+                                                             const int4* __restrict__ incv, TypeRanges tr,
                                                              const int64_t* __restrict__ kptr,
                                                              uint32_t* __restrict__ contrib,
                                                              int32_t* __restrict__ kcol, int32_t* __restrict__ ncols,
@@ -187,7 +194,7 @@ __global__ void __launch_bounds__(kBlock) k_sym_rowsort_wave(int32_t V, const in
             const uint32_t code = inc[start + t];
             const uint32_t k = code >> 2, i = code & 3u;
             const int nv = ft_nverts(type_of(k, tr));
-            const int4 v = st_vid[k];
+            const int4 v = incv[start + t];
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 if (j < nv)
@@ -254,13 +261,13 @@ __global__ void __launch_bounds__(kBlock) k_sym_rowsort(const int32_t* __restric
                                                         const unsigned long long* __restrict__ nrows,
                                                         const int64_t* __restrict__ inc_ptr,
                                                         const uint32_t* __restrict__ inc,
-                                                        const int4* __restrict__ st_vid, TypeRanges tr,
+                                                        const int4* __restrict__ incv, TypeRanges tr,
                                                         const int64_t* __restrict__ kptr,
                                                         uint32_t* __restrict__ contrib, int32_t* __restrict__ kcol,
                                                         int32_t* __restrict__ ncols) {
     const int64_t nr = (int64_t)*nrows;
     for (int64_t idx = blockIdx.x; idx < nr; idx += gridDim.x) {
-        rowsort_lds(rows[idx], inc_ptr, inc, st_vid, tr, kptr, contrib, kcol, ncols);
+        rowsort_lds(rows[idx], inc_ptr, inc, incv, tr, kptr, contrib, kcol, ncols);
         __syncthreads();
     }
 }
@@ -342,27 +349,62 @@ hipError_t launch_sym_count(const int4* st_vid, TypeRanges tr, int32_t* deg, int
 }
 
 hipError_t launch_sym_scatter(const int4* st_vid, TypeRanges tr, const int64_t* inc_ptr, int32_t* fill,
-                              uint32_t* inc, hipStream_t s) {
+                              uint32_t* inc, int4* incv, hipStream_t s) {
     int64_t nb = (tr.off[8] + kBlock - 1) / kBlock;
     if (nb == 0) return hipSuccess;
-    k_sym_scatter<<<(unsigned)nb, kBlock, 0, s>>>(st_vid, tr, inc_ptr, fill, inc);
+    k_sym_scatter<<<(unsigned)nb, kBlock, 0, s>>>(st_vid, tr, inc_ptr, fill, inc, incv);
     return hipGetLastError();
 }
 
 hipError_t launch_sym_rowsort(int32_t V, int32_t max_deg, const int64_t* inc_ptr, const uint32_t* inc,
-                              const int4* st_vid, TypeRanges tr, const int64_t* kptr, uint32_t* contrib,
+                              const int4* incv, TypeRanges tr, const int64_t* kptr, uint32_t* contrib,
                               int32_t* kcol, int32_t* ncols, int32_t* big, int64_t* nbig, hipStream_t s) {
     if (V == 0) return hipSuccess;
     unsigned long long* nb = reinterpret_cast<unsigned long long*>(nbig);
     const unsigned blocks = (unsigned)(((int64_t)V + kBlock / 64 - 1) / (kBlock / 64));
-    k_sym_rowsort_wave<<<blocks, kBlock, 0, s>>>(V, inc_ptr, inc, st_vid, tr, kptr, contrib, kcol, ncols, big, nb);
+    k_sym_rowsort_wave<<<blocks, kBlock, 0, s>>>(V, inc_ptr, inc, incv, tr, kptr, contrib, kcol, ncols, big, nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || max_deg <= kWaveIncidences) return e;
     unsigned N = 64;
     while (N < 4u * (unsigned)max_deg) N <<= 1;
     const size_t lds = sizeof(unsigned long long) * N;
     const unsigned grid = (unsigned)(V < 2048 ? V : 2048);
-    k_sym_rowsort<<<grid, kBlock, lds, s>>>(big, nb, inc_ptr, inc, st_vid, tr, kptr, contrib, kcol, ncols);
+    k_sym_rowsort<<<grid, kBlock, lds, s>>>(big, nb, inc_ptr, inc, incv, tr, kptr, contrib, kcol, ncols);
+    return hipGetLastError();
+}
+
+namespace {
+// slot of the transposed block (c, r) for every block (r, c) with c > r:
+// binary search of r among the sorted columns of row c; -1 for diagonal and
+// lower blocks.  The pattern is symmetric by construction (a pair's local
+// blocks (i, j) and (j, i) both land in it); an upper block without mirror
+// would get -2 and be summed on its own.
+__global__ void __launch_bounds__(kBlock) k_sym_transpose(int64_t nnzb, const int32_t* __restrict__ slot_row,
+                                                          const int32_t* __restrict__ col_idx,
+                                                          const int32_t* __restrict__ row_ptr,
+                                                          int32_t* __restrict__ tslot) {
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= nnzb) return;
+    const int32_t r = slot_row[s], c = col_idx[s];
+    int32_t t = -1;
+    if (c > r) {
+        int32_t lo = row_ptr[c], hi = row_ptr[c + 1] - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (col_idx[mid] < r) lo = mid + 1;
+            else hi = mid;
+        }
+        t = col_idx[lo] == r ? lo : -2;
+    }
+    tslot[s] = t;
+}
+}  // namespace
+
+hipError_t launch_sym_transpose(int64_t nnzb, const int32_t* slot_row, const int32_t* col_idx,
+                                const int32_t* row_ptr, int32_t* tslot, hipStream_t s) {
+    if (nnzb == 0) return hipSuccess;
+    k_sym_transpose<<<(unsigned)((nnzb + kBlock - 1) / kBlock), kBlock, 0, s>>>(nnzb, slot_row, col_idx, row_ptr,
+                                                                                tslot);
     return hipGetLastError();
 }
 

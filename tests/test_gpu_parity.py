@@ -436,6 +436,18 @@ def test_pcg_reports_breakdown_on_indefinite_matrix(gp):
     gpu["ctx"].close()
 
 
+def test_bsr_is_exactly_symmetric(gp):
+    # every block above the diagonal is stored with its transpose below
+    s = scenes.two_sheets(n=16, seed=1)
+    pg, _ = _prm_pair(gp, s.dhat, s.kappa)
+    for dtype in (gp.F64, gp.F32):
+        g = run_gpu(gp, s.x, s.x_rest, s.tuples, pg, np.full(s.V, 10.0), dtype=dtype, inspect=False)
+        blocks, _, _ = blocks_of(g["A"])
+        for (r, c), B in blocks.items():
+            assert np.array_equal(B, blocks[(c, r)].T), (r, c)
+        g["ctx"].close()
+
+
 def test_deterministic_bitwise(gp):
     s = scenes.two_sheets(n=16, seed=1)
     pg, _ = _prm_pair(gp, s.dhat, s.kappa)
