@@ -315,6 +315,8 @@ gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
     for (int t = 0; t < 9; ++t) tr.off[t] = P > 0 ? hc[C_OFF + t] : 0;
     tr.off[0] = 0;
     const TypeRanges raw = tr;
+    if (raw.off[8] >= (int64_t(1) << 28))
+        return fail(ctx, GIPC_ERR_WORKSPACE, "more than 2^28 active pairs (%lld)", (long long)raw.off[8]);
     ctx->merged = false;
     if (tr.off[8] > 0 && !(params->flags & GIPC_FLAG_NO_MERGE)) {
         ctx->ranges = tr;

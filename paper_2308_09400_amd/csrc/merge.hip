@@ -14,10 +14,14 @@
 // constraints.  Counts are integer atomics and the compaction keeps the
 // staged order, so the result is deterministic.
 //
-// Layout: one 16-byte entry per slot (fingerprint, representative), and a
-// key's home slot is proportional to its first vertex plus a 16-slot
-// offset from the fingerprint: staged pairs come in vertex-major order
-// within each sub-type, so neighbouring lanes probe neighbouring lines.
+// Layout: one 8-byte word per slot holding a 36-bit fingerprint above the
+// 28-bit representative (staged indices are below 2^28), so a slot is
+// claimed and its representative lowered with 64-bit atomics on one word
+// (the minimum of two words with the same fingerprint is the one with the
+// smaller representative).  A key's home slot is proportional to its first
+// vertex plus a 16-slot offset from the fingerprint: staged pairs come in
+// vertex-major order within each sub-type, so neighbouring lanes probe
+// neighbouring lines.
 #include "internal.hpp"
 
 namespace gipc {
@@ -40,20 +44,18 @@ __device__ __forceinline__ Key canon(bool pp, int4 v) {
     return Key{v.x, min(v.y, v.z), max(v.y, v.z)};
 }
 
+constexpr int kRepBits = 28;
+constexpr unsigned long long kRepMask = (1ull << kRepBits) - 1ull;
+
+// 36-bit fingerprint in the high bits of a slot word, never 0 (0 = empty)
 __device__ __forceinline__ unsigned long long fingerprint(const Key& k) {
     uint64_t x = ((uint64_t)(uint32_t)k.a << 32) | (uint32_t)k.b;
-    uint64_t f = mix64(x ^ mix64((uint64_t)(uint32_t)k.c + 0x9e3779b97f4a7c15ull));
-    return f ? f : 1ull;  // 0 marks an empty slot
+    uint64_t f = mix64(x ^ mix64((uint64_t)(uint32_t)k.c + 0x9e3779b97f4a7c15ull)) & ~kRepMask;
+    return f ? f : (1ull << kRepBits);
 }
 
-struct Slot {
-    unsigned long long key;  // fingerprint, 0 = empty
-    int32_t rep;             // smallest staged index with this fingerprint
-    int32_t pad;
-};
-
 __device__ __forceinline__ uint64_t home(const Key& k, unsigned long long f, double scale, uint64_t mask) {
-    return ((uint64_t)((double)(uint32_t)k.a * scale) + (f & 15ull)) & mask;
+    return ((uint64_t)((double)(uint32_t)k.a * scale) + ((f >> kRepBits) & 15ull)) & mask;
 }
 
 // Probes stop after kMaxProbe slots: a pair whose key finds neither its
@@ -63,17 +65,19 @@ constexpr int kMaxProbe = 4096;
 
 // pairs [k0, k1) are PE then PP from pp0 on
 __global__ void __launch_bounds__(kBlock) k_merge_insert(const int4* __restrict__ st_vid, int64_t k0, int64_t k1,
-                                                         int64_t pp0, Slot* __restrict__ table, double scale,
-                                                         uint64_t mask) {
+                                                         int64_t pp0, unsigned long long* __restrict__ table,
+                                                         double scale, uint64_t mask) {
     const int64_t k = k0 + (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= k1) return;
     const Key key = canon(k >= pp0, st_vid[k]);
     const unsigned long long f = fingerprint(key);
+    const unsigned long long word = f | (unsigned long long)k;
     uint64_t h = home(key, f, scale, mask);
     for (int t = 0; t < kMaxProbe; ++t) {
-        const unsigned long long prev = atomicCAS(&table[h].key, 0ull, f);
-        if (prev == 0ull || prev == f) {
-            atomicMin(&table[h].rep, (int32_t)k);
+        const unsigned long long prev = atomicCAS(&table[h], 0ull, word);
+        if (prev == 0ull) return;
+        if ((prev & ~kRepMask) == f) {
+            if (word < prev) atomicMin(&table[h], word);
             return;
         }
         h = (h + 1) & mask;
@@ -81,8 +85,8 @@ __global__ void __launch_bounds__(kBlock) k_merge_insert(const int4* __restrict_
 }
 
 __global__ void __launch_bounds__(kBlock) k_merge_resolve(const int4* __restrict__ st_vid, int64_t k0, int64_t k1,
-                                                          int64_t pp0, const Slot* __restrict__ table, double scale,
-                                                          uint64_t mask, int32_t* __restrict__ rep_of,
+                                                          int64_t pp0, const unsigned long long* __restrict__ table,
+                                                          double scale, uint64_t mask, int32_t* __restrict__ rep_of,
                                                           int32_t* __restrict__ mult) {
     const int64_t k = k0 + (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= k1) return;
@@ -92,15 +96,15 @@ __global__ void __launch_bounds__(kBlock) k_merge_resolve(const int4* __restrict
     uint64_t h = home(me, f, scale, mask);
     int32_t my = (int32_t)k;
     for (int t = 0; t < kMaxProbe; ++t) {
-        const unsigned long long kh = table[h].key;
-        if (kh == f) {
-            const int32_t r = table[h].rep;
+        const unsigned long long w = table[h];
+        if ((w & ~kRepMask) == f) {
+            const int32_t r = (int32_t)(w & kRepMask);
             const bool rpp = r >= pp0;
             const Key o = canon(rpp, st_vid[r]);
             if (rpp == pp && o.a == me.a && o.b == me.b && o.c == me.c) my = r;
             break;
         }
-        if (kh == 0ull) break;  // not inserted (probe bound reached on insert)
+        if (w == 0ull) break;  // not inserted (probe bound reached on insert)
         h = (h + 1) & mask;
     }
     rep_of[k - k0] = my;
@@ -137,12 +141,6 @@ __global__ void k_merge_offsets(const int64_t* __restrict__ pos, TypeRanges tr, 
     if (t < 9) out[t] = pos[tr.off[t]];
 }
 
-// empty slots: key 0, representative above any staged index
-__global__ void __launch_bounds__(kBlock) k_merge_clear(Slot* __restrict__ table, int64_t H) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < H) table[i] = Slot{0ull, INT32_MAX, 0};
-}
-
 unsigned grid(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -160,8 +158,7 @@ hipError_t merge_duplicates(gipc_ctx* ctx, int32_t V, hipStream_t s, int64_t* ne
     do {                                \
         if ((e = (x)) != hipSuccess) return e; \
     } while (0)
-    static_assert(sizeof(Slot) == 16, "slot layout");
-    TRY(ensure(ctx->mkeys, sizeof(Slot) * H));
+    TRY(ensure(ctx->mkeys, sizeof(unsigned long long) * H));
     TRY(ensure(ctx->mrep_of, sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
     TRY(ensure(ctx->mcount, sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
     TRY(ensure(ctx->mflag, sizeof(int32_t) * (size_t)(Ps > 0 ? Ps : 1)));
@@ -170,14 +167,14 @@ hipError_t merge_duplicates(gipc_ctx* ctx, int32_t V, hipStream_t s, int64_t* ne
     TRY(ensure(ctx->st_src2, sizeof(int32_t) * (size_t)(Ps > 0 ? Ps : 1)));
     TRY(ensure(ctx->mult, sizeof(int32_t) * (size_t)(Ps > 0 ? Ps : 1)));
     if (n > 0) {
-        k_merge_clear<<<grid((int64_t)H), kBlock, 0, s>>>(as<Slot>(ctx->mkeys), (int64_t)H);
-        TRY(hipGetLastError());
+        TRY(hipMemsetAsync(ctx->mkeys.p, 0, sizeof(unsigned long long) * H, s));
         TRY(hipMemsetAsync(ctx->mcount.p, 0, sizeof(int32_t) * n, s));
-        k_merge_insert<<<grid(n), kBlock, 0, s>>>(as<int4>(ctx->st_vid), k0, k1, pp0, as<Slot>(ctx->mkeys), scale,
-                                                  H - 1);
+        k_merge_insert<<<grid(n), kBlock, 0, s>>>(as<int4>(ctx->st_vid), k0, k1, pp0,
+                                                  as<unsigned long long>(ctx->mkeys), scale, H - 1);
         TRY(hipGetLastError());
-        k_merge_resolve<<<grid(n), kBlock, 0, s>>>(as<int4>(ctx->st_vid), k0, k1, pp0, as<Slot>(ctx->mkeys), scale,
-                                                   H - 1, as<int32_t>(ctx->mrep_of), as<int32_t>(ctx->mcount));
+        k_merge_resolve<<<grid(n), kBlock, 0, s>>>(as<int4>(ctx->st_vid), k0, k1, pp0,
+                                                   as<unsigned long long>(ctx->mkeys), scale, H - 1,
+                                                   as<int32_t>(ctx->mrep_of), as<int32_t>(ctx->mcount));
         TRY(hipGetLastError());
     }
     if (Ps > 0) {

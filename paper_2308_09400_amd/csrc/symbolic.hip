@@ -214,9 +214,10 @@ __global__ void __launch_bounds__(kBlock) k_sym_rowsort_wave(int32_t V, const in
                 for (int q = 0; q < kWaveM; ++q) {
                     const int e = kWaveM * lane + q;
                     const unsigned long long o = shfl_xor64(key[q], j / kWaveM);
-                    const bool up = (e & kk) == 0, lower = (e & j) == 0;
-                    const unsigned long long mn = key[q] < o ? key[q] : o, mx = key[q] < o ? o : key[q];
-                    key[q] = (lower == up) ? mn : mx;
+                    // this element keeps the smaller key iff it is the lower
+                    // one of an ascending pair or the upper one of a descending
+                    const bool take_min = ((e & kk) == 0) == ((e & j) == 0);
+                    if ((o < key[q]) == take_min) key[q] = o;
                 }
             } else {
 #pragma unroll
