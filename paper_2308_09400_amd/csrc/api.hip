@@ -196,7 +196,8 @@ void gipc_ctx_destroy(gipc_ctx* ctx) {
                       &ctx->st_src, &ctx->mult, &ctx->mkeys, &ctx->mrep_of, &ctx->mcount,
                       &ctx->mflag, &ctx->mpos, &ctx->st_vid2, &ctx->st_src2, &ctx->deg, &ctx->kcount, &ctx->fill, &ctx->inc_ptr, &ctx->kptr, &ctx->inc,
                       &ctx->contrib, &ctx->kcol, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
-                      &ctx->slot_row, &ctx->diag_slot, &ctx->maxbuf, &ctx->bigrows, &ctx->tslot, &ctx->incv, &ctx->rec_main, &ctx->rec_extra, &ctx->ev,
+                      &ctx->slot_row, &ctx->diag_slot, &ctx->maxbuf, &ctx->bigrows, &ctx->tslot, &ctx->incv, &ctx->order,
+                      &ctx->obox, &ctx->ocell, &ctx->ohist, &ctx->ooff, &ctx->ofill, &ctx->rec_main, &ctx->rec_extra, &ctx->ev,
                       &ctx->epart, &ctx->vscene, &ctx->pieces, &ctx->poff,
                       &ctx->r, &ctx->z, &ctx->p, &ctx->q, &ctx->p32, &ctx->minv, &ctx->part, &ctx->scal, &ctx->scan_tmp,
                       &ctx->scan_tmp2};
@@ -382,6 +383,7 @@ gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
     CK(launch_sym_transpose(nnzb, as<int32_t>(ctx->slot_row), as<int32_t>(ctx->col_idx), as<int32_t>(ctx->row_ptr),
                             as<int32_t>(ctx->tslot), s),
        "pattern transpose");
+    CK(build_row_order(ctx, mesh->x, V, batch ? batch->vert_off : nullptr, Sc, s), "row order");
 
     ctx->ranges = tr;
     ctx->Ps = Ps;
@@ -467,13 +469,14 @@ hipError_t eval_enqueue(gipc_ctx* ctx, const DevParams& pm, const gipc_mesh* mes
     hipError_t e = launch_eval(as<int4>(ctx->st_vid), mult, tr, mesh->x, xr, pm, as<double>(ctx->rec_main),
                                as<double>(ctx->rec_extra), t.eval_waves, s);
     if (e != hipSuccess) return e;
-    e = launch_rows_diag(assemble ? 3 : 1, ctx->V, as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr),
+    e = launch_rows_diag(assemble ? 3 : 1, ctx->V, as<int32_t>(ctx->order), as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr),
                          as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra), e0, m0,
                          diag, grad, as<double>(ctx->ev), assemble ? A->val : nullptr, assemble ? A->dtype : 0,
                          ctx->nnzb, t.row_lanes, s);
     if (e != hipSuccess) return e;
     if (assemble) {
-        e = launch_offdiag(ctx->nnzb, as<int32_t>(ctx->slot_row), as<int32_t>(ctx->col_idx), as<int32_t>(ctx->tslot), as<int64_t>(ctx->cptr),
+        e = launch_offdiag(ctx->V, as<int32_t>(ctx->order), as<int32_t>(ctx->row_ptr), as<int32_t>(ctx->diag_slot),
+                           ctx->nnzb, as<int32_t>(ctx->col_idx), as<int32_t>(ctx->tslot), as<int64_t>(ctx->cptr),
                            as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra), e0, m0,
                            A->val, A->dtype, t.offdiag_waves, s);
         if (e != hipSuccess) return e;
@@ -524,11 +527,12 @@ gipc_status gipc_assemble_bsr(gipc_ctx* ctx, const double* diag, const gipc_bsr*
     if (!same_pattern(ctx, A)) return fail(ctx, GIPC_ERR_STATE, "A is not the pattern of the last build");
     hipStream_t s = S(stream);
     const int64_t m0 = ctx->ranges.off[FT_EEM], e0 = ctx->ranges.off[FT_EE];
-    CK(launch_rows_diag(2, ctx->V, as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr), as<uint32_t>(ctx->contrib),
+    CK(launch_rows_diag(2, ctx->V, as<int32_t>(ctx->order), as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr), as<uint32_t>(ctx->contrib),
                         as<double>(ctx->rec_main), as<double>(ctx->rec_extra), e0, m0, diag, nullptr, nullptr, A->val,
                         A->dtype, ctx->nnzb, ctx->tune.row_lanes, s),
        "diagonal blocks");
-    CK(launch_offdiag(ctx->nnzb, as<int32_t>(ctx->slot_row), as<int32_t>(ctx->col_idx), as<int32_t>(ctx->tslot), as<int64_t>(ctx->cptr),
+    CK(launch_offdiag(ctx->V, as<int32_t>(ctx->order), as<int32_t>(ctx->row_ptr), as<int32_t>(ctx->diag_slot),
+                           ctx->nnzb, as<int32_t>(ctx->col_idx), as<int32_t>(ctx->tslot), as<int64_t>(ctx->cptr),
                       as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra), e0, m0,
                       A->val, A->dtype, ctx->tune.offdiag_waves, s),
        "off-diagonal blocks");
@@ -663,7 +667,7 @@ gipc_status gipc_autotune(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_param
     bt = INFINITY;
     for (int l : lanes) {
         float ms = time_it([&] {
-            return launch_rows_diag(3, ctx->V, as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr),
+            return launch_rows_diag(3, ctx->V, as<int32_t>(ctx->order), as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr),
                                     as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra),
                                     e0, m0, diag, grad, as<double>(ctx->ev), A->val, A->dtype, ctx->nnzb, l, s);
         });
@@ -672,7 +676,8 @@ gipc_status gipc_autotune(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_param
     bt = INFINITY;
     for (int w : waves) {
         float ms = time_it([&] {
-            return launch_offdiag(ctx->nnzb, as<int32_t>(ctx->slot_row), as<int32_t>(ctx->col_idx), as<int32_t>(ctx->tslot),
+            return launch_offdiag(ctx->V, as<int32_t>(ctx->order), as<int32_t>(ctx->row_ptr), as<int32_t>(ctx->diag_slot),
+                           ctx->nnzb, as<int32_t>(ctx->col_idx), as<int32_t>(ctx->tslot),
                                   as<int64_t>(ctx->cptr), as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main),
                                   as<double>(ctx->rec_extra), e0, m0, A->val, A->dtype, w, s);
         });

@@ -60,16 +60,18 @@ __device__ __forceinline__ void store_block(void* val, int dtype, int64_t nnzb, 
 // the row's diagonal list, then a fixed xor butterfly combines the lanes
 // (same order on every run for a given LANES).
 template <int LANES>
-__global__ void __launch_bounds__(kBlock) k_rows_diag(int mode, int32_t V, const int32_t* __restrict__ diag_slot,
+__global__ void __launch_bounds__(kBlock) k_rows_diag(int mode, int32_t V, const int32_t* __restrict__ order,
+                                                      const int32_t* __restrict__ diag_slot,
                                                       const int64_t* __restrict__ cptr,
                                                       const uint32_t* __restrict__ contrib,
                                                       const double* __restrict__ rec_main,
                                                       const double* __restrict__ rec_extra, int64_t e0, int64_t m0,
                                                       const double* __restrict__ diag, double* __restrict__ grad,
                                                       double* __restrict__ ev, void* val, int dtype, int64_t nnzb) {
-    const int64_t r = (int64_t)blockIdx.x * (kBlock / LANES) + threadIdx.x / LANES;
+    const int64_t gi = (int64_t)blockIdx.x * (kBlock / LANES) + threadIdx.x / LANES;
     const int lg = threadIdx.x % LANES;
-    const bool valid = r < V;
+    const bool valid = gi < V;
+    const int64_t r = valid ? order[gi] : 0;
     double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     d3 g = mk(0, 0, 0);
     double e = 0.0;
@@ -119,31 +121,41 @@ __global__ void __launch_bounds__(kBlock) k_rows_diag(int mode, int32_t V, const
     }
 }
 
-// one lane per block above the diagonal: its contribution list summed in
-// order, stored, and stored transposed in the mirrored slot (the (c, r)
-// list holds the same pairs with i and j swapped, so its sum is the
-// transpose up to rounding; storing the transpose makes A exactly symmetric)
+// kOffLanes lanes per block row, rows visited in the order `order`: lane l
+// takes the row's blocks above the diagonal l, l + kOffLanes, ...; each sums
+// its contribution list in order, is stored, and is stored transposed in
+// the mirrored slot (the (c, r) list holds the same pairs with i and j
+// swapped, so its sum is the transpose up to rounding; storing the
+// transpose makes A exactly symmetric).  Blocks without a mirror (tslot -2)
+// are only stored.
+constexpr int kOffLanes = 16;
+
 template <int BLOCK>
-__global__ void __launch_bounds__(BLOCK) k_offdiag(int64_t nnzb, const int32_t* __restrict__ slot_row,
-                                                    const int32_t* __restrict__ col_idx,
+__global__ void __launch_bounds__(BLOCK) k_offdiag(int32_t V, const int32_t* __restrict__ order,
+                                                    const int32_t* __restrict__ row_ptr,
+                                                    const int32_t* __restrict__ diag_slot,
                                                     const int32_t* __restrict__ tslot,
                                                     const int64_t* __restrict__ cptr,
                                                     const uint32_t* __restrict__ contrib,
                                                     const double* __restrict__ rec_main,
                                                     const double* __restrict__ rec_extra, int64_t e0, int64_t m0,
-                                                    void* val, int dtype) {
-    const int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (s >= nnzb) return;
-    const int32_t t = tslot[s];
-    if (t == -1) return;  // diagonal (k_rows_diag) and lower blocks (written as transposes)
-    double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    const int64_t t0 = cptr[s], t1 = cptr[s + 1];
-    for (int64_t t = t0; t < t1; ++t) {
-        uint32_t code = contrib[t];
-        add_block(B, rec_main, rec_extra, e0, m0, code >> 4, (int)((code >> 2) & 3u), (int)(code & 3u));
+                                                    void* val, int dtype, int64_t nnzb) {
+    const int64_t gi = (int64_t)blockIdx.x * (BLOCK / kOffLanes) + threadIdx.x / kOffLanes;
+    if (gi >= V) return;
+    const int lg = threadIdx.x % kOffLanes;
+    const int32_t r = order[gi];
+    const int32_t end = row_ptr[r + 1];
+    for (int32_t s = diag_slot[r] + 1 + lg; s < end; s += kOffLanes) {
+        const int32_t t = tslot[s];
+        double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        const int64_t t0 = cptr[s], t1 = cptr[s + 1];
+        for (int64_t q = t0; q < t1; ++q) {
+            uint32_t code = contrib[q];
+            add_block(B, rec_main, rec_extra, e0, m0, code >> 4, (int)((code >> 2) & 3u), (int)(code & 3u));
+        }
+        store_block(val, dtype, nnzb, s, B);
+        if (t >= 0) store_block(val, dtype, nnzb, t, B, true);
     }
-    store_block(val, dtype, nnzb, s, B);
-    if (t >= 0) store_block(val, dtype, nnzb, t, B, true);
 }
 
 // Expanded per-pair view of the staged list and the stored factors.
@@ -206,60 +218,59 @@ __global__ void __launch_bounds__(kBlock) k_pair_inspect(const int4* __restrict_
 
 namespace {
 template <int LANES>
-hipError_t rows_launch(int mode, int32_t V, const int32_t* diag_slot, const int64_t* cptr, const uint32_t* contrib,
-                       const double* rec_main, const double* rec_extra, int64_t e0, int64_t m0, const double* diag,
-                       double* grad, double* ev, void* val, int dtype, int64_t nnzb, hipStream_t s) {
+hipError_t rows_launch(int mode, int32_t V, const int32_t* order, const int32_t* diag_slot, const int64_t* cptr,
+                       const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t e0,
+                       int64_t m0, const double* diag, double* grad, double* ev, void* val, int dtype, int64_t nnzb,
+                       hipStream_t s) {
     const int64_t nb = ((int64_t)V * LANES + kBlock - 1) / kBlock;
-    k_rows_diag<LANES><<<(unsigned)nb, kBlock, 0, s>>>(mode, V, diag_slot, cptr, contrib, rec_main, rec_extra, e0, m0,
-                                                       diag, grad, ev, val, dtype, nnzb);
+    k_rows_diag<LANES><<<(unsigned)nb, kBlock, 0, s>>>(mode, V, order, diag_slot, cptr, contrib, rec_main, rec_extra,
+                                                       e0, m0, diag, grad, ev, val, dtype, nnzb);
+    return hipGetLastError();
+}
+
+template <int BLOCK>
+hipError_t offdiag_launch(int32_t V, const int32_t* order, const int32_t* row_ptr, const int32_t* diag_slot,
+                          int64_t nnzb, const int32_t* tslot, const int64_t* cptr, const uint32_t* contrib,
+                          const double* rec_main, const double* rec_extra, int64_t e0, int64_t m0, void* val,
+                          int dtype, hipStream_t s) {
+    const int64_t nb = ((int64_t)V * kOffLanes + BLOCK - 1) / BLOCK;
+    k_offdiag<BLOCK><<<(unsigned)nb, BLOCK, 0, s>>>(V, order, row_ptr, diag_slot, tslot, cptr, contrib, rec_main,
+                                                    rec_extra, e0, m0, val, dtype, nnzb);
     return hipGetLastError();
 }
 }  // namespace
 
-hipError_t launch_rows_diag(int mode, int32_t V, const int32_t* diag_slot, const int64_t* cptr,
+hipError_t launch_rows_diag(int mode, int32_t V, const int32_t* order, const int32_t* diag_slot, const int64_t* cptr,
                             const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t e0,
                             int64_t m0, const double* diag, double* grad, double* ev, void* val, int dtype,
                             int64_t nnzb, int lanes, hipStream_t s) {
     if (V == 0) return hipSuccess;
+#define ROWS(L) rows_launch<L>(mode, V, order, diag_slot, cptr, contrib, rec_main, rec_extra, e0, m0, diag, grad, ev, \
+                               val, dtype, nnzb, s)
     switch (lanes) {
-        case 4: return rows_launch<4>(mode, V, diag_slot, cptr, contrib, rec_main, rec_extra, e0, m0, diag, grad, ev,
-                                      val, dtype, nnzb, s);
-        case 8: return rows_launch<8>(mode, V, diag_slot, cptr, contrib, rec_main, rec_extra, e0, m0, diag, grad, ev,
-                                      val, dtype, nnzb, s);
-        case 32: return rows_launch<32>(mode, V, diag_slot, cptr, contrib, rec_main, rec_extra, e0, m0, diag, grad, ev,
-                                        val, dtype, nnzb, s);
-        default: return rows_launch<16>(mode, V, diag_slot, cptr, contrib, rec_main, rec_extra, e0, m0, diag, grad,
-                                        ev, val, dtype, nnzb, s);
+        case 4: return ROWS(4);
+        case 8: return ROWS(8);
+        case 32: return ROWS(32);
+        default: return ROWS(16);
     }
+#undef ROWS
 }
 
-namespace {
-template <int BLOCK>
-hipError_t offdiag_launch(int64_t nnzb, const int32_t* slot_row, const int32_t* col_idx, const int32_t* tslot,
-                          const int64_t* cptr, const uint32_t* contrib, const double* rec_main,
-                          const double* rec_extra, int64_t e0, int64_t m0, void* val, int dtype, hipStream_t s) {
-    const int64_t nb = (nnzb + BLOCK - 1) / BLOCK;
-    k_offdiag<BLOCK><<<(unsigned)nb, BLOCK, 0, s>>>(nnzb, slot_row, col_idx, tslot, cptr, contrib, rec_main,
-                                                    rec_extra, e0, m0, val, dtype);
-    return hipGetLastError();
-}
-}  // namespace
-
-hipError_t launch_offdiag(int64_t nnzb, const int32_t* slot_row, const int32_t* col_idx, const int32_t* tslot,
-                          const int64_t* cptr, const uint32_t* contrib, const double* rec_main,
-                          const double* rec_extra, int64_t e0, int64_t m0, void* val, int dtype, int waves,
-                          hipStream_t s) {
-    if (nnzb == 0) return hipSuccess;
+hipError_t launch_offdiag(int32_t V, const int32_t* order, const int32_t* row_ptr, const int32_t* diag_slot,
+                          int64_t nnzb, const int32_t* col_idx, const int32_t* tslot, const int64_t* cptr,
+                          const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t e0,
+                          int64_t m0, void* val, int dtype, int waves, hipStream_t s) {
+    (void)col_idx;
+    if (V == 0 || nnzb == 0) return hipSuccess;
+#define OFF(B) offdiag_launch<B>(V, order, row_ptr, diag_slot, nnzb, tslot, cptr, contrib, rec_main, rec_extra, e0, \
+                                 m0, val, dtype, s)
     switch (waves) {
-        case 1: return offdiag_launch<64>(nnzb, slot_row, col_idx, tslot, cptr, contrib, rec_main, rec_extra, e0, m0,
-                                          val, dtype, s);
-        case 2: return offdiag_launch<128>(nnzb, slot_row, col_idx, tslot, cptr, contrib, rec_main, rec_extra, e0,
-                                           m0, val, dtype, s);
-        case 8: return offdiag_launch<512>(nnzb, slot_row, col_idx, tslot, cptr, contrib, rec_main, rec_extra, e0,
-                                           m0, val, dtype, s);
-        default: return offdiag_launch<256>(nnzb, slot_row, col_idx, tslot, cptr, contrib, rec_main, rec_extra, e0,
-                                            m0, val, dtype, s);
+        case 1: return OFF(64);
+        case 2: return OFF(128);
+        case 8: return OFF(512);
+        default: return OFF(256);
     }
+#undef OFF
 }
 
 hipError_t launch_pair_inspect(const int4* st_vid, const int32_t* st_src, const int32_t* smult, TypeRanges tr,

@@ -89,6 +89,8 @@ struct gipc_ctx {
     // symbolic
     gipc::DevBuf deg, kcount, fill, inc_ptr, kptr, inc, contrib, kcol, ncols, row_ptr, col_idx, cptr, slot_row,
         diag_slot, maxbuf, bigrows, tslot, incv;
+    // visiting order of the block rows in the assembly (spatial cells)
+    gipc::DevBuf order, obox, ocell, ohist, ooff, ofill;
     int64_t nnzb = 0, K = 0;
     int32_t max_deg = 0;
     // scenes of the build: scene id per vertex (batches only), energy pieces
@@ -138,6 +140,13 @@ hipError_t launch_stage_offsets(const int64_t* boff, int64_t nb, int64_t* out, h
 // and writes the merged type offsets (9 int64) to new_off_dev
 hipError_t merge_duplicates(gipc_ctx* ctx, int32_t V, hipStream_t s, int64_t* new_off_dev);
 
+// ---- order.hip
+// ctx->order = the vertices sorted into Morton cells of their bounding cube
+// (scene-major with each scene's own cube when S > 1: vert_off device int32
+// [S+1] and ctx->vscene must be set)
+hipError_t build_row_order(gipc_ctx* ctx, const double* x, int32_t V, const int32_t* vert_off, int32_t S,
+                           hipStream_t s);
+
 // ---- symbolic.hip
 hipError_t launch_sym_count(const int4* st_vid, TypeRanges tr, int32_t* deg, int32_t* kcount, hipStream_t s);
 // inc: incidence codes k << 2 | i; incv: the incidence's pair stencil
@@ -167,13 +176,16 @@ hipError_t launch_energy(const double* ev, const int2* pieces, int32_t npieces, 
 // ---- assemble.hip
 // mode bit 1: gradient and per-vertex energy shares, bit 2: diagonal block
 // values; lanes per row: 4, 8, 16 or 32
-hipError_t launch_rows_diag(int mode, int32_t V, const int32_t* diag_slot, const int64_t* cptr,
+// rows are visited in the order `order` (a permutation of 0..V-1)
+hipError_t launch_rows_diag(int mode, int32_t V, const int32_t* order, const int32_t* diag_slot, const int64_t* cptr,
                             const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t e0,
                             int64_t m0, const double* diag, double* grad, double* ev, void* val, int dtype,
                             int64_t nnzb, int lanes, hipStream_t s);
 // blocks above the diagonal are summed once and stored with their
-// transpose at tslot; waves: workgroup size in wavefronts (1, 2, 4 or 8)
-hipError_t launch_offdiag(int64_t nnzb, const int32_t* slot_row, const int32_t* col_idx, const int32_t* tslot,
+// transpose at tslot, row by row in the order `order`; waves: workgroup size
+// in wavefronts (1, 2, 4 or 8)
+hipError_t launch_offdiag(int32_t V, const int32_t* order, const int32_t* row_ptr, const int32_t* diag_slot,
+                          int64_t nnzb, const int32_t* col_idx, const int32_t* tslot,
                           const int64_t* cptr, const uint32_t* contrib, const double* rec_main,
                           const double* rec_extra, int64_t e0, int64_t m0, void* val, int dtype, int waves,
                           hipStream_t s);
