@@ -158,11 +158,107 @@ __device__ __forceinline__ unsigned long long shfl_up64(unsigned long long v, in
     return ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
 }
 
-// one wavefront per row: lane l holds the key slots 8l .. 8l+7 (incidences
-// 2l and 2l+1, four slots each, unused slots ~0); a bitonic network over the
-// first Neff = pow2 >= 4n slots sorts the row, exchanging across lanes with
-// shuffles for distances >= 8 and inside the lane below.  Rows with more
-// incidences are appended to `big` for the workgroup sort.
+// Sort of one row's keys by a wavefront, M keys per lane: element e = M lane
+// + q holds key slot j = e % 4 of incidence t = e / 4 (unused slots ~0), so
+// the row fits when 4 n <= 64 M.  A bitonic network over the first
+// Neff = 64 M elements sorts the row, exchanging across lanes with shuffles
+// for distances >= M and inside the lane below.
+template <int M>
+__device__ __forceinline__ void rowsort_regs(int64_t r, int n, int64_t start, const uint32_t* __restrict__ inc,
+                                             const int4* __restrict__ incv, const TypeRanges& tr,
+                                             const int64_t* __restrict__ kptr, uint32_t* __restrict__ contrib,
+                                             int32_t* __restrict__ kcol, int32_t* __restrict__ ncols) {
+    constexpr int N = 64 * M;
+    const int lane = threadIdx.x & 63;
+    unsigned long long key[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) key[q] = ~0ull;
+    if (M >= 4) {
+#pragma unroll
+        for (int h = 0; h < (M >= 4 ? M / 4 : 1); ++h) {
+            const int t = (M / 4) * lane + h;
+            if (t < n) {
+                const uint32_t code = inc[start + t];
+                const uint32_t k = code >> 2, i = code & 3u;
+                const int nv = ft_nverts(type_of(k, tr));
+                const int4 v = incv[start + t];
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (j < nv)
+                        key[4 * h + j] = ((unsigned long long)(uint32_t)vslot(v, j) << 32) |
+                                         (unsigned long long)((k << 4) | (i << 2) | (uint32_t)j);
+            }
+        }
+    } else {
+        // 4 / M lanes share an incidence; this lane holds its slots j0 .. j0+M-1
+        const int t = lane / (4 / M), j0 = M * (lane % (4 / M));
+        if (t < n) {
+            const uint32_t code = inc[start + t];
+            const uint32_t k = code >> 2, i = code & 3u;
+            const int nv = ft_nverts(type_of(k, tr));
+            const int4 v = incv[start + t];
+#pragma unroll
+            for (int q = 0; q < M; ++q)
+                if (j0 + q < nv)
+                    key[q] = ((unsigned long long)(uint32_t)vslot(v, j0 + q) << 32) |
+                             (unsigned long long)((k << 4) | (i << 2) | (uint32_t)(j0 + q));
+        }
+    }
+#pragma unroll
+    for (int kk = 2; kk <= N; kk <<= 1) {
+#pragma unroll
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            if (j >= M) {
+#pragma unroll
+                for (int q = 0; q < M; ++q) {
+                    const int e = M * lane + q;
+                    const unsigned long long o = shfl_xor64(key[q], j / M);
+                    // this element keeps the smaller key iff it is the lower
+                    // one of an ascending pair or the upper one of a descending
+                    const bool take_min = ((e & kk) == 0) == ((e & j) == 0);
+                    if ((o < key[q]) == take_min) key[q] = o;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < M; ++q) {
+                    if ((q & j) == 0) {
+                        const int l = q | j;
+                        const int e = M * lane + q;
+                        const bool up = (e & kk) == 0;
+                        const unsigned long long a = key[q], b = key[l];
+                        if ((a > b) == up) {
+                            key[q] = b;
+                            key[l] = a;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    const int64_t base = kptr[r];
+    const int K = (int)(kptr[r + 1] - base);
+    const unsigned long long prev_last = shfl_up64(key[M - 1], 1);
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        const int e = M * lane + q;
+        if (e < K) {
+            const int col = (int)(key[q] >> 32);
+            contrib[base + e] = (uint32_t)key[q];
+            kcol[base + e] = col;
+            const unsigned long long pk = q == 0 ? prev_last : key[q > 0 ? q - 1 : 0];
+            if (e == 0 || (int)(pk >> 32) != col) ++c;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if (lane == 0) ncols[r] = c;
+}
+
+// one wavefront per row, keys in registers: the number of keys per lane is
+// the smallest of 1, 2, 4, 8 that holds the row's 4 n key slots; rows with
+// more than kWaveIncidences incidences are appended to `big` for the
+// workgroup sort
 __global__ void __launch_bounds__(kBlock) k_sym_rowsort_wave(int32_t V, const int64_t* __restrict__ inc_ptr,
                                                              const uint32_t* __restrict__ inc,
                                                              const int4* __restrict__ incv, TypeRanges tr,
@@ -184,76 +280,11 @@ __global__ void __launch_bounds__(kBlock) k_sym_rowsort_wave(int32_t V, const in
         if (lane == 0) big[atomicAdd(nbig, 1ull)] = (int32_t)r;
         return;
     }
-    unsigned long long key[kWaveM];
-#pragma unroll
-    for (int q = 0; q < kWaveM; ++q) key[q] = ~0ull;
-#pragma unroll
-    for (int h = 0; h < kWaveM / 4; ++h) {
-        const int t = (kWaveM / 4) * lane + h;
-        if (t < n) {
-            const uint32_t code = inc[start + t];
-            const uint32_t k = code >> 2, i = code & 3u;
-            const int nv = ft_nverts(type_of(k, tr));
-            const int4 v = incv[start + t];
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (j < nv)
-                    key[4 * h + j] = ((unsigned long long)(uint32_t)vslot(v, j) << 32) |
-                                     (unsigned long long)((k << 4) | (i << 2) | (uint32_t)j);
-        }
-    }
-    unsigned Neff = kWaveM;
-    while (Neff < 4u * (unsigned)n) Neff <<= 1;
-#pragma unroll
-    for (int kk = 2; kk <= kWaveN; kk <<= 1) {
-        if ((unsigned)kk > Neff) break;  // uniform in the wavefront
-#pragma unroll
-        for (int j = kk >> 1; j > 0; j >>= 1) {
-            if (j >= kWaveM) {
-#pragma unroll
-                for (int q = 0; q < kWaveM; ++q) {
-                    const int e = kWaveM * lane + q;
-                    const unsigned long long o = shfl_xor64(key[q], j / kWaveM);
-                    // this element keeps the smaller key iff it is the lower
-                    // one of an ascending pair or the upper one of a descending
-                    const bool take_min = ((e & kk) == 0) == ((e & j) == 0);
-                    if ((o < key[q]) == take_min) key[q] = o;
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < kWaveM; ++q) {
-                    if ((q & j) == 0) {
-                        const int l = q | j;
-                        const int e = kWaveM * lane + q;
-                        const bool up = (e & kk) == 0;
-                        const unsigned long long a = key[q], b = key[l];
-                        if ((a > b) == up) {
-                            key[q] = b;
-                            key[l] = a;
-                        }
-                    }
-                }
-            }
-        }
-    }
-    const int64_t base = kptr[r];
-    const int K = (int)(kptr[r + 1] - base);
-    const unsigned long long prev_last = shfl_up64(key[kWaveM - 1], 1);
-    int c = 0;
-#pragma unroll
-    for (int q = 0; q < kWaveM; ++q) {
-        const int e = kWaveM * lane + q;
-        if (e < K) {
-            const int col = (int)(key[q] >> 32);
-            contrib[base + e] = (uint32_t)key[q];
-            kcol[base + e] = col;
-            const unsigned long long pk = q == 0 ? prev_last : key[q > 0 ? q - 1 : 0];
-            if (e == 0 || (int)(pk >> 32) != col) ++c;
-        }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-    if (lane == 0) ncols[r] = c;
+    // the branch is uniform in the wavefront
+    if (n <= 16) rowsort_regs<1>(r, n, start, inc, incv, tr, kptr, contrib, kcol, ncols);
+    else if (n <= 32) rowsort_regs<2>(r, n, start, inc, incv, tr, kptr, contrib, kcol, ncols);
+    else if (n <= 64) rowsort_regs<4>(r, n, start, inc, incv, tr, kptr, contrib, kcol, ncols);
+    else rowsort_regs<8>(r, n, start, inc, incv, tr, kptr, contrib, kcol, ncols);
 }
 
 // one workgroup per listed row (grid-stride over the list of rows the
