@@ -43,6 +43,34 @@ __device__ __forceinline__ void add_block(double* B, const double* __restrict__ 
 }
 
 // store B (tr = false) or its transpose (tr = true) into block slot s
+// the main-record fields a block needs (c1, c2, w~, P22), loaded as three
+// 16-byte words, so several contributions' loads can be in flight at once
+struct MainRec {
+    double2 a, b, c;  // (c1, c2), (w~x, w~y), (w~z, P22)
+};
+
+__device__ __forceinline__ MainRec load_main(const double* __restrict__ rec_main, uint32_t k) {
+    const double2* m = reinterpret_cast<const double2*>(rec_main + 8 * (int64_t)k);
+    return MainRec{m[0], m[1], m[2]};
+}
+
+// add_block with the main record already loaded
+__device__ __forceinline__ void add_block_rec(double* B, const MainRec& mr, const double* __restrict__ rec_extra,
+                                              int64_t e0, int64_t m0, uint32_t k, int i, int j) {
+    const double m[8] = {mr.a.x, mr.a.y, mr.b.x, mr.b.y, mr.c.x, mr.c.y, 0.0, 0.0};
+    const bool ee = (int64_t)k >= e0;
+    d3 wt = mk(m[R_W], m[R_W + 1], m[R_W + 2]);
+    d3 gi = rec_coef(m, i, ee) * wt, gj = rec_coef(m, j, ee) * wt;
+    add_outer(B, m[R_P22], gi, gj);
+    if ((int64_t)k >= m0) {
+        const double* x = rec_extra + 9 * ((int64_t)k - m0);
+        d3 si = sq_slot(x, i), sj = sq_slot(x, j);
+        add_outer(B, x[6], si, sj);
+        add_outer(B, x[7], si, gj);
+        add_outer(B, x[7], gi, sj);
+    }
+}
+
 __device__ __forceinline__ void store_block(void* val, int dtype, int64_t nnzb, int64_t s, const double* B,
                                             bool tr = false) {
     if (dtype == GIPC_F64) {
@@ -79,21 +107,44 @@ __global__ void __launch_bounds__(kBlock) k_rows_diag(int mode, int32_t V, const
     if (valid) {
         s = diag_slot[r];
         const int64_t t0 = cptr[s], t1 = cptr[s + 1];
-        for (int64_t t = t0 + lg; t < t1; t += LANES) {
-            uint32_t code = contrib[t];
-            uint32_t k = code >> 4;
-            int i = (int)((code >> 2) & 3u);
-            if (mode & 1) {
-                const double* m = rec_main + 8 * (int64_t)k;
-                d3 gi = rec_coef(m, i, (int64_t)k >= e0) * mk(m[R_W], m[R_W + 1], m[R_W + 2]);
-                g = g + m[R_A2] * gi;
-                if (i == 0) e += m[R_E];
-                if ((int64_t)k >= m0) {
-                    const double* x = rec_extra + 9 * ((int64_t)k - m0);
-                    g = g + x[8] * sq_slot(x, i);
+        // two of the lane's contributions per step: codes, then the whole
+        // records, then the sums in list order
+        for (int64_t t = t0 + lg; t < t1; t += 2 * LANES) {
+            const bool two = t + LANES < t1;
+            const uint32_t code[2] = {contrib[t], two ? contrib[t + LANES] : 0u};
+            double m[2][8];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (u == 0 || two) {
+                    const double2* p = reinterpret_cast<const double2*>(rec_main + 8 * (int64_t)(code[u] >> 4));
+                    const double2 w0 = p[0], w1 = p[1], w2 = p[2], w3 = p[3];
+                    m[u][0] = w0.x; m[u][1] = w0.y; m[u][2] = w1.x; m[u][3] = w1.y;
+                    m[u][4] = w2.x; m[u][5] = w2.y; m[u][6] = w3.x; m[u][7] = w3.y;
                 }
             }
-            if (mode & 2) add_block(B, rec_main, rec_extra, e0, m0, k, i, i);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (u == 1 && !two) break;
+                const uint32_t k = code[u] >> 4;
+                const int i = (int)((code[u] >> 2) & 3u);
+                const bool ee = (int64_t)k >= e0;
+                const d3 gi = rec_coef(m[u], i, ee) * mk(m[u][R_W], m[u][R_W + 1], m[u][R_W + 2]);
+                const double* x = (int64_t)k >= m0 ? rec_extra + 9 * ((int64_t)k - m0) : nullptr;
+                if (mode & 1) {
+                    g = g + m[u][R_A2] * gi;
+                    if (i == 0) e += m[u][R_E];
+                    if (x) g = g + x[8] * sq_slot(x, i);
+                }
+                if (mode & 2) {
+                    add_outer(B, m[u][R_P22], gi, gi);
+                    if (x) {
+                        const d3 si = sq_slot(x, i);
+                        add_outer(B, x[6], si, si);
+                        add_outer(B, x[7], si, gi);
+                        add_outer(B, x[7], gi, si);
+                    }
+                }
+            }
         }
     }
 #pragma unroll
@@ -149,9 +200,20 @@ __global__ void __launch_bounds__(BLOCK) k_offdiag(int32_t V, const int32_t* __r
         const int32_t t = tslot[s];
         double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         const int64_t t0 = cptr[s], t1 = cptr[s + 1];
-        for (int64_t q = t0; q < t1; ++q) {
-            uint32_t code = contrib[q];
-            add_block(B, rec_main, rec_extra, e0, m0, code >> 4, (int)((code >> 2) & 3u), (int)(code & 3u));
+        // groups of four: codes, then records, then the sums in list order
+        for (int64_t q = t0; q < t1; q += 4) {
+            uint32_t code[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) code[u] = q + u < t1 ? contrib[q + u] : 0u;
+            MainRec mr[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (q + u < t1) mr[u] = load_main(rec_main, code[u] >> 4);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (q + u < t1)
+                    add_block_rec(B, mr[u], rec_extra, e0, m0, code[u] >> 4, (int)((code[u] >> 2) & 3u),
+                                  (int)(code[u] & 3u));
         }
         store_block(val, dtype, nnzb, s, B);
         if (t >= 0) store_block(val, dtype, nnzb, t, B, true);
