@@ -99,9 +99,11 @@ __global__ void __launch_bounds__(kBlock) k_merge_resolve(const int4* __restrict
         const unsigned long long w = table[h];
         if ((w & ~kRepMask) == f) {
             const int32_t r = (int32_t)(w & kRepMask);
-            const bool rpp = r >= pp0;
-            const Key o = canon(rpp, st_vid[r]);
-            if (rpp == pp && o.a == me.a && o.b == me.b && o.c == me.c) my = r;
+            if (r != (int32_t)k) {  // another pair is the representative: compare full keys
+                const bool rpp = r >= pp0;
+                const Key o = canon(rpp, st_vid[r]);
+                if (rpp == pp && o.a == me.a && o.b == me.b && o.c == me.c) my = r;
+            }
             break;
         }
         if (w == 0ull) break;  // not inserted (probe bound reached on insert)

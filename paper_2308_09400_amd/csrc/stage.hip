@@ -81,7 +81,7 @@ __global__ void __launch_bounds__(kBlock) k_stage_classify(const int4* __restric
             }
         }
         ft_out[p] = (uint8_t)ft;
-        vid_out[p] = vo;
+        if (ft != FT_NONE) vid_out[p] = vo;  // read back for active tuples only
     }
 #pragma unroll
     for (int t = 1; t < 8; ++t) {

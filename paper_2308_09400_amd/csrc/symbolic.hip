@@ -304,45 +304,24 @@ __global__ void __launch_bounds__(kBlock) k_sym_rowsort(const int32_t* __restric
     }
 }
 
-__device__ __forceinline__ int block_exscan_i32(int v, int* lds, int& total) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int inc = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int n = __shfl_up(inc, o, 64);
-        if (lane >= o) inc += n;
-    }
-    if (lane == 63) lds[wid] = inc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int s = 0;
-        for (int w = 0; w < kBlock / 64; ++w) {
-            int t = lds[w];
-            lds[w] = s;
-            s += t;
-        }
-        lds[kBlock / 64] = s;
-    }
-    __syncthreads();
-    int ex = lds[wid] + inc - v;
-    total = lds[kBlock / 64];
-    __syncthreads();
-    return ex;
-}
-
+// one wavefront per row: the column boundaries of the row's sorted
+// contribution list (chunks of 64, positions from ballots) give col_idx, the
+// start of each block's list (cptr), the block's row and the diagonal slot
 __global__ void __launch_bounds__(kBlock) k_sym_fill(int32_t V, const int64_t* __restrict__ kptr,
                                                      const int32_t* __restrict__ kcol,
                                                      const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_idx,
                                                      int64_t* __restrict__ cptr, int32_t* __restrict__ slot_row,
                                                      int32_t* __restrict__ diag_slot, int64_t nnzb) {
-    __shared__ int lds[kBlock / 64 + 1];
-    const int r = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t r64 = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (r64 >= V) return;  // the whole wavefront
+    const int r = (int)r64;
     const int64_t base = kptr[r];
     const int K = (int)(kptr[r + 1] - base);
     const int rp = row_ptr[r];
-    if (threadIdx.x == 0 && r == V - 1) cptr[nnzb] = kptr[V];
+    if (lane == 0 && r == V - 1) cptr[nnzb] = kptr[V];
     if (K == 0) {
-        if (threadIdx.x == 0) {
+        if (lane == 0) {
             col_idx[rp] = r;
             cptr[rp] = base;
             slot_row[rp] = r;
@@ -351,23 +330,23 @@ __global__ void __launch_bounds__(kBlock) k_sym_fill(int32_t V, const int64_t* _
         return;
     }
     int carry = 0;
-    for (int c0 = 0; c0 < K; c0 += kBlock) {
-        const int t = c0 + threadIdx.x;
-        int flag = 0, col = -1;
+    for (int c0 = 0; c0 < K; c0 += 64) {
+        const int t = c0 + lane;
+        int col = -1;
+        bool flag = false;
         if (t < K) {
             col = kcol[base + t];
             flag = (t == 0) || (kcol[base + t - 1] != col);
         }
-        int tot;
-        int ex = block_exscan_i32(flag, lds, tot) + carry;
+        const unsigned long long m = __ballot(flag);
         if (flag) {
-            int s = rp + ex;
+            const int s = rp + carry + __popcll(m & __lanemask_lt());
             col_idx[s] = col;
             cptr[s] = base + t;
             slot_row[s] = r;
             if (col == r) diag_slot[r] = s;
         }
-        carry += tot;
+        carry += __popcll(m);
     }
 }
 
@@ -444,7 +423,8 @@ hipError_t launch_sym_fill(int32_t V, const int64_t* kptr, const int32_t* kcol, 
                            int32_t* col_idx, int64_t* cptr, int32_t* slot_row, int32_t* diag_slot, int64_t nnzb,
                            hipStream_t s) {
     if (V == 0) return hipSuccess;
-    k_sym_fill<<<(unsigned)V, kBlock, 0, s>>>(V, kptr, kcol, row_ptr, col_idx, cptr, slot_row, diag_slot, nnzb);
+    const unsigned blocks = (unsigned)(((int64_t)V + kBlock / 64 - 1) / (kBlock / 64));
+    k_sym_fill<<<blocks, kBlock, 0, s>>>(V, kptr, kcol, row_ptr, col_idx, cptr, slot_row, diag_slot, nnzb);
     return hipGetLastError();
 }
 
