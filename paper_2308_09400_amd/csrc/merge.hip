@@ -68,8 +68,15 @@ __global__ void __launch_bounds__(kBlock) k_merge_insert(const int4* __restrict_
                                                          int64_t pp0, unsigned long long* __restrict__ table,
                                                          double scale, uint64_t mask) {
     const int64_t k = k0 + (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= k1) return;
-    const Key key = canon(k >= pp0, st_vid[k]);
+    const bool in = k < k1;
+    const bool pp = k >= pp0;
+    const Key key = in ? canon(pp, st_vid[k]) : Key{-1, -1, -1};
+    // a lane whose left neighbour holds the same key (same kind) leaves the
+    // insert to the head of that run, which has the smaller index
+    const int lane = threadIdx.x & 63;
+    const int pa = __shfl_up(key.a, 1, 64), pb = __shfl_up(key.b, 1, 64), pc = __shfl_up(key.c, 1, 64);
+    const int ppp = __shfl_up((int)pp, 1, 64);
+    if (!in || (lane > 0 && pa == key.a && pb == key.b && pc == key.c && ppp == (int)pp)) return;
     const unsigned long long f = fingerprint(key);
     const unsigned long long word = f | (unsigned long long)k;
     uint64_t h = home(key, f, scale, mask);

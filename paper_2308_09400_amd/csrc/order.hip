@@ -60,14 +60,20 @@ __device__ __forceinline__ uint32_t spread3(uint32_t x) {
     return x;
 }
 
-// the box over all partial boxes: box[0..2] = min, box[3..5] = max
-__global__ void __launch_bounds__(64) k_bbox_final(const double* __restrict__ part, int32_t nparts,
-                                                   double* __restrict__ box) {
-    const int a = threadIdx.x;
-    if (a >= 6) return;
-    double m = part[a];
-    for (int p = 1; p < nparts; ++p) m = a < 3 ? fmin(m, part[6 * p + a]) : fmax(m, part[6 * p + a]);
-    box[a] = m;
+// the box over all partial boxes: box[0..2] = min, box[3..5] = max; one
+// wavefront per coordinate bound
+__global__ void __launch_bounds__(384) k_bbox_final(const double* __restrict__ part, int32_t nparts,
+                                                    double* __restrict__ box) {
+    const int a = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const bool mn = a < 3;
+    double m = mn ? INFINITY : -INFINITY;
+    for (int p = lane; p < nparts; p += 64) m = mn ? fmin(m, part[6 * p + a]) : fmax(m, part[6 * p + a]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double t = __shfl_xor(m, o, 64);
+        m = mn ? fmin(m, t) : fmax(m, t);
+    }
+    if (lane == 0) box[a] = m;
 }
 
 // one workgroup per scene: the box of its vertex range (batches)
@@ -175,7 +181,7 @@ hipError_t build_row_order(gipc_ctx* ctx, const double* x, int32_t V, const int3
         box = as<double>(ctx->obox) + 6 * nparts;
         k_bbox_part<<<nparts, kBlock, 0, s>>>(x, V, as<double>(ctx->obox));
         TRY(hipGetLastError());
-        k_bbox_final<<<1, 64, 0, s>>>(as<double>(ctx->obox), nparts, box);
+        k_bbox_final<<<1, 384, 0, s>>>(as<double>(ctx->obox), nparts, box);
         TRY(hipGetLastError());
     }
     TRY(hipMemsetAsync(ctx->ohist.p, 0, sizeof(int32_t) * (size_t)nbuckets, s));
