@@ -18,7 +18,9 @@ reported alongside.  Prints one JSON line.
 vertices per side with per-scene dhat log-uniform in [1e-4, 1e-2] in one
 batch; a step is the batched stage + build and the eval + assembly replayed
 from a HIP graph (FP32 blocks); the same scenes one context at a time, and
-FP64 blocks without the graph, are timed once afterwards for comparison.
+FP64 blocks without the graph, are timed once afterwards for comparison, and so
+is the plain path: one context per scene, no merging of duplicate
+constraints, evaluation and assembly as separate calls, FP64 blocks.
 
 --workload sheets40 is the precision mode at four times the size: 40 sheets
 (seed 5), FP32 Hessian blocks and FP32 SpMV, PCG to ||r|| / ||b|| <= 1e-6
@@ -217,9 +219,27 @@ def bench_batch(args):
         e1.record(stream)
         torch.cuda.synchronize()
         per_ms.append(e0.elapsed_time(e1))
+    # the plain path: one context per scene, every tuple its own staged pair
+    # (no merging of duplicate constraints), evaluation and assembly as two
+    # calls, FP64 blocks
+    plain_ms = []
+    flags_plain = gp.FLAGS_DEFAULT | gp.FLAG_NO_MERGE
+    for rep in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for (c, ps, xs, xrs, ts, ds), sc in zip(ctxs, b.scenes):
+            pp = gp.params(dhat=sc.dhat, kappa=sc.kappa, flags=flags_plain)
+            gp.pairs_build(c, xs, ts, pp, x_rest=xrs)
+            As = gp.BsrMatrix(c)
+            gp.barrier_eval(c, xs, pp, x_rest=xrs)
+            gp.assemble_bsr(c, As, diag=ds)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        plain_ms.append(e0.elapsed_time(e1))
     for c, *_ in ctxs:
         c.close()
     per_scene = float(np.median(per_ms))
+    plain = float(np.median(plain_ms))
 
     out = {
         "metric": "contact pairs/s (energy+grad+proxy Hessian+BSR assembly), batched scenes",
@@ -243,8 +263,10 @@ def bench_batch(args):
         },
         "breakdown_ms": {"stage_build": build, "eval_assemble_graph_f32": replay,
                          "eval_assemble_eager_f64": fused64, "eval_then_assemble_f64": unfused64,
-                         "per_scene_contexts_build_eval_assemble_f64": per_scene},
+                         "per_scene_contexts_build_eval_assemble_f64": per_scene,
+                         "plain_per_scene_unmerged_unfused_f64": plain},
         "speedup_vs_per_scene_contexts": per_scene / path_ms,
+        "speedup_vs_plain": plain / path_ms,
         "roofline": {"kernel": "eval + assembly graph (numeric, cached pattern)", "bound": "hbm",
                      "achieved": float(num_gbs), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": float(num_gbs / HBM_PEAK_GBS), "traffic": None},

@@ -161,10 +161,10 @@ hipError_t build_row_order(gipc_ctx* ctx, const double* x, int32_t V, const int3
     TRY(ensure(ctx->order, sizeof(int32_t) * (size_t)(V > 0 ? V : 1)));
     if (V == 0) return hipSuccess;
     const int32_t nparts = 512;
-    // bits per axis: 7 for one scene; for S scenes, what 21 bits leave
-    int sbits = 0;
-    while (sbits < 31 && (int64_t(1) << sbits) < (int64_t)S) ++sbits;
-    const int bits = S > 1 ? (sbits >= 21 ? 0 : (21 - sbits) / 3) : kCellBits;
+    // bits per axis: at most 7, and at most about 4 V buckets in all (S
+    // scenes share them), so small builds do not pay for a large histogram
+    int bits = kCellBits;
+    while (bits > 0 && ((int64_t)S << (3 * bits)) > 4 * (int64_t)V) --bits;
     const int64_t nbuckets = (int64_t)S << (3 * bits);
     if (nbuckets > ((int64_t)1 << 31) - 2) return hipErrorInvalidValue;
     TRY(ensure(ctx->obox, sizeof(double) * 6 * (size_t)(S > 1 ? S : nparts + 1)));
