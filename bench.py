@@ -27,6 +27,11 @@ constraints, evaluation and assembly as separate calls, FP64 blocks.
 inside the step; after the timed steps the FP64 path runs once on the same
 pattern for the comparison (block error, iterations, PCG time, solution
 difference).
+
+After the timed steps, every single-scene workload also runs the
+matrix-free operator once against the FP64 BSR matrix of the same eval (one
+product each; the PCG of the step both ways), reported under
+`matrix_free`.
 """
 from __future__ import annotations
 
@@ -121,6 +126,68 @@ def precision_compare(gp, ctx, x, xr, prm, diag, last, stream):
     out["fp32_true_relres"] = float(torch.linalg.norm(b - gp.bsr_spmv(A64, x32)) / torch.linalg.norm(b))
     del A64
     return out
+
+
+INC_PER_TYPE = {"PT": 4, "PE": 3, "PP": 2, "EE": 4, "EE_moll": 4, "PE_moll": 4, "PP_moll": 4}
+
+
+def matrix_free_compare(gp, ctx, x, xr, prm, diag, info, rtol, maxit, stream):
+    """The matrix-free operator against the FP64 BSR matrix of the same eval:
+    one product each, and the linear solve of a Newton step both ways
+    (eval + assembly + PCG against eval + matrix-free PCG)."""
+    import torch
+    A = gp.BsrMatrix(ctx, dtype=gp.F64)
+    gp.eval_assemble(ctx, x, prm, A, diag=diag, x_rest=xr)
+    V = x.shape[0]
+    v = torch.tensor(np.random.default_rng(0).normal(size=(V, 3)), device=x.device)
+    yb, ym = torch.empty_like(v), torch.empty_like(v)
+    t_spmv = _median_ms(lambda: gp.bsr_spmv(A, v, yb), 20, stream)
+    t_mf = _median_ms(lambda: gp.mf_apply(ctx, v, ym, diag=diag), 20, stream)
+    gap = float((ym - yb).abs().max() / yb.abs().max())
+    st = info["n_staged_by_type"]
+    Ps = sum(st.values())
+    Pm = st["EE_moll"] + st["PE_moll"] + st["PP_moll"]
+    inc = sum(INC_PER_TYPE[k] * n for k, n in st.items())
+    # algorithmic bytes of one matrix-free product: stencils 16 B and the
+    # operator fields of the records (c1 c2 w~ P22: 48 B; u v P11 P12:
+    # 64 B) read once, (alpha, beta) 16 B written and read back, 4 B per
+    # incidence, x / diag read and y written once, 16 B of row metadata
+    mf_bytes = Ps * (16 + 48 + 32) + Pm * 64 + 4 * inc + V * (24 + 8 + 24 + 16)
+    nnzb = A.nnzb
+    spmv_bytes = nnzb * (9 * 8 + 4) + 4 * (V + 1) + 48 * V
+    t_eval = _median_ms(lambda: gp.barrier_eval(ctx, x, prm, x_rest=xr), 5, stream)
+    E, g = gp.eval_assemble(ctx, x, prm, A, diag=diag, x_rest=xr)
+    t_evas = _median_ms(lambda: gp.eval_assemble(ctx, x, prm, A, diag=diag, x_rest=xr), 5, stream)
+    b = -g
+    res = {}
+    for name, fn in (("bsr", lambda: gp.pcg(ctx, A, b, rtol=rtol, maxit=maxit)),
+                     ("mf", lambda: gp.pcg_mf(ctx, b, diag=diag, rtol=rtol, maxit=maxit))):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        d, it, rr, stt = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[name] = {"iters": it, "relres": rr, "ms": e0.elapsed_time(e1), "d": d}
+    dgap = float(torch.linalg.norm(res["mf"]["d"] - res["bsr"]["d"]) / torch.linalg.norm(res["bsr"]["d"]))
+    for r in res.values():
+        r.pop("d")
+        r["ms_per_iter"] = r["ms"] / max(r["iters"], 1)
+    del A
+    return {
+        "apply_ms": t_mf,
+        "apply_gbs": mf_bytes / (t_mf * 1e-3) / 1e9,
+        "apply_bytes": int(mf_bytes),
+        "bsr_spmv_f64_ms": t_spmv,
+        "bsr_spmv_f64_gbs": spmv_bytes / (t_spmv * 1e-3) / 1e9,
+        "bsr_spmv_f64_bytes": int(spmv_bytes),
+        "apply_vs_spmv_max_rel_gap": gap,
+        "eval_only_ms": t_eval,
+        "eval_assemble_f64_ms": t_evas,
+        "pcg_bsr_f64": res["bsr"],
+        "pcg_mf": res["mf"],
+        "solution_rel_gap": dgap,
+        "newton_solve_ms": {"bsr": t_evas + res["bsr"]["ms"], "mf": t_eval + res["mf"]["ms"]},
+    }
 
 
 def _median_ms(fn, reps, stream):
@@ -413,6 +480,7 @@ def main():
     del src, dst
     if mixed:
         out["precision"] = precision_compare(gp, ctx, x, xr, prm, diag, last, stream)
+    out["matrix_free"] = matrix_free_compare(gp, ctx, x, xr, prm, diag, info, rtol, maxit, stream)
     ctx.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_sample)

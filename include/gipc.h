@@ -227,6 +227,29 @@ gipc_status gipc_pcg(gipc_ctx* ctx, const gipc_bsr* A, const double* b, double* 
                      int32_t* iters, double* relres, void* stream);
 
 /*
+ * Matrix-free operator: y = (diag (x) I3 + sum_k S_k^T H_k S_k) x with the
+ * proxy Hessians H_k of the last eval (Sec. 5, Eq. 28 and the factor form of
+ * Sec. 4), applied pair by pair from their compact factors without forming a
+ * matrix; this is the operator of the paper's matrix-free PCG (supplement,
+ * Sec. 6).  It equals gipc_bsr_spmv with the matrix gipc_assemble_bsr would
+ * produce in FP64 (same products, summed in another order).  x, y: device
+ * double [V][3], must not alias; diag: device double [V], nullable = 0.  The
+ * context's pattern, records and a scratch of 16 bytes per staged pair are
+ * read and written, so calls on one context must not overlap.
+ * Deterministic.  Errors: INVALID_ARG, STATE (no build + eval), HIP.
+ */
+gipc_status gipc_mf_apply(gipc_ctx* ctx, const double* diag, const double* x, double* y, void* stream);
+
+/*
+ * gipc_pcg on the matrix-free operator above (FP64 throughout): the
+ * preconditioner inverts the 3x3 diagonal blocks summed from the same
+ * factors.  Same arguments, stopping rule, synchronisation and returns as
+ * gipc_pcg, with the matrix replaced by the last eval and diag.
+ */
+gipc_status gipc_pcg_mf(gipc_ctx* ctx, const double* diag, const double* b, double* x, double rtol, int32_t maxit,
+                        int32_t* iters, double* relres, void* stream);
+
+/*
  * Inspection of the staged pairs of the last build and the factors of the
  * last eval, expanded per pair (for tests and tooling).  Device buffers sized
  * for info.n_staged pairs, each nullable:

@@ -77,6 +77,8 @@ def lib():
         L.orc_assemble.restype = i64
         L.orc_spmv.argtypes = [i32, i64, vp, vp, vp, vp, vp]
         L.orc_spmv.restype = None
+        L.orc_matfree.argtypes = [i32, i64, vp, vp, vp, vp, vp]
+        L.orc_matfree.restype = ctypes.c_int
         L.orc_pcg.argtypes = [i32, i64, vp, vp, vp, vp, vp, d, ctypes.c_int, dp]
         L.orc_pcg.restype = ctypes.c_int
         _lib = L
@@ -202,6 +204,18 @@ def spmv(V, rows, cols, vals, x):
     rows = np.ascontiguousarray(rows, dtype=np.int32)
     cols = np.ascontiguousarray(cols, dtype=np.int32)
     lib().orc_spmv(V, rows.shape[0], rows.ctypes.data, cols.ctypes.data, vals.ctypes.data, x.ctypes.data, y.ctypes.data)
+    return y
+
+
+def matfree(V, tuples, pairH, x, diag=None):
+    """y = (diag (x) I3 + sum_k S_k^T H_k S_k) x by local mat-vecs, no global matrix."""
+    t = np.ascontiguousarray(tuples, dtype=np.int32).reshape(-1, 4)
+    H = np.ascontiguousarray(pairH, dtype=np.float64).reshape(-1, 144)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+    dg = None if diag is None else np.ascontiguousarray(diag, dtype=np.float64)
+    y = np.zeros(3 * V)
+    if lib().orc_matfree(V, t.shape[0], t.ctypes.data, H.ctypes.data, _ptr(dg), x.ctypes.data, y.ctypes.data) < 0:
+        raise ValueError("malformed tuple")
     return y
 
 

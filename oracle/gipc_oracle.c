@@ -605,6 +605,38 @@ void orc_spmv(int32_t V, int64_t nb, const int32_t* rows, const int32_t* cols, c
     }
 }
 
+/* y = (diag (x) I3 + sum_k S_k^T H_k S_k) x without forming the global
+ * matrix: each pair gathers its stencil's entries of x, multiplies them by
+ * its dense local Hessian and adds the product back at the same vertices
+ * (supplement Sec. 6, decomposition of the system mat-vec into local
+ * mat-vecs).  Returns -1 on a malformed tuple or a vertex outside [0, V). */
+int orc_matfree(int32_t V, int64_t P, const int32_t* tuples, const double* pairH, const double* diag,
+                const double* x, double* y) {
+    for (int32_t v = 0; v < V; ++v) {
+        double dv = diag ? diag[v] : 0.0;
+        for (int a = 0; a < 3; ++a) y[3 * (int64_t)v + a] = dv * x[3 * (int64_t)v + a];
+    }
+    for (int64_t p = 0; p < P; ++p) {
+        int32_t vid[4];
+        int nv = orc_stencil(tuples + 4 * p, vid);
+        if (nv < 0) return -1;
+        for (int k = 0; k < nv; ++k)
+            if (vid[k] < 0 || vid[k] >= V) return -1;
+        double xl[12], yl[12];
+        for (int k = 0; k < nv; ++k)
+            for (int a = 0; a < 3; ++a) xl[3 * k + a] = x[3 * (int64_t)vid[k] + a];
+        const double* H = pairH + 144 * p;
+        for (int i = 0; i < 3 * nv; ++i) {
+            double acc = 0.0;
+            for (int j = 0; j < 3 * nv; ++j) acc += H[12 * i + j] * xl[j];
+            yl[i] = acc;
+        }
+        for (int k = 0; k < nv; ++k)
+            for (int a = 0; a < 3; ++a) y[3 * (int64_t)vid[k] + a] += yl[3 * k + a];
+    }
+    return 0;
+}
+
 /* inverse of a 3x3 matrix by cofactors; identity if singular */
 static void inv3(const double* A, double* R) {
     double c00 = A[4] * A[8] - A[5] * A[7], c01 = A[5] * A[6] - A[3] * A[8], c02 = A[3] * A[7] - A[4] * A[6];

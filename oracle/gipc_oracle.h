@@ -83,6 +83,13 @@ int64_t orc_eval(int32_t V, const double* x, const double* x_rest, int64_t P, co
 int64_t orc_assemble(int32_t V, int64_t P, const int32_t* tuples, const double* pairH, const double* diag,
                      int32_t* rows, int32_t* cols, double* vals, int64_t cap);
 
+/* y = (diag (x) I3 + sum_k S_k^T H_k S_k) x by local mat-vecs on the dense
+ * 12x12 local Hessians (pairH [P][12][12], the leading 3nv x 3nv used),
+ * without a global matrix.  Returns -1 on a malformed tuple or a vertex
+ * outside [0, V), else 0. */
+int orc_matfree(int32_t V, int64_t P, const int32_t* tuples, const double* pairH, const double* diag,
+                const double* x, double* y);
+
 /* y = A x for a block list produced by orc_assemble. */
 void orc_spmv(int32_t V, int64_t nb, const int32_t* rows, const int32_t* cols, const double* vals,
               const double* x, double* y);

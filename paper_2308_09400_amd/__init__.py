@@ -27,7 +27,8 @@ EXPORTS = [
     "gipc_status_string", "gipc_ctx_create", "gipc_ctx_destroy", "gipc_ctx_last_error", "gipc_pairs_build",
     "gipc_get_info", "gipc_bsr_pattern", "gipc_barrier_eval", "gipc_assemble_bsr", "gipc_eval_assemble",
     "gipc_bsr_spmv", "gipc_pcg", "gipc_pair_inspect", "gipc_copy", "gipc_get_tune", "gipc_set_tune",
-    "gipc_autotune", "gipc_graph_create", "gipc_graph_launch", "gipc_graph_destroy",
+    "gipc_autotune", "gipc_graph_create", "gipc_graph_launch", "gipc_graph_destroy", "gipc_mf_apply",
+    "gipc_pcg_mf",
 ]
 
 
@@ -107,6 +108,8 @@ def lib():
                                         ctypes.POINTER(Bsr), vp]),
             "gipc_bsr_spmv": (st, [ctypes.POINTER(Bsr), vp, vp, vp]),
             "gipc_pcg": (st, [vp, ctypes.POINTER(Bsr), vp, vp, d, i32, ctypes.POINTER(i32), ctypes.POINTER(d), vp]),
+            "gipc_mf_apply": (st, [vp, vp, vp, vp, vp]),
+            "gipc_pcg_mf": (st, [vp, vp, vp, vp, d, i32, ctypes.POINTER(i32), ctypes.POINTER(d), vp]),
             "gipc_pair_inspect": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), vp, vp, vp, vp, vp, vp, vp,
                                        vp]),
             "gipc_copy": (st, [vp, vp, i64, vp]),
@@ -343,6 +346,44 @@ def pcg(ctx: Context, A: BsrMatrix, b, x=None, rtol=1e-6, maxit=1000, stream=Non
     s = lib().gipc_pcg(ctx.h, ctypes.byref(A.desc), _ptr(b), _ptr(x), float(rtol), int(maxit), ctypes.byref(it),
                        ctypes.byref(rr), _stream(stream))
     ctx._check(s, "gipc_pcg")
+    return x, int(it.value), float(rr.value), int(s)
+
+
+def _need_rows(ctx: Context, t, name):
+    if t.shape[0] != ctx.V:
+        raise ValueError(f"{name} must have {ctx.V} rows (the vertex count of the last build)")
+
+
+def mf_apply(ctx: Context, x, y=None, diag=None, stream=None):
+    """Matrix-free y = (diag (x) I3 + H) x over the factors of the last eval."""
+    _need(x, torch.float64, 3, "x")
+    _need_rows(ctx, x, "x")
+    if diag is not None:
+        _need(diag, torch.float64, None, "diag")
+        _need_rows(ctx, diag, "diag")
+    y = torch.empty_like(x) if y is None else y
+    _need(y, torch.float64, 3, "y")
+    _need_rows(ctx, y, "y")
+    ctx._check(lib().gipc_mf_apply(ctx.h, _ptr(diag), _ptr(x), _ptr(y), _stream(stream)), "gipc_mf_apply")
+    return y
+
+
+def pcg_mf(ctx: Context, b, x=None, diag=None, rtol=1e-6, maxit=1000, stream=None):
+    """Block-Jacobi PCG on the matrix-free operator (synchronises).
+    Returns (x, iterations, relres, status)."""
+    _need(b, torch.float64, 3, "b")
+    _need_rows(ctx, b, "b")
+    if diag is not None:
+        _need(diag, torch.float64, None, "diag")
+        _need_rows(ctx, diag, "diag")
+    x = torch.zeros_like(b) if x is None else x
+    _need(x, torch.float64, 3, "x")
+    _need_rows(ctx, x, "x")
+    it = ctypes.c_int32()
+    rr = ctypes.c_double()
+    s = lib().gipc_pcg_mf(ctx.h, _ptr(diag), _ptr(b), _ptr(x), float(rtol), int(maxit), ctypes.byref(it),
+                          ctypes.byref(rr), _stream(stream))
+    ctx._check(s, "gipc_pcg_mf")
     return x, int(it.value), float(rr.value), int(s)
 
 

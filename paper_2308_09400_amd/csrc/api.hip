@@ -198,7 +198,7 @@ void gipc_ctx_destroy(gipc_ctx* ctx) {
                       &ctx->contrib, &ctx->kcol, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
                       &ctx->slot_row, &ctx->diag_slot, &ctx->maxbuf, &ctx->bigrows, &ctx->tslot, &ctx->incv, &ctx->order,
                       &ctx->obox, &ctx->ocell, &ctx->ohist, &ctx->ooff, &ctx->ofill, &ctx->rec_main, &ctx->rec_extra, &ctx->ev,
-                      &ctx->epart, &ctx->vscene, &ctx->pieces, &ctx->poff,
+                      &ctx->epart, &ctx->mfab, &ctx->vscene, &ctx->pieces, &ctx->poff,
                       &ctx->r, &ctx->z, &ctx->p, &ctx->q, &ctx->p32, &ctx->minv, &ctx->part, &ctx->scal, &ctx->scan_tmp,
                       &ctx->scan_tmp2};
     for (DevBuf* b : bufs) release(*b);
@@ -563,6 +563,68 @@ gipc_status gipc_pcg(gipc_ctx* ctx, const gipc_bsr* A, const double* b, double* 
     double rr = 0.0;
     int brk = 0;
     if (A->nbrows > 0) CK(pcg_run(ctx, *A, b, x, rtol, maxit, &it, &rr, &brk, S(stream)), "pcg");
+    if (iters) *iters = it;
+    if (relres) *relres = rr;
+    if (brk) return fail(ctx, GIPC_ERR_BREAKDOWN, "p^T A p <= 0 at iteration %d", it);
+    if (rtol > 0.0 && rr > rtol) return GIPC_WARN_NOT_CONVERGED;
+    return GIPC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// the matrix-free operator over the factors of the last eval
+gipc_status mf_view(gipc_ctx* ctx, const double* diag, MfView& m) {
+    if (!ctx->built || !ctx->evaluated) return fail(ctx, GIPC_ERR_STATE, "build and eval must precede the operator");
+    const int64_t Ps = ctx->ranges.off[8];
+    CK(ensure(ctx->mfab, sizeof(double2) * (size_t)(Ps > 0 ? Ps : 1)), "alloc operator scratch");
+    m.V = ctx->V;
+    m.tr = ctx->ranges;
+    m.st_vid = as<int4>(ctx->st_vid);
+    m.order = as<int32_t>(ctx->order);
+    m.diag_slot = as<int32_t>(ctx->diag_slot);
+    m.cptr = as<int64_t>(ctx->cptr);
+    m.contrib = as<uint32_t>(ctx->contrib);
+    m.rec_main = as<double>(ctx->rec_main);
+    m.rec_extra = as<double>(ctx->rec_extra);
+    m.diag = diag;
+    m.ab = as<double2>(ctx->mfab);
+    return GIPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gipc_status gipc_mf_apply(gipc_ctx* ctx, const double* diag, const double* x, double* y, void* stream) {
+    if (!ctx) return GIPC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    gipc_status st;
+    if ((st = check_device(ctx)) != GIPC_OK) return st;
+    MfView m{};
+    if ((st = mf_view(ctx, diag, m)) != GIPC_OK) return st;
+    if (m.V > 0 && (!x || !y)) return fail(ctx, GIPC_ERR_INVALID_ARG, "x or y is NULL");
+    if (x == y && m.V > 0) return fail(ctx, GIPC_ERR_INVALID_ARG, "x and y must not alias");
+    CK(launch_mf_apply(m, x, y, nullptr, nullptr, S(stream)), "operator");
+    return GIPC_OK;
+}
+
+gipc_status gipc_pcg_mf(gipc_ctx* ctx, const double* diag, const double* b, double* x, double rtol, int32_t maxit,
+                        int32_t* iters, double* relres, void* stream) {
+    if (!ctx) return GIPC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    gipc_status st;
+    if ((st = check_device(ctx)) != GIPC_OK) return st;
+    MfView m{};
+    if ((st = mf_view(ctx, diag, m)) != GIPC_OK) return st;
+    if (m.V > 0 && (!b || !x)) return fail(ctx, GIPC_ERR_INVALID_ARG, "b or x is NULL");
+    if (!(rtol >= 0.0) || maxit < 0) return fail(ctx, GIPC_ERR_INVALID_ARG, "rtol must be >= 0 and maxit >= 0");
+    int32_t it = 0;
+    double rr = 0.0;
+    int brk = 0;
+    gipc_bsr none{};
+    if (m.V > 0) CK(pcg_run(ctx, none, b, x, rtol, maxit, &it, &rr, &brk, S(stream), &m), "pcg");
     if (iters) *iters = it;
     if (relres) *relres = rr;
     if (brk) return fail(ctx, GIPC_ERR_BREAKDOWN, "p^T A p <= 0 at iteration %d", it);

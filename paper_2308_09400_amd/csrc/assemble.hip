@@ -347,3 +347,180 @@ hipError_t launch_pair_inspect(const int4* st_vid, const int32_t* st_src, const 
 }
 
 }  // namespace gipc
+
+// ---------------------------------------------------------------- matrix-free operator
+//
+// y = (diag (x) I3 + sum_k S_k^T H_k S_k) x straight from the compact
+// factors of the last eval, without a BSR matrix (the paper's own PCG
+// operator, supplement Sec. 6, with its local mat-vec written in factor
+// form).  With s_k = grad f . x_k and t_k = grad sqrt(c) . x_k over the
+// pair's stencil, H_k x_k = grad f (P22 s + P12 t) + grad sqrt(c) (P12 s + P11 t).
+// Pass 1 (one lane per staged pair) forms alpha_k = P22 s + P12 t and
+// beta_k = P12 s + P11 t; pass 2 (kMfLanes lanes per row, rows in the
+// spatial order) gathers alpha_k c_i w~ + beta_k gs_i over the row's
+// incidences, in the fixed order of its diagonal contribution list.
+
+namespace gipc {
+namespace {
+
+constexpr int kMfLanes = 16;
+constexpr int kMfBlock = 1024;
+
+__global__ void __launch_bounds__(kBlock) k_mf_pair(const int4* __restrict__ st_vid, TypeRanges tr,
+                                                    const double* __restrict__ rec_main,
+                                                    const double* __restrict__ rec_extra,
+                                                    const double* __restrict__ x, double2* __restrict__ ab,
+                                                    const PcgScalars* __restrict__ sc) {
+    if (sc && sc->done) return;
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= tr.off[8]) return;
+    const int ft = type_of(k, tr);
+    const int nv = ft_nverts(ft);
+    const int4 v4 = st_vid[k];
+    const MainRec mr = load_main(rec_main, (uint32_t)k);
+    const double m[8] = {mr.a.x, mr.a.y, mr.b.x, mr.b.y, mr.c.x, mr.c.y, 0.0, 0.0};
+    const bool ee = k >= tr.off[FT_EE];
+    d3 y = mk(0, 0, 0);
+    d3 xs[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        xs[i] = i < nv ? ld3(x, vslot(v4, i)) : mk(0, 0, 0);
+        if (i < nv) y = y + rec_coef(m, i, ee) * xs[i];
+    }
+    const double s = dot(mk(m[R_W], m[R_W + 1], m[R_W + 2]), y);
+    double a = m[R_P22] * s, b = 0.0;
+    if (k >= tr.off[FT_EEM]) {
+        const double* e = rec_extra + 9 * (k - tr.off[FT_EEM]);
+        const double t = dot(mk(e[0], e[1], e[2]), xs[1] - xs[0]) + dot(mk(e[3], e[4], e[5]), xs[3] - xs[2]);
+        a += e[7] * t;
+        b = e[7] * s + e[6] * t;
+    }
+    ab[k] = make_double2(a, b);
+}
+
+// pass 2; with part, also one partial of x . y per workgroup (the PCG's p.q)
+__global__ void __launch_bounds__(kMfBlock) k_mf_rows(int32_t V, const int32_t* __restrict__ order,
+                                                      const int32_t* __restrict__ diag_slot,
+                                                      const int64_t* __restrict__ cptr,
+                                                      const uint32_t* __restrict__ contrib,
+                                                      const double* __restrict__ rec_main,
+                                                      const double* __restrict__ rec_extra, int64_t e0, int64_t m0,
+                                                      const double2* __restrict__ ab,
+                                                      const double* __restrict__ diag, const double* __restrict__ x,
+                                                      double* __restrict__ y, double* __restrict__ part,
+                                                      const PcgScalars* __restrict__ sc) {
+    if (sc && sc->done) return;
+    __shared__ double lds[kMfBlock / 64];
+    const int64_t gi = (int64_t)blockIdx.x * (kMfBlock / kMfLanes) + threadIdx.x / kMfLanes;
+    const int lg = threadIdx.x % kMfLanes;
+    const bool valid = gi < V;
+    const int64_t r = valid ? order[gi] : 0;
+    d3 acc = mk(0, 0, 0);
+    if (valid) {
+        const int32_t sl = diag_slot[r];
+        const int64_t t0 = cptr[sl], t1 = cptr[sl + 1];
+        for (int64_t t = t0 + lg; t < t1; t += kMfLanes) {
+            const uint32_t code = contrib[t];
+            const uint32_t k = code >> 4;
+            const int i = (int)((code >> 2) & 3u);
+            const MainRec mr = load_main(rec_main, k);
+            const double2 w = ab[k];
+            const double m[8] = {mr.a.x, mr.a.y, mr.b.x, mr.b.y, mr.c.x, mr.c.y, 0.0, 0.0};
+            acc = acc + (w.x * rec_coef(m, i, (int64_t)k >= e0)) * mk(m[R_W], m[R_W + 1], m[R_W + 2]);
+            if ((int64_t)k >= m0) acc = acc + w.y * sq_slot(rec_extra + 9 * ((int64_t)k - m0), i);
+        }
+    }
+#pragma unroll
+    for (int o = kMfLanes / 2; o > 0; o >>= 1) {
+        acc.x += __shfl_xor(acc.x, o, kMfLanes);
+        acc.y += __shfl_xor(acc.y, o, kMfLanes);
+        acc.z += __shfl_xor(acc.z, o, kMfLanes);
+    }
+    double d = 0.0;
+    if (valid && lg == 0) {
+        const d3 xr = ld3(x, (int)r);
+        const double dv = diag ? diag[r] : 0.0;
+        const d3 yr = acc + dv * xr;
+        y[3 * r] = yr.x;
+        y[3 * r + 1] = yr.y;
+        y[3 * r + 2] = yr.z;
+        d = dot(xr, yr);
+    }
+    if (part) {
+        d = block_sum_n<kMfBlock>(d, lds);
+        if (threadIdx.x == 0) part[blockIdx.x] = d;
+    }
+}
+
+// inverse of every diagonal block diag_r I3 + sum_k H_k(i, i), for the
+// block-Jacobi preconditioner of the matrix-free PCG (identity if singular)
+__global__ void __launch_bounds__(kBlock) k_mf_diag_inverse(int32_t V, const int32_t* __restrict__ diag_slot,
+                                                            const int64_t* __restrict__ cptr,
+                                                            const uint32_t* __restrict__ contrib,
+                                                            const double* __restrict__ rec_main,
+                                                            const double* __restrict__ rec_extra, int64_t e0,
+                                                            int64_t m0, const double* __restrict__ diag,
+                                                            double* __restrict__ minv) {
+    const int64_t r = (int64_t)blockIdx.x * (kBlock / kMfLanes) + threadIdx.x / kMfLanes;
+    const int lg = threadIdx.x % kMfLanes;
+    const bool valid = r < V;
+    double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (valid) {
+        const int32_t sl = diag_slot[r];
+        const int64_t t0 = cptr[sl], t1 = cptr[sl + 1];
+        for (int64_t t = t0 + lg; t < t1; t += kMfLanes) {
+            const uint32_t code = contrib[t];
+            add_block(B, rec_main, rec_extra, e0, m0, code >> 4, (int)((code >> 2) & 3u), (int)((code >> 2) & 3u));
+        }
+    }
+#pragma unroll
+    for (int o = kMfLanes / 2; o > 0; o >>= 1)
+#pragma unroll
+        for (int c = 0; c < 9; ++c) B[c] += __shfl_xor(B[c], o, kMfLanes);
+    if (!valid || lg != 0) return;
+    const double dv = diag ? diag[r] : 0.0;
+    B[0] += dv; B[4] += dv; B[8] += dv;
+    B[3] = B[1]; B[6] = B[2]; B[7] = B[5];
+    const double c00 = B[4] * B[8] - B[5] * B[7], c01 = B[5] * B[6] - B[3] * B[8], c02 = B[3] * B[7] - B[4] * B[6];
+    const double det = B[0] * c00 + B[1] * c01 + B[2] * c02;
+    double* M = minv + 9 * r;
+    if (!(fabs(det) > 0.0) || !isfinite(det)) {
+        for (int c = 0; c < 9; ++c) M[c] = (c % 4 == 0) ? 1.0 : 0.0;
+        return;
+    }
+    const double id = 1.0 / det;
+    M[0] = c00 * id; M[1] = (B[2] * B[7] - B[1] * B[8]) * id; M[2] = (B[1] * B[5] - B[2] * B[4]) * id;
+    M[3] = c01 * id; M[4] = (B[0] * B[8] - B[2] * B[6]) * id; M[5] = (B[2] * B[3] - B[0] * B[5]) * id;
+    M[6] = c02 * id; M[7] = (B[1] * B[6] - B[0] * B[7]) * id; M[8] = (B[0] * B[4] - B[1] * B[3]) * id;
+}
+
+}  // namespace
+
+int64_t mf_num_parts(int32_t V) { return ((int64_t)V * kMfLanes + kMfBlock - 1) / kMfBlock; }
+
+hipError_t launch_mf_apply(const MfView& m, const double* x, double* y, double* part, const PcgScalars* sc,
+                           hipStream_t s) {
+    if (m.V == 0) return hipSuccess;
+    if (m.tr.off[8] > 0) {
+        k_mf_pair<<<(unsigned)((m.tr.off[8] + kBlock - 1) / kBlock), kBlock, 0, s>>>(m.st_vid, m.tr, m.rec_main,
+                                                                                     m.rec_extra, x, m.ab, sc);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int64_t e0 = m.tr.off[FT_EE], m0 = m.tr.off[FT_EEM];
+    k_mf_rows<<<(unsigned)mf_num_parts(m.V), kMfBlock, 0, s>>>(m.V, m.order, m.diag_slot, m.cptr, m.contrib,
+                                                               m.rec_main, m.rec_extra, e0, m0, m.ab, m.diag, x, y,
+                                                               part, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_mf_diag_inverse(const MfView& m, double* minv, hipStream_t s) {
+    if (m.V == 0) return hipSuccess;
+    const int64_t e0 = m.tr.off[FT_EE], m0 = m.tr.off[FT_EEM];
+    const int64_t nb = ((int64_t)m.V * kMfLanes + kBlock - 1) / kBlock;
+    k_mf_diag_inverse<<<(unsigned)nb, kBlock, 0, s>>>(m.V, m.diag_slot, m.cptr, m.contrib, m.rec_main, m.rec_extra,
+                                                      e0, m0, m.diag, minv);
+    return hipGetLastError();
+}
+
+}  // namespace gipc

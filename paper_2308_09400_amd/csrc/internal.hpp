@@ -101,6 +101,8 @@ struct gipc_ctx {
     bool batched = false;
     // factors of the last eval; per-vertex energy shares and piece sums
     gipc::DevBuf rec_main, rec_extra, ev, epart;
+    // matrix-free operator scratch: (alpha, beta) per staged pair
+    gipc::DevBuf mfab;
     // launch shapes (gipc_tune)
     gipc_tune tune{4, 16, 4};
     // PCG workspace
@@ -194,10 +196,32 @@ hipError_t launch_pair_inspect(const int4* st_vid, const int32_t* st_src, const 
                                const DevParams& pm, int32_t* src, int32_t* type, int32_t* vid, int32_t* mult,
                                double* energy, double* grad, double* hess, hipStream_t s);
 
+// matrix-free operator (assemble.hip): everything the two passes read
+struct MfView {
+    int32_t V;
+    TypeRanges tr;
+    const int4* st_vid;
+    const int32_t* order;
+    const int32_t* diag_slot;
+    const int64_t* cptr;
+    const uint32_t* contrib;
+    const double* rec_main;
+    const double* rec_extra;
+    const double* diag;  // per-vertex diagonal term, nullable = 0
+    double2* ab;         // per staged pair (alpha, beta) scratch
+};
+// y = (diag (x) I3 + H) x; with part, one partial of x . y per workgroup
+// (mf_num_parts of them); kernels return at once when sc->done (nullable)
+hipError_t launch_mf_apply(const MfView& m, const double* x, double* y, double* part, const PcgScalars* sc,
+                           hipStream_t s);
+hipError_t launch_mf_diag_inverse(const MfView& m, double* minv, hipStream_t s);
+int64_t mf_num_parts(int32_t V);
+
 // ---- solve.hip
 hipError_t launch_spmv(const gipc_bsr& A, const void* x, void* y, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
+// with mf set, the operator is matrix-free (A is not read)
 hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x, double rtol, int32_t maxit,
-                   int32_t* iters, double* relres, int* breakdown, hipStream_t s);
+                   int32_t* iters, double* relres, int* breakdown, hipStream_t s, const MfView* mf = nullptr);
 
 }  // namespace gipc

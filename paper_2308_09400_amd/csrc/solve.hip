@@ -308,11 +308,12 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s)
 }
 
 hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x, double rtol, int32_t maxit,
-                   int32_t* iters, double* relres, int* breakdown, hipStream_t s) {
-    const int32_t V = A.nbrows;
+                   int32_t* iters, double* relres, int* breakdown, hipStream_t s, const MfView* mf) {
+    const int32_t V = mf ? mf->V : A.nbrows;
     const int64_t n3 = 3 * (int64_t)V;
-    const int64_t nbv = (V + kBlock - 1) / kBlock;               // row-parallel kernels
-    const int64_t nbs = ((int64_t)V * kG + kPcgBlock - 1) / kPcgBlock;  // SpMV kernel
+    const int64_t nbv = (V + kBlock - 1) / kBlock;  // row-parallel kernels
+    const int64_t nbs = mf ? mf_num_parts(V)        // operator kernel
+                           : ((int64_t)V * kG + kPcgBlock - 1) / kPcgBlock;
     hipError_t e;
 #define GIPC_TRY(x)                            \
     do {                                       \
@@ -325,7 +326,7 @@ hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x,
     GIPC_TRY(ensure(ctx->minv, sizeof(double) * 9 * (size_t)V));
     GIPC_TRY(ensure(ctx->part, sizeof(double) * 3 * (size_t)(nbv > nbs ? nbv : nbs)));
     GIPC_TRY(ensure(ctx->scal, sizeof(PcgScalars)));
-    const bool f32 = A.dtype == GIPC_F32;
+    const bool f32 = !mf && A.dtype == GIPC_F32;
     if (f32) GIPC_TRY(ensure(ctx->p32, sizeof(float) * n3));
     double *r = as<double>(ctx->r), *z = as<double>(ctx->z), *p = as<double>(ctx->p), *q = as<double>(ctx->q);
     double *minv = as<double>(ctx->minv), *part = as<double>(ctx->part);
@@ -335,7 +336,10 @@ hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x,
 
     GIPC_TRY(hipMemsetAsync(sc, 0, sizeof(PcgScalars), s));
     // r = b - A x0 (for FP32 matrices through an FP32 copy of x0)
-    if (f32) {
+    if (mf) {
+        GIPC_TRY(launch_mf_diag_inverse(*mf, minv, s));
+        GIPC_TRY(launch_mf_apply(*mf, x, q, nullptr, nullptr, s));
+    } else if (f32) {
         k_bj_inverse<float><<<(unsigned)nbv, kBlock, 0, s>>>(V, A.row_ptr, A.col_idx,
                                                              static_cast<const float*>(A.val), A.nnzb, minv);
         k_pupdate<<<nbn, kBlock, 0, s>>>(n3, nullptr, x, p32, sc, 1);  // FP32 copy of x0 in p32
@@ -357,7 +361,9 @@ hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x,
     while (launched < maxit) {
         int32_t m = maxit - launched < chunk ? maxit - launched : chunk;
         for (int32_t it = 0; it < m; ++it) {
-            if (f32)
+            if (mf)
+                GIPC_TRY(launch_mf_apply(*mf, p, q, part, sc, s));
+            else if (f32)
                 k_pcg_spmv<float><<<(unsigned)nbs, kPcgBlock, 0, s>>>(
                     V, A.row_ptr, A.col_idx, static_cast<const float*>(A.val), A.nnzb, p32, p, q, part, sc);
             else

@@ -6,6 +6,8 @@
   with any vector equals the sum of the local products.  Checked against a
   dense numpy build and against scipy.sparse.
 * SpMV against scipy's BSR product.
+* Matrix-free mat-vec (sum of local products, no global matrix) against the
+  hand-built two-spring product and the dense matrix of a small scene.
 * PCG against numpy.linalg.solve.
 * Scene level: energy and gradient of a list equal the sums of the per-pair
   values; a duplicated tuple counts twice (contact multiplicity); the
@@ -46,6 +48,9 @@ def test_two_spring_decomposition():
     local[:6] += A6 @ c[:6]
     local[3:] += B6 @ c[3:]
     assert oracle.spmv(3, rows, cols, vals, c) == pytest.approx(local, rel=1e-13)
+    # the same product without a global matrix, with a diagonal term
+    d = np.array([1.0, 2.0, 3.0])
+    assert oracle.matfree(3, tuples, H, c, d) == pytest.approx(local + np.repeat(d, 3) * c, rel=1e-13)
 
 
 def _tiny_scene():
@@ -79,6 +84,32 @@ def test_assembly_equals_sum_of_local_matrices():
     # the assembled proxy Hessian is symmetric PSD, so with diag > 0 it is SPD
     assert np.abs(G - G.T).max() <= 1e-12 * np.abs(G).max()
     assert np.linalg.eigvalsh(G).min() > 0
+
+
+def test_matfree_equals_dense_product():
+    s, prm = _tiny_scene()
+    out = oracle.eval_scene(s.x, s.tuples, prm, x_rest=s.x_rest, per_pair=True)
+    diag = np.linspace(1.0, 2.0, s.V)
+    ref = np.kron(np.diag(diag), np.eye(3))
+    for t, H in zip(s.tuples, out["pairH"]):
+        nv, vid = oracle.stencil(t)
+        S = np.zeros((3 * nv, 3 * s.V))   # selection matrix of the stencil
+        for k in range(nv):
+            S[3 * k:3 * k + 3, 3 * vid[k]:3 * vid[k] + 3] = np.eye(3)
+        ref += S.T @ H[:3 * nv, :3 * nv] @ S
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        x = rng.normal(size=3 * s.V)
+        y = oracle.matfree(s.V, s.tuples, out["pairH"], x, diag)
+        assert np.abs(y - ref @ x).max() <= 1e-12 * np.abs(ref @ x).max()
+    # no diagonal term: a zero vector maps to zero, and the map is linear
+    x1, x2 = rng.normal(size=(2, 3 * s.V))
+    y12 = oracle.matfree(s.V, s.tuples, out["pairH"], 2.0 * x1 - x2)
+    y1 = oracle.matfree(s.V, s.tuples, out["pairH"], x1)
+    y2 = oracle.matfree(s.V, s.tuples, out["pairH"], x2)
+    assert np.abs(y12 - (2.0 * y1 - y2)).max() <= 1e-12 * np.abs(y12).max()
+    with pytest.raises(ValueError):
+        oracle.matfree(s.V, np.array([[0, 1, 2, 10 ** 6]], np.int32), np.zeros((1, 12, 12)), np.zeros(3 * s.V))
 
 
 def test_pcg_matches_direct_solve():
