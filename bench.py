@@ -148,11 +148,12 @@ def matrix_free_compare(gp, ctx, x, xr, prm, diag, info, rtol, maxit, stream):
     Ps = sum(st.values())
     Pm = st["EE_moll"] + st["PE_moll"] + st["PP_moll"]
     inc = sum(INC_PER_TYPE[k] * n for k, n in st.items())
-    # algorithmic bytes of one matrix-free product: stencils 16 B and the
-    # operator fields of the records (c1 c2 w~ P22: 48 B; u v P11 P12:
-    # 64 B) read once, (alpha, beta) 16 B written and read back, 4 B per
-    # incidence, x / diag read and y written once, 16 B of row metadata
-    mf_bytes = Ps * (16 + 48 + 32) + Pm * 64 + 4 * inc + V * (24 + 8 + 24 + 16)
+    # algorithmic bytes of one matrix-free product (two passes), each datum
+    # counted once: stencils 16 B and the operator fields of the records
+    # (c1 c2 w~ P22: 48 B; u v P11 P12: 64 B); (alpha, beta) 16 B written
+    # and read; per incidence its 24 B vector c_i w~ and 4 B list code; x and
+    # diag read and y written; 16 B of row metadata
+    mf_bytes = Ps * (16 + 48 + 32) + Pm * 64 + inc * (24 + 4) + V * (24 + 8 + 24 + 16)
     nnzb = A.nnzb
     spmv_bytes = nnzb * (9 * 8 + 4) + 4 * (V + 1) + 48 * V
     t_eval = _median_ms(lambda: gp.barrier_eval(ctx, x, prm, x_rest=xr), 5, stream)

@@ -234,8 +234,10 @@ gipc_status gipc_pcg(gipc_ctx* ctx, const gipc_bsr* A, const double* b, double* 
  * Sec. 6).  It equals gipc_bsr_spmv with the matrix gipc_assemble_bsr would
  * produce in FP64 (same products, summed in another order).  x, y: device
  * double [V][3], must not alias; diag: device double [V], nullable = 0.  The
- * context's pattern, records and a scratch of 16 bytes per staged pair are
- * read and written, so calls on one context must not overlap.
+ * context's pattern and records are read; the first call after an eval
+ * also lays out 24 bytes per incidence (pair, vertex) of that eval's
+ * factors, and every call writes 16 bytes of scratch per staged pair, so
+ * calls on one context must not overlap.
  * Deterministic.  Errors: INVALID_ARG, STATE (no build + eval), HIP.
  */
 gipc_status gipc_mf_apply(gipc_ctx* ctx, const double* diag, const double* x, double* y, void* stream);

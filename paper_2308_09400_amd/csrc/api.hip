@@ -198,7 +198,7 @@ void gipc_ctx_destroy(gipc_ctx* ctx) {
                       &ctx->contrib, &ctx->kcol, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
                       &ctx->slot_row, &ctx->diag_slot, &ctx->maxbuf, &ctx->bigrows, &ctx->tslot, &ctx->incv, &ctx->order,
                       &ctx->obox, &ctx->ocell, &ctx->ohist, &ctx->ooff, &ctx->ofill, &ctx->rec_main, &ctx->rec_extra, &ctx->ev,
-                      &ctx->epart, &ctx->mfab, &ctx->vscene, &ctx->pieces, &ctx->poff,
+                      &ctx->epart, &ctx->mfg, &ctx->mfab, &ctx->vscene, &ctx->pieces, &ctx->poff,
                       &ctx->r, &ctx->z, &ctx->p, &ctx->q, &ctx->p32, &ctx->minv, &ctx->part, &ctx->scal, &ctx->scan_tmp,
                       &ctx->scan_tmp2};
     for (DevBuf* b : bufs) release(*b);
@@ -390,6 +390,7 @@ gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
     ctx->V = V;
     ctx->nnzb = nnzb;
     ctx->K = K;
+    ctx->ninc = ninc;
     ctx->max_deg = max_deg;
     gipc_info& in = ctx->info;
     memset(&in, 0, sizeof(in));
@@ -503,6 +504,7 @@ static gipc_status eval_impl(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
     if ((st = eval_prepare(ctx)) != GIPC_OK) return st;
     CK(eval_enqueue(ctx, pm, mesh, energy, grad, diag, A, assemble, ctx->tune, S(stream)), "eval");
     ctx->evaluated = true;
+    ++ctx->eval_gen;
     return GIPC_OK;
 }
 
@@ -575,9 +577,11 @@ gipc_status gipc_pcg(gipc_ctx* ctx, const gipc_bsr* A, const double* b, double* 
 namespace {
 
 // the matrix-free operator over the factors of the last eval
-gipc_status mf_view(gipc_ctx* ctx, const double* diag, MfView& m) {
+gipc_status mf_view(gipc_ctx* ctx, const double* diag, MfView& m, hipStream_t stream) {
     if (!ctx->built || !ctx->evaluated) return fail(ctx, GIPC_ERR_STATE, "build and eval must precede the operator");
     const int64_t Ps = ctx->ranges.off[8];
+    const int64_t ninc = ctx->ninc;
+    CK(ensure(ctx->mfg, sizeof(double) * 3 * (size_t)(ninc > 0 ? ninc : 1)), "alloc operator vectors");
     CK(ensure(ctx->mfab, sizeof(double2) * (size_t)(Ps > 0 ? Ps : 1)), "alloc operator scratch");
     m.V = ctx->V;
     m.tr = ctx->ranges;
@@ -589,7 +593,13 @@ gipc_status mf_view(gipc_ctx* ctx, const double* diag, MfView& m) {
     m.rec_main = as<double>(ctx->rec_main);
     m.rec_extra = as<double>(ctx->rec_extra);
     m.diag = diag;
+    m.inc_ptr = as<int64_t>(ctx->inc_ptr);
+    m.g = as<double>(ctx->mfg);
     m.ab = as<double2>(ctx->mfab);
+    if (ctx->mfg_gen != ctx->eval_gen) {
+        CK(launch_mf_coef(m, as<double>(ctx->mfg), stream), "operator vectors");
+        ctx->mfg_gen = ctx->eval_gen;
+    }
     return GIPC_OK;
 }
 
@@ -603,7 +613,7 @@ gipc_status gipc_mf_apply(gipc_ctx* ctx, const double* diag, const double* x, do
     gipc_status st;
     if ((st = check_device(ctx)) != GIPC_OK) return st;
     MfView m{};
-    if ((st = mf_view(ctx, diag, m)) != GIPC_OK) return st;
+    if ((st = mf_view(ctx, diag, m, S(stream))) != GIPC_OK) return st;
     if (m.V > 0 && (!x || !y)) return fail(ctx, GIPC_ERR_INVALID_ARG, "x or y is NULL");
     if (x == y && m.V > 0) return fail(ctx, GIPC_ERR_INVALID_ARG, "x and y must not alias");
     CK(launch_mf_apply(m, x, y, nullptr, nullptr, S(stream)), "operator");
@@ -617,7 +627,7 @@ gipc_status gipc_pcg_mf(gipc_ctx* ctx, const double* diag, const double* b, doub
     gipc_status st;
     if ((st = check_device(ctx)) != GIPC_OK) return st;
     MfView m{};
-    if ((st = mf_view(ctx, diag, m)) != GIPC_OK) return st;
+    if ((st = mf_view(ctx, diag, m, S(stream))) != GIPC_OK) return st;
     if (m.V > 0 && (!b || !x)) return fail(ctx, GIPC_ERR_INVALID_ARG, "b or x is NULL");
     if (!(rtol >= 0.0) || maxit < 0) return fail(ctx, GIPC_ERR_INVALID_ARG, "rtol must be >= 0 and maxit >= 0");
     int32_t it = 0;
@@ -754,6 +764,7 @@ gipc_status gipc_autotune(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_param
     if (err != hipSuccess) return hip_fail(ctx, err, "autotune");
     ctx->tune = t;
     ctx->evaluated = true;
+    ++ctx->eval_gen;
     if (best) *best = t;
     return GIPC_OK;
 }
@@ -816,6 +827,7 @@ gipc_status gipc_graph_launch(gipc_graph* g, void* stream) {
         return fail(ctx, GIPC_ERR_STATE, "the graph was captured before the last gipc_pairs_build");
     CK(hipGraphLaunch(g->exec, S(stream)), "graph launch");
     ctx->evaluated = true;
+    ++ctx->eval_gen;
     return GIPC_OK;
 }
 

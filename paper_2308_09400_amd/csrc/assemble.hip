@@ -354,17 +354,62 @@ hipError_t launch_pair_inspect(const int4* st_vid, const int32_t* st_src, const 
 // factors of the last eval, without a BSR matrix (the paper's own PCG
 // operator, supplement Sec. 6, with its local mat-vec written in factor
 // form).  With s_k = grad f . x_k and t_k = grad sqrt(c) . x_k over the
-// pair's stencil, H_k x_k = grad f (P22 s + P12 t) + grad sqrt(c) (P12 s + P11 t).
-// Pass 1 (one lane per staged pair) forms alpha_k = P22 s + P12 t and
-// beta_k = P12 s + P11 t; pass 2 (kMfLanes lanes per row, rows in the
-// spatial order) gathers alpha_k c_i w~ + beta_k gs_i over the row's
-// incidences, in the fixed order of its diagonal contribution list.
+// pair's stencil, H_k x_k = grad f (P22 s + P12 t) + grad sqrt(c) (P12 s + P11 t),
+// so incidence (k, i) adds alpha_k c_i w~_k + beta_k gs_i to row v_i, with
+// alpha = P22 s + P12 t, beta = P12 s + P11 t and gs = (-u, u, -v, v).
+//
+// Once per eval the vectors c_i w~_k of all incidences are laid out row by
+// row, in the order of each row's diagonal contribution list (which holds
+// exactly the row's incidences); then every product runs
+//   pass 1 (one lane per staged pair): (alpha_k, beta_k);
+//   pass 2 (kMfLanes lanes per row, rows in the spatial order): the row's
+//     vectors and list codes stream in, alpha (for mollified pairs also
+//     beta and u or v) is gathered per incidence; sums run in list order.
 
 namespace gipc {
 namespace {
 
 constexpr int kMfLanes = 16;
 constexpr int kMfBlock = 1024;
+constexpr int kMfUnroll = 4;
+
+__device__ __forceinline__ d3 ld3_at(const double* __restrict__ p, int64_t i) {
+    return mk(p[3 * i], p[3 * i + 1], p[3 * i + 2]);
+}
+
+// the bounded end of row r's diagonal list: the list holds exactly the
+// row's incidences (stencils have distinct vertices); the bound keeps every
+// access inside the row's run of the incidence array
+__device__ __forceinline__ int64_t diag_end(int64_t t0, const int64_t* cptr, int32_t sl, const int64_t* inc_ptr,
+                                            int64_t r) {
+    return min(cptr[sl + 1], t0 + (inc_ptr[r + 1] - inc_ptr[r]));
+}
+
+// g[inc_ptr[r] + q] = c_i w~_k for the q-th incidence (k, i) of row r
+__global__ void __launch_bounds__(kBlock) k_mf_coef(int32_t V, const int32_t* __restrict__ diag_slot,
+                                                    const int64_t* __restrict__ cptr,
+                                                    const uint32_t* __restrict__ contrib,
+                                                    const int64_t* __restrict__ inc_ptr,
+                                                    const double* __restrict__ rec_main, int64_t e0,
+                                                    double* __restrict__ g) {
+    const int64_t r = (int64_t)blockIdx.x * (kBlock / kMfLanes) + threadIdx.x / kMfLanes;
+    const int lg = threadIdx.x % kMfLanes;
+    if (r >= V) return;
+    const int32_t sl = diag_slot[r];
+    const int64_t t0 = cptr[sl], base = inc_ptr[r];
+    const int64_t t1 = diag_end(t0, cptr, sl, inc_ptr, r);
+    for (int64_t t = t0 + lg; t < t1; t += kMfLanes) {
+        const uint32_t code = contrib[t];
+        const uint32_t k = code >> 4;
+        const MainRec mr = load_main(rec_main, k);
+        const double m[8] = {mr.a.x, mr.a.y, mr.b.x, mr.b.y, mr.c.x, mr.c.y, 0.0, 0.0};
+        const d3 v = rec_coef(m, (int)((code >> 2) & 3u), (int64_t)k >= e0) * mk(m[R_W], m[R_W + 1], m[R_W + 2]);
+        double* o = g + 3 * (base + (t - t0));
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+    }
+}
 
 __global__ void __launch_bounds__(kBlock) k_mf_pair(const int4* __restrict__ st_vid, TypeRanges tr,
                                                     const double* __restrict__ rec_main,
@@ -403,8 +448,9 @@ __global__ void __launch_bounds__(kMfBlock) k_mf_rows(int32_t V, const int32_t* 
                                                       const int32_t* __restrict__ diag_slot,
                                                       const int64_t* __restrict__ cptr,
                                                       const uint32_t* __restrict__ contrib,
-                                                      const double* __restrict__ rec_main,
-                                                      const double* __restrict__ rec_extra, int64_t e0, int64_t m0,
+                                                      const int64_t* __restrict__ inc_ptr,
+                                                      const double* __restrict__ g,
+                                                      const double* __restrict__ rec_extra, int64_t m0,
                                                       const double2* __restrict__ ab,
                                                       const double* __restrict__ diag, const double* __restrict__ x,
                                                       double* __restrict__ y, double* __restrict__ part,
@@ -418,16 +464,32 @@ __global__ void __launch_bounds__(kMfBlock) k_mf_rows(int32_t V, const int32_t* 
     d3 acc = mk(0, 0, 0);
     if (valid) {
         const int32_t sl = diag_slot[r];
-        const int64_t t0 = cptr[sl], t1 = cptr[sl + 1];
-        for (int64_t t = t0 + lg; t < t1; t += kMfLanes) {
-            const uint32_t code = contrib[t];
-            const uint32_t k = code >> 4;
-            const int i = (int)((code >> 2) & 3u);
-            const MainRec mr = load_main(rec_main, k);
-            const double2 w = ab[k];
-            const double m[8] = {mr.a.x, mr.a.y, mr.b.x, mr.b.y, mr.c.x, mr.c.y, 0.0, 0.0};
-            acc = acc + (w.x * rec_coef(m, i, (int64_t)k >= e0)) * mk(m[R_W], m[R_W + 1], m[R_W + 2]);
-            if ((int64_t)k >= m0) acc = acc + w.y * sq_slot(rec_extra + 9 * ((int64_t)k - m0), i);
+        const int64_t t0 = cptr[sl], base = inc_ptr[r];
+        const int64_t t1 = diag_end(t0, cptr, sl, inc_ptr, r);
+        // kMfUnroll incidences' loads in flight per lane, summed in list order
+        for (int64_t t = t0 + lg; t < t1; t += kMfUnroll * kMfLanes) {
+            uint32_t code[kMfUnroll];
+            double2 w[kMfUnroll];
+            d3 gv[kMfUnroll];
+#pragma unroll
+            for (int q = 0; q < kMfUnroll; ++q) code[q] = t + q * kMfLanes < t1 ? contrib[t + q * kMfLanes] : 0u;
+#pragma unroll
+            for (int q = 0; q < kMfUnroll; ++q) {
+                const bool in = t + q * kMfLanes < t1;
+                w[q] = in ? ab[code[q] >> 4] : make_double2(0.0, 0.0);
+                gv[q] = in ? ld3_at(g, base + (t + q * kMfLanes - t0)) : mk(0, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < kMfUnroll; ++q) {
+                acc = acc + w[q].x * gv[q];
+                const int64_t k = code[q] >> 4;
+                if (k >= m0 && t + q * kMfLanes < t1) {
+                    const int i = (int)((code[q] >> 2) & 3u);
+                    const double* e = rec_extra + 9 * (k - m0) + (i < 2 ? 0 : 3);
+                    const double sb = (i & 1) ? w[q].y : -w[q].y;
+                    acc = acc + sb * mk(e[0], e[1], e[2]);
+                }
+            }
         }
     }
 #pragma unroll
@@ -507,10 +569,17 @@ hipError_t launch_mf_apply(const MfView& m, const double* x, double* y, double* 
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    const int64_t e0 = m.tr.off[FT_EE], m0 = m.tr.off[FT_EEM];
     k_mf_rows<<<(unsigned)mf_num_parts(m.V), kMfBlock, 0, s>>>(m.V, m.order, m.diag_slot, m.cptr, m.contrib,
-                                                               m.rec_main, m.rec_extra, e0, m0, m.ab, m.diag, x, y,
-                                                               part, sc);
+                                                               m.inc_ptr, m.g, m.rec_extra, m.tr.off[FT_EEM], m.ab,
+                                                               m.diag, x, y, part, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_mf_coef(const MfView& m, double* g, hipStream_t s) {
+    if (m.V == 0) return hipSuccess;
+    const int64_t nb = ((int64_t)m.V * kMfLanes + kBlock - 1) / kBlock;
+    k_mf_coef<<<(unsigned)nb, kBlock, 0, s>>>(m.V, m.diag_slot, m.cptr, m.contrib, m.inc_ptr, m.rec_main,
+                                              m.tr.off[FT_EE], g);
     return hipGetLastError();
 }
 

@@ -101,8 +101,12 @@ struct gipc_ctx {
     bool batched = false;
     // factors of the last eval; per-vertex energy shares and piece sums
     gipc::DevBuf rec_main, rec_extra, ev, epart;
-    // matrix-free operator scratch: (alpha, beta) per staged pair
-    gipc::DevBuf mfab;
+    // matrix-free operator: the c_i w~_k vectors of every incidence, row by
+    // row (built at the first use after an eval), and (alpha, beta) per pair
+    gipc::DevBuf mfg, mfab;
+    uint64_t eval_gen = 0;   // bumped by every eval
+    uint64_t mfg_gen = 0;    // eval_gen the vectors in mfg belong to
+    int64_t ninc = 0;  // incidences (k, i) of the build: sum of the stencil sizes
     // launch shapes (gipc_tune)
     gipc_tune tune{4, 16, 4};
     // PCG workspace
@@ -207,14 +211,17 @@ struct MfView {
     const uint32_t* contrib;
     const double* rec_main;
     const double* rec_extra;
-    const double* diag;  // per-vertex diagonal term, nullable = 0
-    double2* ab;         // per staged pair (alpha, beta) scratch
+    const int64_t* inc_ptr;  // per-vertex incidence offsets of the build
+    const double* diag;      // per-vertex diagonal term, nullable = 0
+    const double* g;         // [incidences][3] c_i w~_k, row by row (per eval)
+    double2* ab;             // [Ps] (alpha, beta) of the current product (scratch)
 };
 // y = (diag (x) I3 + H) x; with part, one partial of x . y per workgroup
 // (mf_num_parts of them); kernels return at once when sc->done (nullable)
 hipError_t launch_mf_apply(const MfView& m, const double* x, double* y, double* part, const PcgScalars* sc,
                            hipStream_t s);
 hipError_t launch_mf_diag_inverse(const MfView& m, double* minv, hipStream_t s);
+hipError_t launch_mf_coef(const MfView& m, double* g, hipStream_t s);
 int64_t mf_num_parts(int32_t V);
 
 // ---- solve.hip

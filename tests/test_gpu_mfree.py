@@ -186,3 +186,26 @@ def test_pcg_mf_reports_breakdown(gp):
         gp.pcg_mf(r["ctx"], bt, diag=r["D"], rtol=1e-8, maxit=50)
     assert ei.value.status == gp.ERR_BREAKDOWN
     r["ctx"].close()
+
+
+def test_apply_follows_the_last_eval(gp):
+    # the operator's per-eval vectors are rebuilt after every eval: eager,
+    # and replayed from a graph
+    s = scenes.two_sheets(n=16, seed=1)
+    diag = np.full(s.V, 10.0)
+    r = _setup(gp, s, diag)
+    ctx, A, D = r["ctx"], r["A"], r["D"]
+    xt = torch.tensor(np.random.default_rng(4).normal(size=(s.V, 3)), device="cuda")
+    gp.mf_apply(ctx, xt, diag=D)
+    x2 = r["X"] + 0.05 * s.dhat * torch.tensor(np.random.default_rng(6).uniform(-1, 1, size=(s.V, 3)), device="cuda")
+    gp.eval_assemble(ctx, x2, r["pg"], A, diag=D, x_rest=r["XR"])
+    y = gp.mf_apply(ctx, xt, diag=D)
+    yb = gp.bsr_spmv(A, xt)
+    assert float((y - yb).abs().max()) <= 1e-12 * float(yb.abs().max())
+    graph = gp.Graph(ctx, r["X"], r["pg"], A, diag=D, x_rest=r["XR"])
+    graph.launch()
+    y = gp.mf_apply(ctx, xt, diag=D)
+    yb = gp.bsr_spmv(A, xt)
+    assert float((y - yb).abs().max()) <= 1e-12 * float(yb.abs().max())
+    graph.close()
+    ctx.close()
