@@ -251,6 +251,29 @@ gipc_status gipc_mf_apply(gipc_ctx* ctx, const double* diag, const double* x, do
 gipc_status gipc_pcg_mf(gipc_ctx* ctx, const double* diag, const double* b, double* x, double rtol, int32_t maxit,
                         int32_t* iters, double* relres, void* stream);
 
+/* methods of gipc_proxy_dense */
+#define GIPC_PROJ_ANALYTIC 0
+#define GIPC_PROJ_NUMERIC 1
+
+/*
+ * Dense projected proxy Hessian of every staged pair of the last build at
+ * positions mesh->x, for the comparison the paper makes in Table 1 (time
+ * to construct and project a pair's 3n x 3n barrier Hessian).
+ * GIPC_PROJ_ANALYTIC expands the factors of the analytic eigensystems
+ * (Sec. 4.2-4.3, Eq. 18-21; Sec. 5.2, Eq. 32-36); GIPC_PROJ_NUMERIC builds
+ * kappa D^T H D with the unprojected inner Hessian (Eq. 16-17, 31) and
+ * projects it in x-space by cyclic Jacobi rotations (negative eigenvalues
+ * clamped), the traditional route.  Non-mollified pairs give the same
+ * matrix both ways (rank one); mollified pairs differ where the inner 2x2
+ * block is indefinite.  hess: device double [info.n_staged][12][12],
+ * row-major, the leading 3n x 3n block filled (n = stencil vertices in
+ * slot order, as gipc_pair_inspect reports them), the rest zero, times the
+ * pair's multiplicity.  Does not touch the eval state.  Errors:
+ * INVALID_ARG (bad method, NULL), STATE (no build, V differs), HIP.
+ */
+gipc_status gipc_proxy_dense(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params, int32_t method,
+                             double* hess, void* stream);
+
 /*
  * Inspection of the staged pairs of the last build and the factors of the
  * last eval, expanded per pair (for tests and tooling).  Device buffers sized

@@ -73,6 +73,10 @@ def lib():
         L.orc_stencil.restype = ctypes.c_int
         L.orc_eval.argtypes = [i32, vp, vp, i64, vp, ctypes.POINTER(Params), ctypes.c_int, dp, vp, vp, vp, vp, vp, vp]
         L.orc_eval.restype = i64
+        L.orc_pair_xproj.argtypes = [vp, vp, vp, ctypes.POINTER(Params), vp, vp]
+        L.orc_pair_xproj.restype = ctypes.c_int
+        L.orc_eval_xproj.argtypes = [i32, vp, vp, i64, vp, ctypes.POINTER(Params), ctypes.c_int, vp]
+        L.orc_eval_xproj.restype = ctypes.c_int
         L.orc_assemble.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp, i64]
         L.orc_assemble.restype = i64
         L.orc_spmv.argtypes = [i32, i64, vp, vp, vp, vp, vp]
@@ -153,6 +157,40 @@ def pair_local(tuple4, xs, xr=None, prm=None, debug=False):
         M = m.value * m.value
         out.update(m=m.value, innerH=iH[:M * M].reshape(M, M), innerHp=iHp[:M * M].reshape(M, M), dbdJ=bJ[:M])
     return out
+
+
+def pair_xproj(tuple4, xs, xr=None, prm=None):
+    """The unprojected proxy Hessian kappa D^T H D [12][12] of one pair and its
+    projection computed in x-space by Jacobi rotations (the traditional route)."""
+    prm = prm or params()
+    t = np.ascontiguousarray(tuple4, dtype=np.int32)
+    xs = np.ascontiguousarray(np.asarray(xs, np.float64).reshape(-1, 3))
+    if xs.shape[0] < 4:
+        xs = np.vstack([xs, np.zeros((4 - xs.shape[0], 3))])
+    xr_a = None
+    if xr is not None:
+        xr_a = np.ascontiguousarray(np.asarray(xr, np.float64).reshape(-1, 3))
+        if xr_a.shape[0] < 4:
+            xr_a = np.vstack([xr_a, np.zeros((4 - xr_a.shape[0], 3))])
+    K = np.zeros(144)
+    Px = np.zeros(144)
+    if lib().orc_pair_xproj(t.ctypes.data, xs.ctypes.data, _ptr(xr_a), ctypes.byref(prm), K.ctypes.data,
+                            Px.ctypes.data) < 0:
+        raise ValueError("malformed tuple")
+    return K.reshape(12, 12), Px.reshape(12, 12)
+
+
+def eval_xproj(x, tuples, prm=None, x_rest=None, nthreads=0):
+    """pair_xproj's projection for every tuple of a list, [P][12][12]."""
+    prm = prm or params()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    t = np.ascontiguousarray(tuples, dtype=np.int32).reshape(-1, 4)
+    xr = None if x_rest is None else np.ascontiguousarray(x_rest, dtype=np.float64)
+    out = np.zeros((t.shape[0], 144))
+    if lib().orc_eval_xproj(x.shape[0], x.ctypes.data, _ptr(xr), t.shape[0], t.ctypes.data, ctypes.byref(prm),
+                            int(nthreads), out.ctypes.data) < 0:
+        raise ValueError("malformed tuple or vertex index out of range")
+    return out.reshape(-1, 12, 12)
 
 
 def eval_scene(x, tuples, prm=None, x_rest=None, nthreads=0, per_pair=False):

@@ -310,15 +310,22 @@ static void dg_dJ(const double* Jdiag, int m, int nsel, double* out) {
     out[vidx(nsel, nsel, m)] = 2.0 * Jdiag[nsel];
 }
 
-int orc_pair_local(const int32_t tuple[4], const double* xs, const double* xr, const orc_params* prm,
-                   double* E, double* grad12, double* hess144, int* subtype, int* mollified, double* dist2,
-                   double* innerH, double* innerHp, double* dbdJ, int* m_out) {
+/* Kx / Px (nullable, [12][12]): the proxy Hessian before projection,
+ * kappa D^T H D with the unprojected inner Hessian, and its projection onto
+ * the PSD cone computed in x-space by the same Jacobi routine (the
+ * traditional route of projecting the 3n x 3n matrix numerically). */
+static int pair_local_impl(const int32_t tuple[4], const double* xs, const double* xr, const orc_params* prm,
+                           double* E, double* grad12, double* hess144, int* subtype, int* mollified,
+                           double* dist2, double* innerH, double* innerHp, double* dbdJ, int* m_out, double* Kx,
+                           double* Px) {
     int32_t vid[4];
     int kind;
     int nv = decode(tuple, vid, &kind);
     *E = 0.0;
     memset(grad12, 0, sizeof(double) * 12);
     memset(hess144, 0, sizeof(double) * 144);
+    if (Kx) memset(Kx, 0, sizeof(double) * 144);
+    if (Px) memset(Px, 0, sizeof(double) * 144);
     *subtype = ORC_INACTIVE; *mollified = 0; *dist2 = NAN;
     if (m_out) *m_out = 0;
     if (nv < 0) return -1;
@@ -471,7 +478,46 @@ int orc_pair_local(const int32_t tuple[4], const double* xs, const double* xr, c
             }
             hess144[i * 12 + j] = kappa * s;
         }
+
+    /* x-space route: project kappa D^T H D itself */
+    if (Kx || Px) {
+        double K[144], lamx[12], Qx[144];
+        for (int i = 0; i < 12; ++i)
+            for (int j = 0; j < 12; ++j) {
+                double s = 0.0;
+                for (int r = 0; r < M; ++r) {
+                    if (Dm[r][i] == 0.0) continue;
+                    for (int c = 0; c < M; ++c) s += Dm[r][i] * H[r * M + c] * Dm[c][j];
+                }
+                K[i * 12 + j] = kappa * s;
+            }
+        if (Kx) memcpy(Kx, K, sizeof(K));
+        if (Px) {
+            orc_jacobi_eig(12, K, lamx, Qx);
+            for (int i = 0; i < 12; ++i)
+                for (int j = 0; j < 12; ++j) {
+                    double s = 0.0;
+                    for (int k = 0; k < 12; ++k)
+                        if (lamx[k] > 0.0) s += Qx[i * 12 + k] * lamx[k] * Qx[j * 12 + k];
+                    Px[i * 12 + j] = s;
+                }
+        }
+    }
     return 0;
+}
+
+int orc_pair_local(const int32_t tuple[4], const double* xs, const double* xr, const orc_params* prm,
+                   double* E, double* grad12, double* hess144, int* subtype, int* mollified, double* dist2,
+                   double* innerH, double* innerHp, double* dbdJ, int* m_out) {
+    return pair_local_impl(tuple, xs, xr, prm, E, grad12, hess144, subtype, mollified, dist2, innerH, innerHp,
+                           dbdJ, m_out, NULL, NULL);
+}
+
+int orc_pair_xproj(const int32_t tuple[4], const double* xs, const double* xr, const orc_params* prm, double* Kx,
+                   double* Px) {
+    double E, g[12], h[144], d2;
+    int st, mo;
+    return pair_local_impl(tuple, xs, xr, prm, &E, g, h, &st, &mo, &d2, NULL, NULL, NULL, NULL, Kx, Px);
 }
 
 /* ------------------------------------------------------------ whole scene */
@@ -530,6 +576,39 @@ int64_t orc_eval(int32_t V, const double* x, const double* x_rest, int64_t P, co
     if (!pairE) free(lE);
     if (!pairG) free(lG);
     return ndeg;
+}
+
+/* Per pair, the x-space projection of the unprojected proxy Hessian
+ * (orc_pair_xproj) into pairPx [P][12][12].  Returns -1 on a malformed
+ * tuple or a vertex outside [0, V). */
+int orc_eval_xproj(int32_t V, const double* x, const double* x_rest, int64_t P, const int32_t* tuples,
+                   const orc_params* prm, int nthreads, double* pairPx) {
+    for (int64_t p = 0; p < P; ++p) {
+        int32_t vid[4];
+        int nv = orc_stencil(tuples + 4 * p, vid);
+        if (nv < 0) return -1;
+        for (int k = 0; k < nv; ++k)
+            if (vid[k] < 0 || vid[k] >= V) return -1;
+    }
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    #pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < P; ++p) {
+        const int32_t* t = tuples + 4 * p;
+        int32_t vid[4];
+        int nv = orc_stencil(t, vid);
+        double xs[12] = {0}, xr[12] = {0};
+        for (int k = 0; k < nv; ++k)
+            for (int d = 0; d < 3; ++d) {
+                xs[3 * k + d] = x[3 * (int64_t)vid[k] + d];
+                xr[3 * k + d] = (x_rest ? x_rest : x)[3 * (int64_t)vid[k] + d];
+            }
+        orc_pair_xproj(t, xs, xr, prm, NULL, pairPx + 144 * p);
+    }
+    return 0;
 }
 
 /* --------------------------------------------------------------- assembly */

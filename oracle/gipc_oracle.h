@@ -57,6 +57,21 @@ int orc_pair_local(const int32_t tuple[4], const double* xs, const double* xr, c
                    double* E, double* grad12, double* hess144, int* subtype, int* mollified, double* dist2,
                    double* innerH, double* innerHp, double* dbdJ, int* m_out);
 
+/*
+ * The traditional route for the same pair: Kx = kappa D^T H D, the proxy
+ * Hessian with the unprojected inner Hessian, [12][12], and Px, its
+ * projection onto the PSD cone computed in x-space (3n x 3n, padded to 12)
+ * by cyclic Jacobi rotations.  For non-mollified pairs Px equals the proxy
+ * Hessian of orc_pair_local (a rank-one matrix); for mollified pairs it
+ * differs when the inner 2x2 block is indefinite.  Both nullable.
+ */
+int orc_pair_xproj(const int32_t tuple[4], const double* xs, const double* xr, const orc_params* prm, double* Kx,
+                   double* Px);
+
+/* orc_pair_xproj's Px for every tuple of a list, pairPx [P][12][12]. */
+int orc_eval_xproj(int32_t V, const double* x, const double* x_rest, int64_t P, const int32_t* tuples,
+                   const orc_params* prm, int nthreads, double* pairPx);
+
 /* Number of OpenMP threads the scene-level functions use. */
 int orc_num_threads(void);
 

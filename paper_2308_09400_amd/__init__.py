@@ -28,7 +28,7 @@ EXPORTS = [
     "gipc_get_info", "gipc_bsr_pattern", "gipc_barrier_eval", "gipc_assemble_bsr", "gipc_eval_assemble",
     "gipc_bsr_spmv", "gipc_pcg", "gipc_pair_inspect", "gipc_copy", "gipc_get_tune", "gipc_set_tune",
     "gipc_autotune", "gipc_graph_create", "gipc_graph_launch", "gipc_graph_destroy", "gipc_mf_apply",
-    "gipc_pcg_mf",
+    "gipc_pcg_mf", "gipc_proxy_dense",
 ]
 
 
@@ -110,6 +110,7 @@ def lib():
             "gipc_pcg": (st, [vp, ctypes.POINTER(Bsr), vp, vp, d, i32, ctypes.POINTER(i32), ctypes.POINTER(d), vp]),
             "gipc_mf_apply": (st, [vp, vp, vp, vp, vp]),
             "gipc_pcg_mf": (st, [vp, vp, vp, vp, d, i32, ctypes.POINTER(i32), ctypes.POINTER(d), vp]),
+            "gipc_proxy_dense": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), i32, vp, vp]),
             "gipc_pair_inspect": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), vp, vp, vp, vp, vp, vp, vp,
                                        vp]),
             "gipc_copy": (st, [vp, vp, i64, vp]),
@@ -347,6 +348,24 @@ def pcg(ctx: Context, A: BsrMatrix, b, x=None, rtol=1e-6, maxit=1000, stream=Non
                        ctypes.byref(rr), _stream(stream))
     ctx._check(s, "gipc_pcg")
     return x, int(it.value), float(rr.value), int(s)
+
+
+PROJ_ANALYTIC, PROJ_NUMERIC = 0, 1
+
+
+def proxy_dense(ctx: Context, x, prm: Params, method=PROJ_ANALYTIC, x_rest=None, hess=None, stream=None):
+    """Dense projected proxy Hessian [n_staged][12][12] of every staged pair,
+    from the analytic eigensystems or by numeric Jacobi projection in x-space."""
+    mesh = Context._mesh(x, x_rest)
+    n = int(ctx.info["n_staged"]) if ctx.info else 0
+    if hess is None:
+        hess = torch.empty((n, 12, 12), dtype=torch.float64, device=x.device)
+    _need(hess, torch.float64, 12, "hess")
+    if hess.shape[0] < n:
+        raise ValueError(f"hess must hold {n} pairs")
+    ctx._check(lib().gipc_proxy_dense(ctx.h, ctypes.byref(mesh), ctypes.byref(prm), int(method), _ptr(hess),
+                                      _stream(stream)), "gipc_proxy_dense")
+    return hess
 
 
 def _need_rows(ctx: Context, t, name):

@@ -669,6 +669,28 @@ gipc_status gipc_pair_inspect(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_p
     return GIPC_OK;
 }
 
+gipc_status gipc_proxy_dense(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params, int32_t method,
+                             double* hess, void* stream) {
+    if (!ctx) return GIPC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    gipc_status st;
+    if ((st = check_device(ctx)) != GIPC_OK) return st;
+    if (method != GIPC_PROJ_ANALYTIC && method != GIPC_PROJ_NUMERIC)
+        return fail(ctx, GIPC_ERR_INVALID_ARG, "method must be GIPC_PROJ_ANALYTIC or GIPC_PROJ_NUMERIC");
+    if ((st = check_mesh(ctx, mesh)) != GIPC_OK) return st;
+    DevParams pm;
+    if ((st = to_dev_params(ctx, params, pm)) != GIPC_OK) return st;
+    if (!ctx->built) return fail(ctx, GIPC_ERR_STATE, "gipc_pairs_build has not succeeded");
+    if (mesh->V != ctx->V) return fail(ctx, GIPC_ERR_STATE, "V = %d differs from the build (%d)", mesh->V, ctx->V);
+    if ((st = bind_batch(ctx, params, pm)) != GIPC_OK) return st;
+    if (ctx->Ps > 0 && !hess) return fail(ctx, GIPC_ERR_INVALID_ARG, "hess is NULL");
+    const double* xr = mesh->x_rest ? mesh->x_rest : mesh->x;
+    CK(launch_proxy_dense(method, as<int4>(ctx->st_vid), ctx->merged ? as<int32_t>(ctx->mult) : nullptr,
+                          ctx->ranges, mesh->x, xr, pm, hess, S(stream)),
+       "dense proxy Hessians");
+    return GIPC_OK;
+}
+
 gipc_status gipc_copy(const void* src, void* dst, int64_t bytes, void* stream) {
     if (bytes < 0 || (bytes > 0 && (!src || !dst))) return GIPC_ERR_INVALID_ARG;
     if (launch_copy(src, dst, bytes, S(stream)) != hipSuccess) return GIPC_ERR_HIP;

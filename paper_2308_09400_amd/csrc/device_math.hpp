@@ -279,6 +279,10 @@ struct PairFactors {
     int moll;
     d3 u, v;
     double P11, P12, a1;
+    // the same inner coefficients before projection (kappa included):
+    // H22r gf gf^T + H12r (gs gf^T + gf gs^T) + H11r gs gs^T is the proxy
+    // Hessian with the unprojected inner Hessian
+    double H11r, H12r, H22r;
 };
 
 // Stored main record of an evaluated pair, 8 doubles (64 B):
@@ -306,6 +310,7 @@ __device__ inline void eval_typed(int ft, const int* v, const double* __restrict
     o.moll = 0;
     o.u = o.v = mk(0, 0, 0);
     o.P11 = o.P12 = o.a1 = 0.0;
+    o.H11r = o.H12r = o.H22r = 0.0;
     if (ft == FT_NONE) return;
 
     d3 w;
@@ -391,6 +396,7 @@ __device__ inline void eval_typed(int ft, const int* v, const double* __restrict
     double lam1 = 2.0 * dbF + 4.0 * gf * d2bF;   // Eq. 18
     if (!o.moll) {
         o.P22 = kappa * fmax(lam1, 0.0);
+        o.H22r = kappa * lam1;
     } else {
         double lg1 = 2.0 * (de * bF + 2.0 * cpar * d2e * bF);   // lambda_gamma1
         double lq1 = e * lam1;                                  // lambda_g1
@@ -398,6 +404,7 @@ __device__ inline void eval_typed(int ft, const int* v, const double* __restrict
         double P11, P12, P22;
         psd2(lg1, 4.0 * t, lq1, P11, P12, P22);
         o.P11 = kappa * P11; o.P12 = kappa * P12; o.P22 = kappa * P22;
+        o.H11r = kappa * lg1; o.H12r = kappa * 4.0 * t; o.H22r = kappa * lq1;
     }
 }
 

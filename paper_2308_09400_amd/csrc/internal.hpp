@@ -224,6 +224,11 @@ hipError_t launch_mf_diag_inverse(const MfView& m, double* minv, hipStream_t s);
 hipError_t launch_mf_coef(const MfView& m, double* g, hipStream_t s);
 int64_t mf_num_parts(int32_t V);
 
+// dense projected proxy Hessians per staged pair, analytic or numeric
+// (numeric.hip); hess [Ps][12][12]
+hipError_t launch_proxy_dense(int method, const int4* st_vid, const int32_t* mult, const TypeRanges& tr,
+                              const double* x, const double* xr, const DevParams& pm, double* hess, hipStream_t s);
+
 // ---- solve.hip
 hipError_t launch_spmv(const gipc_bsr& A, const void* x, void* y, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);

@@ -1,0 +1,151 @@
+"""Dense projected proxy Hessians (gipc_proxy_dense): the analytic
+eigensystems expanded, and the numeric baseline (x-space Jacobi projection).
+
+* analytic route against the oracle's proxy Hessians (inner-space Jacobi
+  projection, Eq. 16-17 / 31), per staged pair, keyed by vertex id, within
+  1e-9 of the pair's largest entry, multiplicity included;
+* numeric route against the oracle's x-space route (orc_pair_xproj), same
+  bar;
+* the two GPU routes agree on every non-mollified pair (rank one);
+* the analytic route equals the expansion of the eval's stored factors
+  (gipc_pair_inspect) to rounding, on a scene and on a batch;
+* 4000 sampled pairs of the ten-sheet, 256 x 256 scene against the oracle;
+* errors: bad method, no build.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import scenes  # noqa: E402
+
+TOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def gp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2308_09400_amd as gp
+    torch.cuda.set_device(0)
+    return gp
+
+
+def _build(gp, s):
+    dev = torch.device("cuda", 0)
+    pg = gp.params(dhat=s.dhat, kappa=s.kappa)
+    X = torch.tensor(s.x, device=dev)
+    XR = torch.tensor(s.x_rest, device=dev)
+    T = torch.tensor(np.asarray(s.tuples, np.int32).reshape(-1, 4), device=dev)
+    ctx = gp.Context()
+    gp.pairs_build(ctx, X, T, pg, x_rest=XR)
+    return ctx, pg, X, XR
+
+
+def _blocks(H, vid):
+    out = {}
+    for i in range(4):
+        for j in range(4):
+            if vid[i] >= 0 and vid[j] >= 0:
+                out[(int(vid[i]), int(vid[j]))] = H[3 * i:3 * i + 3, 3 * j:3 * j + 3]
+    return out
+
+
+def _compare(dense, pairs, tuples, ref_h, rows=None):
+    """dense[k] (staged slot order) against mult x ref_h[src] (tuple slot order)"""
+    src, vid, mult = pairs["src"], pairs["vid"], pairs["mult"]
+    ks = range(len(src)) if rows is None else rows
+    for k in ks:
+        p = int(src[k])
+        nv, ov = oracle.stencil(tuples[p])
+        ovv = [int(ov[i]) if i < nv else -1 for i in range(4)]
+        o = _blocks(float(mult[k]) * ref_h[p], ovv)
+        g = _blocks(dense[k], vid[k])
+        sc = max(float(mult[k]) * np.abs(ref_h[p]).max(), 1e-300)
+        for key in set(o) | set(g):
+            assert np.abs(g.get(key, 0.0) - o.get(key, 0.0)).max() <= TOL * sc, (k, p, key)
+
+
+@pytest.mark.parametrize("which", ["tiny", "sheets16"])
+def test_routes_against_the_oracle(gp, which):
+    if which == "tiny":
+        s = scenes.two_sheets(n=6, dhat=0.15, kappa=10.0, seed=3, offset=0.5, jitter=0.3)
+    else:
+        s = scenes.two_sheets(n=16, seed=1)
+    ctx, pg, X, XR = _build(gp, s)
+    po = oracle.params(dhat=s.dhat, kappa=s.kappa)
+    Ha = gp.proxy_dense(ctx, X, pg, gp.PROJ_ANALYTIC, x_rest=XR).cpu().numpy()
+    Hn = gp.proxy_dense(ctx, X, pg, gp.PROJ_NUMERIC, x_rest=XR).cpu().numpy()
+    pi = gp.pair_inspect(ctx, want=("src", "type", "vid", "mult"))
+    pairs = {k: v.cpu().numpy() for k, v in pi.items()}
+    ref = oracle.eval_scene(s.x, s.tuples, po, x_rest=s.x_rest, per_pair=True)
+    _compare(Ha, pairs, s.tuples, ref["pairH"])
+    _compare(Hn, pairs, s.tuples, oracle.eval_xproj(s.x, s.tuples, po, x_rest=s.x_rest))
+    nonm = pairs["type"] < 5
+    assert nonm.any()
+    sc = np.abs(Ha[nonm]).max(axis=(1, 2))[:, None, None]
+    assert (np.abs(Ha[nonm] - Hn[nonm]) <= TOL * sc + 1e-300).all()
+    ctx.close()
+
+
+def test_analytic_route_equals_stored_factors(gp):
+    s = scenes.two_sheets(n=16, seed=1)
+    ctx, pg, X, XR = _build(gp, s)
+    gp.barrier_eval(ctx, X, pg, x_rest=XR)
+    Hi = gp.pair_inspect(ctx, X, pg, x_rest=XR, want=("hess",))["hess"]
+    Ha = gp.proxy_dense(ctx, X, pg, gp.PROJ_ANALYTIC, x_rest=XR)
+    sc = Hi.abs().amax(dim=(1, 2), keepdim=True)
+    assert bool(((Ha - Hi).abs() <= 1e-12 * sc + 1e-300).all())
+    ctx.close()
+    # a batch: per-scene dhat and kappa
+    b = scenes.batch_two_sheets(S=4, r_lo=6, r_hi=16, dhat_lo=1e-3, dhat_hi=2e-1, seed_base=900)
+    dev = torch.device("cuda", 0)
+    X, XR, T = (torch.tensor(a, device=dev) for a in (b.x, b.x_rest, b.tuples))
+    prm = gp.params(batch=gp.Batch(b.vert_off, b.dhat, b.kappa))
+    ctx = gp.Context()
+    gp.pairs_build(ctx, X, T, prm, x_rest=XR)
+    gp.barrier_eval(ctx, X, prm, x_rest=XR)
+    Hi = gp.pair_inspect(ctx, X, prm, x_rest=XR, want=("hess",))["hess"]
+    Ha = gp.proxy_dense(ctx, X, prm, gp.PROJ_ANALYTIC, x_rest=XR)
+    sc = Hi.abs().amax(dim=(1, 2), keepdim=True)
+    assert bool(((Ha - Hi).abs() <= 1e-12 * sc + 1e-300).all())
+    ctx.close()
+
+
+def test_full_scale_sampled_pairs(gp):
+    s = scenes.stacked_sheets(n_sheets=10, n=256, seed=2)
+    ctx, pg, X, XR = _build(gp, s)
+    po = oracle.params(dhat=s.dhat, kappa=s.kappa)
+    pi = gp.pair_inspect(ctx, want=("src", "type", "vid", "mult"))
+    n = pi["src"].shape[0]
+    pick = np.sort(np.random.default_rng(13).choice(n, min(n, 4000), replace=False))
+    idx = torch.tensor(pick, device="cuda")
+    pairs = {k: v[idx].cpu().numpy() for k, v in pi.items()}
+    Ha = gp.proxy_dense(ctx, X, pg, gp.PROJ_ANALYTIC, x_rest=XR)[idx].cpu().numpy()
+    Hn = gp.proxy_dense(ctx, X, pg, gp.PROJ_NUMERIC, x_rest=XR)[idx].cpu().numpy()
+    sub = s.tuples[pairs["src"]]
+    ref = oracle.eval_scene(s.x, sub, po, x_rest=s.x_rest, per_pair=True)
+    refx = oracle.eval_xproj(s.x, sub, po, x_rest=s.x_rest)
+    pairs["src"] = np.arange(len(pick))
+    _compare(Ha, pairs, sub, ref["pairH"])
+    _compare(Hn, pairs, sub, refx)
+    assert (pairs["type"] >= 5).any() and (pairs["type"] < 5).any()
+    ctx.close()
+
+
+def test_errors(gp):
+    s = scenes.two_sheets(n=6, dhat=0.15, kappa=10.0, seed=3, offset=0.5, jitter=0.3)
+    ctx, pg, X, XR = _build(gp, s)
+    with pytest.raises(gp.GipcError) as ei:
+        gp.proxy_dense(ctx, X, pg, 7, x_rest=XR)
+    assert ei.value.status == gp.ERR_INVALID_ARG
+    ctx.close()
+    ctx = gp.Context()
+    ctx.info = {"n_staged": 1}
+    with pytest.raises(gp.GipcError) as ei:
+        gp.proxy_dense(ctx, X, pg, gp.PROJ_ANALYTIC, x_rest=XR)
+    assert ei.value.status in (gp.ERR_STATE, gp.ERR_INVALID_ARG)
+    ctx.close()
