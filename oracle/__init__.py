@@ -35,6 +35,14 @@ def params(dhat=1e-3, kappa=1e4, dthr_ratio=0.1, epsx_ratio=1e-3, filter=True, m
     return Params(dhat, kappa, dthr_ratio, epsx_ratio, int(filter), int(mollify), int(eq12))
 
 
+class FParams(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("eps_v", ctypes.c_double), ("dt", ctypes.c_double)]
+
+
+def fparams(mu=0.2, eps_v=1e-3, dt=1e-2):
+    return FParams(mu, eps_v, dt)
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain C, OpenMP)."""
     if force or not os.path.exists(_LIB_PATH):
@@ -73,6 +81,14 @@ def lib():
         L.orc_stencil.restype = ctypes.c_int
         L.orc_eval.argtypes = [i32, vp, vp, i64, vp, ctypes.POINTER(Params), ctypes.c_int, dp, vp, vp, vp, vp, vp, vp]
         L.orc_eval.restype = i64
+        L.orc_friction_f.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp, dp]
+        L.orc_friction_f.restype = None
+        L.orc_friction_pair.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Params), ctypes.POINTER(FParams), dp, vp, vp,
+                                        vp]
+        L.orc_friction_pair.restype = ctypes.c_int
+        L.orc_friction_eval.argtypes = [i32, vp, vp, vp, i64, vp, ctypes.POINTER(Params), ctypes.POINTER(FParams),
+                                        ctypes.c_int, dp, vp, vp, vp, vp]
+        L.orc_friction_eval.restype = i64
         L.orc_pair_xproj.argtypes = [vp, vp, vp, ctypes.POINTER(Params), vp, vp]
         L.orc_pair_xproj.restype = ctypes.c_int
         L.orc_eval_xproj.argtypes = [i32, vp, vp, i64, vp, ctypes.POINTER(Params), ctypes.c_int, vp]
@@ -191,6 +207,64 @@ def eval_xproj(x, tuples, prm=None, x_rest=None, nthreads=0):
                             int(nthreads), out.ctypes.data) < 0:
         raise ValueError("malformed tuple or vertex index out of range")
     return out.reshape(-1, 12, 12)
+
+
+def friction_f(y, eps_v, dt):
+    f0, f1, df1 = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    lib().orc_friction_f(float(y), float(eps_v), float(dt), ctypes.byref(f0), ctypes.byref(f1), ctypes.byref(df1))
+    return f0.value, f1.value, df1.value
+
+
+def _pad4(a):
+    a = np.ascontiguousarray(np.asarray(a, np.float64).reshape(-1, 3))
+    if a.shape[0] < 4:
+        a = np.vstack([a, np.zeros((4 - a.shape[0], 3))])
+    return np.ascontiguousarray(a)
+
+
+def friction_pair(tuple4, xs_n, xs, xr=None, prm=None, fp=None):
+    """Lagged friction of one pair: dict with D, grad (12,), hess (12, 12),
+    lam, normal (3,), coef (4,), u (2,)."""
+    prm = prm or params()
+    fp = fp or fparams()
+    t = np.ascontiguousarray(tuple4, dtype=np.int32)
+    xn, xc = _pad4(xs_n), _pad4(xs)
+    xr_a = None if xr is None else _pad4(xr)
+    D = ctypes.c_double()
+    g = np.zeros(12)
+    H = np.zeros(144)
+    info = np.zeros(10)
+    if lib().orc_friction_pair(t.ctypes.data, xn.ctypes.data, _ptr(xr_a), xc.ctypes.data, ctypes.byref(prm),
+                               ctypes.byref(fp), ctypes.byref(D), g.ctypes.data, H.ctypes.data,
+                               info.ctypes.data) < 0:
+        raise ValueError("malformed tuple")
+    return dict(D=D.value, grad=g, hess=H.reshape(12, 12), lam=info[0], normal=info[1:4], coef=info[4:8],
+                u=info[8:10])
+
+
+def friction_scene(x_n, x, tuples, prm=None, fp=None, x_rest=None, nthreads=0, per_pair=False):
+    """Friction energy and gradient of a list (plus per-pair data on request)."""
+    prm = prm or params()
+    fp = fp or fparams()
+    x_n = np.ascontiguousarray(x_n, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    t = np.ascontiguousarray(tuples, dtype=np.int32).reshape(-1, 4)
+    xr = None if x_rest is None else np.ascontiguousarray(x_rest, dtype=np.float64)
+    V, P = x.shape[0], t.shape[0]
+    grad = np.zeros((V, 3))
+    E = ctypes.c_double()
+    pE = np.zeros(P) if per_pair else None
+    pG = np.zeros((P, 12)) if per_pair else None
+    pH = np.zeros((P, 144)) if per_pair else None
+    rc = lib().orc_friction_eval(V, x_n.ctypes.data, x.ctypes.data, _ptr(xr), P, t.ctypes.data, ctypes.byref(prm),
+                                 ctypes.byref(fp), int(nthreads), ctypes.byref(E), grad.ctypes.data, _ptr(pE),
+                                 _ptr(pG), _ptr(pH))
+    if rc < 0:
+        raise ValueError("malformed tuple or vertex index out of range")
+    out = dict(E=E.value, grad=grad)
+    if per_pair:
+        out.update(pairE=pE, pairG=pG, pairH=pH.reshape(P, 12, 12))
+    return out
 
 
 def eval_scene(x, tuples, prm=None, x_rest=None, nthreads=0, per_pair=False):

@@ -611,6 +611,189 @@ int orc_eval_xproj(int32_t V, const double* x, const double* x_rest, int64_t P, 
     return 0;
 }
 
+/* ------------------------------------------------------------- friction */
+
+/* f0, f1 = f0' and f1' of the smooth static-to-dynamic transition
+ * (supplement Sec. 5; h = dt): f1(y) = -y^2/(eps h)^2 + 2y/(eps h) below
+ * eps h, 1 above; f0 its antiderivative with f0(eps h) = eps h. */
+void orc_friction_f(double y, double eps_v, double dt, double* f0, double* f1, double* df1) {
+    const double s = eps_v * dt;
+    if (y < s) {
+        *f0 = -y * y * y / (3.0 * s * s) + y * y / s + s / 3.0;
+        *f1 = -y * y / (s * s) + 2.0 * y / s;
+        *df1 = -2.0 * y / (s * s) + 2.0 / s;
+    } else {
+        *f0 = y;
+        *f1 = 1.0;
+        *df1 = 0.0;
+    }
+}
+
+/* One pair's lagged friction (supplement Sec. 5).  At the previous
+ * positions xs_n: the closest-point coefficients c and direction w of the
+ * pair's constrained distance, the normal force lambda = kappa e |db/dd|
+ * (the distance derivative of the pair's barrier energy, with its
+ * mollifier e), and the sliding basis T = c (x) P (12 x 2) with P an
+ * orthonormal basis of the plane normal to w.  At the current positions
+ * xs: u = T^T (xs - xs_n), D = mu lambda f0(|u|), grad = mu lambda
+ * f1(|u|)/|u| T u and the Hessian mu lambda T M T^T with the 2x2
+ * M = (f1'|u| - f1)/|u|^3 u u^T + f1/|u| I projected to PSD (Jacobi on the
+ * 2x2).  info (nullable, 10): lambda, n[3], c[4], u[2].  Returns -1 on a
+ * malformed tuple; pairs inactive or degenerate at xs_n give zeros. */
+int orc_friction_pair(const int32_t tuple[4], const double* xs_n, const double* xr, const double* xs,
+                      const orc_params* prm, const orc_fparams* fp, double* Dout, double* grad12, double* hess144,
+                      double* info) {
+    int32_t vid[4];
+    int kind;
+    int nv = decode(tuple, vid, &kind);
+    *Dout = 0.0;
+    memset(grad12, 0, sizeof(double) * 12);
+    memset(hess144, 0, sizeof(double) * 144);
+    if (info) memset(info, 0, sizeof(double) * 10);
+    if (nv < 0) return -1;
+    double X[4][3];
+    for (int k = 0; k < 4; ++k)
+        for (int d = 0; d < 3; ++d) X[k][d] = (k < nv) ? xs_n[3 * k + d] : 0.0;
+    orc_dist Dd;
+    if (kind == K_PT) dist_pt(X, &Dd);
+    else if (kind == K_EE) dist_ee(X, &Dd);
+    else if (kind == K_PE) dist_pe(X, &Dd);
+    else dist_pp(X, &Dd);
+    const double dhat = prm->dhat, kappa = prm->kappa;
+    if (!(Dd.d2 > 0.0) || !isfinite(Dd.d2)) return 0;
+    const double g = Dd.d2 / (dhat * dhat);
+    if (g >= 1.0) return 0;
+    const double d = sqrt(Dd.d2);
+    double e = 1.0;
+    if (kind == K_EE && prm->mollify) {
+        double a[3], b[3], n[3], ar[3], br[3];
+        sub3(X[1], X[0], a); sub3(X[3], X[2], b); cross3_acc(a, b, n);
+        const double cpar = dot3(n, n);
+        const double* R = xr ? xr : xs_n;
+        sub3(R + 3, R + 0, ar); sub3(R + 9, R + 6, br);
+        const double epsx = prm->epsx_ratio * dot3(ar, ar) * dot3(br, br);
+        if (cpar < epsx) {
+            double de, d2e;
+            orc_mollifier(cpar, epsx, &e, &de, &d2e);
+        }
+    }
+    double b, db, d2b;
+    orc_barrier(g, dhat, prm->eq12, &b, &db, &d2b);
+    const double lam = kappa * e * fabs(db * 2.0 * d / (dhat * dhat));
+    /* normal and an orthonormal basis of its plane */
+    double nrm[3] = {Dd.w[0] / d, Dd.w[1] / d, Dd.w[2] / d};
+    double ax[3] = {1.0, 0.0, 0.0};
+    if (fabs(nrm[0]) > 0.9) { ax[0] = 0.0; ax[1] = 1.0; }
+    double p1[3], p2[3];
+    const double an = dot3(ax, nrm);
+    for (int r = 0; r < 3; ++r) p1[r] = ax[r] - an * nrm[r];
+    const double l1 = sqrt(dot3(p1, p1));
+    for (int r = 0; r < 3; ++r) p1[r] /= l1;
+    cross3(nrm, p1, p2);
+    double T[12][2];
+    for (int k = 0; k < 4; ++k)
+        for (int r = 0; r < 3; ++r) {
+            T[3 * k + r][0] = Dd.coef[k] * p1[r];
+            T[3 * k + r][1] = Dd.coef[k] * p2[r];
+        }
+    double u[2] = {0.0, 0.0};
+    for (int i = 0; i < 12; ++i) {
+        const int k = i / 3;
+        const double dx = k < nv ? xs[i] - xs_n[i] : 0.0;
+        u[0] += T[i][0] * dx;
+        u[1] += T[i][1] * dx;
+    }
+    const double y = sqrt(u[0] * u[0] + u[1] * u[1]);
+    double f0, f1, df1;
+    orc_friction_f(y, fp->eps_v, fp->dt, &f0, &f1, &df1);
+    const double ml = fp->mu * lam;
+    *Dout = ml * f0;
+    const double s = fp->eps_v * fp->dt;
+    /* f1(y)/y and (f1'(y) y - f1(y)) / y^3, in closed form below eps h */
+    double f1y, cuu;
+    if (y < s) {
+        f1y = 2.0 / s - y / (s * s);
+        cuu = y > 0.0 ? -1.0 / (s * s * y) : 0.0;
+    } else {
+        f1y = 1.0 / y;
+        cuu = -1.0 / (y * y * y);
+    }
+    for (int i = 0; i < 12; ++i) grad12[i] = ml * f1y * (T[i][0] * u[0] + T[i][1] * u[1]);
+    double M[4] = {cuu * u[0] * u[0] + f1y, cuu * u[0] * u[1], cuu * u[1] * u[0], cuu * u[1] * u[1] + f1y};
+    double lm[2], Q[4];
+    orc_jacobi_eig(2, M, lm, Q);
+    double Mp[4];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 2; ++k)
+                if (lm[k] > 0.0) acc += Q[i * 2 + k] * lm[k] * Q[j * 2 + k];
+            Mp[i * 2 + j] = acc;
+        }
+    for (int i = 0; i < 12; ++i)
+        for (int j = 0; j < 12; ++j) {
+            double acc = 0.0;
+            for (int a2 = 0; a2 < 2; ++a2)
+                for (int b2 = 0; b2 < 2; ++b2) acc += T[i][a2] * Mp[a2 * 2 + b2] * T[j][b2];
+            hess144[i * 12 + j] = ml * acc;
+        }
+    if (info) {
+        info[0] = lam;
+        for (int r = 0; r < 3; ++r) info[1 + r] = nrm[r];
+        for (int k = 0; k < 4; ++k) info[4 + k] = Dd.coef[k];
+        info[8] = u[0]; info[9] = u[1];
+    }
+    return 0;
+}
+
+/* Friction of a whole list: energy and gradient sums in pair order, and per
+ * pair D, gradient and Hessian on request (nullable). */
+int64_t orc_friction_eval(int32_t V, const double* x_n, const double* x, const double* x_rest, int64_t P,
+                          const int32_t* tuples, const orc_params* prm, const orc_fparams* fp, int nthreads,
+                          double* energy, double* grad, double* pairE, double* pairG, double* pairH) {
+    for (int64_t p = 0; p < P; ++p) {
+        int32_t vid[4];
+        int nv = orc_stencil(tuples + 4 * p, vid);
+        if (nv < 0) return -1;
+        for (int k = 0; k < nv; ++k)
+            if (vid[k] < 0 || vid[k] >= V) return -1;
+    }
+    double* lE = pairE ? pairE : (double*)malloc(sizeof(double) * (P > 0 ? P : 1));
+    double* lG = pairG ? pairG : (double*)malloc(sizeof(double) * 12 * (P > 0 ? P : 1));
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    #pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < P; ++p) {
+        const int32_t* t = tuples + 4 * p;
+        int32_t vid[4];
+        int nv = orc_stencil(t, vid);
+        double xn[12] = {0}, xc[12] = {0}, xr[12] = {0}, H[144];
+        for (int k = 0; k < nv; ++k)
+            for (int d = 0; d < 3; ++d) {
+                xn[3 * k + d] = x_n[3 * (int64_t)vid[k] + d];
+                xc[3 * k + d] = x[3 * (int64_t)vid[k] + d];
+                xr[3 * k + d] = (x_rest ? x_rest : x_n)[3 * (int64_t)vid[k] + d];
+            }
+        orc_friction_pair(t, xn, xr, xc, prm, fp, &lE[p], lG + 12 * p, pairH ? pairH + 144 * p : H, NULL);
+    }
+    double Es = 0.0;
+    memset(grad, 0, sizeof(double) * 3 * (size_t)V);
+    for (int64_t p = 0; p < P; ++p) {
+        int32_t vid[4];
+        int nv = orc_stencil(tuples + 4 * p, vid);
+        Es += lE[p];
+        for (int k = 0; k < nv; ++k)
+            for (int d = 0; d < 3; ++d) grad[3 * (int64_t)vid[k] + d] += lG[12 * p + 3 * k + d];
+    }
+    *energy = Es;
+    if (!pairE) free(lE);
+    if (!pairG) free(lG);
+    return 0;
+}
+
 /* --------------------------------------------------------------- assembly */
 
 typedef struct { int32_t r, c; int64_t seq; } blk_key;

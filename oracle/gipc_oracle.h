@@ -33,6 +33,14 @@ typedef struct {
     int eq12;           /* use the non-stiffened barrier Eq. 12 instead of Eq. 24 */
 } orc_params;
 
+/* lagged friction (supplement Sec. 5): coefficient, the velocity threshold
+ * eps_v of f1 and the time step h */
+typedef struct {
+    double mu;
+    double eps_v;
+    double dt;
+} orc_fparams;
+
 /* sub-type codes reported per pair */
 enum { ORC_INACTIVE = 0, ORC_PT = 1, ORC_PE = 2, ORC_PP = 3, ORC_EE = 4, ORC_DEGENERATE = 7 };
 
@@ -71,6 +79,24 @@ int orc_pair_xproj(const int32_t tuple[4], const double* xs, const double* xr, c
 /* orc_pair_xproj's Px for every tuple of a list, pairPx [P][12][12]. */
 int orc_eval_xproj(int32_t V, const double* x, const double* x_rest, int64_t P, const int32_t* tuples,
                    const orc_params* prm, int nthreads, double* pairPx);
+
+/* f0, f1 and f1' of the friction transition at y (h = dt). */
+void orc_friction_f(double y, double eps_v, double dt, double* f0, double* f1, double* df1);
+
+/*
+ * Lagged friction of one pair: basis, normal force and closest-point
+ * coefficients at xs_n [4][3], sliding from xs_n to xs; outputs D, gradient
+ * [12] and PSD-projected Hessian [12][12] over the tuple's slots; info
+ * (nullable, 10 doubles): lambda, normal[3], c[4], u[2].
+ */
+int orc_friction_pair(const int32_t tuple[4], const double* xs_n, const double* xr, const double* xs,
+                      const orc_params* prm, const orc_fparams* fp, double* D, double* grad12, double* hess144,
+                      double* info);
+
+/* Friction of a list of tuples (per-pair outputs nullable). */
+int64_t orc_friction_eval(int32_t V, const double* x_n, const double* x, const double* x_rest, int64_t P,
+                          const int32_t* tuples, const orc_params* prm, const orc_fparams* fp, int nthreads,
+                          double* energy, double* grad, double* pairE, double* pairG, double* pairH);
 
 /* Number of OpenMP threads the scene-level functions use. */
 int orc_num_threads(void);
