@@ -251,6 +251,44 @@ gipc_status gipc_mf_apply(gipc_ctx* ctx, const double* diag, const double* x, do
 gipc_status gipc_pcg_mf(gipc_ctx* ctx, const double* diag, const double* b, double* x, double rtol, int32_t maxit,
                         int32_t* iters, double* relres, void* stream);
 
+/* Lagged friction parameters (supplement Sec. 5): friction coefficient mu,
+ * the velocity threshold eps_v of the transition f1 and the time step dt
+ * (f1 reaches 1 at |u| = eps_v dt). */
+typedef struct {
+    double mu;
+    double eps_v;
+    double dt;
+} gipc_friction;
+
+/*
+ * Lag the friction of the staged pairs of the last build at the previous
+ * positions mesh->x (x^n; mesh->x_rest as for the barrier): per pair the
+ * closest-point coefficients c of its constrained distance, the contact
+ * normal n, the normal force lambda = kappa e |db/dd| (distance derivative
+ * of the pair's barrier energy with its mollifier; per-scene dhat / kappa
+ * of params) times mu and the multiplicity, and the anchor
+ * (I - n n^T) sum_i c_i x_i^n.  Pairs inactive at x^n get no friction.
+ * Stored in the context until the next gipc_pairs_build.  Errors:
+ * INVALID_ARG (NULL, mu < 0, eps_v <= 0, dt <= 0, non-finite), STATE (no
+ * build, V differs), HIP.
+ */
+gipc_status gipc_friction_lag(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params,
+                              const gipc_friction* fr, void* stream);
+
+/*
+ * Lagged friction at the current positions x (device double [V][3]):
+ * energy (device double [S], one per scene) = sum_k mu lambda_k f0(|u_k|),
+ * grad (device double [V][3], overwritten) = its gradient, and, with A
+ * non-NULL (the pattern of the last build, FP64 or FP32), the PSD-projected
+ * friction Hessian blocks c_i c_j S_k ADDED to A's values; u_k is the
+ * tangential sliding of the pair since x^n in the lagged basis and S_k the
+ * 3x3 form of the projected 2x2 block (eigenvalues f1'(|u|) along u and
+ * f1(|u|)/|u| across it, clamped at 0).  Deterministic.  Errors:
+ * INVALID_ARG, STATE (no lag since the last build), HIP.
+ */
+gipc_status gipc_friction_eval(gipc_ctx* ctx, const double* x, double* energy, double* grad, const gipc_bsr* A,
+                               void* stream);
+
 /* methods of gipc_proxy_dense */
 #define GIPC_PROJ_ANALYTIC 0
 #define GIPC_PROJ_NUMERIC 1

@@ -28,7 +28,7 @@ EXPORTS = [
     "gipc_get_info", "gipc_bsr_pattern", "gipc_barrier_eval", "gipc_assemble_bsr", "gipc_eval_assemble",
     "gipc_bsr_spmv", "gipc_pcg", "gipc_pair_inspect", "gipc_copy", "gipc_get_tune", "gipc_set_tune",
     "gipc_autotune", "gipc_graph_create", "gipc_graph_launch", "gipc_graph_destroy", "gipc_mf_apply",
-    "gipc_pcg_mf", "gipc_proxy_dense",
+    "gipc_pcg_mf", "gipc_proxy_dense", "gipc_friction_lag", "gipc_friction_eval",
 ]
 
 
@@ -66,6 +66,10 @@ class Pairs(ctypes.Structure):
 class Bsr(ctypes.Structure):
     _fields_ = [("nbrows", ctypes.c_int32), ("nnzb", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
                 ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p), ("dtype", ctypes.c_int32)]
+
+
+class Friction(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("eps_v", ctypes.c_double), ("dt", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -111,6 +115,9 @@ def lib():
             "gipc_mf_apply": (st, [vp, vp, vp, vp, vp]),
             "gipc_pcg_mf": (st, [vp, vp, vp, vp, d, i32, ctypes.POINTER(i32), ctypes.POINTER(d), vp]),
             "gipc_proxy_dense": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), i32, vp, vp]),
+            "gipc_friction_lag": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), ctypes.POINTER(Friction),
+                                       vp]),
+            "gipc_friction_eval": (st, [vp, vp, vp, vp, ctypes.POINTER(Bsr), vp]),
             "gipc_pair_inspect": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), vp, vp, vp, vp, vp, vp, vp,
                                        vp]),
             "gipc_copy": (st, [vp, vp, i64, vp]),
@@ -348,6 +355,29 @@ def pcg(ctx: Context, A: BsrMatrix, b, x=None, rtol=1e-6, maxit=1000, stream=Non
                        ctypes.byref(rr), _stream(stream))
     ctx._check(s, "gipc_pcg")
     return x, int(it.value), float(rr.value), int(s)
+
+
+def friction_lag(ctx: Context, x_n, prm: Params, mu, eps_v, dt, x_rest=None, stream=None):
+    """Lag the friction of the staged pairs at the previous positions x_n."""
+    mesh = Context._mesh(x_n, x_rest)
+    fr = Friction(float(mu), float(eps_v), float(dt))
+    ctx._check(lib().gipc_friction_lag(ctx.h, ctypes.byref(mesh), ctypes.byref(prm), ctypes.byref(fr),
+                                       _stream(stream)), "gipc_friction_lag")
+
+
+def friction_eval(ctx: Context, x, prm: Params, A: "BsrMatrix | None" = None, energy=None, grad=None, stream=None):
+    """Friction energy (per scene) and gradient at x; with A, its Hessian
+    blocks are added to A.  Returns (energy, grad)."""
+    _need(x, torch.float64, 3, "x")
+    _need_rows(ctx, x, "x")
+    energy = _energy_out(prm, x.device) if energy is None else energy
+    grad = torch.empty_like(x) if grad is None else grad
+    _need(grad, torch.float64, 3, "grad")
+    _need_rows(ctx, grad, "grad")
+    ctx._check(lib().gipc_friction_eval(ctx.h, _ptr(x), _ptr(energy), _ptr(grad),
+                                        ctypes.byref(A.desc) if A is not None else None, _stream(stream)),
+               "gipc_friction_eval")
+    return energy, grad
 
 
 PROJ_ANALYTIC, PROJ_NUMERIC = 0, 1

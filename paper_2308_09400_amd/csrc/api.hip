@@ -198,7 +198,7 @@ void gipc_ctx_destroy(gipc_ctx* ctx) {
                       &ctx->contrib, &ctx->kcol, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
                       &ctx->slot_row, &ctx->diag_slot, &ctx->maxbuf, &ctx->bigrows, &ctx->tslot, &ctx->incv, &ctx->order,
                       &ctx->obox, &ctx->ocell, &ctx->ohist, &ctx->ooff, &ctx->ofill, &ctx->rec_main, &ctx->rec_extra, &ctx->ev,
-                      &ctx->epart, &ctx->mfg, &ctx->mfab, &ctx->vscene, &ctx->pieces, &ctx->poff,
+                      &ctx->epart, &ctx->mfg, &ctx->mfab, &ctx->flag, &ctx->ffr, &ctx->fev, &ctx->fpart, &ctx->vscene, &ctx->pieces, &ctx->poff,
                       &ctx->r, &ctx->z, &ctx->p, &ctx->q, &ctx->p32, &ctx->minv, &ctx->part, &ctx->scal, &ctx->scan_tmp,
                       &ctx->scan_tmp2};
     for (DevBuf* b : bufs) release(*b);
@@ -666,6 +666,63 @@ gipc_status gipc_pair_inspect(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_p
                            as<double>(ctx->rec_extra), x, xr, pm, src, type, vid, mult, energy, grad, hess,
                            S(stream)),
        "pair inspect");
+    return GIPC_OK;
+}
+
+gipc_status gipc_friction_lag(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params,
+                              const gipc_friction* fr, void* stream) {
+    if (!ctx) return GIPC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    gipc_status st;
+    if ((st = check_device(ctx)) != GIPC_OK) return st;
+    if (!fr) return fail(ctx, GIPC_ERR_INVALID_ARG, "friction parameters are NULL");
+    if (!(fr->mu >= 0.0) || !std::isfinite(fr->mu) || !(fr->eps_v > 0.0) || !std::isfinite(fr->eps_v) ||
+        !(fr->dt > 0.0) || !std::isfinite(fr->dt))
+        return fail(ctx, GIPC_ERR_INVALID_ARG, "need mu >= 0, eps_v > 0 and dt > 0, finite");
+    if ((st = check_mesh(ctx, mesh)) != GIPC_OK) return st;
+    DevParams pm;
+    if ((st = to_dev_params(ctx, params, pm)) != GIPC_OK) return st;
+    if (!ctx->built) return fail(ctx, GIPC_ERR_STATE, "gipc_pairs_build has not succeeded");
+    if (mesh->V != ctx->V) return fail(ctx, GIPC_ERR_STATE, "V = %d differs from the build (%d)", mesh->V, ctx->V);
+    if ((st = bind_batch(ctx, params, pm)) != GIPC_OK) return st;
+    const int64_t Ps = ctx->Ps;
+    CK(ensure(ctx->flag, sizeof(double) * 9 * (size_t)(Ps > 0 ? Ps : 1)), "alloc friction");
+    const double* xr = mesh->x_rest ? mesh->x_rest : mesh->x;
+    CK(launch_fric_lag(as<int4>(ctx->st_vid), ctx->merged ? as<int32_t>(ctx->mult) : nullptr, ctx->ranges, mesh->x,
+                       xr, pm, fr->mu, as<double>(ctx->flag), S(stream)),
+       "friction lag");
+    ctx->fric_gen = ctx->build_gen;
+    ctx->fric_sv = fr->eps_v * fr->dt;
+    return GIPC_OK;
+}
+
+gipc_status gipc_friction_eval(gipc_ctx* ctx, const double* x, double* energy, double* grad, const gipc_bsr* A,
+                               void* stream) {
+    if (!ctx) return GIPC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    gipc_status st;
+    if ((st = check_device(ctx)) != GIPC_OK) return st;
+    if (!ctx->built || ctx->fric_gen != ctx->build_gen)
+        return fail(ctx, GIPC_ERR_STATE, "gipc_friction_lag must follow the last gipc_pairs_build");
+    if (!energy || (ctx->V > 0 && (!x || !grad))) return fail(ctx, GIPC_ERR_INVALID_ARG, "x, energy or grad is NULL");
+    if (A) {
+        if (!A->val) return fail(ctx, GIPC_ERR_INVALID_ARG, "A->val is NULL");
+        if (A->dtype != GIPC_F64 && A->dtype != GIPC_F32) return fail(ctx, GIPC_ERR_INVALID_ARG, "bad dtype");
+        if (!same_pattern(ctx, A)) return fail(ctx, GIPC_ERR_STATE, "A is not the pattern of the last build");
+    }
+    const int64_t Ps = ctx->Ps;
+    CK(ensure(ctx->ffr, sizeof(double) * 10 * (size_t)(Ps > 0 ? Ps : 1)), "alloc friction");
+    CK(ensure(ctx->fev, sizeof(double) * (size_t)(ctx->V > 0 ? ctx->V : 1)), "alloc friction");
+    CK(ensure(ctx->fpart, sizeof(double) * (size_t)(ctx->npieces > 0 ? ctx->npieces : 1)), "alloc friction");
+    hipStream_t s = S(stream);
+    CK(launch_fric_eval(ctx->V, as<int4>(ctx->st_vid), ctx->ranges, as<double>(ctx->flag), x, ctx->fric_sv,
+                        as<double>(ctx->ffr), as<int32_t>(ctx->row_ptr), as<int32_t>(ctx->diag_slot),
+                        as<int64_t>(ctx->cptr), as<uint32_t>(ctx->contrib), grad, as<double>(ctx->fev),
+                        A ? A->val : nullptr, A ? A->dtype : 0, ctx->nnzb, s),
+       "friction eval");
+    CK(launch_energy(as<double>(ctx->fev), as<int2>(ctx->pieces), ctx->npieces, as<int32_t>(ctx->poff), ctx->S,
+                     as<double>(ctx->fpart), energy, s),
+       "friction energy");
     return GIPC_OK;
 }
 

@@ -104,6 +104,11 @@ struct gipc_ctx {
     // matrix-free operator: the c_i w~_k vectors of every incidence, row by
     // row (built at the first use after an eval), and (alpha, beta) per pair
     gipc::DevBuf mfg, mfab;
+    // lagged friction: per-pair lag and eval records, energy shares and
+    // pieces; the build it was lagged for and eps_v dt
+    gipc::DevBuf flag, ffr, fev, fpart;
+    uint64_t fric_gen = 0;
+    double fric_sv = 0.0;
     uint64_t eval_gen = 0;   // bumped by every eval
     uint64_t mfg_gen = 0;    // eval_gen the vectors in mfg belong to
     int64_t ninc = 0;  // incidences (k, i) of the build: sum of the stencil sizes
@@ -228,6 +233,15 @@ int64_t mf_num_parts(int32_t V);
 // (numeric.hip); hess [Ps][12][12]
 hipError_t launch_proxy_dense(int method, const int4* st_vid, const int32_t* mult, const TypeRanges& tr,
                               const double* x, const double* xr, const DevParams& pm, double* hess, hipStream_t s);
+
+// lagged friction (friction.hip): lag [Ps][9] at x^n; eval writes fr [Ps][10],
+// grad [V][3], energy shares ev [V] and, with val, adds the blocks
+hipError_t launch_fric_lag(const int4* st_vid, const int32_t* mult, const TypeRanges& tr, const double* x,
+                           const double* xr, const DevParams& pm, double mu, double* lag, hipStream_t s);
+hipError_t launch_fric_eval(int32_t V, const int4* st_vid, const TypeRanges& tr, const double* lag, const double* x,
+                            double sv, double* fr, const int32_t* row_ptr, const int32_t* diag_slot,
+                            const int64_t* cptr, const uint32_t* contrib, double* grad, double* ev, void* val,
+                            int dtype, int64_t nnzb, hipStream_t s);
 
 // ---- solve.hip
 hipError_t launch_spmv(const gipc_bsr& A, const void* x, void* y, hipStream_t s);
