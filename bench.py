@@ -33,7 +33,8 @@ matrix-free operator once against the FP64 BSR matrix of the same eval (one
 product each; the PCG of the step both ways), reported under
 `matrix_free`; the default workload also times the dense projected proxy
 Hessians of all staged pairs from the analytic eigensystems against the
-numeric baseline (x-space Jacobi projection), under `numeric_eigen_baseline`.
+numeric baseline (x-space Jacobi projection), under `numeric_eigen_baseline`,
+and the lagged friction on the same pairs under `friction`.
 """
 from __future__ import annotations
 
@@ -213,6 +214,25 @@ def numeric_compare(gp, ctx, x, xr, prm, info, stream):
         "paper_table1": "10^7 12x12 Hessians: Eigen (CPU) 2.42e3 ms vs analytic 4.95e2 ms on the CPU (4.9x); "
                         "analytic on the GPU 9.01e1 ms; 16-core Intel Core i9 12900K and RTX 4090 (Sec. 7)",
     }
+
+
+def friction_compare(gp, ctx, x, xr, prm, diag, info, stream):
+    """Lagged friction on the same staged pairs: lag at x, then energy,
+    gradient and Hessian blocks added to the FP64 matrix at a moved x, next
+    to the barrier's own eval (mu 0.2, eps_v 1e-3, dt 1e-2)."""
+    import torch
+    A = gp.BsrMatrix(ctx, dtype=gp.F64)
+    gp.eval_assemble(ctx, x, prm, A, diag=diag, x_rest=xr)
+    g = torch.Generator(device=x.device).manual_seed(7)
+    x1 = x + 1e-5 * torch.randn(x.shape, dtype=x.dtype, device=x.device, generator=g)
+    t_lag = _median_ms(lambda: gp.friction_lag(ctx, x, prm, 0.2, 1e-3, 1e-2, x_rest=xr), 5, stream)
+    t_eval = _median_ms(lambda: gp.friction_eval(ctx, x1, prm), 5, stream)
+    t_asm = _median_ms(lambda: gp.friction_eval(ctx, x1, prm, A), 5, stream)
+    t_bar = _median_ms(lambda: gp.barrier_eval(ctx, x, prm, x_rest=xr), 5, stream)
+    t_bar_asm = _median_ms(lambda: gp.eval_assemble(ctx, x, prm, A, diag=diag, x_rest=xr), 5, stream)
+    del A
+    return {"pairs": int(info["n_staged"]), "lag_ms": t_lag, "eval_ms": t_eval, "eval_add_blocks_ms": t_asm,
+            "barrier_eval_ms": t_bar, "barrier_eval_assemble_ms": t_bar_asm}
 
 
 def _median_ms(fn, reps, stream):
@@ -508,6 +528,7 @@ def main():
     out["matrix_free"] = matrix_free_compare(gp, ctx, x, xr, prm, diag, info, rtol, maxit, stream)
     if args.workload == "sheets10":
         out["numeric_eigen_baseline"] = numeric_compare(gp, ctx, x, xr, prm, info, stream)
+        out["friction"] = friction_compare(gp, ctx, x, xr, prm, diag, info, stream)
     ctx.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_sample)

@@ -711,7 +711,7 @@ gipc_status gipc_friction_eval(gipc_ctx* ctx, const double* x, double* energy, d
         if (!same_pattern(ctx, A)) return fail(ctx, GIPC_ERR_STATE, "A is not the pattern of the last build");
     }
     const int64_t Ps = ctx->Ps;
-    CK(ensure(ctx->ffr, sizeof(double) * 10 * (size_t)(Ps > 0 ? Ps : 1)), "alloc friction");
+    CK(ensure(ctx->ffr, sizeof(double) * 16 * (size_t)(Ps > 0 ? Ps : 1)), "alloc friction");
     CK(ensure(ctx->fev, sizeof(double) * (size_t)(ctx->V > 0 ? ctx->V : 1)), "alloc friction");
     CK(ensure(ctx->fpart, sizeof(double) * (size_t)(ctx->npieces > 0 ? ctx->npieces : 1)), "alloc friction");
     hipStream_t s = S(stream);

@@ -58,7 +58,9 @@ __global__ void __launch_bounds__(kBlock) k_fric_lag(const int4* __restrict__ st
     r[6] = a.x; r[7] = a.y; r[8] = a.z;
 }
 
-// friction record [D, gx, gy, gz, S00, S01, S02, S11, S12, S22]
+// friction record, 16 doubles (one 128-byte line per pair for the row pass):
+// [D, gx, gy, gz, S00, S01, S02, S11, S12, S22, c1, c2, -, -, -, -]
+constexpr int kFr = 16;
 __global__ void __launch_bounds__(kBlock) k_fric_pair(const int4* __restrict__ st_vid, TypeRanges tr,
                                                       const double* __restrict__ lag, const double* __restrict__ X,
                                                       double sv, double* __restrict__ fr) {
@@ -92,7 +94,9 @@ __global__ void __launch_bounds__(kBlock) k_fric_pair(const int4* __restrict__ s
     const double be = ml * fmax(f1y, 0.0);
     const double al = y > 0.0 ? (ml * fmax(df1, 0.0) - be) / (y * y) : 0.0;
     const d3 g = (ml * f1y) * t;
-    double* r = fr + 10 * k;
+    double* r = fr + kFr * k;
+    r[10] = L[0];
+    r[11] = L[1];
     r[0] = ml * f0;
     r[1] = g.x; r[2] = g.y; r[3] = g.z;
     // S = be (I - n n^T) + al t t^T
@@ -104,66 +108,93 @@ __global__ void __launch_bounds__(kBlock) k_fric_pair(const int4* __restrict__ s
     r[9] = be * (1.0 - n.z * n.z) + al * t.z * t.z;
 }
 
-__device__ __forceinline__ double lag_coef(const double* __restrict__ lag, uint32_t k, int i, int64_t e0) {
-    const double m[8] = {lag[9 * (int64_t)k], lag[9 * (int64_t)k + 1], 0, 0, 0, 0, 0, 0};
+// c_i of pair k from its friction record
+__device__ __forceinline__ double fr_coef(const double* f, uint32_t k, int i, int64_t e0) {
+    const double m[8] = {f[10], f[11], 0, 0, 0, 0, 0, 0};
     return rec_coef(m, i, (int64_t)k >= e0);
 }
 
-// kFrLanes lanes per row; each lane sums whole blocks of the row in their
-// contribution order; the diagonal block also gives the gradient and the
-// energy shares (pairs whose slot 0 is the row)
+// adds the symmetric 3x3 given by its upper triangle U to stored block sl
+__device__ __forceinline__ void add_block_sym(void* val, int dtype, int64_t nnzb, int64_t sl, const double* U) {
+    const double F[9] = {U[0], U[1], U[2], U[1], U[3], U[4], U[2], U[4], U[5]};
+    if (dtype == GIPC_F64) {
+        double* vv = static_cast<double*>(val);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) vv[c * nnzb + sl] += F[c];
+    } else {
+        float* vv = static_cast<float*>(val);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) vv[c * nnzb + sl] = (float)((double)vv[c * nnzb + sl] + F[c]);
+    }
+}
+
+// kFrLanes lanes per row.  The diagonal list (the row's incidences) is
+// split over the lanes and reduced by a fixed butterfly: gradient, energy
+// share (pairs whose slot 0 is the row) and the diagonal block.  With val,
+// every off-diagonal block of the row is then summed by one lane, four
+// contributions' loads in flight, in list order.
 __global__ void __launch_bounds__(kBlock) k_fric_rows(int32_t V, const int32_t* __restrict__ row_ptr,
                                                       const int32_t* __restrict__ diag_slot,
                                                       const int64_t* __restrict__ cptr,
                                                       const uint32_t* __restrict__ contrib,
-                                                      const double* __restrict__ lag, const double* __restrict__ fr,
-                                                      int64_t e0, double* __restrict__ grad, double* __restrict__ ev,
+                                                      const double* __restrict__ fr, int64_t e0,
+                                                      double* __restrict__ grad, double* __restrict__ ev,
                                                       void* __restrict__ val, int dtype, int64_t nnzb) {
     const int64_t r = (int64_t)blockIdx.x * (kBlock / kFrLanes) + threadIdx.x / kFrLanes;
     const int lg = threadIdx.x % kFrLanes;
-    if (r >= V) return;
-    const int32_t ds = diag_slot[r];
-    for (int32_t sl = row_ptr[r] + lg; sl < row_ptr[r + 1]; sl += kFrLanes) {
-        const bool dg = sl == ds;
-        if (!val && !dg) continue;
-        double B[6] = {0, 0, 0, 0, 0, 0};
-        d3 gsum = mk(0, 0, 0);
-        double es = 0.0;
-        for (int64_t t = cptr[sl]; t < cptr[sl + 1]; ++t) {
+    const bool valid = r < V;
+    const int32_t ds = valid ? diag_slot[r] : 0;
+    double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // gradient, energy, diagonal block
+    if (valid) {
+        for (int64_t t = cptr[ds] + lg; t < cptr[ds + 1]; t += kFrLanes) {
             const uint32_t code = contrib[t];
             const uint32_t k = code >> 4;
-            const int i = (int)((code >> 2) & 3u), j = (int)(code & 3u);
-            const double ci = lag_coef(lag, k, i, e0), cj = i == j ? ci : lag_coef(lag, k, j, e0);
-            const double* f = fr + 10 * (int64_t)k;
-            if (val) {
-                const double cc = ci * cj;
+            const int i = (int)((code >> 2) & 3u);
+            const double* f = fr + kFr * (int64_t)k;
+            const double ci = fr_coef(f, k, i, e0);
+            acc[0] += ci * f[1];
+            acc[1] += ci * f[2];
+            acc[2] += ci * f[3];
+            if (i == 0) acc[3] += f[0];
+            const double cc = ci * ci;
 #pragma unroll
-                for (int q = 0; q < 6; ++q) B[q] += cc * f[4 + q];
-            }
-            if (dg) {
-                gsum = gsum + ci * mk(f[1], f[2], f[3]);
-                if (i == 0) es += f[0];
+            for (int q = 0; q < 6; ++q) acc[4 + q] += cc * f[4 + q];
+        }
+    }
+#pragma unroll
+    for (int o = kFrLanes / 2; o > 0; o >>= 1)
+#pragma unroll
+        for (int q = 0; q < 10; ++q) acc[q] += __shfl_xor(acc[q], o, kFrLanes);
+    if (!valid) return;
+    if (lg == 0) {
+        grad[3 * r] = acc[0];
+        grad[3 * r + 1] = acc[1];
+        grad[3 * r + 2] = acc[2];
+        ev[r] = acc[3];
+    }
+    if (!val) return;
+    if (lg == 0) add_block_sym(val, dtype, nnzb, ds, acc + 4);
+    for (int32_t sl = row_ptr[r] + lg; sl < row_ptr[r + 1]; sl += kFrLanes) {
+        if (sl == ds) continue;
+        double B[6] = {0, 0, 0, 0, 0, 0};
+        const int64_t t1 = cptr[sl + 1];
+        constexpr int U = 4;
+        for (int64_t t = cptr[sl]; t < t1; t += U) {
+            uint32_t code[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) code[q] = t + q < t1 ? contrib[t + q] : 0u;
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                if (t + q >= t1) break;
+                const uint32_t k = code[q] >> 4;
+                const int i = (int)((code[q] >> 2) & 3u), j = (int)(code[q] & 3u);
+                const double* f = fr + kFr * (int64_t)k;
+                const double cc = fr_coef(f, k, i, e0) * fr_coef(f, k, j, e0);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) B[c] += cc * f[4 + c];
             }
         }
-        if (dg) {
-            grad[3 * r] = gsum.x;
-            grad[3 * r + 1] = gsum.y;
-            grad[3 * r + 2] = gsum.z;
-            ev[r] = es;
-        }
-        if (val) {
-            // symmetric 3x3 from its upper triangle, added to the stored block
-            const double F[9] = {B[0], B[1], B[2], B[1], B[3], B[4], B[2], B[4], B[5]};
-            if (dtype == GIPC_F64) {
-                double* vv = static_cast<double*>(val);
-#pragma unroll
-                for (int c = 0; c < 9; ++c) vv[c * nnzb + sl] += F[c];
-            } else {
-                float* vv = static_cast<float*>(val);
-#pragma unroll
-                for (int c = 0; c < 9; ++c) vv[c * nnzb + sl] = (float)((double)vv[c * nnzb + sl] + F[c]);
-            }
-        }
+        add_block_sym(val, dtype, nnzb, sl, B);
     }
 }
 
@@ -189,8 +220,8 @@ hipError_t launch_fric_eval(int32_t V, const int4* st_vid, const TypeRanges& tr,
     }
     if (V == 0) return hipSuccess;
     const int64_t nb = ((int64_t)V * kFrLanes + kBlock - 1) / kBlock;
-    k_fric_rows<<<(unsigned)nb, kBlock, 0, s>>>(V, row_ptr, diag_slot, cptr, contrib, lag, fr, tr.off[FT_EE], grad,
-                                                ev, val, dtype, nnzb);
+    k_fric_rows<<<(unsigned)nb, kBlock, 0, s>>>(V, row_ptr, diag_slot, cptr, contrib, fr, tr.off[FT_EE], grad, ev,
+                                                val, dtype, nnzb);
     return hipGetLastError();
 }
 

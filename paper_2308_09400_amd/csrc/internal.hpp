@@ -234,7 +234,7 @@ int64_t mf_num_parts(int32_t V);
 hipError_t launch_proxy_dense(int method, const int4* st_vid, const int32_t* mult, const TypeRanges& tr,
                               const double* x, const double* xr, const DevParams& pm, double* hess, hipStream_t s);
 
-// lagged friction (friction.hip): lag [Ps][9] at x^n; eval writes fr [Ps][10],
+// lagged friction (friction.hip): lag [Ps][9] at x^n; eval writes fr [Ps][16],
 // grad [V][3], energy shares ev [V] and, with val, adds the blocks
 hipError_t launch_fric_lag(const int4* st_vid, const int32_t* mult, const TypeRanges& tr, const double* x,
                            const double* xr, const DevParams& pm, double mu, double* lag, hipStream_t s);
