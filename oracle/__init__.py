@@ -89,6 +89,8 @@ def lib():
         L.orc_friction_eval.argtypes = [i32, vp, vp, vp, i64, vp, ctypes.POINTER(Params), ctypes.POINTER(FParams),
                                         ctypes.c_int, dp, vp, vp, vp, vp]
         L.orc_friction_eval.restype = i64
+        L.orc_candidates.argtypes = [i32, vp, vp, i64, vp, i64, vp, ctypes.c_double, vp, i64]
+        L.orc_candidates.restype = i64
         L.orc_pair_xproj.argtypes = [vp, vp, vp, ctypes.POINTER(Params), vp, vp]
         L.orc_pair_xproj.restype = ctypes.c_int
         L.orc_eval_xproj.argtypes = [i32, vp, vp, i64, vp, ctypes.POINTER(Params), ctypes.c_int, vp]
@@ -265,6 +267,20 @@ def friction_scene(x_n, x, tuples, prm=None, fp=None, x_rest=None, nthreads=0, p
     if per_pair:
         out.update(pairE=pE, pairG=pG, pairH=pH.reshape(P, 12, 12))
     return out
+
+
+def candidates(x, vobj, tris, edges, dhat):
+    """All contact candidates by brute force, int32 [P][4] (PT then EE)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    vobj = np.ascontiguousarray(vobj, dtype=np.int32)
+    tris = np.ascontiguousarray(tris, dtype=np.int32).reshape(-1, 3)
+    edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+    args = (x.shape[0], x.ctypes.data, vobj.ctypes.data, tris.shape[0], tris.ctypes.data, edges.shape[0],
+            edges.ctypes.data, float(dhat))
+    n = lib().orc_candidates(*args, None, 0)
+    out = np.zeros((max(n, 1), 4), np.int32)
+    lib().orc_candidates(*args, out.ctypes.data, n)
+    return out[:n]
 
 
 def eval_scene(x, tuples, prm=None, x_rest=None, nthreads=0, per_pair=False):

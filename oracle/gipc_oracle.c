@@ -794,6 +794,69 @@ int64_t orc_friction_eval(int32_t V, const double* x_n, const double* x, const d
     return 0;
 }
 
+/* ----------------------------------------------------------- candidates */
+
+/* axis-aligned box of n vertices */
+static void cand_box(const double* x, const int32_t* v, int n, double lo[3], double hi[3]) {
+    for (int d = 0; d < 3; ++d) { lo[d] = INFINITY; hi[d] = -INFINITY; }
+    for (int k = 0; k < n; ++k)
+        for (int d = 0; d < 3; ++d) {
+            const double c = x[3 * (int64_t)v[k] + d];
+            if (c < lo[d]) lo[d] = c;
+            if (c > hi[d]) hi[d] = c;
+        }
+}
+
+/* box a inflated by dhat overlaps box b (closed intervals) */
+static int cand_overlap(const double alo[3], const double ahi[3], double dhat, const double blo[3],
+                        const double bhi[3]) {
+    for (int d = 0; d < 3; ++d)
+        if (alo[d] - dhat > bhi[d] || blo[d] > ahi[d] + dhat) return 0;
+    return 1;
+}
+
+/* Contact candidates by brute force over all point-triangle and edge-edge
+ * pairs (the pairs the barrier sum of Eq. 3 ranges over, restricted to
+ * those whose bounding boxes come within dhat): a point p and a triangle t
+ * of another object (vobj), p not a vertex of t, with p's box inflated by
+ * dhat overlapping t's box -> [-(p+1), t0, t1, t2]; edges i < j of
+ * different objects sharing no vertex, i's box inflated by dhat overlapping
+ * j's -> [a0, a1, b0, b1].  Point-triangle first, in (p, t) order, then
+ * edge-edge in (i, j) order.  Returns the count; writes at most cap tuples
+ * to out (nullable). */
+int64_t orc_candidates(int32_t V, const double* x, const int32_t* vobj, int64_t F, const int32_t* tris, int64_t E,
+                       const int32_t* edges, double dhat, int32_t* out, int64_t cap) {
+    int64_t n = 0;
+    for (int32_t p = 0; p < V; ++p) {
+        double plo[3], phi[3];
+        cand_box(x, &p, 1, plo, phi);
+        for (int64_t f = 0; f < F; ++f) {
+            const int32_t* t = tris + 3 * f;
+            if (vobj[t[0]] == vobj[p] || t[0] == p || t[1] == p || t[2] == p) continue;
+            double tlo[3], thi[3];
+            cand_box(x, t, 3, tlo, thi);
+            if (!cand_overlap(plo, phi, dhat, tlo, thi)) continue;
+            if (out && n < cap) { out[4 * n] = -(p + 1); out[4 * n + 1] = t[0]; out[4 * n + 2] = t[1]; out[4 * n + 3] = t[2]; }
+            ++n;
+        }
+    }
+    for (int64_t i = 0; i < E; ++i) {
+        const int32_t* a = edges + 2 * i;
+        double alo[3], ahi[3];
+        cand_box(x, a, 2, alo, ahi);
+        for (int64_t j = i + 1; j < E; ++j) {
+            const int32_t* b = edges + 2 * j;
+            if (vobj[a[0]] == vobj[b[0]] || a[0] == b[0] || a[0] == b[1] || a[1] == b[0] || a[1] == b[1]) continue;
+            double blo[3], bhi[3];
+            cand_box(x, b, 2, blo, bhi);
+            if (!cand_overlap(alo, ahi, dhat, blo, bhi)) continue;
+            if (out && n < cap) { out[4 * n] = a[0]; out[4 * n + 1] = a[1]; out[4 * n + 2] = b[0]; out[4 * n + 3] = b[1]; }
+            ++n;
+        }
+    }
+    return n;
+}
+
 /* --------------------------------------------------------------- assembly */
 
 typedef struct { int32_t r, c; int64_t seq; } blk_key;

@@ -98,6 +98,12 @@ int64_t orc_friction_eval(int32_t V, const double* x_n, const double* x, const d
                           const int32_t* tuples, const orc_params* prm, const orc_fparams* fp, int nthreads,
                           double* energy, double* grad, double* pairE, double* pairG, double* pairH);
 
+/* Contact candidates by brute force (every point-triangle and edge-edge
+ * pair of different objects, no shared vertex, boxes within dhat); returns
+ * the count and writes at most cap sign-encoded tuples to out (nullable). */
+int64_t orc_candidates(int32_t V, const double* x, const int32_t* vobj, int64_t F, const int32_t* tris, int64_t E,
+                       const int32_t* edges, double dhat, int32_t* out, int64_t cap);
+
 /* Number of OpenMP threads the scene-level functions use. */
 int orc_num_threads(void);
 
