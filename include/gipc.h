@@ -251,6 +251,37 @@ gipc_status gipc_mf_apply(gipc_ctx* ctx, const double* diag, const double* x, do
 gipc_status gipc_pcg_mf(gipc_ctx* ctx, const double* diag, const double* b, double* x, double rtol, int32_t maxit,
                         int32_t* iters, double* relres, void* stream);
 
+/* Surface topology for candidate generation (device arrays): the object
+ * id of every vertex (candidates only pair different objects; a triangle or
+ * edge belongs to the object of its first vertex), triangles int32 [F][3]
+ * and edges int32 [E][2]. */
+typedef struct {
+    const int32_t* vobj;
+    const int32_t* tris;
+    int64_t F;
+    const int32_t* edges;
+    int64_t E;
+} gipc_topology;
+
+/*
+ * Contact candidates on the GPU: every (point p, triangle t) with p not a
+ * vertex of t and every pair of edges i < j sharing no vertex, of different
+ * objects, whose axis-aligned boxes come within dhat (one box inflated by
+ * dhat, closed intervals): the pairs the sum of Eq. 3 ranges over before
+ * the distance decides which are active.  A uniform grid stands in for the
+ * paper's BVH (Sec. 6.2).  Output tuples in the encoding above, int32
+ * [count][4] device: point-triangle [-(p+1), t0, t1, t2] grouped by point
+ * in increasing p, then edge-edge [a0, a1, b0, b1] grouped by first edge;
+ * deterministic.  *count (host) receives the number of candidates; tuples
+ * are written only when tuples is non-NULL and cap >= count (else
+ * WORKSPACE with *count set, nothing written; tuples = NULL only counts).
+ * Synchronises `stream`.  Errors: INVALID_ARG (NULL, dhat < 0 or
+ * non-finite, non-finite positions), INDEX (topology ids out of range or
+ * repeated within a primitive), WORKSPACE (grid above 2^28 cells, cap), HIP.
+ */
+gipc_status gipc_candidates(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_topology* topo, double dhat,
+                            int32_t* tuples, int64_t cap, int64_t* count, void* stream);
+
 /* Lagged friction parameters (supplement Sec. 5): friction coefficient mu,
  * the velocity threshold eps_v of the transition f1 and the time step dt
  * (f1 reaches 1 at |u| = eps_v dt). */

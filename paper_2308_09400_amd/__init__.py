@@ -28,7 +28,7 @@ EXPORTS = [
     "gipc_get_info", "gipc_bsr_pattern", "gipc_barrier_eval", "gipc_assemble_bsr", "gipc_eval_assemble",
     "gipc_bsr_spmv", "gipc_pcg", "gipc_pair_inspect", "gipc_copy", "gipc_get_tune", "gipc_set_tune",
     "gipc_autotune", "gipc_graph_create", "gipc_graph_launch", "gipc_graph_destroy", "gipc_mf_apply",
-    "gipc_pcg_mf", "gipc_proxy_dense", "gipc_friction_lag", "gipc_friction_eval",
+    "gipc_pcg_mf", "gipc_proxy_dense", "gipc_friction_lag", "gipc_friction_eval", "gipc_candidates",
 ]
 
 
@@ -66,6 +66,11 @@ class Pairs(ctypes.Structure):
 class Bsr(ctypes.Structure):
     _fields_ = [("nbrows", ctypes.c_int32), ("nnzb", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
                 ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p), ("dtype", ctypes.c_int32)]
+
+
+class Topology(ctypes.Structure):
+    _fields_ = [("vobj", ctypes.c_void_p), ("tris", ctypes.c_void_p), ("F", ctypes.c_int64),
+                ("edges", ctypes.c_void_p), ("E", ctypes.c_int64)]
 
 
 class Friction(ctypes.Structure):
@@ -118,6 +123,8 @@ def lib():
             "gipc_friction_lag": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), ctypes.POINTER(Friction),
                                        vp]),
             "gipc_friction_eval": (st, [vp, vp, vp, vp, ctypes.POINTER(Bsr), vp]),
+            "gipc_candidates": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Topology), d, vp, i64,
+                                     ctypes.POINTER(i64), vp]),
             "gipc_pair_inspect": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), vp, vp, vp, vp, vp, vp, vp,
                                        vp]),
             "gipc_copy": (st, [vp, vp, i64, vp]),
@@ -355,6 +362,23 @@ def pcg(ctx: Context, A: BsrMatrix, b, x=None, rtol=1e-6, maxit=1000, stream=Non
                        ctypes.byref(rr), _stream(stream))
     ctx._check(s, "gipc_pcg")
     return x, int(it.value), float(rr.value), int(s)
+
+
+def candidates(ctx: Context, x, vobj, tris, edges, dhat, stream=None):
+    """Contact candidates (point-triangle, then edge-edge) of a surface mesh
+    on the GPU: device int32 [P][4] in the sign encoding."""
+    mesh = Context._mesh(x, None)
+    for t, name in ((vobj, "vobj"), (tris, "tris"), (edges, "edges")):
+        _need(t, torch.int32, None, name)
+    topo = Topology(_ptr(vobj), _ptr(tris), int(tris.numel() // 3), _ptr(edges), int(edges.numel() // 2))
+    n = ctypes.c_int64()
+    ctx._check(lib().gipc_candidates(ctx.h, ctypes.byref(mesh), ctypes.byref(topo), float(dhat), None, 0,
+                                     ctypes.byref(n), _stream(stream)), "gipc_candidates")
+    out = torch.empty((max(int(n.value), 0), 4), dtype=torch.int32, device=x.device)
+    if n.value > 0:
+        ctx._check(lib().gipc_candidates(ctx.h, ctypes.byref(mesh), ctypes.byref(topo), float(dhat), _ptr(out),
+                                         int(n.value), ctypes.byref(n), _stream(stream)), "gipc_candidates")
+    return out
 
 
 def friction_lag(ctx: Context, x_n, prm: Params, mu, eps_v, dt, x_rest=None, stream=None):

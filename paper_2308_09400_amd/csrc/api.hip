@@ -198,7 +198,7 @@ void gipc_ctx_destroy(gipc_ctx* ctx) {
                       &ctx->contrib, &ctx->kcol, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
                       &ctx->slot_row, &ctx->diag_slot, &ctx->maxbuf, &ctx->bigrows, &ctx->tslot, &ctx->incv, &ctx->order,
                       &ctx->obox, &ctx->ocell, &ctx->ohist, &ctx->ooff, &ctx->ofill, &ctx->rec_main, &ctx->rec_extra, &ctx->ev,
-                      &ctx->epart, &ctx->mfg, &ctx->mfab, &ctx->flag, &ctx->ffr, &ctx->fev, &ctx->fpart, &ctx->vscene, &ctx->pieces, &ctx->poff,
+                      &ctx->epart, &ctx->mfg, &ctx->mfab, &ctx->flag, &ctx->ffr, &ctx->fev, &ctx->fpart, &ctx->cpart, &ctx->ccnt, &ctx->ccount, &ctx->cfill, &ctx->coff_t, &ctx->cent_t, &ctx->coff_e, &ctx->cent_e, &ctx->qcnt, &ctx->qoff_p, &ctx->qoff_e, &ctx->vscene, &ctx->pieces, &ctx->poff,
                       &ctx->r, &ctx->z, &ctx->p, &ctx->q, &ctx->p32, &ctx->minv, &ctx->part, &ctx->scal, &ctx->scan_tmp,
                       &ctx->scan_tmp2};
     for (DevBuf* b : bufs) release(*b);
@@ -666,6 +666,126 @@ gipc_status gipc_pair_inspect(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_p
                            as<double>(ctx->rec_extra), x, xr, pm, src, type, vid, mult, energy, grad, hess,
                            S(stream)),
        "pair inspect");
+    return GIPC_OK;
+}
+
+gipc_status gipc_candidates(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_topology* topo, double dhat,
+                            int32_t* tuples, int64_t cap, int64_t* count, void* stream) {
+    if (!ctx) return GIPC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    gipc_status st;
+    if ((st = check_device(ctx)) != GIPC_OK) return st;
+    if ((st = check_mesh(ctx, mesh)) != GIPC_OK) return st;
+    if (!topo || !count) return fail(ctx, GIPC_ERR_INVALID_ARG, "topology or count is NULL");
+    if (topo->F < 0 || topo->E < 0 || topo->F >= (int64_t(1) << 31) || topo->E >= (int64_t(1) << 31))
+        return fail(ctx, GIPC_ERR_INVALID_ARG, "F and E must be in [0, 2^31)");
+    if ((topo->F > 0 && !topo->tris) || (topo->E > 0 && !topo->edges) || (mesh->V > 0 && !topo->vobj))
+        return fail(ctx, GIPC_ERR_INVALID_ARG, "topology array is NULL");
+    if (!(dhat >= 0.0) || !std::isfinite(dhat)) return fail(ctx, GIPC_ERR_INVALID_ARG, "dhat must be >= 0, finite");
+    *count = 0;
+    const int32_t V = mesh->V;
+    const int64_t F = topo->F, E = topo->E;
+    if (V == 0) return GIPC_OK;
+    hipStream_t s = S(stream);
+    const double* x = mesh->x;
+
+    // topology ids
+    CK(ensure(ctx->ccnt, sizeof(int64_t) * 2), "alloc candidates");
+    const int64_t init[2] = {0, INT64_MAX};
+    CK(hipMemcpyAsync(ctx->ccnt.p, init, sizeof(init), hipMemcpyHostToDevice, s), "copy");
+    CK(launch_cand_check(V, topo->vobj, topo->tris, F, topo->edges, E, as<int64_t>(ctx->ccnt), s), "topology check");
+    int64_t bad[2];
+    CK(hipMemcpyAsync(bad, ctx->ccnt.p, sizeof(bad), hipMemcpyDeviceToHost, s), "copy");
+    CK(hipStreamSynchronize(s), "stream synchronize");
+    if (bad[0] > 0)
+        return fail(ctx, GIPC_ERR_INDEX, "%lld primitives have vertex ids out of range or repeated (first: %lld)",
+                    (long long)bad[0], (long long)bad[1]);
+
+    // bounds and grid
+    const int32_t nb = cand_bound_blocks(V, F + E);
+    CK(ensure(ctx->cpart, sizeof(double) * 7 * (size_t)nb), "alloc candidates");
+    CK(launch_cand_bounds(x, V, topo->tris, F, topo->edges, E, as<double>(ctx->cpart), nb, s), "bounds");
+    std::vector<double> part(7 * (size_t)nb);
+    CK(hipMemcpyAsync(part.data(), ctx->cpart.p, sizeof(double) * part.size(), hipMemcpyDeviceToHost, s), "copy");
+    CK(hipStreamSynchronize(s), "stream synchronize");
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, ext = 0.0;
+    for (int32_t b = 0; b < nb; ++b) {
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = std::min(lo[d], part[7 * b + d]);
+            hi[d] = std::max(hi[d], part[7 * b + 3 + d]);
+        }
+        ext = std::max(ext, part[7 * b + 6]);
+    }
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(lo[d]) || !std::isfinite(hi[d])) return fail(ctx, GIPC_ERR_INVALID_ARG, "non-finite positions");
+    CandGrid g;
+    g.h = ext + dhat;
+    if (!(g.h > 0.0)) g.h = dhat > 0.0 ? dhat : 1.0;
+    double ncell_d = 1.0;
+    for (int d = 0; d < 3; ++d) {
+        g.org[d] = lo[d] - 4.0 * dhat;
+        const double nd = std::floor((hi[d] + dhat - g.org[d]) / g.h) + 1.0;
+        if (!(nd < 2147483647.0)) return fail(ctx, GIPC_ERR_WORKSPACE, "grid too large");
+        g.n[d] = (int32_t)std::max(1.0, nd);
+        ncell_d *= g.n[d];
+    }
+    if (ncell_d > (double)(int64_t(1) << 28))
+        return fail(ctx, GIPC_ERR_WORKSPACE,
+                    "grid of %.0f cells exceeds 2^28 (extent too large for the largest primitive plus dhat)", ncell_d);
+    const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+
+    CK(ensure(ctx->ccount, sizeof(int32_t) * (size_t)ncell), "alloc candidates");
+    CK(ensure(ctx->cfill, sizeof(int32_t) * (size_t)ncell), "alloc candidates");
+    CK(ensure(ctx->coff_t, sizeof(int64_t) * (size_t)(ncell + 1)), "alloc candidates");
+    CK(ensure(ctx->coff_e, sizeof(int64_t) * (size_t)(ncell + 1)), "alloc candidates");
+    CK(ensure(ctx->qcnt, sizeof(int32_t) * (size_t)std::max<int64_t>(V, E)), "alloc candidates");
+    CK(ensure(ctx->qoff_p, sizeof(int64_t) * (size_t)(V + 1)), "alloc candidates");
+    CK(ensure(ctx->qoff_e, sizeof(int64_t) * (size_t)(E + 1)), "alloc candidates");
+
+    // cell tables, each sized from its own count
+    int64_t nent = 0;
+    CK(launch_cell_count(ctx, x, topo->tris, 3, F, g, as<int32_t>(ctx->ccount), as<int32_t>(ctx->cfill),
+                         as<int64_t>(ctx->coff_t), s),
+       "triangle cells");
+    CK(hipMemcpyAsync(&nent, as<int64_t>(ctx->coff_t) + ncell, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
+    CK(hipStreamSynchronize(s), "stream synchronize");
+    CK(ensure(ctx->cent_t, sizeof(int32_t) * (size_t)(nent + 1)), "alloc candidates");
+    CK(launch_cell_fill(x, topo->tris, 3, F, g, as<int32_t>(ctx->cfill), as<int64_t>(ctx->coff_t),
+                        as<int32_t>(ctx->cent_t), s),
+       "triangle cells");
+    CK(launch_cand_query(0, false, x, V, topo->vobj, nullptr, topo->tris, g, dhat, as<int64_t>(ctx->coff_t),
+                         as<int32_t>(ctx->cent_t), as<int32_t>(ctx->qcnt), nullptr, nullptr, s),
+       "point-triangle count");
+    CK((exclusive_scan<int32_t, int64_t>(as<int32_t>(ctx->qcnt), V, as<int64_t>(ctx->qoff_p), ctx, s)), "scan");
+    CK(launch_cell_count(ctx, x, topo->edges, 2, E, g, as<int32_t>(ctx->ccount), as<int32_t>(ctx->cfill),
+                         as<int64_t>(ctx->coff_e), s),
+       "edge cells");
+    CK(hipMemcpyAsync(&nent, as<int64_t>(ctx->coff_e) + ncell, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
+    CK(hipStreamSynchronize(s), "stream synchronize");
+    CK(ensure(ctx->cent_e, sizeof(int32_t) * (size_t)(nent + 1)), "alloc candidates");
+    CK(launch_cell_fill(x, topo->edges, 2, E, g, as<int32_t>(ctx->cfill), as<int64_t>(ctx->coff_e),
+                        as<int32_t>(ctx->cent_e), s),
+       "edge cells");
+    CK(launch_cand_query(1, false, x, E, topo->vobj, topo->edges, topo->edges, g, dhat, as<int64_t>(ctx->coff_e),
+                         as<int32_t>(ctx->cent_e), as<int32_t>(ctx->qcnt), nullptr, nullptr, s),
+       "edge-edge count");
+    CK((exclusive_scan<int32_t, int64_t>(as<int32_t>(ctx->qcnt), E, as<int64_t>(ctx->qoff_e), ctx, s)), "scan");
+    int64_t npt = 0, nee = 0;
+    CK(hipMemcpyAsync(&npt, as<int64_t>(ctx->qoff_p) + V, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
+    CK(hipMemcpyAsync(&nee, as<int64_t>(ctx->qoff_e) + E, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
+    CK(hipStreamSynchronize(s), "stream synchronize");
+    *count = npt + nee;
+    if (!tuples) return GIPC_OK;
+    if (cap < *count)
+        return fail(ctx, GIPC_ERR_WORKSPACE, "cap = %lld is below the %lld candidates", (long long)cap,
+                    (long long)*count);
+    CK(launch_cand_query(0, true, x, V, topo->vobj, nullptr, topo->tris, g, dhat, as<int64_t>(ctx->coff_t),
+                         as<int32_t>(ctx->cent_t), nullptr, as<int64_t>(ctx->qoff_p), tuples, s),
+       "point-triangle emit");
+    CK(launch_cand_query(1, true, x, E, topo->vobj, topo->edges, topo->edges, g, dhat, as<int64_t>(ctx->coff_e),
+                         as<int32_t>(ctx->cent_e), nullptr, as<int64_t>(ctx->qoff_e), tuples + 4 * npt, s),
+       "edge-edge emit");
+    CK(hipStreamSynchronize(s), "stream synchronize");
     return GIPC_OK;
 }
 

@@ -107,6 +107,9 @@ struct gipc_ctx {
     // lagged friction: per-pair lag and eval records, energy shares and
     // pieces; the build it was lagged for and eps_v dt
     gipc::DevBuf flag, ffr, fev, fpart;
+    // contact candidates: bounds partials, counters, cell tables (points
+    // against triangles, edges against edges), per-query counts and offsets
+    gipc::DevBuf cpart, ccnt, ccount, cfill, coff_t, cent_t, coff_e, cent_e, qcnt, qoff_p, qoff_e;
     uint64_t fric_gen = 0;
     double fric_sv = 0.0;
     uint64_t eval_gen = 0;   // bumped by every eval
@@ -242,6 +245,31 @@ hipError_t launch_fric_eval(int32_t V, const int4* st_vid, const TypeRanges& tr,
                             double sv, double* fr, const int32_t* row_ptr, const int32_t* diag_slot,
                             const int64_t* cptr, const uint32_t* contrib, double* grad, double* ev, void* val,
                             int dtype, int64_t nnzb, hipStream_t s);
+
+// contact candidates (candidates.hip)
+struct CandGrid {
+    double org[3];
+    double h;
+    int32_t n[3];
+};
+int32_t cand_bound_blocks(int64_t V, int64_t FE);
+// part [nb][7]: min x y z, max x y z, largest primitive extent
+hipError_t launch_cand_bounds(const double* x, int32_t V, const int32_t* tris, int64_t F, const int32_t* edges,
+                              int64_t E, double* part, int32_t nb, hipStream_t s);
+hipError_t launch_cand_check(int32_t V, const int32_t* vobj, const int32_t* tris, int64_t F, const int32_t* edges,
+                             int64_t E, int64_t* counters, hipStream_t s);
+// cell table of n primitives of nper vertices: counts and offsets off
+// [ncell+1] (off[ncell] = entries), then the entries ent [off[ncell]]
+hipError_t launch_cell_count(gipc_ctx* ctx, const double* x, const int32_t* prims, int nper, int64_t n,
+                             const CandGrid& g, int32_t* count, int32_t* fill, int64_t* off, hipStream_t s);
+hipError_t launch_cell_fill(const double* x, const int32_t* prims, int nper, int64_t n, const CandGrid& g,
+                            int32_t* fill, const int64_t* off, int32_t* ent, hipStream_t s);
+// kind 0: points vs triangles, 1: edges vs edges; counts into cnt, or emits
+// int32 [4] tuples at out + 4 qoff[q]
+hipError_t launch_cand_query(int kind, bool emit, const double* x, int64_t nq, const int32_t* vobj,
+                             const int32_t* qprims, const int32_t* tprims, const CandGrid& g, double dhat,
+                             const int64_t* coff, const int32_t* cent, int32_t* cnt, const int64_t* qoff,
+                             int32_t* out, hipStream_t s);
 
 // ---- solve.hip
 hipError_t launch_spmv(const gipc_bsr& A, const void* x, void* y, hipStream_t s);
