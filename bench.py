@@ -34,11 +34,13 @@ product each; the PCG of the step both ways), reported under
 `matrix_free`; the default workload also times the dense projected proxy
 Hessians of all staged pairs from the analytic eigensystems against the
 numeric baseline (x-space Jacobi projection), under `numeric_eigen_baseline`,
-and the lagged friction on the same pairs under `friction`.
+the lagged friction on the same pairs under `friction`, and the GPU contact
+candidates of the scene's surfaces under `candidates`.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -233,6 +235,36 @@ def friction_compare(gp, ctx, x, xr, prm, diag, info, stream):
     del A
     return {"pairs": int(info["n_staged"]), "lag_ms": t_lag, "eval_ms": t_eval, "eval_add_blocks_ms": t_asm,
             "barrier_eval_ms": t_bar, "barrier_eval_assemble_ms": t_bar_asm}
+
+
+def candidates_compare(gp, ctx, s, x, stream):
+    """Contact candidates of the scene's surfaces on the GPU (count + emit in
+    one call, capacity known), next to the host grid generator that made the
+    bench's input list (same set; its time on the host's threads)."""
+    import torch
+    import scenes
+    dev = x.device
+    vobj = torch.tensor(s.vobj, dtype=torch.int32, device=dev)
+    tris = torch.tensor(s.tris, dtype=torch.int32, device=dev)
+    edges = torch.tensor(s.edges, dtype=torch.int32, device=dev)
+    out = gp.candidates(ctx, x, vobj, tris, edges, s.dhat)
+    n = int(out.shape[0])
+    mesh = gp.Context._mesh(x, None)
+    topo = gp.Topology(vobj.data_ptr(), tris.data_ptr(), int(tris.shape[0]), edges.data_ptr(), int(edges.shape[0]))
+    cnt = ctypes.c_int64()
+
+    def run():
+        gp.lib().gipc_candidates(ctx.h, ctypes.byref(mesh), ctypes.byref(topo),
+                                 float(s.dhat), ctypes.c_void_p(out.data_ptr()), n,
+                                 ctypes.byref(cnt), gp._stream(None))
+    t_gpu = _median_ms(run, 3, stream)
+    t0 = time.perf_counter()
+    host = scenes.broadphase(s.x, s.vobj, s.tris, s.edges, s.dhat)
+    t_host = (time.perf_counter() - t0) * 1e3
+    del out
+    return {"candidates": n, "same_count_as_host": int(len(host)) == n, "gpu_ms": t_gpu,
+            "gpu_candidates_per_s": n / (t_gpu * 1e-3), "host_grid_ms": t_host, "host_threads": os.cpu_count(),
+            "triangles": int(s.tris.shape[0]), "edges": int(s.edges.shape[0])}
 
 
 def _median_ms(fn, reps, stream):
@@ -529,6 +561,7 @@ def main():
     if args.workload == "sheets10":
         out["numeric_eigen_baseline"] = numeric_compare(gp, ctx, x, xr, prm, info, stream)
         out["friction"] = friction_compare(gp, ctx, x, xr, prm, diag, info, stream)
+        out["candidates"] = candidates_compare(gp, ctx, s, x, stream)
     ctx.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_sample)

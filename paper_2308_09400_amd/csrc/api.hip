@@ -198,7 +198,7 @@ void gipc_ctx_destroy(gipc_ctx* ctx) {
                       &ctx->contrib, &ctx->kcol, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
                       &ctx->slot_row, &ctx->diag_slot, &ctx->maxbuf, &ctx->bigrows, &ctx->tslot, &ctx->incv, &ctx->order,
                       &ctx->obox, &ctx->ocell, &ctx->ohist, &ctx->ooff, &ctx->ofill, &ctx->rec_main, &ctx->rec_extra, &ctx->ev,
-                      &ctx->epart, &ctx->mfg, &ctx->mfab, &ctx->flag, &ctx->ffr, &ctx->fev, &ctx->fpart, &ctx->cpart, &ctx->ccnt, &ctx->ccount, &ctx->cfill, &ctx->coff_t, &ctx->cent_t, &ctx->coff_e, &ctx->cent_e, &ctx->qcnt, &ctx->qoff_p, &ctx->qoff_e, &ctx->vscene, &ctx->pieces, &ctx->poff,
+                      &ctx->epart, &ctx->mfg, &ctx->mfab, &ctx->flag, &ctx->ffr, &ctx->fev, &ctx->fpart, &ctx->cpart, &ctx->ccnt, &ctx->ccount, &ctx->cfill, &ctx->coff_t, &ctx->cent_t, &ctx->coff_e, &ctx->cent_e, &ctx->qcnt, &ctx->qoff_p, &ctx->qoff_e, &ctx->crec_t, &ctx->crec_e, &ctx->vscene, &ctx->pieces, &ctx->poff,
                       &ctx->r, &ctx->z, &ctx->p, &ctx->q, &ctx->p32, &ctx->minv, &ctx->part, &ctx->scal, &ctx->scan_tmp,
                       &ctx->scan_tmp2};
     for (DevBuf* b : bufs) release(*b);
@@ -703,28 +703,31 @@ gipc_status gipc_candidates(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_top
 
     // bounds and grid
     const int32_t nb = cand_bound_blocks(V, F + E);
-    CK(ensure(ctx->cpart, sizeof(double) * 7 * (size_t)nb), "alloc candidates");
+    CK(ensure(ctx->cpart, sizeof(double) * 9 * (size_t)nb), "alloc candidates");
     CK(launch_cand_bounds(x, V, topo->tris, F, topo->edges, E, as<double>(ctx->cpart), nb, s), "bounds");
-    std::vector<double> part(7 * (size_t)nb);
+    std::vector<double> part(9 * (size_t)nb);
     CK(hipMemcpyAsync(part.data(), ctx->cpart.p, sizeof(double) * part.size(), hipMemcpyDeviceToHost, s), "copy");
     CK(hipStreamSynchronize(s), "stream synchronize");
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, ext = 0.0;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, ext[3] = {0, 0, 0};
     for (int32_t b = 0; b < nb; ++b) {
         for (int d = 0; d < 3; ++d) {
-            lo[d] = std::min(lo[d], part[7 * b + d]);
-            hi[d] = std::max(hi[d], part[7 * b + 3 + d]);
+            lo[d] = std::min(lo[d], part[9 * b + d]);
+            hi[d] = std::max(hi[d], part[9 * b + 3 + d]);
+            ext[d] = std::max(ext[d], part[9 * b + 6 + d]);
         }
-        ext = std::max(ext, part[7 * b + 6]);
     }
     for (int d = 0; d < 3; ++d)
         if (!std::isfinite(lo[d]) || !std::isfinite(hi[d])) return fail(ctx, GIPC_ERR_INVALID_ARG, "non-finite positions");
+    // per axis: the largest extent plus dhat (at least a thousandth of the
+    // largest one, so flat meshes do not make empty slivers of cells)
     CandGrid g;
-    g.h = ext + dhat;
-    if (!(g.h > 0.0)) g.h = dhat > 0.0 ? dhat : 1.0;
+    const double hmax = std::max(ext[0], std::max(ext[1], ext[2])) + dhat;
     double ncell_d = 1.0;
     for (int d = 0; d < 3; ++d) {
+        g.h[d] = std::max(ext[d] + dhat, 1e-3 * hmax);
+        if (!(g.h[d] > 0.0)) g.h[d] = 1.0;
         g.org[d] = lo[d] - 4.0 * dhat;
-        const double nd = std::floor((hi[d] + dhat - g.org[d]) / g.h) + 1.0;
+        const double nd = std::floor((hi[d] + dhat - g.org[d]) / g.h[d]) + 1.0;
         if (!(nd < 2147483647.0)) return fail(ctx, GIPC_ERR_WORKSPACE, "grid too large");
         g.n[d] = (int32_t)std::max(1.0, nd);
         ncell_d *= g.n[d];
@@ -742,6 +745,10 @@ gipc_status gipc_candidates(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_top
     CK(ensure(ctx->qoff_p, sizeof(int64_t) * (size_t)(V + 1)), "alloc candidates");
     CK(ensure(ctx->qoff_e, sizeof(int64_t) * (size_t)(E + 1)), "alloc candidates");
 
+    CK(ensure(ctx->crec_t, (size_t)kPrimRecBytes * (size_t)(F > 0 ? F : 1)), "alloc candidates");
+    CK(ensure(ctx->crec_e, (size_t)kPrimRecBytes * (size_t)(E > 0 ? E : 1)), "alloc candidates");
+    CK(launch_prim_records(x, topo->tris, 3, F, topo->vobj, ctx->crec_t.p, s), "triangle records");
+    CK(launch_prim_records(x, topo->edges, 2, E, topo->vobj, ctx->crec_e.p, s), "edge records");
     // cell tables, each sized from its own count
     int64_t nent = 0;
     CK(launch_cell_count(ctx, x, topo->tris, 3, F, g, as<int32_t>(ctx->ccount), as<int32_t>(ctx->cfill),
@@ -753,7 +760,7 @@ gipc_status gipc_candidates(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_top
     CK(launch_cell_fill(x, topo->tris, 3, F, g, as<int32_t>(ctx->cfill), as<int64_t>(ctx->coff_t),
                         as<int32_t>(ctx->cent_t), s),
        "triangle cells");
-    CK(launch_cand_query(0, false, x, V, topo->vobj, nullptr, topo->tris, g, dhat, as<int64_t>(ctx->coff_t),
+    CK(launch_cand_query(0, false, x, V, topo->vobj, nullptr, ctx->crec_t.p, g, dhat, as<int64_t>(ctx->coff_t),
                          as<int32_t>(ctx->cent_t), as<int32_t>(ctx->qcnt), nullptr, nullptr, s),
        "point-triangle count");
     CK((exclusive_scan<int32_t, int64_t>(as<int32_t>(ctx->qcnt), V, as<int64_t>(ctx->qoff_p), ctx, s)), "scan");
@@ -766,7 +773,7 @@ gipc_status gipc_candidates(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_top
     CK(launch_cell_fill(x, topo->edges, 2, E, g, as<int32_t>(ctx->cfill), as<int64_t>(ctx->coff_e),
                         as<int32_t>(ctx->cent_e), s),
        "edge cells");
-    CK(launch_cand_query(1, false, x, E, topo->vobj, topo->edges, topo->edges, g, dhat, as<int64_t>(ctx->coff_e),
+    CK(launch_cand_query(1, false, x, E, topo->vobj, ctx->crec_e.p, ctx->crec_e.p, g, dhat, as<int64_t>(ctx->coff_e),
                          as<int32_t>(ctx->cent_e), as<int32_t>(ctx->qcnt), nullptr, nullptr, s),
        "edge-edge count");
     CK((exclusive_scan<int32_t, int64_t>(as<int32_t>(ctx->qcnt), E, as<int64_t>(ctx->qoff_e), ctx, s)), "scan");
@@ -779,10 +786,10 @@ gipc_status gipc_candidates(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_top
     if (cap < *count)
         return fail(ctx, GIPC_ERR_WORKSPACE, "cap = %lld is below the %lld candidates", (long long)cap,
                     (long long)*count);
-    CK(launch_cand_query(0, true, x, V, topo->vobj, nullptr, topo->tris, g, dhat, as<int64_t>(ctx->coff_t),
+    CK(launch_cand_query(0, true, x, V, topo->vobj, nullptr, ctx->crec_t.p, g, dhat, as<int64_t>(ctx->coff_t),
                          as<int32_t>(ctx->cent_t), nullptr, as<int64_t>(ctx->qoff_p), tuples, s),
        "point-triangle emit");
-    CK(launch_cand_query(1, true, x, E, topo->vobj, topo->edges, topo->edges, g, dhat, as<int64_t>(ctx->coff_e),
+    CK(launch_cand_query(1, true, x, E, topo->vobj, ctx->crec_e.p, ctx->crec_e.p, g, dhat, as<int64_t>(ctx->coff_e),
                          as<int32_t>(ctx->cent_e), nullptr, as<int64_t>(ctx->qoff_e), tuples + 4 * npt, s),
        "edge-edge emit");
     CK(hipStreamSynchronize(s), "stream synchronize");

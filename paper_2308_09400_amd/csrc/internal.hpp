@@ -109,7 +109,7 @@ struct gipc_ctx {
     gipc::DevBuf flag, ffr, fev, fpart;
     // contact candidates: bounds partials, counters, cell tables (points
     // against triangles, edges against edges), per-query counts and offsets
-    gipc::DevBuf cpart, ccnt, ccount, cfill, coff_t, cent_t, coff_e, cent_e, qcnt, qoff_p, qoff_e;
+    gipc::DevBuf cpart, ccnt, ccount, cfill, coff_t, cent_t, coff_e, cent_e, qcnt, qoff_p, qoff_e, crec_t, crec_e;
     uint64_t fric_gen = 0;
     double fric_sv = 0.0;
     uint64_t eval_gen = 0;   // bumped by every eval
@@ -249,11 +249,11 @@ hipError_t launch_fric_eval(int32_t V, const int4* st_vid, const TypeRanges& tr,
 // contact candidates (candidates.hip)
 struct CandGrid {
     double org[3];
-    double h;
+    double h[3];
     int32_t n[3];
 };
 int32_t cand_bound_blocks(int64_t V, int64_t FE);
-// part [nb][7]: min x y z, max x y z, largest primitive extent
+// part [nb][9]: min x y z, max x y z, largest primitive extent along x y z
 hipError_t launch_cand_bounds(const double* x, int32_t V, const int32_t* tris, int64_t F, const int32_t* edges,
                               int64_t E, double* part, int32_t nb, hipStream_t s);
 hipError_t launch_cand_check(int32_t V, const int32_t* vobj, const int32_t* tris, int64_t F, const int32_t* edges,
@@ -264,10 +264,14 @@ hipError_t launch_cell_count(gipc_ctx* ctx, const double* x, const int32_t* prim
                              const CandGrid& g, int32_t* count, int32_t* fill, int64_t* off, hipStream_t s);
 hipError_t launch_cell_fill(const double* x, const int32_t* prims, int nper, int64_t n, const CandGrid& g,
                             int32_t* fill, const int64_t* off, int32_t* ent, hipStream_t s);
-// kind 0: points vs triangles, 1: edges vs edges; counts into cnt, or emits
-// int32 [4] tuples at out + 4 qoff[q]
+// 64-byte query records of n primitives (box, vertex ids, object)
+constexpr int kPrimRecBytes = 64;
+hipError_t launch_prim_records(const double* x, const int32_t* prims, int nper, int64_t n, const int32_t* vobj,
+                               void* rec, hipStream_t s);
+// kind 0: points vs triangle records, 1: edge records vs edge records;
+// counts into cnt, or emits int32 [4] tuples at out + 4 qoff[q]
 hipError_t launch_cand_query(int kind, bool emit, const double* x, int64_t nq, const int32_t* vobj,
-                             const int32_t* qprims, const int32_t* tprims, const CandGrid& g, double dhat,
+                             const void* qrec, const void* trec, const CandGrid& g, double dhat,
                              const int64_t* coff, const int32_t* cent, int32_t* cnt, const int64_t* qoff,
                              int32_t* out, hipStream_t s);
 
