@@ -63,6 +63,33 @@ __device__ __forceinline__ uint64_t home(const Key& k, unsigned long long f, dou
 // slower); both passes walk the same sequence, so they agree.
 constexpr int kMaxProbe = 4096;
 
+// Lanes of a wavefront carrying the same key (same kind) form a group; its
+// leader is its lowest lane, which holds the group's smallest staged index.
+// Only leaders touch the table.  The loop runs once per distinct key of the
+// wavefront (the mask of pending lanes is the same in every lane).
+struct Group {
+    int leader;                  // lane of this lane's leader (-1 if not in)
+    unsigned long long members;  // lanes of this lane's group
+};
+
+__device__ __forceinline__ Group wave_group(const Key& key, bool pp, bool in) {
+    Group g{-1, 0ull};
+    unsigned long long pending = __ballot(in);
+    while (pending) {
+        const int l = __ffsll((long long)pending) - 1;
+        const int ka = __shfl(key.a, l, 64), kb = __shfl(key.b, l, 64), kc = __shfl(key.c, l, 64);
+        const int kp = __shfl((int)pp, l, 64);
+        const bool same = in && key.a == ka && key.b == kb && key.c == kc && (int)pp == kp;
+        const unsigned long long grp = __ballot(same);
+        if (same) {
+            g.leader = l;
+            g.members = grp;
+        }
+        pending &= ~grp;
+    }
+    return g;
+}
+
 // pairs [k0, k1) are PE then PP from pp0 on
 __global__ void __launch_bounds__(kBlock) k_merge_insert(const int4* __restrict__ st_vid, int64_t k0, int64_t k1,
                                                          int64_t pp0, unsigned long long* __restrict__ table,
@@ -71,12 +98,9 @@ __global__ void __launch_bounds__(kBlock) k_merge_insert(const int4* __restrict_
     const bool in = k < k1;
     const bool pp = k >= pp0;
     const Key key = in ? canon(pp, st_vid[k]) : Key{-1, -1, -1};
-    // a lane whose left neighbour holds the same key (same kind) leaves the
-    // insert to the head of that run, which has the smaller index
-    const int lane = threadIdx.x & 63;
-    const int pa = __shfl_up(key.a, 1, 64), pb = __shfl_up(key.b, 1, 64), pc = __shfl_up(key.c, 1, 64);
-    const int ppp = __shfl_up((int)pp, 1, 64);
-    if (!in || (lane > 0 && pa == key.a && pb == key.b && pc == key.c && ppp == (int)pp)) return;
+    // only the leader of each group of equal keys in the wavefront inserts
+    const Group grp = wave_group(key, pp, in);
+    if (!in || grp.leader != (int)(threadIdx.x & 63)) return;
     const unsigned long long f = fingerprint(key);
     const unsigned long long word = f | (unsigned long long)k;
     uint64_t h = home(key, f, scale, mask);
@@ -96,28 +120,36 @@ __global__ void __launch_bounds__(kBlock) k_merge_resolve(const int4* __restrict
                                                           double scale, uint64_t mask, int32_t* __restrict__ rep_of,
                                                           int32_t* __restrict__ mult) {
     const int64_t k = k0 + (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= k1) return;
+    const bool in = k < k1;
     const bool pp = k >= pp0;
-    const Key me = canon(pp, st_vid[k]);
-    const unsigned long long f = fingerprint(me);
-    uint64_t h = home(me, f, scale, mask);
+    const Key me = in ? canon(pp, st_vid[k]) : Key{-1, -1, -1};
+    const Group grp = wave_group(me, pp, in);
+    const int lane = threadIdx.x & 63;
+    // the leader finds the representative of the group's key; a group whose
+    // key is in no slot (probe bound) takes its leader
     int32_t my = (int32_t)k;
-    for (int t = 0; t < kMaxProbe; ++t) {
-        const unsigned long long w = table[h];
-        if ((w & ~kRepMask) == f) {
-            const int32_t r = (int32_t)(w & kRepMask);
-            if (r != (int32_t)k) {  // another pair is the representative: compare full keys
-                const bool rpp = r >= pp0;
-                const Key o = canon(rpp, st_vid[r]);
-                if (rpp == pp && o.a == me.a && o.b == me.b && o.c == me.c) my = r;
+    if (in && grp.leader == lane) {
+        const unsigned long long f = fingerprint(me);
+        uint64_t h = home(me, f, scale, mask);
+        for (int t = 0; t < kMaxProbe; ++t) {
+            const unsigned long long w = table[h];
+            if ((w & ~kRepMask) == f) {
+                const int32_t r = (int32_t)(w & kRepMask);
+                if (r != (int32_t)k) {  // another pair is the representative: compare full keys
+                    const bool rpp = r >= pp0;
+                    const Key o = canon(rpp, st_vid[r]);
+                    if (rpp == pp && o.a == me.a && o.b == me.b && o.c == me.c) my = r;
+                }
+                break;
             }
-            break;
+            if (w == 0ull) break;  // not inserted (probe bound reached on insert)
+            h = (h + 1) & mask;
         }
-        if (w == 0ull) break;  // not inserted (probe bound reached on insert)
-        h = (h + 1) & mask;
     }
-    rep_of[k - k0] = my;
-    atomicAdd(&mult[my - k0], 1);
+    const int32_t rep = __shfl(my, grp.leader < 0 ? lane : grp.leader, 64);
+    if (!in) return;
+    rep_of[k - k0] = rep;
+    if (grp.leader == lane) atomicAdd(&mult[rep - k0], __popcll(grp.members));
 }
 
 __global__ void __launch_bounds__(kBlock) k_merge_flags(int64_t Ps, int64_t k0, int64_t k1,
