@@ -20,29 +20,30 @@
 namespace gipc {
 namespace {
 
-// Runs of equal keys in consecutive lanes share one atomic: the run head
-// (found with a wave ballot) adds the run length, and the members take
-// consecutive positions after the head's old value.  Staged pairs are sorted
-// by type and then by their first vertex, so slot-0 runs are long.
-struct WaveRun {
-    int head;  // lane of this lane's run head
-    int len;   // run length (valid in the head lane)
+// Lanes of the wavefront with equal keys (key, key2) form a group led by its
+// lowest lane, wherever they sit in the wavefront: one atomic per group
+// instead of one per lane.  The loop runs once per distinct key (the
+// pending mask is the same in every lane).
+struct WaveGroup {
+    int leader;                  // -1 for lanes not in
+    unsigned long long members;  // the group's lanes
 };
 
-__device__ __forceinline__ WaveRun wave_run(int key, int key2, bool valid) {
-    const int lane = threadIdx.x & 63;
-    const int prev = __shfl_up(key, 1, 64);
-    const int prev2 = __shfl_up(key2, 1, 64);
-    const int prev_ok = __shfl_up((int)valid, 1, 64);
-    const bool head = valid && (lane == 0 || !prev_ok || prev != key || prev2 != key2);
-    const unsigned long long heads = __ballot(head);
-    const unsigned long long le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-    WaveRun w;
-    w.head = 63 - __clzll(heads & le);
-    // a run ends at the next head or at the first invalid lane
-    const unsigned long long stop = (heads | ~__ballot(valid)) & ~le;
-    w.len = (stop ? __ffsll((long long)stop) - 1 : 64) - lane;
-    return w;
+__device__ __forceinline__ WaveGroup wave_group(int key, int key2, bool in) {
+    WaveGroup g{-1, 0ull};
+    unsigned long long pending = __ballot(in);
+    while (pending) {
+        const int l = __ffsll((long long)pending) - 1;
+        const int a = __shfl(key, l, 64), b = __shfl(key2, l, 64);
+        const bool same = in && key == a && key2 == b;
+        const unsigned long long grp = __ballot(same);
+        if (same) {
+            g.leader = l;
+            g.members = grp;
+        }
+        pending &= ~grp;
+    }
+    return g;
 }
 
 __global__ void __launch_bounds__(kBlock) k_sym_count(const int4* __restrict__ st_vid, TypeRanges tr,
@@ -56,10 +57,11 @@ __global__ void __launch_bounds__(kBlock) k_sym_count(const int4* __restrict__ s
     for (int i = 0; i < 4; ++i) {
         const int vi = vslot(v, i);
         const bool valid = i < nv;
-        WaveRun w = wave_run(valid ? vi : -1, nv, valid);
-        if (valid && w.head == lane) {
-            atomicAdd(&deg[vi], w.len);
-            atomicAdd(&kcount[vi], w.len * nv);
+        const WaveGroup g = wave_group(valid ? vi : -1, nv, valid);
+        if (valid && g.leader == lane) {
+            const int n = __popcll(g.members);
+            atomicAdd(&deg[vi], n);
+            atomicAdd(&kcount[vi], n * nv);
         }
     }
 }
@@ -79,12 +81,13 @@ __global__ void __launch_bounds__(kBlock) k_sym_scatter(const int4* __restrict__
     for (int i = 0; i < 4; ++i) {
         const int vi = vslot(v, i);
         const bool valid = i < nv;
-        WaveRun w = wave_run(valid ? vi : -1, 0, valid);
+        const WaveGroup g = wave_group(valid ? vi : -1, 0, valid);
         int base = 0;
-        if (valid && w.head == lane) base = atomicAdd(&fill[vi], w.len);
-        base = __shfl(base, valid ? w.head : lane, 64);
+        if (valid && g.leader == lane) base = atomicAdd(&fill[vi], __popcll(g.members));
+        base = __shfl(base, valid ? g.leader : lane, 64);
         if (valid) {
-            const int64_t at = inc_ptr[vi] + base + (lane - w.head);
+            const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+            const int64_t at = inc_ptr[vi] + base + __popcll(g.members & below);
             inc[at] = ((uint32_t)k << 2) | (uint32_t)i;
             incv[at] = v;
         }
