@@ -151,9 +151,44 @@ __device__ void rowsort_lds(int r, const int64_t* __restrict__ inc_ptr, const ui
     if (threadIdx.x == 0) ncols[r] = cnt;
 }
 
-__device__ __forceinline__ unsigned long long shfl_xor64(unsigned long long v, int m) {
-    const int lo = __shfl_xor((int)(uint32_t)v, m, 64), hi = __shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+// value of lane (lane ^ D) for a compile-time lane distance D.  Distances 1
+// and 2 are DPP quad permutations and 4 and 8 two DPP row shifts (lane
+// i <- i + D and i <- i - D within its row of 16, picked by bit D of the
+// lane), all plain VALU moves; 16 is an LDS swizzle in bitmask mode (no
+// memory access); 32 goes through ds_bpermute.  The sort network is bound
+// by these exchanges, and the crossbar form of all of them was its limit.
+template <int D>
+__device__ __forceinline__ int xor_lanes32(int v) {
+    if constexpr (D == 1) {
+        return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    } else if constexpr (D == 2) {
+        return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    } else if constexpr (D == 4 || D == 8) {
+        const int up = __builtin_amdgcn_mov_dpp(v, 0x100 + D, 0xF, 0xF, false);  // row_shl:D
+        const int dn = __builtin_amdgcn_mov_dpp(v, 0x110 + D, 0xF, 0xF, false);  // row_shr:D
+        return (__lane_id() & D) ? dn : up;
+    } else if constexpr (D == 16) {
+        return __builtin_amdgcn_ds_swizzle(v, 0x401F);  // and 0x1f, or 0, xor 16
+    } else {
+        return __shfl_xor(v, D, 64);
+    }
+}
+
+template <int D>
+__device__ __forceinline__ unsigned long long xor_lanes64(unsigned long long v) {
+    const int lo = xor_lanes32<D>((int)(uint32_t)v), hi = xor_lanes32<D>((int)(uint32_t)(v >> 32));
     return ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+__device__ __forceinline__ unsigned long long xor_lanes64(unsigned long long v, int d) {
+    switch (d) {  // d is a constant once the network is unrolled
+        case 1: return xor_lanes64<1>(v);
+        case 2: return xor_lanes64<2>(v);
+        case 4: return xor_lanes64<4>(v);
+        case 8: return xor_lanes64<8>(v);
+        case 16: return xor_lanes64<16>(v);
+        default: return xor_lanes64<32>(v);
+    }
 }
 
 __device__ __forceinline__ unsigned long long shfl_up64(unsigned long long v, int d) {
@@ -215,7 +250,7 @@ __device__ __forceinline__ void rowsort_regs(int64_t r, int n, int64_t start, co
 #pragma unroll
                 for (int q = 0; q < M; ++q) {
                     const int e = M * lane + q;
-                    const unsigned long long o = shfl_xor64(key[q], j / M);
+                    const unsigned long long o = xor_lanes64(key[q], j / M);
                     // this element keeps the smaller key iff it is the lower
                     // one of an ascending pair or the upper one of a descending
                     const bool take_min = ((e & kk) == 0) == ((e & j) == 0);
