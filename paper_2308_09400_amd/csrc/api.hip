@@ -197,7 +197,7 @@ void gipc_ctx_destroy(gipc_ctx* ctx) {
                       &ctx->mflag, &ctx->mpos, &ctx->st_vid2, &ctx->st_src2, &ctx->deg, &ctx->kcount, &ctx->fill, &ctx->inc_ptr, &ctx->kptr, &ctx->inc,
                       &ctx->contrib, &ctx->kcol, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
                       &ctx->slot_row, &ctx->diag_slot, &ctx->maxbuf, &ctx->bigrows, &ctx->tslot, &ctx->incv, &ctx->order,
-                      &ctx->obox, &ctx->ocell, &ctx->ohist, &ctx->ooff, &ctx->ofill, &ctx->rec_main, &ctx->rec_extra, &ctx->ev,
+                      &ctx->obox, &ctx->ocell, &ctx->ohist, &ctx->ooff, &ctx->ofill, &ctx->rec_main, &ctx->rec_extra, &ctx->rec_a1, &ctx->ev,
                       &ctx->epart, &ctx->mfg, &ctx->mfab, &ctx->flag, &ctx->ffr, &ctx->fev, &ctx->fpart, &ctx->cpart, &ctx->ccnt, &ctx->ccount, &ctx->cfill, &ctx->coff_t, &ctx->cent_t, &ctx->coff_e, &ctx->cent_e, &ctx->qcnt, &ctx->qoff_p, &ctx->qoff_e, &ctx->crec_t, &ctx->crec_e, &ctx->vscene, &ctx->pieces, &ctx->poff,
                       &ctx->r, &ctx->z, &ctx->p, &ctx->q, &ctx->p32, &ctx->minv, &ctx->part, &ctx->scal, &ctx->scan_tmp,
                       &ctx->scan_tmp2};
@@ -454,7 +454,8 @@ gipc_status eval_prepare(gipc_ctx* ctx) {
     const TypeRanges& tr = ctx->ranges;
     const int64_t Ps = ctx->Ps, Pm = tr.off[8] - tr.off[FT_EEM];
     CK(ensure(ctx->rec_main, sizeof(double) * 8 * (size_t)Ps), "alloc factors");
-    CK(ensure(ctx->rec_extra, sizeof(double) * 9 * (size_t)Pm), "alloc factors");
+    CK(ensure(ctx->rec_extra, sizeof(double) * 8 * (size_t)Pm), "alloc factors");
+    CK(ensure(ctx->rec_a1, sizeof(double) * (size_t)Pm), "alloc factors");
     CK(ensure(ctx->ev, sizeof(double) * (size_t)(ctx->V > 0 ? ctx->V : 1)), "alloc energy shares");
     CK(ensure(ctx->epart, sizeof(double) * (size_t)(ctx->npieces > 0 ? ctx->npieces : 1)), "alloc energy pieces");
     return GIPC_OK;
@@ -468,10 +469,10 @@ hipError_t eval_enqueue(gipc_ctx* ctx, const DevParams& pm, const gipc_mesh* mes
     const int64_t m0 = tr.off[FT_EEM], e0 = tr.off[FT_EE];
     const int32_t* mult = ctx->merged ? as<int32_t>(ctx->mult) : nullptr;
     hipError_t e = launch_eval(as<int4>(ctx->st_vid), mult, tr, mesh->x, xr, pm, as<double>(ctx->rec_main),
-                               as<double>(ctx->rec_extra), t.eval_waves, s);
+                               as<double>(ctx->rec_extra), as<double>(ctx->rec_a1), t.eval_waves, s);
     if (e != hipSuccess) return e;
     e = launch_rows_diag(assemble ? 3 : 1, ctx->V, as<int32_t>(ctx->order), as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr),
-                         as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra), e0, m0,
+                         as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra), as<double>(ctx->rec_a1), e0, m0,
                          diag, grad, as<double>(ctx->ev), assemble ? A->val : nullptr, assemble ? A->dtype : 0,
                          ctx->nnzb, t.row_lanes, s);
     if (e != hipSuccess) return e;
@@ -530,7 +531,7 @@ gipc_status gipc_assemble_bsr(gipc_ctx* ctx, const double* diag, const gipc_bsr*
     hipStream_t s = S(stream);
     const int64_t m0 = ctx->ranges.off[FT_EEM], e0 = ctx->ranges.off[FT_EE];
     CK(launch_rows_diag(2, ctx->V, as<int32_t>(ctx->order), as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr), as<uint32_t>(ctx->contrib),
-                        as<double>(ctx->rec_main), as<double>(ctx->rec_extra), e0, m0, diag, nullptr, nullptr, A->val,
+                        as<double>(ctx->rec_main), as<double>(ctx->rec_extra), as<double>(ctx->rec_a1), e0, m0, diag, nullptr, nullptr, A->val,
                         A->dtype, ctx->nnzb, ctx->tune.row_lanes, s),
        "diagonal blocks");
     CK(launch_offdiag(ctx->V, as<int32_t>(ctx->order), as<int32_t>(ctx->row_ptr), as<int32_t>(ctx->diag_slot),
@@ -663,7 +664,7 @@ gipc_status gipc_pair_inspect(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_p
     }
     CK(launch_pair_inspect(as<int4>(ctx->st_vid), as<int32_t>(ctx->st_src),
                            ctx->merged ? as<int32_t>(ctx->mult) : nullptr, ctx->ranges, as<double>(ctx->rec_main),
-                           as<double>(ctx->rec_extra), x, xr, pm, src, type, vid, mult, energy, grad, hess,
+                           as<double>(ctx->rec_extra), as<double>(ctx->rec_a1), x, xr, pm, src, type, vid, mult, energy, grad, hess,
                            S(stream)),
        "pair inspect");
     return GIPC_OK;
@@ -938,7 +939,8 @@ gipc_status gipc_autotune(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_param
     for (int w : waves) {
         float ms = time_it([&] {
             return launch_eval(as<int4>(ctx->st_vid), ctx->merged ? as<int32_t>(ctx->mult) : nullptr, tr, mesh->x,
-                               xr, pm, as<double>(ctx->rec_main), as<double>(ctx->rec_extra), w, s);
+                               xr, pm, as<double>(ctx->rec_main), as<double>(ctx->rec_extra),
+                               as<double>(ctx->rec_a1), w, s);
         });
         if (ms < bt) { bt = ms; t.eval_waves = w; }
     }
@@ -946,7 +948,7 @@ gipc_status gipc_autotune(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_param
     for (int l : lanes) {
         float ms = time_it([&] {
             return launch_rows_diag(3, ctx->V, as<int32_t>(ctx->order), as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr),
-                                    as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra),
+                                    as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra), as<double>(ctx->rec_a1),
                                     e0, m0, diag, grad, as<double>(ctx->ev), A->val, A->dtype, ctx->nnzb, l, s);
         });
         if (ms < bt) { bt = ms; t.row_lanes = l; }

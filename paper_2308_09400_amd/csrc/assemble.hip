@@ -34,7 +34,7 @@ __device__ __forceinline__ void add_block(double* B, const double* __restrict__ 
     d3 gi = rec_coef(m, i, ee) * wt, gj = rec_coef(m, j, ee) * wt;
     add_outer(B, m[R_P22], gi, gj);
     if ((int64_t)k >= m0) {
-        const double* x = rec_extra + 9 * ((int64_t)k - m0);
+        const double* x = rec_extra + 8 * ((int64_t)k - m0);
         d3 si = sq_slot(x, i), sj = sq_slot(x, j);
         add_outer(B, x[6], si, sj);
         add_outer(B, x[7], si, gj);
@@ -54,7 +54,8 @@ __device__ __forceinline__ MainRec load_main(const double* __restrict__ rec_main
     return MainRec{m[0], m[1], m[2]};
 }
 
-// add_block with the main record already loaded
+// add_block with the main record already loaded; the extra record (64
+// bytes, one line) is read as four 16-byte words
 __device__ __forceinline__ void add_block_rec(double* B, const MainRec& mr, const double* __restrict__ rec_extra,
                                               int64_t e0, int64_t m0, uint32_t k, int i, int j) {
     const double m[8] = {mr.a.x, mr.a.y, mr.b.x, mr.b.y, mr.c.x, mr.c.y, 0.0, 0.0};
@@ -63,7 +64,9 @@ __device__ __forceinline__ void add_block_rec(double* B, const MainRec& mr, cons
     d3 gi = rec_coef(m, i, ee) * wt, gj = rec_coef(m, j, ee) * wt;
     add_outer(B, m[R_P22], gi, gj);
     if ((int64_t)k >= m0) {
-        const double* x = rec_extra + 9 * ((int64_t)k - m0);
+        const double2* xp = reinterpret_cast<const double2*>(rec_extra + 8 * ((int64_t)k - m0));
+        const double2 x0 = xp[0], x1 = xp[1], x2 = xp[2], x3 = xp[3];
+        const double x[8] = {x0.x, x0.y, x1.x, x1.y, x2.x, x2.y, x3.x, x3.y};
         d3 si = sq_slot(x, i), sj = sq_slot(x, j);
         add_outer(B, x[6], si, sj);
         add_outer(B, x[7], si, gj);
@@ -93,7 +96,8 @@ __global__ void __launch_bounds__(kBlock) k_rows_diag(int mode, int32_t V, const
                                                       const int64_t* __restrict__ cptr,
                                                       const uint32_t* __restrict__ contrib,
                                                       const double* __restrict__ rec_main,
-                                                      const double* __restrict__ rec_extra, int64_t e0, int64_t m0,
+                                                      const double* __restrict__ rec_extra,
+                                                      const double* __restrict__ rec_a1, int64_t e0, int64_t m0,
                                                       const double* __restrict__ diag, double* __restrict__ grad,
                                                       double* __restrict__ ev, void* val, int dtype, int64_t nnzb) {
     const int64_t gi = (int64_t)blockIdx.x * (kBlock / LANES) + threadIdx.x / LANES;
@@ -129,11 +133,11 @@ __global__ void __launch_bounds__(kBlock) k_rows_diag(int mode, int32_t V, const
                 const int i = (int)((code[u] >> 2) & 3u);
                 const bool ee = (int64_t)k >= e0;
                 const d3 gi = rec_coef(m[u], i, ee) * mk(m[u][R_W], m[u][R_W + 1], m[u][R_W + 2]);
-                const double* x = (int64_t)k >= m0 ? rec_extra + 9 * ((int64_t)k - m0) : nullptr;
+                const double* x = (int64_t)k >= m0 ? rec_extra + 8 * ((int64_t)k - m0) : nullptr;
                 if (mode & 1) {
                     g = g + m[u][R_A2] * gi;
                     if (i == 0) e += m[u][R_E];
-                    if (x) g = g + x[8] * sq_slot(x, i);
+                    if (x) g = g + rec_a1[(int64_t)k - m0] * sq_slot(x, i);
                 }
                 if (mode & 2) {
                     add_outer(B, m[u][R_P22], gi, gi);
@@ -226,6 +230,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_inspect(const int4* __restrict_
                                                          const int32_t* __restrict__ smult, TypeRanges tr,
                                                          const double* __restrict__ rec_main,
                                                          const double* __restrict__ rec_extra,
+                                                         const double* __restrict__ rec_a1,
                                                          const double* __restrict__ X, const double* __restrict__ XR,
                                                          DevParams pm, int32_t* src, int32_t* type, int32_t* vid,
                                                          int32_t* mult, double* energy, double* grad,
@@ -256,8 +261,8 @@ __global__ void __launch_bounds__(kBlock) k_pair_inspect(const int4* __restrict_
             if (i < nv) {
                 g = m[R_A2] * (rec_coef(m, i, k >= e0) * mk(m[R_W], m[R_W + 1], m[R_W + 2]));
                 if (k >= m0) {
-                    const double* x = rec_extra + 9 * (k - m0);
-                    g = g + x[8] * sq_slot(x, i);
+                    const double* x = rec_extra + 8 * (k - m0);
+                    g = g + rec_a1[k - m0] * sq_slot(x, i);
                 }
             }
             grad[12 * k + 3 * i + 0] = g.x;
@@ -281,12 +286,13 @@ __global__ void __launch_bounds__(kBlock) k_pair_inspect(const int4* __restrict_
 namespace {
 template <int LANES>
 hipError_t rows_launch(int mode, int32_t V, const int32_t* order, const int32_t* diag_slot, const int64_t* cptr,
-                       const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t e0,
+                       const uint32_t* contrib, const double* rec_main, const double* rec_extra,
+                       const double* rec_a1, int64_t e0,
                        int64_t m0, const double* diag, double* grad, double* ev, void* val, int dtype, int64_t nnzb,
                        hipStream_t s) {
     const int64_t nb = ((int64_t)V * LANES + kBlock - 1) / kBlock;
     k_rows_diag<LANES><<<(unsigned)nb, kBlock, 0, s>>>(mode, V, order, diag_slot, cptr, contrib, rec_main, rec_extra,
-                                                       e0, m0, diag, grad, ev, val, dtype, nnzb);
+                                                       rec_a1, e0, m0, diag, grad, ev, val, dtype, nnzb);
     return hipGetLastError();
 }
 
@@ -303,12 +309,13 @@ hipError_t offdiag_launch(int32_t V, const int32_t* order, const int32_t* row_pt
 }  // namespace
 
 hipError_t launch_rows_diag(int mode, int32_t V, const int32_t* order, const int32_t* diag_slot, const int64_t* cptr,
-                            const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t e0,
+                            const uint32_t* contrib, const double* rec_main, const double* rec_extra,
+                            const double* rec_a1, int64_t e0,
                             int64_t m0, const double* diag, double* grad, double* ev, void* val, int dtype,
                             int64_t nnzb, int lanes, hipStream_t s) {
     if (V == 0) return hipSuccess;
-#define ROWS(L) rows_launch<L>(mode, V, order, diag_slot, cptr, contrib, rec_main, rec_extra, e0, m0, diag, grad, ev, \
-                               val, dtype, nnzb, s)
+#define ROWS(L) rows_launch<L>(mode, V, order, diag_slot, cptr, contrib, rec_main, rec_extra, rec_a1, e0, m0, diag, \
+                               grad, ev, val, dtype, nnzb, s)
     switch (lanes) {
         case 4: return ROWS(4);
         case 8: return ROWS(8);
@@ -336,12 +343,13 @@ hipError_t launch_offdiag(int32_t V, const int32_t* order, const int32_t* row_pt
 }
 
 hipError_t launch_pair_inspect(const int4* st_vid, const int32_t* st_src, const int32_t* smult, TypeRanges tr,
-                               const double* rec_main, const double* rec_extra, const double* x, const double* xr,
+                               const double* rec_main, const double* rec_extra, const double* rec_a1, const double* x,
+                               const double* xr,
                                const DevParams& pm, int32_t* src, int32_t* type, int32_t* vid, int32_t* mult,
                                double* energy, double* grad, double* hess, hipStream_t s) {
     int64_t nb = (tr.off[8] + kBlock - 1) / kBlock;
     if (nb == 0) return hipSuccess;
-    k_pair_inspect<<<(unsigned)nb, kBlock, 0, s>>>(st_vid, st_src, smult, tr, rec_main, rec_extra, x, xr, pm, src,
+    k_pair_inspect<<<(unsigned)nb, kBlock, 0, s>>>(st_vid, st_src, smult, tr, rec_main, rec_extra, rec_a1, x, xr, pm, src,
                                                   type, vid, mult, energy, grad, hess);
     return hipGetLastError();
 }
@@ -435,7 +443,7 @@ __global__ void __launch_bounds__(kBlock) k_mf_pair(const int4* __restrict__ st_
     const double s = dot(mk(m[R_W], m[R_W + 1], m[R_W + 2]), y);
     double a = m[R_P22] * s, b = 0.0;
     if (k >= tr.off[FT_EEM]) {
-        const double* e = rec_extra + 9 * (k - tr.off[FT_EEM]);
+        const double* e = rec_extra + 8 * (k - tr.off[FT_EEM]);
         const double t = dot(mk(e[0], e[1], e[2]), xs[1] - xs[0]) + dot(mk(e[3], e[4], e[5]), xs[3] - xs[2]);
         a += e[7] * t;
         b = e[7] * s + e[6] * t;
@@ -485,7 +493,7 @@ __global__ void __launch_bounds__(kMfBlock) k_mf_rows(int32_t V, const int32_t* 
                 const int64_t k = code[q] >> 4;
                 if (k >= m0 && t + q * kMfLanes < t1) {
                     const int i = (int)((code[q] >> 2) & 3u);
-                    const double* e = rec_extra + 9 * (k - m0) + (i < 2 ? 0 : 3);
+                    const double* e = rec_extra + 8 * (k - m0) + (i < 2 ? 0 : 3);
                     const double sb = (i & 1) ? w[q].y : -w[q].y;
                     acc = acc + sb * mk(e[0], e[1], e[2]);
                 }

@@ -291,7 +291,9 @@ struct PairFactors {
 // (PT, PE, PP) have c0 = 1 and c0 + c1 + c2 + c3 = 0; the edge-edge kinds
 // (EE, EEM, PEM, PPM) have c0 + c1 = 1 and c2 + c3 = -1.  The staged order
 // puts the edge-edge family last, from the first EE pair on.
-// Extra record of a mollified pair, 9 doubles: [u, v, P11, P12, a1].
+// Extra record of a mollified pair, 8 doubles (64 B, one line for the
+// gathers of the assembly): [u, v, P11, P12]; its a1 is kept in an array of
+// its own, read only by the gradient.
 enum RecIdx { R_C1 = 0, R_C2 = 1, R_W = 2, R_P22 = 5, R_A2 = 6, R_E = 7 };
 
 __device__ __forceinline__ double rec_coef(const double* m, int i, bool ee_family) {

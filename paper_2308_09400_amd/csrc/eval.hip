@@ -2,7 +2,7 @@
 // distance of the pair's sub-type, barrier energy, gradient factors and the
 // analytically projected proxy Hessian, stored as compact factors:
 //   main  [Ps][8]  = c1 c2 w~x w~y w~z P22 a2 E     (c0, c3 from the family)
-//   extra [Pm][9]  = u v P11 P12 a1                  (mollified kinds only)
+//   extra [Pm][8]  = u v P11 P12, a1 [Pm]            (mollified kinds only)
 // The energy is not reduced here: the row pass gathers each pair's E into
 // the vertex in its slot 0, and the per-scene sums below run over fixed
 // vertex pieces, so the result does not depend on how pairs map to lanes.
@@ -17,7 +17,8 @@ template <int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_eval(const int4* __restrict__ st_vid, const int32_t* __restrict__ mult,
                                                 TypeRanges tr, const double* __restrict__ X,
                                                 const double* __restrict__ XR, DevParams pm,
-                                                double* __restrict__ rec_main, double* __restrict__ rec_extra) {
+                                                double* __restrict__ rec_main, double* __restrict__ rec_extra,
+                                                double* __restrict__ rec_a1) {
     const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (k >= tr.off[8]) return;
     const int ft = type_of(k, tr);
@@ -32,10 +33,12 @@ __global__ void __launch_bounds__(BLOCK) k_eval(const int4* __restrict__ st_vid,
     m[2] = make_double2(o.wt.z, w * o.P22);
     m[3] = make_double2(w * o.a2, w * o.E);
     if (ft >= FT_EEM) {
-        double* x = rec_extra + 9 * (k - tr.off[FT_EEM]);
-        x[0] = o.u.x; x[1] = o.u.y; x[2] = o.u.z;
-        x[3] = o.v.x; x[4] = o.v.y; x[5] = o.v.z;
-        x[6] = w * o.P11; x[7] = w * o.P12; x[8] = w * o.a1;
+        double2* x = reinterpret_cast<double2*>(rec_extra + 8 * (k - tr.off[FT_EEM]));
+        x[0] = make_double2(o.u.x, o.u.y);
+        x[1] = make_double2(o.u.z, o.v.x);
+        x[2] = make_double2(o.v.y, o.v.z);
+        x[3] = make_double2(w * o.P11, w * o.P12);
+        rec_a1[k - tr.off[FT_EEM]] = w * o.a1;
     }
 }
 
@@ -69,22 +72,23 @@ __global__ void __launch_bounds__(kBlock) k_energy_scenes(const double* __restri
 
 template <int BLOCK>
 hipError_t eval_launch(const int4* st_vid, const int32_t* mult, TypeRanges tr, const double* x, const double* xr,
-                       const DevParams& pm, double* rec_main, double* rec_extra, hipStream_t s) {
+                       const DevParams& pm, double* rec_main, double* rec_extra, double* rec_a1, hipStream_t s) {
     const int64_t nb = (tr.off[8] + BLOCK - 1) / BLOCK;
-    k_eval<BLOCK><<<(unsigned)nb, BLOCK, 0, s>>>(st_vid, mult, tr, x, xr, pm, rec_main, rec_extra);
+    k_eval<BLOCK><<<(unsigned)nb, BLOCK, 0, s>>>(st_vid, mult, tr, x, xr, pm, rec_main, rec_extra, rec_a1);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_eval(const int4* st_vid, const int32_t* mult, TypeRanges tr, const double* x, const double* xr,
-                       const DevParams& pm, double* rec_main, double* rec_extra, int waves, hipStream_t s) {
+                       const DevParams& pm, double* rec_main, double* rec_extra, double* rec_a1, int waves,
+                       hipStream_t s) {
     if (tr.off[8] == 0) return hipSuccess;
     switch (waves) {
-        case 1: return eval_launch<64>(st_vid, mult, tr, x, xr, pm, rec_main, rec_extra, s);
-        case 2: return eval_launch<128>(st_vid, mult, tr, x, xr, pm, rec_main, rec_extra, s);
-        case 8: return eval_launch<512>(st_vid, mult, tr, x, xr, pm, rec_main, rec_extra, s);
-        default: return eval_launch<256>(st_vid, mult, tr, x, xr, pm, rec_main, rec_extra, s);
+        case 1: return eval_launch<64>(st_vid, mult, tr, x, xr, pm, rec_main, rec_extra, rec_a1, s);
+        case 2: return eval_launch<128>(st_vid, mult, tr, x, xr, pm, rec_main, rec_extra, rec_a1, s);
+        case 8: return eval_launch<512>(st_vid, mult, tr, x, xr, pm, rec_main, rec_extra, rec_a1, s);
+        default: return eval_launch<256>(st_vid, mult, tr, x, xr, pm, rec_main, rec_extra, rec_a1, s);
     }
 }
 

@@ -100,7 +100,7 @@ struct gipc_ctx {
     int32_t S = 1, npieces = 0;
     bool batched = false;
     // factors of the last eval; per-vertex energy shares and piece sums
-    gipc::DevBuf rec_main, rec_extra, ev, epart;
+    gipc::DevBuf rec_main, rec_extra, rec_a1, ev, epart;
     // matrix-free operator: the c_i w~_k vectors of every incidence, row by
     // row (built at the first use after an eval), and (alpha, beta) per pair
     gipc::DevBuf mfg, mfab;
@@ -182,7 +182,8 @@ hipError_t launch_sym_transpose(int64_t nnzb, const int32_t* slot_row, const int
 // waves: workgroup size in wavefronts (1, 2, 4 or 8)
 // mult: multiplicity per staged pair, nullable (all 1)
 hipError_t launch_eval(const int4* st_vid, const int32_t* mult, TypeRanges tr, const double* x, const double* xr,
-                       const DevParams& pm, double* rec_main, double* rec_extra, int waves, hipStream_t s);
+                       const DevParams& pm, double* rec_main, double* rec_extra, double* rec_a1, int waves,
+                       hipStream_t s);
 // per-scene energies from the per-vertex shares: pieces, then scenes
 hipError_t launch_energy(const double* ev, const int2* pieces, int32_t npieces, const int32_t* poff, int32_t S,
                          double* part, double* energy, hipStream_t s);
@@ -192,7 +193,8 @@ hipError_t launch_energy(const double* ev, const int2* pieces, int32_t npieces, 
 // values; lanes per row: 4, 8, 16 or 32
 // rows are visited in the order `order` (a permutation of 0..V-1)
 hipError_t launch_rows_diag(int mode, int32_t V, const int32_t* order, const int32_t* diag_slot, const int64_t* cptr,
-                            const uint32_t* contrib, const double* rec_main, const double* rec_extra, int64_t e0,
+                            const uint32_t* contrib, const double* rec_main, const double* rec_extra,
+                            const double* rec_a1, int64_t e0,
                             int64_t m0, const double* diag, double* grad, double* ev, void* val, int dtype,
                             int64_t nnzb, int lanes, hipStream_t s);
 // blocks above the diagonal are summed once and stored with their
@@ -204,7 +206,8 @@ hipError_t launch_offdiag(int32_t V, const int32_t* order, const int32_t* row_pt
                           const double* rec_extra, int64_t e0, int64_t m0, void* val, int dtype, int waves,
                           hipStream_t s);
 hipError_t launch_pair_inspect(const int4* st_vid, const int32_t* st_src, const int32_t* smult, TypeRanges tr,
-                               const double* rec_main, const double* rec_extra, const double* x, const double* xr,
+                               const double* rec_main, const double* rec_extra, const double* rec_a1, const double* x,
+                               const double* xr,
                                const DevParams& pm, int32_t* src, int32_t* type, int32_t* vid, int32_t* mult,
                                double* energy, double* grad, double* hess, hipStream_t s);
 
