@@ -195,7 +195,7 @@ void gipc_ctx_destroy(gipc_ctx* ctx) {
     DevBuf* bufs[] = {&ctx->cand_ft, &ctx->cand_vid, &ctx->bcount, &ctx->boff, &ctx->counters, &ctx->st_vid,
                       &ctx->st_src, &ctx->mult, &ctx->mkeys, &ctx->mrep_of, &ctx->mcount,
                       &ctx->mflag, &ctx->mpos, &ctx->st_vid2, &ctx->st_src2, &ctx->deg, &ctx->kcount, &ctx->fill, &ctx->inc_ptr, &ctx->kptr, &ctx->inc,
-                      &ctx->contrib, &ctx->kcol, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
+                      &ctx->contrib, &ctx->kcol, &ctx->kbeg, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
                       &ctx->slot_row, &ctx->diag_slot, &ctx->maxbuf, &ctx->bigrows, &ctx->tslot, &ctx->incv, &ctx->order,
                       &ctx->obox, &ctx->ocell, &ctx->ohist, &ctx->ooff, &ctx->ofill, &ctx->rec_main, &ctx->rec_extra, &ctx->rec_a1, &ctx->ev,
                       &ctx->epart, &ctx->mfg, &ctx->mfab, &ctx->flag, &ctx->ffr, &ctx->fev, &ctx->fpart, &ctx->cpart, &ctx->ccnt, &ctx->ccount, &ctx->cfill, &ctx->coff_t, &ctx->cent_t, &ctx->coff_e, &ctx->cent_e, &ctx->qcnt, &ctx->qoff_p, &ctx->qoff_e, &ctx->crec_t, &ctx->crec_e, &ctx->vscene, &ctx->pieces, &ctx->poff,
@@ -358,13 +358,15 @@ gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
     CK(ensure(ctx->incv, sizeof(int4) * (size_t)(ninc > 0 ? ninc : 1)), "alloc incidences");
     CK(ensure(ctx->contrib, sizeof(uint32_t) * (size_t)K), "alloc contributions");
     CK(ensure(ctx->kcol, sizeof(int32_t) * (size_t)K), "alloc contributions");
+    CK(ensure(ctx->kbeg, sizeof(int32_t) * (size_t)K), "alloc contributions");
     CK(launch_sym_scatter(as<int4>(ctx->st_vid), tr, as<int64_t>(ctx->inc_ptr), as<int32_t>(ctx->fill),
                           as<uint32_t>(ctx->inc), as<int4>(ctx->incv), s),
        "incidence scatter");
     CK(ensure(ctx->bigrows, sizeof(int32_t) * Vs), "alloc pattern");
     CK(launch_sym_rowsort(V, max_deg, as<int64_t>(ctx->inc_ptr), as<uint32_t>(ctx->inc), as<int4>(ctx->incv), tr,
                           as<int64_t>(ctx->kptr), as<uint32_t>(ctx->contrib), as<int32_t>(ctx->kcol),
-                          as<int32_t>(ctx->ncols), as<int32_t>(ctx->bigrows), cnt + C_NBIG, s),
+                          as<int32_t>(ctx->kbeg), as<int32_t>(ctx->ncols), as<int32_t>(ctx->bigrows), cnt + C_NBIG,
+                          s),
        "row sort");
     CK((exclusive_scan<int32_t, int32_t>(as<int32_t>(ctx->ncols), V, as<int32_t>(ctx->row_ptr), ctx, s,
                                          cnt + C_NNZB)),
@@ -375,7 +377,8 @@ gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
     CK(ensure(ctx->col_idx, sizeof(int32_t) * (size_t)nnzb), "alloc pattern");
     CK(ensure(ctx->slot_row, sizeof(int32_t) * (size_t)nnzb), "alloc pattern");
     CK(ensure(ctx->cptr, sizeof(int64_t) * (size_t)(nnzb + 1)), "alloc pattern");
-    CK(launch_sym_fill(V, as<int64_t>(ctx->kptr), as<int32_t>(ctx->kcol), as<int32_t>(ctx->row_ptr),
+    CK(launch_sym_fill(V, as<int64_t>(ctx->kptr), as<int32_t>(ctx->kcol), as<int32_t>(ctx->kbeg),
+                       as<int32_t>(ctx->row_ptr),
                        as<int32_t>(ctx->col_idx), as<int64_t>(ctx->cptr), as<int32_t>(ctx->slot_row),
                        as<int32_t>(ctx->diag_slot), nnzb, s),
        "pattern fill");

@@ -87,7 +87,7 @@ struct gipc_ctx {
     int64_t Ps = 0;
     int32_t V = 0;
     // symbolic
-    gipc::DevBuf deg, kcount, fill, inc_ptr, kptr, inc, contrib, kcol, ncols, row_ptr, col_idx, cptr, slot_row,
+    gipc::DevBuf deg, kcount, fill, inc_ptr, kptr, inc, contrib, kcol, kbeg, ncols, row_ptr, col_idx, cptr, slot_row,
         diag_slot, maxbuf, bigrows, tslot, incv;
     // visiting order of the block rows in the assembly (spatial cells)
     gipc::DevBuf order, obox, ocell, ohist, ooff, ofill;
@@ -168,12 +168,16 @@ hipError_t launch_sym_scatter(const int4* st_vid, TypeRanges tr, const int64_t* 
                               uint32_t* inc, int4* incv, hipStream_t s);
 // big: int32 [V] scratch for the rows sorted by whole workgroups, nbig: a
 // device counter that must be zero on entry
+// contrib: each row's sorted contribution codes; kcol / kbeg: the row's
+// distinct columns and the offset of each one's first contribution, written
+// compactly from the row's contribution offset; ncols: their count
 hipError_t launch_sym_rowsort(int32_t V, int32_t max_deg, const int64_t* inc_ptr, const uint32_t* inc,
                               const int4* incv, TypeRanges tr, const int64_t* kptr, uint32_t* contrib,
-                              int32_t* kcol, int32_t* ncols, int32_t* big, int64_t* nbig, hipStream_t s);
-hipError_t launch_sym_fill(int32_t V, const int64_t* kptr, const int32_t* kcol, const int32_t* row_ptr,
-                           int32_t* col_idx, int64_t* cptr, int32_t* slot_row, int32_t* diag_slot, int64_t nnzb,
-                           hipStream_t s);
+                              int32_t* kcol, int32_t* kbeg, int32_t* ncols, int32_t* big, int64_t* nbig,
+                              hipStream_t s);
+hipError_t launch_sym_fill(int32_t V, const int64_t* kptr, const int32_t* kcol, const int32_t* kbeg,
+                           const int32_t* row_ptr, int32_t* col_idx, int64_t* cptr, int32_t* slot_row,
+                           int32_t* diag_slot, int64_t nnzb, hipStream_t s);
 // tslot[s] = slot of (c, r) for every block s = (r, c) with c > r, else -1
 hipError_t launch_sym_transpose(int64_t nnzb, const int32_t* slot_row, const int32_t* col_idx,
                                 const int32_t* row_ptr, int32_t* tslot, hipStream_t s);

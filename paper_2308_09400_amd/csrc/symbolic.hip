@@ -10,9 +10,10 @@
 //     registers (bitonic network over cross-lane shuffles) for rows of up to
 //     128 incidences, one workgroup per row with the keys in LDS for the
 //     rest; the sorted codes are the row's contribution lists, grouped by
-//     column;
+//     column, and the row's distinct columns with the offset of each one's
+//     first contribution are written compactly at the row's start;
 //  5. scan of the per-row column counts -> row_ptr;
-//  6. per row, the column boundaries give col_idx and the start of each
+//  6. per row, the compact column list gives col_idx and the start of each
 //     block's contribution list.
 // A contribution code is k << 4 | i << 2 | j (staged pair k, local block i, j).
 #include "internal.hpp"
@@ -102,9 +103,11 @@ constexpr int kWaveIncidences = kWaveN / 4;  // 128 incidences of 4 key slots
 // kWaveIncidences incidences)
 __device__ void rowsort_lds(int r, const int64_t* __restrict__ inc_ptr, const uint32_t* __restrict__ inc,
                             const int4* __restrict__ incv, const TypeRanges& tr, const int64_t* __restrict__ kptr,
-                            uint32_t* __restrict__ contrib, int32_t* __restrict__ kcol, int32_t* __restrict__ ncols) {
+                            uint32_t* __restrict__ contrib, int32_t* __restrict__ kcol, int32_t* __restrict__ kbeg,
+                            int32_t* __restrict__ ncols) {
     extern __shared__ unsigned long long keys[];
     __shared__ int32_t cnt;
+    __shared__ int32_t wcnt[kBlock / 64];
     const int64_t start = inc_ptr[r];
     const int n = (int)(inc_ptr[r + 1] - start);
     unsigned N = 1;
@@ -138,17 +141,37 @@ __device__ void rowsort_lds(int r, const int64_t* __restrict__ inc_ptr, const ui
     }
     const int64_t base = kptr[r];
     const int K = (int)(kptr[r + 1] - base);
-    int c = 0;
-    for (int t = threadIdx.x; t < K; t += kBlock) {
-        unsigned long long key = keys[t];
-        int col = (int)(key >> 32);
-        contrib[base + t] = (uint32_t)key;
-        kcol[base + t] = col;
-        if (t == 0 || (int)(keys[t - 1] >> 32) != col) ++c;
+    // the first contribution of every column, ranked in order (chunks of a
+    // workgroup: wave ballots, then the waves' counts in order)
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int carry = 0;
+    for (int c0 = 0; c0 < K; c0 += kBlock) {
+        const int t = c0 + (int)threadIdx.x;
+        bool first = false;
+        int col = 0;
+        if (t < K) {
+            const unsigned long long key = keys[t];
+            col = (int)(key >> 32);
+            contrib[base + t] = (uint32_t)key;
+            first = t == 0 || (int)(keys[t - 1] >> 32) != col;
+        }
+        const unsigned long long m = __ballot(first);
+        if (lane == 0) wcnt[wid] = __popcll(m);
+        __syncthreads();
+        int before = carry, total = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            if (w < wid) before += wcnt[w];
+            total += wcnt[w];
+        }
+        if (first) {
+            const int rank = before + __popcll(m & __lanemask_lt());
+            kcol[base + rank] = col;
+            kbeg[base + rank] = t;
+        }
+        carry += total;
+        __syncthreads();
     }
-    atomicAdd(&cnt, c);
-    __syncthreads();
-    if (threadIdx.x == 0) ncols[r] = cnt;
+    if (threadIdx.x == 0) ncols[r] = carry;
 }
 
 // value of lane (lane ^ D) for a compile-time lane distance D.  Distances 1
@@ -205,7 +228,8 @@ template <int M>
 __device__ __forceinline__ void rowsort_regs(int64_t r, int n, int64_t start, const uint32_t* __restrict__ inc,
                                              const int4* __restrict__ incv, const TypeRanges& tr,
                                              const int64_t* __restrict__ kptr, uint32_t* __restrict__ contrib,
-                                             int32_t* __restrict__ kcol, int32_t* __restrict__ ncols) {
+                                             int32_t* __restrict__ kcol, int32_t* __restrict__ kbeg,
+                                             int32_t* __restrict__ ncols) {
     constexpr int N = 64 * M;
     const int lane = threadIdx.x & 63;
     unsigned long long key[M];
@@ -276,21 +300,39 @@ __device__ __forceinline__ void rowsort_regs(int64_t r, int n, int64_t start, co
     const int64_t base = kptr[r];
     const int K = (int)(kptr[r + 1] - base);
     const unsigned long long prev_last = shfl_up64(key[M - 1], 1);
+    // the first contribution of every column: flags, this lane's count, its
+    // rank among all (exclusive scan of the counts over the lanes)
+    bool first[M];
     int c = 0;
 #pragma unroll
     for (int q = 0; q < M; ++q) {
         const int e = M * lane + q;
+        first[q] = false;
         if (e < K) {
             const int col = (int)(key[q] >> 32);
             contrib[base + e] = (uint32_t)key[q];
-            kcol[base + e] = col;
             const unsigned long long pk = q == 0 ? prev_last : key[q > 0 ? q - 1 : 0];
-            if (e == 0 || (int)(pk >> 32) != col) ++c;
+            first[q] = e == 0 || (int)(pk >> 32) != col;
+            c += first[q] ? 1 : 0;
         }
     }
+    int pre = c;  // inclusive scan over the lanes, then exclusive
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-    if (lane == 0) ncols[r] = c;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(pre, o, 64);
+        if (lane >= o) pre += v;
+    }
+    const int total = __shfl(pre, 63, 64);
+    int rank = pre - c;
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        if (first[q]) {
+            kcol[base + rank] = (int)(key[q] >> 32);
+            kbeg[base + rank] = M * lane + q;
+            ++rank;
+        }
+    }
+    if (lane == 0) ncols[r] = total;
 }
 
 // one wavefront per row, keys in registers: the number of keys per lane is
@@ -302,7 +344,8 @@ __global__ void __launch_bounds__(kBlock) k_sym_rowsort_wave(int32_t V, const in
                                                              const int4* __restrict__ incv, TypeRanges tr,
                                                              const int64_t* __restrict__ kptr,
                                                              uint32_t* __restrict__ contrib,
-                                                             int32_t* __restrict__ kcol, int32_t* __restrict__ ncols,
+                                                             int32_t* __restrict__ kcol, int32_t* __restrict__ kbeg,
+                                                             int32_t* __restrict__ ncols,
                                                              int32_t* __restrict__ big,
                                                              unsigned long long* __restrict__ nbig) {
     const int lane = threadIdx.x & 63;
@@ -319,10 +362,10 @@ __global__ void __launch_bounds__(kBlock) k_sym_rowsort_wave(int32_t V, const in
         return;
     }
     // the branch is uniform in the wavefront
-    if (n <= 16) rowsort_regs<1>(r, n, start, inc, incv, tr, kptr, contrib, kcol, ncols);
-    else if (n <= 32) rowsort_regs<2>(r, n, start, inc, incv, tr, kptr, contrib, kcol, ncols);
-    else if (n <= 64) rowsort_regs<4>(r, n, start, inc, incv, tr, kptr, contrib, kcol, ncols);
-    else rowsort_regs<8>(r, n, start, inc, incv, tr, kptr, contrib, kcol, ncols);
+    if (n <= 16) rowsort_regs<1>(r, n, start, inc, incv, tr, kptr, contrib, kcol, kbeg, ncols);
+    else if (n <= 32) rowsort_regs<2>(r, n, start, inc, incv, tr, kptr, contrib, kcol, kbeg, ncols);
+    else if (n <= 64) rowsort_regs<4>(r, n, start, inc, incv, tr, kptr, contrib, kcol, kbeg, ncols);
+    else rowsort_regs<8>(r, n, start, inc, incv, tr, kptr, contrib, kcol, kbeg, ncols);
 }
 
 // one workgroup per listed row (grid-stride over the list of rows the
@@ -334,19 +377,20 @@ __global__ void __launch_bounds__(kBlock) k_sym_rowsort(const int32_t* __restric
                                                         const int4* __restrict__ incv, TypeRanges tr,
                                                         const int64_t* __restrict__ kptr,
                                                         uint32_t* __restrict__ contrib, int32_t* __restrict__ kcol,
-                                                        int32_t* __restrict__ ncols) {
+                                                        int32_t* __restrict__ kbeg, int32_t* __restrict__ ncols) {
     const int64_t nr = (int64_t)*nrows;
     for (int64_t idx = blockIdx.x; idx < nr; idx += gridDim.x) {
-        rowsort_lds(rows[idx], inc_ptr, inc, incv, tr, kptr, contrib, kcol, ncols);
+        rowsort_lds(rows[idx], inc_ptr, inc, incv, tr, kptr, contrib, kcol, kbeg, ncols);
         __syncthreads();
     }
 }
 
-// one wavefront per row: the column boundaries of the row's sorted
-// contribution list (chunks of 64, positions from ballots) give col_idx, the
-// start of each block's list (cptr), the block's row and the diagonal slot
+// one wavefront per row: the row's compact column list (written by the row
+// sort at the row's contribution offset) gives col_idx, the start of each
+// block's list (cptr), the block's row and the diagonal slot
 __global__ void __launch_bounds__(kBlock) k_sym_fill(int32_t V, const int64_t* __restrict__ kptr,
                                                      const int32_t* __restrict__ kcol,
+                                                     const int32_t* __restrict__ kbeg,
                                                      const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_idx,
                                                      int64_t* __restrict__ cptr, int32_t* __restrict__ slot_row,
                                                      int32_t* __restrict__ diag_slot, int64_t nnzb) {
@@ -367,24 +411,14 @@ __global__ void __launch_bounds__(kBlock) k_sym_fill(int32_t V, const int64_t* _
         }
         return;
     }
-    int carry = 0;
-    for (int c0 = 0; c0 < K; c0 += 64) {
-        const int t = c0 + lane;
-        int col = -1;
-        bool flag = false;
-        if (t < K) {
-            col = kcol[base + t];
-            flag = (t == 0) || (kcol[base + t - 1] != col);
-        }
-        const unsigned long long m = __ballot(flag);
-        if (flag) {
-            const int s = rp + carry + __popcll(m & __lanemask_lt());
-            col_idx[s] = col;
-            cptr[s] = base + t;
-            slot_row[s] = r;
-            if (col == r) diag_slot[r] = s;
-        }
-        carry += __popcll(m);
+    const int nc = row_ptr[r + 1] - rp;
+    for (int j = lane; j < nc; j += 64) {
+        const int col = kcol[base + j];
+        const int s = rp + j;
+        col_idx[s] = col;
+        cptr[s] = base + kbeg[base + j];
+        slot_row[s] = r;
+        if (col == r) diag_slot[r] = s;
     }
 }
 
@@ -407,18 +441,20 @@ hipError_t launch_sym_scatter(const int4* st_vid, TypeRanges tr, const int64_t* 
 
 hipError_t launch_sym_rowsort(int32_t V, int32_t max_deg, const int64_t* inc_ptr, const uint32_t* inc,
                               const int4* incv, TypeRanges tr, const int64_t* kptr, uint32_t* contrib,
-                              int32_t* kcol, int32_t* ncols, int32_t* big, int64_t* nbig, hipStream_t s) {
+                              int32_t* kcol, int32_t* kbeg, int32_t* ncols, int32_t* big, int64_t* nbig,
+                              hipStream_t s) {
     if (V == 0) return hipSuccess;
     unsigned long long* nb = reinterpret_cast<unsigned long long*>(nbig);
     const unsigned blocks = (unsigned)(((int64_t)V + kBlock / 64 - 1) / (kBlock / 64));
-    k_sym_rowsort_wave<<<blocks, kBlock, 0, s>>>(V, inc_ptr, inc, incv, tr, kptr, contrib, kcol, ncols, big, nb);
+    k_sym_rowsort_wave<<<blocks, kBlock, 0, s>>>(V, inc_ptr, inc, incv, tr, kptr, contrib, kcol, kbeg, ncols, big,
+                                                 nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || max_deg <= kWaveIncidences) return e;
     unsigned N = 64;
     while (N < 4u * (unsigned)max_deg) N <<= 1;
     const size_t lds = sizeof(unsigned long long) * N;
     const unsigned grid = (unsigned)(V < 2048 ? V : 2048);
-    k_sym_rowsort<<<grid, kBlock, lds, s>>>(big, nb, inc_ptr, inc, incv, tr, kptr, contrib, kcol, ncols);
+    k_sym_rowsort<<<grid, kBlock, lds, s>>>(big, nb, inc_ptr, inc, incv, tr, kptr, contrib, kcol, kbeg, ncols);
     return hipGetLastError();
 }
 
@@ -457,12 +493,12 @@ hipError_t launch_sym_transpose(int64_t nnzb, const int32_t* slot_row, const int
     return hipGetLastError();
 }
 
-hipError_t launch_sym_fill(int32_t V, const int64_t* kptr, const int32_t* kcol, const int32_t* row_ptr,
-                           int32_t* col_idx, int64_t* cptr, int32_t* slot_row, int32_t* diag_slot, int64_t nnzb,
-                           hipStream_t s) {
+hipError_t launch_sym_fill(int32_t V, const int64_t* kptr, const int32_t* kcol, const int32_t* kbeg,
+                           const int32_t* row_ptr, int32_t* col_idx, int64_t* cptr, int32_t* slot_row,
+                           int32_t* diag_slot, int64_t nnzb, hipStream_t s) {
     if (V == 0) return hipSuccess;
     const unsigned blocks = (unsigned)(((int64_t)V + kBlock / 64 - 1) / (kBlock / 64));
-    k_sym_fill<<<blocks, kBlock, 0, s>>>(V, kptr, kcol, row_ptr, col_idx, cptr, slot_row, diag_slot, nnzb);
+    k_sym_fill<<<blocks, kBlock, 0, s>>>(V, kptr, kcol, kbeg, row_ptr, col_idx, cptr, slot_row, diag_slot, nnzb);
     return hipGetLastError();
 }
 
