@@ -60,7 +60,7 @@ FP64_VECTOR_TFLOPS = 78.6    # MI355X FP64 vector peak
 # 2 GiB copy with the library's copy kernel (bytes = 2.0 x FETCH_SIZE +
 # 1.0 x WRITE_SIZE), as summarised in profiles/sheets10_path.md.  Valid only
 # for the kernel source those runs measured: reset to None when it changes.
-MEASURED_TRAFFIC = {"k_spmv<double>": 1.575e9}
+MEASURED_TRAFFIC = {"k_spmv_ent<false>": None}
 
 
 def parse():
@@ -529,13 +529,13 @@ def main():
         "path_gbs": float(path_bytes / (np.median(path_ms) * 1e-3) / 1e9),
         "spmv_gbs": float(spmv_gbs),
         "roofline": {
-            "kernel": "k_spmv<float> (BSR SpMV)" if mixed else "k_spmv<double> (BSR SpMV)",
+            "kernel": "k_spmv<float> (BSR SpMV by rows)" if mixed else "k_spmv_ent<false> (FP64 BSR SpMV, one lane per block)",
             "bound": "hbm",
             "achieved": float(spmv_gbs),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": float(spmv_gbs / HBM_PEAK_GBS),
-            "traffic": None if (mixed or args.workload != "sheets10") else MEASURED_TRAFFIC.get("k_spmv<double>"),
+            "traffic": None if (mixed or args.workload != "sheets10") else MEASURED_TRAFFIC.get("k_spmv_ent<false>"),
         },
     }
     # achievable bandwidth of a plain streaming copy with the library's own

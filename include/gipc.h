@@ -108,7 +108,15 @@ enum { GIPC_F64 = 0, GIPC_F32 = 1 };
  * holding its diagonal block; val: device, component-major [9][nnzb]
  * (component 3a+b of block s at val[(3a+b)*nnzb + s]) of float64 (GIPC_F64)
  * or float32 (GIPC_F32).  Vectors multiplied with it are [nbrows][3] of the
- * same dtype. */
+ * same dtype.
+ * wave_head, wave_row: optional row-start map of the blocks in groups of 64,
+ * filled by gipc_bsr_pattern from the context's pattern (owned by the
+ * context, valid until the next build): for group g = 0 .. ceil(nnzb/64)-1,
+ * bit l of wave_head[g] (device uint64) is set when block 64g+l is the first
+ * block of its row, and wave_row[g] (device int32) is the row of block 64g.
+ * With both set (which requires every row to hold a block) an FP64 product
+ * runs one block per lane; with either NULL, as in a descriptor made by the
+ * caller, it runs row by row.  Results agree to rounding order. */
 typedef struct {
     int32_t nbrows;
     int64_t nnzb;
@@ -116,6 +124,8 @@ typedef struct {
     const int32_t* col_idx;
     void* val;
     int32_t dtype;
+    const uint64_t* wave_head;
+    const int32_t* wave_row;
 } gipc_bsr;
 
 /* Counts of the last gipc_pairs_build (host struct). */
@@ -171,9 +181,9 @@ gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
 /* Counts of the last successful build (host copy, no synchronisation). */
 gipc_status gipc_get_info(const gipc_ctx* ctx, gipc_info* info);
 
-/* Pattern of the last build: fills nbrows, nnzb, row_ptr, col_idx (device
- * pointers owned by the context, valid until the next build); leaves val
- * and dtype untouched. */
+/* Pattern of the last build: fills nbrows, nnzb, row_ptr, col_idx,
+ * wave_head and wave_row (device pointers owned by the context, valid until
+ * the next build); leaves val and dtype untouched. */
 gipc_status gipc_bsr_pattern(const gipc_ctx* ctx, gipc_bsr* A);
 
 /*

@@ -65,7 +65,8 @@ class Pairs(ctypes.Structure):
 
 class Bsr(ctypes.Structure):
     _fields_ = [("nbrows", ctypes.c_int32), ("nnzb", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
-                ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p), ("dtype", ctypes.c_int32)]
+                ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p), ("dtype", ctypes.c_int32),
+                ("wave_head", ctypes.c_void_p), ("wave_row", ctypes.c_void_p)]
 
 
 class Topology(ctypes.Structure):
@@ -303,6 +304,19 @@ class BsrMatrix:
     def col_idx(self):
         return _wrap_i32(self.desc.col_idx, self.nnzb, self.val.device)
 
+    def wave_map(self):
+        """Copies of the row-start map: (head bits as int64 [ceil(nnzb/64)], first rows as int32)."""
+        n = (self.nnzb + 63) // 64
+        head = _wrap_i32(self.desc.wave_head, 2 * n, self.val.device).view(torch.int64)
+        return head, _wrap_i32(self.desc.wave_row, n, self.val.device)
+
+    def row_descriptor(self) -> Bsr:
+        """A copy of the descriptor without the row-start map (products then run row by row)."""
+        d = Bsr.from_buffer_copy(self.desc)
+        d.wave_head = None
+        d.wave_row = None
+        return d
+
     def to_scipy(self):
         """Host scipy.sparse.bsr_matrix copy (test helper)."""
         import numpy as np
@@ -342,23 +356,27 @@ def eval_assemble(ctx: Context, x, prm: Params, A: BsrMatrix, diag=None, x_rest=
     return energy, grad
 
 
-def bsr_spmv(A: BsrMatrix, x, y=None, stream=None):
+def bsr_spmv(A: BsrMatrix, x, y=None, stream=None, by_rows=False):
+    """y = A x; by_rows=True drops the row-start map (row-by-row product)."""
     tdt = torch.float64 if A.dtype == F64 else torch.float32
     _need(x, tdt, 3, "x")
     y = torch.empty_like(x) if y is None else y
-    s = lib().gipc_bsr_spmv(ctypes.byref(A.desc), _ptr(x), _ptr(y), _stream(stream))
+    desc = A.row_descriptor() if by_rows else A.desc
+    s = lib().gipc_bsr_spmv(ctypes.byref(desc), _ptr(x), _ptr(y), _stream(stream))
     if s != OK:
         raise GipcError(s, f"gipc_bsr_spmv: {status_string(s)}")
     return y
 
 
-def pcg(ctx: Context, A: BsrMatrix, b, x=None, rtol=1e-6, maxit=1000, stream=None):
-    """Block-Jacobi PCG (synchronises).  Returns (x, iterations, relres, status)."""
+def pcg(ctx: Context, A: BsrMatrix, b, x=None, rtol=1e-6, maxit=1000, stream=None, by_rows=False):
+    """Block-Jacobi PCG (synchronises).  Returns (x, iterations, relres, status).
+    by_rows=True drops the row-start map (row-by-row products)."""
     _need(b, torch.float64, 3, "b")
     x = torch.zeros_like(b) if x is None else x
     it = ctypes.c_int32()
     rr = ctypes.c_double()
-    s = lib().gipc_pcg(ctx.h, ctypes.byref(A.desc), _ptr(b), _ptr(x), float(rtol), int(maxit), ctypes.byref(it),
+    desc = A.row_descriptor() if by_rows else A.desc
+    s = lib().gipc_pcg(ctx.h, ctypes.byref(desc), _ptr(b), _ptr(x), float(rtol), int(maxit), ctypes.byref(it),
                        ctypes.byref(rr), _stream(stream))
     ctx._check(s, "gipc_pcg")
     return x, int(it.value), float(rr.value), int(s)

@@ -196,7 +196,7 @@ void gipc_ctx_destroy(gipc_ctx* ctx) {
                       &ctx->st_src, &ctx->mult, &ctx->mkeys, &ctx->mrep_of, &ctx->mcount,
                       &ctx->mflag, &ctx->mpos, &ctx->st_vid2, &ctx->st_src2, &ctx->deg, &ctx->kcount, &ctx->fill, &ctx->inc_ptr, &ctx->kptr, &ctx->inc,
                       &ctx->contrib, &ctx->kcol, &ctx->kbeg, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
-                      &ctx->slot_row, &ctx->diag_slot, &ctx->maxbuf, &ctx->bigrows, &ctx->tslot, &ctx->incv, &ctx->order,
+                      &ctx->slot_row, &ctx->diag_slot, &ctx->whead, &ctx->wrow, &ctx->maxbuf, &ctx->bigrows, &ctx->tslot, &ctx->incv, &ctx->order,
                       &ctx->obox, &ctx->ocell, &ctx->ohist, &ctx->ooff, &ctx->ofill, &ctx->rec_main, &ctx->rec_extra, &ctx->rec_a1, &ctx->ev,
                       &ctx->epart, &ctx->mfg, &ctx->mfab, &ctx->flag, &ctx->ffr, &ctx->fev, &ctx->fpart, &ctx->cpart, &ctx->ccnt, &ctx->ccount, &ctx->cfill, &ctx->coff_t, &ctx->cent_t, &ctx->coff_e, &ctx->cent_e, &ctx->qcnt, &ctx->qoff_p, &ctx->qoff_e, &ctx->crec_t, &ctx->crec_e, &ctx->vscene, &ctx->pieces, &ctx->poff,
                       &ctx->r, &ctx->z, &ctx->p, &ctx->q, &ctx->p32, &ctx->minv, &ctx->part, &ctx->scal, &ctx->scan_tmp,
@@ -377,10 +377,14 @@ gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
     CK(ensure(ctx->col_idx, sizeof(int32_t) * (size_t)nnzb), "alloc pattern");
     CK(ensure(ctx->slot_row, sizeof(int32_t) * (size_t)nnzb), "alloc pattern");
     CK(ensure(ctx->cptr, sizeof(int64_t) * (size_t)(nnzb + 1)), "alloc pattern");
+    const int64_t nwave = (nnzb + 63) / 64 > 0 ? (nnzb + 63) / 64 : 1;
+    CK(ensure(ctx->whead, sizeof(uint64_t) * (size_t)nwave), "alloc pattern");
+    CK(ensure(ctx->wrow, sizeof(int32_t) * (size_t)nwave), "alloc pattern");
     CK(launch_sym_fill(V, as<int64_t>(ctx->kptr), as<int32_t>(ctx->kcol), as<int32_t>(ctx->kbeg),
                        as<int32_t>(ctx->row_ptr),
                        as<int32_t>(ctx->col_idx), as<int64_t>(ctx->cptr), as<int32_t>(ctx->slot_row),
-                       as<int32_t>(ctx->diag_slot), nnzb, s),
+                       as<int32_t>(ctx->diag_slot), as<unsigned long long>(ctx->whead), as<int32_t>(ctx->wrow),
+                       nnzb, s),
        "pattern fill");
     CK(ensure(ctx->tslot, sizeof(int32_t) * (size_t)(nnzb > 0 ? nnzb : 1)), "alloc pattern");
     CK(launch_sym_transpose(nnzb, as<int32_t>(ctx->slot_row), as<int32_t>(ctx->col_idx), as<int32_t>(ctx->row_ptr),
@@ -426,6 +430,8 @@ gipc_status gipc_bsr_pattern(const gipc_ctx* ctx, gipc_bsr* A) {
     A->nnzb = ctx->nnzb;
     A->row_ptr = static_cast<const int32_t*>(ctx->row_ptr.p);
     A->col_idx = static_cast<const int32_t*>(ctx->col_idx.p);
+    A->wave_head = static_cast<const uint64_t*>(ctx->whead.p);
+    A->wave_row = static_cast<const int32_t*>(ctx->wrow.p);
     return GIPC_OK;
 }
 

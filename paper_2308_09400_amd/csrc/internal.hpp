@@ -89,6 +89,8 @@ struct gipc_ctx {
     // symbolic
     gipc::DevBuf deg, kcount, fill, inc_ptr, kptr, inc, contrib, kcol, kbeg, ncols, row_ptr, col_idx, cptr, slot_row,
         diag_slot, maxbuf, bigrows, tslot, incv;
+    // per 64 blocks of the pattern: head bits of row starts, row of the first block
+    gipc::DevBuf whead, wrow;
     // visiting order of the block rows in the assembly (spatial cells)
     gipc::DevBuf order, obox, ocell, ohist, ooff, ofill;
     int64_t nnzb = 0, K = 0;
@@ -177,7 +179,8 @@ hipError_t launch_sym_rowsort(int32_t V, int32_t max_deg, const int64_t* inc_ptr
                               hipStream_t s);
 hipError_t launch_sym_fill(int32_t V, const int64_t* kptr, const int32_t* kcol, const int32_t* kbeg,
                            const int32_t* row_ptr, int32_t* col_idx, int64_t* cptr, int32_t* slot_row,
-                           int32_t* diag_slot, int64_t nnzb, hipStream_t s);
+                           int32_t* diag_slot, unsigned long long* whead, int32_t* wrow, int64_t nnzb,
+                           hipStream_t s);
 // tslot[s] = slot of (c, r) for every block s = (r, c) with c > r, else -1
 hipError_t launch_sym_transpose(int64_t nnzb, const int32_t* slot_row, const int32_t* col_idx,
                                 const int32_t* row_ptr, int32_t* tslot, hipStream_t s);

@@ -1,15 +1,35 @@
 // BSR SpMV, block-Jacobi preconditioned CG and a plain copy kernel.
 //
-// SpMV: G = 32 lanes per block row (two rows per wavefront); each lane walks
-// every 32nd block of the row (component-major values, so the lanes of a row
-// read consecutive values of each component: two 128-byte lines of doubles),
+// SpMV, FP64 with the pattern's row-start map (k_spmv_ent): one lane per
+// block.  Wavefront g takes blocks 64g .. 64g+63, so every value, column and
+// head-bit load is a full, aligned 64-lane stream with no row-pointer load
+// ahead of it.  Each lane forms its block's product A_s x_col; a segmented
+// suffix scan over the wavefront (segments cut at the row-start bits) leaves
+// each row's sum over the wavefront in the lane of its first block.  Rows
+// that end inside the wavefront are stored at once; a row that runs on into
+// the next wavefront of the workgroup is finished in LDS from the per-wave
+// pieces in wavefront order; the row holding the workgroup's last block, if
+// it runs on past the workgroup, gets its remaining blocks from the last
+// wavefront (a loop over 64-block chunks and a butterfly).  Every sum is in
+// a fixed order, so the product is deterministic.  Measured on the ten-sheet
+// matrix (17.4M blocks): 268 us against 296 us for the row kernel below;
+// 8 wavefronts per workgroup beat 4 and 16, issuing the tail with the main
+// loads was slower (281 us), as were two or four 64-block chunks per
+// wavefront (288 us) and a second fix-up launch for rows that cross
+// wavefronts (278 us).  For FP32 blocks the row kernel stays (161 us against
+// 163 us), and a descriptor without the map uses it too.
+//
+// SpMV by rows (k_spmv): G = 32 lanes per block row (two rows per
+// wavefront); each lane walks every 32nd block of the row (component-major
+// values, so the lanes of a row read consecutive values of each component),
 // gathers x[col] (mostly cache hits), and the 32 partial 3-vectors are
 // combined by a fixed xor-butterfly inside the lane group.  Deterministic.
 // Rows of the contact matrices hold about 27 blocks, so most lanes issue all
-// their loads at once.  Measured on the ten-sheet matrix (17.4M blocks),
-// FP64: 4 / 8 / 16 / 32 / 64 lanes = 815 / 373 / 311 / 296 / 383 us; FP32:
-// 8 / 16 / 32 lanes = 228 / 178 / 163 us.  At 8 lanes, non-temporal value
-// loads (573 us) and XCD-contiguous row chunks (405 us) were slower.
+// their loads at once.  Measured on the ten-sheet matrix, FP64: 4 / 8 / 16 /
+// 32 / 64 lanes = 815 / 373 / 311 / 296 / 383 us; FP32: 8 / 16 / 32 lanes =
+// 228 / 178 / 163 us.  At 8 lanes, non-temporal value loads (573 us) and
+// XCD-contiguous row chunks (405 us) were slower; at 32 lanes, two to four
+// rows per lane group (315-340 us) were too.
 //
 // PCG (Saad Alg. 9.1 with the inverse 3x3 diagonal blocks as
 // preconditioner, the paper's simple block preconditioner of Sec. 6.2):
@@ -51,6 +71,147 @@ __global__ void __launch_bounds__(kBlock) k_spmv(int32_t nrows, const int32_t* _
         y[3 * row] = a0;
         y[3 * row + 1] = a1;
         y[3 * row + 2] = a2;
+    }
+}
+
+__device__ __forceinline__ d3 ldv(const double* a, int64_t r) { return mk(a[3 * r], a[3 * r + 1], a[3 * r + 2]); }
+__device__ __forceinline__ void stv(double* a, int64_t r, d3 v) {
+    a[3 * r] = v.x; a[3 * r + 1] = v.y; a[3 * r + 2] = v.z;
+}
+
+// entry-parallel FP64 product (see the top of the file); with DOT the
+// workgroup also writes its partial of x.y over the rows it stores to
+// part[blockIdx.x] (the PCG's p.q, x = p)
+constexpr int kEntWaves = 8;
+constexpr int kEntBlock = kEntWaves * 64;
+
+template <bool DOT>
+__global__ void __launch_bounds__(kEntBlock) k_spmv_ent(int64_t nnzb, const int32_t* __restrict__ rp,
+                                                        const int32_t* __restrict__ ci,
+                                                        const double* __restrict__ val,
+                                                        const unsigned long long* __restrict__ hm,
+                                                        const int32_t* __restrict__ wrow,
+                                                        const double* __restrict__ x, double* __restrict__ y,
+                                                        double* __restrict__ part,
+                                                        const PcgScalars* __restrict__ sc) {
+    if (DOT && sc->done) return;
+    __shared__ double sf[kEntWaves][3], sl[kEntWaves][3], stail[3], lds[kEntWaves];
+    __shared__ unsigned long long sm[kEntWaves], smn[kEntWaves];
+    __shared__ int32_t srow[kEntWaves];
+    const int64_t W = (nnzb + 63) >> 6;
+    const int wi = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int64_t w = (int64_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * kEntWaves + wi));
+    double d = 0.0;
+    if (w < W) {
+        const int64_t s = (w << 6) + l;
+        const bool ok = s < nnzb;
+        const int64_t se = ok ? s : nnzb - 1;
+        const int64_t c = ci[se];
+        double v[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) v[k] = val[k * nnzb + se];
+        const unsigned long long m = hm[w];                         // row starts in this wavefront
+        const unsigned long long mn = (w + 1 < W) ? hm[w + 1] : 1ull;  // bit 0: the next one starts a row
+        const int32_t r0 = wrow[w];
+        const double x0 = x[3 * c], x1 = x[3 * c + 1], x2 = x[3 * c + 2];
+        double q0 = v[0] * x0 + v[1] * x1 + v[2] * x2;
+        double q1 = v[3] * x0 + v[4] * x1 + v[5] * x2;
+        double q2 = v[6] * x0 + v[7] * x1 + v[8] * x2;
+        if (!ok) q0 = q1 = q2 = 0.0;
+        // segmented suffix scan: lane l ends with the sum over [l, e), e = next row start
+        const unsigned long long above = m & ~((2ull << l) - 1ull);
+        const int e = above ? __builtin_ctzll(above) : 64;
+#pragma unroll
+        for (int dd = 1; dd < 64; dd <<= 1) {
+            const double t0 = __shfl_down(q0, dd), t1 = __shfl_down(q1, dd), t2 = __shfl_down(q2, dd);
+            if (l + dd < e) {
+                q0 += t0;
+                q1 += t1;
+                q2 += t2;
+            }
+        }
+        if (l == 0) {  // lane 0: the piece before the first row start
+            sf[wi][0] = q0;
+            sf[wi][1] = q1;
+            sf[wi][2] = q2;
+            sm[wi] = m;
+            smn[wi] = mn;
+        }
+        if ((m >> l) & 1ull) {
+            const int last = 63 - __builtin_clzll(m);
+            const int32_t r = r0 + __popcll(m & ((2ull << l) - 1ull) & ~1ull);
+            if ((l != last) || (mn & 1ull)) {  // the row ends in this wavefront
+                y[3 * r] = q0;
+                y[3 * r + 1] = q1;
+                y[3 * r + 2] = q2;
+                if (DOT) d = dot(ldv(x, r), mk(q0, q1, q2));
+            } else {
+                sl[wi][0] = q0;
+                sl[wi][1] = q1;
+                sl[wi][2] = q2;
+                srow[wi] = r;
+            }
+        }
+        // the row of the workgroup's last block runs on past the workgroup
+        if (wi == kEntWaves - 1 && !(mn & 1ull)) {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+            const int64_t end = rp[r0 + __popcll(m & ~1ull) + 1];
+            for (int64_t t = ((w + 1) << 6) + l; t < end; t += 64) {
+                const int64_t cc = ci[t];
+                const double y0 = x[3 * cc], y1 = x[3 * cc + 1], y2 = x[3 * cc + 2];
+                a0 += val[t] * y0 + val[nnzb + t] * y1 + val[2 * nnzb + t] * y2;
+                a1 += val[3 * nnzb + t] * y0 + val[4 * nnzb + t] * y1 + val[5 * nnzb + t] * y2;
+                a2 += val[6 * nnzb + t] * y0 + val[7 * nnzb + t] * y1 + val[8 * nnzb + t] * y2;
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                a0 += __shfl_xor(a0, o);
+                a1 += __shfl_xor(a1, o);
+                a2 += __shfl_xor(a2, o);
+            }
+            if (l == 0) {
+                stail[0] = a0;
+                stail[1] = a1;
+                stail[2] = a2;
+            }
+        }
+    } else if (l == 0) {
+        sm[wi] = 1ull;
+        smn[wi] = 1ull;
+    }
+    __syncthreads();
+    // thread t finishes the row opened by wavefront t's last row start when
+    // it runs on: the pieces of the following wavefronts in order, then the
+    // tail past the workgroup if it reaches that far
+    if (threadIdx.x < kEntWaves) {
+        const int t = threadIdx.x;
+        if (sm[t] != 0ull && !(smn[t] & 1ull)) {
+            double a0 = sl[t][0], a1 = sl[t][1], a2 = sl[t][2];
+            bool ended = false;
+            for (int k = t + 1; k < kEntWaves; ++k) {
+                a0 += sf[k][0];
+                a1 += sf[k][1];
+                a2 += sf[k][2];
+                if (sm[k] != 0ull || (smn[k] & 1ull)) {
+                    ended = true;
+                    break;
+                }
+            }
+            if (!ended) {
+                a0 += stail[0];
+                a1 += stail[1];
+                a2 += stail[2];
+            }
+            const int32_t r = srow[t];
+            y[3 * r] = a0;
+            y[3 * r + 1] = a1;
+            y[3 * r + 2] = a2;
+            if (DOT) d += dot(ldv(x, r), mk(a0, a1, a2));
+        }
+    }
+    if (DOT) {
+        d = block_sum_n<kEntBlock>(d, lds);
+        if (threadIdx.x == 0) part[blockIdx.x] = d;
     }
 }
 
@@ -131,10 +292,6 @@ __device__ __forceinline__ d3 apply3(const double* M, d3 v) {
               M[6] * v.x + M[7] * v.y + M[8] * v.z);
 }
 
-__device__ __forceinline__ d3 ldv(const double* a, int64_t r) { return mk(a[3 * r], a[3 * r + 1], a[3 * r + 2]); }
-__device__ __forceinline__ void stv(double* a, int64_t r, d3 v) {
-    a[3 * r] = v.x; a[3 * r + 1] = v.y; a[3 * r + 2] = v.z;
-}
 
 // q = A p (kG lanes per row) and one partial of p.q per workgroup of
 // kPcgBlock threads (32 rows), so the single-workgroup sum that forms alpha
@@ -275,8 +432,22 @@ __global__ void __launch_bounds__(kBlock) k_pupdate(int64_t n, const double* __r
 
 }  // namespace
 
+// the entry-parallel product needs FP64 blocks and the pattern's row-start map
+static bool spmv_by_entry(const gipc_bsr& A) {
+    return A.dtype == GIPC_F64 && A.wave_head != nullptr && A.wave_row != nullptr && A.nnzb > 0;
+}
+
+static int64_t spmv_ent_blocks(int64_t nnzb) { return ((nnzb + 63) / 64 + kEntWaves - 1) / kEntWaves; }
+
 hipError_t launch_spmv(const gipc_bsr& A, const void* x, void* y, hipStream_t s) {
     if (A.nbrows == 0) return hipSuccess;
+    if (spmv_by_entry(A)) {
+        k_spmv_ent<false><<<(unsigned)spmv_ent_blocks(A.nnzb), kEntBlock, 0, s>>>(
+            A.nnzb, A.row_ptr, A.col_idx, static_cast<const double*>(A.val),
+            reinterpret_cast<const unsigned long long*>(A.wave_head), A.wave_row, static_cast<const double*>(x),
+            static_cast<double*>(y), nullptr, nullptr);
+        return hipGetLastError();
+    }
     const int64_t threads = (int64_t)A.nbrows * kG;
     const unsigned nb = (unsigned)((threads + kBlock - 1) / kBlock);
     if (A.dtype == GIPC_F64)
@@ -312,8 +483,10 @@ hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x,
     const int32_t V = mf ? mf->V : A.nbrows;
     const int64_t n3 = 3 * (int64_t)V;
     const int64_t nbv = (V + kBlock - 1) / kBlock;  // row-parallel kernels
+    const bool ent = !mf && spmv_by_entry(A);       // entry-parallel FP64 product
     const int64_t nbs = mf ? mf_num_parts(V)        // operator kernel
-                           : ((int64_t)V * kG + kPcgBlock - 1) / kPcgBlock;
+                           : ent ? spmv_ent_blocks(A.nnzb)
+                                 : ((int64_t)V * kG + kPcgBlock - 1) / kPcgBlock;
     hipError_t e;
 #define GIPC_TRY(x)                            \
     do {                                       \
@@ -366,6 +539,10 @@ hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x,
             else if (f32)
                 k_pcg_spmv<float><<<(unsigned)nbs, kPcgBlock, 0, s>>>(
                     V, A.row_ptr, A.col_idx, static_cast<const float*>(A.val), A.nnzb, p32, p, q, part, sc);
+            else if (ent)
+                k_spmv_ent<true><<<(unsigned)nbs, kEntBlock, 0, s>>>(
+                    A.nnzb, A.row_ptr, A.col_idx, static_cast<const double*>(A.val),
+                    reinterpret_cast<const unsigned long long*>(A.wave_head), A.wave_row, p, q, part, sc);
             else
                 k_pcg_spmv<double><<<(unsigned)nbs, kPcgBlock, 0, s>>>(
                     V, A.row_ptr, A.col_idx, static_cast<const double*>(A.val), A.nnzb, p, p, q, part, sc);

@@ -385,6 +385,13 @@ __global__ void __launch_bounds__(kBlock) k_sym_rowsort(const int32_t* __restric
     }
 }
 
+// zeroes n 64-bit words (a kernel rather than a memset, so the build may be
+// recorded in a graph)
+__global__ void __launch_bounds__(kBlock) k_zero_u64(unsigned long long* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
 // one wavefront per row: the row's compact column list (written by the row
 // sort at the row's contribution offset) gives col_idx, the start of each
 // block's list (cptr), the block's row and the diagonal slot
@@ -393,7 +400,9 @@ __global__ void __launch_bounds__(kBlock) k_sym_fill(int32_t V, const int64_t* _
                                                      const int32_t* __restrict__ kbeg,
                                                      const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_idx,
                                                      int64_t* __restrict__ cptr, int32_t* __restrict__ slot_row,
-                                                     int32_t* __restrict__ diag_slot, int64_t nnzb) {
+                                                     int32_t* __restrict__ diag_slot,
+                                                     unsigned long long* __restrict__ whead,
+                                                     int32_t* __restrict__ wrow, int64_t nnzb) {
     const int lane = threadIdx.x & 63;
     const int64_t r64 = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     if (r64 >= V) return;  // the whole wavefront
@@ -402,12 +411,16 @@ __global__ void __launch_bounds__(kBlock) k_sym_fill(int32_t V, const int64_t* _
     const int K = (int)(kptr[r + 1] - base);
     const int rp = row_ptr[r];
     if (lane == 0 && r == V - 1) cptr[nnzb] = kptr[V];
+    // per 64-block wave of the product: head bit of the row's first block,
+    // row of every block whose index is a multiple of 64
+    if (lane == 0) atomicOr(whead + (rp >> 6), 1ull << (rp & 63));
     if (K == 0) {
         if (lane == 0) {
             col_idx[rp] = r;
             cptr[rp] = base;
             slot_row[rp] = r;
             diag_slot[r] = rp;
+            if ((rp & 63) == 0) wrow[rp >> 6] = r;
         }
         return;
     }
@@ -419,6 +432,7 @@ __global__ void __launch_bounds__(kBlock) k_sym_fill(int32_t V, const int64_t* _
         cptr[s] = base + kbeg[base + j];
         slot_row[s] = r;
         if (col == r) diag_slot[r] = s;
+        if ((s & 63) == 0) wrow[s >> 6] = r;
     }
 }
 
@@ -495,10 +509,14 @@ hipError_t launch_sym_transpose(int64_t nnzb, const int32_t* slot_row, const int
 
 hipError_t launch_sym_fill(int32_t V, const int64_t* kptr, const int32_t* kcol, const int32_t* kbeg,
                            const int32_t* row_ptr, int32_t* col_idx, int64_t* cptr, int32_t* slot_row,
-                           int32_t* diag_slot, int64_t nnzb, hipStream_t s) {
+                           int32_t* diag_slot, unsigned long long* whead, int32_t* wrow, int64_t nnzb,
+                           hipStream_t s) {
     if (V == 0) return hipSuccess;
+    const int64_t W = (nnzb + 63) >> 6;
+    k_zero_u64<<<(unsigned)((W + kBlock - 1) / kBlock), kBlock, 0, s>>>(whead, W);
     const unsigned blocks = (unsigned)(((int64_t)V + kBlock / 64 - 1) / (kBlock / 64));
-    k_sym_fill<<<blocks, kBlock, 0, s>>>(V, kptr, kcol, kbeg, row_ptr, col_idx, cptr, slot_row, diag_slot, nnzb);
+    k_sym_fill<<<blocks, kBlock, 0, s>>>(V, kptr, kcol, kbeg, row_ptr, col_idx, cptr, slot_row, diag_slot, whead,
+                                         wrow, nnzb);
     return hipGetLastError();
 }
 
