@@ -12,12 +12,14 @@
 // it runs on past the workgroup, gets its remaining blocks from the last
 // wavefront (a loop over 64-block chunks and a butterfly).  Every sum is in
 // a fixed order, so the product is deterministic.  Measured on the ten-sheet
-// matrix (17.4M blocks): 268 us against 296 us for the row kernel below;
-// 8 wavefronts per workgroup beat 4 and 16, issuing the tail with the main
-// loads was slower (281 us), as were two or four 64-block chunks per
-// wavefront (288 us) and a second fix-up launch for rows that cross
-// wavefronts (278 us).  For FP32 blocks the row kernel stays (161 us against
-// 163 us), and a descriptor without the map uses it too.
+// matrix (17.4M blocks): 260 us against 296 us for the row kernel below;
+// non-temporal value loads gave 260 against 271 us (the values are read
+// once; the gathered x lines then stay in L2 longer), 8 wavefronts per
+// workgroup beat 4 and 16, issuing the tail with the main loads was slower
+// (281 us), as were two or four 64-block chunks per wavefront (288 us), a
+// second fix-up launch for rows that cross wavefronts (278 us) and
+// non-temporal column loads (264 us).  For FP32 blocks the row kernel stays
+// (161 us against 163 us), and a descriptor without the map uses it too.
 //
 // SpMV by rows (k_spmv): G = 32 lanes per block row (two rows per
 // wavefront); each lane walks every 32nd block of the row (component-major
@@ -107,9 +109,9 @@ __global__ void __launch_bounds__(kEntBlock) k_spmv_ent(int64_t nnzb, const int3
         const bool ok = s < nnzb;
         const int64_t se = ok ? s : nnzb - 1;
         const int64_t c = ci[se];
-        double v[9];
+        double v[9];  // read once: non-temporal, so the x lines stay in L2
 #pragma unroll
-        for (int k = 0; k < 9; ++k) v[k] = val[k * nnzb + se];
+        for (int k = 0; k < 9; ++k) v[k] = __builtin_nontemporal_load(val + k * nnzb + se);
         const unsigned long long m = hm[w];                         // row starts in this wavefront
         const unsigned long long mn = (w + 1 < W) ? hm[w + 1] : 1ull;  // bit 0: the next one starts a row
         const int32_t r0 = wrow[w];
