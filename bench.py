@@ -60,7 +60,7 @@ FP64_VECTOR_TFLOPS = 78.6    # MI355X FP64 vector peak
 # 2 GiB copy with the library's copy kernel (bytes = 2.0 x FETCH_SIZE +
 # 1.0 x WRITE_SIZE), as summarised in profiles/sheets10_path.md.  Valid only
 # for the kernel source those runs measured: reset to None when it changes.
-MEASURED_TRAFFIC = {"k_spmv_ent<false>": None}
+MEASURED_TRAFFIC = {"k_spmv_ent<false>": 1.799e9}
 
 
 def parse():
