@@ -219,53 +219,31 @@ __device__ __forceinline__ unsigned long long shfl_up64(unsigned long long v, in
     return ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
 }
 
-// Sort of one row's keys by a wavefront, M keys per lane: element e = M lane
-// + q holds key slot j = e % 4 of incidence t = e / 4 (unused slots ~0), so
-// the row fits when 4 n <= 64 M.  A bitonic network over the first
-// Neff = 64 M elements sorts the row, exchanging across lanes with shuffles
-// for distances >= M and inside the lane below.
-template <int M>
-__device__ __forceinline__ void rowsort_regs(int64_t r, int n, int64_t start, const uint32_t* __restrict__ inc,
-                                             const int4* __restrict__ incv, const TypeRanges& tr,
-                                             const int64_t* __restrict__ kptr, uint32_t* __restrict__ contrib,
-                                             int32_t* __restrict__ kcol, int32_t* __restrict__ kbeg,
-                                             int32_t* __restrict__ ncols) {
+__device__ __forceinline__ uint32_t xor_lanes_any(uint32_t v, int d) {
+    switch (d) {  // d is a constant once the network is unrolled
+        case 1: return (uint32_t)xor_lanes32<1>((int)v);
+        case 2: return (uint32_t)xor_lanes32<2>((int)v);
+        case 4: return (uint32_t)xor_lanes32<4>((int)v);
+        case 8: return (uint32_t)xor_lanes32<8>((int)v);
+        case 16: return (uint32_t)xor_lanes32<16>((int)v);
+        default: return (uint32_t)xor_lanes32<32>((int)v);
+    }
+}
+
+__device__ __forceinline__ unsigned long long xor_lanes_any(unsigned long long v, int d) { return xor_lanes64(v, d); }
+
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Ascending bitonic sort of the 64 M elements e = M lane + q of a wavefront:
+// shuffles across lanes for distances >= M, swaps inside the lane below.
+template <int M, typename K>
+__device__ __forceinline__ void bitonic_wave(K (&key)[M]) {
     constexpr int N = 64 * M;
     const int lane = threadIdx.x & 63;
-    unsigned long long key[M];
-#pragma unroll
-    for (int q = 0; q < M; ++q) key[q] = ~0ull;
-    if (M >= 4) {
-#pragma unroll
-        for (int h = 0; h < (M >= 4 ? M / 4 : 1); ++h) {
-            const int t = (M / 4) * lane + h;
-            if (t < n) {
-                const uint32_t code = inc[start + t];
-                const uint32_t k = code >> 2, i = code & 3u;
-                const int nv = ft_nverts(type_of(k, tr));
-                const int4 v = incv[start + t];
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (j < nv)
-                        key[4 * h + j] = ((unsigned long long)(uint32_t)vslot(v, j) << 32) |
-                                         (unsigned long long)((k << 4) | (i << 2) | (uint32_t)j);
-            }
-        }
-    } else {
-        // 4 / M lanes share an incidence; this lane holds its slots j0 .. j0+M-1
-        const int t = lane / (4 / M), j0 = M * (lane % (4 / M));
-        if (t < n) {
-            const uint32_t code = inc[start + t];
-            const uint32_t k = code >> 2, i = code & 3u;
-            const int nv = ft_nverts(type_of(k, tr));
-            const int4 v = incv[start + t];
-#pragma unroll
-            for (int q = 0; q < M; ++q)
-                if (j0 + q < nv)
-                    key[q] = ((unsigned long long)(uint32_t)vslot(v, j0 + q) << 32) |
-                             (unsigned long long)((k << 4) | (i << 2) | (uint32_t)(j0 + q));
-        }
-    }
 #pragma unroll
     for (int kk = 2; kk <= N; kk <<= 1) {
 #pragma unroll
@@ -274,7 +252,7 @@ __device__ __forceinline__ void rowsort_regs(int64_t r, int n, int64_t start, co
 #pragma unroll
                 for (int q = 0; q < M; ++q) {
                     const int e = M * lane + q;
-                    const unsigned long long o = xor_lanes64(key[q], j / M);
+                    const K o = xor_lanes_any(key[q], j / M);
                     // this element keeps the smaller key iff it is the lower
                     // one of an ascending pair or the upper one of a descending
                     const bool take_min = ((e & kk) == 0) == ((e & j) == 0);
@@ -287,7 +265,7 @@ __device__ __forceinline__ void rowsort_regs(int64_t r, int n, int64_t start, co
                         const int l = q | j;
                         const int e = M * lane + q;
                         const bool up = (e & kk) == 0;
-                        const unsigned long long a = key[q], b = key[l];
+                        const K a = key[q], b = key[l];
                         if ((a > b) == up) {
                             key[q] = b;
                             key[l] = a;
@@ -297,23 +275,59 @@ __device__ __forceinline__ void rowsort_regs(int64_t r, int n, int64_t start, co
             }
         }
     }
+}
+
+// Second half of the wavefront row sort: the T keys (column << 32 | code) of
+// the slots j != i, packed in lk, sorted with M keys per lane (64 M >= T),
+// merged with the row's n own-column contributions (dsort: their codes
+// sorted, element MD lane + q).  A single sort by (column, code) would put
+// the own column r between the columns below and above it; that is the list
+// written here: codes to contrib, each column's first offset to kbeg, the
+// columns to kcol, all at the row's contribution offset.
+template <int M>
+__device__ __forceinline__ void rowsort_main(int64_t r, int n, int T, int MD, const uint32_t (&dsort)[2],
+                                             const unsigned long long* lk, const int64_t* __restrict__ kptr,
+                                             uint32_t* __restrict__ contrib, int32_t* __restrict__ kcol,
+                                             int32_t* __restrict__ kbeg, int32_t* __restrict__ ncols) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long key[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        const int e = M * lane + q;
+        key[q] = e < T ? lk[e] : ~0ull;
+    }
+    bitonic_wave<M>(key);
     const int64_t base = kptr[r];
-    const int K = (int)(kptr[r + 1] - base);
+    const int ri = (int)r;
+    // L = keys with a column below r (a prefix, the keys being sorted)
+    int lt = 0;
+#pragma unroll
+    for (int q = 0; q < M; ++q) lt += (M * lane + q < T && (int)(key[q] >> 32) < ri) ? 1 : 0;
+    const int L = wave_sum_i(lt);
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        const int e = M * lane + q;
+        if (e < T) contrib[base + (e < L ? e : e + n)] = (uint32_t)key[q];
+    }
+    for (int q = 0; q < MD; ++q) {
+        const int e = MD * lane + q;
+        if (e < n) contrib[base + L + e] = dsort[q];
+    }
+    // the first key of every column: flags, this lane's count, its rank
+    // among all (exclusive scan of the counts over the lanes)
     const unsigned long long prev_last = shfl_up64(key[M - 1], 1);
-    // the first contribution of every column: flags, this lane's count, its
-    // rank among all (exclusive scan of the counts over the lanes)
     bool first[M];
-    int c = 0;
+    int c = 0, cb = 0;
 #pragma unroll
     for (int q = 0; q < M; ++q) {
         const int e = M * lane + q;
         first[q] = false;
-        if (e < K) {
+        if (e < T) {
             const int col = (int)(key[q] >> 32);
-            contrib[base + e] = (uint32_t)key[q];
             const unsigned long long pk = q == 0 ? prev_last : key[q > 0 ? q - 1 : 0];
             first[q] = e == 0 || (int)(pk >> 32) != col;
             c += first[q] ? 1 : 0;
+            cb += (first[q] && col < ri) ? 1 : 0;
         }
     }
     int pre = c;  // inclusive scan over the lanes, then exclusive
@@ -323,22 +337,33 @@ __device__ __forceinline__ void rowsort_regs(int64_t r, int n, int64_t start, co
         if (lane >= o) pre += v;
     }
     const int total = __shfl(pre, 63, 64);
+    const int below = wave_sum_i(cb);  // columns below r
     int rank = pre - c;
 #pragma unroll
     for (int q = 0; q < M; ++q) {
         if (first[q]) {
-            kcol[base + rank] = (int)(key[q] >> 32);
-            kbeg[base + rank] = M * lane + q;
+            const int e = M * lane + q;
+            const int col = (int)(key[q] >> 32);
+            const bool lo = col < ri;
+            kcol[base + rank + (lo ? 0 : 1)] = col;
+            kbeg[base + rank + (lo ? 0 : 1)] = lo ? e : e + n;
             ++rank;
         }
     }
-    if (lane == 0) ncols[r] = total;
+    if (lane == 0) {
+        kcol[base + below] = ri;
+        kbeg[base + below] = L;
+        ncols[r] = total + 1;
+    }
 }
 
-// one wavefront per row, keys in registers: the number of keys per lane is
-// the smallest of 1, 2, 4, 8 that holds the row's 4 n key slots; rows with
-// more than kWaveIncidences incidences are appended to `big` for the
-// workgroup sort
+// one wavefront per row, keys in registers.  The slot j = i of an incidence
+// (k, i) is the row's own column, so those n keys are sorted as 32-bit codes
+// apart from the rest, and only the other slots (sum of nv - 1 over the
+// incidences, packed, not 4 slots per incidence) go through the 64-bit
+// network: the ten-sheet rows (about 54 incidences, 2.2 other slots each)
+// sort 128 keys instead of 256.  Rows with more than kWaveIncidences
+// incidences are appended to `big` for the workgroup sort.
 __global__ void __launch_bounds__(kBlock) k_sym_rowsort_wave(int32_t V, const int64_t* __restrict__ inc_ptr,
                                                              const uint32_t* __restrict__ inc,
                                                              const int4* __restrict__ incv, TypeRanges tr,
@@ -348,6 +373,7 @@ __global__ void __launch_bounds__(kBlock) k_sym_rowsort_wave(int32_t V, const in
                                                              int32_t* __restrict__ ncols,
                                                              int32_t* __restrict__ big,
                                                              unsigned long long* __restrict__ nbig) {
+    __shared__ unsigned long long skeys[kBlock / 64][kWaveN];
     const int lane = threadIdx.x & 63;
     const int64_t r = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     if (r >= V) return;  // the whole wavefront
@@ -361,11 +387,73 @@ __global__ void __launch_bounds__(kBlock) k_sym_rowsort_wave(int32_t V, const in
         if (lane == 0) big[atomicAdd(nbig, 1ull)] = (int32_t)r;
         return;
     }
+    // incidences t = lane and lane + 64: the own-column code (slot j = i) as
+    // a 32-bit key, the other nv - 1 slots as (column, code) keys packed in
+    // incidence order into this wavefront's LDS row
+    unsigned long long* lk = skeys[threadIdx.x >> 6];
+    uint32_t dkey[2] = {~0u, ~0u};
+    int o[2] = {0, 0};
+    uint32_t kc[2] = {0u, 0u};
+    int4 vv[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int t = lane + 64 * h;
+        vv[h] = make_int4(-1, -1, -1, -1);
+        if (t < n) {
+            const uint32_t code = inc[start + t];
+            const uint32_t k = code >> 2, i = code & 3u;
+            o[h] = ft_nverts(type_of(k, tr)) - 1;
+            kc[h] = code;
+            vv[h] = incv[start + t];
+            dkey[h] = (k << 4) | (i << 2) | i;
+        }
+    }
+    int pos[2], T = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        int sc = o[h];
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int v = __shfl_up(sc, d, 64);
+            if (lane >= d) sc += v;
+        }
+        pos[h] = T + sc - o[h];
+        T += __shfl(sc, 63, 64);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (o[h] > 0) {
+            const uint32_t k = kc[h] >> 2, i = kc[h] & 3u;
+            int p = pos[h];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (j <= o[h] && j != (int)i)
+                    lk[p++] = ((unsigned long long)(uint32_t)vslot(vv[h], j) << 32) |
+                              (unsigned long long)((k << 4) | (i << 2) | (uint32_t)j);
+        }
+    }
+    // the own-column codes, sorted while the LDS writes land
+    uint32_t dsort[2] = {~0u, ~0u};
+    int MD = 1;
+    if (n <= 64) {
+        uint32_t d1[1] = {dkey[0]};
+        bitonic_wave<1>(d1);
+        dsort[0] = d1[0];
+    } else {
+        uint32_t d2[2] = {dkey[0], dkey[1]};
+        bitonic_wave<2>(d2);
+        dsort[0] = d2[0];
+        dsort[1] = d2[1];
+        MD = 2;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // the branch is uniform in the wavefront
-    if (n <= 16) rowsort_regs<1>(r, n, start, inc, incv, tr, kptr, contrib, kcol, kbeg, ncols);
-    else if (n <= 32) rowsort_regs<2>(r, n, start, inc, incv, tr, kptr, contrib, kcol, kbeg, ncols);
-    else if (n <= 64) rowsort_regs<4>(r, n, start, inc, incv, tr, kptr, contrib, kcol, kbeg, ncols);
-    else rowsort_regs<8>(r, n, start, inc, incv, tr, kptr, contrib, kcol, kbeg, ncols);
+    if (T <= 64) rowsort_main<1>(r, n, T, MD, dsort, lk, kptr, contrib, kcol, kbeg, ncols);
+    else if (T <= 128) rowsort_main<2>(r, n, T, MD, dsort, lk, kptr, contrib, kcol, kbeg, ncols);
+    else if (T <= 256) rowsort_main<4>(r, n, T, MD, dsort, lk, kptr, contrib, kcol, kbeg, ncols);
+    else rowsort_main<8>(r, n, T, MD, dsort, lk, kptr, contrib, kcol, kbeg, ncols);
 }
 
 // one workgroup per listed row (grid-stride over the list of rows the
