@@ -17,9 +17,11 @@
 // once; the gathered x lines then stay in L2 longer), 8 wavefronts per
 // workgroup beat 4 and 16, issuing the tail with the main loads was slower
 // (281 us), as were two or four 64-block chunks per wavefront (288 us), a
-// second fix-up launch for rows that cross wavefronts (278 us) and
-// non-temporal column loads (264 us).  For FP32 blocks the row kernel stays
-// (161 us against 163 us), and a descriptor without the map uses it too.
+// second fix-up launch for rows that cross wavefronts (278 us),
+// non-temporal column loads (264 us) and a contiguous eighth of the
+// workgroups per XCD (259 against 257 us in that run).  For FP32 blocks the
+// row kernel stays (161 us against 163 us), and a descriptor without the map
+// uses it too.
 //
 // SpMV by rows (k_spmv): G = 32 lanes per block row (two rows per
 // wavefront); each lane walks every 32nd block of the row (component-major
