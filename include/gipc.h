@@ -382,12 +382,17 @@ gipc_status gipc_copy(const void* src, void* dst, int64_t bytes, void* stream);
  *                  gather: 4, 8, 16, 32 (changes the summation order of
  *                  those sums, hence their last bits)
  *   offdiag_waves  wavefronts per workgroup of the off-diagonal blocks: 1, 2, 4, 8
- * Default {4, 16, 4}.  Set: INVALID_ARG for other values.
+ *   row_order      order in which those two passes visit the block rows:
+ *                  0 = spatial cells of the build's positions, 1 = storage
+ *                  order (same results; 1 assembles faster but leaves more
+ *                  of the matrix to be written back during the next kernel)
+ * Default {4, 16, 4, 0}.  Set: INVALID_ARG for other values.
  */
 typedef struct {
     int32_t eval_waves;
     int32_t row_lanes;
     int32_t offdiag_waves;
+    int32_t row_order;
 } gipc_tune;
 
 gipc_status gipc_get_tune(const gipc_ctx* ctx, gipc_tune* tune);
@@ -396,7 +401,8 @@ gipc_status gipc_set_tune(gipc_ctx* ctx, const gipc_tune* tune);
 /*
  * Autotuner: with the arguments of gipc_eval_assemble on the current build,
  * time every eval_waves, row_lanes and offdiag_waves choice (each kernel
- * alone, `reps` launches after one warm-up, HIP events on `stream`), keep
+ * alone, `reps` launches after one warm-up, HIP events on `stream`), then
+ * both row orders (the two assembly passes together), keep
  * the fastest of each in the context and in *best (host, nullable).  The
  * outputs hold the result of the last timed launch of each kernel, which
  * equals a gipc_eval_assemble with the chosen shapes only up to summation

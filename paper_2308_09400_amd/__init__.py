@@ -49,7 +49,8 @@ class Params(ctypes.Structure):
 
 
 class Tune(ctypes.Structure):
-    _fields_ = [("eval_waves", ctypes.c_int32), ("row_lanes", ctypes.c_int32), ("offdiag_waves", ctypes.c_int32)]
+    _fields_ = [("eval_waves", ctypes.c_int32), ("row_lanes", ctypes.c_int32), ("offdiag_waves", ctypes.c_int32),
+                ("row_order", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -555,8 +556,8 @@ def get_tune(ctx: Context) -> dict:
     return t.as_dict()
 
 
-def set_tune(ctx: Context, eval_waves=4, row_lanes=16, offdiag_waves=4):
-    t = Tune(int(eval_waves), int(row_lanes), int(offdiag_waves))
+def set_tune(ctx: Context, eval_waves=4, row_lanes=16, offdiag_waves=4, row_order=0):
+    t = Tune(int(eval_waves), int(row_lanes), int(offdiag_waves), int(row_order))
     ctx._check(lib().gipc_set_tune(ctx.h, ctypes.byref(t)), "gipc_set_tune")
 
 

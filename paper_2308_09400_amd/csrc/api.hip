@@ -439,6 +439,13 @@ gipc_status gipc_bsr_pattern(const gipc_ctx* ctx, gipc_bsr* A) {
 
 namespace {
 
+// rows of the gradient / diagonal pass and of the off-diagonal blocks: the
+// spatial cells of the build's positions, or storage order (null) when
+// row_order = 1; the results are the same bits either way
+const int32_t* visit_order(gipc_ctx* ctx, int32_t row_order) {
+    return row_order ? nullptr : as<int32_t>(ctx->order);
+}
+
 // argument checks shared by the eval entry points; fills pm
 gipc_status eval_check(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_params* params, double* energy,
                        double* grad, const gipc_bsr* A, bool assemble, DevParams& pm) {
@@ -480,13 +487,13 @@ hipError_t eval_enqueue(gipc_ctx* ctx, const DevParams& pm, const gipc_mesh* mes
     hipError_t e = launch_eval(as<int4>(ctx->st_vid), mult, tr, mesh->x, xr, pm, as<double>(ctx->rec_main),
                                as<double>(ctx->rec_extra), as<double>(ctx->rec_a1), t.eval_waves, s);
     if (e != hipSuccess) return e;
-    e = launch_rows_diag(assemble ? 3 : 1, ctx->V, as<int32_t>(ctx->order), as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr),
+    e = launch_rows_diag(assemble ? 3 : 1, ctx->V, visit_order(ctx, t.row_order), as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr),
                          as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra), as<double>(ctx->rec_a1), e0, m0,
                          diag, grad, as<double>(ctx->ev), assemble ? A->val : nullptr, assemble ? A->dtype : 0,
                          ctx->nnzb, t.row_lanes, s);
     if (e != hipSuccess) return e;
     if (assemble) {
-        e = launch_offdiag(ctx->V, as<int32_t>(ctx->order), as<int32_t>(ctx->row_ptr), as<int32_t>(ctx->diag_slot),
+        e = launch_offdiag(ctx->V, visit_order(ctx, t.row_order), as<int32_t>(ctx->row_ptr), as<int32_t>(ctx->diag_slot),
                            ctx->nnzb, as<int32_t>(ctx->col_idx), as<int32_t>(ctx->tslot), as<int64_t>(ctx->cptr),
                            as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra), e0, m0,
                            A->val, A->dtype, t.offdiag_waves, s);
@@ -499,7 +506,8 @@ hipError_t eval_enqueue(gipc_ctx* ctx, const DevParams& pm, const gipc_mesh* mes
 bool tune_ok(const gipc_tune& t) {
     auto w = [](int v) { return v == 1 || v == 2 || v == 4 || v == 8; };
     return w(t.eval_waves) && w(t.offdiag_waves) &&
-           (t.row_lanes == 4 || t.row_lanes == 8 || t.row_lanes == 16 || t.row_lanes == 32);
+           (t.row_lanes == 4 || t.row_lanes == 8 || t.row_lanes == 16 || t.row_lanes == 32) &&
+           (t.row_order == 0 || t.row_order == 1);
 }
 
 }  // namespace
@@ -539,11 +547,11 @@ gipc_status gipc_assemble_bsr(gipc_ctx* ctx, const double* diag, const gipc_bsr*
     if (!same_pattern(ctx, A)) return fail(ctx, GIPC_ERR_STATE, "A is not the pattern of the last build");
     hipStream_t s = S(stream);
     const int64_t m0 = ctx->ranges.off[FT_EEM], e0 = ctx->ranges.off[FT_EE];
-    CK(launch_rows_diag(2, ctx->V, as<int32_t>(ctx->order), as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr), as<uint32_t>(ctx->contrib),
+    CK(launch_rows_diag(2, ctx->V, visit_order(ctx, ctx->tune.row_order), as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr), as<uint32_t>(ctx->contrib),
                         as<double>(ctx->rec_main), as<double>(ctx->rec_extra), as<double>(ctx->rec_a1), e0, m0, diag, nullptr, nullptr, A->val,
                         A->dtype, ctx->nnzb, ctx->tune.row_lanes, s),
        "diagonal blocks");
-    CK(launch_offdiag(ctx->V, as<int32_t>(ctx->order), as<int32_t>(ctx->row_ptr), as<int32_t>(ctx->diag_slot),
+    CK(launch_offdiag(ctx->V, visit_order(ctx, ctx->tune.row_order), as<int32_t>(ctx->row_ptr), as<int32_t>(ctx->diag_slot),
                            ctx->nnzb, as<int32_t>(ctx->col_idx), as<int32_t>(ctx->tslot), as<int64_t>(ctx->cptr),
                       as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra), e0, m0,
                       A->val, A->dtype, ctx->tune.offdiag_waves, s),
@@ -903,8 +911,8 @@ gipc_status gipc_set_tune(gipc_ctx* ctx, const gipc_tune* tune) {
     if (!ctx || !tune) return GIPC_ERR_INVALID_ARG;
     ctx->err.clear();
     if (!tune_ok(*tune))
-        return fail(ctx, GIPC_ERR_INVALID_ARG, "unsupported launch shape {%d, %d, %d}", tune->eval_waves,
-                    tune->row_lanes, tune->offdiag_waves);
+        return fail(ctx, GIPC_ERR_INVALID_ARG, "unsupported launch shape {%d, %d, %d, %d}", tune->eval_waves,
+                    tune->row_lanes, tune->offdiag_waves, tune->row_order);
     ctx->tune = *tune;
     return GIPC_OK;
 }
@@ -956,7 +964,7 @@ gipc_status gipc_autotune(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_param
     bt = INFINITY;
     for (int l : lanes) {
         float ms = time_it([&] {
-            return launch_rows_diag(3, ctx->V, as<int32_t>(ctx->order), as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr),
+            return launch_rows_diag(3, ctx->V, visit_order(ctx, t.row_order), as<int32_t>(ctx->diag_slot), as<int64_t>(ctx->cptr),
                                     as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main), as<double>(ctx->rec_extra), as<double>(ctx->rec_a1),
                                     e0, m0, diag, grad, as<double>(ctx->ev), A->val, A->dtype, ctx->nnzb, l, s);
         });
@@ -965,12 +973,29 @@ gipc_status gipc_autotune(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_param
     bt = INFINITY;
     for (int w : waves) {
         float ms = time_it([&] {
-            return launch_offdiag(ctx->V, as<int32_t>(ctx->order), as<int32_t>(ctx->row_ptr), as<int32_t>(ctx->diag_slot),
+            return launch_offdiag(ctx->V, visit_order(ctx, t.row_order), as<int32_t>(ctx->row_ptr), as<int32_t>(ctx->diag_slot),
                            ctx->nnzb, as<int32_t>(ctx->col_idx), as<int32_t>(ctx->tslot),
                                   as<int64_t>(ctx->cptr), as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main),
                                   as<double>(ctx->rec_extra), e0, m0, A->val, A->dtype, w, s);
         });
         if (ms < bt) { bt = ms; t.offdiag_waves = w; }
+    }
+    // the row order, both passes together with the chosen shapes
+    bt = INFINITY;
+    for (int o = 0; o < 2; ++o) {
+        float ms = time_it([&] {
+            hipError_t e2 = launch_rows_diag(3, ctx->V, visit_order(ctx, o), as<int32_t>(ctx->diag_slot),
+                                             as<int64_t>(ctx->cptr), as<uint32_t>(ctx->contrib),
+                                             as<double>(ctx->rec_main), as<double>(ctx->rec_extra),
+                                             as<double>(ctx->rec_a1), e0, m0, diag, grad, as<double>(ctx->ev),
+                                             A->val, A->dtype, ctx->nnzb, t.row_lanes, s);
+            if (e2 != hipSuccess) return e2;
+            return launch_offdiag(ctx->V, visit_order(ctx, o), as<int32_t>(ctx->row_ptr), as<int32_t>(ctx->diag_slot),
+                                  ctx->nnzb, as<int32_t>(ctx->col_idx), as<int32_t>(ctx->tslot),
+                                  as<int64_t>(ctx->cptr), as<uint32_t>(ctx->contrib), as<double>(ctx->rec_main),
+                                  as<double>(ctx->rec_extra), e0, m0, A->val, A->dtype, t.offdiag_waves, s);
+        });
+        if (ms < bt) { bt = ms; t.row_order = o; }
     }
     if (err == hipSuccess)
         err = launch_energy(as<double>(ctx->ev), as<int2>(ctx->pieces), ctx->npieces, as<int32_t>(ctx->poff),

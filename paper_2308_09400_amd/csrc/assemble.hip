@@ -89,7 +89,8 @@ __device__ __forceinline__ void store_block(void* val, int dtype, int64_t nnzb, 
 
 // LANES lanes per block row: each lane sums every LANES-th contribution of
 // the row's diagonal list, then a fixed xor butterfly combines the lanes
-// (same order on every run for a given LANES).
+// (same order on every run for a given LANES).  Rows are visited in `order`,
+// or in storage order when it is null.
 template <int LANES>
 __global__ void __launch_bounds__(kBlock) k_rows_diag(int mode, int32_t V, const int32_t* __restrict__ order,
                                                       const int32_t* __restrict__ diag_slot,
@@ -103,7 +104,7 @@ __global__ void __launch_bounds__(kBlock) k_rows_diag(int mode, int32_t V, const
     const int64_t gi = (int64_t)blockIdx.x * (kBlock / LANES) + threadIdx.x / LANES;
     const int lg = threadIdx.x % LANES;
     const bool valid = gi < V;
-    const int64_t r = valid ? order[gi] : 0;
+    const int64_t r = valid ? (order ? order[gi] : gi) : 0;
     double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     d3 g = mk(0, 0, 0);
     double e = 0.0;
@@ -176,7 +177,9 @@ __global__ void __launch_bounds__(kBlock) k_rows_diag(int mode, int32_t V, const
     }
 }
 
-// kOffLanes lanes per block row, rows visited in the order `order`: lane l
+// kOffLanes lanes per block row, rows visited in `order` (storage order when
+// null; the mirrored stores of adjacent rows then fall in adjacent slots of
+// each neighbour row): lane l
 // takes the row's blocks above the diagonal l, l + kOffLanes, ...; each sums
 // its contribution list in order, is stored, and is stored transposed in
 // the mirrored slot (the (c, r) list holds the same pairs with i and j
@@ -198,7 +201,7 @@ __global__ void __launch_bounds__(BLOCK) k_offdiag(int32_t V, const int32_t* __r
     const int64_t gi = (int64_t)blockIdx.x * (BLOCK / kOffLanes) + threadIdx.x / kOffLanes;
     if (gi >= V) return;
     const int lg = threadIdx.x % kOffLanes;
-    const int32_t r = order[gi];
+    const int32_t r = order ? order[gi] : (int32_t)gi;
     const int32_t end = row_ptr[r + 1];
     for (int32_t s = diag_slot[r] + 1 + lg; s < end; s += kOffLanes) {
         const int32_t t = tslot[s];

@@ -118,7 +118,7 @@ struct gipc_ctx {
     uint64_t mfg_gen = 0;    // eval_gen the vectors in mfg belong to
     int64_t ninc = 0;  // incidences (k, i) of the build: sum of the stencil sizes
     // launch shapes (gipc_tune)
-    gipc_tune tune{4, 16, 4};
+    gipc_tune tune{4, 16, 4, 0};
     // PCG workspace
     gipc::DevBuf r, z, p, q, p32, minv, part, scal;
     // scan scratch
@@ -198,14 +198,14 @@ hipError_t launch_energy(const double* ev, const int2* pieces, int32_t npieces, 
 // ---- assemble.hip
 // mode bit 1: gradient and per-vertex energy shares, bit 2: diagonal block
 // values; lanes per row: 4, 8, 16 or 32
-// rows are visited in the order `order` (a permutation of 0..V-1)
+// rows are visited in the order `order` (a permutation of 0..V-1; null: 0..V-1)
 hipError_t launch_rows_diag(int mode, int32_t V, const int32_t* order, const int32_t* diag_slot, const int64_t* cptr,
                             const uint32_t* contrib, const double* rec_main, const double* rec_extra,
                             const double* rec_a1, int64_t e0,
                             int64_t m0, const double* diag, double* grad, double* ev, void* val, int dtype,
                             int64_t nnzb, int lanes, hipStream_t s);
 // blocks above the diagonal are summed once and stored with their
-// transpose at tslot, row by row in the order `order`; waves: workgroup size
+// transpose at tslot, row by row in the order `order` (null: storage order); waves: workgroup size
 // in wavefronts (1, 2, 4 or 8)
 hipError_t launch_offdiag(int32_t V, const int32_t* order, const int32_t* row_ptr, const int32_t* diag_slot,
                           int64_t nnzb, const int32_t* col_idx, const int32_t* tslot,

@@ -189,7 +189,7 @@ def test_autotune(gp, tmp_path):
     cache = tmp_path / "tune.json"
     best = gp.autotune(ctx, X, prm, A, diag=diag, x_rest=XR, reps=3, cache=str(cache), key="small")
     assert best["eval_waves"] in (1, 2, 4, 8) and best["offdiag_waves"] in (1, 2, 4, 8)
-    assert best["row_lanes"] in (4, 8, 16, 32)
+    assert best["row_lanes"] in (4, 8, 16, 32) and best["row_order"] in (0, 1)
     assert gp.get_tune(ctx) == best
     E1, g1 = gp.eval_assemble(ctx, X, prm, A, diag=diag, x_rest=XR)
     assert torch.allclose(E1, E0, rtol=1e-12, atol=0)
@@ -201,6 +201,15 @@ def test_autotune(gp, tmp_path):
     assert again == best and gp.get_tune(ctx) == best
     with pytest.raises(gp.GipcError):
         gp.set_tune(ctx, 3, 16, 4)
+    with pytest.raises(gp.GipcError):
+        gp.set_tune(ctx, 4, 16, 4, 2)
+    # the row order changes only the schedule: the same bits
+    out = []
+    for order in (0, 1):
+        gp.set_tune(ctx, 4, 16, 4, order)
+        E, g = gp.eval_assemble(ctx, X, prm, A, diag=diag, x_rest=XR)
+        out.append((E.clone(), g.clone(), A.val.clone()))
+    assert all(torch.equal(a, b) for a, b in zip(out[0], out[1]))
     ctx.close()
 
 
