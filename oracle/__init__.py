@@ -75,6 +75,10 @@ def lib():
                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), dp,
                                      vp, vp, vp, ctypes.POINTER(ctypes.c_int)]
         L.orc_pair_local.restype = ctypes.c_int
+        L.orc_pair_exact.argtypes = [vp, vp, vp, ctypes.POINTER(Params), vp, vp]
+        L.orc_pair_exact.restype = ctypes.c_int
+        L.orc_eval_exact.argtypes = [i32, vp, vp, i64, vp, ctypes.POINTER(Params), ctypes.c_int, vp, vp]
+        L.orc_eval_exact.restype = ctypes.c_int
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_stencil.argtypes = [vp, vp]
@@ -209,6 +213,36 @@ def eval_xproj(x, tuples, prm=None, x_rest=None, nthreads=0):
                             int(nthreads), out.ctypes.data) < 0:
         raise ValueError("malformed tuple or vertex index out of range")
     return out.reshape(-1, 12, 12)
+
+
+def pair_exact(tuple4, xs, xr=None, prm=None):
+    """Exact Hessian of one pair's energy and its numeric PSD projection
+    (both [12][12]); the traditional route of Table 1."""
+    prm = prm or params()
+    t = np.ascontiguousarray(tuple4, dtype=np.int32)
+    xs = _pad4(xs)
+    xr_a = None if xr is None else _pad4(xr)
+    H = np.zeros(144)
+    Hp = np.zeros(144)
+    if lib().orc_pair_exact(t.ctypes.data, xs.ctypes.data, _ptr(xr_a), ctypes.byref(prm), H.ctypes.data,
+                            Hp.ctypes.data) < 0:
+        raise ValueError("malformed tuple")
+    return H.reshape(12, 12), Hp.reshape(12, 12)
+
+
+def eval_exact(x, tuples, prm=None, x_rest=None, nthreads=0, want_exact=True, want_proj=True):
+    """orc_pair_exact over a tuple list: (pairH or None, pairHp or None), [P][12][12]."""
+    prm = prm or params()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    t = np.ascontiguousarray(tuples, dtype=np.int32).reshape(-1, 4)
+    xr = None if x_rest is None else np.ascontiguousarray(x_rest, dtype=np.float64)
+    P = t.shape[0]
+    H = np.zeros((P, 12, 12)) if want_exact else None
+    Hp = np.zeros((P, 12, 12)) if want_proj else None
+    if lib().orc_eval_exact(int(x.shape[0]), x.ctypes.data, _ptr(xr), P, t.ctypes.data, ctypes.byref(prm),
+                            int(nthreads), _ptr(H), _ptr(Hp)) < 0:
+        raise ValueError("malformed tuple or vertex index out of range")
+    return H, Hp
 
 
 def friction_f(y, eps_v, dt):

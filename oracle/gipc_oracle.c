@@ -23,6 +23,10 @@
  *   8. contraction with the change-of-basis dJ/dx, whose only non-zero rows
  *      belong to the varying diagonal entries of J (Sec. 4, supplement Sec. 2);
  *      the d^2 J / dx^2 term is dropped as in the paper (Eq. 15, 22).
+ * Tuples follow the paper's sign encoding (Sec. 7.2), including the
+ * close-to-parallel point-edge / point-point encodings, whose distance is
+ * the point-segment / point-point sub-problem of Eq. 5 and whose mollifier
+ * is decided from their two edges like an edge-edge pair's.
  * Readings of points the paper leaves open are listed with the project's
  * design notes; every function below cites the passage it implements.
  */
@@ -41,7 +45,10 @@
  * decide (reading of Eq. 4-5 for degenerate primitives). */
 #define ORC_TOL 1e-10
 
-enum { K_EE = 0, K_PT = 1, K_PE = 2, K_PP = 3 };
+/* tuple kinds: edge-edge, point-triangle, point-edge, point-point, and the
+ * point-edge / point-point pairs cut from a close-to-parallel edge-edge pair
+ * (the paper's encodings with a negative second entry, Sec. 7.2) */
+enum { K_EE = 0, K_PT = 1, K_PE = 2, K_PP = 3, K_PE_PAR = 4, K_PP_PAR = 5 };
 
 static double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 static void sub3(const double* a, const double* b, double* o) { o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2]; }
@@ -152,6 +159,8 @@ typedef struct {
     double coef[4]; /* closest points: p* - q* = sum_k coef[k] x_k */
     double w[3];    /* p* - q* */
     int sub;        /* ORC_PT / PE / PP / EE */
+    int sp[4];      /* slots of the winning sub-problem: PT, EE all four; PE
+                       (point, segment end, segment end, -1); PP (point, point, -1, -1) */
 } orc_dist;
 
 /* point P against segment AB, parameter clamped to [0, 1] */
@@ -169,13 +178,23 @@ static double seg_closest(const double* P, const double* A, const double* B, dou
 
 /* keep candidate if strictly closer (first candidate wins ties: the fixed
  * enumeration order is the tie-break) */
-static void keep(orc_dist* best, double d2, const double coef[4], const double w[3], int sub) {
+static void keep(orc_dist* best, double d2, const double coef[4], const double w[3], int sub, int s0, int s1,
+                 int s2, int s3) {
     if (d2 < best->d2) {
         best->d2 = d2;
         memcpy(best->coef, coef, sizeof(double) * 4);
         memcpy(best->w, w, sizeof(double) * 3);
         best->sub = sub;
+        best->sp[0] = s0; best->sp[1] = s1; best->sp[2] = s2; best->sp[3] = s3;
     }
+}
+
+/* point slot P against segment slots A B with clamped parameter a: the
+ * sub-problem kept, point-edge inside the segment, point-point at an end */
+static void keep_seg(orc_dist* best, double d2, const double coef[4], const double w[3], double a, int P, int A,
+                     int B) {
+    if (a > 0.0 && a < 1.0) keep(best, d2, coef, w, ORC_PE, P, A, B, -1);
+    else keep(best, d2, coef, w, ORC_PP, P, a <= 0.0 ? A : B, -1, -1);
 }
 
 /* Eq. 4: point p = X[0] against triangle X[1], X[2], X[3]. */
@@ -193,7 +212,7 @@ static void dist_pt(const double X[4][3], orc_dist* o) {
             double w[3];
             for (int d = 0; d < 3; ++d) w[d] = p[d] - (t0[d] + be1 * e1[d] + be2 * e2[d]);
             double coef[4] = {1.0, -(1.0 - be1 - be2), -be1, -be2};
-            keep(o, dot3(w, w), coef, w, ORC_PT);
+            keep(o, dot3(w, w), coef, w, ORC_PT, 0, 1, 2, 3);
         }
     }
     static const int segs[3][2] = {{1, 2}, {2, 3}, {3, 1}};
@@ -203,7 +222,7 @@ static void dist_pt(const double X[4][3], orc_dist* o) {
         double d2 = seg_closest(p, X[ia], X[ib], &a, w);
         double coef[4] = {1.0, 0.0, 0.0, 0.0};
         coef[ia] = -(1.0 - a); coef[ib] = -a;
-        keep(o, d2, coef, w, (a > 0.0 && a < 1.0) ? ORC_PE : ORC_PP);
+        keep_seg(o, d2, coef, w, a, 0, ia, ib);
     }
 }
 
@@ -213,7 +232,7 @@ static void dist_pe(const double X[4][3], orc_dist* o) {
     double a, w[3];
     double d2 = seg_closest(X[0], X[1], X[2], &a, w);
     double coef[4] = {1.0, -(1.0 - a), -a, 0.0};
-    keep(o, d2, coef, w, (a > 0.0 && a < 1.0) ? ORC_PE : ORC_PP);
+    keep_seg(o, d2, coef, w, a, 0, 1, 2);
 }
 
 static void dist_pp(const double X[4][3], orc_dist* o) {
@@ -221,7 +240,27 @@ static void dist_pp(const double X[4][3], orc_dist* o) {
     double w[3];
     sub3(X[0], X[1], w);
     double coef[4] = {1.0, -1.0, 0.0, 0.0};
-    keep(o, dot3(w, w), coef, w, ORC_PP);
+    keep(o, dot3(w, w), coef, w, ORC_PP, 0, 1, -1, -1);
+}
+
+/* Eq. 5 restricted to one boundary sub-problem: point X[0] (an endpoint of
+ * edge X[0]X[1]) against segment X[2]X[3] -- the point-edge pair of a
+ * close-to-parallel edge-edge pair (Sec. 7.2 encodings). */
+static void dist_pe_par(const double X[4][3], orc_dist* o) {
+    o->d2 = INFINITY; o->sub = ORC_INACTIVE;
+    double a, w[3];
+    double d2 = seg_closest(X[0], X[2], X[3], &a, w);
+    double coef[4] = {1.0, 0.0, -(1.0 - a), -a};
+    keep_seg(o, d2, coef, w, a, 0, 2, 3);
+}
+
+/* point X[0] against point X[2] (endpoints of edges X[0]X[1] and X[2]X[3]) */
+static void dist_pp_par(const double X[4][3], orc_dist* o) {
+    o->d2 = INFINITY; o->sub = ORC_INACTIVE;
+    double w[3];
+    sub3(X[0], X[2], w);
+    double coef[4] = {1.0, 0.0, -1.0, 0.0};
+    keep(o, dot3(w, w), coef, w, ORC_PP, 0, 2, -1, -1);
 }
 
 /* Eq. 5: edge X[0]X[1] against edge X[2]X[3]. */
@@ -238,7 +277,7 @@ static void dist_ee(const double X[4][3], orc_dist* o) {
             double w[3];
             for (int d = 0; d < 3; ++d) w[d] = (X[0][d] + g1 * a[d]) - (X[2][d] + g2 * b[d]);
             double coef[4] = {1.0 - g1, g1, -(1.0 - g2), -g2};
-            keep(o, dot3(w, w), coef, w, ORC_EE);
+            keep(o, dot3(w, w), coef, w, ORC_EE, 0, 1, 2, 3);
         }
     }
     /* boundary: an endpoint of one edge against the other edge */
@@ -253,7 +292,8 @@ static void dist_ee(const double X[4][3], orc_dist* o) {
             for (int d = 0; d < 3; ++d) w[d] = -wq[d];
             coef[0] = 1.0 - al; coef[1] = al; coef[s] = -1.0;
         }
-        keep(o, d2, coef, w, (al > 0.0 && al < 1.0) ? ORC_PE : ORC_PP);
+        if (s < 2) keep_seg(o, d2, coef, w, al, s, 2, 3);
+        else keep_seg(o, d2, coef, w, al, s, 0, 1);
     }
 }
 
@@ -269,13 +309,33 @@ static int decode(const int32_t t[4], int32_t vid[4], int* kind) {
         return 4;
     }
     vid[0] = -t[0] - 1;
-    if (t[1] < 0) return -1;
+    if (t[1] < 0) { /* close to parallel: [-p, -o, e0, -e1] or [-p, -o, -q, -r] */
+        if (t[3] >= 0 || t[2] == INT32_MIN || t[3] == INT32_MIN) return -1;
+        vid[1] = -t[1] - 1;
+        vid[3] = -t[3] - 1;
+        if (t[2] >= 0) { vid[2] = t[2]; *kind = K_PE_PAR; }
+        else { vid[2] = -t[2] - 1; *kind = K_PP_PAR; }
+        return 4;
+    }
     vid[1] = t[1];
     if (t[2] >= 0 && t[3] >= 0) { vid[2] = t[2]; vid[3] = t[3]; *kind = K_PT; return 4; }
     if (t[2] >= 0 && t[3] == -1) { vid[2] = t[2]; *kind = K_PE; return 3; }
     if (t[2] == -1 && t[3] == -1) { *kind = K_PP; return 2; }
     return -1;
 }
+
+/* distance of a decoded tuple: its constrained minimum (Eq. 4 / Eq. 5) */
+static void dist_of(int kind, const double X[4][3], orc_dist* D) {
+    if (kind == K_PT) dist_pt(X, D);
+    else if (kind == K_EE) dist_ee(X, D);
+    else if (kind == K_PE) dist_pe(X, D);
+    else if (kind == K_PE_PAR) dist_pe_par(X, D);
+    else if (kind == K_PP_PAR) dist_pp_par(X, D);
+    else dist_pp(X, D);
+}
+
+/* the kinds built on two edges X[0]X[1], X[2]X[3]: the mollifier applies */
+static int edge_family(int kind) { return kind == K_EE || kind == K_PE_PAR || kind == K_PP_PAR; }
 
 int orc_num_threads(void) {
 #ifdef _OPENMP
@@ -335,10 +395,7 @@ static int pair_local_impl(const int32_t tuple[4], const double* xs, const doubl
         for (int d = 0; d < 3; ++d) X[k][d] = (k < nv) ? xs[3 * k + d] : 0.0;
 
     orc_dist D;
-    if (kind == K_PT) dist_pt(X, &D);
-    else if (kind == K_EE) dist_ee(X, &D);
-    else if (kind == K_PE) dist_pe(X, &D);
-    else dist_pp(X, &D);
+    dist_of(kind, X, &D);
     *dist2 = D.d2;
 
     const double dhat = prm->dhat, kappa = prm->kappa;
@@ -358,7 +415,7 @@ static int pair_local_impl(const int32_t tuple[4], const double* xs, const doubl
     int moll = 0;
     double cpar = 0.0, e = 1.0, de = 0.0, d2e = 0.0, gsc[12];
     memset(gsc, 0, sizeof(gsc));
-    if (kind == K_EE && prm->mollify) {
+    if (edge_family(kind) && prm->mollify) {
         double a[3], b[3], n[3], ar[3], br[3];
         sub3(X[1], X[0], a); sub3(X[3], X[2], b); cross3_acc(a, b, n);
         cpar = dot3(n, n);
@@ -611,6 +668,227 @@ int orc_eval_xproj(int32_t V, const double* x, const double* x_rest, int64_t P, 
     return 0;
 }
 
+/* ------------------------------------------------- exact local Hessian */
+
+/* The traditional route the paper's Table 1 compares against ("construct,
+ * then numerically project"): the exact Hessian of one pair's energy
+ * kappa e(c) b(g(x)), g = d^2 / dhat^2, with d^2 the squared distance of the
+ * pair's sub-problem (Eq. 4 / Eq. 5 at the active set found at x) -- Eq. 15
+ * with the d^2 J / dx^2 term kept, or Eq. 22 without dropping b_d grad^2 d
+ * -- projected onto the PSD cone by the cyclic Jacobi routine above.  It is
+ * obtained by second-order forward differentiation: every quantity carries
+ * its value, gradient and Hessian in the 12 stencil coordinates, and the
+ * sub-type's distance is written as a closed form in the coordinates:
+ *   point-triangle  ((p - t0) . n)^2 / |n|^2,  n = (t1 - t0) x (t2 - t0)
+ *   edge-edge       ((a0 - b0) . n)^2 / |n|^2,  n = (a1 - a0) x (b1 - b0)
+ *   point-edge      |p - a|^2 - ((p - a) . (b - a))^2 / |b - a|^2
+ *   point-point     |p - q|^2
+ * and the parallelness c = |(x1 - x0) x (x3 - x2)|^2 of the mollifier. */
+
+typedef struct {
+    double v, g[12], h[144];
+} jet;
+
+static void j_const(jet* o, double c) {
+    memset(o, 0, sizeof(jet));
+    o->v = c;
+}
+static void j_var(jet* o, double c, int i) {
+    j_const(o, c);
+    o->g[i] = 1.0;
+}
+static void j_add(jet* o, const jet* a, const jet* b) {
+    o->v = a->v + b->v;
+    for (int i = 0; i < 12; ++i) o->g[i] = a->g[i] + b->g[i];
+    for (int i = 0; i < 144; ++i) o->h[i] = a->h[i] + b->h[i];
+}
+static void j_sub(jet* o, const jet* a, const jet* b) {
+    o->v = a->v - b->v;
+    for (int i = 0; i < 12; ++i) o->g[i] = a->g[i] - b->g[i];
+    for (int i = 0; i < 144; ++i) o->h[i] = a->h[i] - b->h[i];
+}
+/* product rule, to second order */
+static void j_mul(jet* o, const jet* a, const jet* b) {
+    jet r;
+    r.v = a->v * b->v;
+    for (int i = 0; i < 12; ++i) r.g[i] = a->g[i] * b->v + a->v * b->g[i];
+    for (int i = 0; i < 12; ++i)
+        for (int j = 0; j < 12; ++j)
+            r.h[12 * i + j] = a->h[12 * i + j] * b->v + a->v * b->h[12 * i + j] + a->g[i] * b->g[j] +
+                              b->g[i] * a->g[j];
+    *o = r;
+}
+/* f(a) with f, f', f'' at a->v: chain rule to second order */
+static void j_apply(jet* o, const jet* a, double f, double fp, double fpp) {
+    jet r;
+    r.v = f;
+    for (int i = 0; i < 12; ++i) r.g[i] = fp * a->g[i];
+    for (int i = 0; i < 12; ++i)
+        for (int j = 0; j < 12; ++j) r.h[12 * i + j] = fp * a->h[12 * i + j] + fpp * a->g[i] * a->g[j];
+    *o = r;
+}
+static void j_div(jet* o, const jet* a, const jet* b) {
+    jet inv;
+    const double y = b->v;
+    j_apply(&inv, b, 1.0 / y, -1.0 / (y * y), 2.0 / (y * y * y));
+    j_mul(o, a, &inv);
+}
+static void j3_sub(jet* o, const jet* a, const jet* b) {
+    for (int d = 0; d < 3; ++d) j_sub(&o[d], &a[d], &b[d]);
+}
+static void j3_dot(jet* o, const jet* a, const jet* b) {
+    jet t;
+    j_mul(o, &a[0], &b[0]);
+    j_mul(&t, &a[1], &b[1]);
+    j_add(o, o, &t);
+    j_mul(&t, &a[2], &b[2]);
+    j_add(o, o, &t);
+}
+static void j3_cross(jet* o, const jet* a, const jet* b) {
+    jet t, u;
+    for (int d = 0; d < 3; ++d) {
+        const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+        j_mul(&t, &a[d1], &b[d2]);
+        j_mul(&u, &a[d2], &b[d1]);
+        j_sub(&o[d], &t, &u);
+    }
+}
+/* (r . n)^2 / |n|^2 with n = e x f */
+static void j_plane_d2(jet* o, const jet* r, const jet* e, const jet* f) {
+    jet n[3], rn, nn;
+    j3_cross(n, e, f);
+    j3_dot(&rn, r, n);
+    j3_dot(&nn, n, n);
+    j_mul(&rn, &rn, &rn);
+    j_div(o, &rn, &nn);
+}
+
+/* exact Hessian H and its projection Hp ([12][12] over the stencil slots;
+ * nullable) of one pair; returns -1 on a malformed tuple, 0 otherwise
+ * (inactive or degenerate pairs give zeros) */
+int orc_pair_exact(const int32_t tuple[4], const double* xs, const double* xr, const orc_params* prm, double* H,
+                   double* Hp) {
+    int32_t vid[4];
+    int kind;
+    const int nv = decode(tuple, vid, &kind);
+    if (H) memset(H, 0, sizeof(double) * 144);
+    if (Hp) memset(Hp, 0, sizeof(double) * 144);
+    if (nv < 0) return -1;
+    double X[4][3];
+    for (int k = 0; k < 4; ++k)
+        for (int d = 0; d < 3; ++d) X[k][d] = (k < nv) ? xs[3 * k + d] : 0.0;
+    orc_dist D;
+    dist_of(kind, X, &D);
+    const double dhat = prm->dhat, kappa = prm->kappa;
+    if (!(D.d2 > 0.0) || !isfinite(D.d2)) return 0;
+    const double g0 = D.d2 / (dhat * dhat);
+    if (g0 >= 1.0) return 0;
+
+    jet x[4][3];
+    for (int k = 0; k < 4; ++k)
+        for (int d = 0; d < 3; ++d) j_var(&x[k][d], X[k][d], 3 * k + d);
+    /* squared distance of the winning sub-problem */
+    jet d2;
+    if (D.sub == ORC_PT || D.sub == ORC_EE) {
+        jet r[3], e[3], f[3];
+        if (D.sub == ORC_PT) {
+            j3_sub(r, x[0], x[1]); j3_sub(e, x[2], x[1]); j3_sub(f, x[3], x[1]);
+        } else {
+            j3_sub(r, x[0], x[2]); j3_sub(e, x[1], x[0]); j3_sub(f, x[3], x[2]);
+        }
+        j_plane_d2(&d2, r, e, f);
+    } else if (D.sub == ORC_PE) {
+        jet r[3], e[3], rr, re, ee, t;
+        j3_sub(r, x[D.sp[0]], x[D.sp[1]]);
+        j3_sub(e, x[D.sp[2]], x[D.sp[1]]);
+        j3_dot(&rr, r, r); j3_dot(&re, r, e); j3_dot(&ee, e, e);
+        j_mul(&re, &re, &re);
+        j_div(&t, &re, &ee);
+        j_sub(&d2, &rr, &t);
+    } else {
+        jet r[3];
+        j3_sub(r, x[D.sp[0]], x[D.sp[1]]);
+        j3_dot(&d2, r, r);
+    }
+    /* barrier of the gap g = d^2 / dhat^2 */
+    jet gj, E;
+    j_apply(&gj, &d2, d2.v / (dhat * dhat), 1.0 / (dhat * dhat), 0.0);
+    double b, db, d2b;
+    orc_barrier(gj.v, dhat, prm->eq12, &b, &db, &d2b);
+    j_apply(&E, &gj, b, db, d2b);
+    /* mollifier of the edge-edge family (Eq. 25) */
+    if (edge_family(kind) && prm->mollify) {
+        const double* R = xr ? xr : xs;
+        double ar[3], br[3];
+        sub3(R + 3, R + 0, ar); sub3(R + 9, R + 6, br);
+        const double epsx = prm->epsx_ratio * dot3(ar, ar) * dot3(br, br);
+        jet a[3], bb[3], n[3], c, ej;
+        j3_sub(a, x[1], x[0]); j3_sub(bb, x[3], x[2]);
+        j3_cross(n, a, bb);
+        j3_dot(&c, n, n);
+        if (c.v < epsx) {
+            double e, de, d2e;
+            orc_mollifier(c.v, epsx, &e, &de, &d2e);
+            j_apply(&ej, &c, e, de, d2e);
+            j_mul(&E, &E, &ej);
+        }
+    }
+    for (int i = 0; i < 144; ++i) E.h[i] *= kappa;
+    /* exactly symmetric (the jets carry both orders of every product) */
+    for (int i = 0; i < 12; ++i)
+        for (int j = 0; j < i; ++j) {
+            const double m = 0.5 * (E.h[12 * i + j] + E.h[12 * j + i]);
+            E.h[12 * i + j] = E.h[12 * j + i] = m;
+        }
+    if (H) memcpy(H, E.h, sizeof(double) * 144);
+    if (Hp) {
+        /* PSD projection of the stencil's 3 nv x 3 nv block by Jacobi */
+        const int n = 3 * nv;
+        double A[144], lam[12], V[144];
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) A[n * i + j] = E.h[12 * i + j];
+        orc_jacobi_eig(n, A, lam, V);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double acc = 0.0;
+                for (int k = 0; k < n; ++k)
+                    if (lam[k] > 0.0) acc += V[n * i + k] * lam[k] * V[n * j + k];
+                Hp[12 * i + j] = acc;
+            }
+    }
+    return 0;
+}
+
+int orc_eval_exact(int32_t V, const double* x, const double* x_rest, int64_t P, const int32_t* tuples,
+                   const orc_params* prm, int nthreads, double* pairH, double* pairHp) {
+    for (int64_t p = 0; p < P; ++p) {
+        int32_t vid[4];
+        int nv = orc_stencil(tuples + 4 * p, vid);
+        if (nv < 0) return -1;
+        for (int k = 0; k < nv; ++k)
+            if (vid[k] < 0 || vid[k] >= V) return -1;
+    }
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t p = 0; p < P; ++p) {
+        const int32_t* t = tuples + 4 * p;
+        int32_t vid[4];
+        int nv = orc_stencil(t, vid);
+        double xs[12] = {0}, xr[12] = {0};
+        for (int k = 0; k < nv; ++k)
+            for (int d = 0; d < 3; ++d) {
+                xs[3 * k + d] = x[3 * (int64_t)vid[k] + d];
+                xr[3 * k + d] = (x_rest ? x_rest : x)[3 * (int64_t)vid[k] + d];
+            }
+        orc_pair_exact(t, xs, xr, prm, pairH ? pairH + 144 * p : NULL, pairHp ? pairHp + 144 * p : NULL);
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------- friction */
 
 /* f0, f1 = f0' and f1' of the smooth static-to-dynamic transition
@@ -655,17 +933,14 @@ int orc_friction_pair(const int32_t tuple[4], const double* xs_n, const double* 
     for (int k = 0; k < 4; ++k)
         for (int d = 0; d < 3; ++d) X[k][d] = (k < nv) ? xs_n[3 * k + d] : 0.0;
     orc_dist Dd;
-    if (kind == K_PT) dist_pt(X, &Dd);
-    else if (kind == K_EE) dist_ee(X, &Dd);
-    else if (kind == K_PE) dist_pe(X, &Dd);
-    else dist_pp(X, &Dd);
+    dist_of(kind, X, &Dd);
     const double dhat = prm->dhat, kappa = prm->kappa;
     if (!(Dd.d2 > 0.0) || !isfinite(Dd.d2)) return 0;
     const double g = Dd.d2 / (dhat * dhat);
     if (g >= 1.0) return 0;
     const double d = sqrt(Dd.d2);
     double e = 1.0;
-    if (kind == K_EE && prm->mollify) {
+    if (edge_family(kind) && prm->mollify) {
         double a[3], b[3], n[3], ar[3], br[3];
         sub3(X[1], X[0], a); sub3(X[3], X[2], b); cross3_acc(a, b, n);
         const double cpar = dot3(n, n);

@@ -6,14 +6,19 @@
  * code with the HIP library.  Only the tests, the smoke check and the CPU
  * baseline leg of the benchmark may load it.
  *
- * Contact tuples use the paper's sign encoding (Sec. 6.2, "Data structures"):
- *   [a0, a1, b0, b1]          edge-edge pair (a1 may be -(v+1): same pair)
+ * Contact tuples use the paper's sign encoding (Sec. 7.2, "Data structures"):
+ *   [a0, a1, b0, b1]          edge-edge pair (a1 may be -(v+1): close to parallel)
  *   [-(p+1), t0, t1, t2]      point-triangle pair
  *   [-(p+1), e0, e1, -1]      point-edge pair
  *   [-(p+1), q, -1, -1]       point-point pair
+ *   [-(p+1), -(o+1), e0, -(e1+1)]     point p of edge (p, o) vs edge (e0, e1),
+ *   [-(p+1), -(o+1), -(q+1), -(r+1)]  point p of edge (p, o) vs point q of
+ *                             edge (q, r): the close-to-parallel encodings
  * Every pair's distance is the constrained minimum over its primitives
- * (Eq. 4 / Eq. 5, point-edge as the segment sub-problem of Eq. 4).  The
- * mollifier applies to the edge-edge kind.  Other sign patterns are rejected.
+ * (Eq. 4 / Eq. 5, point-edge as the segment sub-problem of Eq. 4, the last
+ * two as the point-segment / point-point sub-problems of Eq. 5).  The
+ * mollifier applies to the kinds built on two edges (edge-edge and the last
+ * two).  Other sign patterns are rejected.
  */
 #ifndef GIPC_ORACLE_H
 #define GIPC_ORACLE_H
@@ -79,6 +84,25 @@ int orc_pair_xproj(const int32_t tuple[4], const double* xs, const double* xr, c
 /* orc_pair_xproj's Px for every tuple of a list, pairPx [P][12][12]. */
 int orc_eval_xproj(int32_t V, const double* x, const double* x_rest, int64_t P, const int32_t* tuples,
                    const orc_params* prm, int nthreads, double* pairPx);
+
+/*
+ * The traditional route of the paper's Table 1 comparison for one pair: H,
+ * the exact Hessian of the pair's energy kappa e(c) b(g(x)) (Eq. 15 with the
+ * d^2 J / dx^2 term, equivalently Eq. 22 without dropping b_d grad^2 d), for
+ * the sub-problem of Eq. 4 / Eq. 5 active at x, by second-order forward
+ * differentiation of closed-form distances; and Hp, its projection onto the
+ * PSD cone by cyclic Jacobi rotations (negative eigenvalues clamped).  No
+ * filter (Eq. 23 belongs to the proxy).  [12][12] over the stencil slots,
+ * both nullable; inactive or degenerate pairs give zeros.  Returns -1 on a
+ * malformed tuple.
+ */
+int orc_pair_exact(const int32_t tuple[4], const double* xs, const double* xr, const orc_params* prm, double* H,
+                   double* Hp);
+
+/* orc_pair_exact for every tuple of a list: pairH, pairHp [P][12][12]
+ * (nullable).  Returns -1 on a malformed tuple or index. */
+int orc_eval_exact(int32_t V, const double* x, const double* x_rest, int64_t P, const int32_t* tuples,
+                   const orc_params* prm, int nthreads, double* pairH, double* pairHp);
 
 /* f0, f1 and f1' of the friction transition at y (h = dt). */
 void orc_friction_f(double y, double eps_v, double dt, double* f0, double* f1, double* df1);

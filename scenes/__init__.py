@@ -202,6 +202,11 @@ def decode_tuples(tuples: np.ndarray):
     st = t.copy()
     st[:, 0] = np.where(t[:, 0] < 0, -t[:, 0] - 1, t[:, 0])
     st[:, 1] = np.where(t[:, 1] < 0, -t[:, 1] - 1, t[:, 1])
+    # close-to-parallel point-edge / point-point encodings: the first two
+    # entries negative, then every negative entry is a vertex -(i+1)
+    par = (t[:, 0] < 0) & (t[:, 1] < 0)
+    for c in (2, 3):
+        st[:, c] = np.where(par & (t[:, c] < 0), -t[:, c] - 1, st[:, c])
     return kind, st
 
 
