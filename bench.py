@@ -1,6 +1,6 @@
 """Benchmark of the GIPC barrier hot path on one MI355X.
 
-Workload (default): 10 stacked cloth sheets of 256 x 256 vertices over the
+Headline workload: 10 stacked cloth sheets of 256 x 256 vertices over the
 unit square, sheet k at z = 0.6 k dhat with +-0.3 dhat per-vertex jitter, one
 sheet sheared by 1 degree, dhat = 1e-3, kappa = 1e4, mass 1e-3 and dt = 1e-2
 (diagonal term m / dt^2 = 10); contact candidates from an AABB broad phase
@@ -10,30 +10,32 @@ One step = the whole hot path on the resident candidate list:
   stage + pattern build (classification, type sort, BSR symbolic)
   + fused energy / gradient / proxy Hessian / BSR assembly
   + one BSR SpMV + 100 block-Jacobi PCG iterations on (M/dt^2 + H) d = -grad.
-`value` is candidate pairs per second through stage + build + eval/assembly
-(the metric's scope); the SpMV and PCG are timed in the same step and
-reported alongside.  Prints one JSON line.
+`value` is contact pairs per second -- the candidates that classification
+finds closer than dhat, each one a term of the barrier sum -- through stage
++ build + eval/assembly (the metric's scope); candidate and staged-pair rates
+are reported beside it, and the SpMV and PCG are timed in the same step.
+Prints one JSON line.
 
---workload batch64 is the batching extension: 64 two-sheet scenes of 32..256
-vertices per side with per-scene dhat log-uniform in [1e-4, 1e-2] in one
-batch; a step is the batched stage + build and the eval + assembly replayed
-from a HIP graph (FP32 blocks); the same scenes one context at a time, and
-FP64 blocks without the graph, are timed once afterwards for comparison, and so
-is the plain path: one context per scene, no merging of duplicate
-constraints, evaluation and assembly as separate calls, FP64 blocks.
+After the headline steps the default run also measures the two targets of
+the extensions on their own workloads (`targets` in the JSON; skip with
+--no-targets), with contact candidates generated on the GPU:
+  batch64: 64 two-sheet scenes of 32..256 vertices per side with per-scene
+    dhat log-uniform in [1e-4, 1e-2] in one batch; a step is the batched
+    stage + build and the eval + assembly replayed from a HIP graph (FP32
+    blocks); against it the plain path: one context per scene, no merging
+    of duplicate constraints, evaluation and assembly as separate calls,
+    FP64 blocks, and the HBM fraction of the graph step;
+  sheets40: 40 sheets (seed 5), FP32 Hessian blocks and FP32 SpMV, PCG to
+    ||r|| / ||b|| <= 1e-6; the FP32 product and PCG iteration against the
+    HBM roofline, and the FP64 path once on the same pattern for the
+    comparison (block error, iterations, PCG time, solution difference).
+--workload batch64 / sheets40 run one of them alone as the headline line.
 
---workload sheets40 is the precision mode at four times the size: 40 sheets
-(seed 5), FP32 Hessian blocks and FP32 SpMV, PCG to ||r|| / ||b|| <= 1e-6
-inside the step; after the timed steps the FP64 path runs once on the same
-pattern for the comparison (block error, iterations, PCG time, solution
-difference).
-
-After the timed steps, every single-scene workload also runs the
-matrix-free operator once against the FP64 BSR matrix of the same eval (one
-product each; the PCG of the step both ways), reported under
-`matrix_free`; the default workload also times the dense projected proxy
-Hessians of all staged pairs from the analytic eigensystems against the
-numeric baseline (x-space Jacobi projection), under `numeric_eigen_baseline`,
+After the timed steps the headline workload also runs the matrix-free
+operator once against the FP64 BSR matrix of the same eval (one product
+each; the PCG of the step both ways), reported under `matrix_free`, times
+the dense projected proxy Hessians of all staged pairs from the analytic
+eigensystems against the numeric baseline under `numeric_eigen_baseline`,
 the lagged friction on the same pairs under `friction`, and the GPU contact
 candidates of the scene's surfaces under `candidates`.
 """
@@ -41,6 +43,7 @@ from __future__ import annotations
 
 import argparse
 import ctypes
+import hashlib
 import json
 import os
 import sys
@@ -55,12 +58,30 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, vendor figure
 FP64_VECTOR_TFLOPS = 78.6    # MI355X FP64 vector peak
 
-# HBM bytes per launch of the roofline kernel on the default workload, from
-# two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the counts of a
-# 2 GiB copy with the library's copy kernel (bytes = 2.0 x FETCH_SIZE +
-# 1.0 x WRITE_SIZE), as summarised in profiles/sheets10_path.md.  Valid only
-# for the kernel source those runs measured: reset to None when it changes.
-MEASURED_TRAFFIC = {"k_spmv_ent<false>": 1.799e9}
+# HBM bytes per launch of the roofline kernel on the headline workload from
+# two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by what the
+# same counters read for the library's copy kernel on a 2 GiB buffer.  The
+# figure holds only for the kernel source it was measured on: it is reported
+# only while the SHA-256 of that source file still matches, else null.
+MEASURED_TRAFFIC = {
+    "kernel": "k_spmv_ent<false>",
+    "bytes": 1.799e9,
+    "source": "profiles/sheets10_path.md (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-kernel calibration)",
+    "file": "paper_2308_09400_amd/csrc/solve.hip",
+    "sha256": None,
+}
+
+
+def _traffic_if_current():
+    m = MEASURED_TRAFFIC
+    try:
+        with open(os.path.join(ROOT, m["file"]), "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None, None
+    if m["sha256"] is None or h != m["sha256"]:
+        return None, f"null: {m['file']} changed since the counters were taken"
+    return m["bytes"], m["source"]
 
 
 def parse():
@@ -72,21 +93,38 @@ def parse():
     ap.add_argument("--pcg-iters", type=int, default=100)
     ap.add_argument("--cpu-sample", type=int, default=5_000_000, help="candidates in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
+    ap.add_argument("--no-targets", action="store_true", help="skip the batch64 / sheets40 target legs")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the matrix-free, numeric-eigen, friction and candidate legs")
     return ap.parse_args()
 
 
-def make_scene(name):
+def gpu_candidates(gp, x, s):
+    """Contact candidates of a scene's surfaces on the GPU (the same set as
+    the host grid generator; device int32 [P][4])."""
+    import torch
+    dev = x.device
+    ctx = gp.Context()
+    vobj = torch.tensor(s.vobj, dtype=torch.int32, device=dev)
+    tris = torch.tensor(s.tris, dtype=torch.int32, device=dev)
+    edges = torch.tensor(s.edges, dtype=torch.int32, device=dev)
+    t = gp.candidates(ctx, x, vobj, tris, edges, s.dhat)
+    ctx.close()
+    return t
+
+
+def make_scene(name, with_pairs=True):
     import scenes
     if name == "sheets10":
-        s = scenes.stacked_sheets(n_sheets=10, n=256, seed=2)
+        s = scenes.stacked_sheets(n_sheets=10, n=256, seed=2, with_pairs=with_pairs)
         desc = ("10 stacked 256x256 sheets, spacing 0.6 dhat, jitter +-0.3 dhat, 1 sheared sheet, dhat=1e-3, "
                 "kappa=1e4, m/dt^2=10, AABB candidates within dhat")
     elif name == "sheets40":
-        s = scenes.stacked_sheets(n_sheets=40, n=256, seed=5)
+        s = scenes.stacked_sheets(n_sheets=40, n=256, seed=5, with_pairs=with_pairs)
         desc = ("40 stacked 256x256 sheets, spacing 0.6 dhat, jitter +-0.3 dhat, 1 sheared sheet, dhat=1e-3, "
                 "kappa=1e4, m/dt^2=10, AABB candidates within dhat; FP32 blocks and SpMV, PCG to 1e-6")
     else:
-        s = scenes.two_sheets(n=16, seed=1)
+        s = scenes.two_sheets(n=16, seed=1, with_pairs=with_pairs)
         s.diag = np.full(s.V, 10.0)
         desc = "two 16x16 sheets, offset 0.5 dhat, jitter +-0.2 dhat, dhat=1e-3, kappa=1e4"
     return s, desc
@@ -280,20 +318,43 @@ def _median_ms(fn, reps, stream):
     return float(np.median(ts))
 
 
-def bench_batch(args):
+def _batch_scene_gpu(gp, dev):
+    """The 64-scene batch with each scene's candidates found on the GPU at
+    its own dhat (the host generator's set), concatenated with offsets."""
     import torch
-    import paper_2308_09400_amd as gp
     import scenes
+    rng_scenes = []
+    for s in range(64):
+        rng = np.random.default_rng(1000 + s)
+        r = int(rng.integers(32, 257))
+        dhat = float(10.0 ** rng.uniform(-4.0, -2.0))
+        rng_scenes.append(scenes.two_sheets(n=r, dhat=dhat, kappa=1e4, seed=1000 + s, with_pairs=False))
+    b = scenes.concat_scenes(rng_scenes, name="batch_two_sheets_64")
+    xs = torch.tensor(b.x, device=dev)
+    tups, pair_off = [], [0]
+    for s, sc in enumerate(b.scenes):
+        v0, v1 = int(b.vert_off[s]), int(b.vert_off[s + 1])
+        t = gpu_candidates(gp, xs[v0:v1], sc)
+        sc.tuples = t.cpu().numpy()
+        tups.append(torch.tensor(scenes.offset_tuples(sc.tuples, v0), device=dev))
+        pair_off.append(pair_off[-1] + sc.tuples.shape[0])
+    b.tuples = np.zeros((0, 4), np.int32)
+    b.pair_off = np.array(pair_off, np.int64)
+    return b, xs, torch.cat(tups)
+
+
+def batch_leg(gp, steps, warmup):
+    """The batching target: batched build + eval/assembly replayed from a HIP
+    graph (FP32 blocks) against the plain per-scene FP64 path."""
+    import torch
     dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
-    b = scenes.batch_two_sheets(S=64, seed_base=1000)
-    print(f"[bench] batch64: S={b.S} V={b.V} candidates={b.P} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr,
+    b, x, tup = _batch_scene_gpu(gp, dev)
+    P = int(tup.shape[0])
+    print(f"[bench] batch64: S={b.S} V={b.V} candidates={P} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr,
           flush=True)
-    x = torch.tensor(b.x, device=dev)
     xr = torch.tensor(b.x_rest, device=dev)
-    tup = torch.tensor(b.tuples, device=dev)
     diag = torch.full((b.V,), 10.0, dtype=torch.float64, device=dev)
     bt = gp.Batch(b.vert_off, b.dhat, b.kappa)
     prm = gp.params(batch=bt)
@@ -305,14 +366,14 @@ def bench_batch(args):
 
     # a rebuild invalidates a graph: each step times the build, captures the
     # graph again outside the timed events, then times its replay
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         gp.pairs_build(ctx, x, tup, prm, x_rest=xr)
         graph.close()
         graph = gp.Graph(ctx, x, prm, A32, diag=diag, x_rest=xr)
         graph.launch()
     torch.cuda.synchronize()
     build_ms, replay_ms = [], []
-    for _ in range(args.steps):
+    for _ in range(steps):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         e[0].record(stream)
         gp.pairs_build(ctx, x, tup, prm, x_rest=xr)
@@ -325,14 +386,18 @@ def bench_batch(args):
     build = float(np.median(build_ms))
     replay = float(np.median(replay_ms))
     path_ms = build + replay
-    value = b.P / (path_ms * 1e-3)
     nnzb = A32.nnzb
     V = b.V
+    n_active = int(info["n_active"])
     # algorithmic bytes of the numeric eval + assembly with a cached pattern:
     # staged pairs 16 B, positions and rest positions, gradient, BSR (FP32
     # values + column), row pointers, diagonal term, per-scene energies
     num_bytes = 16 * info["n_staged"] + 48 * V + 24 * V + nnzb * (36 + 4) + 4 * (V + 1) + 8 * V + 8 * b.S
     num_gbs = num_bytes / (replay * 1e-3) / 1e9
+    # the whole step from a fresh candidate list: candidates 16 B read once
+    # on top of the numeric bytes
+    path_bytes = num_bytes + 16 * P
+    path_gbs = path_bytes / (path_ms * 1e-3) / 1e9
 
     # the same pairs, FP64 blocks, eager eval_assemble (no graph) and the
     # unfused barrier_eval + assemble_bsr
@@ -349,7 +414,6 @@ def bench_batch(args):
     ctxs = []
     for s, sc in enumerate(b.scenes):
         v0, v1 = int(b.vert_off[s]), int(b.vert_off[s + 1])
-        p0, p1 = int(b.pair_off[s]), int(b.pair_off[s + 1])
         c = gp.Context()
         ps = gp.params(dhat=sc.dhat, kappa=sc.kappa)
         ctxs.append((c, ps, x[v0:v1], xr[v0:v1], torch.tensor(sc.tuples, device=dev), diag[v0:v1]))
@@ -384,66 +448,46 @@ def bench_batch(args):
         c.close()
     per_scene = float(np.median(per_ms))
     plain = float(np.median(plain_ms))
-
-    out = {
-        "metric": "contact pairs/s (energy+grad+proxy Hessian+BSR assembly), batched scenes",
-        "value": float(value),
-        "unit": "pairs/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+    return {
+        "workload": "64 two-sheet scenes, 32..256 vertices per side, dhat log-uniform in [1e-4, 1e-2], "
+                    "kappa=1e4, seeds 1000+s, AABB candidates within each scene's dhat (found on the GPU)",
+        "scenes": b.S, "vertices": V, "candidates": P, "active_pairs": n_active,
+        "staged_pairs": int(info["n_staged"]), "active_by_type": info["n_by_type"], "nnzb": int(nnzb),
+        "tune": tune,
+        "active_pairs_per_s": n_active / (path_ms * 1e-3),
         "ms_per_step": path_ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64 geometry, f32 blocks",
-        "data": "synthetic",
-        "config": {
-            "workload": "64 two-sheet scenes, 32..256 vertices per side, dhat log-uniform in [1e-4, 1e-2], "
-                        "kappa=1e4, seeds 1000+s, AABB candidates within each scene's dhat",
-            "scenes": b.S, "vertices": V, "candidates": b.P, "active_pairs": int(info["n_active"]),
-            "staged_pairs": int(info["n_staged"]),
-            "active_by_type": info["n_by_type"], "nnzb": int(nnzb), "tune": tune,
-        },
         "breakdown_ms": {"stage_build": build, "eval_assemble_graph_f32": replay,
                          "eval_assemble_eager_f64": fused64, "eval_then_assemble_f64": unfused64,
                          "per_scene_contexts_build_eval_assemble_f64": per_scene,
                          "plain_per_scene_unmerged_unfused_f64": plain},
         "speedup_vs_per_scene_contexts": per_scene / path_ms,
         "speedup_vs_plain": plain / path_ms,
-        "roofline": {"kernel": "eval + assembly graph (numeric, cached pattern)", "bound": "hbm",
-                     "achieved": float(num_gbs), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": float(num_gbs / HBM_PEAK_GBS), "traffic": None},
+        "target_speedup_vs_plain": 3.0,
+        "graph_step_gbs": num_gbs, "graph_step_hbm_frac": num_gbs / HBM_PEAK_GBS,
+        "graph_step_bytes": int(num_bytes),
+        "path_gbs": path_gbs, "path_hbm_frac": path_gbs / HBM_PEAK_GBS,
+        "target_hbm_frac": 0.60,
     }
-    print(json.dumps(out))
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (sharding is described, "
-                                   "not implemented)"}))
-        sys.exit(2)
-    if args.workload == "batch64":
-        return bench_batch(args)
+def single_run(gp, args, workload, steps, warmup, cands_on_gpu):
+    """One single-scene workload: timed steps of build + eval/assembly + SpMV
+    + PCG; returns the result dict and what the comparison legs need."""
     import torch
-    import paper_2308_09400_amd as gp
-
     dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
     t0 = time.perf_counter()
-    s, desc = make_scene(args.workload)
-    t_scene = time.perf_counter() - t0
-    print(f"[bench] scene {args.workload}: V={s.V} candidates={s.P} ({t_scene:.1f} s)", file=sys.stderr, flush=True)
-
-    prm = gp.params(dhat=s.dhat, kappa=s.kappa)
+    s, desc = make_scene(workload, with_pairs=not cands_on_gpu)
     x = torch.tensor(s.x, device=dev)
+    tup = gpu_candidates(gp, x, s) if cands_on_gpu else torch.tensor(s.tuples, device=dev)
+    P = int(tup.shape[0])
+    print(f"[bench] scene {workload}: V={s.V} candidates={P} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr,
+          flush=True)
+    prm = gp.params(dhat=s.dhat, kappa=s.kappa)
     xr = torch.tensor(s.x_rest, device=dev)
-    tup = torch.tensor(s.tuples, device=dev)
     diag = torch.tensor(s.diag, device=dev)
     ctx = gp.Context()
     stream = torch.cuda.current_stream()
-    mixed = args.workload == "sheets40"
+    mixed = workload == "sheets40"
     dt = gp.F32 if mixed else gp.F64
     rtol, maxit = (1e-6, 20000) if mixed else (0.0, args.pcg_iters)
 
@@ -466,16 +510,16 @@ def main():
             rec.append((ev, info, it, A.nnzb, rr))
         return E, y, A, d, b
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step(None)
     torch.cuda.synchronize()
     recs = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         last = step(recs)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    print(f"[bench] {args.steps} steps in {wall:.3f} s", file=sys.stderr, flush=True)
+    print(f"[bench] {workload}: {steps} steps in {wall:.3f} s", file=sys.stderr, flush=True)
 
     build_ms = np.array([r[0][0].elapsed_time(r[0][1]) for r in recs])
     evas_ms = np.array([r[0][1].elapsed_time(r[0][2]) for r in recs])
@@ -484,23 +528,28 @@ def main():
     step_ms = np.array([r[0][0].elapsed_time(r[0][5]) for r in recs])
     info, iters, nnzb = recs[-1][1], recs[-1][2], recs[-1][3]
     V = s.V
-    path_ms = build_ms + evas_ms
-    value = s.P / (np.median(path_ms) * 1e-3)
+    path_ms = float(np.median(build_ms + evas_ms))
+    n_active = int(info["n_active"])
     # algorithmic bytes of one BSR SpMV: blocks (9 values + 4 B column), row
     # pointers, x read once, y written once
     sv = 4 if mixed else 8
     spmv_bytes = nnzb * (9 * sv + 4) + 4 * (V + 1) + 3 * sv * V + 3 * sv * V
     spmv_gbs = spmv_bytes / (np.mean(spmv_ms) * 1e-3) / 1e9
+    # one PCG iteration: the product, plus the vector passes (x, r, z, p, q
+    # read or written, 13 passes of 3V FP64) and the inverse diagonal blocks
+    pcg_iter_ms = float(np.median(pcg_ms) / max(iters, 1))
+    pcg_iter_bytes = spmv_bytes + 13 * 24 * V + 72 * V
     # algorithmic bytes of stage + build + eval/assembly (metric scope):
-    # tuples 16 B, positions + rest read once, gradient written, BSR written
-    path_bytes = 16 * s.P + 48 * V + 24 * V + nnzb * (9 * sv + 4) + 4 * (V + 1) + 8 * V
+    # candidates 16 B, positions + rest read once, gradient written, BSR
+    # written, diagonal term
+    path_bytes = 16 * P + 48 * V + 24 * V + nnzb * (9 * sv + 4) + 4 * (V + 1) + 8 * V
     out = {
         "metric": "contact pairs/s (energy+grad+proxy Hessian+BSR assembly); BSR SpMV GB/s vs roofline",
-        "value": float(value),
+        "value": float(n_active / (path_ms * 1e-3)),
         "unit": "pairs/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": float(np.mean(step_ms)),
         "higher_is_better": True,
         "scaling": "weak",
@@ -510,60 +559,130 @@ def main():
         "config": {
             "workload": desc,
             "vertices": V,
-            "candidates": s.P,
-            "active_pairs": int(info["n_active"]),
+            "candidates": P,
+            "contact_pairs": n_active,
             "active_by_type": info["n_by_type"],
             "staged_pairs": int(info["n_staged"]),
             "nnzb": int(nnzb),
             "pcg_iters": int(iters),
             "pcg_rtol": rtol,
         },
+        "value_counts": "contact pairs = candidates closer than dhat after classification (one term of the "
+                        "barrier sum each); candidates and staged pairs (after merging duplicate point-edge / "
+                        "point-point constraints) are reported as rates beside it",
+        "candidates_per_s": float(P / (path_ms * 1e-3)),
+        "staged_pairs_per_s": float(info["n_staged"] / (path_ms * 1e-3)),
         "breakdown_ms": {
             "stage_build": float(np.median(build_ms)),
             "eval_assemble": float(np.median(evas_ms)),
             "spmv": float(np.median(spmv_ms)),
             "pcg": float(np.median(pcg_ms)),
-            "pcg_per_iter": float(np.median(pcg_ms) / max(iters, 1)),
+            "pcg_per_iter": pcg_iter_ms,
         },
-        "active_pairs_per_s": float(info["n_active"] / (np.median(path_ms) * 1e-3)),
-        "path_gbs": float(path_bytes / (np.median(path_ms) * 1e-3) / 1e9),
+        "path_gbs": float(path_bytes / (path_ms * 1e-3) / 1e9),
+        "path_hbm_frac": float(path_bytes / (path_ms * 1e-3) / 1e9 / HBM_PEAK_GBS),
         "spmv_gbs": float(spmv_gbs),
-        "roofline": {
-            "kernel": "k_spmv<float> (BSR SpMV by rows)" if mixed else "k_spmv_ent<false> (FP64 BSR SpMV, one lane per block)",
-            "bound": "hbm",
-            "achieved": float(spmv_gbs),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": float(spmv_gbs / HBM_PEAK_GBS),
-            "traffic": None if (mixed or args.workload != "sheets10") else MEASURED_TRAFFIC.get("k_spmv_ent<false>"),
-        },
+        "pcg_iter_gbs": float(pcg_iter_bytes / (pcg_iter_ms * 1e-3) / 1e9),
+        "pcg_iter_vs_spmv": float(pcg_iter_ms / np.mean(spmv_ms)),
     }
-    # achievable bandwidth of a plain streaming copy with the library's own
-    # kernel (reference for the roofline fraction; also the calibration
-    # kernel for the HBM byte counters)
+    traffic, tsrc = (None, None) if mixed else _traffic_if_current()
+    out["roofline"] = {
+        "kernel": "k_spmv<float> (FP32 BSR SpMV by rows)" if mixed
+        else "k_spmv_ent<false> (FP64 BSR SpMV, one lane per block)",
+        "bound": "hbm",
+        "achieved": float(spmv_gbs),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": float(spmv_gbs / HBM_PEAK_GBS),
+        "traffic": traffic,
+        "traffic_source": tsrc,
+        "bytes_per_launch": int(spmv_bytes),
+    }
+    return out, (ctx, s, x, xr, prm, diag, info, rtol, maxit, stream, last)
+
+
+def bandwidth_reference(gp, stream):
+    """Achievable HBM bandwidth with the library's own streaming kernels on a
+    2 GiB buffer: a copy (read + write) and a plain read."""
+    import torch
+    dev = torch.device("cuda", 0)
     nbytes = 2 << 30
     src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
     dst = torch.empty_like(src)
-    gp.copy(src, dst)
-    ce = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-    for i in range(5):
-        ce[i].record(stream)
-        gp.copy(src, dst)
-    ce[5].record(stream)
-    torch.cuda.synchronize()
-    copy_ms = np.mean([ce[i].elapsed_time(ce[i + 1]) for i in range(5)])
-    out["copy_gbs"] = float(2 * nbytes / (copy_ms * 1e-3) / 1e9)
-    out["roofline"]["frac_of_copy"] = float(spmv_gbs / out["copy_gbs"])
+    sink = torch.zeros(1, dtype=torch.int32, device=dev)
+    out = {}
+    for name, fn, moved in (("copy_gbs", lambda: gp.copy(src, dst), 2 * nbytes),
+                            ("read_gbs", lambda: gp.read(src, sink=sink), nbytes)):
+        fn()
+        ce = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        for i in range(5):
+            ce[i].record(stream)
+            fn()
+        ce[5].record(stream)
+        torch.cuda.synchronize()
+        ms = np.median([ce[i].elapsed_time(ce[i + 1]) for i in range(5)])
+        out[name] = float(moved / (ms * 1e-3) / 1e9)
     del src, dst
-    if mixed:
-        out["precision"] = precision_compare(gp, ctx, x, xr, prm, diag, last, stream)
-    out["matrix_free"] = matrix_free_compare(gp, ctx, x, xr, prm, diag, info, rtol, maxit, stream)
-    if args.workload == "sheets10":
-        out["numeric_eigen_baseline"] = numeric_compare(gp, ctx, x, xr, prm, info, stream)
-        out["friction"] = friction_compare(gp, ctx, x, xr, prm, diag, info, stream)
-        out["candidates"] = candidates_compare(gp, ctx, s, x, stream)
+    return out
+
+
+def sheets40_leg(gp, args):
+    """The precision target: FP32 blocks and SpMV on forty sheets, PCG to 1e-6,
+    against the HBM roofline; the FP64 path once for the comparison."""
+    out, (ctx, s, x, xr, prm, diag, info, rtol, maxit, stream, last) = single_run(gp, args, "sheets40", 2, 1, True)
+    leg = {k: out[k] for k in ("config", "breakdown_ms", "spmv_gbs", "pcg_iter_gbs", "pcg_iter_vs_spmv", "roofline")}
+    leg["value_contact_pairs_per_s"] = out["value"]
+    leg["spmv_hbm_frac"] = out["spmv_gbs"] / HBM_PEAK_GBS
+    leg["pcg_iter_hbm_frac"] = out["pcg_iter_gbs"] / HBM_PEAK_GBS
+    leg["precision"] = precision_compare(gp, ctx, x, xr, prm, diag, last, stream)
     ctx.close()
-    if not args.no_cpu:
+    return leg
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (sharding is described, "
+                                   "not implemented)"}))
+        sys.exit(2)
+    import torch
+    import paper_2308_09400_amd as gp
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    if args.workload == "batch64":
+        leg = batch_leg(gp, args.steps, args.warmup)
+        line = {"metric": "contact pairs/s (energy+grad+proxy Hessian+BSR assembly), batched scenes",
+                "value": leg["active_pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+                "warmup": args.warmup, "ms_per_step": leg["ms_per_step"], "higher_is_better": True,
+                "scaling": "weak", "vs_baseline": None, "dtype": "f64 geometry, f32 blocks", "data": "synthetic",
+                "config": {"workload": leg["workload"]}, "batch64": leg}
+        print(json.dumps(line))
+        return
+    workload = args.workload
+    out, (ctx, s, x, xr, prm, diag, info, rtol, maxit, stream, last) = single_run(
+        gp, args, workload, args.steps, args.warmup, workload == "sheets40")
+    bw = bandwidth_reference(gp, stream)
+    out["bandwidth_reference"] = bw
+    out["roofline"]["frac_of_copy"] = out["roofline"]["achieved"] / bw["copy_gbs"]
+    out["roofline"]["frac_of_read"] = out["roofline"]["achieved"] / bw["read_gbs"]
+    if workload == "sheets40":
+        out["precision"] = precision_compare(gp, ctx, x, xr, prm, diag, last, stream)
+    if not args.no_extras:
+        out["matrix_free"] = matrix_free_compare(gp, ctx, x, xr, prm, diag, info, rtol, maxit, stream)
+        if workload == "sheets10":
+            out["numeric_eigen_baseline"] = numeric_compare(gp, ctx, x, xr, prm, info, stream)
+            out["friction"] = friction_compare(gp, ctx, x, xr, prm, diag, info, stream)
+            out["candidates"] = candidates_compare(gp, ctx, s, x, stream)
+    ctx.close()
+    del x, xr, diag
+    if workload == "sheets10" and not args.no_targets:
+        torch.cuda.empty_cache()
+        out["targets"] = {"batch64": batch_leg(gp, 3, 1)}
+        torch.cuda.empty_cache()
+        out["targets"]["sheets40"] = sheets40_leg(gp, args)
+        torch.cuda.empty_cache()
+    if not args.no_cpu and workload == "sheets10":
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_sample)
         out["cpu_baseline_1thread"] = cpu_baseline(s, max(args.cpu_sample // 20, 1000), nthreads=1)
     print(json.dumps(out))

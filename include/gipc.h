@@ -41,7 +41,9 @@ typedef enum {
     GIPC_ERR_WORKSPACE = -5,     /* allocation failed or a documented capacity limit was exceeded */
     GIPC_ERR_BREAKDOWN = -6,     /* PCG: p^T A p <= 0 (A not positive definite) */
     GIPC_ERR_STATE = -7,         /* call order violated (e.g. eval before build) */
-    GIPC_WARN_NOT_CONVERGED = 1  /* PCG stopped at maxit above the tolerance */
+    GIPC_WARN_NOT_CONVERGED = 1, /* PCG stopped at maxit above the tolerance */
+    GIPC_WARN_STALE = 2          /* gipc_pairs_check: the staged pairs no longer match the tuples at x;
+                                    rebuild with gipc_pairs_build before evaluating there */
 } gipc_status;
 
 /* parameter flags */
@@ -87,15 +89,23 @@ typedef struct {
     const double* x_rest;
 } gipc_mesh;
 
-/* Contact tuples of vertex ids with the type in the signs (Sec. 6.2,
- * "Data structures"); device, int32 [P][4]:
- *   [a0, a1, b0, b1]        edge-edge pair (a1 may carry the nearly-parallel
- *                           flag -(a1+1); the mollifier is decided anyway)
- *   [-(p+1), t0, t1, t2]    point-triangle pair
- *   [-(p+1), e0, e1, -1]    point-edge pair
- *   [-(p+1), q, -1, -1]     point-point pair
+/* Contact tuples of vertex ids with the type in the signs (Sec. 7.2,
+ * "Data structures"; a negative entry -(i+1) stands for vertex i); device,
+ * int32 [P][4]:
+ *   [a0, a1, b0, b1]            edge-edge pair
+ *   [-(p+1), t0, t1, t2]        point-triangle pair
+ *   [-(p+1), e0, e1, -1]        point-edge pair
+ *   [-(p+1), q, -1, -1]         point-point pair
+ * and the close-to-parallel encodings (second entry negative):
+ *   [a0, -(a1+1), b0, b1]       edge-edge pair
+ *   [-(p+1), -(o+1), e0, -(e1+1)]   point p of edge (p, o) against edge (e0, e1)
+ *   [-(p+1), -(o+1), -(q+1), -(r+1)] point p of edge (p, o) against point q of edge (q, r)
  * Every pair's distance is the constrained minimum over its primitives
- * (Eq. 4 / Eq. 5); the library reduces it to its sub-type itself. */
+ * (Eq. 4 / Eq. 5; the last two are the point-segment and point-point
+ * sub-problems of Eq. 5); the library reduces it to its sub-type itself.
+ * Whether the mollifier of Eq. 25 applies is decided from the two edges
+ * (c = |a x b|^2 against eps_x) for every edge-edge family tuple, whatever
+ * its encoding says. */
 typedef struct {
     int64_t P;
     const int32_t* tuples;
@@ -141,6 +151,11 @@ typedef struct {
     int64_t nnzb;           /* blocks of the assembled matrix */
     int64_t n_contrib;      /* local-block contributions gathered by the assembly */
     int32_t max_row_pairs;  /* largest number of pairs touching one vertex */
+    int64_t n_degenerate_prims;  /* tuples with an edge of zero length or a triangle of zero area whose
+                                    distance is positive: evaluated by the remaining sub-problems of
+                                    Eq. 4 / Eq. 5 (the smallest over the triangle's edges, or over the
+                                    endpoints), counted here */
+    int64_t first_degenerate_prim; /* tuple index of the first one, -1 if none */
 } gipc_info;
 
 typedef struct gipc_ctx gipc_ctx;
@@ -177,6 +192,35 @@ const char* gipc_ctx_last_error(const gipc_ctx* ctx);
  */
 gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pairs* pairs,
                              const gipc_params* params, void* stream, gipc_info* info);
+
+/* Result of gipc_pairs_check (host struct). */
+typedef struct {
+    int64_t n_entered;     /* tuples closer than dhat at x that were not at the build */
+    int64_t n_left;        /* tuples active at the build, at or beyond dhat at x, whose staged sub-type
+                              formula also gives d >= dhat there (the evaluation drops them: harmless) */
+    int64_t n_changed;     /* tuples active at the build whose sub-type, stencil or mollifier decision
+                              differs at x, or that left dhat while their staged formula did not */
+    int64_t n_degenerate;  /* tuples at distance 0 or non-finite at x */
+    int64_t first;         /* index of the first tuple counted in n_entered or n_changed, -1 if none */
+} gipc_check;
+
+/*
+ * Whether the staged pairs of the last build still describe the tuples at
+ * positions mesh->x.  The evaluation entry points evaluate each staged pair
+ * with the sub-type formula fixed at the build (Eq. 4 / Eq. 5 reduced to the
+ * active constraints there): exact at the build's positions and wherever
+ * the constrained minimum keeps the same active set, but not once a point
+ * slides off a triangle or edge, a pair comes within dhat, or an edge pair
+ * crosses the mollifier threshold of Eq. 25.  This call classifies the same
+ * tuples (pairs: the build's list, unchanged; params as at the build) at
+ * mesh->x and compares tuple by tuple.  Returns GIPC_OK when the build still
+ * holds (n_entered = n_changed = 0), GIPC_WARN_STALE when it must be rebuilt
+ * before an evaluation at x, or an error: INVALID_ARG, STATE (no build, V,
+ * P or the batch differ from the build), INDEX (malformed tuples), HIP.
+ * out (host, nullable) receives the counts.  Synchronises `stream`.
+ */
+gipc_status gipc_pairs_check(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pairs* pairs,
+                             const gipc_params* params, gipc_check* out, void* stream);
 
 /* Counts of the last successful build (host copy, no synchronisation). */
 gipc_status gipc_get_info(const gipc_ctx* ctx, gipc_info* info);
@@ -333,18 +377,25 @@ gipc_status gipc_friction_eval(gipc_ctx* ctx, const double* x, double* energy, d
 /* methods of gipc_proxy_dense */
 #define GIPC_PROJ_ANALYTIC 0
 #define GIPC_PROJ_NUMERIC 1
+#define GIPC_PROJ_EXACT 2
 
 /*
  * Dense projected proxy Hessian of every staged pair of the last build at
  * positions mesh->x, for the comparison the paper makes in Table 1 (time
  * to construct and project a pair's 3n x 3n barrier Hessian).
  * GIPC_PROJ_ANALYTIC expands the factors of the analytic eigensystems
- * (Sec. 4.2-4.3, Eq. 18-21; Sec. 5.2, Eq. 32-36); GIPC_PROJ_NUMERIC builds
+ * (Sec. 5.2-5.3, Eq. 18-21; Sec. 6.2, Eq. 32-36); GIPC_PROJ_NUMERIC builds
  * kappa D^T H D with the unprojected inner Hessian (Eq. 16-17, 31) and
  * projects it in x-space by cyclic Jacobi rotations (negative eigenvalues
- * clamped), the traditional route.  Non-mollified pairs give the same
- * matrix both ways (rank one); mollified pairs differ where the inner 2x2
- * block is indefinite.  hess: device double [info.n_staged][12][12],
+ * clamped).  Non-mollified pairs give the same matrix both ways (rank one);
+ * mollified pairs differ where the inner 2x2 block is indefinite.
+ * GIPC_PROJ_EXACT is the traditional route the paper's table compares
+ * against: the exact Hessian of the pair's energy kappa e(c) b(g(x)) -- Eq. 15
+ * with the d^2 J / dx^2 term, i.e. Eq. 22 without dropping b_d grad^2 d, for
+ * the sub-problem staged at the build (no filter) -- projected onto the PSD
+ * cone by cyclic Jacobi rotations, on the complement of rigid translations
+ * (where that matrix has its whole range: it vanishes on translations).
+ * hess: device double [info.n_staged][12][12],
  * row-major, the leading 3n x 3n block filled (n = stencil vertices in
  * slot order, as gipc_pair_inspect reports them), the rest zero, times the
  * pair's multiplicity.  Does not touch the eval state.  Errors:
@@ -374,6 +425,13 @@ gipc_status gipc_pair_inspect(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_p
 /* Plain device-to-device copy of `bytes` bytes with the library's own
  * streaming kernel (bandwidth reference for roofline fractions). */
 gipc_status gipc_copy(const void* src, void* dst, int64_t bytes, void* stream);
+
+/* Streaming read of the first bytes - bytes % 16 bytes of src (device,
+ * 16-byte aligned) with the library's own read kernel: the read-bandwidth
+ * reference for roofline fractions.  sink: device, 4 bytes, written only if
+ * the xor of all words read equals 0x9e3779b9 (so that no load is
+ * dropped).  Errors: INVALID_ARG (negative size, NULL, misaligned src), HIP. */
+gipc_status gipc_read(const void* src, int64_t bytes, void* sink, void* stream);
 
 /*
  * Launch shapes of the evaluation and assembly kernels (per context).

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgipc.so")
 
 OK, ERR_INVALID_ARG, ERR_INDEX, ERR_DEGENERATE, ERR_HIP, ERR_WORKSPACE, ERR_BREAKDOWN, ERR_STATE = 0, -1, -2, -3, -4, -5, -6, -7
-WARN_NOT_CONVERGED = 1
+WARN_NOT_CONVERGED, WARN_STALE = 1, 2
 FLAG_FILTER, FLAG_MOLLIFY, FLAG_BARRIER_EQ12, FLAG_NO_MERGE = 0x1, 0x2, 0x4, 0x8
 FLAGS_DEFAULT = FLAG_FILTER | FLAG_MOLLIFY
 F64, F32 = 0, 1
@@ -29,6 +29,7 @@ EXPORTS = [
     "gipc_bsr_spmv", "gipc_pcg", "gipc_pair_inspect", "gipc_copy", "gipc_get_tune", "gipc_set_tune",
     "gipc_autotune", "gipc_graph_create", "gipc_graph_launch", "gipc_graph_destroy", "gipc_mf_apply",
     "gipc_pcg_mf", "gipc_proxy_dense", "gipc_friction_lag", "gipc_friction_eval", "gipc_candidates",
+    "gipc_read", "gipc_pairs_check",
 ]
 
 
@@ -83,13 +84,22 @@ class Info(ctypes.Structure):
     _fields_ = [("n_candidates", ctypes.c_int64), ("n_active", ctypes.c_int64), ("n_by_type", ctypes.c_int64 * 8),
                 ("n_staged", ctypes.c_int64), ("n_staged_by_type", ctypes.c_int64 * 8),
                 ("n_degenerate", ctypes.c_int64), ("first_degenerate", ctypes.c_int64), ("nnzb", ctypes.c_int64),
-                ("n_contrib", ctypes.c_int64), ("max_row_pairs", ctypes.c_int32)]
+                ("n_contrib", ctypes.c_int64), ("max_row_pairs", ctypes.c_int32),
+                ("n_degenerate_prims", ctypes.c_int64), ("first_degenerate_prim", ctypes.c_int64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("n_by_type", "n_staged_by_type")}
         d["n_by_type"] = {SUBTYPES[t]: int(self.n_by_type[t]) for t in range(1, 8)}
         d["n_staged_by_type"] = {SUBTYPES[t]: int(self.n_staged_by_type[t]) for t in range(1, 8)}
         return d
+
+
+class Check(ctypes.Structure):
+    _fields_ = [("n_entered", ctypes.c_int64), ("n_left", ctypes.c_int64), ("n_changed", ctypes.c_int64),
+                ("n_degenerate", ctypes.c_int64), ("first", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 _lib = None
@@ -112,6 +122,8 @@ def lib():
             "gipc_pairs_build": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Pairs), ctypes.POINTER(Params), vp,
                                       ctypes.POINTER(Info)]),
             "gipc_get_info": (st, [vp, ctypes.POINTER(Info)]),
+            "gipc_pairs_check": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Pairs), ctypes.POINTER(Params),
+                                      ctypes.POINTER(Check), vp]),
             "gipc_bsr_pattern": (st, [vp, ctypes.POINTER(Bsr)]),
             "gipc_barrier_eval": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), vp, vp, vp]),
             "gipc_assemble_bsr": (st, [vp, vp, ctypes.POINTER(Bsr), vp]),
@@ -130,6 +142,7 @@ def lib():
             "gipc_pair_inspect": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), vp, vp, vp, vp, vp, vp, vp,
                                        vp]),
             "gipc_copy": (st, [vp, vp, i64, vp]),
+            "gipc_read": (st, [vp, i64, vp, vp]),
             "gipc_get_tune": (st, [vp, ctypes.POINTER(Tune)]),
             "gipc_set_tune": (st, [vp, ctypes.POINTER(Tune)]),
             "gipc_autotune": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), vp, vp, vp, ctypes.POINTER(Bsr),
@@ -260,6 +273,21 @@ def pairs_build(ctx: Context, x, tuples, prm: Params, x_rest=None, stream=None) 
     ctx.V = int(x.shape[0])
     ctx.info = info.as_dict()
     return ctx.info
+
+
+def pairs_check(ctx: Context, x, tuples, prm: Params, x_rest=None, stream=None):
+    """Whether the last build still holds at positions x (synchronises):
+    returns (stale, counts) with stale True when gipc_pairs_check answers
+    GIPC_WARN_STALE (rebuild before evaluating at x)."""
+    _need(tuples, torch.int32, 4, "tuples")
+    mesh = Context._mesh(x, x_rest)
+    pairs = Pairs(int(tuples.shape[0]), tuples.data_ptr())
+    c = Check()
+    s = lib().gipc_pairs_check(ctx.h, ctypes.byref(mesh), ctypes.byref(pairs), ctypes.byref(prm), ctypes.byref(c),
+                               _stream(stream))
+    if s < 0:
+        ctx._check(s, "gipc_pairs_check")
+    return s == WARN_STALE, c.as_dict()
 
 
 def bsr_pattern(ctx: Context) -> Bsr:
@@ -423,7 +451,7 @@ def friction_eval(ctx: Context, x, prm: Params, A: "BsrMatrix | None" = None, en
     return energy, grad
 
 
-PROJ_ANALYTIC, PROJ_NUMERIC = 0, 1
+PROJ_ANALYTIC, PROJ_NUMERIC, PROJ_EXACT = 0, 1, 2
 
 
 def proxy_dense(ctx: Context, x, prm: Params, method=PROJ_ANALYTIC, x_rest=None, hess=None, stream=None):
@@ -509,6 +537,18 @@ def copy(src, dst, nbytes=None, stream=None):
     return dst
 
 
+def read(src, nbytes=None, sink=None, stream=None):
+    """Streaming read of ``src`` with the library's read kernel (bandwidth
+    reference); ``sink`` is a 4-byte device buffer it may write."""
+    nbytes = src.numel() * src.element_size() if nbytes is None else nbytes
+    if sink is None:
+        sink = torch.empty(1, dtype=torch.int32, device=src.device)
+    s = lib().gipc_read(_ptr(src), int(nbytes), _ptr(sink), _stream(stream))
+    if s != OK:
+        raise GipcError(s, "gipc_read failed")
+    return sink
+
+
 class BarrierEnergy(torch.autograd.Function):
     """Total barrier energy kappa * sum_k e_k b_k of the pairs staged in ``gctx``
     as a differentiable function of the positions (Eq. 3, 24, 29); with a
@@ -565,21 +605,32 @@ def autotune(ctx: Context, x, prm: Params, A: BsrMatrix, diag=None, x_rest=None,
              stream=None) -> dict:
     """Pick the fastest launch shapes of the eval / row / off-diagonal kernels
     for the current build (``gipc_autotune``, synchronises).  With ``cache``
-    (a JSON file path) and ``key`` (a string naming the workload), a stored
-    choice for (device, key) is applied instead of timing, and a new one is
-    stored."""
+    (a JSON file path), a stored choice is applied instead of timing, and a
+    new one is stored.  The cache key is the device architecture, the tune
+    fields of this library, the build's mix of staged sub-types (rounded
+    shares) and its size bucket (powers of two of staged pairs and vertices),
+    plus ``key`` if given; an entry missing any tune field is timed again.
+    Returns the shapes in force afterwards (``get_tune``)."""
     import json
+    import math
     dkey = None
-    if cache is not None and key is not None:
-        dkey = f"{torch.cuda.get_device_name(x.device)}|{key}"
+    if cache is not None:
+        st = ctx.info["n_staged_by_type"]
+        tot = max(sum(st.values()), 1)
+        mix = ",".join(f"{k}:{round(10 * n / tot)}" for k, n in sorted(st.items()))
+        bucket = f"P2^{int(math.log2(max(tot, 1)))},V2^{int(math.log2(max(int(x.shape[0]), 1)))}"
+        arch = torch.cuda.get_device_properties(x.device).gcnArchName
+        fields = ",".join(f for f, _ in Tune._fields_)
+        dkey = f"{arch}|{fields}|{mix}|{bucket}|{key or ''}"
         try:
             with open(cache) as f:
                 table = json.load(f)
         except (OSError, ValueError):
             table = {}
-        if dkey in table:
-            set_tune(ctx, **table[dkey])
-            return dict(table[dkey])
+        entry = table.get(dkey)
+        if isinstance(entry, dict) and all(f in entry for f, _ in Tune._fields_):
+            set_tune(ctx, **{f: entry[f] for f, _ in Tune._fields_})
+            return get_tune(ctx)
     mesh = Context._mesh(x, x_rest)
     if diag is not None:
         _need(diag, torch.float64, None, "diag")
@@ -589,7 +640,7 @@ def autotune(ctx: Context, x, prm: Params, A: BsrMatrix, diag=None, x_rest=None,
     ctx._check(lib().gipc_autotune(ctx.h, ctypes.byref(mesh), ctypes.byref(prm), _ptr(energy), _ptr(grad),
                                    _ptr(diag), ctypes.byref(A.desc), int(reps), ctypes.byref(t), _stream(stream)),
                "gipc_autotune")
-    best = t.as_dict()
+    best = get_tune(ctx)
     if dkey is not None:
         try:
             with open(cache) as f:

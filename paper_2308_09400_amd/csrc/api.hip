@@ -51,6 +51,7 @@ enum {
     C_NBAD = 0, C_FIRST_BAD = 1, C_NDEG = 2, C_FIRST_DEG = 3, C_ACTIVE = 4, C_OFF = 5,  // 5..13: type offsets
     C_INC = 16, C_K = 17, C_NNZB = 18, C_MAXDEG = 19, C_NSPAN = 20, C_FIRST_SPAN = 21, C_NBIG = 22,
     C_MOFF = 24,  // 24..32: merged type offsets
+    C_NDPRIM = 14, C_FIRST_DPRIM = 15,
     C_NSLOTS = 40
 };
 
@@ -166,6 +167,7 @@ const char* gipc_status_string(int st) {
         case GIPC_ERR_BREAKDOWN: return "GIPC_ERR_BREAKDOWN";
         case GIPC_ERR_STATE: return "GIPC_ERR_STATE";
         case GIPC_WARN_NOT_CONVERGED: return "GIPC_WARN_NOT_CONVERGED";
+        case GIPC_WARN_STALE: return "GIPC_WARN_STALE";
         default: return "GIPC_UNKNOWN_STATUS";
     }
 }
@@ -200,7 +202,7 @@ void gipc_ctx_destroy(gipc_ctx* ctx) {
                       &ctx->obox, &ctx->ocell, &ctx->ohist, &ctx->ooff, &ctx->ofill, &ctx->rec_main, &ctx->rec_extra, &ctx->rec_a1, &ctx->ev,
                       &ctx->epart, &ctx->mfg, &ctx->mfab, &ctx->flag, &ctx->ffr, &ctx->fev, &ctx->fpart, &ctx->cpart, &ctx->ccnt, &ctx->ccount, &ctx->cfill, &ctx->coff_t, &ctx->cent_t, &ctx->coff_e, &ctx->cent_e, &ctx->qcnt, &ctx->qoff_p, &ctx->qoff_e, &ctx->crec_t, &ctx->crec_e, &ctx->vscene, &ctx->pieces, &ctx->poff,
                       &ctx->r, &ctx->z, &ctx->p, &ctx->q, &ctx->p32, &ctx->minv, &ctx->part, &ctx->scal, &ctx->scan_tmp,
-                      &ctx->scan_tmp2};
+                      &ctx->scan_tmp2, &ctx->chk};
     for (DevBuf* b : bufs) release(*b);
     if (prev >= 0) (void)hipSetDevice(prev);
     delete ctx;
@@ -292,6 +294,7 @@ gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
     CK(hipMemsetAsync(cnt, 0, sizeof(int64_t) * C_NSLOTS, s), "clear counters");
     CK(hipMemsetAsync(cnt + C_FIRST_BAD, 0xff, sizeof(int64_t), s), "clear counters");
     CK(hipMemsetAsync(cnt + C_FIRST_DEG, 0xff, sizeof(int64_t), s), "clear counters");
+    CK(hipMemsetAsync(cnt + C_FIRST_DPRIM, 0xff, sizeof(int64_t), s), "clear counters");
     if (P > 0) {
         CK(launch_stage_classify(pairs->tuples, P, V, mesh->x, xr, pm, as<uint8_t>(ctx->cand_ft),
                                  as<int4>(ctx->cand_vid), as<int32_t>(ctx->bcount), cnt, s),
@@ -411,9 +414,44 @@ gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
     in.nnzb = nnzb;
     in.n_contrib = K;
     in.max_row_pairs = max_deg;
+    in.n_degenerate_prims = hc[C_NDPRIM];
+    in.first_degenerate_prim = hc[C_NDPRIM] > 0 ? hc[C_FIRST_DPRIM] : -1;
     if (info) *info = in;
     ctx->built = true;
     return GIPC_OK;
+}
+
+gipc_status gipc_pairs_check(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pairs* pairs,
+                             const gipc_params* params, gipc_check* out, void* stream) {
+    if (!ctx) return GIPC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    gipc_status st;
+    if ((st = check_device(ctx)) != GIPC_OK) return st;
+    if ((st = check_mesh(ctx, mesh)) != GIPC_OK) return st;
+    if (!pairs || (pairs->P > 0 && !pairs->tuples)) return fail(ctx, GIPC_ERR_INVALID_ARG, "pairs is NULL");
+    DevParams pm;
+    if ((st = to_dev_params(ctx, params, pm)) != GIPC_OK) return st;
+    if (!ctx->built) return fail(ctx, GIPC_ERR_STATE, "gipc_pairs_build has not succeeded");
+    if (mesh->V != ctx->V) return fail(ctx, GIPC_ERR_STATE, "V = %d differs from the build (%d)", mesh->V, ctx->V);
+    if (pairs->P != ctx->info.n_candidates)
+        return fail(ctx, GIPC_ERR_STATE, "P = %lld differs from the build (%lld)", (long long)pairs->P,
+                    (long long)ctx->info.n_candidates);
+    if ((st = bind_batch(ctx, params, pm)) != GIPC_OK) return st;
+    hipStream_t s = S(stream);
+    const double* xr = mesh->x_rest ? mesh->x_rest : mesh->x;
+    CK(ensure(ctx->chk, sizeof(int64_t) * 6), "alloc check counters");
+    const int64_t init[6] = {0, 0, 0, 0, 0, INT64_MAX};
+    CK(hipMemcpyAsync(ctx->chk.p, init, sizeof(init), hipMemcpyHostToDevice, s), "clear check counters");
+    CK(launch_stage_check(pairs->tuples, pairs->P, mesh->V, mesh->x, xr, pm, as<uint8_t>(ctx->cand_ft),
+                          as<int4>(ctx->cand_vid), as<int64_t>(ctx->chk), s),
+       "check");
+    int64_t h[6];
+    CK(hipMemcpyAsync(h, ctx->chk.p, sizeof(h), hipMemcpyDeviceToHost, s), "copy check counters");
+    CK(hipStreamSynchronize(s), "stream synchronize");
+    if (h[4] > 0) return fail(ctx, GIPC_ERR_INDEX, "%lld malformed tuple(s)", (long long)h[4]);
+    gipc_check c{h[0], h[1], h[2], h[3], (h[0] + h[2] > 0) ? h[5] : -1};
+    if (out) *out = c;
+    return (c.n_entered + c.n_changed > 0) ? GIPC_WARN_STALE : GIPC_OK;
 }
 
 gipc_status gipc_get_info(const gipc_ctx* ctx, gipc_info* info) {
@@ -877,8 +915,8 @@ gipc_status gipc_proxy_dense(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
     ctx->err.clear();
     gipc_status st;
     if ((st = check_device(ctx)) != GIPC_OK) return st;
-    if (method != GIPC_PROJ_ANALYTIC && method != GIPC_PROJ_NUMERIC)
-        return fail(ctx, GIPC_ERR_INVALID_ARG, "method must be GIPC_PROJ_ANALYTIC or GIPC_PROJ_NUMERIC");
+    if (method != GIPC_PROJ_ANALYTIC && method != GIPC_PROJ_NUMERIC && method != GIPC_PROJ_EXACT)
+        return fail(ctx, GIPC_ERR_INVALID_ARG, "method must be GIPC_PROJ_ANALYTIC, _NUMERIC or _EXACT");
     if ((st = check_mesh(ctx, mesh)) != GIPC_OK) return st;
     DevParams pm;
     if ((st = to_dev_params(ctx, params, pm)) != GIPC_OK) return st;
@@ -896,6 +934,13 @@ gipc_status gipc_proxy_dense(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
 gipc_status gipc_copy(const void* src, void* dst, int64_t bytes, void* stream) {
     if (bytes < 0 || (bytes > 0 && (!src || !dst))) return GIPC_ERR_INVALID_ARG;
     if (launch_copy(src, dst, bytes, S(stream)) != hipSuccess) return GIPC_ERR_HIP;
+    return GIPC_OK;
+}
+
+gipc_status gipc_read(const void* src, int64_t bytes, void* sink, void* stream) {
+    if (bytes < 0 || (bytes >= 16 && (!src || !sink)) || (reinterpret_cast<uintptr_t>(src) & 15))
+        return GIPC_ERR_INVALID_ARG;
+    if (launch_read(src, bytes, static_cast<uint32_t*>(sink), S(stream)) != hipSuccess) return GIPC_ERR_HIP;
     return GIPC_OK;
 }
 

@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(kBlock) k_rows_diag(int mode, int32_t V, const
                                                       const double* __restrict__ rec_a1, int64_t e0, int64_t m0,
                                                       const double* __restrict__ diag, double* __restrict__ grad,
                                                       double* __restrict__ ev, void* val, int dtype, int64_t nnzb) {
-    const int64_t gi = (int64_t)blockIdx.x * (kBlock / LANES) + threadIdx.x / LANES;
+    const int64_t gi = xcd_block() * (kBlock / LANES) + threadIdx.x / LANES;
     const int lg = threadIdx.x % LANES;
     const bool valid = gi < V;
     const int64_t r = valid ? (order ? order[gi] : gi) : 0;
@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(BLOCK) k_offdiag(int32_t V, const int32_t* __r
                                                     const double* __restrict__ rec_main,
                                                     const double* __restrict__ rec_extra, int64_t e0, int64_t m0,
                                                     void* val, int dtype, int64_t nnzb) {
-    const int64_t gi = (int64_t)blockIdx.x * (BLOCK / kOffLanes) + threadIdx.x / kOffLanes;
+    const int64_t gi = xcd_block() * (BLOCK / kOffLanes) + threadIdx.x / kOffLanes;
     if (gi >= V) return;
     const int lg = threadIdx.x % kOffLanes;
     const int32_t r = order ? order[gi] : (int32_t)gi;
@@ -403,7 +403,7 @@ __global__ void __launch_bounds__(kBlock) k_mf_coef(int32_t V, const int32_t* __
                                                     const int64_t* __restrict__ inc_ptr,
                                                     const double* __restrict__ rec_main, int64_t e0,
                                                     double* __restrict__ g) {
-    const int64_t r = (int64_t)blockIdx.x * (kBlock / kMfLanes) + threadIdx.x / kMfLanes;
+    const int64_t r = xcd_block() * (kBlock / kMfLanes) + threadIdx.x / kMfLanes;
     const int lg = threadIdx.x % kMfLanes;
     if (r >= V) return;
     const int32_t sl = diag_slot[r];
@@ -468,7 +468,7 @@ __global__ void __launch_bounds__(kMfBlock) k_mf_rows(int32_t V, const int32_t* 
                                                       const PcgScalars* __restrict__ sc) {
     if (sc && sc->done) return;
     __shared__ double lds[kMfBlock / 64];
-    const int64_t gi = (int64_t)blockIdx.x * (kMfBlock / kMfLanes) + threadIdx.x / kMfLanes;
+    const int64_t gi = xcd_block() * (kMfBlock / kMfLanes) + threadIdx.x / kMfLanes;
     const int lg = threadIdx.x % kMfLanes;
     const bool valid = gi < V;
     const int64_t r = valid ? order[gi] : 0;

@@ -120,11 +120,15 @@ struct Staged {
     int v[4];
 };
 
-__device__ inline Staged classify_pt(const double* __restrict__ X, int vp, int v0, int v1, int v2, double& d2) {
+// degen (out): the triangle has zero area (its vertices are collinear or
+// coincide); its distance is then the smallest over its edges
+__device__ inline Staged classify_pt(const double* __restrict__ X, int vp, int v0, int v1, int v2, double& d2,
+                                     bool& degen) {
     d3 p = ld3(X, vp), t0 = ld3(X, v0), t1 = ld3(X, v1), t2 = ld3(X, v2);
     d3 e1 = t1 - t0, e2 = t2 - t0, r = p - t0;
     d3 n = cross(e1, e2);
     double nn = dot(n, n), a11 = dot(e1, e1), a22 = dot(e2, e2);
+    degen = !(nn > 0.0);
     double best = INFINITY;
     Staged s{FT_NONE, {-1, -1, -1, -1}};
     if (nn > kInteriorTol * a11 * a22) {
@@ -153,9 +157,13 @@ __device__ inline Staged classify_pt(const double* __restrict__ X, int vp, int v
     return s;
 }
 
-__device__ inline Staged classify_pe(const double* __restrict__ X, int vp, int v0, int v1, double& d2) {
+// degen (out): the edge has zero length (the pair is then point-point)
+__device__ inline Staged classify_pe(const double* __restrict__ X, int vp, int v0, int v1, double& d2, bool& degen) {
     double al;
-    d2 = seg_dist2(ld3(X, vp), ld3(X, v0), ld3(X, v1), al);
+    const d3 a = ld3(X, v0), b = ld3(X, v1);
+    const d3 e = b - a;
+    degen = !(dot(e, e) > 0.0);
+    d2 = seg_dist2(ld3(X, vp), a, b, al);
     if (al > 0.0 && al < 1.0) return Staged{FT_PE, {vp, v0, v1, -1}};
     return Staged{FT_PP, {vp, al <= 0.0 ? v0 : v1, -1, -1}};
 }
@@ -166,12 +174,14 @@ __device__ __forceinline__ double eps_x(const double* __restrict__ XR, int a0, i
     return ratio * dot(a, a) * dot(b, b);
 }
 
+// degen (out): an edge has zero length
 __device__ inline Staged classify_ee(const double* __restrict__ X, const double* __restrict__ XR, int va0, int va1,
-                                     int vb0, int vb1, const DevParams& pm, double& d2) {
+                                     int vb0, int vb1, const DevParams& pm, double& d2, bool& degen) {
     d3 a0 = ld3(X, va0), a1 = ld3(X, va1), b0 = ld3(X, vb0), b1 = ld3(X, vb1);
     d3 a = a1 - a0, b = b1 - b0, r = a0 - b0;
     d3 n = cross(a, b);
     double cc = dot(n, n), aa = dot(a, a), bb = dot(b, b);
+    degen = !(aa > 0.0) || !(bb > 0.0);
     bool moll = pm.mollify && cc < eps_x(XR, va0, va1, vb0, vb1, pm.epsx_ratio);
     double best = INFINITY;
     Staged s{FT_NONE, {-1, -1, -1, -1}};
@@ -207,6 +217,33 @@ __device__ inline Staged classify_ee(const double* __restrict__ X, const double*
     }
     d2 = best;
     return s;
+}
+
+// A point-edge or point-point pair cut from a close-to-parallel edge-edge
+// pair, given in the paper's encodings (Sec. 7.2, "Data structures"): point
+// p of edge (p, o) against edge (e0, e1) (edge = true) or against its
+// endpoint e0, whose edge is (e0, e1) (edge = false).  The distance is the
+// point-segment (or point-point) sub-problem of Eq. 5; the mollifier is
+// decided from both edges, as for an edge-edge pair.
+// degen (out): an edge has zero length.
+__device__ inline Staged classify_par(const double* __restrict__ X, const double* __restrict__ XR, int vp, int vo,
+                                      int ve0, int ve1, bool edge, const DevParams& pm, double& d2, bool& degen) {
+    const d3 P = ld3(X, vp), O = ld3(X, vo), E0 = ld3(X, ve0), E1 = ld3(X, ve1);
+    const d3 a = O - P, b = E1 - E0;
+    const d3 n = cross(a, b);
+    degen = !(dot(a, a) > 0.0) || !(dot(b, b) > 0.0);
+    const bool moll = pm.mollify && dot(n, n) < eps_x(XR, vp, vo, ve0, ve1, pm.epsx_ratio);
+    if (!edge) {
+        const d3 w = P - E0;
+        d2 = dot(w, w);
+        return moll ? Staged{FT_PPM, {vp, vo, ve0, ve1}} : Staged{FT_PP, {vp, ve0, -1, -1}};
+    }
+    double al;
+    d2 = seg_dist2(P, E0, E1, al);
+    if (al > 0.0 && al < 1.0)
+        return moll ? Staged{FT_PEM, {vp, vo, ve0, ve1}} : Staged{FT_PE, {vp, ve0, ve1, -1}};
+    const int q = al <= 0.0 ? ve0 : ve1, rr = al <= 0.0 ? ve1 : ve0;
+    return moll ? Staged{FT_PPM, {vp, vo, q, rr}} : Staged{FT_PP, {vp, q, -1, -1}};
 }
 
 // ------------------------------------------------------------------------

@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(kBlock) k_fric_rows(int32_t V, const int32_t* 
                                                       const double* __restrict__ fr, int64_t e0,
                                                       double* __restrict__ grad, double* __restrict__ ev,
                                                       void* __restrict__ val, int dtype, int64_t nnzb) {
-    const int64_t r = (int64_t)blockIdx.x * (kBlock / kFrLanes) + threadIdx.x / kFrLanes;
+    const int64_t r = xcd_block() * (kBlock / kFrLanes) + threadIdx.x / kFrLanes;
     const int lg = threadIdx.x % kFrLanes;
     const bool valid = r < V;
     const int32_t ds = valid ? diag_slot[r] : 0;

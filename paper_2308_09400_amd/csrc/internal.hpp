@@ -30,6 +30,18 @@ void release(DevBuf& b);
 template <typename T>
 inline T* as(DevBuf& b) { return static_cast<T*>(b.p); }
 
+// Workgroups go to the chip's 8 XCDs in turn (workgroup b runs on XCD
+// b mod 8), and every XCD has an L2 of its own.  xcd_block() renumbers the
+// launch so that each XCD takes one contiguous run of logical workgroups:
+// the neighbouring rows of a gather kernel then read the records they share
+// through the same L2.  It is a permutation of 0 .. gridDim.x-1.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_block() {
+    const int64_t b = blockIdx.x, n = gridDim.x;
+    const int64_t q = n / kXcds, r = n % kXcds, x = b % kXcds;
+    return x * q + (x < r ? x : r) + b / kXcds;
+}
+
 // Ranges of staged pairs per sub-type: pairs of type t occupy [off[t], off[t+1]).
 struct TypeRanges {
     int64_t off[9];
@@ -121,8 +133,8 @@ struct gipc_ctx {
     gipc_tune tune{4, 16, 4, 0};
     // PCG workspace
     gipc::DevBuf r, z, p, q, p32, minv, part, scal;
-    // scan scratch
-    gipc::DevBuf scan_tmp, scan_tmp2;
+    // scan scratch; counters of gipc_pairs_check
+    gipc::DevBuf scan_tmp, scan_tmp2, chk;
 
     gipc_info info{};
     bool built = false;
@@ -148,6 +160,12 @@ hipError_t launch_stage_classify(const int32_t* tuples, int64_t P, int32_t V, co
                                  hipStream_t s);
 hipError_t launch_stage_scatter(const uint8_t* ft, const int4* vid, int64_t P, const int64_t* boff, int4* st_vid,
                                 int32_t* st_src, hipStream_t s);
+// the build's classification (ft_b, vid_b) against the one at x; counters
+// (device int64 [6], zeroed, [5] = INT64_MAX): entered, left, changed,
+// degenerate, malformed, first changed tuple
+hipError_t launch_stage_check(const int32_t* tuples, int64_t P, int32_t V, const double* x, const double* xr,
+                              const DevParams& pm, const uint8_t* ft_b, const int4* vid_b, int64_t* counters,
+                              hipStream_t s);
 hipError_t launch_stage_offsets(const int64_t* boff, int64_t nb, int64_t* out, hipStream_t s);
 
 // ---- merge.hip
@@ -288,8 +306,15 @@ hipError_t launch_cand_query(int kind, bool emit, const double* x, int64_t nq, c
 // ---- solve.hip
 hipError_t launch_spmv(const gipc_bsr& A, const void* x, void* y, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
+// streaming read of bytes / 16 aligned 16-byte words (sink: device uint32, written only by chance)
+hipError_t launch_read(const void* src, int64_t bytes, uint32_t* sink, hipStream_t s);
 // with mf set, the operator is matrix-free (A is not read)
 hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x, double rtol, int32_t maxit,
                    int32_t* iters, double* relres, int* breakdown, hipStream_t s, const MfView* mf = nullptr);
+// the same on buffers carved from one device range ws of at least
+// pcg_workspace_bytes(A, mf) bytes (no allocation)
+size_t pcg_workspace_bytes(const gipc_bsr& A, const MfView* mf);
+hipError_t pcg_run_in(void* ws, const gipc_bsr& A, const double* b, double* x, double rtol, int32_t maxit,
+                      int32_t* iters, double* relres, int* breakdown, hipStream_t s, const MfView* mf = nullptr);
 
 }  // namespace gipc

@@ -233,6 +233,26 @@ __global__ void __launch_bounds__(kBlock) k_copy16(const uint4* __restrict__ src
     for (; i < n; i += stride) dst[i] = src[i];
 }
 
+// streaming read of n 16-byte words, 4 independent loads in flight per lane
+// (the chip's read bandwidth for roofline fractions); the xor of all words
+// is stored only if it equals a fixed constant, which keeps every load live
+// while writing nothing in practice
+__global__ void __launch_bounds__(kBlock) k_read16(const uint4* __restrict__ src, int64_t n,
+                                                   uint32_t* __restrict__ sink) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    uint32_t acc = 0;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        acc ^= (a.x ^ a.y ^ a.z ^ a.w) ^ (b.x ^ b.y ^ b.z ^ b.w) ^ (c.x ^ c.y ^ c.z ^ c.w) ^ (d.x ^ d.y ^ d.z ^ d.w);
+    }
+    for (; i < n; i += stride) {
+        const uint4 a = src[i];
+        acc ^= a.x ^ a.y ^ a.z ^ a.w;
+    }
+    if (acc == 0x9e3779b9u) sink[0] = acc;
+}
+
 __global__ void k_copy1(const uint8_t* __restrict__ src, uint8_t* __restrict__ dst, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         dst[i] = src[i];
@@ -397,6 +417,12 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(int first, int32_t V, con
     }
 }
 
+// all scalars zero (a kernel, not a memset, so the sequence stays free of
+// memset nodes wherever it is recorded)
+__global__ void k_pcg_reset(PcgScalars* sc) {
+    if (threadIdx.x == 0) *sc = PcgScalars{};
+}
+
 // first: initial scalars; otherwise beta, the new r.z and the stopping test
 __global__ void __launch_bounds__(kRed) k_pcg_beta(int first, const double* __restrict__ part, int64_t nb,
                                                      PcgScalars* sc, double rtol2, int maxit) {
@@ -482,8 +508,100 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_read(const void* src, int64_t bytes, uint32_t* sink, hipStream_t s) {
+    const int64_t n16 = bytes / 16;
+    if (n16 <= 0) return hipSuccess;
+    int64_t blocks = (n16 + 4 * kBlock - 1) / (4 * kBlock);
+    if (blocks > 16384) blocks = 16384;
+    k_read16<<<(unsigned)blocks, kBlock, 0, s>>>(static_cast<const uint4*>(src), n16, sink);
+    return hipGetLastError();
+}
+
+// work buffers of one PCG solve
+struct PcgWork {
+    double *r, *z, *p, *q, *minv, *part;
+    float* p32;
+    PcgScalars* sc;
+};
+
+// the partials the reductions need: one per workgroup of the widest kernel
+static int64_t pcg_num_parts(const gipc_bsr& A, const MfView* mf) {
+    const int32_t V = mf ? mf->V : A.nbrows;
+    const int64_t nbv = (V + kBlock - 1) / kBlock;
+    const int64_t nbs = mf ? mf_num_parts(V)
+                           : spmv_by_entry(A) ? spmv_ent_blocks(A.nnzb)
+                                              : ((int64_t)V * kG + kPcgBlock - 1) / kPcgBlock;
+    return nbv > nbs ? nbv : nbs;
+}
+
+// bytes of every PCG buffer, each rounded up to 256
+static size_t pcg_round(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t pcg_workspace_bytes(const gipc_bsr& A, const MfView* mf) {
+    const int32_t V = mf ? mf->V : A.nbrows;
+    const size_t n3 = 3 * (size_t)V;
+    const bool f32 = !mf && A.dtype == GIPC_F32;
+    return 4 * pcg_round(sizeof(double) * n3) + pcg_round(sizeof(double) * 9 * (size_t)V) +
+           pcg_round(sizeof(double) * 3 * (size_t)pcg_num_parts(A, mf)) + pcg_round(sizeof(PcgScalars)) +
+           (f32 ? pcg_round(sizeof(float) * n3) : 0);
+}
+
+static hipError_t pcg_exec(const gipc_bsr& A, const double* b, double* x, double rtol, int32_t maxit,
+                           int32_t* iters, double* relres, int* breakdown, hipStream_t s, const MfView* mf,
+                           const PcgWork& w);
+
+// the buffers carved out of one device range of pcg_workspace_bytes bytes
+hipError_t pcg_run_in(void* ws, const gipc_bsr& A, const double* b, double* x, double rtol, int32_t maxit,
+                      int32_t* iters, double* relres, int* breakdown, hipStream_t s, const MfView* mf) {
+    const int32_t V = mf ? mf->V : A.nbrows;
+    const size_t n3 = 3 * (size_t)V;
+    const bool f32 = !mf && A.dtype == GIPC_F32;
+    char* c = static_cast<char*>(ws);
+    auto take = [&](size_t bytes) {
+        char* p = c;
+        c += pcg_round(bytes);
+        return p;
+    };
+    PcgWork w;
+    w.r = reinterpret_cast<double*>(take(sizeof(double) * n3));
+    w.z = reinterpret_cast<double*>(take(sizeof(double) * n3));
+    w.p = reinterpret_cast<double*>(take(sizeof(double) * n3));
+    w.q = reinterpret_cast<double*>(take(sizeof(double) * n3));
+    w.minv = reinterpret_cast<double*>(take(sizeof(double) * 9 * (size_t)V));
+    w.part = reinterpret_cast<double*>(take(sizeof(double) * 3 * (size_t)pcg_num_parts(A, mf)));
+    w.sc = reinterpret_cast<PcgScalars*>(take(sizeof(PcgScalars)));
+    w.p32 = f32 ? reinterpret_cast<float*>(take(sizeof(float) * n3)) : nullptr;
+    return pcg_exec(A, b, x, rtol, maxit, iters, relres, breakdown, s, mf, w);
+}
+
 hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x, double rtol, int32_t maxit,
                    int32_t* iters, double* relres, int* breakdown, hipStream_t s, const MfView* mf) {
+    const int32_t V = mf ? mf->V : A.nbrows;
+    const size_t n3 = 3 * (size_t)V;
+    hipError_t e;
+#define GIPC_TRY(x)                            \
+    do {                                       \
+        if ((e = (x)) != hipSuccess) return e; \
+    } while (0)
+    GIPC_TRY(ensure(ctx->r, sizeof(double) * n3));
+    GIPC_TRY(ensure(ctx->z, sizeof(double) * n3));
+    GIPC_TRY(ensure(ctx->p, sizeof(double) * n3));
+    GIPC_TRY(ensure(ctx->q, sizeof(double) * n3));
+    GIPC_TRY(ensure(ctx->minv, sizeof(double) * 9 * (size_t)V));
+    GIPC_TRY(ensure(ctx->part, sizeof(double) * 3 * (size_t)pcg_num_parts(A, mf)));
+    GIPC_TRY(ensure(ctx->scal, sizeof(PcgScalars)));
+    const bool f32 = !mf && A.dtype == GIPC_F32;
+    if (f32) GIPC_TRY(ensure(ctx->p32, sizeof(float) * n3));
+#undef GIPC_TRY
+    PcgWork w{as<double>(ctx->r), as<double>(ctx->z), as<double>(ctx->p), as<double>(ctx->q),
+              as<double>(ctx->minv), as<double>(ctx->part), f32 ? as<float>(ctx->p32) : nullptr,
+              as<PcgScalars>(ctx->scal)};
+    return pcg_exec(A, b, x, rtol, maxit, iters, relres, breakdown, s, mf, w);
+}
+
+static hipError_t pcg_exec(const gipc_bsr& A, const double* b, double* x, double rtol, int32_t maxit,
+                           int32_t* iters, double* relres, int* breakdown, hipStream_t s, const MfView* mf,
+                           const PcgWork& w) {
     const int32_t V = mf ? mf->V : A.nbrows;
     const int64_t n3 = 3 * (int64_t)V;
     const int64_t nbv = (V + kBlock - 1) / kBlock;  // row-parallel kernels
@@ -496,22 +614,14 @@ hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x,
     do {                                       \
         if ((e = (x)) != hipSuccess) return e; \
     } while (0)
-    GIPC_TRY(ensure(ctx->r, sizeof(double) * n3));
-    GIPC_TRY(ensure(ctx->z, sizeof(double) * n3));
-    GIPC_TRY(ensure(ctx->p, sizeof(double) * n3));
-    GIPC_TRY(ensure(ctx->q, sizeof(double) * n3));
-    GIPC_TRY(ensure(ctx->minv, sizeof(double) * 9 * (size_t)V));
-    GIPC_TRY(ensure(ctx->part, sizeof(double) * 3 * (size_t)(nbv > nbs ? nbv : nbs)));
-    GIPC_TRY(ensure(ctx->scal, sizeof(PcgScalars)));
     const bool f32 = !mf && A.dtype == GIPC_F32;
-    if (f32) GIPC_TRY(ensure(ctx->p32, sizeof(float) * n3));
-    double *r = as<double>(ctx->r), *z = as<double>(ctx->z), *p = as<double>(ctx->p), *q = as<double>(ctx->q);
-    double *minv = as<double>(ctx->minv), *part = as<double>(ctx->part);
-    float* p32 = f32 ? as<float>(ctx->p32) : nullptr;
-    PcgScalars* sc = as<PcgScalars>(ctx->scal);
+    double *r = w.r, *z = w.z, *p = w.p, *q = w.q;
+    double *minv = w.minv, *part = w.part;
+    float* p32 = w.p32;
+    PcgScalars* sc = w.sc;
     const unsigned nbn = (unsigned)((n3 + kBlock - 1) / kBlock);
 
-    GIPC_TRY(hipMemsetAsync(sc, 0, sizeof(PcgScalars), s));
+    k_pcg_reset<<<1, 64, 0, s>>>(sc);
     // r = b - A x0 (for FP32 matrices through an FP32 copy of x0)
     if (mf) {
         GIPC_TRY(launch_mf_diag_inverse(*mf, minv, s));

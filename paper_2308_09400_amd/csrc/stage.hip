@@ -12,10 +12,85 @@ namespace {
 
 // counters (relative to the pointer the kernel gets): [0] malformed tuples,
 // [1] first malformed index, [2] degenerate pairs, [3] first degenerate
-// index, [20] tuples whose vertices lie in different scenes, [21] the first
+// index, [14] tuples with a degenerate primitive, [15] the first, [20]
+// tuples whose vertices lie in different scenes, [21] the first
 __device__ __forceinline__ void flag_index(unsigned long long* cnt, unsigned long long* first, int64_t p) {
     atomicAdd(cnt, 1ull);
     atomicMin(first, (unsigned long long)p);
+}
+
+enum TupleStatus { TS_OK = 0, TS_BAD = 1, TS_SPAN = 2, TS_DEGEN = 3 };
+
+// One tuple in the paper's sign encoding (Sec. 7.2, "Data structures"),
+// negative ids as -(i+1), decoded with ~i:
+//   [a0, a1, b0, b1]            edge-edge (a1 negative: close to parallel)
+//   [-p, t0, t1, t2]            point-triangle
+//   [-p, e0, e1, -1]            point-edge
+//   [-p, q, -1, -1]             point-point
+//   [-p, -o, e0, -e1]           point-edge cut from a close-to-parallel
+//                               edge-edge pair (p's edge is (p, o))
+//   [-p, -o, -q, -r]            point-point cut from one (q's edge is (q, r))
+// The vertex ids are checked, then the tuple is classified at X: ft is its
+// sub-type if it is closer than its scene's dhat (else FT_NONE), vo its
+// staged stencil, dprim whether a primitive is degenerate (an edge of zero
+// length, a triangle of zero area) while the distance is still positive.
+__device__ inline int classify_tuple(const int4 t, int32_t V, const double* __restrict__ X,
+                                     const double* __restrict__ XR, const DevParams& pm, int& ft, int4& vo,
+                                     bool& dprim) {
+    ft = FT_NONE;
+    vo = make_int4(-1, -1, -1, -1);
+    dprim = false;
+    int kind = -1;  // 0 EE, 1 PT, 2 PE, 3 PP, 4 PE cut from EE, 5 PP cut from EE
+    int v[4] = {-1, -1, -1, -1};
+    int nv = 0;
+    if (t.x >= 0) {
+        if (t.z >= 0 && t.w >= 0) {
+            kind = 0; nv = 4;
+            v[0] = t.x; v[1] = t.y >= 0 ? t.y : ~t.y; v[2] = t.z; v[3] = t.w;
+        }
+    } else if (t.y >= 0) {
+        v[0] = ~t.x; v[1] = t.y;
+        if (t.z >= 0 && t.w >= 0) { kind = 1; nv = 4; v[2] = t.z; v[3] = t.w; }
+        else if (t.z >= 0 && t.w == -1) { kind = 2; nv = 3; v[2] = t.z; }
+        else if (t.z == -1 && t.w == -1) { kind = 3; nv = 2; }
+    } else if (t.w < 0) {
+        v[0] = ~t.x; v[1] = ~t.y; v[3] = ~t.w; nv = 4;
+        if (t.z >= 0) { kind = 4; v[2] = t.z; }
+        else { kind = 5; v[2] = ~t.z; }
+    }
+    bool ok = kind >= 0;
+    for (int k = 0; k < nv && ok; ++k) {
+        ok = v[k] >= 0 && v[k] < V;
+        for (int l = 0; l < k && ok; ++l) ok = v[l] != v[k];
+    }
+    if (!ok) return TS_BAD;
+    if (pm.vscene) {
+        const int s0 = pm.vscene[v[0]];
+        for (int k = 1; k < nv; ++k)
+            if (pm.vscene[v[k]] != s0) return TS_SPAN;
+    }
+    double d2;
+    bool degen = false;
+    Staged s;
+    if (kind == 0) s = classify_ee(X, XR, v[0], v[1], v[2], v[3], pm, d2, degen);
+    else if (kind == 1) s = classify_pt(X, v[0], v[1], v[2], v[3], d2, degen);
+    else if (kind == 2) s = classify_pe(X, v[0], v[1], v[2], d2, degen);
+    else if (kind == 3) {
+        d3 w = ld3(X, v[0]) - ld3(X, v[1]);
+        d2 = dot(w, w);
+        s = Staged{FT_PP, {v[0], v[1], -1, -1}};
+    } else {
+        s = classify_par(X, XR, v[0], v[1], v[2], v[3], kind == 4, pm, d2, degen);
+    }
+    if (!(d2 > 0.0) || !(d2 < INFINITY)) return TS_DEGEN;
+    dprim = degen;
+    double dhat, kappa;
+    scene_params(pm, v[0], dhat, kappa);
+    if (d2 < dhat * dhat) {
+        ft = s.ft;
+        vo = make_int4(s.v[0], s.v[1], s.v[2], s.v[3]);
+    }
+    return TS_OK;
 }
 
 __global__ void __launch_bounds__(kBlock) k_stage_classify(const int4* __restrict__ tuples, int64_t P, int32_t V,
@@ -27,59 +102,14 @@ __global__ void __launch_bounds__(kBlock) k_stage_classify(const int4* __restric
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     int ft = FT_NONE;
-    int4 vo = make_int4(-1, -1, -1, -1);
     if (p < P) {
-        const int4 t = tuples[p];
-        int kind = -1;  // 0 EE, 1 PT, 2 PE, 3 PP
-        int v[4] = {-1, -1, -1, -1};
-        int nv = 0;
-        if (t.x != INT32_MIN && t.y != INT32_MIN) {
-            if (t.x >= 0) {
-                if (t.z >= 0 && t.w >= 0) {
-                    kind = 0; nv = 4;
-                    v[0] = t.x; v[1] = t.y >= 0 ? t.y : -t.y - 1; v[2] = t.z; v[3] = t.w;
-                }
-            } else if (t.y >= 0) {
-                v[0] = -t.x - 1; v[1] = t.y;
-                if (t.z >= 0 && t.w >= 0) { kind = 1; nv = 4; v[2] = t.z; v[3] = t.w; }
-                else if (t.z >= 0 && t.w == -1) { kind = 2; nv = 3; v[2] = t.z; }
-                else if (t.z == -1 && t.w == -1) { kind = 3; nv = 2; }
-            }
-        }
-        bool ok = kind >= 0;
-        for (int k = 0; k < nv && ok; ++k) {
-            ok = v[k] >= 0 && v[k] < V;
-            for (int l = 0; l < k && ok; ++l) ok = v[l] != v[k];
-        }
-        bool same_scene = true;
-        if (ok && pm.vscene) {
-            const int s0 = pm.vscene[v[0]];
-            for (int k = 1; k < nv; ++k) same_scene = same_scene && pm.vscene[v[k]] == s0;
-        }
-        if (!ok) {
-            flag_index(&counters[0], &counters[1], p);
-        } else if (!same_scene) {
-            flag_index(&counters[20], &counters[21], p);
-        } else {
-            double d2;
-            Staged s;
-            if (kind == 0) s = classify_ee(X, XR, v[0], v[1], v[2], v[3], pm, d2);
-            else if (kind == 1) s = classify_pt(X, v[0], v[1], v[2], v[3], d2);
-            else if (kind == 2) s = classify_pe(X, v[0], v[1], v[2], d2);
-            else {
-                d3 w = ld3(X, v[0]) - ld3(X, v[1]);
-                d2 = dot(w, w);
-                s = Staged{FT_PP, {v[0], v[1], -1, -1}};
-            }
-            double dhat, kappa;
-            scene_params(pm, v[0], dhat, kappa);
-            if (!(d2 > 0.0) || !(d2 < INFINITY)) {
-                flag_index(&counters[2], &counters[3], p);
-            } else if (d2 < dhat * dhat) {
-                ft = s.ft;
-                vo = make_int4(s.v[0], s.v[1], s.v[2], s.v[3]);
-            }
-        }
+        int4 vo;
+        bool dprim;
+        const int st = classify_tuple(tuples[p], V, X, XR, pm, ft, vo, dprim);
+        if (st == TS_BAD) flag_index(&counters[0], &counters[1], p);
+        else if (st == TS_SPAN) flag_index(&counters[20], &counters[21], p);
+        else if (st == TS_DEGEN) flag_index(&counters[2], &counters[3], p);
+        else if (dprim) flag_index(&counters[14], &counters[15], p);
         ft_out[p] = (uint8_t)ft;
         if (ft != FT_NONE) vid_out[p] = vo;  // read back for active tuples only
     }
@@ -95,6 +125,54 @@ __global__ void __launch_bounds__(kBlock) k_stage_classify(const int4* __restric
         bcount[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
     }
     if (threadIdx.x == 0) bcount[blockIdx.x] = 0;
+}
+
+// The build's classification against the one at X, tuple by tuple (the
+// build's sub-types in ft_b, stencils of its active tuples in vid_b):
+// counters [0] tuples closer than dhat now but not at the build, [1] active
+// at the build but not now (the build's sub-type formula also puts them at
+// or beyond dhat, so the evaluation drops them), [2] active at the build
+// with another sub-type or stencil now, or inactive now while the build's
+// formula still finds them within dhat, [3] degenerate now (distance 0 or
+// not finite), [4] malformed or spanning two scenes, [5] the first tuple
+// counted in [0] or [2].
+__global__ void __launch_bounds__(kBlock) k_stage_check(const int4* __restrict__ tuples, int64_t P, int32_t V,
+                                                        const double* __restrict__ X, const double* __restrict__ XR,
+                                                        DevParams pm, const uint8_t* __restrict__ ft_b,
+                                                        const int4* __restrict__ vid_b,
+                                                        unsigned long long* __restrict__ counters) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= P) return;
+    int ft;
+    int4 vo;
+    bool dprim;
+    const int st = classify_tuple(tuples[p], V, X, XR, pm, ft, vo, dprim);
+    if (st == TS_BAD || st == TS_SPAN) {
+        atomicAdd(&counters[4], 1ull);
+        return;
+    }
+    if (st == TS_DEGEN) {
+        atomicAdd(&counters[3], 1ull);
+        ft = FT_NONE;
+    }
+    const int fb = ft_b[p];
+    int which = -1;
+    if (fb == FT_NONE && ft != FT_NONE) {
+        which = 0;
+    } else if (fb != FT_NONE && ft == FT_NONE) {
+        // harmless if the build's sub-type formula, which the evaluation
+        // uses, also puts the pair at or beyond dhat
+        const int4 b = vid_b[p];
+        const int bv[4] = {b.x, b.y, b.z, b.w};
+        PairFactors o;
+        eval_typed(fb, bv, X, XR, pm, o);
+        which = (o.E != 0.0 || o.a2 != 0.0 || o.P22 != 0.0) ? 2 : 1;
+    } else if (fb != FT_NONE) {
+        const int4 b = vid_b[p];
+        if (fb != ft || b.x != vo.x || b.y != vo.y || b.z != vo.z || b.w != vo.w) which = 2;
+    }
+    if (which == 1) atomicAdd(&counters[1], 1ull);
+    else if (which >= 0) flag_index(&counters[which], &counters[5], p);
 }
 
 __global__ void __launch_bounds__(kBlock) k_stage_scatter(const uint8_t* __restrict__ ft_in,
@@ -131,6 +209,16 @@ hipError_t launch_stage_classify(const int32_t* tuples, int64_t P, int32_t V, co
     if (nb == 0) return hipSuccess;
     k_stage_classify<<<(unsigned)nb, kBlock, 0, s>>>(reinterpret_cast<const int4*>(tuples), P, V, x, xr, pm, ft, vid,
                                                      bcount, reinterpret_cast<unsigned long long*>(counters));
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_check(const int32_t* tuples, int64_t P, int32_t V, const double* x, const double* xr,
+                              const DevParams& pm, const uint8_t* ft_b, const int4* vid_b, int64_t* counters,
+                              hipStream_t s) {
+    int64_t nb = (P + kBlock - 1) / kBlock;
+    if (nb == 0) return hipSuccess;
+    k_stage_check<<<(unsigned)nb, kBlock, 0, s>>>(reinterpret_cast<const int4*>(tuples), P, V, x, xr, pm, ft_b, vid_b,
+                                                  reinterpret_cast<unsigned long long*>(counters));
     return hipGetLastError();
 }
 

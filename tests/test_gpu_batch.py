@@ -15,7 +15,9 @@ sequence), the HIP-graph replay of eval + assembly, and the autotuner.
   default shapes to 1e-12 (only summation order changes);
 * the 64-scene workload (resolution 32..256 per side, dhat log-uniform in
   [1e-4, 1e-2], seeds 1000 + s): per-scene energies of four scenes vs the
-  oracle, and three scenes vs their own single-scene runs, bitwise.
+  oracle; BSR blocks on sampled rows of six scenes vs the oracle, FP64
+  (1e-9) and the FP32 graph replay (1e-5); three scenes vs their own
+  single-scene runs, bitwise.
 """
 import numpy as np
 import pytest
@@ -199,6 +201,20 @@ def test_autotune(gp, tmp_path):
     gp.set_tune(ctx, 4, 16, 4)
     again = gp.autotune(ctx, X, prm, A, diag=diag, x_rest=XR, cache=str(cache), key="small")
     assert again == best and gp.get_tune(ctx) == best
+    # an entry written before a tune field existed is timed again, not applied
+    import json
+    table = json.loads(cache.read_text())
+    (k,) = [k for k in table if k.endswith("|small")]
+    assert "gfx" in k.split("|")[0]
+    stale = dict(table[k])
+    del stale["row_order"]
+    table[k] = stale
+    cache.write_text(json.dumps(table))
+    gp.set_tune(ctx, 4, 16, 4)
+    fresh = gp.autotune(ctx, X, prm, A, diag=diag, x_rest=XR, reps=1, cache=str(cache), key="small")
+    assert set(fresh) == {"eval_waves", "row_lanes", "offdiag_waves", "row_order"}
+    assert "row_order" in json.loads(cache.read_text())[k]
+    gp.set_tune(ctx, **best)
     with pytest.raises(gp.GipcError):
         gp.set_tune(ctx, 3, 16, 4)
     with pytest.raises(gp.GipcError):
@@ -231,6 +247,48 @@ def test_64_scene_batch_energies_against_oracle(c4):
         assert E[s] == pytest.approx(r["E"], rel=TOL), s
         g = res["g"][b.vert_off[s]:b.vert_off[s + 1]].cpu().numpy()
         assert np.abs(g - r["grad"]).max() <= TOL * np.abs(r["grad"]).max(), s
+
+
+def _row_blocks(A, r):
+    rp = A.row_ptr()
+    lo, hi = int(rp[r]), int(rp[r + 1])
+    ci = A.col_idx()[lo:hi].cpu().numpy()
+    vals = A.val[:, lo:hi].double().cpu().numpy().T.reshape(-1, 3, 3)
+    return {int(c): B for c, B in zip(ci, vals)}
+
+
+def test_64_scene_batch_blocks_against_oracle_on_sampled_rows(gp, c4):
+    # FP64 blocks of the eager call and FP32 blocks replayed from the graph,
+    # both on sampled rows of the largest, the smallest and four more scenes
+    b, res = c4
+    ctx, A64 = res["ctx"], res["A"]
+    A32 = gp.BsrMatrix(ctx, dtype=gp.F32)
+    graph = gp.Graph(ctx, res["X"], res["prm"], A32, diag=res["diag"], x_rest=res["XR"])
+    E32, g32 = graph.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(E32, res["E"]) and torch.equal(g32, res["g"])   # FP32 changes only the blocks
+    sizes = np.diff(b.pair_off)
+    rng = np.random.default_rng(31)
+    pick = [int(np.argmax(sizes)), int(np.argmin(sizes))] + [int(v) for v in rng.choice(b.S, 4, replace=False)]
+    for s in pick:
+        sc = b.scenes[s]
+        v0 = int(b.vert_off[s])
+        rows = rng.choice(sc.V, 4, replace=False)
+        kind, st = scenes.decode_tuples(sc.tuples)
+        sub = sc.tuples[np.isin(st, rows).any(1)]
+        po = oracle.params(dhat=sc.dhat, kappa=sc.kappa)
+        r = oracle.eval_scene(sc.x, sub, po, x_rest=sc.x_rest, per_pair=True)
+        orows, ocols, ovals = oracle.assemble(sc.V, sub, r["pairH"], np.full(sc.V, 10.0))
+        for row in rows:
+            sel = orows == row
+            o = {int(c): B for c, B in zip(ocols[sel], ovals[sel])}
+            hs = max(np.abs(B).max() for B in o.values())
+            for A, tol in ((A64, TOL), (A32, 1e-5)):
+                g = {c - v0: B for c, B in _row_blocks(A, v0 + int(row)).items()}
+                assert all(0 <= c < sc.V for c in g), s
+                for c in set(g) | set(o):
+                    assert np.abs(g.get(c, 0.0) - o.get(c, 0.0)).max() <= tol * hs, (s, int(row), c, tol)
+    graph.close()
 
 
 def test_64_scene_batch_equals_single_runs(gp, c4):

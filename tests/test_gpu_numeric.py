@@ -6,6 +6,9 @@ eigensystems expanded, and the numeric baseline (x-space Jacobi projection).
   1e-9 of the pair's largest entry, multiplicity included;
 * numeric route against the oracle's x-space route (orc_pair_xproj), same
   bar;
+* exact route (the exact local Hessian, Eq. 15 / Eq. 22 in full, projected
+  by Jacobi rotations) against the oracle's exact Hessians (second-order
+  forward differentiation) projected by its own Jacobi routine, same bar;
 * the two GPU routes agree on every non-mollified pair (rank one);
 * the analytic route equals the expansion of the eval's stored factors
   (gipc_pair_inspect) to rounding, on a scene and on a batch;
@@ -84,6 +87,9 @@ def test_routes_against_the_oracle(gp, which):
     ref = oracle.eval_scene(s.x, s.tuples, po, x_rest=s.x_rest, per_pair=True)
     _compare(Ha, pairs, s.tuples, ref["pairH"])
     _compare(Hn, pairs, s.tuples, oracle.eval_xproj(s.x, s.tuples, po, x_rest=s.x_rest))
+    Hx = gp.proxy_dense(ctx, X, pg, gp.PROJ_EXACT, x_rest=XR).cpu().numpy()
+    _, Hxo = oracle.eval_exact(s.x, s.tuples, po, x_rest=s.x_rest, want_exact=False)
+    _compare(Hx, pairs, s.tuples, Hxo)
     nonm = pairs["type"] < 5
     assert nonm.any()
     sc = np.abs(Ha[nonm]).max(axis=(1, 2))[:, None, None]
@@ -126,13 +132,60 @@ def test_full_scale_sampled_pairs(gp):
     pairs = {k: v[idx].cpu().numpy() for k, v in pi.items()}
     Ha = gp.proxy_dense(ctx, X, pg, gp.PROJ_ANALYTIC, x_rest=XR)[idx].cpu().numpy()
     Hn = gp.proxy_dense(ctx, X, pg, gp.PROJ_NUMERIC, x_rest=XR)[idx].cpu().numpy()
+    Hx = gp.proxy_dense(ctx, X, pg, gp.PROJ_EXACT, x_rest=XR)[idx].cpu().numpy()
     sub = s.tuples[pairs["src"]]
     ref = oracle.eval_scene(s.x, sub, po, x_rest=s.x_rest, per_pair=True)
     refx = oracle.eval_xproj(s.x, sub, po, x_rest=s.x_rest)
+    _, refe = oracle.eval_exact(s.x, sub, po, x_rest=s.x_rest, want_exact=False)
     pairs["src"] = np.arange(len(pick))
     _compare(Ha, pairs, sub, ref["pairH"])
     _compare(Hn, pairs, sub, refx)
+    _compare(Hx, pairs, sub, refe)
     assert (pairs["type"] >= 5).any() and (pairs["type"] < 5).any()
+    ctx.close()
+
+
+def test_exact_route_on_every_subtype(gp):
+    # point-triangle, point-edge, point-point, edge-edge and the mollified
+    # kinds (close-to-parallel encodings too), unmerged and merged
+    rng = np.random.default_rng(21)
+    xs, tup = [], []
+    for g in range(40):
+        off = np.array([3.0 * g, 0.0, 0.0])
+        b = len(xs)
+        kind = g % 5
+        if kind == 0:      # point over a triangle
+            xs += [off + [0.3, 0.3, rng.uniform(0.2, 0.8) * 0.1], off + [0, 0, 0], off + [1, 0, 0], off + [0, 1, 0]]
+            tup.append([-(b + 1), b + 1, b + 2, b + 3])
+        elif kind == 1:    # point beside an edge of a triangle
+            xs += [off + [0.5, -0.03, 0.05], off + [0, 0, 0], off + [1, 0, 0], off + [0, 1, 0]]
+            tup.append([-(b + 1), b + 1, b + 2, b + 3])
+        elif kind == 2:    # crossing edges
+            xs += [off + [0.5, -0.5, 0.06], off + [0.5, 0.5, 0.07], off + [0, 0, 0], off + [1, 0, 0]]
+            tup.append([b, b + 1, b + 2, b + 3])
+        elif kind == 3:    # nearly parallel edges, interior
+            t = rng.uniform(1e-4, 1e-3)
+            xs += [off + [0.1, -0.5 * t, 0.05], off + [0.9, 0.5 * t, 0.05], off + [0, 0, 0], off + [1, 0, 0]]
+            tup.append([b, -(b + 2), b + 2, b + 3])
+        else:              # nearly parallel, endpoint against edge
+            t = rng.uniform(1e-4, 1e-3)
+            xs += [off + [0.0, 0.0, 0.05], off + [-0.8, t, 0.05 + t], off + [-0.5, 0, 0], off + [0.5, 0, 0]]
+            tup.append([-(b + 1), -(b + 2), b + 2, -(b + 4)])
+    x = np.array(xs, float) + rng.normal(size=(len(xs), 3)) * 1e-4
+    t = np.array(tup, np.int32)
+    s = scenes.Scene("mix", x, x.copy(), np.zeros((0, 3), np.int32), np.zeros((0, 2), np.int32),
+                     np.zeros(len(x), np.int32), 0.1, 10.0, t)
+    ctx, pg, X, XR = _build(gp, s)
+    po = oracle.params(dhat=s.dhat, kappa=s.kappa)
+    pi = gp.pair_inspect(ctx, want=("src", "type", "vid", "mult"))
+    pairs = {k: v.cpu().numpy() for k, v in pi.items()}
+    assert len(pairs["src"]) == len(t) and set(pairs["type"].tolist()) >= {1, 2, 4, 5, 6}
+    Hx = gp.proxy_dense(ctx, X, pg, gp.PROJ_EXACT, x_rest=XR).cpu().numpy()
+    He, Hxo = oracle.eval_exact(s.x, s.tuples, po, x_rest=s.x_rest)
+    _compare(Hx, pairs, s.tuples, Hxo)
+    # indefinite inputs: the projection removed negative eigenvalues from most pairs
+    neg = sum(np.linalg.eigvalsh(He[p]).min() < -1e-9 * np.abs(He[p]).max() for p in range(len(t)))
+    assert neg >= len(t) // 2
     ctx.close()
 
 

@@ -6,6 +6,8 @@ is reduced in FP64 registers and rounded once to FP32; the SpMV reads FP32
 blocks and accumulates in FP32; PCG vectors, dot products and the block
 Jacobi preconditioner stay FP64.
 
+* FP64 energy and gradient against the oracle over the whole candidate list
+  (1e-9 relative, the active count within rounding of dhat);
 * FP32 against FP64 blocks of the same pattern: relative Frobenius error of
   the whole matrix <= 1e-5, and of every block <= 2^-24 (one rounding to
   nearest per entry);
@@ -56,6 +58,19 @@ def test_precision_mode_keeps_fp64_energy_and_gradient(c5):
     assert c5["E64"].item() == c5["E32"].item()
     assert torch.equal(c5["g64"], c5["g32"])
     assert c5["info"]["n_active"] > 50_000_000
+
+
+def test_fp64_energy_and_gradient_full_list_against_oracle(c5):
+    # every one of the ~234M candidates through the oracle (energy and
+    # gradient only), as the ten-sheet parity test does for its list
+    s = c5["s"]
+    po = oracle.params(dhat=s.dhat, kappa=s.kappa)
+    ref = oracle.eval_scene(s.x, s.tuples, po, x_rest=s.x_rest)
+    assert c5["E64"].item() == pytest.approx(ref["E"], rel=1e-9)
+    g = c5["g64"].cpu().numpy()
+    assert np.abs(g - ref["grad"]).max() <= 1e-9 * np.abs(ref["grad"]).max()
+    act = (ref["subtype"] > 0) & (ref["subtype"] != oracle.DEGENERATE)
+    assert abs(c5["info"]["n_active"] - int(act.sum())) <= 1e-6 * act.sum()
 
 
 def test_fp32_blocks_against_fp64_blocks(c5):
