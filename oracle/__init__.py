@@ -79,6 +79,10 @@ def lib():
         L.orc_pair_exact.restype = ctypes.c_int
         L.orc_eval_exact.argtypes = [i32, vp, vp, i64, vp, ctypes.POINTER(Params), ctypes.c_int, vp, vp]
         L.orc_eval_exact.restype = ctypes.c_int
+        L.orc_accd.argtypes = [vp, vp, vp, d, d, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int)]
+        L.orc_accd.restype = ctypes.c_int
+        L.orc_accd_scene.argtypes = [i32, vp, vp, i64, vp, d, d, ctypes.c_int, ctypes.c_int, vp]
+        L.orc_accd_scene.restype = i64
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_stencil.argtypes = [vp, vp]
@@ -243,6 +247,33 @@ def eval_exact(x, tuples, prm=None, x_rest=None, nthreads=0, want_exact=True, wa
                             int(nthreads), _ptr(H), _ptr(Hp)) < 0:
         raise ValueError("malformed tuple or vertex index out of range")
     return H, Hp
+
+
+def accd(tuple4, xs, ps, s=0.1, tc=1.0, max_iter=1_000_000):
+    """Additive CCD of one tuple moving by ps: (toi, trial steps; -1 if capped)."""
+    t = np.ascontiguousarray(tuple4, dtype=np.int32)
+    xs = _pad4(xs)
+    ps = _pad4(ps)
+    toi = ctypes.c_double()
+    it = ctypes.c_int()
+    rc = lib().orc_accd(t.ctypes.data, xs.ctypes.data, ps.ctypes.data, float(s), float(tc), int(max_iter),
+                        ctypes.byref(toi), ctypes.byref(it))
+    if rc == -2:
+        raise ValueError("malformed tuple")
+    return toi.value, it.value
+
+
+def accd_scene(x, disp, tuples, s=0.1, tc=1.0, max_iter=1_000_000, nthreads=0):
+    """orc_accd over a tuple list: (toi [P], number stopped by max_iter)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    d = np.ascontiguousarray(disp, dtype=np.float64)
+    t = np.ascontiguousarray(tuples, dtype=np.int32).reshape(-1, 4)
+    toi = np.zeros(t.shape[0])
+    n = lib().orc_accd_scene(int(x.shape[0]), x.ctypes.data, d.ctypes.data, t.shape[0], t.ctypes.data, float(s),
+                             float(tc), int(max_iter), int(nthreads), toi.ctypes.data)
+    if n < 0:
+        raise ValueError("malformed tuple or vertex index out of range")
+    return toi, int(n)
 
 
 def friction_f(y, eps_v, dt):

@@ -889,6 +889,115 @@ int orc_eval_exact(int32_t V, const double* x, const double* x_rest, int64_t P, 
     return 0;
 }
 
+/* ------------------------------------------------------------------ ACCD */
+
+/* Additive CCD (the line search's step bound, maxFeasibleStepSize of
+ * Algorithm 1; the paper adopts the additive CCD of Li et al., Codimensional
+ * IPC, 2021, as its Related Work says), restated: the pair moves as
+ * x(t) = x + t p.  The common translation is removed from p (the mean over
+ * the vertices the distance involves); l_p is the largest |p_i| over the
+ * first primitive plus the largest over the second, a bound on how fast the
+ * distance can fall.  With d0 the distance at t = 0 and the gap g = s d0:
+ *   t = 0, t_l = (1 - s) d0 / l_p
+ *   repeat: d = distance at t + t_l; if t > 0 and d < g stop;
+ *           t = t + t_l; if t > t_c return t_c; t_l = 0.9 d / l_p
+ * and t is returned.  The trial positions are x + (t + t_l) p, formed from
+ * x each time.  l_p = 0 (no relative motion) returns t_c; d0 = 0 returns 0.
+ * *iters receives the trial steps taken; a search stopped by max_iter
+ * returns the t accumulated so far and -1. */
+int orc_accd(const int32_t tuple[4], const double* xs, const double* ps, double s, double tc, int max_iter,
+             double* toi, int* iters) {
+    int32_t vid[4];
+    int kind;
+    const int nv = decode(tuple, vid, &kind);
+    *toi = 0.0;
+    if (iters) *iters = 0;
+    if (nv < 0) return -2;
+    double X[4][3], Pd[4][3];
+    for (int k = 0; k < 4; ++k)
+        for (int d = 0; d < 3; ++d) {
+            X[k][d] = k < nv ? xs[3 * k + d] : 0.0;
+            Pd[k][d] = k < nv ? ps[3 * k + d] : 0.0;
+        }
+    /* the two primitives of the kind, as slot lists */
+    int first[2], nf, second[3], ns;
+    switch (kind) {
+        case K_EE: first[0] = 0; first[1] = 1; nf = 2; second[0] = 2; second[1] = 3; ns = 2; break;
+        case K_PT: first[0] = 0; nf = 1; second[0] = 1; second[1] = 2; second[2] = 3; ns = 3; break;
+        case K_PE: first[0] = 0; nf = 1; second[0] = 1; second[1] = 2; ns = 2; break;
+        case K_PP: first[0] = 0; nf = 1; second[0] = 1; ns = 1; break;
+        case K_PE_PAR: first[0] = 0; nf = 1; second[0] = 2; second[1] = 3; ns = 2; break;
+        default: first[0] = 0; nf = 1; second[0] = 2; ns = 1; break;
+    }
+    double mean[3] = {0, 0, 0};
+    for (int a = 0; a < nf; ++a)
+        for (int d = 0; d < 3; ++d) mean[d] += Pd[first[a]][d];
+    for (int a = 0; a < ns; ++a)
+        for (int d = 0; d < 3; ++d) mean[d] += Pd[second[a]][d];
+    for (int d = 0; d < 3; ++d) mean[d] /= (double)(nf + ns);
+    for (int k = 0; k < 4; ++k)
+        for (int d = 0; d < 3; ++d) Pd[k][d] -= mean[d];
+    double l1 = 0.0, l2 = 0.0;
+    for (int a = 0; a < nf; ++a) l1 = fmax(l1, sqrt(dot3(Pd[first[a]], Pd[first[a]])));
+    for (int a = 0; a < ns; ++a) l2 = fmax(l2, sqrt(dot3(Pd[second[a]], Pd[second[a]])));
+    const double lp = l1 + l2;
+    orc_dist D;
+    dist_of(kind, X, &D);
+    if (!(D.d2 > 0.0) || !isfinite(D.d2)) return 1;   /* touching: no step */
+    if (!(lp > 0.0)) { *toi = tc; return 0; }
+    const double d0 = sqrt(D.d2), g = s * d0;
+    double t = 0.0, tl = (1.0 - s) * d0 / lp;
+    for (int it = 1; it <= max_iter; ++it) {
+        double Xt[4][3];
+        for (int k = 0; k < 4; ++k)
+            for (int d = 0; d < 3; ++d) Xt[k][d] = X[k][d] + (t + tl) * Pd[k][d];
+        orc_dist Dt;
+        dist_of(kind, Xt, &Dt);
+        const double dd = sqrt(Dt.d2);
+        if (iters) *iters = it;
+        if (t > 0.0 && dd < g) { *toi = t; return 0; }
+        t = t + tl;
+        if (t > tc) { *toi = tc; return 0; }
+        tl = 0.9 * dd / lp;
+    }
+    *toi = t;
+    if (iters) *iters = -1;
+    return 0;
+}
+
+int64_t orc_accd_scene(int32_t V, const double* x, const double* disp, int64_t P, const int32_t* tuples, double s,
+                       double tc, int max_iter, int nthreads, double* toi) {
+    for (int64_t p = 0; p < P; ++p) {
+        int32_t vid[4];
+        int nv = orc_stencil(tuples + 4 * p, vid);
+        if (nv < 0) return -1;
+        for (int k = 0; k < nv; ++k)
+            if (vid[k] < 0 || vid[k] >= V) return -1;
+    }
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    int64_t capped = 0;
+    #pragma omp parallel for schedule(dynamic, 256) reduction(+:capped)
+    for (int64_t p = 0; p < P; ++p) {
+        const int32_t* t = tuples + 4 * p;
+        int32_t vid[4];
+        int nv = orc_stencil(t, vid);
+        double xs[12] = {0}, ps[12] = {0};
+        for (int k = 0; k < nv; ++k)
+            for (int d = 0; d < 3; ++d) {
+                xs[3 * k + d] = x[3 * (int64_t)vid[k] + d];
+                ps[3 * k + d] = disp[3 * (int64_t)vid[k] + d];
+            }
+        int it = 0;
+        orc_accd(t, xs, ps, s, tc, max_iter, toi + p, &it);
+        if (it < 0) ++capped;
+    }
+    return capped;
+}
+
 /* ------------------------------------------------------------- friction */
 
 /* f0, f1 = f0' and f1' of the smooth static-to-dynamic transition
@@ -1256,7 +1365,7 @@ static double vdot(int64_t n, const double* a, const double* b) {
 
 /* Preconditioned conjugate gradients (Saad, "Iterative Methods for Sparse
  * Linear Systems", Alg. 9.1) with the 3x3 block diagonal as preconditioner,
- * the paper's simple block preconditioner (Sec. 6.2). */
+ * the paper's simple block preconditioner (Sec. 7.2). */
 int orc_pcg(int32_t V, int64_t nb, const int32_t* rows, const int32_t* cols, const double* vals,
             const double* b, double* x, double rtol, int maxit, double* relres) {
     const int64_t n = 3 * (int64_t)V;

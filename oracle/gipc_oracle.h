@@ -104,6 +104,22 @@ int orc_pair_exact(const int32_t tuple[4], const double* xs, const double* xr, c
 int orc_eval_exact(int32_t V, const double* x, const double* x_rest, int64_t P, const int32_t* tuples,
                    const orc_params* prm, int nthreads, double* pairH, double* pairHp);
 
+/*
+ * Additive CCD of one tuple moving as x(t) = xs + t ps (both [4][3]): the
+ * accumulated safe time *toi (lower bound on the time of impact, at most tc;
+ * tc without relative motion; 0 at distance 0), with the minimum
+ * separation fraction s.  *iters (nullable) = trial steps, -1 if max_iter
+ * stopped it.  Returns -2 on a malformed tuple, 1 at distance 0, else 0.
+ */
+int orc_accd(const int32_t tuple[4], const double* xs, const double* ps, double s, double tc, int max_iter,
+             double* toi, int* iters);
+
+/* orc_accd for every tuple of a list (positions x, displacements disp, both
+ * [V][3]): toi [P].  Returns the number stopped by max_iter, -1 on a
+ * malformed tuple or index. */
+int64_t orc_accd_scene(int32_t V, const double* x, const double* disp, int64_t P, const int32_t* tuples, double s,
+                       double tc, int max_iter, int nthreads, double* toi);
+
 /* f0, f1 and f1' of the friction transition at y (h = dt). */
 void orc_friction_f(double y, double eps_v, double dt, double* f0, double* f1, double* df1);
 
