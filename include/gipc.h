@@ -281,6 +281,30 @@ gipc_status gipc_pcg(gipc_ctx* ctx, const gipc_bsr* A, const double* b, double* 
                      int32_t* iters, double* relres, void* stream);
 
 /*
+ * gipc_pcg for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same solve, kernels and launch sequence as gipc_pcg, with its work
+ * vectors, inverted diagonal blocks, reduction partials and scalars in a
+ * fixed area of GIPC_PCG_STATIC_SCRATCH_BYTES bytes that the library's code
+ * object holds on every GPU it is loaded on (kept until the process ends).
+ * No context; calls no hipMalloc or hipFree.  The caller passes the matrix
+ * and the vectors (b, x: device double [nbrows][3], x holds x0 on entry) as
+ * for gipc_pcg, and gets the same results.  The area needs about
+ * 168 bytes per block row (180 with FP32 blocks) plus 24 bytes per
+ * workgroup of the product, so it holds systems of up to about 390,000
+ * block rows (370,000 with FP32 blocks); larger ones return WORKSPACE with
+ * nothing launched.  Every
+ * call on a GPU uses that GPU's one area, which keeps the last call's
+ * contents (each call initialises what it reads): calls that overlap on one
+ * GPU -- from two host threads, or on two streams without ordering -- race
+ * and give wrong results.  Synchronises `stream`.  Returns as gipc_pcg
+ * (BREAKDOWN, WARN_NOT_CONVERGED, INVALID_ARG, WORKSPACE, HIP).
+ */
+#define GIPC_PCG_STATIC_SCRATCH_BYTES (64u << 20)
+gipc_status gipc_pcg_static(const gipc_bsr* A, const double* b, double* x, double rtol, int32_t maxit,
+                            int32_t* iters, double* relres, void* stream);
+
+/*
  * Matrix-free operator: y = (diag (x) I3 + sum_k S_k^T H_k S_k) x with the
  * proxy Hessians H_k of the last eval (Sec. 5, Eq. 28 and the factor form of
  * Sec. 4), applied pair by pair from their compact factors without forming a

@@ -29,7 +29,7 @@ EXPORTS = [
     "gipc_bsr_spmv", "gipc_pcg", "gipc_pair_inspect", "gipc_copy", "gipc_get_tune", "gipc_set_tune",
     "gipc_autotune", "gipc_graph_create", "gipc_graph_launch", "gipc_graph_destroy", "gipc_mf_apply",
     "gipc_pcg_mf", "gipc_proxy_dense", "gipc_friction_lag", "gipc_friction_eval", "gipc_candidates",
-    "gipc_read", "gipc_pairs_check",
+    "gipc_read", "gipc_pairs_check", "gipc_pcg_static",
 ]
 
 
@@ -131,6 +131,8 @@ def lib():
                                         ctypes.POINTER(Bsr), vp]),
             "gipc_bsr_spmv": (st, [ctypes.POINTER(Bsr), vp, vp, vp]),
             "gipc_pcg": (st, [vp, ctypes.POINTER(Bsr), vp, vp, d, i32, ctypes.POINTER(i32), ctypes.POINTER(d), vp]),
+            "gipc_pcg_static": (st, [ctypes.POINTER(Bsr), vp, vp, d, i32, ctypes.POINTER(i32), ctypes.POINTER(d),
+                                     vp]),
             "gipc_mf_apply": (st, [vp, vp, vp, vp, vp]),
             "gipc_pcg_mf": (st, [vp, vp, vp, vp, d, i32, ctypes.POINTER(i32), ctypes.POINTER(d), vp]),
             "gipc_proxy_dense": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), i32, vp, vp]),
@@ -408,6 +410,20 @@ def pcg(ctx: Context, A: BsrMatrix, b, x=None, rtol=1e-6, maxit=1000, stream=Non
     s = lib().gipc_pcg(ctx.h, ctypes.byref(desc), _ptr(b), _ptr(x), float(rtol), int(maxit), ctypes.byref(it),
                        ctypes.byref(rr), _stream(stream))
     ctx._check(s, "gipc_pcg")
+    return x, int(it.value), float(rr.value), int(s)
+
+
+def pcg_static(A: BsrMatrix, b, x=None, rtol=1e-6, maxit=1000, stream=None):
+    """gipc_pcg on the library's fixed work area (no context, no device
+    allocation by the library).  Returns (x, iterations, relres, status)."""
+    _need(b, torch.float64, 3, "b")
+    x = torch.zeros_like(b) if x is None else x
+    it = ctypes.c_int32()
+    rr = ctypes.c_double()
+    s = lib().gipc_pcg_static(ctypes.byref(A.desc), _ptr(b), _ptr(x), float(rtol), int(maxit), ctypes.byref(it),
+                              ctypes.byref(rr), _stream(stream))
+    if s < 0:
+        raise GipcError(s, f"gipc_pcg_static: {status_string(s)}")
     return x, int(it.value), float(rr.value), int(s)
 
 

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgipc.so")
-SOURCES = ["api.hip", "scan.hip", "stage.hip", "merge.hip", "order.hip", "symbolic.hip", "eval.hip", "assemble.hip", "solve.hip", "numeric.hip", "friction.hip", "candidates.hip"]
+SOURCES = ["api.hip", "scan.hip", "stage.hip", "merge.hip", "order.hip", "symbolic.hip", "eval.hip", "assemble.hip", "solve.hip", "numeric.hip", "friction.hip", "candidates.hip",
+           "noalloc.hip"]
 ARCH = "gfx950"
 
 FLAGS = [
