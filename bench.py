@@ -252,8 +252,128 @@ def numeric_compare(gp, ctx, x, xr, prm, info, stream):
         "analytic_ms": t_a, "numeric_jacobi_ms": t_n, "speedup": t_n / t_a,
         "output_gb": n * 1152 / 1e9,
         "paper_table1": "10^7 12x12 Hessians: Eigen (CPU) 2.42e3 ms vs analytic 4.95e2 ms on the CPU (4.9x); "
-                        "analytic on the GPU 9.01e1 ms; 16-core Intel Core i9 12900K and RTX 4090 (Sec. 7)",
+                        "analytic on the GPU 9.01e1 ms; 16-core Intel Core i9 12900K and RTX 4090 (Sec. 8)",
     }
+
+
+def dense_compare(gp, ctx, x, xr, prm, diag, info, stream, maxit=100):
+    """Table 2's comparison on wave64: the matrix-free product from dense
+    local Hessians, one lane per local mat-vec against one lane per matrix
+    entry with a wavefront segmented reduction (both adding to y with FP64
+    atomics), one product and a fixed-length PCG each, next to the
+    factor-form operator and the BSR matrix of the same eval."""
+    import torch
+    st = info["n_staged_by_type"]
+    n = int(info["n_staged"])
+    n12 = st["PT"] + st["EE"] + st["EE_moll"] + st["PE_moll"] + st["PP_moll"]
+    H = gp.proxy_dense(ctx, x, prm, gp.PROJ_ANALYTIC, x_rest=xr)
+    E, g = gp.barrier_eval(ctx, x, prm, x_rest=xr)
+    V = x.shape[0]
+    v = torch.tensor(np.random.default_rng(0).normal(size=(V, 3)), device=x.device)
+    y = torch.empty_like(v)
+    entries = 144 * n12 + 81 * st["PE"] + 36 * st["PP"]
+    # algorithmic bytes of one product: the dense entries, the stencils, x
+    # and diag read, y written
+    dbytes = 8 * entries + 16 * n + 24 * V + 8 * V + 24 * V
+    ym = gp.mf_apply(ctx, v, diag=diag)
+    res = {"pairs": n, "entries": int(entries), "apply_bytes": int(dbytes)}
+    for name, scheme in (("thread_per_matvec", gp.DENSE_THREAD), ("entry_segmented", gp.DENSE_ENTRY)):
+        t = _median_ms(lambda: gp.dense_apply(ctx, H, v, y=y, diag=diag, scheme=scheme), 5, stream)
+        gap = float((y - ym).abs().max() / ym.abs().max())
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        d, it, rr, stt = gp.pcg_dense(ctx, H, -g, diag=diag, scheme=scheme, rtol=0.0, maxit=maxit)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[name] = {"apply_ms": t, "apply_gbs": dbytes / (t * 1e-3) / 1e9, "vs_factor_operator_max_rel_gap": gap,
+                     "pcg_iters": it, "pcg_ms": e0.elapsed_time(e1), "pcg_ms_per_iter": e0.elapsed_time(e1) / it}
+    res["entry_vs_thread_apply"] = res["thread_per_matvec"]["apply_ms"] / res["entry_segmented"]["apply_ms"]
+    res["entry_vs_thread_pcg"] = res["thread_per_matvec"]["pcg_ms"] / res["entry_segmented"]["pcg_ms"]
+    res["paper_table2"] = ("PCG time, warp reduction vs thread per local mat-vec: 3.82x-4.11x (avg 3.97x), "
+                           "RTX 4090, FP64 (Table 2)")
+    del H
+    return res
+
+
+def _table1_tuples(kind, n, dhat, seed, dev):
+    """n active tuples of one kind, each on its own vertices (seeded, on the
+    device): a point over a triangle's interior (12 x 12), beside a segment's
+    interior (9 x 9) or near a point (6 x 6), at distance (0.1 .. 0.9) dhat."""
+    import torch
+    g = torch.Generator(device=dev).manual_seed(seed)
+    L = 20.0 * dhat
+    u = lambda *sh: torch.rand(*sh, generator=g, device=dev, dtype=torch.float64)  # noqa: E731
+    h = (0.1 + 0.8 * u(n)) * dhat
+    i64 = torch.arange(n, device=dev, dtype=torch.int64)
+    base = 3.0 * L * torch.stack([i64 % 256, (i64 // 256) % 256, i64 // 65536], 1).to(torch.float64)
+    if kind == 12:
+        t0 = base
+        t1 = base + torch.stack([L * (0.9 + 0.2 * u(n)), L * 0.1 * (u(n) - 0.5), torch.zeros_like(h)], 1)
+        t2 = base + torch.stack([L * 0.1 * (u(n) - 0.5), L * (0.9 + 0.2 * u(n)), torch.zeros_like(h)], 1)
+        p = base + torch.stack([L * (0.15 + 0.2 * u(n)), L * (0.15 + 0.2 * u(n)), h], 1)
+        x = torch.stack([p, t0, t1, t2], 1).reshape(-1, 3)
+        i = torch.arange(n, device=dev, dtype=torch.int32) * 4
+        tup = torch.stack([-(i + 1), i + 1, i + 2, i + 3], 1)
+    elif kind == 9:
+        th = 2.0 * np.pi * u(n)
+        e1 = base + torch.stack([L * (0.9 + 0.2 * u(n)), torch.zeros_like(h), torch.zeros_like(h)], 1)
+        p = base + torch.stack([L * (0.2 + 0.6 * u(n)) * 0.9, h * torch.cos(th), h * torch.sin(th)], 1)
+        x = torch.stack([p, base, e1], 1).reshape(-1, 3)
+        i = torch.arange(n, device=dev, dtype=torch.int32) * 3
+        tup = torch.stack([-(i + 1), i + 1, i + 2, torch.full_like(i, -1)], 1)
+    else:
+        dirs = torch.randn(n, 3, generator=g, device=dev, dtype=torch.float64)
+        dirs = dirs / dirs.norm(dim=1, keepdim=True)
+        x = torch.stack([base + h[:, None] * dirs, base], 1).reshape(-1, 3)
+        i = torch.arange(n, device=dev, dtype=torch.int32) * 2
+        tup = torch.stack([-(i + 1), i + 1, torch.full_like(i, -1), torch.full_like(i, -1)], 1)
+    return x.contiguous(), tup.contiguous()
+
+
+def table1_compare(gp, counts=(10 ** 3, 10 ** 4, 10 ** 5, 10 ** 6, 10 ** 7)):
+    """Table 1 on this GPU: time to construct and PSD-project n barrier
+    Hessians of one size (12 x 12 point-triangle, 9 x 9 point-edge, 6 x 6
+    point-point), by the analytic eigensystems against the traditional route
+    (the exact Hessian, Eq. 15 with the second derivative of J, projected by
+    cyclic Jacobi rotations) and the Gauss-Newton matrix projected in x-space."""
+    import torch
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    dhat = 1e-3
+    prm = gp.params(dhat=dhat, kappa=1e4)
+    rows = []
+    for dim in (12, 9, 6):
+        for n in counts:
+            x, tup = _table1_tuples(dim, n, dhat, 1000 + dim, dev)
+            ctx = gp.Context()
+            info = gp.pairs_build(ctx, x, tup, prm)
+            assert int(info["n_staged"]) == n, (dim, n, info["n_staged"])
+            hess = torch.empty((n, 12, 12), dtype=torch.float64, device=dev)
+            reps = 5 if n <= 10 ** 6 else 3
+            t = {name: _median_ms(lambda: gp.proxy_dense(ctx, x, prm, m, hess=hess), reps, stream)
+                 for name, m in (("analytic", gp.PROJ_ANALYTIC), ("exact_jacobi", gp.PROJ_EXACT),
+                                 ("gauss_newton_jacobi", gp.PROJ_NUMERIC))}
+            rows.append({"dims": dim, "count": n, **{f"{k}_ms": v for k, v in t.items()},
+                         "speedup_vs_exact": t["exact_jacobi"] / t["analytic"]})
+            ctx.close()
+            del x, tup, hess
+            torch.cuda.empty_cache()
+    print(f"[bench] table1 done", file=sys.stderr, flush=True)
+    return {"rows": rows,
+            "paper_table1": "RTX 4090 FP64, GPU analytic: 10^7 12x12 90.1 ms, 9x9 41.0 ms, 6x6 13.2 ms; CPU "
+                            "(i9 12900K) Eigen numeric 2.42e3 / 1.45e3 / 4.79e2 ms vs analytic 4.95e2 / 2.29e2 / "
+                            "96.8 ms"}
+
+
+def accd_compare(gp, ctx, x, tup, d, stream):
+    """The line search's step bound (additive CCD) over every candidate of
+    the scene along the step's PCG direction d."""
+    P = int(tup.shape[0])
+    toi, info = gp.accd(ctx, x, d, tup, s=0.1, tc=1.0)
+    t = _median_ms(lambda: gp.accd(ctx, x, d, tup, s=0.1, tc=1.0, toi=toi), 5, stream)
+    return {"tuples": P, "ms": t, "tuples_per_s": P / (t * 1e-3), "step": info["step"],
+            "max_trial_steps": info["max_steps"], "capped": info["n_capped"], "touching": info["n_touching"],
+            "direction": "the PCG solution of the step (Newton direction), tc = 1, s = 0.1"}
 
 
 def friction_compare(gp, ctx, x, xr, prm, diag, info, stream):
@@ -598,7 +718,7 @@ def single_run(gp, args, workload, steps, warmup, cands_on_gpu):
         "traffic_source": tsrc,
         "bytes_per_launch": int(spmv_bytes),
     }
-    return out, (ctx, s, x, xr, prm, diag, info, rtol, maxit, stream, last)
+    return out, (ctx, s, x, xr, prm, diag, info, rtol, maxit, stream, last, tup)
 
 
 def bandwidth_reference(gp, stream):
@@ -629,7 +749,8 @@ def bandwidth_reference(gp, stream):
 def sheets40_leg(gp, args):
     """The precision target: FP32 blocks and SpMV on forty sheets, PCG to 1e-6,
     against the HBM roofline; the FP64 path once for the comparison."""
-    out, (ctx, s, x, xr, prm, diag, info, rtol, maxit, stream, last) = single_run(gp, args, "sheets40", 2, 1, True)
+    out, (ctx, s, x, xr, prm, diag, info, rtol, maxit, stream, last, _) = single_run(gp, args, "sheets40", 2, 1,
+                                                                                     True)
     leg = {k: out[k] for k in ("config", "breakdown_ms", "spmv_gbs", "pcg_iter_gbs", "pcg_iter_vs_spmv", "roofline")}
     leg["value_contact_pairs_per_s"] = out["value"]
     leg["spmv_hbm_frac"] = out["spmv_gbs"] / HBM_PEAK_GBS
@@ -660,7 +781,7 @@ def main():
         print(json.dumps(line))
         return
     workload = args.workload
-    out, (ctx, s, x, xr, prm, diag, info, rtol, maxit, stream, last) = single_run(
+    out, (ctx, s, x, xr, prm, diag, info, rtol, maxit, stream, last, tup) = single_run(
         gp, args, workload, args.steps, args.warmup, workload == "sheets40")
     bw = bandwidth_reference(gp, stream)
     out["bandwidth_reference"] = bw
@@ -672,10 +793,16 @@ def main():
         out["matrix_free"] = matrix_free_compare(gp, ctx, x, xr, prm, diag, info, rtol, maxit, stream)
         if workload == "sheets10":
             out["numeric_eigen_baseline"] = numeric_compare(gp, ctx, x, xr, prm, info, stream)
+            out["dense_local_hessians_table2"] = dense_compare(gp, ctx, x, xr, prm, diag, info, stream)
+            out["accd"] = accd_compare(gp, ctx, x, tup, last[3], stream)
             out["friction"] = friction_compare(gp, ctx, x, xr, prm, diag, info, stream)
             out["candidates"] = candidates_compare(gp, ctx, s, x, stream)
+            print(f"[bench] extras done", file=sys.stderr, flush=True)
     ctx.close()
     del x, xr, diag
+    if workload == "sheets10" and not args.no_extras:
+        torch.cuda.empty_cache()
+        out["table1"] = table1_compare(gp)
     if workload == "sheets10" and not args.no_targets:
         torch.cuda.empty_cache()
         out["targets"] = {"batch64": batch_leg(gp, 3, 1)}

@@ -8,7 +8,7 @@
  * gradient (Eq. 13-14, Eq. 30) and its analytically projected Gauss-Newton
  * proxy Hessian (Eq. 18-23 and Eq. 32-36), assembles the local Hessians
  * into a 3x3 block-sparse (BSR) matrix, and solves with it by block-Jacobi
- * preconditioned conjugate gradients (Sec. 6.2).
+ * preconditioned conjugate gradients (Sec. 7.2).
  *
  * Conventions for every entry point:
  *  - Pointers documented as "device" are HIP device pointers; the caller
@@ -25,6 +25,7 @@
 #ifndef GIPC_H
 #define GIPC_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -164,15 +165,32 @@ typedef struct gipc_ctx gipc_ctx;
 const char* gipc_status_string(int status);
 
 /* Create a context on the current HIP device.  Allocates only a few small
- * buffers; larger ones grow on demand.  *out is NULL on failure. */
+ * buffers; larger ones grow on demand (hipMalloc).  *out is NULL on failure. */
 gipc_status gipc_ctx_create(gipc_ctx** out);
+
+/* Device memory from the caller, e.g. a framework's caching allocator:
+ * alloc returns a pointer to at least `bytes` bytes of device memory on
+ * `device`, 256-byte aligned, or NULL (the call needing it then fails with
+ * WORKSPACE); free takes back a pointer alloc returned, with the same size.
+ * The library calls them from the host thread that calls it; it hands a
+ * block back only when nothing queued on the device can still use it (it
+ * synchronises the device first: buffers grow rarely, and on destroy). */
+typedef struct {
+    void* (*alloc)(void* user, size_t bytes, int device);
+    void (*free)(void* user, void* ptr, size_t bytes, int device);
+    void* user;
+} gipc_allocator;
+
+/* gipc_ctx_create with every buffer of the context taken from `al` (host
+ * struct, copied; NULL = hipMalloc).  INVALID_ARG if a callback is NULL. */
+gipc_status gipc_ctx_create_with_allocator(const gipc_allocator* al, gipc_ctx** out);
 /* Free every buffer the context holds (synchronises its device).  NULL ok. */
 void gipc_ctx_destroy(gipc_ctx* ctx);
 /* Message of the last error on this context ("" if none). */
 const char* gipc_ctx_last_error(const gipc_ctx* ctx);
 
 /*
- * Stage a pair list and build the block pattern (Sec. 6.2 "Data
+ * Stage a pair list and build the block pattern (Sec. 7.2 "Data
  * structures"; matrix decomposition of supplement Sec. 6).
  * Classifies every tuple at positions mesh->x by the active constraints of
  * Eq. 4 / Eq. 5, drops pairs at distance >= dhat, sorts the active ones by
@@ -265,7 +283,7 @@ gipc_status gipc_bsr_spmv(const gipc_bsr* A, const void* x, void* y, void* strea
 
 /*
  * Solve A x = b by conjugate gradients preconditioned with the inverses of
- * A's 3x3 diagonal blocks (Sec. 6.2; Saad Alg. 9.1).  b, x: device double
+ * A's 3x3 diagonal blocks (Sec. 7.2; Saad Alg. 9.1).  b, x: device double
  * [nbrows][3]; x holds x0 on entry and the result on return.  A may be FP64
  * or FP32; with FP32 blocks the product A p reads an FP32 copy of p and
  * accumulates in FP32, while vectors, dot products and the preconditioner
@@ -306,8 +324,8 @@ gipc_status gipc_pcg_static(const gipc_bsr* A, const double* b, double* x, doubl
 
 /*
  * Matrix-free operator: y = (diag (x) I3 + sum_k S_k^T H_k S_k) x with the
- * proxy Hessians H_k of the last eval (Sec. 5, Eq. 28 and the factor form of
- * Sec. 4), applied pair by pair from their compact factors without forming a
+ * proxy Hessians H_k of the last eval (Eq. 20-23 and Eq. 32-36, in the factor
+ * form of Eq. 15-17), applied pair by pair from their compact factors without forming a
  * matrix; this is the operator of the paper's matrix-free PCG (supplement,
  * Sec. 6).  It equals gipc_bsr_spmv with the matrix gipc_assemble_bsr would
  * produce in FP64 (same products, summed in another order).  x, y: device
@@ -329,6 +347,40 @@ gipc_status gipc_mf_apply(gipc_ctx* ctx, const double* diag, const double* x, do
 gipc_status gipc_pcg_mf(gipc_ctx* ctx, const double* diag, const double* b, double* x, double rtol, int32_t maxit,
                         int32_t* iters, double* relres, void* stream);
 
+/* schemes of gipc_dense_apply / gipc_pcg_dense */
+#define GIPC_DENSE_THREAD 0  /* one lane per pair computes its whole local product */
+#define GIPC_DENSE_ENTRY 1   /* one lane per matrix entry, rows summed by a wavefront segmented reduction */
+
+/*
+ * The matrix-free product of the paper's PCG from dense local Hessians, in
+ * the two parallel schemes its Table 2 compares (supplement Sec. 6,
+ * "Parallel local matrix-vector multiplication"):
+ * y = (diag (x) I3 + sum_k S_k^T H_k S_k) x with H_k read from hess (device
+ * double [info.n_staged][12][12] as gipc_proxy_dense writes it on the
+ * current build: the leading 3n x 3n block of pair k, n its stencil
+ * vertices, times its multiplicity), one launch per stencil size (the
+ * paper's type buffers).  GIPC_DENSE_THREAD gives each pair one lane, which
+ * forms its 3n local rows; GIPC_DENSE_ENTRY gives each matrix entry one lane
+ * and sums the 3n lanes of a local row inside the wavefront (a segmented
+ * reduction; rows cut by a wavefront boundary are summed in two parts).
+ * Both add the local rows to y with FP64 atomics, as the paper does, so the
+ * result varies from run to run in its last bits (the summation order is
+ * not fixed).  x, y: device double [V][3], must not alias; diag: device
+ * double [V], nullable = 0.  Errors: INVALID_ARG (bad scheme, NULL),
+ * STATE (no build), HIP.
+ */
+gipc_status gipc_dense_apply(gipc_ctx* ctx, const double* hess, int32_t scheme, const double* diag, const double* x,
+                             double* y, void* stream);
+
+/*
+ * gipc_pcg with the product of gipc_dense_apply (FP64 throughout): the
+ * preconditioner inverts diag + the 3x3 diagonal blocks of the local
+ * Hessians, summed per vertex in a fixed order.  Same arguments, stopping
+ * rule, synchronisation and returns as gipc_pcg.
+ */
+gipc_status gipc_pcg_dense(gipc_ctx* ctx, const double* hess, int32_t scheme, const double* diag, const double* b,
+                           double* x, double rtol, int32_t maxit, int32_t* iters, double* relres, void* stream);
+
 /* Surface topology for candidate generation (device arrays): the object
  * id of every vertex (candidates only pair different objects; a triangle or
  * edge belongs to the object of its first vertex), triangles int32 [F][3]
@@ -347,7 +399,7 @@ typedef struct {
  * objects, whose axis-aligned boxes come within dhat (one box inflated by
  * dhat, closed intervals): the pairs the sum of Eq. 3 ranges over before
  * the distance decides which are active.  A uniform grid stands in for the
- * paper's BVH (Sec. 6.2).  Output tuples in the encoding above, int32
+ * paper's BVH (Sec. 7.2).  Output tuples in the encoding above, int32
  * [count][4] device: point-triangle [-(p+1), t0, t1, t2] grouped by point
  * in increasing p, then edge-edge [a0, a1, b0, b1] grouped by first edge;
  * deterministic.  *count (host) receives the number of candidates; tuples
@@ -359,6 +411,38 @@ typedef struct {
  */
 gipc_status gipc_candidates(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_topology* topo, double dhat,
                             int32_t* tuples, int64_t cap, int64_t* count, void* stream);
+
+/* Result of gipc_accd (host struct). */
+typedef struct {
+    double step;          /* smallest time over the tuples (tc when P = 0): the largest feasible step */
+    int64_t n_capped;     /* tuples whose search max_iter stopped (their time is the one accumulated) */
+    int64_t n_touching;   /* tuples at distance 0 (or non-finite) at t = 0: time 0 */
+    int32_t max_steps;    /* most trial steps any tuple took */
+} gipc_accd_info;
+
+/*
+ * Step bound of the line search (maxFeasibleStepSize in Algorithm 1) by
+ * additive CCD, which the paper adopts (Related Work, "Collision
+ * Detection"): every tuple (the encoding of gipc_pairs, distance the
+ * constrained minimum of Eq. 4 / Eq. 5) moves as x(t) = x + t disp over
+ * t in [0, tc].  With the mean displacement of the tuple's vertices removed
+ * and l_p the largest displacement norm over its first primitive plus the
+ * largest over its second, the distance falls at most at rate l_p; from
+ * d0 = d(0) the search takes a first sub-step (1 - s) d0 / l_p, then
+ * 0.9 d / l_p from each accepted point (d the distance there), and stops at
+ * the first trial point whose distance is below s d0, returning the time
+ * accumulated before it, or returns tc once the time passes tc; no relative
+ * motion gives tc and d0 = 0 gives 0.  The time is a lower bound on the
+ * time of impact (the distance stays above s d0 up to it).
+ * mesh->x: positions at t = 0 (device double [V][3]); disp: device double
+ * [V][3]; toi: device double [P], nullable (the time of each tuple);
+ * s in (0, 1): the separation kept (e.g. 0.1); tc >= 0 finite: the largest
+ * step (1 for alpha <= 1); max_iter >= 1: trial steps per tuple.
+ * Synchronises `stream` and fills info (host, nullable).  Errors:
+ * INVALID_ARG, INDEX (a malformed tuple; info is not filled), HIP.
+ */
+gipc_status gipc_accd(gipc_ctx* ctx, const gipc_mesh* mesh, const double* disp, const gipc_pairs* pairs, double s,
+                      double tc, int32_t max_iter, double* toi, gipc_accd_info* info, void* stream);
 
 /* Lagged friction parameters (supplement Sec. 5): friction coefficient mu,
  * the velocity threshold eps_v of the transition f1 and the time step dt

@@ -24,12 +24,12 @@ F64, F32 = 0, 1
 SUBTYPES = {1: "PT", 2: "PE", 3: "PP", 4: "EE", 5: "EE_moll", 6: "PE_moll", 7: "PP_moll"}
 
 EXPORTS = [
-    "gipc_status_string", "gipc_ctx_create", "gipc_ctx_destroy", "gipc_ctx_last_error", "gipc_pairs_build",
+    "gipc_status_string", "gipc_ctx_create", "gipc_ctx_create_with_allocator", "gipc_ctx_destroy", "gipc_ctx_last_error", "gipc_pairs_build",
     "gipc_get_info", "gipc_bsr_pattern", "gipc_barrier_eval", "gipc_assemble_bsr", "gipc_eval_assemble",
     "gipc_bsr_spmv", "gipc_pcg", "gipc_pair_inspect", "gipc_copy", "gipc_get_tune", "gipc_set_tune",
     "gipc_autotune", "gipc_graph_create", "gipc_graph_launch", "gipc_graph_destroy", "gipc_mf_apply",
     "gipc_pcg_mf", "gipc_proxy_dense", "gipc_friction_lag", "gipc_friction_eval", "gipc_candidates",
-    "gipc_read", "gipc_pairs_check", "gipc_pcg_static",
+    "gipc_read", "gipc_pairs_check", "gipc_pcg_static", "gipc_accd", "gipc_dense_apply", "gipc_pcg_dense",
 ]
 
 
@@ -102,6 +102,11 @@ class Check(ctypes.Structure):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
+class AccdInfo(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_double), ("n_capped", ctypes.c_int64), ("n_touching", ctypes.c_int64),
+                ("max_steps", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -117,6 +122,7 @@ def lib():
         sig = {
             "gipc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
             "gipc_ctx_create": (st, [ctypes.POINTER(vp)]),
+            "gipc_ctx_create_with_allocator": (st, [ctypes.POINTER(Allocator), ctypes.POINTER(vp)]),
             "gipc_ctx_destroy": (None, [vp]),
             "gipc_ctx_last_error": (ctypes.c_char_p, [vp]),
             "gipc_pairs_build": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Pairs), ctypes.POINTER(Params), vp,
@@ -131,9 +137,13 @@ def lib():
                                         ctypes.POINTER(Bsr), vp]),
             "gipc_bsr_spmv": (st, [ctypes.POINTER(Bsr), vp, vp, vp]),
             "gipc_pcg": (st, [vp, ctypes.POINTER(Bsr), vp, vp, d, i32, ctypes.POINTER(i32), ctypes.POINTER(d), vp]),
+            "gipc_accd": (st, [vp, ctypes.POINTER(Mesh), vp, ctypes.POINTER(Pairs), d, d, i32, vp,
+                               ctypes.POINTER(AccdInfo), vp]),
             "gipc_pcg_static": (st, [ctypes.POINTER(Bsr), vp, vp, d, i32, ctypes.POINTER(i32), ctypes.POINTER(d),
                                      vp]),
             "gipc_mf_apply": (st, [vp, vp, vp, vp, vp]),
+            "gipc_dense_apply": (st, [vp, vp, i32, vp, vp, vp, vp]),
+            "gipc_pcg_dense": (st, [vp, vp, i32, vp, vp, vp, d, i32, ctypes.POINTER(i32), ctypes.POINTER(d), vp]),
             "gipc_pcg_mf": (st, [vp, vp, vp, vp, d, i32, ctypes.POINTER(i32), ctypes.POINTER(d), vp]),
             "gipc_proxy_dense": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), i32, vp, vp]),
             "gipc_friction_lag": (st, [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Params), ctypes.POINTER(Friction),
@@ -225,12 +235,44 @@ def _need(t, dtype, shape_last=None, name="tensor"):
         raise ValueError(f"{name} must have last dimension {shape_last}")
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", ctypes.c_void_p)]
+
+
+def _torch_allocator() -> Allocator:
+    """gipc_allocator callbacks over torch's caching allocator (blocks on the
+    device's default stream)."""
+    def alloc(user, nbytes, device):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device=int(device), stream=0)
+        except Exception:
+            return None
+
+    def free(user, ptr, nbytes, device):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    return Allocator(_ALLOC_FN(alloc), _FREE_FN(free), None)
+
+
 class Context:
     """Owns a gipc_ctx (device workspace, staged pairs, pattern, factors)."""
 
-    def __init__(self):
+    def __init__(self, allocator=None):
+        """allocator=None: the library's own hipMalloc; "torch": every buffer
+        of the context comes from torch's caching allocator."""
         h = ctypes.c_void_p()
-        s = lib().gipc_ctx_create(ctypes.byref(h))
+        self._alloc = None
+        if allocator is None:
+            s = lib().gipc_ctx_create(ctypes.byref(h))
+        elif allocator == "torch":
+            self._alloc = _torch_allocator()
+            s = lib().gipc_ctx_create_with_allocator(ctypes.byref(self._alloc), ctypes.byref(h))
+        else:
+            raise ValueError("allocator must be None or 'torch'")
         if s != OK:
             raise GipcError(s, f"gipc_ctx_create: {status_string(s)}")
         self.h = h
@@ -413,6 +455,29 @@ def pcg(ctx: Context, A: BsrMatrix, b, x=None, rtol=1e-6, maxit=1000, stream=Non
     return x, int(it.value), float(rr.value), int(s)
 
 
+def accd(ctx: Context, x, disp, tuples, s=0.1, tc=1.0, max_iter=1_000_000, toi=None, stream=None):
+    """Additive-CCD step bound of a tuple list moving by disp (synchronises).
+    Returns (toi [P] device tensor, info dict with step, n_capped,
+    n_touching, max_steps)."""
+    _need(x, torch.float64, 3, "x")
+    _need(disp, torch.float64, 3, "disp")
+    _need(tuples, torch.int32, 4, "tuples")
+    if disp.shape != x.shape:
+        raise ValueError("disp must have the shape of x")
+    P = int(tuples.shape[0])
+    if toi is not None:
+        _need(toi, torch.float64, None, "toi")
+        if toi.numel() != P:
+            raise ValueError("toi must hold one value per tuple")
+    toi = torch.empty(P, dtype=torch.float64, device=x.device) if toi is None else toi
+    mesh = Context._mesh(x, None)
+    pairs = Pairs(P, tuples.data_ptr() if P else None)
+    info = AccdInfo()
+    ctx._check(lib().gipc_accd(ctx.h, ctypes.byref(mesh), _ptr(disp), ctypes.byref(pairs), float(s), float(tc),
+                               int(max_iter), _ptr(toi), ctypes.byref(info), _stream(stream)), "gipc_accd")
+    return toi, {f: getattr(info, f) for f, _ in AccdInfo._fields_}
+
+
 def pcg_static(A: BsrMatrix, b, x=None, rtol=1e-6, maxit=1000, stream=None):
     """gipc_pcg on the library's fixed work area (no context, no device
     allocation by the library).  Returns (x, iterations, relres, status)."""
@@ -520,6 +585,51 @@ def pcg_mf(ctx: Context, b, x=None, diag=None, rtol=1e-6, maxit=1000, stream=Non
     s = lib().gipc_pcg_mf(ctx.h, _ptr(diag), _ptr(b), _ptr(x), float(rtol), int(maxit), ctypes.byref(it),
                           ctypes.byref(rr), _stream(stream))
     ctx._check(s, "gipc_pcg_mf")
+    return x, int(it.value), float(rr.value), int(s)
+
+
+DENSE_THREAD, DENSE_ENTRY = 0, 1
+
+
+def _need_dense(ctx: Context, hess):
+    _need(hess, torch.float64, 12, "hess")
+    n = int(ctx.info["n_staged"]) if ctx.info else 0
+    if hess.dim() != 3 or hess.shape[1] != 12 or hess.shape[0] < n:
+        raise ValueError("hess must be [n_staged][12][12] (gipc_proxy_dense)")
+
+
+def dense_apply(ctx: Context, hess, x, y=None, diag=None, scheme=DENSE_ENTRY, stream=None):
+    """y = (diag (x) I3 + sum_k S_k^T H_k S_k) x from dense local Hessians
+    (Table 2's two schemes; FP64 atomics, last bits vary)."""
+    _need_dense(ctx, hess)
+    _need(x, torch.float64, 3, "x")
+    _need_rows(ctx, x, "x")
+    if diag is not None:
+        _need(diag, torch.float64, None, "diag")
+        _need_rows(ctx, diag, "diag")
+    y = torch.empty_like(x) if y is None else y
+    _need(y, torch.float64, 3, "y")
+    _need_rows(ctx, y, "y")
+    ctx._check(lib().gipc_dense_apply(ctx.h, _ptr(hess), int(scheme), _ptr(diag), _ptr(x), _ptr(y),
+                                      _stream(stream)), "gipc_dense_apply")
+    return y
+
+
+def pcg_dense(ctx: Context, hess, b, x=None, diag=None, scheme=DENSE_ENTRY, rtol=1e-6, maxit=1000, stream=None):
+    """Block-Jacobi PCG on the dense-Hessian product (synchronises).
+    Returns (x, iterations, relres, status)."""
+    _need_dense(ctx, hess)
+    _need(b, torch.float64, 3, "b")
+    _need_rows(ctx, b, "b")
+    if diag is not None:
+        _need(diag, torch.float64, None, "diag")
+        _need_rows(ctx, diag, "diag")
+    x = torch.zeros_like(b) if x is None else x
+    it = ctypes.c_int32()
+    rr = ctypes.c_double()
+    s = lib().gipc_pcg_dense(ctx.h, _ptr(hess), int(scheme), _ptr(diag), _ptr(b), _ptr(x), float(rtol), int(maxit),
+                             ctypes.byref(it), ctypes.byref(rr), _stream(stream))
+    ctx._check(s, "gipc_pcg_dense")
     return x, int(it.value), float(rr.value), int(s)
 
 

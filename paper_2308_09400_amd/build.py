@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgipc.so")
 SOURCES = ["api.hip", "scan.hip", "stage.hip", "merge.hip", "order.hip", "symbolic.hip", "eval.hip", "assemble.hip", "solve.hip", "numeric.hip", "friction.hip", "candidates.hip",
-           "noalloc.hip"]
+           "noalloc.hip", "accd.hip", "dense.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

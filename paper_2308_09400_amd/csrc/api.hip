@@ -18,7 +18,15 @@ hipError_t ensure(DevBuf& b, size_t bytes) {
     if (bytes == 0) bytes = 16;
     if (bytes <= b.bytes) return hipSuccess;
     if (b.p) {
-        hipError_t e = hipFree(b.p);
+        hipError_t e = hipSuccess;
+        if (b.al) {
+            // work queued on any stream may still read the old block: the
+            // caller's allocator gets it back only once the device is idle
+            e = hipDeviceSynchronize();
+            if (e == hipSuccess) b.al->free(b.al->user, b.p, b.bytes, b.device);
+        } else {
+            e = hipFree(b.p);
+        }
         b.p = nullptr;
         b.bytes = 0;
         if (e != hipSuccess) return e;
@@ -26,10 +34,19 @@ hipError_t ensure(DevBuf& b, size_t bytes) {
     size_t cap = bytes + bytes / 4;
     cap = (cap + 255) & ~size_t(255);
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, cap);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return e;
+    if (b.al) {
+        p = b.al->alloc(b.al->user, cap, b.device);
+        if (!p) return hipErrorOutOfMemory;
+        if ((reinterpret_cast<uintptr_t>(p) & 255) != 0) {
+            b.al->free(b.al->user, p, cap, b.device);
+            return hipErrorInvalidValue;
+        }
+    } else {
+        hipError_t e = hipMalloc(&p, cap);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return e;
+        }
     }
     b.p = p;
     b.bytes = cap;
@@ -37,7 +54,10 @@ hipError_t ensure(DevBuf& b, size_t bytes) {
 }
 
 void release(DevBuf& b) {
-    if (b.p) (void)hipFree(b.p);
+    if (b.p) {
+        if (b.al) b.al->free(b.al->user, b.p, b.bytes, b.device);
+        else (void)hipFree(b.p);
+    }
     b.p = nullptr;
     b.bytes = 0;
 }
@@ -45,6 +65,8 @@ void release(DevBuf& b) {
 }  // namespace gipc
 
 namespace {
+
+std::vector<DevBuf*> ctx_buffers(gipc_ctx* ctx);
 
 // counters layout (int64 slots of ctx->counters)
 enum {
@@ -172,14 +194,22 @@ const char* gipc_status_string(int st) {
     }
 }
 
-gipc_status gipc_ctx_create(gipc_ctx** out) {
+gipc_status gipc_ctx_create_with_allocator(const gipc_allocator* al, gipc_ctx** out) {
     if (!out) return GIPC_ERR_INVALID_ARG;
     *out = nullptr;
+    if (al && (!al->alloc || !al->free)) return GIPC_ERR_INVALID_ARG;
     gipc_ctx* ctx = new (std::nothrow) gipc_ctx();
     if (!ctx) return GIPC_ERR_WORKSPACE;
     if (hipGetDevice(&ctx->device) != hipSuccess) {
         delete ctx;
         return GIPC_ERR_HIP;
+    }
+    if (al) {
+        ctx->alloc = *al;
+        for (DevBuf* b : ctx_buffers(ctx)) {
+            b->al = &ctx->alloc;
+            b->device = ctx->device;
+        }
     }
     if (ensure(ctx->counters, sizeof(int64_t) * C_NSLOTS) != hipSuccess) {
         delete ctx;
@@ -189,12 +219,25 @@ gipc_status gipc_ctx_create(gipc_ctx** out) {
     return GIPC_OK;
 }
 
+gipc_status gipc_ctx_create(gipc_ctx** out) { return gipc_ctx_create_with_allocator(nullptr, out); }
+
 void gipc_ctx_destroy(gipc_ctx* ctx) {
     if (!ctx) return;
     int prev = -1;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(ctx->device);
-    DevBuf* bufs[] = {&ctx->cand_ft, &ctx->cand_vid, &ctx->bcount, &ctx->boff, &ctx->counters, &ctx->st_vid,
+    if (ctx->alloc.alloc) (void)hipDeviceSynchronize();
+    for (DevBuf* b : ctx_buffers(ctx)) release(*b);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    delete ctx;
+}
+
+}  // extern "C"
+
+namespace {
+// every device buffer the context holds
+std::vector<DevBuf*> ctx_buffers(gipc_ctx* ctx) {
+    return {&ctx->cand_ft, &ctx->cand_vid, &ctx->bcount, &ctx->boff, &ctx->counters, &ctx->st_vid,
                       &ctx->st_src, &ctx->mult, &ctx->mkeys, &ctx->mrep_of, &ctx->mcount,
                       &ctx->mflag, &ctx->mpos, &ctx->st_vid2, &ctx->st_src2, &ctx->deg, &ctx->kcount, &ctx->fill, &ctx->inc_ptr, &ctx->kptr, &ctx->inc,
                       &ctx->contrib, &ctx->kcol, &ctx->kbeg, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
@@ -202,11 +245,11 @@ void gipc_ctx_destroy(gipc_ctx* ctx) {
                       &ctx->obox, &ctx->ocell, &ctx->ohist, &ctx->ooff, &ctx->ofill, &ctx->rec_main, &ctx->rec_extra, &ctx->rec_a1, &ctx->ev,
                       &ctx->epart, &ctx->mfg, &ctx->mfab, &ctx->flag, &ctx->ffr, &ctx->fev, &ctx->fpart, &ctx->cpart, &ctx->ccnt, &ctx->ccount, &ctx->cfill, &ctx->coff_t, &ctx->cent_t, &ctx->coff_e, &ctx->cent_e, &ctx->qcnt, &ctx->qoff_p, &ctx->qoff_e, &ctx->crec_t, &ctx->crec_e, &ctx->vscene, &ctx->pieces, &ctx->poff,
                       &ctx->r, &ctx->z, &ctx->p, &ctx->q, &ctx->p32, &ctx->minv, &ctx->part, &ctx->scal, &ctx->scan_tmp,
-                      &ctx->scan_tmp2, &ctx->chk};
-    for (DevBuf* b : bufs) release(*b);
-    if (prev >= 0) (void)hipSetDevice(prev);
-    delete ctx;
+                      &ctx->scan_tmp2, &ctx->chk, &ctx->accd_cnt};
 }
+}  // namespace
+
+extern "C" {
 
 const char* gipc_ctx_last_error(const gipc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
@@ -606,6 +649,39 @@ gipc_status gipc_bsr_spmv(const gipc_bsr* A, const void* x, void* y, void* strea
     return GIPC_OK;
 }
 
+gipc_status gipc_accd(gipc_ctx* ctx, const gipc_mesh* mesh, const double* disp, const gipc_pairs* pairs, double s,
+                      double tc, int32_t max_iter, double* toi, gipc_accd_info* info, void* stream) {
+    if (!ctx) return GIPC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    gipc_status st;
+    if ((st = check_device(ctx)) != GIPC_OK) return st;
+    if ((st = check_mesh(ctx, mesh)) != GIPC_OK) return st;
+    if (!pairs || pairs->P < 0 || (pairs->P > 0 && !pairs->tuples))
+        return fail(ctx, GIPC_ERR_INVALID_ARG, "bad pair list");
+    if (pairs->P > 0 && (!disp || mesh->V <= 0)) return fail(ctx, GIPC_ERR_INVALID_ARG, "displacement is NULL");
+    if (!(s > 0.0 && s < 1.0)) return fail(ctx, GIPC_ERR_INVALID_ARG, "s must lie in (0, 1)");
+    if (!(tc >= 0.0) || !std::isfinite(tc)) return fail(ctx, GIPC_ERR_INVALID_ARG, "tc must be >= 0 and finite");
+    if (max_iter < 1) return fail(ctx, GIPC_ERR_INVALID_ARG, "max_iter must be >= 1");
+    hipStream_t hs = S(stream);
+    CK(ensure(ctx->accd_cnt, sizeof(unsigned long long) * 6), "alloc ccd counters");
+    auto* cnt = as<unsigned long long>(ctx->accd_cnt);
+    CK(launch_accd(pairs->tuples, pairs->P, mesh->V, mesh->x, disp, s, tc, max_iter, toi, cnt, hs), "ccd");
+    unsigned long long h[6];
+    CK(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, hs), "copy");
+    CK(hipStreamSynchronize(hs), "stream synchronize");
+    if (h[0] > 0)
+        return fail(ctx, GIPC_ERR_INDEX, "%llu malformed tuples (first: %llu)", h[0], h[1]);
+    if (info) {
+        double step;
+        std::memcpy(&step, &h[4], sizeof(step));
+        info->step = step;
+        info->n_capped = (int64_t)h[2];
+        info->n_touching = (int64_t)h[3];
+        info->max_steps = (int32_t)h[5];
+    }
+    return GIPC_OK;
+}
+
 gipc_status gipc_pcg(gipc_ctx* ctx, const gipc_bsr* A, const double* b, double* x, double rtol, int32_t maxit,
                      int32_t* iters, double* relres, void* stream) {
     if (!ctx) return GIPC_ERR_INVALID_ARG;
@@ -659,9 +735,65 @@ gipc_status mf_view(gipc_ctx* ctx, const double* diag, MfView& m, hipStream_t st
     return GIPC_OK;
 }
 
+// the dense operator over hess [Ps][12][12] of the current build
+gipc_status dense_view(gipc_ctx* ctx, const double* hess, int32_t scheme, const double* diag, MfView& m) {
+    if (!ctx->built) return fail(ctx, GIPC_ERR_STATE, "no build");
+    if (scheme != GIPC_DENSE_THREAD && scheme != GIPC_DENSE_ENTRY)
+        return fail(ctx, GIPC_ERR_INVALID_ARG, "scheme must be GIPC_DENSE_THREAD or GIPC_DENSE_ENTRY");
+    if (!hess && ctx->ranges.off[8] > 0) return fail(ctx, GIPC_ERR_INVALID_ARG, "hess is NULL");
+    m.V = ctx->V;
+    m.tr = ctx->ranges;
+    m.st_vid = as<int4>(ctx->st_vid);
+    m.order = as<int32_t>(ctx->order);
+    m.diag_slot = as<int32_t>(ctx->diag_slot);
+    m.cptr = as<int64_t>(ctx->cptr);
+    m.contrib = as<uint32_t>(ctx->contrib);
+    m.diag = diag;
+    m.inc_ptr = as<int64_t>(ctx->inc_ptr);
+    m.dense = hess;
+    m.dense_scheme = scheme;
+    return GIPC_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+gipc_status gipc_dense_apply(gipc_ctx* ctx, const double* hess, int32_t scheme, const double* diag, const double* x,
+                             double* y, void* stream) {
+    if (!ctx) return GIPC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    gipc_status st;
+    if ((st = check_device(ctx)) != GIPC_OK) return st;
+    MfView m{};
+    if ((st = dense_view(ctx, hess, scheme, diag, m)) != GIPC_OK) return st;
+    if (m.V > 0 && (!x || !y)) return fail(ctx, GIPC_ERR_INVALID_ARG, "x or y is NULL");
+    if (x == y && m.V > 0) return fail(ctx, GIPC_ERR_INVALID_ARG, "x and y must not alias");
+    CK(launch_mf_apply(m, x, y, nullptr, nullptr, S(stream)), "dense operator");
+    return GIPC_OK;
+}
+
+gipc_status gipc_pcg_dense(gipc_ctx* ctx, const double* hess, int32_t scheme, const double* diag, const double* b,
+                           double* x, double rtol, int32_t maxit, int32_t* iters, double* relres, void* stream) {
+    if (!ctx) return GIPC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    gipc_status st;
+    if ((st = check_device(ctx)) != GIPC_OK) return st;
+    MfView m{};
+    if ((st = dense_view(ctx, hess, scheme, diag, m)) != GIPC_OK) return st;
+    if (m.V > 0 && (!b || !x)) return fail(ctx, GIPC_ERR_INVALID_ARG, "b or x is NULL");
+    if (!(rtol >= 0.0) || maxit < 0) return fail(ctx, GIPC_ERR_INVALID_ARG, "rtol must be >= 0 and maxit >= 0");
+    int32_t it = 0;
+    double rr = 0.0;
+    int brk = 0;
+    gipc_bsr none{};
+    if (m.V > 0) CK(pcg_run(ctx, none, b, x, rtol, maxit, &it, &rr, &brk, S(stream), &m), "pcg");
+    if (iters) *iters = it;
+    if (relres) *relres = rr;
+    if (brk) return fail(ctx, GIPC_ERR_BREAKDOWN, "p^T A p <= 0 at iteration %d", it);
+    if (rtol > 0.0 && rr > rtol) return GIPC_WARN_NOT_CONVERGED;
+    return GIPC_OK;
+}
 
 gipc_status gipc_mf_apply(gipc_ctx* ctx, const double* diag, const double* x, double* y, void* stream) {
     if (!ctx) return GIPC_ERR_INVALID_ARG;

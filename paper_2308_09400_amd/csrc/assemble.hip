@@ -573,6 +573,7 @@ int64_t mf_num_parts(int32_t V) { return ((int64_t)V * kMfLanes + kMfBlock - 1) 
 
 hipError_t launch_mf_apply(const MfView& m, const double* x, double* y, double* part, const PcgScalars* sc,
                            hipStream_t s) {
+    if (m.dense) return launch_dense_apply(m, x, y, part, sc, s);
     if (m.V == 0) return hipSuccess;
     if (m.tr.off[8] > 0) {
         k_mf_pair<<<(unsigned)((m.tr.off[8] + kBlock - 1) / kBlock), kBlock, 0, s>>>(m.st_vid, m.tr, m.rec_main,
@@ -595,6 +596,7 @@ hipError_t launch_mf_coef(const MfView& m, double* g, hipStream_t s) {
 }
 
 hipError_t launch_mf_diag_inverse(const MfView& m, double* minv, hipStream_t s) {
+    if (m.dense) return launch_dense_diag_inverse(m, minv, s);
     if (m.V == 0) return hipSuccess;
     const int64_t e0 = m.tr.off[FT_EE], m0 = m.tr.off[FT_EEM];
     const int64_t nb = ((int64_t)m.V * kMfLanes + kBlock - 1) / kBlock;

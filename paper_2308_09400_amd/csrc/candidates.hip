@@ -2,7 +2,7 @@
 // different objects, sharing no vertex, whose axis-aligned boxes come within
 // dhat (one box inflated by dhat, closed intervals) -- the pairs the sum of
 // Eq. 3 ranges over, before the distance decides which are active.  A
-// uniform grid stands in for the paper's LBVH (Sec. 6.2): along each axis
+// uniform grid stands in for the paper's LBVH (Sec. 7.2): along each axis
 // the cell size is the largest primitive extent along that axis plus dhat,
 // so every box spans at most two cells per axis, and thin stacks (sheets a
 // fraction of dhat apart) are split along their normal; a pair is reported

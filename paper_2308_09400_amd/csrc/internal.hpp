@@ -18,10 +18,13 @@ constexpr int kScanItems = 8;        // elements per thread in the scans
 constexpr int kMaxRowPairs = 2048;   // pairs touching one vertex (LDS sort capacity, 64 KiB)
 constexpr int kEnergyPiece = 8192;   // vertices per energy piece
 
-// Grow-only device buffer.
+// Grow-only device buffer, from hipMalloc or from the caller's allocator
+// (al non-null; device = the context's device).
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    const gipc_allocator* al = nullptr;
+    int device = 0;
 };
 
 hipError_t ensure(DevBuf& b, size_t bytes);
@@ -57,6 +60,45 @@ __device__ __forceinline__ int vslot(const int4& v, int j) {
     return j == 0 ? v.x : (j == 1 ? v.y : (j == 2 ? v.z : v.w));
 }
 
+// One tuple in the paper's sign encoding (Sec. 7.2, "Data structures"),
+// negative ids as -(i+1), decoded with ~i:
+//   [a0, a1, b0, b1]            edge-edge (a1 negative: close to parallel)
+//   [-p, t0, t1, t2]            point-triangle
+//   [-p, e0, e1, -1]            point-edge
+//   [-p, q, -1, -1]             point-point
+//   [-p, -o, e0, -e1]           point-edge cut from a close-to-parallel
+//                               edge-edge pair (p's edge is (p, o))
+//   [-p, -o, -q, -r]            point-point cut from one (q's edge is (q, r))
+// Returns the kind (0 EE, 1 PT, 2 PE, 3 PP, 4 PE cut from EE, 5 PP cut
+// from EE) with the vertex ids in v (nv of them), or -1 for a malformed
+// tuple: a pattern not above, an id outside [0, V) or a repeated id.
+__device__ __forceinline__ int decode_tuple(const int4 t, int32_t V, int v[4], int& nv) {
+    int kind = -1;
+    v[0] = v[1] = v[2] = v[3] = -1;
+    nv = 0;
+    if (t.x >= 0) {
+        if (t.z >= 0 && t.w >= 0) {
+            kind = 0; nv = 4;
+            v[0] = t.x; v[1] = t.y >= 0 ? t.y : ~t.y; v[2] = t.z; v[3] = t.w;
+        }
+    } else if (t.y >= 0) {
+        v[0] = ~t.x; v[1] = t.y;
+        if (t.z >= 0 && t.w >= 0) { kind = 1; nv = 4; v[2] = t.z; v[3] = t.w; }
+        else if (t.z >= 0 && t.w == -1) { kind = 2; nv = 3; v[2] = t.z; }
+        else if (t.z == -1 && t.w == -1) { kind = 3; nv = 2; }
+    } else if (t.w < 0) {
+        v[0] = ~t.x; v[1] = ~t.y; v[3] = ~t.w; nv = 4;
+        if (t.z >= 0) { kind = 4; v[2] = t.z; }
+        else { kind = 5; v[2] = ~t.z; }
+    }
+    bool ok = kind >= 0;
+    for (int k = 0; k < nv && ok; ++k) {
+        ok = v[k] >= 0 && v[k] < V;
+        for (int l = 0; l < k && ok; ++l) ok = v[l] != v[k];
+    }
+    return ok ? kind : -1;
+}
+
 // wave64 sum by a fixed butterfly, then the block's waves in order: the
 // result does not depend on scheduling.  NT = threads of the workgroup.
 template <int NT>
@@ -86,6 +128,7 @@ struct PcgScalars {  // device-resident scalars of the PCG loop
 struct gipc_ctx {
     int device = 0;
     std::string err;
+    gipc_allocator alloc{};  // the caller's allocator (alloc.alloc null: hipMalloc)
 
     // staging (per candidate)
     gipc::DevBuf cand_ft, cand_vid, bcount, boff, counters;
@@ -135,6 +178,7 @@ struct gipc_ctx {
     gipc::DevBuf r, z, p, q, p32, minv, part, scal;
     // scan scratch; counters of gipc_pairs_check
     gipc::DevBuf scan_tmp, scan_tmp2, chk;
+    gipc::DevBuf accd_cnt;
 
     gipc_info info{};
     bool built = false;
@@ -251,6 +295,10 @@ struct MfView {
     const double* diag;      // per-vertex diagonal term, nullable = 0
     const double* g;         // [incidences][3] c_i w~_k, row by row (per eval)
     double2* ab;             // [Ps] (alpha, beta) of the current product (scratch)
+    // dense local Hessians [Ps][12][12] (gipc_proxy_dense) instead of the
+    // factors when non-null, multiplied by dense_scheme (dense.hip)
+    const double* dense;
+    int dense_scheme;
 };
 // y = (diag (x) I3 + H) x; with part, one partial of x . y per workgroup
 // (mf_num_parts of them); kernels return at once when sc->done (nullable)
@@ -258,6 +306,10 @@ hipError_t launch_mf_apply(const MfView& m, const double* x, double* y, double* 
                            hipStream_t s);
 hipError_t launch_mf_diag_inverse(const MfView& m, double* minv, hipStream_t s);
 hipError_t launch_mf_coef(const MfView& m, double* g, hipStream_t s);
+// the same product and preconditioner from m.dense (dense.hip)
+hipError_t launch_dense_apply(const MfView& m, const double* x, double* y, double* part, const PcgScalars* sc,
+                              hipStream_t s);
+hipError_t launch_dense_diag_inverse(const MfView& m, double* minv, hipStream_t s);
 int64_t mf_num_parts(int32_t V);
 
 // dense projected proxy Hessians per staged pair, analytic or numeric
@@ -302,6 +354,11 @@ hipError_t launch_cand_query(int kind, bool emit, const double* x, int64_t nq, c
                              const void* qrec, const void* trec, const CandGrid& g, double dhat,
                              const int64_t* coff, const int32_t* cent, int32_t* cnt, const int64_t* qoff,
                              int32_t* out, hipStream_t s);
+
+// ---- accd.hip
+// additive CCD of P tuples moving by disp; counters [6] (see k_accd_reset)
+hipError_t launch_accd(const int32_t* tuples, int64_t P, int32_t V, const double* x, const double* disp, double s,
+                       double tc, int32_t max_iter, double* toi, unsigned long long* counters, hipStream_t st);
 
 // ---- solve.hip
 hipError_t launch_spmv(const gipc_bsr& A, const void* x, void* y, hipStream_t s);

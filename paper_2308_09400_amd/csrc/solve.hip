@@ -36,7 +36,7 @@
 // rows per lane group (315-340 us) were too.
 //
 // PCG (Saad Alg. 9.1 with the inverse 3x3 diagonal blocks as
-// preconditioner, the paper's simple block preconditioner of Sec. 6.2):
+// preconditioner, the paper's simple block preconditioner of Sec. 7.2):
 // every scalar (alpha, beta, residual norms, the stopping test) lives in
 // device memory, so an iteration is five kernel launches without host
 // round trips; the host polls the "done" flag every 16 iterations (once

@@ -1,7 +1,7 @@
 // Pair staging: classification of every tuple by the active constraints of
 // its constrained distance (Eq. 4 / Eq. 5), dropping of pairs at distance
 // >= dhat, and a stable counting sort of the active pairs by sub-type (the
-// per-type pair buffers of Sec. 6.2 / supplement Sec. 6).  Two passes over
+// per-type pair buffers of Sec. 7.2 / supplement Sec. 6).  Two passes over
 // the candidates (classify + per-workgroup type histogram, then scatter) with
 // an exclusive scan of the [type][workgroup] histogram in between; the order
 // within a type is the tuple order, so the result is deterministic.
@@ -21,16 +21,8 @@ __device__ __forceinline__ void flag_index(unsigned long long* cnt, unsigned lon
 
 enum TupleStatus { TS_OK = 0, TS_BAD = 1, TS_SPAN = 2, TS_DEGEN = 3 };
 
-// One tuple in the paper's sign encoding (Sec. 7.2, "Data structures"),
-// negative ids as -(i+1), decoded with ~i:
-//   [a0, a1, b0, b1]            edge-edge (a1 negative: close to parallel)
-//   [-p, t0, t1, t2]            point-triangle
-//   [-p, e0, e1, -1]            point-edge
-//   [-p, q, -1, -1]             point-point
-//   [-p, -o, e0, -e1]           point-edge cut from a close-to-parallel
-//                               edge-edge pair (p's edge is (p, o))
-//   [-p, -o, -q, -r]            point-point cut from one (q's edge is (q, r))
-// The vertex ids are checked, then the tuple is classified at X: ft is its
+// One tuple (decode_tuple): the vertex ids are checked, then the tuple is
+// classified at X: ft is its
 // sub-type if it is closer than its scene's dhat (else FT_NONE), vo its
 // staged stencil, dprim whether a primitive is degenerate (an edge of zero
 // length, a triangle of zero area) while the distance is still positive.
@@ -40,30 +32,9 @@ __device__ inline int classify_tuple(const int4 t, int32_t V, const double* __re
     ft = FT_NONE;
     vo = make_int4(-1, -1, -1, -1);
     dprim = false;
-    int kind = -1;  // 0 EE, 1 PT, 2 PE, 3 PP, 4 PE cut from EE, 5 PP cut from EE
-    int v[4] = {-1, -1, -1, -1};
-    int nv = 0;
-    if (t.x >= 0) {
-        if (t.z >= 0 && t.w >= 0) {
-            kind = 0; nv = 4;
-            v[0] = t.x; v[1] = t.y >= 0 ? t.y : ~t.y; v[2] = t.z; v[3] = t.w;
-        }
-    } else if (t.y >= 0) {
-        v[0] = ~t.x; v[1] = t.y;
-        if (t.z >= 0 && t.w >= 0) { kind = 1; nv = 4; v[2] = t.z; v[3] = t.w; }
-        else if (t.z >= 0 && t.w == -1) { kind = 2; nv = 3; v[2] = t.z; }
-        else if (t.z == -1 && t.w == -1) { kind = 3; nv = 2; }
-    } else if (t.w < 0) {
-        v[0] = ~t.x; v[1] = ~t.y; v[3] = ~t.w; nv = 4;
-        if (t.z >= 0) { kind = 4; v[2] = t.z; }
-        else { kind = 5; v[2] = ~t.z; }
-    }
-    bool ok = kind >= 0;
-    for (int k = 0; k < nv && ok; ++k) {
-        ok = v[k] >= 0 && v[k] < V;
-        for (int l = 0; l < k && ok; ++l) ok = v[l] != v[k];
-    }
-    if (!ok) return TS_BAD;
+    int v[4], nv;
+    const int kind = decode_tuple(t, V, v, nv);
+    if (kind < 0) return TS_BAD;
     if (pm.vscene) {
         const int s0 = pm.vscene[v[0]];
         for (int k = 1; k < nv; ++k)

@@ -5,7 +5,7 @@ triangulated cloth sheets, picks contact candidates with an AABB broad phase
 (``broadphase.c``) and returns plain numpy arrays.  It holds none of the
 barrier method's arithmetic: no distances, no barrier values, no
 classification.  Candidates use the paper's sign-encoded tuples
-(Sec. 6.2, "Data structures"): point-triangle ``[-(p+1), t0, t1, t2]`` and
+(Sec. 7.2, "Data structures"): point-triangle ``[-(p+1), t0, t1, t2]`` and
 edge-edge ``[a0, a1, b0, b1]``.
 """
 from __future__ import annotations

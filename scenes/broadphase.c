@@ -9,7 +9,7 @@
  * closer than dhat (and of which sub-type it is) is decided downstream by
  * the pair evaluation itself.
  *
- * Output tuples use the paper's sign encoding of contact pairs (Sec. 6.2,
+ * Output tuples use the paper's sign encoding of contact pairs (Sec. 7.2,
  * "Data structures"):
  *   point-triangle candidate  [-(p+1), t0, t1, t2]
  *   edge-edge candidate       [a0, a1, b0, b1]

@@ -57,11 +57,46 @@ def _blocks(H, vid):
     return out
 
 
-def _compare(dense, pairs, tuples, ref_h, rows=None):
+# staged sub-type (1..7) -> (oracle sub-type of the candidate, mollified)
+_BASE = {1: (1, False), 2: (2, False), 3: (3, False), 4: (4, False), 5: (4, True), 6: (2, True), 7: (3, True)}
+
+
+def _typed_tuple(t, v):
+    n = lambda i: -(int(i) + 1)  # noqa: E731
+    return {1: [n(v[0]), v[1], v[2], v[3]], 2: [n(v[0]), v[1], v[2], -1], 3: [n(v[0]), v[1], -1, -1],
+            4: [v[0], v[1], v[2], v[3]]}[t]
+
+
+def _ties(pairs, x, tuples, ref, po):
+    """Staged pairs whose candidate the oracle reduces to another sub-problem.
+    The exact Hessian is discontinuous across the boundary between two
+    sub-problems of Eq. 4 / Eq. 5 (d, grad d and the proxy Hessian are not),
+    so there both reductions are correct only if the two distances agree:
+    checked here, and such pairs are left out of the exact-route comparison."""
+    skip = set()
+    for k in range(len(pairs["src"])):
+        p = int(pairs["src"][k])
+        t, moll = _BASE[int(pairs["type"][k])]
+        if (int(ref["subtype"][p]), bool(ref["mollified"][p])) == (t, moll):
+            continue
+        v = [int(a) for a in pairs["vid"][k]]
+        nv = {1: 4, 2: 3, 3: 2, 4: 4}[t]
+        typed = np.array(_typed_tuple(t, v), np.int32)
+        d2_gpu = oracle.pair_local(typed, x[v[:nv]], None, po)["d2"]
+        nvo, ov = oracle.stencil(tuples[p])
+        d2_ref = oracle.pair_local(tuples[p], x[ov[:nvo]], None, po)["d2"]
+        assert abs(d2_gpu - d2_ref) <= 1e-12 * d2_ref, (k, p, d2_gpu, d2_ref)
+        skip.add(k)
+    return skip
+
+
+def _compare(dense, pairs, tuples, ref_h, rows=None, skip=()):
     """dense[k] (staged slot order) against mult x ref_h[src] (tuple slot order)"""
     src, vid, mult = pairs["src"], pairs["vid"], pairs["mult"]
     ks = range(len(src)) if rows is None else rows
     for k in ks:
+        if k in skip:
+            continue
         p = int(src[k])
         nv, ov = oracle.stencil(tuples[p])
         ovv = [int(ov[i]) if i < nv else -1 for i in range(4)]
@@ -89,7 +124,9 @@ def test_routes_against_the_oracle(gp, which):
     _compare(Hn, pairs, s.tuples, oracle.eval_xproj(s.x, s.tuples, po, x_rest=s.x_rest))
     Hx = gp.proxy_dense(ctx, X, pg, gp.PROJ_EXACT, x_rest=XR).cpu().numpy()
     _, Hxo = oracle.eval_exact(s.x, s.tuples, po, x_rest=s.x_rest, want_exact=False)
-    _compare(Hx, pairs, s.tuples, Hxo)
+    skip = _ties(pairs, s.x, s.tuples, ref, po)
+    assert len(skip) <= len(pairs["src"]) // 2
+    _compare(Hx, pairs, s.tuples, Hxo, skip=skip)
     nonm = pairs["type"] < 5
     assert nonm.any()
     sc = np.abs(Ha[nonm]).max(axis=(1, 2))[:, None, None]
@@ -140,7 +177,9 @@ def test_full_scale_sampled_pairs(gp):
     pairs["src"] = np.arange(len(pick))
     _compare(Ha, pairs, sub, ref["pairH"])
     _compare(Hn, pairs, sub, refx)
-    _compare(Hx, pairs, sub, refe)
+    skip = _ties(pairs, s.x, sub, ref, po)
+    assert len(skip) <= len(pick) // 2
+    _compare(Hx, pairs, sub, refe, skip=skip)
     assert (pairs["type"] >= 5).any() and (pairs["type"] < 5).any()
     ctx.close()
 
@@ -163,8 +202,9 @@ def test_exact_route_on_every_subtype(gp):
         elif kind == 2:    # crossing edges
             xs += [off + [0.5, -0.5, 0.06], off + [0.5, 0.5, 0.07], off + [0, 0, 0], off + [1, 0, 0]]
             tup.append([b, b + 1, b + 2, b + 3])
-        elif kind == 3:    # nearly parallel edges, interior
-            t = rng.uniform(1e-4, 1e-3)
+        elif kind == 3:    # nearly parallel edges, interior (c = t^2 below eps_x = 6.4e-4, and t^2 well above
+            # what the 1e-4 jitter of the heights can tilt, so the closest points stay interior)
+            t = rng.uniform(0.015, 0.024)
             xs += [off + [0.1, -0.5 * t, 0.05], off + [0.9, 0.5 * t, 0.05], off + [0, 0, 0], off + [1, 0, 0]]
             tup.append([b, -(b + 2), b + 2, b + 3])
         else:              # nearly parallel, endpoint against edge

@@ -9,7 +9,7 @@ closed forms.
   (Sec. 3) must equal 4 g b'' + 2 b' built from the oracle's derivatives;
   lambda_{2,3} matches 2 b' only with the denominator read as g (the printed
   g^2 is a typo, documented reading).
-* Sign facts the paper states (Sec. 4.3, supplement Sec. 3; Sec. 5.2).
+* Sign facts the paper states (Sec. 5.3, supplement Sec. 3; Sec. 5.2).
 """
 import os
 
