@@ -65,10 +65,11 @@ FP64_VECTOR_TFLOPS = 78.6    # MI355X FP64 vector peak
 # only while the SHA-256 of that source file still matches, else null.
 MEASURED_TRAFFIC = {
     "kernel": "k_spmv_ent<false>",
-    "bytes": 1.799e9,
-    "source": "profiles/sheets10_path.md (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-kernel calibration)",
+    "bytes": 1.800e9,
+    "source": "profiles/sheets10_path.md (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 per dispatch, "
+              "calibrated on the library's 2 GiB copy in the same run)",
     "file": "paper_2308_09400_amd/csrc/solve.hip",
-    "sha256": None,
+    "sha256": "bc3ba50b9bb686cace18e0be110b74cfe12ff1a255dee23e438675569d3c4de1",
 }
 
 
@@ -96,6 +97,8 @@ def parse():
     ap.add_argument("--no-targets", action="store_true", help="skip the batch64 / sheets40 target legs")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the matrix-free, numeric-eigen, friction and candidate legs")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="batch64: time only the batched step (no eager, per-scene or plain comparisons)")
     return ap.parse_args()
 
 
@@ -131,19 +134,31 @@ def make_scene(name, with_pairs=True):
 
 
 def cpu_baseline(s, n_sample, nthreads=0):
-    """The oracle as it stands (eval with per-pair Hessians + assembly) on a seeded sample."""
+    """The oracle as it stands (eval with per-pair Hessians + assembly) on a
+    seeded sample, each stage timed, then its SpMV and ten PCG iterations on
+    the sample's matrix."""
     import oracle
     import scenes
     sub = scenes.subsample(s, n_sample, seed=7)
     prm = oracle.params(dhat=s.dhat, kappa=s.kappa)
     t0 = time.perf_counter()
     r = oracle.eval_scene(s.x, sub, prm, x_rest=s.x_rest, nthreads=nthreads, per_pair=True)
-    oracle.assemble(s.V, sub, r["pairH"], s.diag)
-    dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    rows, cols, vals = oracle.assemble(s.V, sub, r["pairH"], s.diag)
+    t2 = time.perf_counter()
+    xv = np.random.default_rng(0).normal(size=3 * s.V)
+    oracle.spmv(s.V, rows, cols, vals, xv)
+    t3 = time.perf_counter()
+    oracle.pcg(s.V, rows, cols, vals, -r["grad"].reshape(-1), rtol=0.0, maxit=10)
+    t4 = time.perf_counter()
+    dt = t2 - t0
     cores = nthreads if nthreads > 0 else oracle.num_threads()
     return {"value": len(sub) / dt, "unit": "pairs/s", "cores": cores, "kind": "oracle",
             "sample": f"{len(sub)} candidates drawn (seed 7) from the same list; oracle eval with per-pair "
-                      f"Hessians ({cores} thread(s)) + assembly (serial sort); {dt:.1f} s"}
+                      f"Hessians ({cores} thread(s), {t1 - t0:.1f} s) + assembly (serial sort, {t2 - t1:.1f} s); "
+                      f"{dt:.1f} s",
+            "eval_pairs_per_s": len(sub) / (t1 - t0), "assembly_s": t2 - t1,
+            "sample_nnzb": int(len(rows)), "spmv_ms": (t3 - t2) * 1e3, "pcg_ms_per_iter": (t4 - t3) * 1e3 / 10}
 
 
 def precision_compare(gp, ctx, x, xr, prm, diag, last, stream):
@@ -463,7 +478,7 @@ def _batch_scene_gpu(gp, dev):
     return b, xs, torch.cat(tups)
 
 
-def batch_leg(gp, steps, warmup):
+def batch_leg(gp, steps, warmup, compare=True):
     """The batching target: batched build + eval/assembly replayed from a HIP
     graph (FP32 blocks) against the plain per-scene FP64 path."""
     import torch
@@ -519,6 +534,24 @@ def batch_leg(gp, steps, warmup):
     path_bytes = num_bytes + 16 * P
     path_gbs = path_bytes / (path_ms * 1e-3) / 1e9
 
+    common = {
+        "workload": "64 two-sheet scenes, 32..256 vertices per side, dhat log-uniform in [1e-4, 1e-2], "
+                    "kappa=1e4, seeds 1000+s, AABB candidates within each scene's dhat (found on the GPU)",
+        "scenes": b.S, "vertices": V, "candidates": P, "active_pairs": n_active,
+        "staged_pairs": int(info["n_staged"]), "active_by_type": info["n_by_type"], "nnzb": int(nnzb),
+        "tune": tune,
+        "active_pairs_per_s": n_active / (path_ms * 1e-3),
+        "ms_per_step": path_ms,
+        "graph_step_gbs": num_gbs, "graph_step_hbm_frac": num_gbs / HBM_PEAK_GBS,
+        "graph_step_bytes": int(num_bytes),
+        "path_gbs": path_gbs, "path_hbm_frac": path_gbs / HBM_PEAK_GBS,
+    }
+    if not compare:
+        graph.close()
+        ctx.close()
+        common["breakdown_ms"] = {"stage_build": build, "eval_assemble_graph_f32": replay}
+        return common
+
     # the same pairs, FP64 blocks, eager eval_assemble (no graph) and the
     # unfused barrier_eval + assemble_bsr
     A64 = gp.BsrMatrix(ctx, dtype=gp.F64)
@@ -569,13 +602,7 @@ def batch_leg(gp, steps, warmup):
     per_scene = float(np.median(per_ms))
     plain = float(np.median(plain_ms))
     return {
-        "workload": "64 two-sheet scenes, 32..256 vertices per side, dhat log-uniform in [1e-4, 1e-2], "
-                    "kappa=1e4, seeds 1000+s, AABB candidates within each scene's dhat (found on the GPU)",
-        "scenes": b.S, "vertices": V, "candidates": P, "active_pairs": n_active,
-        "staged_pairs": int(info["n_staged"]), "active_by_type": info["n_by_type"], "nnzb": int(nnzb),
-        "tune": tune,
-        "active_pairs_per_s": n_active / (path_ms * 1e-3),
-        "ms_per_step": path_ms,
+        **common,
         "breakdown_ms": {"stage_build": build, "eval_assemble_graph_f32": replay,
                          "eval_assemble_eager_f64": fused64, "eval_then_assemble_f64": unfused64,
                          "per_scene_contexts_build_eval_assemble_f64": per_scene,
@@ -583,9 +610,6 @@ def batch_leg(gp, steps, warmup):
         "speedup_vs_per_scene_contexts": per_scene / path_ms,
         "speedup_vs_plain": plain / path_ms,
         "target_speedup_vs_plain": 3.0,
-        "graph_step_gbs": num_gbs, "graph_step_hbm_frac": num_gbs / HBM_PEAK_GBS,
-        "graph_step_bytes": int(num_bytes),
-        "path_gbs": path_gbs, "path_hbm_frac": path_gbs / HBM_PEAK_GBS,
         "target_hbm_frac": 0.60,
     }
 
@@ -772,7 +796,7 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     if args.workload == "batch64":
-        leg = batch_leg(gp, args.steps, args.warmup)
+        leg = batch_leg(gp, args.steps, args.warmup, compare=not args.no_compare)
         line = {"metric": "contact pairs/s (energy+grad+proxy Hessian+BSR assembly), batched scenes",
                 "value": leg["active_pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
                 "warmup": args.warmup, "ms_per_step": leg["ms_per_step"], "higher_is_better": True,

@@ -455,10 +455,10 @@ def pcg(ctx: Context, A: BsrMatrix, b, x=None, rtol=1e-6, maxit=1000, stream=Non
     return x, int(it.value), float(rr.value), int(s)
 
 
-def accd(ctx: Context, x, disp, tuples, s=0.1, tc=1.0, max_iter=1_000_000, toi=None, stream=None):
+def accd(ctx: Context, x, disp, tuples, s=0.1, tc=1.0, max_iter=1_000_000, toi=None, per_tuple=True, stream=None):
     """Additive-CCD step bound of a tuple list moving by disp (synchronises).
-    Returns (toi [P] device tensor, info dict with step, n_capped,
-    n_touching, max_steps)."""
+    Returns (toi [P] device tensor, or None with per_tuple=False; info dict
+    with step, n_capped, n_touching, max_steps)."""
     _need(x, torch.float64, 3, "x")
     _need(disp, torch.float64, 3, "disp")
     _need(tuples, torch.int32, 4, "tuples")
@@ -469,7 +469,10 @@ def accd(ctx: Context, x, disp, tuples, s=0.1, tc=1.0, max_iter=1_000_000, toi=N
         _need(toi, torch.float64, None, "toi")
         if toi.numel() != P:
             raise ValueError("toi must hold one value per tuple")
-    toi = torch.empty(P, dtype=torch.float64, device=x.device) if toi is None else toi
+    if per_tuple and toi is None:
+        toi = torch.empty(P, dtype=torch.float64, device=x.device)
+    if not per_tuple:
+        toi = None
     mesh = Context._mesh(x, None)
     pairs = Pairs(P, tuples.data_ptr() if P else None)
     info = AccdInfo()

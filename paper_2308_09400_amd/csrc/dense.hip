@@ -56,7 +56,9 @@ __global__ void __launch_bounds__(kBlock) k_dense_thread(int64_t k0, int64_t k1,
 }
 
 // one lane per entry of the pairs of [k0, k1): entry e = (pair, row, col)
-// in row-major order of the local matrices
+// in row-major order of the local matrices.  The wavefront's first entry is
+// split into (pair, offset) once, on the scalar unit; each lane then needs
+// only 32-bit divisions by the constants D*D and D.
 template <int N>
 __global__ void __launch_bounds__(kBlock) k_dense_entry(int64_t k0, int64_t k1, const int4* __restrict__ st_vid,
                                                         const double* __restrict__ hess,
@@ -64,35 +66,38 @@ __global__ void __launch_bounds__(kBlock) k_dense_entry(int64_t k0, int64_t k1, 
                                                         const PcgScalars* __restrict__ sc) {
     if (sc && sc->done) return;
     constexpr int D = 3 * N;
-    const int64_t ne = (k1 - k0) * (int64_t)(D * D);
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    constexpr uint32_t D2 = D * D;
+    const int64_t ne = (k1 - k0) * (int64_t)D2;
     const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)));
+    const int64_t wave0 = (int64_t)wv * 64;
+    const int64_t kw = wave0 / D2;                                // pair of the wavefront's first entry
+    const uint32_t off = (uint32_t)(wave0 - kw * D2) + (uint32_t)lane;  // < D2 + 64
+    const uint32_t q = off / D2, rem = off - q * D2;
+    const uint32_t r = rem / D, c = rem - r * D;
+    const int64_t e = wave0 + lane;
     const bool in = e < ne;
-    const int64_t kk = in ? e / (D * D) : 0;
-    const int rem = in ? (int)(e - kk * (D * D)) : 0;
-    const int r = rem / D, c = rem % D;
-    const int64_t k = k0 + kk;
+    const int64_t k = k0 + kw + q;
     double v = 0.0;
     int4 v4 = make_int4(0, 0, 0, 0);
     if (in) {
         v4 = st_vid[k];
-        const int vc = vslot(v4, c / 3);
+        const int vc = vslot(v4, (int)(c / 3));
         v = hess[144 * k + 12 * r + c] * x[3ll * vc + c % 3];
     }
-    // the segment of this lane: the local row (kk, r) of the pair range,
-    // clipped to the wavefront; seg_end = last lane of the segment here
-    const int64_t row = in ? e / D : -1;
-    const int64_t wave0 = e - lane;
-    const int64_t row_end_e = (row + 1) * D - 1;                    // last entry of the row
-    const int seg_end = in ? (int)min<int64_t>(63, row_end_e - wave0) : lane;
-    const int seg_beg = in ? (int)max<int64_t>(0, row * D - wave0) : lane;
-    // inclusive suffix sums inside the segment (Hillis-Steele on shfl_down)
+    // the segment of this lane: its local row, clipped to the wavefront;
+    // seg_beg / seg_end = first / last lane of the segment here
+    const int seg_beg = max(0, lane - (int)c);
+    const int seg_end = min(63, lane + (D - 1 - (int)c));
+    // inclusive suffix sums inside the segment (Hillis-Steele on shfl_down);
+    // a segment spans at most D <= 12 lanes, so distances 1, 2, 4, 8 reach
+    // its end
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
+    for (int o = 1; o < D; o <<= 1) {
         const double t = __shfl_down(v, o, 64);
         if (lane + o <= seg_end) v += t;
     }
-    if (in && lane == seg_beg) atomicAdd(&y[3ll * vslot(v4, r / 3) + r % 3], v);
+    if (in && lane == seg_beg) atomicAdd(&y[3ll * vslot(v4, (int)(r / 3)) + r % 3], v);
 }
 
 // partial sums of x . y over kDenseDotRows rows per workgroup (the partial

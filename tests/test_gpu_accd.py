@@ -13,6 +13,7 @@
 * the ten-sheet candidate list (51M tuples) moved toward contact: sampled
   tuples against the oracle, the step against the smallest sampled time
   and the whole-list minimum;
+* without the per-tuple output the same step;
 * malformed tuples and bad arguments are errors.
 """
 import numpy as np
@@ -124,6 +125,9 @@ def test_dense_scene_against_oracle(gp, ctx, seed):
     assert info["step"] == pytest.approx(ref.min(), rel=REL)
     assert info["n_capped"] == capped == 0
     assert info["n_touching"] == 0
+    # without the per-tuple output: the same step
+    none, info2 = gp.accd(ctx, _dev(s.x), _dev(d), _dev(t, torch.int32), s=S, tc=1.0, per_tuple=False)
+    assert none is None and info2["step"] == info["step"]
 
 
 def test_encoded_tuples_against_oracle(gp, ctx):
@@ -225,3 +229,5 @@ def test_ten_sheets_sampled(gp, ctx):
     assert info["step"] == g.min()
     assert info["step"] <= ref.min()
     assert info["n_capped"] == 0 and capped == 0
+    _, info2 = gp.accd(ctx, x, _dev(disp), tup, s=S, tc=1.0, per_tuple=False)
+    assert info2["step"] == info["step"] and info2["max_steps"] == info["max_steps"]
