@@ -315,8 +315,12 @@ gipc_status gipc_pcg(gipc_ctx* ctx, const gipc_bsr* A, const double* b, double* 
  * call on a GPU uses that GPU's one area, which keeps the last call's
  * contents (each call initialises what it reads): calls that overlap on one
  * GPU -- from two host threads, or on two streams without ordering -- race
- * and give wrong results.  Synchronises `stream`.  Returns as gipc_pcg
- * (BREAKDOWN, WARN_NOT_CONVERGED, INVALID_ARG, WORKSPACE, HIP).
+ * and give wrong results.  Synchronises `stream`, except with rtol = 0 and
+ * both iters and relres NULL: the call then only enqueues its kernels (no
+ * read-back, no synchronisation, no memset, so it can be recorded in a HIP
+ * graph) and cannot report a breakdown (the kernels stop iterating at one).
+ * Returns as gipc_pcg (BREAKDOWN, WARN_NOT_CONVERGED, INVALID_ARG, WORKSPACE,
+ * HIP).
  */
 #define GIPC_PCG_STATIC_SCRATCH_BYTES (64u << 20)
 gipc_status gipc_pcg_static(const gipc_bsr* A, const double* b, double* x, double rtol, int32_t maxit,

@@ -481,17 +481,22 @@ def accd(ctx: Context, x, disp, tuples, s=0.1, tc=1.0, max_iter=1_000_000, toi=N
     return toi, {f: getattr(info, f) for f, _ in AccdInfo._fields_}
 
 
-def pcg_static(A: BsrMatrix, b, x=None, rtol=1e-6, maxit=1000, stream=None):
+def pcg_static(A: BsrMatrix, b, x=None, rtol=1e-6, maxit=1000, stream=None, counts=True):
     """gipc_pcg on the library's fixed work area (no context, no device
-    allocation by the library).  Returns (x, iterations, relres, status)."""
+    allocation by the library).  Returns (x, iterations, relres, status);
+    with rtol=0 and counts=False it only enqueues (capturable in a HIP
+    graph) and returns (x, None, None, status)."""
     _need(b, torch.float64, 3, "b")
     x = torch.zeros_like(b) if x is None else x
     it = ctypes.c_int32()
     rr = ctypes.c_double()
-    s = lib().gipc_pcg_static(ctypes.byref(A.desc), _ptr(b), _ptr(x), float(rtol), int(maxit), ctypes.byref(it),
-                              ctypes.byref(rr), _stream(stream))
+    pit, prr = (ctypes.byref(it), ctypes.byref(rr)) if counts else (None, None)
+    s = lib().gipc_pcg_static(ctypes.byref(A.desc), _ptr(b), _ptr(x), float(rtol), int(maxit), pit, prr,
+                              _stream(stream))
     if s < 0:
         raise GipcError(s, f"gipc_pcg_static: {status_string(s)}")
+    if not counts:
+        return x, None, None, int(s)
     return x, int(it.value), float(rr.value), int(s)
 
 

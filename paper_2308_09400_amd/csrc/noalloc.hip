@@ -47,12 +47,15 @@ extern "C" gipc_status gipc_pcg_static(const gipc_bsr* A, const double* b, doubl
     int32_t it = 0;
     double rr = 0.0;
     int brk = 0;
+    // rtol = 0 with no counts asked for: enqueue only (nothing read back)
+    const bool enqueue_only = rtol == 0.0 && !iters && !relres;
     if (A->nbrows > 0) {
         int dev = -1;
         if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return GIPC_ERR_HIP;
         void* ws = nullptr;
         if (scratch_ptr(dev, &ws) != hipSuccess) return GIPC_ERR_HIP;
-        if (pcg_run_in(ws, *A, b, x, rtol, maxit, &it, &rr, &brk, static_cast<hipStream_t>(stream)) != hipSuccess) {
+        if (pcg_run_in(ws, *A, b, x, rtol, maxit, enqueue_only ? nullptr : &it, enqueue_only ? nullptr : &rr,
+                       enqueue_only ? nullptr : &brk, static_cast<hipStream_t>(stream)) != hipSuccess) {
             (void)hipGetLastError();
             return GIPC_ERR_HIP;
         }

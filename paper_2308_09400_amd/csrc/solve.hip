@@ -643,6 +643,10 @@ static hipError_t pcg_exec(const gipc_bsr& A, const double* b, double* x, double
     GIPC_TRY(hipGetLastError());
 
     PcgScalars hs{};
+    // nothing read back (no synchronisation, so the launches can be
+    // captured) when the stopping test needs no host poll and the caller
+    // asked for no counts
+    const bool host = rtol > 0.0 || iters || relres || breakdown;
     const int32_t chunk = rtol > 0.0 ? 16 : (maxit > 0 ? maxit : 1);
     int32_t launched = 0;
     while (launched < maxit) {
@@ -667,11 +671,12 @@ static hipError_t pcg_exec(const gipc_bsr& A, const double* b, double* x, double
         }
         GIPC_TRY(hipGetLastError());
         launched += m;
+        if (!host) break;  // rtol = 0: one chunk of maxit iterations
         GIPC_TRY(hipMemcpyAsync(&hs, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
         GIPC_TRY(hipStreamSynchronize(s));
         if (hs.done) break;
     }
-    if (maxit <= 0) {
+    if (maxit <= 0 && host) {
         GIPC_TRY(hipMemcpyAsync(&hs, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
         GIPC_TRY(hipStreamSynchronize(s));
     }

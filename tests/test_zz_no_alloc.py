@@ -6,7 +6,10 @@ rounding (checked to 1e-12 of the largest entry, iterations and residuals
 equal).  Two calls in a row, the second on a smaller system, show that the
 area keeps no state that the next call reads; FP32 blocks and a converging
 solve (rtol > 0) run as well; a system beyond the area's capacity returns
-WORKSPACE before anything is launched.
+WORKSPACE before anything is launched.  With rtol = 0 and no counts the
+call only enqueues: recorded in a HIP graph and replayed three times, with
+eager work and synchronisations in between, every replay gives gipc_pcg's
+solution.
 """
 import ctypes
 
@@ -80,4 +83,31 @@ def test_capacity_rejected_before_launch(gp):
     assert it.value == -1
     # the area still works afterwards
     _compare(gp, ctx, A, b, 0.0, 10)
+    ctx.close()
+
+
+def test_recorded_in_a_graph(gp):
+    ctx, A, b = _system(gp, 16, 1, 0)
+    x_ref, it_ref, _, _ = gp.pcg(ctx, A, b, rtol=0.0, maxit=20)
+    xbuf = torch.zeros_like(b)
+    gp.pcg_static(A, b, x=xbuf, rtol=0.0, maxit=20, counts=False)  # eager once (device set-up)
+    torch.cuda.synchronize()
+    assert torch.equal(xbuf, x_ref)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            xbuf.zero_()
+            gp.pcg_static(A, b, x=xbuf, rtol=0.0, maxit=20, counts=False)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        xbuf.fill_(float(rep + 1))  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        err = float((xbuf - x_ref).abs().max() / x_ref.abs().max())
+        print(f"graph replay {rep}: max rel diff {err:.2e}", flush=True)
+        assert err <= 1e-12
+    del g
     ctx.close()
