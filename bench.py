@@ -65,11 +65,11 @@ FP64_VECTOR_TFLOPS = 78.6    # MI355X FP64 vector peak
 # only while the SHA-256 of that source file still matches, else null.
 MEASURED_TRAFFIC = {
     "kernel": "k_spmv_ent<false>",
-    "bytes": 1.800e9,
+    "bytes": 1.801e9,
     "source": "profiles/sheets10_path.md (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 per dispatch, "
               "calibrated on the library's 2 GiB copy in the same run)",
     "file": "paper_2308_09400_amd/csrc/solve.hip",
-    "sha256": "bc3ba50b9bb686cace18e0be110b74cfe12ff1a255dee23e438675569d3c4de1",
+    "sha256": "13f74f6e3edbbf8c22fc5bd525be4845a9f756b01a8a975aa8d7e672dc13c40a",
 }
 
 
