@@ -239,9 +239,9 @@ namespace {
 std::vector<DevBuf*> ctx_buffers(gipc_ctx* ctx) {
     return {&ctx->cand_ft, &ctx->cand_vid, &ctx->bcount, &ctx->boff, &ctx->counters, &ctx->st_vid,
                       &ctx->st_src, &ctx->mult, &ctx->mkeys, &ctx->mrep_of, &ctx->mcount,
-                      &ctx->mflag, &ctx->mpos, &ctx->st_vid2, &ctx->st_src2, &ctx->deg, &ctx->kcount, &ctx->fill, &ctx->inc_ptr, &ctx->kptr, &ctx->inc,
+                      &ctx->mflag, &ctx->mpos, &ctx->st_vid2, &ctx->st_src2, &ctx->deg, &ctx->kcount, &ctx->fill, &ctx->inc_ptr, &ctx->kptr,
                       &ctx->contrib, &ctx->kcol, &ctx->kbeg, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
-                      &ctx->slot_row, &ctx->diag_slot, &ctx->whead, &ctx->wrow, &ctx->maxbuf, &ctx->bigrows, &ctx->tslot, &ctx->incv, &ctx->order,
+                      &ctx->slot_row, &ctx->diag_slot, &ctx->whead, &ctx->wrow, &ctx->maxbuf, &ctx->bigrows, &ctx->tslot, &ctx->incr, &ctx->order,
                       &ctx->obox, &ctx->ocell, &ctx->ohist, &ctx->ooff, &ctx->ofill, &ctx->rec_main, &ctx->rec_extra, &ctx->rec_a1, &ctx->ev,
                       &ctx->epart, &ctx->mfg, &ctx->mfab, &ctx->flag, &ctx->ffr, &ctx->fev, &ctx->fpart, &ctx->cpart, &ctx->ccnt, &ctx->ccount, &ctx->cfill, &ctx->coff_t, &ctx->cent_t, &ctx->coff_e, &ctx->cent_e, &ctx->qcnt, &ctx->qoff_p, &ctx->qoff_e, &ctx->crec_t, &ctx->crec_e, &ctx->vscene, &ctx->pieces, &ctx->poff,
                       &ctx->r, &ctx->z, &ctx->p, &ctx->q, &ctx->p32, &ctx->minv, &ctx->part, &ctx->scal, &ctx->scan_tmp,
@@ -400,16 +400,15 @@ gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
         return fail(ctx, GIPC_ERR_WORKSPACE, "a vertex is touched by %d active pairs (limit %d)", max_deg,
                     kMaxRowPairs);
     const int64_t ninc = hc[C_INC], K = hc[C_K];
-    CK(ensure(ctx->inc, sizeof(uint32_t) * (size_t)ninc), "alloc incidences");
-    CK(ensure(ctx->incv, sizeof(int4) * (size_t)(ninc > 0 ? ninc : 1)), "alloc incidences");
+    CK(ensure(ctx->incr, sizeof(int4) * (size_t)(ninc > 0 ? ninc : 1)), "alloc incidences");
     CK(ensure(ctx->contrib, sizeof(uint32_t) * (size_t)K), "alloc contributions");
     CK(ensure(ctx->kcol, sizeof(int32_t) * (size_t)K), "alloc contributions");
     CK(ensure(ctx->kbeg, sizeof(int32_t) * (size_t)K), "alloc contributions");
     CK(launch_sym_scatter(as<int4>(ctx->st_vid), tr, as<int64_t>(ctx->inc_ptr), as<int32_t>(ctx->fill),
-                          as<uint32_t>(ctx->inc), as<int4>(ctx->incv), s),
+                          as<int4>(ctx->incr), s),
        "incidence scatter");
     CK(ensure(ctx->bigrows, sizeof(int32_t) * Vs), "alloc pattern");
-    CK(launch_sym_rowsort(V, max_deg, as<int64_t>(ctx->inc_ptr), as<uint32_t>(ctx->inc), as<int4>(ctx->incv), tr,
+    CK(launch_sym_rowsort(V, max_deg, as<int64_t>(ctx->inc_ptr), as<int4>(ctx->incr), tr,
                           as<int64_t>(ctx->kptr), as<uint32_t>(ctx->contrib), as<int32_t>(ctx->kcol),
                           as<int32_t>(ctx->kbeg), as<int32_t>(ctx->ncols), as<int32_t>(ctx->bigrows), cnt + C_NBIG,
                           s),

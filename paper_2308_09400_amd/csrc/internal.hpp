@@ -142,8 +142,8 @@ struct gipc_ctx {
     int64_t Ps = 0;
     int32_t V = 0;
     // symbolic
-    gipc::DevBuf deg, kcount, fill, inc_ptr, kptr, inc, contrib, kcol, kbeg, ncols, row_ptr, col_idx, cptr, slot_row,
-        diag_slot, maxbuf, bigrows, tslot, incv;
+    gipc::DevBuf deg, kcount, fill, inc_ptr, kptr, contrib, kcol, kbeg, ncols, row_ptr, col_idx, cptr, slot_row,
+        diag_slot, maxbuf, bigrows, tslot, incr;
     // per 64 blocks of the pattern: head bits of row starts, row of the first block
     gipc::DevBuf whead, wrow;
     // visiting order of the block rows in the assembly (spatial cells)
@@ -227,16 +227,17 @@ hipError_t build_row_order(gipc_ctx* ctx, const double* x, int32_t V, const int3
 
 // ---- symbolic.hip
 hipError_t launch_sym_count(const int4* st_vid, TypeRanges tr, int32_t* deg, int32_t* kcount, hipStream_t s);
-// inc: incidence codes k << 2 | i; incv: the incidence's pair stencil
+// incr: one record per incidence: k << 2 | i, then the vertices of the pair's other
+// slots in slot order (-1 past the stencil)
 hipError_t launch_sym_scatter(const int4* st_vid, TypeRanges tr, const int64_t* inc_ptr, int32_t* fill,
-                              uint32_t* inc, int4* incv, hipStream_t s);
+                              int4* incr, hipStream_t s);
 // big: int32 [V] scratch for the rows sorted by whole workgroups, nbig: a
 // device counter that must be zero on entry
 // contrib: each row's sorted contribution codes; kcol / kbeg: the row's
 // distinct columns and the offset of each one's first contribution, written
 // compactly from the row's contribution offset; ncols: their count
-hipError_t launch_sym_rowsort(int32_t V, int32_t max_deg, const int64_t* inc_ptr, const uint32_t* inc,
-                              const int4* incv, TypeRanges tr, const int64_t* kptr, uint32_t* contrib,
+hipError_t launch_sym_rowsort(int32_t V, int32_t max_deg, const int64_t* inc_ptr, const int4* incr,
+                              TypeRanges tr, const int64_t* kptr, uint32_t* contrib,
                               int32_t* kcol, int32_t* kbeg, int32_t* ncols, int32_t* big, int64_t* nbig,
                               hipStream_t s);
 hipError_t launch_sym_fill(int32_t V, const int64_t* kptr, const int32_t* kcol, const int32_t* kbeg,

@@ -4,7 +4,9 @@
 //
 //  1. incidence counts per vertex (integer atomics: counts are exact);
 //  2. exclusive scans -> per-vertex incidence and contribution offsets;
-//  3. incidence scatter (order inside a vertex is irrelevant: step 4 sorts);
+//  3. incidence scatter (order inside a vertex is irrelevant: step 4 sorts):
+//     one 16-byte record per incidence, (k << 2 | i, the vertices of the
+//     pair's other slots in slot order, -1 past the stencil);
 //  4. per block row, the keys (column, k, i, j) of all local blocks landing
 //     in that row are sorted: one wavefront per row with the keys in
 //     registers (bitonic network over cross-lane shuffles) for rows of up to
@@ -67,12 +69,11 @@ __global__ void __launch_bounds__(kBlock) k_sym_count(const int4* __restrict__ s
     }
 }
 
-// every incidence also carries its pair's stencil (incv), so the row sort
-// streams contiguous records instead of gathering the staged list
+// every incidence carries the rest of its pair's stencil, so the row sort
+// streams one record per incidence instead of gathering the staged list
 __global__ void __launch_bounds__(kBlock) k_sym_scatter(const int4* __restrict__ st_vid, TypeRanges tr,
                                                         const int64_t* __restrict__ inc_ptr,
-                                                        int32_t* __restrict__ fill, uint32_t* __restrict__ inc,
-                                                        int4* __restrict__ incv) {
+                                                        int32_t* __restrict__ fill, int4* __restrict__ incr) {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool in = k < tr.off[8];
     const int nv = in ? ft_nverts(type_of(k, tr)) : 0;
@@ -89,11 +90,21 @@ __global__ void __launch_bounds__(kBlock) k_sym_scatter(const int4* __restrict__
         if (valid) {
             const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
             const int64_t at = inc_ptr[vi] + base + __popcll(g.members & below);
-            inc[at] = ((uint32_t)k << 2) | (uint32_t)i;
-            incv[at] = v;
+            int o[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const int j = m < i ? m : m + 1;
+                o[m] = j < nv ? vslot(v, j) : -1;
+            }
+            incr[at] = make_int4((int)(((uint32_t)k << 2) | (uint32_t)i), o[0], o[1], o[2]);
         }
     }
 }
+
+// slot j != i of an incidence record: its m-th other slot
+__device__ __forceinline__ int other_slot(int j, int i) { return j < i ? j : j - 1; }
+
+__device__ __forceinline__ int rec_other(const int4& rec, int m) { return m == 0 ? rec.y : (m == 1 ? rec.z : rec.w); }
 
 constexpr int kWaveM = 8;                    // keys per lane in the wavefront sort
 constexpr int kWaveN = 64 * kWaveM;          // 512 keys per row
@@ -101,8 +112,8 @@ constexpr int kWaveIncidences = kWaveN / 4;  // 128 incidences of 4 key slots
 
 // sort of one row's keys in LDS by a whole workgroup (rows with more than
 // kWaveIncidences incidences)
-__device__ void rowsort_lds(int r, const int64_t* __restrict__ inc_ptr, const uint32_t* __restrict__ inc,
-                            const int4* __restrict__ incv, const TypeRanges& tr, const int64_t* __restrict__ kptr,
+__device__ void rowsort_lds(int r, const int64_t* __restrict__ inc_ptr, const int4* __restrict__ incr,
+                            const TypeRanges& tr, const int64_t* __restrict__ kptr,
                             uint32_t* __restrict__ contrib, int32_t* __restrict__ kcol, int32_t* __restrict__ kbeg,
                             int32_t* __restrict__ ncols) {
     extern __shared__ unsigned long long keys[];
@@ -116,12 +127,14 @@ __device__ void rowsort_lds(int r, const int64_t* __restrict__ inc_ptr, const ui
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
     for (int t = threadIdx.x; t < n; t += kBlock) {
-        uint32_t code = inc[start + t];
-        uint32_t k = code >> 2, i = code & 3u;
-        int nv = ft_nverts(type_of(k, tr));
-        int4 v = incv[start + t];
-        for (int j = 0; j < nv; ++j)
-            keys[4 * t + j] = ((unsigned long long)(uint32_t)vslot(v, j) << 32) | (unsigned long long)((k << 4) | (i << 2) | (uint32_t)j);
+        const int4 rec = incr[start + t];
+        const uint32_t code = (uint32_t)rec.x;
+        const uint32_t k = code >> 2, i = code & 3u;
+        const int nv = ft_nverts(type_of(k, tr));
+        for (int j = 0; j < nv; ++j) {
+            const int col = j == (int)i ? r : rec_other(rec, other_slot(j, (int)i));
+            keys[4 * t + j] = ((unsigned long long)(uint32_t)col << 32) | (unsigned long long)((k << 4) | (i << 2) | (uint32_t)j);
+        }
     }
     __syncthreads();
     // bitonic sort, ascending
@@ -365,8 +378,7 @@ __device__ __forceinline__ void rowsort_main(int64_t r, int n, int T, int MD, co
 // sort 128 keys instead of 256.  Rows with more than kWaveIncidences
 // incidences are appended to `big` for the workgroup sort.
 __global__ void __launch_bounds__(kBlock) k_sym_rowsort_wave(int32_t V, const int64_t* __restrict__ inc_ptr,
-                                                             const uint32_t* __restrict__ inc,
-                                                             const int4* __restrict__ incv, TypeRanges tr,
+                                                             const int4* __restrict__ incr, TypeRanges tr,
                                                              const int64_t* __restrict__ kptr,
                                                              uint32_t* __restrict__ contrib,
                                                              int32_t* __restrict__ kcol, int32_t* __restrict__ kbeg,
@@ -398,13 +410,13 @@ __global__ void __launch_bounds__(kBlock) k_sym_rowsort_wave(int32_t V, const in
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int t = lane + 64 * h;
-        vv[h] = make_int4(-1, -1, -1, -1);
+        vv[h] = make_int4(0, -1, -1, -1);
         if (t < n) {
-            const uint32_t code = inc[start + t];
+            vv[h] = incr[start + t];
+            const uint32_t code = (uint32_t)vv[h].x;
             const uint32_t k = code >> 2, i = code & 3u;
             o[h] = ft_nverts(type_of(k, tr)) - 1;
             kc[h] = code;
-            vv[h] = incv[start + t];
             dkey[h] = (k << 4) | (i << 2) | i;
         }
     }
@@ -428,7 +440,7 @@ __global__ void __launch_bounds__(kBlock) k_sym_rowsort_wave(int32_t V, const in
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 if (j <= o[h] && j != (int)i)
-                    lk[p++] = ((unsigned long long)(uint32_t)vslot(vv[h], j) << 32) |
+                    lk[p++] = ((unsigned long long)(uint32_t)rec_other(vv[h], other_slot(j, (int)i)) << 32) |
                               (unsigned long long)((k << 4) | (i << 2) | (uint32_t)j);
         }
     }
@@ -461,14 +473,13 @@ __global__ void __launch_bounds__(kBlock) k_sym_rowsort_wave(int32_t V, const in
 __global__ void __launch_bounds__(kBlock) k_sym_rowsort(const int32_t* __restrict__ rows,
                                                         const unsigned long long* __restrict__ nrows,
                                                         const int64_t* __restrict__ inc_ptr,
-                                                        const uint32_t* __restrict__ inc,
-                                                        const int4* __restrict__ incv, TypeRanges tr,
+                                                        const int4* __restrict__ incr, TypeRanges tr,
                                                         const int64_t* __restrict__ kptr,
                                                         uint32_t* __restrict__ contrib, int32_t* __restrict__ kcol,
                                                         int32_t* __restrict__ kbeg, int32_t* __restrict__ ncols) {
     const int64_t nr = (int64_t)*nrows;
     for (int64_t idx = blockIdx.x; idx < nr; idx += gridDim.x) {
-        rowsort_lds(rows[idx], inc_ptr, inc, incv, tr, kptr, contrib, kcol, kbeg, ncols);
+        rowsort_lds(rows[idx], inc_ptr, incr, tr, kptr, contrib, kcol, kbeg, ncols);
         __syncthreads();
     }
 }
@@ -534,29 +545,28 @@ hipError_t launch_sym_count(const int4* st_vid, TypeRanges tr, int32_t* deg, int
 }
 
 hipError_t launch_sym_scatter(const int4* st_vid, TypeRanges tr, const int64_t* inc_ptr, int32_t* fill,
-                              uint32_t* inc, int4* incv, hipStream_t s) {
+                              int4* incr, hipStream_t s) {
     int64_t nb = (tr.off[8] + kBlock - 1) / kBlock;
     if (nb == 0) return hipSuccess;
-    k_sym_scatter<<<(unsigned)nb, kBlock, 0, s>>>(st_vid, tr, inc_ptr, fill, inc, incv);
+    k_sym_scatter<<<(unsigned)nb, kBlock, 0, s>>>(st_vid, tr, inc_ptr, fill, incr);
     return hipGetLastError();
 }
 
-hipError_t launch_sym_rowsort(int32_t V, int32_t max_deg, const int64_t* inc_ptr, const uint32_t* inc,
-                              const int4* incv, TypeRanges tr, const int64_t* kptr, uint32_t* contrib,
+hipError_t launch_sym_rowsort(int32_t V, int32_t max_deg, const int64_t* inc_ptr, const int4* incr,
+                              TypeRanges tr, const int64_t* kptr, uint32_t* contrib,
                               int32_t* kcol, int32_t* kbeg, int32_t* ncols, int32_t* big, int64_t* nbig,
                               hipStream_t s) {
     if (V == 0) return hipSuccess;
     unsigned long long* nb = reinterpret_cast<unsigned long long*>(nbig);
     const unsigned blocks = (unsigned)(((int64_t)V + kBlock / 64 - 1) / (kBlock / 64));
-    k_sym_rowsort_wave<<<blocks, kBlock, 0, s>>>(V, inc_ptr, inc, incv, tr, kptr, contrib, kcol, kbeg, ncols, big,
-                                                 nb);
+    k_sym_rowsort_wave<<<blocks, kBlock, 0, s>>>(V, inc_ptr, incr, tr, kptr, contrib, kcol, kbeg, ncols, big, nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || max_deg <= kWaveIncidences) return e;
     unsigned N = 64;
     while (N < 4u * (unsigned)max_deg) N <<= 1;
     const size_t lds = sizeof(unsigned long long) * N;
     const unsigned grid = (unsigned)(V < 2048 ? V : 2048);
-    k_sym_rowsort<<<grid, kBlock, lds, s>>>(big, nb, inc_ptr, inc, incv, tr, kptr, contrib, kcol, kbeg, ncols);
+    k_sym_rowsort<<<grid, kBlock, lds, s>>>(big, nb, inc_ptr, incr, tr, kptr, contrib, kcol, kbeg, ncols);
     return hipGetLastError();
 }
 
