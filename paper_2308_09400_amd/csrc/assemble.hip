@@ -177,16 +177,22 @@ __global__ void __launch_bounds__(kBlock) k_rows_diag(int mode, int32_t V, const
     }
 }
 
-// kOffLanes lanes per block row, rows visited in `order` (storage order when
-// null; the mirrored stores of adjacent rows then fall in adjacent slots of
-// each neighbour row): lane l
-// takes the row's blocks above the diagonal l, l + kOffLanes, ...; each sums
-// its contribution list in order, is stored, and is stored transposed in
-// the mirrored slot (the (c, r) list holds the same pairs with i and j
-// swapped, so its sum is the transpose up to rounding; storing the
-// transpose makes A exactly symmetric).  Blocks without a mirror (tslot -2)
-// are only stored.
-constexpr int kOffLanes = 16;
+// Off-diagonal blocks, kOffLanes lanes per block row, rows visited in
+// `order` (storage order when null).  The row's blocks above the diagonal
+// are taken kOffLanes at a time (a window; lane l owns block l of it), and
+// the window's contribution lists, which are contiguous, are spread evenly
+// over the lanes: kOffLanes x kOffGroup contributions per step, each lane
+// gathering kOffGroup records at once and writing its local 3x3 terms to
+// LDS, after which every owner adds its own block's terms in list order.
+// A block's sum is thus in list order whatever the launch shape, and no
+// lane waits on a long list while the others idle (the lists of one row
+// run from 1 to about 40 contributions).  Each block is stored, and stored
+// transposed in the mirrored slot (the (c, r) list holds the same pairs
+// with i and j swapped, so its sum is the transpose up to rounding;
+// storing the transpose makes A exactly symmetric).  Blocks without a
+// mirror (tslot -2) are only stored.
+constexpr int kOffLanes = 32;
+constexpr int kOffGroup = 2;
 
 template <int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_offdiag(int32_t V, const int32_t* __restrict__ order,
@@ -198,32 +204,70 @@ __global__ void __launch_bounds__(BLOCK) k_offdiag(int32_t V, const int32_t* __r
                                                     const double* __restrict__ rec_main,
                                                     const double* __restrict__ rec_extra, int64_t e0, int64_t m0,
                                                     void* val, int dtype, int64_t nnzb) {
-    const int64_t gi = xcd_block() * (BLOCK / kOffLanes) + threadIdx.x / kOffLanes;
-    if (gi >= V) return;
-    const int lg = threadIdx.x % kOffLanes;
+    constexpr int L = kOffLanes, G = kOffGroup, C = L * G;
+    __shared__ double lds[BLOCK / L][C][9];
+    const int64_t gi = xcd_block() * (BLOCK / L) + threadIdx.x / L;
+    if (gi >= V) return;  // the whole lane group (L divides the wavefront)
+    const int lg = threadIdx.x % L;
+    double(*T)[9] = lds[threadIdx.x / L];
     const int32_t r = order ? order[gi] : (int32_t)gi;
-    const int32_t end = row_ptr[r + 1];
-    for (int32_t s = diag_slot[r] + 1 + lg; s < end; s += kOffLanes) {
-        const int32_t t = tslot[s];
-        double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-        const int64_t t0 = cptr[s], t1 = cptr[s + 1];
-        // groups of four: codes, then records, then the sums in list order
-        for (int64_t q = t0; q < t1; q += 4) {
-            uint32_t code[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) code[u] = q + u < t1 ? contrib[q + u] : 0u;
-            MainRec mr[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (q + u < t1) mr[u] = load_main(rec_main, code[u] >> 4);
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (q + u < t1)
-                    add_block_rec(B, mr[u], rec_extra, e0, m0, code[u] >> 4, (int)((code[u] >> 2) & 3u),
-                                  (int)(code[u] & 3u));
+    const int32_t dg = diag_slot[r], end = row_ptr[r + 1];
+    const int nbk = end - dg - 1;  // blocks above the diagonal
+    for (int w0 = 0; w0 < nbk; w0 += L) {
+        const bool own = w0 + lg < nbk;
+        const int32_t s = dg + 1 + w0 + lg;
+        int64_t o0 = 0, o1 = 0;
+        if (own) {
+            o0 = cptr[s];
+            o1 = cptr[s + 1];
         }
-        store_block(val, dtype, nnzb, s, B);
-        if (t >= 0) store_block(val, dtype, nnzb, t, B, true);
+        // the window's contributions (slot end is the next row's first)
+        const int64_t W0 = cptr[dg + 1 + w0], W1 = cptr[dg + 1 + min(w0 + L, nbk)];
+        double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int64_t c0 = W0; c0 < W1; c0 += C) {
+            uint32_t code[G];
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const int64_t t = c0 + u * L + lg;
+                code[u] = t < W1 ? contrib[t] : 0u;
+            }
+            MainRec mr[G];
+#pragma unroll
+            for (int u = 0; u < G; ++u)
+                if (c0 + u * L + lg < W1) mr[u] = load_main(rec_main, code[u] >> 4);
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                if (c0 + u * L + lg < W1) {
+                    double tm[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                    add_block_rec(tm, mr[u], rec_extra, e0, m0, code[u] >> 4, (int)((code[u] >> 2) & 3u),
+                                  (int)(code[u] & 3u));
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) T[u * L + lg][c] = tm[c];
+                }
+            }
+            // the lane group lies in one wavefront: its LDS writes are
+            // visible to its reads once the compiler keeps their order
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (own) {
+                const int64_t a = o0 > c0 ? o0 : c0, z = o1 < c0 + C ? o1 : c0 + C;
+                for (int64_t t = a; t < z; ++t) {
+                    const double* tm = T[t - c0];
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) B[c] += tm[c];
+                }
+            }
+            // every owner has read the step's terms before the next writes
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (own) {
+            store_block(val, dtype, nnzb, s, B);
+            const int32_t t = tslot[s];
+            if (t >= 0) store_block(val, dtype, nnzb, t, B, true);
+        }
     }
 }
 
