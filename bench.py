@@ -64,12 +64,12 @@ FP64_VECTOR_TFLOPS = 78.6    # MI355X FP64 vector peak
 # figure holds only for the kernel source it was measured on: it is reported
 # only while the SHA-256 of that source file still matches, else null.
 MEASURED_TRAFFIC = {
-    "kernel": "k_spmv_ent<false>",
+    "kernel": "k_spmv_ent",
     "bytes": 1.801e9,
     "source": "profiles/sheets10_path.md (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 per dispatch, "
               "calibrated on the library's 2 GiB copy in the same run)",
     "file": "paper_2308_09400_amd/csrc/solve.hip",
-    "sha256": "13f74f6e3edbbf8c22fc5bd525be4845a9f756b01a8a975aa8d7e672dc13c40a",
+    "sha256": "f540f23320b00d1eeccfd47ee47dd086ba3e741fb28debb5a965bff5e6c71a37",
 }
 
 
@@ -732,7 +732,7 @@ def single_run(gp, args, workload, steps, warmup, cands_on_gpu):
     traffic, tsrc = (None, None) if mixed else _traffic_if_current()
     out["roofline"] = {
         "kernel": "k_spmv<float> (FP32 BSR SpMV by rows)" if mixed
-        else "k_spmv_ent<false> (FP64 BSR SpMV, one lane per block)",
+        else "k_spmv_ent (FP64 BSR SpMV, one lane per block)",
         "bound": "hbm",
         "achieved": float(spmv_gbs),
         "peak": HBM_PEAK_GBS,

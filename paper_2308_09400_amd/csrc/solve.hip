@@ -38,9 +38,13 @@
 // PCG (Saad Alg. 9.1 with the inverse 3x3 diagonal blocks as
 // preconditioner, the paper's simple block preconditioner of Sec. 7.2):
 // every scalar (alpha, beta, residual norms, the stopping test) lives in
-// device memory, so an iteration is five kernel launches without host
-// round trips; the host polls the "done" flag every 16 iterations (once
-// when rtol = 0).
+// device memory, so an iteration is six kernel launches without host
+// round trips (product, p.q partials, alpha, update with the r.z and r.r
+// partials, beta, p update); the host polls the "done" flag every 16
+// iterations (once when rtol = 0).  The p.q partials are a pass of their
+// own over p and q: formed in the product's epilogue (a block reduction
+// at the end of every product workgroup) they cost 355 against 327 us per
+// FP64 iteration on the ten-sheet matrix, and 254 against 223 us in FP32.
 #include "internal.hpp"
 
 namespace gipc {
@@ -83,29 +87,25 @@ __device__ __forceinline__ void stv(double* a, int64_t r, d3 v) {
     a[3 * r] = v.x; a[3 * r + 1] = v.y; a[3 * r + 2] = v.z;
 }
 
-// entry-parallel FP64 product (see the top of the file); with DOT the
-// workgroup also writes its partial of x.y over the rows it stores to
-// part[blockIdx.x] (the PCG's p.q, x = p)
+// entry-parallel FP64 product (see the top of the file); inside the PCG
+// (sc not null) it does nothing once the solve has stopped
 constexpr int kEntWaves = 8;
 constexpr int kEntBlock = kEntWaves * 64;
 
-template <bool DOT>
 __global__ void __launch_bounds__(kEntBlock) k_spmv_ent(int64_t nnzb, const int32_t* __restrict__ rp,
                                                         const int32_t* __restrict__ ci,
                                                         const double* __restrict__ val,
                                                         const unsigned long long* __restrict__ hm,
                                                         const int32_t* __restrict__ wrow,
                                                         const double* __restrict__ x, double* __restrict__ y,
-                                                        double* __restrict__ part,
                                                         const PcgScalars* __restrict__ sc) {
-    if (DOT && sc->done) return;
-    __shared__ double sf[kEntWaves][3], sl[kEntWaves][3], stail[3], lds[kEntWaves];
+    if (sc && sc->done) return;
+    __shared__ double sf[kEntWaves][3], sl[kEntWaves][3], stail[3];
     __shared__ unsigned long long sm[kEntWaves], smn[kEntWaves];
     __shared__ int32_t srow[kEntWaves];
     const int64_t W = (nnzb + 63) >> 6;
     const int wi = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int64_t w = (int64_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * kEntWaves + wi));
-    double d = 0.0;
     if (w < W) {
         const int64_t s = (w << 6) + l;
         const bool ok = s < nnzb;
@@ -148,7 +148,6 @@ __global__ void __launch_bounds__(kEntBlock) k_spmv_ent(int64_t nnzb, const int3
                 y[3 * r] = q0;
                 y[3 * r + 1] = q1;
                 y[3 * r + 2] = q2;
-                if (DOT) d = dot(ldv(x, r), mk(q0, q1, q2));
             } else {
                 sl[wi][0] = q0;
                 sl[wi][1] = q1;
@@ -210,12 +209,7 @@ __global__ void __launch_bounds__(kEntBlock) k_spmv_ent(int64_t nnzb, const int3
             y[3 * r] = a0;
             y[3 * r + 1] = a1;
             y[3 * r + 2] = a2;
-            if (DOT) d += dot(ldv(x, r), mk(a0, a1, a2));
         }
-    }
-    if (DOT) {
-        d = block_sum_n<kEntBlock>(d, lds);
-        if (threadIdx.x == 0) part[blockIdx.x] = d;
     }
 }
 
@@ -317,24 +311,16 @@ __device__ __forceinline__ d3 apply3(const double* M, d3 v) {
 }
 
 
-// q = A p (kG lanes per row) and one partial of p.q per workgroup of
-// kPcgBlock threads (32 rows), so the single-workgroup sum that forms alpha
-// reads few partials.  (A fixed grid walking row groups with a stride gave
-// fewer partials still but a slower product.)  T is the matrix type: for
-// FP32 matrices the product runs in FP32 on the FP32 copy pm of p and is
-// widened to FP64 when stored; the dot is FP64.
-constexpr int kPcgBlock = 1024;
-
+// q = A p (kG lanes per row).  T is the matrix type: for FP32 matrices the
+// product runs in FP32 on the FP32 copy pm of p and is widened to FP64 when
+// stored.
 template <typename T>
-__global__ void __launch_bounds__(kPcgBlock) k_pcg_spmv(int32_t nrows, const int32_t* __restrict__ rp,
-                                                        const int32_t* __restrict__ ci, const T* __restrict__ val,
-                                                        int64_t nnzb, const T* __restrict__ pm,
-                                                        const double* __restrict__ p, double* __restrict__ q,
-                                                        double* __restrict__ part,
-                                                        const PcgScalars* __restrict__ sc) {
+__global__ void __launch_bounds__(kBlock) k_pcg_spmv(int32_t nrows, const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ ci, const T* __restrict__ val,
+                                                     int64_t nnzb, const T* __restrict__ pm, double* __restrict__ q,
+                                                     const PcgScalars* __restrict__ sc) {
     if (sc->done) return;
-    __shared__ double lds[kPcgBlock / 64];
-    const int64_t row = ((int64_t)blockIdx.x * kPcgBlock + threadIdx.x) / kG;
+    const int64_t row = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kG;
     const int lg = threadIdx.x % kG;
     T a0 = 0, a1 = 0, a2 = 0;
     if (row < nrows) {
@@ -353,13 +339,19 @@ __global__ void __launch_bounds__(kPcgBlock) k_pcg_spmv(int32_t nrows, const int
         a1 += __shfl_xor(a1, o, kG);
         a2 += __shfl_xor(a2, o, kG);
     }
+    if (row < nrows && lg == 0) stv(q, row, mk((double)a0, (double)a1, (double)a2));
+}
+
+// partials of p.q, one per workgroup of kBlock rows
+__global__ void __launch_bounds__(kBlock) k_pcg_pq(int32_t V, const double* __restrict__ p,
+                                                   const double* __restrict__ q, double* __restrict__ part,
+                                                   const PcgScalars* __restrict__ sc) {
+    if (sc->done) return;
+    __shared__ double lds[kBlock / 64];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double d = 0.0;
-    if (row < nrows && lg == 0) {
-        const d3 qv = mk((double)a0, (double)a1, (double)a2);
-        stv(q, row, qv);
-        d = dot(ldv(p, row), qv);
-    }
-    d = block_sum_n<kPcgBlock>(d, lds);
+    if (i < V) d = dot(ldv(p, i), ldv(q, i));
+    d = block_sum(d, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = d;
 }
 
@@ -472,10 +464,10 @@ static int64_t spmv_ent_blocks(int64_t nnzb) { return ((nnzb + 63) / 64 + kEntWa
 hipError_t launch_spmv(const gipc_bsr& A, const void* x, void* y, hipStream_t s) {
     if (A.nbrows == 0) return hipSuccess;
     if (spmv_by_entry(A)) {
-        k_spmv_ent<false><<<(unsigned)spmv_ent_blocks(A.nnzb), kEntBlock, 0, s>>>(
+        k_spmv_ent<<<(unsigned)spmv_ent_blocks(A.nnzb), kEntBlock, 0, s>>>(
             A.nnzb, A.row_ptr, A.col_idx, static_cast<const double*>(A.val),
             reinterpret_cast<const unsigned long long*>(A.wave_head), A.wave_row, static_cast<const double*>(x),
-            static_cast<double*>(y), nullptr, nullptr);
+            static_cast<double*>(y), nullptr);
         return hipGetLastError();
     }
     const int64_t threads = (int64_t)A.nbrows * kG;
@@ -524,13 +516,12 @@ struct PcgWork {
     PcgScalars* sc;
 };
 
-// the partials the reductions need: one per workgroup of the widest kernel
+// the partials the reductions need: one per workgroup of kBlock rows (the
+// matrix-free operator forms its p.q partials in its own layout)
 static int64_t pcg_num_parts(const gipc_bsr& A, const MfView* mf) {
     const int32_t V = mf ? mf->V : A.nbrows;
     const int64_t nbv = (V + kBlock - 1) / kBlock;
-    const int64_t nbs = mf ? mf_num_parts(V)
-                           : spmv_by_entry(A) ? spmv_ent_blocks(A.nnzb)
-                                              : ((int64_t)V * kG + kPcgBlock - 1) / kPcgBlock;
+    const int64_t nbs = mf ? mf_num_parts(V) : nbv;
     return nbv > nbs ? nbv : nbs;
 }
 
@@ -606,9 +597,8 @@ static hipError_t pcg_exec(const gipc_bsr& A, const double* b, double* x, double
     const int64_t n3 = 3 * (int64_t)V;
     const int64_t nbv = (V + kBlock - 1) / kBlock;  // row-parallel kernels
     const bool ent = !mf && spmv_by_entry(A);       // entry-parallel FP64 product
-    const int64_t nbs = mf ? mf_num_parts(V)        // operator kernel
-                           : ent ? spmv_ent_blocks(A.nnzb)
-                                 : ((int64_t)V * kG + kPcgBlock - 1) / kPcgBlock;
+    const int64_t nbs = mf ? mf_num_parts(V) : nbv;  // p.q partials
+    const unsigned nbrow = (unsigned)(((int64_t)V * kG + kBlock - 1) / kBlock);  // kG lanes per row
     hipError_t e;
 #define GIPC_TRY(x)                            \
     do {                                       \
@@ -630,8 +620,8 @@ static hipError_t pcg_exec(const gipc_bsr& A, const double* b, double* x, double
         k_bj_inverse<float><<<(unsigned)nbv, kBlock, 0, s>>>(V, A.row_ptr, A.col_idx,
                                                              static_cast<const float*>(A.val), A.nnzb, minv);
         k_pupdate<<<nbn, kBlock, 0, s>>>(n3, nullptr, x, p32, sc, 1);  // FP32 copy of x0 in p32
-        k_pcg_spmv<float><<<(unsigned)nbs, kPcgBlock, 0, s>>>(V, A.row_ptr, A.col_idx, static_cast<const float*>(A.val),
-                                                           A.nnzb, p32, x, q, part, sc);
+        k_pcg_spmv<float><<<nbrow, kBlock, 0, s>>>(V, A.row_ptr, A.col_idx, static_cast<const float*>(A.val),
+                                                   A.nnzb, p32, q, sc);
     } else {
         k_bj_inverse<double><<<(unsigned)nbv, kBlock, 0, s>>>(V, A.row_ptr, A.col_idx,
                                                               static_cast<const double*>(A.val), A.nnzb, minv);
@@ -652,18 +642,21 @@ static hipError_t pcg_exec(const gipc_bsr& A, const double* b, double* x, double
     while (launched < maxit) {
         int32_t m = maxit - launched < chunk ? maxit - launched : chunk;
         for (int32_t it = 0; it < m; ++it) {
-            if (mf)
+            if (mf) {
                 GIPC_TRY(launch_mf_apply(*mf, p, q, part, sc, s));
-            else if (f32)
-                k_pcg_spmv<float><<<(unsigned)nbs, kPcgBlock, 0, s>>>(
-                    V, A.row_ptr, A.col_idx, static_cast<const float*>(A.val), A.nnzb, p32, p, q, part, sc);
-            else if (ent)
-                k_spmv_ent<true><<<(unsigned)nbs, kEntBlock, 0, s>>>(
-                    A.nnzb, A.row_ptr, A.col_idx, static_cast<const double*>(A.val),
-                    reinterpret_cast<const unsigned long long*>(A.wave_head), A.wave_row, p, q, part, sc);
-            else
-                k_pcg_spmv<double><<<(unsigned)nbs, kPcgBlock, 0, s>>>(
-                    V, A.row_ptr, A.col_idx, static_cast<const double*>(A.val), A.nnzb, p, p, q, part, sc);
+            } else {
+                if (f32)
+                    k_pcg_spmv<float><<<nbrow, kBlock, 0, s>>>(V, A.row_ptr, A.col_idx,
+                                                               static_cast<const float*>(A.val), A.nnzb, p32, q, sc);
+                else if (ent)
+                    k_spmv_ent<<<(unsigned)spmv_ent_blocks(A.nnzb), kEntBlock, 0, s>>>(
+                        A.nnzb, A.row_ptr, A.col_idx, static_cast<const double*>(A.val),
+                        reinterpret_cast<const unsigned long long*>(A.wave_head), A.wave_row, p, q, sc);
+                else
+                    k_pcg_spmv<double><<<nbrow, kBlock, 0, s>>>(V, A.row_ptr, A.col_idx,
+                                                                static_cast<const double*>(A.val), A.nnzb, p, q, sc);
+                k_pcg_pq<<<(unsigned)nbv, kBlock, 0, s>>>(V, p, q, part, sc);
+            }
             k_pcg_alpha<<<1, kRed, 0, s>>>(part, nbs, sc);
             k_pcg_update<<<(unsigned)nbv, kBlock, 0, s>>>(0, V, b, x, r, z, p, q, minv, part, sc);
             k_pcg_beta<<<1, kRed, 0, s>>>(0, part, nbv, sc, 0.0, 0);
