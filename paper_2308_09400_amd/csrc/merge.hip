@@ -152,34 +152,73 @@ __global__ void __launch_bounds__(kBlock) k_merge_resolve(const int4* __restrict
     if (grp.leader == lane) atomicAdd(&mult[rep - k0], __popcll(grp.members));
 }
 
-__global__ void __launch_bounds__(kBlock) k_merge_flags(int64_t Ps, int64_t k0, int64_t k1,
-                                                        const int32_t* __restrict__ rep_of,
-                                                        int32_t* __restrict__ flag) {
-    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= Ps) return;
-    flag[k] = (k < k0 || k >= k1) ? 1 : (rep_of[k - k0] == (int32_t)k ? 1 : 0);
+// the pairs the compaction keeps: those outside [k0, k1), and inside it
+// the representatives
+__device__ __forceinline__ bool survives(int64_t k, int64_t Ps, int64_t k0, int64_t k1,
+                                         const int32_t* __restrict__ rep_of) {
+    return k < Ps && (k < k0 || k >= k1 || rep_of[k - k0] == (int32_t)k);
 }
 
+// survivors per workgroup of kBlock staged pairs
+__global__ void __launch_bounds__(kBlock) k_merge_count(int64_t Ps, int64_t k0, int64_t k1,
+                                                        const int32_t* __restrict__ rep_of,
+                                                        int32_t* __restrict__ bcnt) {
+    __shared__ int32_t cnt[kBlock / 64];
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const unsigned long long m = __ballot(survives(k, Ps, k0, k1, rep_of));
+    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t c = 0;
+        for (int w = 0; w < kBlock / 64; ++w) c += cnt[w];
+        bcnt[blockIdx.x] = c;
+    }
+}
+
+// stable compaction: a survivor's position is its workgroup's offset plus
+// the survivors before it in the workgroup
 __global__ void __launch_bounds__(kBlock) k_merge_scatter(int64_t Ps, int64_t k0, int64_t k1,
-                                                          const int32_t* __restrict__ flag,
-                                                          const int64_t* __restrict__ pos,
+                                                          const int32_t* __restrict__ rep_of,
+                                                          const int64_t* __restrict__ boff,
                                                           const int4* __restrict__ st_vid,
                                                           const int32_t* __restrict__ st_src,
                                                           const int32_t* __restrict__ mult_in,
                                                           int4* __restrict__ vid_out, int32_t* __restrict__ src_out,
                                                           int32_t* __restrict__ mult_out) {
+    __shared__ int32_t cnt[kBlock / 64];
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= Ps || !flag[k]) return;
-    const int64_t n = pos[k];
+    const int wid = threadIdx.x >> 6;
+    const bool f = survives(k, Ps, k0, k1, rep_of);
+    const unsigned long long m = __ballot(f);
+    if ((threadIdx.x & 63) == 0) cnt[wid] = __popcll(m);
+    __syncthreads();
+    if (!f) return;
+    int64_t n = boff[blockIdx.x];
+    for (int w = 0; w < wid; ++w) n += cnt[w];
+    n += __popcll(m & __lanemask_lt());
     vid_out[n] = st_vid[k];
     src_out[n] = st_src[k];
     mult_out[n] = (k >= k0 && k < k1) ? mult_in[k - k0] : 1;
 }
 
-// merged type offsets: out[t] = pos[off[t]]
-__global__ void k_merge_offsets(const int64_t* __restrict__ pos, TypeRanges tr, int64_t* __restrict__ out) {
-    const int t = threadIdx.x;
-    if (t < 9) out[t] = pos[tr.off[t]];
+// merged type offsets, one workgroup per t = 0..8: out[t] = the survivors
+// before tr.off[t]
+__global__ void __launch_bounds__(kBlock) k_merge_offsets(int64_t Ps, int64_t k0, int64_t k1,
+                                                          const int32_t* __restrict__ rep_of,
+                                                          const int64_t* __restrict__ boff, TypeRanges tr,
+                                                          int64_t* __restrict__ out) {
+    __shared__ int32_t cnt[kBlock / 64];
+    const int64_t o = tr.off[blockIdx.x];
+    const int64_t b = o / kBlock;
+    const int64_t k = b * kBlock + threadIdx.x;
+    const unsigned long long m = __ballot(k < o && survives(k, Ps, k0, k1, rep_of));
+    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t c = boff[b];
+        for (int w = 0; w < kBlock / 64; ++w) c += cnt[w];
+        out[blockIdx.x] = c;
+    }
 }
 
 unsigned grid(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -202,8 +241,9 @@ hipError_t merge_duplicates(gipc_ctx* ctx, int32_t V, hipStream_t s, int64_t* ne
     TRY(ensure(ctx->mkeys, sizeof(unsigned long long) * H));
     TRY(ensure(ctx->mrep_of, sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
     TRY(ensure(ctx->mcount, sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
-    TRY(ensure(ctx->mflag, sizeof(int32_t) * (size_t)(Ps > 0 ? Ps : 1)));
-    TRY(ensure(ctx->mpos, sizeof(int64_t) * (size_t)(Ps + 1)));
+    const int64_t nbk = (Ps + kBlock - 1) / kBlock;  // compaction workgroups
+    TRY(ensure(ctx->mflag, sizeof(int32_t) * (size_t)(nbk > 0 ? nbk : 1)));
+    TRY(ensure(ctx->mpos, sizeof(int64_t) * (size_t)(nbk + 1)));
     TRY(ensure(ctx->st_vid2, sizeof(int4) * (size_t)(Ps > 0 ? Ps : 1)));
     TRY(ensure(ctx->st_src2, sizeof(int32_t) * (size_t)(Ps > 0 ? Ps : 1)));
     TRY(ensure(ctx->mult, sizeof(int32_t) * (size_t)(Ps > 0 ? Ps : 1)));
@@ -218,19 +258,20 @@ hipError_t merge_duplicates(gipc_ctx* ctx, int32_t V, hipStream_t s, int64_t* ne
                                                    as<int32_t>(ctx->mrep_of), as<int32_t>(ctx->mcount));
         TRY(hipGetLastError());
     }
+    const int32_t* rep = as<int32_t>(ctx->mrep_of);
     if (Ps > 0) {
-        k_merge_flags<<<grid(Ps), kBlock, 0, s>>>(Ps, k0, k1, as<int32_t>(ctx->mrep_of), as<int32_t>(ctx->mflag));
+        k_merge_count<<<(unsigned)nbk, kBlock, 0, s>>>(Ps, k0, k1, rep, as<int32_t>(ctx->mflag));
         TRY(hipGetLastError());
     }
-    TRY((exclusive_scan<int32_t, int64_t>(as<int32_t>(ctx->mflag), Ps, as<int64_t>(ctx->mpos), ctx, s)));
+    TRY((exclusive_scan<int32_t, int64_t>(as<int32_t>(ctx->mflag), nbk, as<int64_t>(ctx->mpos), ctx, s)));
     if (Ps > 0) {
-        k_merge_scatter<<<grid(Ps), kBlock, 0, s>>>(Ps, k0, k1, as<int32_t>(ctx->mflag), as<int64_t>(ctx->mpos),
-                                                    as<int4>(ctx->st_vid), as<int32_t>(ctx->st_src),
-                                                    as<int32_t>(ctx->mcount), as<int4>(ctx->st_vid2),
-                                                    as<int32_t>(ctx->st_src2), as<int32_t>(ctx->mult));
+        k_merge_scatter<<<(unsigned)nbk, kBlock, 0, s>>>(Ps, k0, k1, rep, as<int64_t>(ctx->mpos),
+                                                         as<int4>(ctx->st_vid), as<int32_t>(ctx->st_src),
+                                                         as<int32_t>(ctx->mcount), as<int4>(ctx->st_vid2),
+                                                         as<int32_t>(ctx->st_src2), as<int32_t>(ctx->mult));
         TRY(hipGetLastError());
     }
-    k_merge_offsets<<<1, 64, 0, s>>>(as<int64_t>(ctx->mpos), tr, new_off_dev);
+    k_merge_offsets<<<9, kBlock, 0, s>>>(Ps, k0, k1, rep, as<int64_t>(ctx->mpos), tr, new_off_dev);
     TRY(hipGetLastError());
 #undef TRY
     std::swap(ctx->st_vid, ctx->st_vid2);
