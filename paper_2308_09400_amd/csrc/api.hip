@@ -239,7 +239,7 @@ namespace {
 std::vector<DevBuf*> ctx_buffers(gipc_ctx* ctx) {
     return {&ctx->cand_ft, &ctx->cand_vid, &ctx->bcount, &ctx->boff, &ctx->counters, &ctx->st_vid,
                       &ctx->st_src, &ctx->mult, &ctx->mkeys, &ctx->mrep_of, &ctx->mcount,
-                      &ctx->mflag, &ctx->mpos, &ctx->st_vid2, &ctx->st_src2, &ctx->deg, &ctx->kcount, &ctx->fill, &ctx->inc_ptr, &ctx->kptr,
+                      &ctx->mbcount, &ctx->mpos, &ctx->st_vid2, &ctx->st_src2, &ctx->deg, &ctx->kcount, &ctx->fill, &ctx->inc_ptr, &ctx->kptr,
                       &ctx->contrib, &ctx->kcol, &ctx->kbeg, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
                       &ctx->slot_row, &ctx->diag_slot, &ctx->whead, &ctx->wrow, &ctx->maxbuf, &ctx->bigrows, &ctx->tslot, &ctx->incr, &ctx->order,
                       &ctx->obox, &ctx->ocell, &ctx->ohist, &ctx->ooff, &ctx->ofill, &ctx->rec_main, &ctx->rec_extra, &ctx->rec_a1, &ctx->ev,

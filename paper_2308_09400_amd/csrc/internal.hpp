@@ -137,7 +137,7 @@ struct gipc_ctx {
     gipc::DevBuf st_vid, st_src, mult;
     bool merged = false;
     // merge scratch
-    gipc::DevBuf mkeys, mrep_of, mcount, mflag, mpos, st_vid2, st_src2;
+    gipc::DevBuf mkeys, mrep_of, mcount, mbcount, mpos, st_vid2, st_src2;
     gipc::TypeRanges ranges{};
     int64_t Ps = 0;
     int32_t V = 0;

@@ -242,7 +242,7 @@ hipError_t merge_duplicates(gipc_ctx* ctx, int32_t V, hipStream_t s, int64_t* ne
     TRY(ensure(ctx->mrep_of, sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
     TRY(ensure(ctx->mcount, sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
     const int64_t nbk = (Ps + kBlock - 1) / kBlock;  // compaction workgroups
-    TRY(ensure(ctx->mflag, sizeof(int32_t) * (size_t)(nbk > 0 ? nbk : 1)));
+    TRY(ensure(ctx->mbcount, sizeof(int32_t) * (size_t)(nbk > 0 ? nbk : 1)));
     TRY(ensure(ctx->mpos, sizeof(int64_t) * (size_t)(nbk + 1)));
     TRY(ensure(ctx->st_vid2, sizeof(int4) * (size_t)(Ps > 0 ? Ps : 1)));
     TRY(ensure(ctx->st_src2, sizeof(int32_t) * (size_t)(Ps > 0 ? Ps : 1)));
@@ -260,10 +260,10 @@ hipError_t merge_duplicates(gipc_ctx* ctx, int32_t V, hipStream_t s, int64_t* ne
     }
     const int32_t* rep = as<int32_t>(ctx->mrep_of);
     if (Ps > 0) {
-        k_merge_count<<<(unsigned)nbk, kBlock, 0, s>>>(Ps, k0, k1, rep, as<int32_t>(ctx->mflag));
+        k_merge_count<<<(unsigned)nbk, kBlock, 0, s>>>(Ps, k0, k1, rep, as<int32_t>(ctx->mbcount));
         TRY(hipGetLastError());
     }
-    TRY((exclusive_scan<int32_t, int64_t>(as<int32_t>(ctx->mflag), nbk, as<int64_t>(ctx->mpos), ctx, s)));
+    TRY((exclusive_scan<int32_t, int64_t>(as<int32_t>(ctx->mbcount), nbk, as<int64_t>(ctx->mpos), ctx, s)));
     if (Ps > 0) {
         k_merge_scatter<<<(unsigned)nbk, kBlock, 0, s>>>(Ps, k0, k1, rep, as<int64_t>(ctx->mpos),
                                                          as<int4>(ctx->st_vid), as<int32_t>(ctx->st_src),
