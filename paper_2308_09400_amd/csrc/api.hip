@@ -77,6 +77,15 @@ enum {
     C_NSLOTS = 40
 };
 
+// every build counter to zero, the "first index" slots to all ones (so an
+// atomic minimum over the flagged indices gives the first one)
+__global__ void k_reset_counters(int64_t* __restrict__ cnt) {
+    const int i = threadIdx.x;
+    if (i >= C_NSLOTS) return;
+    const bool first = i == C_FIRST_BAD || i == C_FIRST_DEG || i == C_FIRST_DPRIM || i == C_FIRST_SPAN;
+    cnt[i] = first ? -1 : 0;
+}
+
 gipc_status fail(gipc_ctx* ctx, gipc_status st, const char* fmt, ...) {
     if (ctx) {
         char buf[512];
@@ -334,10 +343,8 @@ gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
     CK(ensure(ctx->st_vid, sizeof(int4) * (size_t)P), "alloc staged pairs");
     CK(ensure(ctx->st_src, sizeof(int32_t) * (size_t)P), "alloc staged pairs");
     int64_t* cnt = as<int64_t>(ctx->counters);
-    CK(hipMemsetAsync(cnt, 0, sizeof(int64_t) * C_NSLOTS, s), "clear counters");
-    CK(hipMemsetAsync(cnt + C_FIRST_BAD, 0xff, sizeof(int64_t), s), "clear counters");
-    CK(hipMemsetAsync(cnt + C_FIRST_DEG, 0xff, sizeof(int64_t), s), "clear counters");
-    CK(hipMemsetAsync(cnt + C_FIRST_DPRIM, 0xff, sizeof(int64_t), s), "clear counters");
+    k_reset_counters<<<1, 64, 0, s>>>(cnt);
+    CK(hipGetLastError(), "clear counters");
     if (P > 0) {
         CK(launch_stage_classify(pairs->tuples, P, V, mesh->x, xr, pm, as<uint8_t>(ctx->cand_ft),
                                  as<int4>(ctx->cand_vid), as<int32_t>(ctx->bcount), cnt, s),
@@ -385,9 +392,8 @@ gipc_status gipc_pairs_build(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_pa
     CK(ensure(ctx->ncols, sizeof(int32_t) * Vs), "alloc pattern");
     CK(ensure(ctx->row_ptr, sizeof(int32_t) * (Vs + 1)), "alloc pattern");
     CK(ensure(ctx->diag_slot, sizeof(int32_t) * Vs), "alloc pattern");
-    CK(hipMemsetAsync(ctx->deg.p, 0, sizeof(int32_t) * Vs, s), "clear pattern");
-    CK(hipMemsetAsync(ctx->kcount.p, 0, sizeof(int32_t) * Vs, s), "clear pattern");
-    CK(hipMemsetAsync(ctx->fill.p, 0, sizeof(int32_t) * Vs, s), "clear pattern");
+    CK(zero_i32(as<int32_t>(ctx->deg), as<int32_t>(ctx->kcount), as<int32_t>(ctx->fill), (int64_t)Vs, s),
+       "clear pattern");
     CK(launch_sym_count(as<int4>(ctx->st_vid), tr, as<int32_t>(ctx->deg), as<int32_t>(ctx->kcount), s), "count");
     CK(reduce_max_i32(as<int32_t>(ctx->deg), V, reinterpret_cast<int32_t*>(cnt + C_MAXDEG), s), "max degree");
     CK((exclusive_scan<int32_t, int64_t>(as<int32_t>(ctx->deg), V, as<int64_t>(ctx->inc_ptr), ctx, s, cnt + C_INC)),

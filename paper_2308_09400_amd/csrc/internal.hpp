@@ -195,6 +195,8 @@ namespace gipc {
 template <typename TIn, typename TOut>
 hipError_t exclusive_scan(const TIn* in, int64_t n, TOut* out, gipc_ctx* ctx, hipStream_t s,
                           int64_t* total_dev = nullptr);
+// zeroes a[0..n), and b and c when not null, in one launch
+hipError_t zero_i32(int32_t* a, int32_t* b, int32_t* c, int64_t n, hipStream_t s);
 hipError_t reduce_max_i32(const int32_t* in, int64_t n, int32_t* out_dev, hipStream_t s);
 
 // ---- stage.hip

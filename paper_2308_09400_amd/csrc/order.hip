@@ -184,8 +184,7 @@ hipError_t build_row_order(gipc_ctx* ctx, const double* x, int32_t V, const int3
         k_bbox_final<<<1, 384, 0, s>>>(as<double>(ctx->obox), nparts, box);
         TRY(hipGetLastError());
     }
-    TRY(hipMemsetAsync(ctx->ohist.p, 0, sizeof(int32_t) * (size_t)nbuckets, s));
-    TRY(hipMemsetAsync(ctx->ofill.p, 0, sizeof(int32_t) * (size_t)nbuckets, s));
+    TRY(zero_i32(as<int32_t>(ctx->ohist), as<int32_t>(ctx->ofill), nullptr, nbuckets, s));
     const unsigned nb = (unsigned)(((int64_t)V + kBlock - 1) / kBlock);
     k_cell_count<<<nb, kBlock, 0, s>>>(x, V, S > 1 ? as<int32_t>(ctx->vscene) : nullptr, box, bits,
                                       as<int32_t>(ctx->ocell), as<int32_t>(ctx->ohist));

@@ -147,12 +147,32 @@ template hipError_t exclusive_scan<int32_t, int32_t>(const int32_t*, int64_t, in
 template hipError_t exclusive_scan<int64_t, int64_t>(const int64_t*, int64_t, int64_t*, gipc_ctx*, hipStream_t,
                                                      int64_t*);
 
+namespace {
+// zeroes up to three int32 arrays of n entries in one launch (b, c nullable)
+__global__ void __launch_bounds__(kBlock) k_zero_i32(int32_t* __restrict__ a, int32_t* __restrict__ b,
+                                                     int32_t* __restrict__ c, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    a[i] = 0;
+    if (b) b[i] = 0;
+    if (c) c[i] = 0;
+}
+}  // namespace
+
+hipError_t zero_i32(int32_t* a, int32_t* b, int32_t* c, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_zero_i32<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(a, b, c, n);
+    return hipGetLastError();
+}
+
 hipError_t reduce_max_i32(const int32_t* in, int64_t n, int32_t* out_dev, hipStream_t s) {
     hipError_t e = hipMemsetAsync(out_dev, 0, sizeof(int32_t), s);
     if (e != hipSuccess) return e;
     if (n <= 0) return hipSuccess;
+    // one atomic per workgroup on the same word: few workgroups, each
+    // striding over many elements
     int64_t blocks = (n + kBlock - 1) / kBlock;
-    if (blocks > 2048) blocks = 2048;
+    if (blocks > 256) blocks = 256;
     k_max_i32<<<(unsigned)blocks, kBlock, 0, s>>>(in, n, out_dev);
     return hipGetLastError();
 }

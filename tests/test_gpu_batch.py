@@ -130,13 +130,14 @@ def test_batch_errors(gp):
     dev = torch.device("cuda", 0)
     X = torch.tensor(b.x, device=dev)
     ctx = gp.Context()
-    # a tuple joining the first vertex of scene 0 and of scene 1
+    # a tuple joining the first vertex of scene 0 and of scene 1 (at index 5,
+    # which the message names)
     bad = b.tuples.copy()
-    bad[0] = [-(0 + 1), int(b.vert_off[1]), -1, -1]
+    bad[5] = [-(0 + 1), int(b.vert_off[1]), -1, -1]
     bt = gp.Batch(b.vert_off, b.dhat, b.kappa)
     with pytest.raises(gp.GipcError, match="two scenes") as ei:
         gp.pairs_build(ctx, X, torch.tensor(bad, device=dev), gp.params(batch=bt))
-    assert ei.value.status == gp.ERR_INDEX
+    assert ei.value.status == gp.ERR_INDEX and "first at 5" in str(ei.value)
     # scene offsets that do not end at V, or decrease
     for vo in ([0, 5, 3, b.V], [0, 10, 20, b.V - 1]):
         with pytest.raises(gp.GipcError) as ei:
