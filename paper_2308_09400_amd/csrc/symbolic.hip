@@ -117,14 +117,12 @@ __device__ void rowsort_lds(int r, const int64_t* __restrict__ inc_ptr, const in
                             uint32_t* __restrict__ contrib, int32_t* __restrict__ kcol, int32_t* __restrict__ kbeg,
                             int32_t* __restrict__ ncols) {
     extern __shared__ unsigned long long keys[];
-    __shared__ int32_t cnt;
     __shared__ int32_t wcnt[kBlock / 64];
     const int64_t start = inc_ptr[r];
     const int n = (int)(inc_ptr[r + 1] - start);
     unsigned N = 1;
     while (N < 4u * (unsigned)n) N <<= 1;
     for (unsigned t = threadIdx.x; t < N; t += kBlock) keys[t] = ~0ull;
-    if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
     for (int t = threadIdx.x; t < n; t += kBlock) {
         const int4 rec = incr[start + t];
