@@ -735,15 +735,29 @@ def set_tune(ctx: Context, eval_waves=4, row_lanes=16, offdiag_waves=4, row_orde
     ctx._check(lib().gipc_set_tune(ctx.h, ctypes.byref(t)), "gipc_set_tune")
 
 
+_LIB_DIGEST = None
+
+
+def _lib_digest() -> str:
+    """First 16 hex digits of the SHA-256 of the loaded library file."""
+    global _LIB_DIGEST
+    if _LIB_DIGEST is None:
+        import hashlib
+        with open(LIB_PATH, "rb") as f:
+            _LIB_DIGEST = hashlib.sha256(f.read()).hexdigest()[:16]
+    return _LIB_DIGEST
+
+
 def autotune(ctx: Context, x, prm: Params, A: BsrMatrix, diag=None, x_rest=None, reps=5, cache=None, key=None,
              stream=None) -> dict:
     """Pick the fastest launch shapes of the eval / row / off-diagonal kernels
     for the current build (``gipc_autotune``, synchronises).  With ``cache``
     (a JSON file path), a stored choice is applied instead of timing, and a
     new one is stored.  The cache key is the device architecture, the tune
-    fields of this library, the build's mix of staged sub-types (rounded
-    shares) and its size bucket (powers of two of staged pairs and vertices),
-    plus ``key`` if given; an entry missing any tune field is timed again.
+    fields and a digest of this library's binary (a rebuilt kernel is timed
+    again), the build's mix of staged sub-types (rounded shares) and its size
+    bucket (powers of two of staged pairs and vertices), plus ``key`` if
+    given; an entry missing any tune field is timed again.
     Returns the shapes in force afterwards (``get_tune``)."""
     import json
     import math
@@ -755,7 +769,7 @@ def autotune(ctx: Context, x, prm: Params, A: BsrMatrix, diag=None, x_rest=None,
         bucket = f"P2^{int(math.log2(max(tot, 1)))},V2^{int(math.log2(max(int(x.shape[0]), 1)))}"
         arch = torch.cuda.get_device_properties(x.device).gcnArchName
         fields = ",".join(f for f, _ in Tune._fields_)
-        dkey = f"{arch}|{fields}|{mix}|{bucket}|{key or ''}"
+        dkey = f"{arch}|{fields}|{_lib_digest()}|{mix}|{bucket}|{key or ''}"
         try:
             with open(cache) as f:
                 table = json.load(f)

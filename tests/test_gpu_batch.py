@@ -206,7 +206,15 @@ def test_autotune(gp, tmp_path):
     import json
     table = json.loads(cache.read_text())
     (k,) = [k for k in table if k.endswith("|small")]
-    assert "gfx" in k.split("|")[0]
+    assert "gfx" in k.split("|")[0] and k.split("|")[2] == gp._lib_digest()
+    # an entry stored by another build of the library is not applied: the
+    # choice is timed again and stored under this build's key
+    other = k.replace(gp._lib_digest(), "0" * 16)
+    cache.write_text(json.dumps({other: table[k]}))
+    gp.set_tune(ctx, 4, 16, 4)
+    gp.autotune(ctx, X, prm, A, diag=diag, x_rest=XR, reps=1, cache=str(cache), key="small")
+    assert set(json.loads(cache.read_text())) == {other, k}
+    cache.write_text(json.dumps(table))
     stale = dict(table[k])
     del stale["row_order"]
     table[k] = stale
