@@ -231,7 +231,7 @@ hipError_t merge_duplicates(gipc_ctx* ctx, int32_t V, hipStream_t s, int64_t* ne
     const int64_t n = k1 - k0;
     uint64_t H = 1024;
     while (H < (uint64_t)n + (uint64_t)n / 4) H <<= 1;
-    // home slots spread over the whole table: V is this build's vertex count
+    // home slots spread over the whole table: V is the vertex count of the pair set
     const double scale = V > 0 ? (double)H / (double)V : 1.0;
     hipError_t e;
 #define TRY(x)                          \

@@ -208,7 +208,7 @@ def test_autotune(gp, tmp_path):
     (k,) = [k for k in table if k.endswith("|small")]
     assert "gfx" in k.split("|")[0] and k.split("|")[2] == gp._lib_digest()
     # an entry stored by another build of the library is not applied: the
-    # choice is timed again and stored under this build's key
+    # choice is timed again and stored under the loaded library's key
     other = k.replace(gp._lib_digest(), "0" * 16)
     cache.write_text(json.dumps({other: table[k]}))
     gp.set_tune(ctx, 4, 16, 4)
