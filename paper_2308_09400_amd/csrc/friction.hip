@@ -17,8 +17,9 @@
 // the eigen-decomposition of the 2x2 M (eigenvalue f1' along u, f1/|u|
 // across it) clamped to PSD; the Hessian block (i, j) is c_i c_j S.  A row
 // pass then gathers the gradient, per-vertex energy shares and, on request,
-// adds c_i c_j S to every BSR block, each block summing its contribution
-// list in the order of the symbolic phase.
+// the diagonal blocks; a second pass adds c_i c_j S to every off-diagonal
+// BSR block, each block summing its contribution list in the order of the
+// symbolic phase.
 #include "internal.hpp"
 
 namespace gipc {
@@ -130,9 +131,7 @@ __device__ __forceinline__ void add_block_sym(void* val, int dtype, int64_t nnzb
 
 // kFrLanes lanes per row.  The diagonal list (the row's incidences) is
 // split over the lanes and reduced by a fixed butterfly: gradient, energy
-// share (pairs whose slot 0 is the row) and the diagonal block.  With val,
-// every off-diagonal block of the row is then summed by one lane, four
-// contributions' loads in flight, in list order.
+// share (pairs whose slot 0 is the row) and, with val, the diagonal block.
 __global__ void __launch_bounds__(kBlock) k_fric_rows(int32_t V, const int32_t* __restrict__ row_ptr,
                                                       const int32_t* __restrict__ diag_slot,
                                                       const int64_t* __restrict__ cptr,
@@ -172,29 +171,83 @@ __global__ void __launch_bounds__(kBlock) k_fric_rows(int32_t V, const int32_t* 
         grad[3 * r + 2] = acc[2];
         ev[r] = acc[3];
     }
-    if (!val) return;
-    if (lg == 0) add_block_sym(val, dtype, nnzb, ds, acc + 4);
-    for (int32_t sl = row_ptr[r] + lg; sl < row_ptr[r + 1]; sl += kFrLanes) {
-        if (sl == ds) continue;
-        double B[6] = {0, 0, 0, 0, 0, 0};
-        const int64_t t1 = cptr[sl + 1];
-        constexpr int U = 4;
-        for (int64_t t = cptr[sl]; t < t1; t += U) {
-            uint32_t code[U];
-#pragma unroll
-            for (int q = 0; q < U; ++q) code[q] = t + q < t1 ? contrib[t + q] : 0u;
-#pragma unroll
-            for (int q = 0; q < U; ++q) {
-                if (t + q >= t1) break;
-                const uint32_t k = code[q] >> 4;
-                const int i = (int)((code[q] >> 2) & 3u), j = (int)(code[q] & 3u);
-                const double* f = fr + kFr * (int64_t)k;
-                const double cc = fr_coef(f, k, i, e0) * fr_coef(f, k, j, e0);
-#pragma unroll
-                for (int c = 0; c < 6; ++c) B[c] += cc * f[4 + c];
+    if (val && lg == 0) add_block_sym(val, dtype, nnzb, ds, acc + 4);
+}
+
+// Off-diagonal blocks, kFoLanes lanes per row: the row's blocks below and
+// above the diagonal are taken kFoLanes at a time (a window of consecutive
+// slots, whose contribution lists are contiguous), the window's
+// contributions dealt evenly to the lanes, kFoLanes x kFoGroup per step; each
+// lane writes its terms c_i c_j S (upper triangles) to LDS and the owner of
+// each block adds its own in list order.  Block (c, r) sums the same pairs
+// as (r, c) in the same order with the same products c_i c_j, so the two
+// are equal, as S is symmetric.
+constexpr int kFoLanes = 32, kFoGroup = 2;
+
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_fric_offdiag(int32_t V, const int32_t* __restrict__ row_ptr,
+                                                        const int32_t* __restrict__ diag_slot,
+                                                        const int64_t* __restrict__ cptr,
+                                                        const uint32_t* __restrict__ contrib,
+                                                        const double* __restrict__ fr, int64_t e0,
+                                                        void* __restrict__ val, int dtype, int64_t nnzb) {
+    constexpr int L = kFoLanes, G = kFoGroup, C = L * G;
+    __shared__ double lds[BLOCK / L][C][6];
+    const int64_t r = xcd_block() * (BLOCK / L) + threadIdx.x / L;
+    if (r >= V) return;  // the whole lane group (L divides the wavefront)
+    const int lg = threadIdx.x % L;
+    double(*T)[6] = lds[threadIdx.x / L];
+    const int32_t ds = diag_slot[r];
+    // the two runs of off-diagonal slots: [row start, ds) and (ds, row end)
+    const int32_t lo[2] = {row_ptr[r], ds + 1}, hi[2] = {ds, row_ptr[r + 1]};
+    for (int h = 0; h < 2; ++h) {
+        for (int32_t w0 = lo[h]; w0 < hi[h]; w0 += L) {
+            const int32_t w1 = min(w0 + L, hi[h]);
+            const int32_t sl = w0 + lg;
+            const bool own = sl < w1;
+            int64_t o0 = 0, o1 = 0;
+            if (own) {
+                o0 = cptr[sl];
+                o1 = cptr[sl + 1];
             }
+            const int64_t W0 = cptr[w0], W1 = cptr[w1];
+            double B[6] = {0, 0, 0, 0, 0, 0};
+            for (int64_t c0 = W0; c0 < W1; c0 += C) {
+                uint32_t code[G];
+#pragma unroll
+                for (int u = 0; u < G; ++u) {
+                    const int64_t t = c0 + u * L + lg;
+                    code[u] = t < W1 ? contrib[t] : 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < G; ++u) {
+                    if (c0 + u * L + lg < W1) {
+                        const uint32_t k = code[u] >> 4;
+                        const int i = (int)((code[u] >> 2) & 3u), j = (int)(code[u] & 3u);
+                        const double* f = fr + kFr * (int64_t)k;
+                        const double cc = fr_coef(f, k, i, e0) * fr_coef(f, k, j, e0);
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) T[u * L + lg][c] = cc * f[4 + c];
+                    }
+                }
+                // the lane group lies in one wavefront: its LDS writes are
+                // visible to its reads once the compiler keeps their order
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (own) {
+                    const int64_t a = o0 > c0 ? o0 : c0, z = o1 < c0 + C ? o1 : c0 + C;
+                    for (int64_t t = a; t < z; ++t) {
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) B[c] += T[t - c0][c];
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            if (own) add_block_sym(val, dtype, nnzb, sl, B);
         }
-        add_block_sym(val, dtype, nnzb, sl, B);
     }
 }
 
@@ -222,6 +275,11 @@ hipError_t launch_fric_eval(int32_t V, const int4* st_vid, const TypeRanges& tr,
     const int64_t nb = ((int64_t)V * kFrLanes + kBlock - 1) / kBlock;
     k_fric_rows<<<(unsigned)nb, kBlock, 0, s>>>(V, row_ptr, diag_slot, cptr, contrib, fr, tr.off[FT_EE], grad, ev,
                                                 val, dtype, nnzb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !val) return e;
+    const int64_t nbo = ((int64_t)V * kFoLanes + kBlock - 1) / kBlock;
+    k_fric_offdiag<kBlock><<<(unsigned)nbo, kBlock, 0, s>>>(V, row_ptr, diag_slot, cptr, contrib, fr, tr.off[FT_EE],
+                                                            val, dtype, nnzb);
     return hipGetLastError();
 }
 
