@@ -668,7 +668,7 @@ gipc_status gipc_accd(gipc_ctx* ctx, const gipc_mesh* mesh, const double* disp, 
     if (!(tc >= 0.0) || !std::isfinite(tc)) return fail(ctx, GIPC_ERR_INVALID_ARG, "tc must be >= 0 and finite");
     if (max_iter < 1) return fail(ctx, GIPC_ERR_INVALID_ARG, "max_iter must be >= 1");
     hipStream_t hs = S(stream);
-    CK(ensure(ctx->accd_cnt, sizeof(unsigned long long) * 6), "alloc ccd counters");
+    CK(ensure(ctx->accd_cnt, sizeof(unsigned long long) * 8), "alloc ccd counters");
     auto* cnt = as<unsigned long long>(ctx->accd_cnt);
     CK(launch_accd(pairs->tuples, pairs->P, mesh->V, mesh->x, disp, s, tc, max_iter, toi, cnt, hs), "ccd");
     unsigned long long h[6];
