@@ -502,18 +502,37 @@ def pcg_static(A: BsrMatrix, b, x=None, rtol=1e-6, maxit=1000, stream=None, coun
 
 def candidates(ctx: Context, x, vobj, tris, edges, dhat, stream=None):
     """Contact candidates (point-triangle, then edge-edge) of a surface mesh
-    on the GPU: device int32 [P][4] in the sign encoding."""
+    on the GPU: device int32 [P][4] in the sign encoding.
+
+    The context remembers a capacity from its last call (the count plus a
+    quarter); while the count stays under it, one library call counts and
+    emits, and the result is the leading rows of a buffer of that capacity.
+    Otherwise (and on a context's first call) a counting call sizes the
+    output exactly and a second call emits."""
     mesh = Context._mesh(x, None)
     for t, name in ((vobj, "vobj"), (tris, "tris"), (edges, "edges")):
         _need(t, torch.int32, None, name)
     topo = Topology(_ptr(vobj), _ptr(tris), int(tris.numel() // 3), _ptr(edges), int(edges.numel() // 2))
     n = ctypes.c_int64()
-    ctx._check(lib().gipc_candidates(ctx.h, ctypes.byref(mesh), ctypes.byref(topo), float(dhat), None, 0,
-                                     ctypes.byref(n), _stream(stream)), "gipc_candidates")
+    cap = getattr(ctx, "_cand_cap", 0)
+    if cap > 0:
+        out = torch.empty((cap, 4), dtype=torch.int32, device=x.device)
+        st = lib().gipc_candidates(ctx.h, ctypes.byref(mesh), ctypes.byref(topo), float(dhat), _ptr(out), cap,
+                                   ctypes.byref(n), _stream(stream))
+        if st == OK:
+            ctx._cand_cap = max(cap, int(n.value) + int(n.value) // 4)
+            return out[: int(n.value)]
+        if st != ERR_WORKSPACE:
+            ctx._check(st, "gipc_candidates")
+        del out
+    else:
+        ctx._check(lib().gipc_candidates(ctx.h, ctypes.byref(mesh), ctypes.byref(topo), float(dhat), None, 0,
+                                         ctypes.byref(n), _stream(stream)), "gipc_candidates")
     out = torch.empty((max(int(n.value), 0), 4), dtype=torch.int32, device=x.device)
     if n.value > 0:
         ctx._check(lib().gipc_candidates(ctx.h, ctypes.byref(mesh), ctypes.byref(topo), float(dhat), _ptr(out),
                                          int(n.value), ctypes.byref(n), _stream(stream)), "gipc_candidates")
+    ctx._cand_cap = int(n.value) + int(n.value) // 4 + 64
     return out
 
 

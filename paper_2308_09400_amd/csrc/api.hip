@@ -252,7 +252,7 @@ std::vector<DevBuf*> ctx_buffers(gipc_ctx* ctx) {
                       &ctx->contrib, &ctx->kcol, &ctx->kbeg, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
                       &ctx->slot_row, &ctx->diag_slot, &ctx->whead, &ctx->wrow, &ctx->maxbuf, &ctx->bigrows, &ctx->tslot, &ctx->incr, &ctx->order,
                       &ctx->obox, &ctx->ocell, &ctx->ohist, &ctx->ooff, &ctx->ofill, &ctx->rec_main, &ctx->rec_extra, &ctx->rec_a1, &ctx->ev,
-                      &ctx->epart, &ctx->mfg, &ctx->mfab, &ctx->flag, &ctx->ffr, &ctx->fev, &ctx->fpart, &ctx->cpart, &ctx->ccnt, &ctx->ccount, &ctx->cfill, &ctx->coff_t, &ctx->cent_t, &ctx->coff_e, &ctx->cent_e, &ctx->qcnt, &ctx->qoff_p, &ctx->qoff_e, &ctx->crec_t, &ctx->crec_e, &ctx->vscene, &ctx->pieces, &ctx->poff,
+                      &ctx->epart, &ctx->mfg, &ctx->mfab, &ctx->flag, &ctx->ffr, &ctx->fev, &ctx->fpart, &ctx->cpart, &ctx->ccnt, &ctx->ccount, &ctx->cfill, &ctx->coff_t, &ctx->cent_t, &ctx->coff_e, &ctx->cent_e, &ctx->qcnt, &ctx->qoff_p, &ctx->qoff_e, &ctx->crec_t, &ctx->crec_e, &ctx->qtoff_p, &ctx->qtoff_e, &ctx->qent_p, &ctx->qent_e, &ctx->ecnt_p, &ctx->ecnt_e, &ctx->eoff_p, &ctx->eoff_e, &ctx->craw, &ctx->vscene, &ctx->pieces, &ctx->poff,
                       &ctx->r, &ctx->z, &ctx->p, &ctx->q, &ctx->p32, &ctx->minv, &ctx->part, &ctx->scal, &ctx->scan_tmp,
                       &ctx->scan_tmp2, &ctx->chk, &ctx->accd_cnt};
 }
@@ -930,61 +930,90 @@ gipc_status gipc_candidates(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_top
                     "grid of %.0f cells exceeds 2^28 (extent too large for the largest primitive plus dhat)", ncell_d);
     const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
 
-    CK(ensure(ctx->ccount, sizeof(int32_t) * (size_t)ncell), "alloc candidates");
-    CK(ensure(ctx->cfill, sizeof(int32_t) * (size_t)ncell), "alloc candidates");
-    CK(ensure(ctx->coff_t, sizeof(int64_t) * (size_t)(ncell + 1)), "alloc candidates");
-    CK(ensure(ctx->coff_e, sizeof(int64_t) * (size_t)(ncell + 1)), "alloc candidates");
-    CK(ensure(ctx->qcnt, sizeof(int32_t) * (size_t)std::max<int64_t>(V, E)), "alloc candidates");
-    CK(ensure(ctx->qoff_p, sizeof(int64_t) * (size_t)(V + 1)), "alloc candidates");
-    CK(ensure(ctx->qoff_e, sizeof(int64_t) * (size_t)(E + 1)), "alloc candidates");
-
+    // four cell tables: triangles, edges (each primitive in the cells its box
+    // covers, lists sorted by id), and the point and edge queries (each in
+    // the cells its box inflated by dhat covers); counters and fills per table
+    const int64_t Q[2] = {V, E};
+    CK(ensure(ctx->ccount, sizeof(int32_t) * 4 * (size_t)ncell), "alloc candidates");
+    CK(ensure(ctx->cfill, sizeof(int32_t) * 4 * (size_t)ncell), "alloc candidates");
+    int32_t* cnt4 = as<int32_t>(ctx->ccount);
+    int32_t* fill4 = as<int32_t>(ctx->cfill);
+    DevBuf* toff[2] = {&ctx->coff_t, &ctx->coff_e};
+    DevBuf* tent[2] = {&ctx->cent_t, &ctx->cent_e};
+    DevBuf* trec[2] = {&ctx->crec_t, &ctx->crec_e};
+    DevBuf* qtoff[2] = {&ctx->qtoff_p, &ctx->qtoff_e};
+    DevBuf* qent[2] = {&ctx->qent_p, &ctx->qent_e};
+    DevBuf* qeoff[2] = {&ctx->qoff_p, &ctx->qoff_e};
+    DevBuf* ecnt[2] = {&ctx->ecnt_p, &ctx->ecnt_e};
+    DevBuf* eoff[2] = {&ctx->eoff_p, &ctx->eoff_e};
+    for (int k = 0; k < 2; ++k) {
+        CK(ensure(*toff[k], sizeof(int64_t) * (size_t)(ncell + 1)), "alloc candidates");
+        CK(ensure(*qtoff[k], sizeof(int64_t) * (size_t)(ncell + 1)), "alloc candidates");
+        CK(ensure(*qeoff[k], sizeof(int64_t) * (size_t)(Q[k] + 1)), "alloc candidates");
+    }
+    CK(ensure(ctx->qcnt, sizeof(int32_t) * (size_t)std::max<int64_t>(std::max<int64_t>(V, E), 1)), "alloc candidates");
     CK(ensure(ctx->crec_t, (size_t)kPrimRecBytes * (size_t)(F > 0 ? F : 1)), "alloc candidates");
     CK(ensure(ctx->crec_e, (size_t)kPrimRecBytes * (size_t)(E > 0 ? E : 1)), "alloc candidates");
     CK(launch_prim_records(x, topo->tris, 3, F, topo->vobj, ctx->crec_t.p, s), "triangle records");
     CK(launch_prim_records(x, topo->edges, 2, E, topo->vobj, ctx->crec_e.p, s), "edge records");
-    // cell tables, each sized from its own count
-    int64_t nent = 0;
-    CK(launch_cell_count(ctx, x, topo->tris, 3, F, g, as<int32_t>(ctx->ccount), as<int32_t>(ctx->cfill),
-                         as<int64_t>(ctx->coff_t), s),
-       "triangle cells");
-    CK(hipMemcpyAsync(&nent, as<int64_t>(ctx->coff_t) + ncell, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
-    CK(hipStreamSynchronize(s), "stream synchronize");
-    CK(ensure(ctx->cent_t, sizeof(int32_t) * (size_t)(nent + 1)), "alloc candidates");
-    CK(launch_cell_fill(x, topo->tris, 3, F, g, as<int32_t>(ctx->cfill), as<int64_t>(ctx->coff_t),
-                        as<int32_t>(ctx->cent_t), s),
-       "triangle cells");
-    CK(launch_cand_query(0, false, x, V, topo->vobj, nullptr, ctx->crec_t.p, g, dhat, as<int64_t>(ctx->coff_t),
-                         as<int32_t>(ctx->cent_t), as<int32_t>(ctx->qcnt), nullptr, nullptr, s),
-       "point-triangle count");
-    CK((exclusive_scan<int32_t, int64_t>(as<int32_t>(ctx->qcnt), V, as<int64_t>(ctx->qoff_p), ctx, s)), "scan");
-    CK(launch_cell_count(ctx, x, topo->edges, 2, E, g, as<int32_t>(ctx->ccount), as<int32_t>(ctx->cfill),
-                         as<int64_t>(ctx->coff_e), s),
+    CK(launch_cell_count(ctx, x, topo->tris, 3, F, g, cnt4, fill4, as<int64_t>(ctx->coff_t), s), "triangle cells");
+    CK(launch_cell_count(ctx, x, topo->edges, 2, E, g, cnt4 + ncell, fill4 + ncell, as<int64_t>(ctx->coff_e), s),
        "edge cells");
-    CK(hipMemcpyAsync(&nent, as<int64_t>(ctx->coff_e) + ncell, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
+    CK(hipMemsetAsync(cnt4 + 2 * ncell, 0, sizeof(int32_t) * 2 * (size_t)ncell, s), "clear");
+    CK(hipMemsetAsync(fill4 + 2 * ncell, 0, sizeof(int32_t) * 2 * (size_t)ncell, s), "clear");
+    for (int k = 0; k < 2; ++k) {
+        int32_t* span = as<int32_t>(ctx->qcnt);
+        CK(launch_qcells_count(k, x, Q[k], k ? ctx->crec_e.p : nullptr, g, dhat, span, cnt4 + (2 + k) * ncell, s),
+           "query cells");
+        CK((exclusive_scan<int32_t, int64_t>(cnt4 + (2 + k) * ncell, ncell, as<int64_t>(*qtoff[k]), ctx, s)), "scan");
+        CK((exclusive_scan<int32_t, int64_t>(span, Q[k], as<int64_t>(*qeoff[k]), ctx, s)), "scan");
+    }
+    int64_t tot[4];  // triangle entries, edge entries, point visits, edge visits
+    CK(hipMemcpyAsync(&tot[0], as<int64_t>(ctx->coff_t) + ncell, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
+    CK(hipMemcpyAsync(&tot[1], as<int64_t>(ctx->coff_e) + ncell, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
+    CK(hipMemcpyAsync(&tot[2], as<int64_t>(ctx->qoff_p) + V, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
+    CK(hipMemcpyAsync(&tot[3], as<int64_t>(ctx->qoff_e) + E, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
     CK(hipStreamSynchronize(s), "stream synchronize");
-    CK(ensure(ctx->cent_e, sizeof(int32_t) * (size_t)(nent + 1)), "alloc candidates");
-    CK(launch_cell_fill(x, topo->edges, 2, E, g, as<int32_t>(ctx->cfill), as<int64_t>(ctx->coff_e),
-                        as<int32_t>(ctx->cent_e), s),
-       "edge cells");
-    CK(launch_cand_query(1, false, x, E, topo->vobj, ctx->crec_e.p, ctx->crec_e.p, g, dhat, as<int64_t>(ctx->coff_e),
-                         as<int32_t>(ctx->cent_e), as<int32_t>(ctx->qcnt), nullptr, nullptr, s),
-       "edge-edge count");
-    CK((exclusive_scan<int32_t, int64_t>(as<int32_t>(ctx->qcnt), E, as<int64_t>(ctx->qoff_e), ctx, s)), "scan");
+
+    // fills, then per query and cell visited: candidate counts, offsets
+    const int32_t* tp[2] = {topo->tris, topo->edges};
+    CK(ensure(ctx->craw, sizeof(int32_t) * (size_t)(std::max(tot[0], tot[1]) + 1)), "alloc candidates");
+    for (int k = 0; k < 2; ++k) {
+        CK(ensure(*tent[k], sizeof(int32_t) * (size_t)(tot[k] + 1)), "alloc candidates");
+        CK(ensure(*qent[k], sizeof(int32_t) * (size_t)(tot[2 + k] + 1)), "alloc candidates");
+        CK(ensure(*ecnt[k], sizeof(int32_t) * (size_t)(tot[2 + k] + 1)), "alloc candidates");
+        CK(ensure(*eoff[k], sizeof(int64_t) * (size_t)(tot[2 + k] + 1)), "alloc candidates");
+        CK(launch_cell_fill(x, tp[k], 3 - k, k ? E : F, g, fill4 + k * ncell, as<int64_t>(*toff[k]),
+                            as<int32_t>(ctx->craw), as<int32_t>(*tent[k]), s),
+           "primitive cells");
+        CK(launch_qcells_fill(k, x, Q[k], k ? ctx->crec_e.p : nullptr, g, dhat, as<int64_t>(*qtoff[k]),
+                              fill4 + (2 + k) * ncell, as<int32_t>(*qent[k]), s),
+           "query cells");
+    }
+    for (int k = 0; k < 2; ++k) {
+        CK(launch_cell_pairs(k, false, x, topo->vobj, k ? ctx->crec_e.p : nullptr, trec[k]->p, g, dhat,
+                             as<int64_t>(*qtoff[k]), as<int32_t>(*qent[k]), as<int64_t>(*qeoff[k]),
+                             as<int64_t>(*toff[k]), as<int32_t>(*tent[k]), as<int32_t>(*ecnt[k]), nullptr, nullptr, s),
+           k ? "edge-edge count" : "point-triangle count");
+        CK((exclusive_scan<int32_t, int64_t>(as<int32_t>(*ecnt[k]), tot[2 + k], as<int64_t>(*eoff[k]), ctx, s)),
+           "scan");
+    }
     int64_t npt = 0, nee = 0;
-    CK(hipMemcpyAsync(&npt, as<int64_t>(ctx->qoff_p) + V, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
-    CK(hipMemcpyAsync(&nee, as<int64_t>(ctx->qoff_e) + E, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
+    CK(hipMemcpyAsync(&npt, as<int64_t>(ctx->eoff_p) + tot[2], sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
+    CK(hipMemcpyAsync(&nee, as<int64_t>(ctx->eoff_e) + tot[3], sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
     CK(hipStreamSynchronize(s), "stream synchronize");
     *count = npt + nee;
     if (!tuples) return GIPC_OK;
     if (cap < *count)
         return fail(ctx, GIPC_ERR_WORKSPACE, "cap = %lld is below the %lld candidates", (long long)cap,
                     (long long)*count);
-    CK(launch_cand_query(0, true, x, V, topo->vobj, nullptr, ctx->crec_t.p, g, dhat, as<int64_t>(ctx->coff_t),
-                         as<int32_t>(ctx->cent_t), nullptr, as<int64_t>(ctx->qoff_p), tuples, s),
-       "point-triangle emit");
-    CK(launch_cand_query(1, true, x, E, topo->vobj, ctx->crec_e.p, ctx->crec_e.p, g, dhat, as<int64_t>(ctx->coff_e),
-                         as<int32_t>(ctx->cent_e), nullptr, as<int64_t>(ctx->qoff_e), tuples + 4 * npt, s),
-       "edge-edge emit");
+    for (int k = 0; k < 2; ++k) {
+        CK(launch_cell_pairs(k, true, x, topo->vobj, k ? ctx->crec_e.p : nullptr, trec[k]->p, g, dhat,
+                             as<int64_t>(*qtoff[k]), as<int32_t>(*qent[k]), as<int64_t>(*qeoff[k]),
+                             as<int64_t>(*toff[k]), as<int32_t>(*tent[k]), nullptr, as<int64_t>(*eoff[k]),
+                             tuples + (k ? 4 * npt : 0), s),
+           k ? "edge-edge emit" : "point-triangle emit");
+    }
     CK(hipStreamSynchronize(s), "stream synchronize");
     return GIPC_OK;
 }

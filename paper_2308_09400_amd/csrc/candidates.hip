@@ -66,6 +66,24 @@ __device__ __forceinline__ bool overlap(const Box& a, double dhat, const Box& b)
              a.lo.z - dhat > b.hi.z || b.lo.z > a.hi.z + dhat);
 }
 
+// The item of a lane, -1 past the end.  SPREAD = false: consecutive lanes,
+// consecutive items.  SPREAD = true: a wave's lanes take items n/64 apart
+// (item = lane * waves + wave), so that a wave's per-cell atomics go to
+// cells far apart instead of the same few; measured faster for the point
+// queries only (a point's few cells are shared by all its neighbours).
+template <bool SPREAD>
+__device__ __forceinline__ int64_t item_of(int64_t n) {
+    if (!SPREAD) {
+        const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+        return i < n ? i : -1;
+    }
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t nw = (n + 63) / 64;
+    if ((i >> 6) >= nw) return -1;
+    const int64_t k = (i & 63) * nw + (i >> 6);
+    return k < n ? k : -1;
+}
+
 // per block: min x,y,z, max x,y,z of the positions, largest primitive
 // extent along x, y, z
 __global__ void __launch_bounds__(kBlock) k_cand_bounds(const double* __restrict__ X, int32_t V,
@@ -128,8 +146,8 @@ template <int NPER>
 __global__ void __launch_bounds__(kBlock) k_cell_count_prims(const double* __restrict__ X,
                                                              const int32_t* __restrict__ prims, int64_t n, Grid g,
                                                              int32_t* __restrict__ count) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
+    const int64_t i = item_of<false>(n);
+    if (i < 0) return;
     const Box b = prim_box(X, prims + NPER * i, NPER);
     int lo[3], hi[3];
     for (int d = 0; d < 3; ++d) {
@@ -146,8 +164,8 @@ __global__ void __launch_bounds__(kBlock) k_cell_fill_prims(const double* __rest
                                                             const int32_t* __restrict__ prims, int64_t n, Grid g,
                                                             const int64_t* __restrict__ off,
                                                             int32_t* __restrict__ fill, int32_t* __restrict__ ent) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
+    const int64_t i = item_of<false>(n);
+    if (i < 0) return;
     const Box b = prim_box(X, prims + NPER * i, NPER);
     int lo[3], hi[3];
     for (int d = 0; d < 3; ++d) {
@@ -179,38 +197,37 @@ __global__ void __launch_bounds__(kBlock) k_prim_records(const double* __restric
     rec[i] = r;
 }
 
-// each cell's list in increasing primitive id (insertion sort: lists are short)
+// each cell's list in increasing primitive id, one wave per cell: an entry's
+// place is the number of entries of the cell below it (the ids of a cell
+// are distinct), counted against the others handed over by lane reads;
+// raw -> ent
 __global__ void __launch_bounds__(kBlock) k_cell_sort(int64_t ncell, const int64_t* __restrict__ off,
+                                                      const int32_t* __restrict__ raw,
                                                       int32_t* __restrict__ ent) {
-    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t c =
+        (int64_t)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (c >= ncell) return;
-    const int64_t b = off[c], e = off[c + 1];
-    for (int64_t i = b + 1; i < e; ++i) {
-        const int32_t v = ent[i];
-        int64_t j = i - 1;
-        while (j >= b && ent[j] > v) {
-            ent[j + 1] = ent[j];
-            --j;
+    const int64_t b = off[c], n = off[c + 1] - b;
+    for (int64_t c0 = 0; c0 < n; c0 += 64) {
+        const bool mine_ok = c0 + lane < n;
+        const int32_t mine = mine_ok ? raw[b + c0 + lane] : 0;
+        int64_t rank = 0;
+        for (int64_t c1 = 0; c1 < n; c1 += 64) {
+            const int32_t other = c1 + lane < n ? raw[b + c1 + lane] : 0;
+            const int m = (int)(n - c1 < 64 ? n - c1 : 64);
+            for (int k = 0; k < m; ++k) rank += __builtin_amdgcn_readlane(other, k) < mine;
         }
-        ent[j + 1] = v;
+        if (mine_ok) ent[b + rank] = mine;
     }
 }
 
-// queries: KIND 0 = points against triangles, 1 = edges against edges of
-// larger index; EMIT = 0 counts per query, 1 writes at out + off[q].
-// Candidate primitives are read from their 64-byte records.
-template <int KIND, bool EMIT>
-__global__ void __launch_bounds__(kBlock) k_cand_query(const double* __restrict__ X, int64_t nq,
-                                                       const int32_t* __restrict__ vobj,
-                                                       const PrimRec* __restrict__ qrec,
-                                                       const PrimRec* __restrict__ trec, Grid g, double dhat,
-                                                       const int64_t* __restrict__ coff,
-                                                       const int32_t* __restrict__ cent, int32_t* __restrict__ cnt,
-                                                       const int64_t* __restrict__ qoff, int4* __restrict__ out) {
-    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (q >= nq) return;
-    Box qb;
-    int32_t q0, q1, qo;
+// The queries' side, one record per query primitive: KIND 0 = points (their
+// position, a zero-size box), 1 = edges (their 64-byte record).
+template <int KIND>
+__device__ __forceinline__ void query_of(int64_t q, const double* __restrict__ X, const int32_t* __restrict__ vobj,
+                                         const PrimRec* __restrict__ qrec, Box& qb, int32_t& q0, int32_t& q1,
+                                         int32_t& qo) {
     if (KIND == 0) {
         qb.lo = qb.hi = ld3(X, (int)q);
         q0 = q1 = (int32_t)q;
@@ -221,53 +238,178 @@ __global__ void __launch_bounds__(kBlock) k_cand_query(const double* __restrict_
         qb.hi = mk(r.hi[0], r.hi[1], r.hi[2]);
         q0 = r.v[0]; q1 = r.v[1]; qo = r.obj;
     }
-    int lo[3], hi[3];
+}
+
+// the cells covered by a query's box inflated by dhat
+__device__ __forceinline__ void query_cells(const Box& qb, const Grid& g, double dhat, int lo[3], int hi[3]) {
     for (int d = 0; d < 3; ++d) {
         lo[d] = cell_of(get(qb.lo, d) - dhat, g.org[d], g.h[d], g.n[d]);
         hi[d] = cell_of(get(qb.hi, d) + dhat, g.org[d], g.h[d], g.n[d]);
     }
-    int64_t w = EMIT ? qoff[q] : 0;
-    int32_t found = 0;
+}
+
+// query table, counting: span[q] = cells the query covers, count[cell] +=
+// queries covering the cell
+template <int KIND>
+__global__ void __launch_bounds__(kBlock) k_qcells_count(const double* __restrict__ X, int64_t nq,
+                                                         const PrimRec* __restrict__ qrec, Grid g, double dhat,
+                                                         int32_t* __restrict__ span, int32_t* __restrict__ count) {
+    const int64_t q = item_of<KIND == 0>(nq);
+    if (q < 0) return;
+    Box qb;
+    int32_t q0, q1, qo;
+    query_of<KIND>(q, X, nullptr, qrec, qb, q0, q1, qo);
+    int lo[3], hi[3];
+    query_cells(qb, g, dhat, lo, hi);
+    span[q] = (hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1);
+    for (int a = lo[0]; a <= hi[0]; ++a)
+        for (int c = lo[1]; c <= hi[1]; ++c)
+            for (int e = lo[2]; e <= hi[2]; ++e) atomicAdd(&count[((int64_t)a * g.n[1] + c) * g.n[2] + e], 1);
+}
+
+// query table, filling: the queries covering each cell, in no particular
+// order (the output positions come from the query and the cell, not from
+// this order)
+template <int KIND>
+__global__ void __launch_bounds__(kBlock) k_qcells_fill(const double* __restrict__ X, int64_t nq,
+                                                        const PrimRec* __restrict__ qrec, Grid g, double dhat,
+                                                        const int64_t* __restrict__ off, int32_t* __restrict__ fill,
+                                                        int32_t* __restrict__ ent) {
+    const int64_t q = item_of<KIND == 0>(nq);
+    if (q < 0) return;
+    Box qb;
+    int32_t q0, q1, qo;
+    query_of<KIND>(q, X, nullptr, qrec, qb, q0, q1, qo);
+    int lo[3], hi[3];
+    query_cells(qb, g, dhat, lo, hi);
     for (int a = lo[0]; a <= hi[0]; ++a)
         for (int c = lo[1]; c <= hi[1]; ++c)
             for (int e = lo[2]; e <= hi[2]; ++e) {
                 const int64_t cell = ((int64_t)a * g.n[1] + c) * g.n[2] + e;
-                const int cc[3] = {a, c, e};
-                int64_t t = coff[cell];
-                const int64_t t1 = coff[cell + 1];
-                if (KIND == 1) {
-                    // entries are sorted by edge id: skip those not above q
-                    while (t < t1 && (int64_t)cent[t] <= q) ++t;
+                ent[off[cell] + atomicAdd(&fill[cell], 1)] = (int32_t)q;
+            }
+}
+
+// a lane's double, read by every lane (k wave-uniform)
+__device__ __forceinline__ double read_lane(double v, int k) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// One wave per cell: its lanes take the queries covering the cell, 64 at a
+// time, and the cell's primitive list 64 records at a time, one record per
+// lane; each record is then handed to every lane from the lane holding it
+// (a lane read, no memory access), so the records are read once per 64
+// queries.  The query q's visit of the cell is entry e = qeoff[q] + j, j the
+// cell's rank in the query's walk (x slowest, z fastest): EMIT = false
+// stores the entry's candidate count in cnt[e], EMIT = true writes its
+// candidates at out + eoff[e], in list order.  KIND 1 takes only edges of
+// larger index than the query.
+//
+// The cell reporting a pair holds the lower corner of the overlap, whose
+// coordinate along d is the larger of the inflated query's and the
+// primitive's lower bounds; the cell index is monotonic in the coordinate,
+// so that cell is, per axis, the larger of the two lower bounds' cells, and
+// both are at most the current cell's (both boxes cover it): the pair is
+// this cell's when, along every axis, one of the two lower cells is this
+// cell's.
+template <int KIND, bool EMIT>
+__global__ void __launch_bounds__(kBlock) k_cell_pairs(const double* __restrict__ X,
+                                                       const int32_t* __restrict__ vobj,
+                                                       const PrimRec* __restrict__ qrec,
+                                                       const PrimRec* __restrict__ trec, Grid g, double dhat,
+                                                       int64_t ncell, const int64_t* __restrict__ qtoff,
+                                                       const int32_t* __restrict__ qent,
+                                                       const int64_t* __restrict__ qeoff,
+                                                       const int64_t* __restrict__ coff,
+                                                       const int32_t* __restrict__ cent, int32_t* __restrict__ cnt,
+                                                       const int64_t* __restrict__ eoff, int4* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t cell =
+        (int64_t)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (cell >= ncell) return;
+    const int64_t qa = qtoff[cell], qz = qtoff[cell + 1];
+    const int64_t ta = coff[cell], tz = coff[cell + 1];
+    if (qa == qz || (EMIT && ta == tz)) return;
+    const int cc[3] = {(int)(cell / ((int64_t)g.n[1] * g.n[2])), (int)((cell / g.n[2]) % g.n[1]),
+                       (int)(cell % g.n[2])};
+    for (int64_t qb0 = qa; qb0 < qz; qb0 += 64) {
+        const int64_t i = qb0 + lane;
+        const bool act = i < qz;
+        const int64_t q = qent[act ? i : qa];
+        Box qb;
+        int32_t q0, q1, qo;
+        query_of<KIND>(q, X, vobj, qrec, qb, q0, q1, qo);
+        int lo[3], hi[3];
+        query_cells(qb, g, dhat, lo, hi);
+        const int64_t e = qeoff[q] + ((int64_t)(cc[0] - lo[0]) * (hi[1] - lo[1] + 1) + (cc[1] - lo[1])) *
+                                         (hi[2] - lo[2] + 1) + (cc[2] - lo[2]);
+        const bool own0 = lo[0] == cc[0], own1 = lo[1] == cc[1], own2 = lo[2] == cc[2];
+        const double qlx = qb.lo.x - dhat, qly = qb.lo.y - dhat, qlz = qb.lo.z - dhat;
+        const double qhx = qb.hi.x + dhat, qhy = qb.hi.y + dhat, qhz = qb.hi.z + dhat;
+        int64_t w = 0, wz = 0;
+        if (EMIT) {
+            w = act ? eoff[e] : 0;
+            wz = act ? eoff[e + 1] : 0;
+            if (__ballot(w < wz) == 0) continue;
+        }
+        int64_t t0 = ta;
+        if (KIND == 1) {
+            // the list is in increasing edge id: skip what no lane takes
+            int64_t qmin = act ? q : INT64_MAX;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const int64_t v = __shfl_xor(qmin, o, 64);
+                qmin = v < qmin ? v : qmin;
+            }
+            qmin = __builtin_amdgcn_readfirstlane((int)qmin);
+            while (t0 < tz && (int64_t)cent[t0] <= qmin) ++t0;
+        }
+        int32_t found = 0;
+        for (int64_t tb0 = t0; tb0 < tz; tb0 += 64) {
+            // this lane's record of the chunk
+            const int64_t j = tb0 + lane;
+            const int32_t id = cent[j < tz ? j : tb0];
+            const PrimRec r = trec[id];
+            int tsel = 0;
+            for (int d = 0; d < 3; ++d)
+                tsel |= (cell_of(r.lo[d], g.org[d], g.h[d], g.n[d]) == cc[d]) << d;
+            const int nk = (int)(tz - tb0 < 64 ? tz - tb0 : 64);
+            for (int k = 0; k < nk; ++k) {
+                const double lx = read_lane(r.lo[0], k), ly = read_lane(r.lo[1], k), lz = read_lane(r.lo[2], k);
+                const double hx = read_lane(r.hi[0], k), hy = read_lane(r.hi[1], k), hz = read_lane(r.hi[2], k);
+                const int32_t v0 = __builtin_amdgcn_readlane(r.v[0], k), v1 = __builtin_amdgcn_readlane(r.v[1], k);
+                const int32_t v2 = __builtin_amdgcn_readlane(r.v[2], k), ob = __builtin_amdgcn_readlane(r.obj, k);
+                const int ts = __builtin_amdgcn_readlane(tsel, k);
+                bool hit = act && ob != qo;
+                if (KIND == 0) {
+                    hit = hit && v0 != q0 && v1 != q0 && v2 != q0;
+                } else {
+                    const int32_t tid = __builtin_amdgcn_readlane(id, k);
+                    hit = hit && (int64_t)tid > q && v0 != q0 && v0 != q1 && v1 != q0 && v1 != q1;
                 }
-                for (; t < t1; ++t) {
-                    const PrimRec r = trec[cent[t]];
-                    if (r.obj == qo) continue;
-                    if (KIND == 0) {
-                        if (r.v[0] == q0 || r.v[1] == q0 || r.v[2] == q0) continue;
-                    } else {
-                        if (r.v[0] == q0 || r.v[0] == q1 || r.v[1] == q0 || r.v[1] == q1) continue;
-                    }
-                    const Box tb{mk(r.lo[0], r.lo[1], r.lo[2]), mk(r.hi[0], r.hi[1], r.hi[2])};
-                    if (!overlap(qb, dhat, tb)) continue;
-                    // the cell of the overlap's lower corner reports the pair
-                    bool own = true;
-                    for (int d = 0; d < 3 && own; ++d) {
-                        const double m = fmax(get(qb.lo, d) - dhat, get(tb.lo, d));
-                        own = cell_of(m, g.org[d], g.h[d], g.n[d]) == cc[d];
-                    }
-                    if (!own) continue;
-                    if (EMIT) {
-                        out[w++] = KIND == 0 ? make_int4(-(q0 + 1), r.v[0], r.v[1], r.v[2])
-                                             : make_int4(q0, q1, r.v[0], r.v[1]);
-                    } else {
-                        ++found;
-                    }
+                hit = hit && !(qlx > hx || lx > qhx || qly > hy || ly > qhy || qlz > hz || lz > qhz);
+                hit = hit && (own0 || (ts & 1)) && (own1 || (ts & 2)) && (own2 || (ts & 4));
+                if (hit) {
+                    if (EMIT) out[w++] = KIND == 0 ? make_int4(-(q0 + 1), v0, v1, v2) : make_int4(q0, q1, v0, v1);
+                    else ++found;
                 }
             }
-    if (!EMIT) cnt[q] = found;
+            if (EMIT && __ballot(w < wz) == 0) break;
+        }
+        if (!EMIT && act) cnt[e] = found;
+    }
 }
 
 unsigned grid1(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+Grid to_grid(const CandGrid& cg) {
+    Grid g;
+    for (int d = 0; d < 3; ++d) { g.org[d] = cg.org[d]; g.n[d] = cg.n[d]; g.h[d] = cg.h[d]; }
+    return g;
+}
 
 }  // namespace
 
@@ -293,8 +435,7 @@ hipError_t launch_cand_check(int32_t V, const int32_t* vobj, const int32_t* tris
 
 hipError_t launch_cell_count(gipc_ctx* ctx, const double* x, const int32_t* prims, int nper, int64_t n,
                              const CandGrid& cg, int32_t* count, int32_t* fill, int64_t* off, hipStream_t s) {
-    Grid g;
-    for (int d = 0; d < 3; ++d) { g.org[d] = cg.org[d]; g.n[d] = cg.n[d]; g.h[d] = cg.h[d]; }
+    const Grid g = to_grid(cg);
     const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
     hipError_t e;
     if ((e = hipMemsetAsync(count, 0, sizeof(int32_t) * ncell, s)) != hipSuccess) return e;
@@ -308,17 +449,16 @@ hipError_t launch_cell_count(gipc_ctx* ctx, const double* x, const int32_t* prim
 }
 
 hipError_t launch_cell_fill(const double* x, const int32_t* prims, int nper, int64_t n, const CandGrid& cg,
-                            int32_t* fill, const int64_t* off, int32_t* ent, hipStream_t s) {
-    Grid g;
-    for (int d = 0; d < 3; ++d) { g.org[d] = cg.org[d]; g.n[d] = cg.n[d]; g.h[d] = cg.h[d]; }
+                            int32_t* fill, const int64_t* off, int32_t* raw, int32_t* ent, hipStream_t s) {
+    const Grid g = to_grid(cg);
     const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
     if (n > 0) {
-        if (nper == 3) k_cell_fill_prims<3><<<grid1(n), kBlock, 0, s>>>(x, prims, n, g, off, fill, ent);
-        else k_cell_fill_prims<2><<<grid1(n), kBlock, 0, s>>>(x, prims, n, g, off, fill, ent);
+        if (nper == 3) k_cell_fill_prims<3><<<grid1(n), kBlock, 0, s>>>(x, prims, n, g, off, fill, raw);
+        else k_cell_fill_prims<2><<<grid1(n), kBlock, 0, s>>>(x, prims, n, g, off, fill, raw);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    k_cell_sort<<<grid1(ncell), kBlock, 0, s>>>(ncell, off, const_cast<int32_t*>(ent));
+    k_cell_sort<<<(unsigned)((ncell + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0, s>>>(ncell, off, raw, ent);
     return hipGetLastError();
 }
 
@@ -332,23 +472,46 @@ hipError_t launch_prim_records(const double* x, const int32_t* prims, int nper, 
     return hipGetLastError();
 }
 
-hipError_t launch_cand_query(int kind, bool emit, const double* x, int64_t nq, const int32_t* vobj,
-                             const void* qrec, const void* trec, const CandGrid& cg, double dhat,
-                             const int64_t* coff, const int32_t* cent, int32_t* cnt, const int64_t* qoff,
-                             int32_t* out, hipStream_t s) {
+hipError_t launch_qcells_count(int kind, const double* x, int64_t nq, const void* qrec, const CandGrid& cg,
+                               double dhat, int32_t* span, int32_t* count, hipStream_t s) {
     if (nq == 0) return hipSuccess;
-    Grid g;
-    for (int d = 0; d < 3; ++d) { g.org[d] = cg.org[d]; g.n[d] = cg.n[d]; g.h[d] = cg.h[d]; }
+    const Grid g = to_grid(cg);
+    const PrimRec* qr = static_cast<const PrimRec*>(qrec);
+    if (kind == 0) k_qcells_count<0><<<grid1(nq), kBlock, 0, s>>>(x, nq, qr, g, dhat, span, count);
+    else k_qcells_count<1><<<grid1(nq), kBlock, 0, s>>>(x, nq, qr, g, dhat, span, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_qcells_fill(int kind, const double* x, int64_t nq, const void* qrec, const CandGrid& cg,
+                              double dhat, const int64_t* off, int32_t* fill, int32_t* ent, hipStream_t s) {
+    if (nq == 0) return hipSuccess;
+    const Grid g = to_grid(cg);
+    const PrimRec* qr = static_cast<const PrimRec*>(qrec);
+    if (kind == 0) k_qcells_fill<0><<<grid1(nq), kBlock, 0, s>>>(x, nq, qr, g, dhat, off, fill, ent);
+    else k_qcells_fill<1><<<grid1(nq), kBlock, 0, s>>>(x, nq, qr, g, dhat, off, fill, ent);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_pairs(int kind, bool emit, const double* x, const int32_t* vobj, const void* qrec,
+                             const void* trec, const CandGrid& cg, double dhat, const int64_t* qtoff,
+                             const int32_t* qent, const int64_t* qeoff, const int64_t* coff, const int32_t* cent,
+                             int32_t* cnt, const int64_t* eoff, int32_t* out, hipStream_t s) {
+    const Grid g = to_grid(cg);
+    const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    const unsigned nb = (unsigned)((ncell + kBlock / 64 - 1) / (kBlock / 64));
     int4* o = reinterpret_cast<int4*>(out);
     const PrimRec* qr = static_cast<const PrimRec*>(qrec);
     const PrimRec* tr = static_cast<const PrimRec*>(trec);
+#define GIPC_CELL_PAIRS(K, EM) \
+    k_cell_pairs<K, EM><<<nb, kBlock, 0, s>>>(x, vobj, qr, tr, g, dhat, ncell, qtoff, qent, qeoff, coff, cent, cnt, eoff, o)
     if (kind == 0) {
-        if (emit) k_cand_query<0, true><<<grid1(nq), kBlock, 0, s>>>(x, nq, vobj, qr, tr, g, dhat, coff, cent, cnt, qoff, o);
-        else k_cand_query<0, false><<<grid1(nq), kBlock, 0, s>>>(x, nq, vobj, qr, tr, g, dhat, coff, cent, cnt, qoff, o);
+        if (emit) GIPC_CELL_PAIRS(0, true);
+        else GIPC_CELL_PAIRS(0, false);
     } else {
-        if (emit) k_cand_query<1, true><<<grid1(nq), kBlock, 0, s>>>(x, nq, vobj, qr, tr, g, dhat, coff, cent, cnt, qoff, o);
-        else k_cand_query<1, false><<<grid1(nq), kBlock, 0, s>>>(x, nq, vobj, qr, tr, g, dhat, coff, cent, cnt, qoff, o);
+        if (emit) GIPC_CELL_PAIRS(1, true);
+        else GIPC_CELL_PAIRS(1, false);
     }
+#undef GIPC_CELL_PAIRS
     return hipGetLastError();
 }
 

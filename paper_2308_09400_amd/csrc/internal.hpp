@@ -167,6 +167,7 @@ struct gipc_ctx {
     // contact candidates: bounds partials, counters, cell tables (points
     // against triangles, edges against edges), per-query counts and offsets
     gipc::DevBuf cpart, ccnt, ccount, cfill, coff_t, cent_t, coff_e, cent_e, qcnt, qoff_p, qoff_e, crec_t, crec_e;
+    gipc::DevBuf qtoff_p, qtoff_e, qent_p, qent_e, ecnt_p, ecnt_e, eoff_p, eoff_e, craw;
     uint64_t fric_gen = 0;
     double fric_sv = 0.0;
     uint64_t eval_gen = 0;   // bumped by every eval
@@ -342,21 +343,31 @@ hipError_t launch_cand_bounds(const double* x, int32_t V, const int32_t* tris, i
 hipError_t launch_cand_check(int32_t V, const int32_t* vobj, const int32_t* tris, int64_t F, const int32_t* edges,
                              int64_t E, int64_t* counters, hipStream_t s);
 // cell table of n primitives of nper vertices: counts and offsets off
-// [ncell+1] (off[ncell] = entries), then the entries ent [off[ncell]]
+// [ncell+1] (off[ncell] = entries), then the entries ent [off[ncell]],
+// each cell's in increasing id (raw [off[ncell]]: unsorted, scratch)
 hipError_t launch_cell_count(gipc_ctx* ctx, const double* x, const int32_t* prims, int nper, int64_t n,
                              const CandGrid& g, int32_t* count, int32_t* fill, int64_t* off, hipStream_t s);
 hipError_t launch_cell_fill(const double* x, const int32_t* prims, int nper, int64_t n, const CandGrid& g,
-                            int32_t* fill, const int64_t* off, int32_t* ent, hipStream_t s);
+                            int32_t* fill, const int64_t* off, int32_t* raw, int32_t* ent, hipStream_t s);
 // 64-byte query records of n primitives (box, vertex ids, object)
 constexpr int kPrimRecBytes = 64;
 hipError_t launch_prim_records(const double* x, const int32_t* prims, int nper, int64_t n, const int32_t* vobj,
                                void* rec, hipStream_t s);
-// kind 0: points vs triangle records, 1: edge records vs edge records;
-// counts into cnt, or emits int32 [4] tuples at out + 4 qoff[q]
-hipError_t launch_cand_query(int kind, bool emit, const double* x, int64_t nq, const int32_t* vobj,
-                             const void* qrec, const void* trec, const CandGrid& g, double dhat,
-                             const int64_t* coff, const int32_t* cent, int32_t* cnt, const int64_t* qoff,
-                             int32_t* out, hipStream_t s);
+// query tables, kind 0: points, 1: edge records (qrec): span[q] = cells
+// the query's box inflated by dhat covers, count[cell] += queries covering
+// it; then the queries of each cell at ent + off[cell]
+hipError_t launch_qcells_count(int kind, const double* x, int64_t nq, const void* qrec, const CandGrid& g,
+                               double dhat, int32_t* span, int32_t* count, hipStream_t s);
+hipError_t launch_qcells_fill(int kind, const double* x, int64_t nq, const void* qrec, const CandGrid& g,
+                              double dhat, const int64_t* off, int32_t* fill, int32_t* ent, hipStream_t s);
+// per cell, its queries (qtoff/qent) against its primitives (coff/cent,
+// records trec): kind 0 points vs triangles, 1 edges vs edges of larger
+// index; per visit e = qeoff[q] + rank of the cell in q's walk, counts into
+// cnt[e] (emit = false) or int32 [4] tuples at out + 4 eoff[e] (emit = true)
+hipError_t launch_cell_pairs(int kind, bool emit, const double* x, const int32_t* vobj, const void* qrec,
+                             const void* trec, const CandGrid& g, double dhat, const int64_t* qtoff,
+                             const int32_t* qent, const int64_t* qeoff, const int64_t* coff, const int32_t* cent,
+                             int32_t* cnt, const int64_t* eoff, int32_t* out, hipStream_t s);
 
 // ---- accd.hip
 // additive CCD of P tuples moving by disp; counters [6] (see k_accd_reset)

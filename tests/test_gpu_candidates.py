@@ -3,7 +3,10 @@
 * small seeded two-sheet scenes (several sizes and dhat): the candidate set
   equals the brute-force set exactly (integer work: bit-exact), in the
   documented order (point-triangle by point, then edge-edge by first edge);
-  two calls give the same array;
+  two calls give the same array; the largest puts hundreds of primitives
+  and queries in a cell (several 64-wide chunks per cell);
+* a context's capacity hint: calls whose count grows past it, then falls
+  back under it, each give the brute-force set;
 * the two-sheet 16 x 16 and ten-sheet 256 x 256 scenes: the set equals the
   scenes' own grid generator's (pinned against brute force on the CPU);
 * the list fed to the hot path gives the same active pairs and energy as
@@ -43,7 +46,7 @@ def _set(t):
     return set(map(tuple, np.asarray(t).reshape(-1, 4).tolist()))
 
 
-@pytest.mark.parametrize("n,dhat,seed", [(6, 0.15, 3), (9, 0.3, 7), (12, 0.05, 1), (8, 0.0, 2)])
+@pytest.mark.parametrize("n,dhat,seed", [(6, 0.15, 3), (9, 0.3, 7), (12, 0.05, 1), (8, 0.0, 2), (24, 0.3, 5)])
 def test_small_scenes_against_brute_force(gp, n, dhat, seed):
     s = scenes.two_sheets(n=n, dhat=max(dhat, 1e-3), kappa=10.0, seed=seed, offset=0.5, jitter=0.3)
     x, vobj, tris, edges = _dev(s)
@@ -62,6 +65,22 @@ def test_small_scenes_against_brute_force(gp, n, dhat, seed):
     assert (np.diff(first) >= 0).all()
     c2 = gp.candidates(ctx, x, vobj, tris, edges, dhat).cpu().numpy()
     assert np.array_equal(c, c2)
+    ctx.close()
+
+
+def test_capacity_hint_across_calls(gp):
+    s = scenes.two_sheets(n=9, dhat=0.3, kappa=10.0, seed=7, offset=0.5, jitter=0.3)
+    x, vobj, tris, edges = _dev(s)
+    ctx = gp.Context()
+    got = []
+    for dhat in (0.02, 0.3, 0.02, 0.02):
+        c = gp.candidates(ctx, x, vobj, tris, edges, dhat).cpu().numpy()
+        ref = oracle.candidates(s.x, s.vobj, s.tris, s.edges, dhat)
+        assert len(c) == len(ref) and _set(c) == _set(ref), dhat
+        assert ctx._cand_cap >= len(c)
+        got.append(c)
+    assert len(got[1]) > 2 * len(got[0])  # the second call outgrew the hint
+    assert np.array_equal(got[0], got[2]) and np.array_equal(got[2], got[3])
     ctx.close()
 
 
