@@ -252,7 +252,7 @@ std::vector<DevBuf*> ctx_buffers(gipc_ctx* ctx) {
                       &ctx->contrib, &ctx->kcol, &ctx->kbeg, &ctx->ncols, &ctx->row_ptr, &ctx->col_idx, &ctx->cptr,
                       &ctx->slot_row, &ctx->diag_slot, &ctx->whead, &ctx->wrow, &ctx->maxbuf, &ctx->bigrows, &ctx->tslot, &ctx->incr, &ctx->order,
                       &ctx->obox, &ctx->ocell, &ctx->ohist, &ctx->ooff, &ctx->ofill, &ctx->rec_main, &ctx->rec_extra, &ctx->rec_a1, &ctx->ev,
-                      &ctx->epart, &ctx->mfg, &ctx->mfab, &ctx->flag, &ctx->ffr, &ctx->fev, &ctx->fpart, &ctx->cpart, &ctx->ccnt, &ctx->ccount, &ctx->cfill, &ctx->coff_t, &ctx->cent_t, &ctx->coff_e, &ctx->cent_e, &ctx->qcnt, &ctx->qoff_p, &ctx->qoff_e, &ctx->crec_t, &ctx->crec_e, &ctx->qtoff_p, &ctx->qtoff_e, &ctx->qent_p, &ctx->qent_e, &ctx->ecnt_p, &ctx->ecnt_e, &ctx->eoff_p, &ctx->eoff_e, &ctx->craw, &ctx->vscene, &ctx->pieces, &ctx->poff,
+                      &ctx->epart, &ctx->mfg, &ctx->mfab, &ctx->flag, &ctx->ffr, &ctx->fev, &ctx->fpart, &ctx->cpart, &ctx->ccnt, &ctx->ccount, &ctx->cfill, &ctx->coff_t, &ctx->cent_t, &ctx->coff_e, &ctx->cent_e, &ctx->qcnt, &ctx->qoff_p, &ctx->qoff_e, &ctx->crec_t, &ctx->crec_e, &ctx->qtoff_p, &ctx->qtoff_e, &ctx->qent_p, &ctx->qent_e, &ctx->ecnt_p, &ctx->ecnt_e, &ctx->eoff_p, &ctx->eoff_e, &ctx->craw, &ctx->bslot, &ctx->boff_p, &ctx->boff_e, &ctx->bal_p, &ctx->bal_e, &ctx->evis_p, &ctx->evis_e, &ctx->vscene, &ctx->pieces, &ctx->poff,
                       &ctx->r, &ctx->z, &ctx->p, &ctx->q, &ctx->p32, &ctx->minv, &ctx->part, &ctx->scal, &ctx->scan_tmp,
                       &ctx->scan_tmp2, &ctx->chk, &ctx->accd_cnt};
 }
@@ -968,11 +968,24 @@ gipc_status gipc_candidates(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_top
         CK((exclusive_scan<int32_t, int64_t>(cnt4 + (2 + k) * ncell, ncell, as<int64_t>(*qtoff[k]), ctx, s)), "scan");
         CK((exclusive_scan<int32_t, int64_t>(span, Q[k], as<int64_t>(*qeoff[k]), ctx, s)), "scan");
     }
-    int64_t tot[4];  // triangle entries, edge entries, point visits, edge visits
+    // hit-mask slots of each kind's pairs pass, per cell
+    DevBuf* boff[2] = {&ctx->boff_p, &ctx->boff_e};
+    DevBuf* bal[2] = {&ctx->bal_p, &ctx->bal_e};
+    DevBuf* evis[2] = {&ctx->evis_p, &ctx->evis_e};
+    CK(ensure(ctx->bslot, sizeof(int64_t) * (size_t)ncell), "alloc candidates");
+    for (int k = 0; k < 2; ++k) {
+        CK(ensure(*boff[k], sizeof(int64_t) * (size_t)(ncell + 1)), "alloc candidates");
+        CK(launch_cell_slots(g, as<int64_t>(*qtoff[k]), as<int64_t>(*toff[k]), as<int64_t>(ctx->bslot), s),
+           "mask slots");
+        CK((exclusive_scan<int64_t, int64_t>(as<int64_t>(ctx->bslot), ncell, as<int64_t>(*boff[k]), ctx, s)), "scan");
+    }
+    int64_t tot[6];  // triangle entries, edge entries, point visits, edge visits, mask slots (2)
     CK(hipMemcpyAsync(&tot[0], as<int64_t>(ctx->coff_t) + ncell, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
     CK(hipMemcpyAsync(&tot[1], as<int64_t>(ctx->coff_e) + ncell, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
     CK(hipMemcpyAsync(&tot[2], as<int64_t>(ctx->qoff_p) + V, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
     CK(hipMemcpyAsync(&tot[3], as<int64_t>(ctx->qoff_e) + E, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
+    CK(hipMemcpyAsync(&tot[4], as<int64_t>(ctx->boff_p) + ncell, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
+    CK(hipMemcpyAsync(&tot[5], as<int64_t>(ctx->boff_e) + ncell, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
     CK(hipStreamSynchronize(s), "stream synchronize");
 
     // fills, then per query and cell visited: candidate counts, offsets
@@ -983,6 +996,8 @@ gipc_status gipc_candidates(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_top
         CK(ensure(*qent[k], sizeof(int32_t) * (size_t)(tot[2 + k] + 1)), "alloc candidates");
         CK(ensure(*ecnt[k], sizeof(int32_t) * (size_t)(tot[2 + k] + 1)), "alloc candidates");
         CK(ensure(*eoff[k], sizeof(int64_t) * (size_t)(tot[2 + k] + 1)), "alloc candidates");
+        CK(ensure(*bal[k], sizeof(uint64_t) * (size_t)(tot[4 + k] + 1)), "alloc candidates");
+        CK(ensure(*evis[k], sizeof(int64_t) * (size_t)(tot[2 + k] + 1)), "alloc candidates");
         CK(launch_cell_fill(x, tp[k], 3 - k, k ? E : F, g, fill4 + k * ncell, as<int64_t>(*toff[k]),
                             as<int32_t>(ctx->craw), as<int32_t>(*tent[k]), s),
            "primitive cells");
@@ -993,7 +1008,8 @@ gipc_status gipc_candidates(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_top
     for (int k = 0; k < 2; ++k) {
         CK(launch_cell_pairs(k, false, x, topo->vobj, k ? ctx->crec_e.p : nullptr, trec[k]->p, g, dhat,
                              as<int64_t>(*qtoff[k]), as<int32_t>(*qent[k]), as<int64_t>(*qeoff[k]),
-                             as<int64_t>(*toff[k]), as<int32_t>(*tent[k]), as<int32_t>(*ecnt[k]), nullptr, nullptr, s),
+                             as<int64_t>(*toff[k]), as<int32_t>(*tent[k]), as<int32_t>(*ecnt[k]), nullptr,
+                             as<int64_t>(*boff[k]), as<uint64_t>(*bal[k]), as<int64_t>(*evis[k]), nullptr, s),
            k ? "edge-edge count" : "point-triangle count");
         CK((exclusive_scan<int32_t, int64_t>(as<int32_t>(*ecnt[k]), tot[2 + k], as<int64_t>(*eoff[k]), ctx, s)),
            "scan");
@@ -1011,6 +1027,7 @@ gipc_status gipc_candidates(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_top
         CK(launch_cell_pairs(k, true, x, topo->vobj, k ? ctx->crec_e.p : nullptr, trec[k]->p, g, dhat,
                              as<int64_t>(*qtoff[k]), as<int32_t>(*qent[k]), as<int64_t>(*qeoff[k]),
                              as<int64_t>(*toff[k]), as<int32_t>(*tent[k]), nullptr, as<int64_t>(*eoff[k]),
+                             as<int64_t>(*boff[k]), as<uint64_t>(*bal[k]), as<int64_t>(*evis[k]),
                              tuples + (k ? 4 * npt : 0), s),
            k ? "edge-edge emit" : "point-triangle emit");
     }

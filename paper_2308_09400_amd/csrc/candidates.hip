@@ -290,6 +290,13 @@ __global__ void __launch_bounds__(kBlock) k_qcells_fill(const double* __restrict
             }
 }
 
+// a lane's 64-bit value, read by every lane (k wave-uniform)
+__device__ __forceinline__ unsigned long long read_lane_u64(unsigned long long v, int k) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)v, k);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(v >> 32), k);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 // a lane's double, read by every lane (k wave-uniform)
 __device__ __forceinline__ double read_lane(double v, int k) {
     const long long b = __double_as_longlong(v);
@@ -306,7 +313,13 @@ __device__ __forceinline__ double read_lane(double v, int k) {
 // cell's rank in the query's walk (x slowest, z fastest): EMIT = false
 // stores the entry's candidate count in cnt[e], EMIT = true writes its
 // candidates at out + eoff[e], in list order.  KIND 1 takes only edges of
-// larger index than the query.
+// larger index than the query.  The counting pass also stores, per record
+// and chunk of queries, the 64-lane mask of the queries it pairs with
+// (bal, from boff[cell]); the emitting pass replays those masks instead of
+// testing again, reading only the records' vertex ids, and writes query by
+// query so that a store covers consecutive slots of one query.  The
+// counting pass also leaves each visit's entry e in evis (by position in
+// the cell's query list), so the emitting pass needs no query boxes.
 //
 // The cell reporting a pair holds the lower corner of the overlap, whose
 // coordinate along d is the larger of the inflated query's and the
@@ -316,7 +329,9 @@ __device__ __forceinline__ double read_lane(double v, int k) {
 // this cell's when, along every axis, one of the two lower cells is this
 // cell's.
 template <int KIND, bool EMIT>
-__global__ void __launch_bounds__(kBlock) k_cell_pairs(const double* __restrict__ X,
+// (seven waves per SIMD asked for: the compiler then keeps the counting
+// passes at 56 / 66 registers instead of 74 / 84, without spills)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) k_cell_pairs(const double* __restrict__ X,
                                                        const int32_t* __restrict__ vobj,
                                                        const PrimRec* __restrict__ qrec,
                                                        const PrimRec* __restrict__ trec, Grid g, double dhat,
@@ -325,7 +340,10 @@ __global__ void __launch_bounds__(kBlock) k_cell_pairs(const double* __restrict_
                                                        const int64_t* __restrict__ qeoff,
                                                        const int64_t* __restrict__ coff,
                                                        const int32_t* __restrict__ cent, int32_t* __restrict__ cnt,
-                                                       const int64_t* __restrict__ eoff, int4* __restrict__ out) {
+                                                       const int64_t* __restrict__ eoff,
+                                                       const int64_t* __restrict__ boff,
+                                                       unsigned long long* __restrict__ bal,
+                                                       int64_t* __restrict__ evis, int4* __restrict__ out) {
     const int lane = threadIdx.x & 63;
     const int64_t cell =
         (int64_t)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -339,22 +357,33 @@ __global__ void __launch_bounds__(kBlock) k_cell_pairs(const double* __restrict_
         const int64_t i = qb0 + lane;
         const bool act = i < qz;
         const int64_t q = qent[act ? i : qa];
-        Box qb;
-        int32_t q0, q1, qo;
-        query_of<KIND>(q, X, vobj, qrec, qb, q0, q1, qo);
-        int lo[3], hi[3];
-        query_cells(qb, g, dhat, lo, hi);
-        const int64_t e = qeoff[q] + ((int64_t)(cc[0] - lo[0]) * (hi[1] - lo[1] + 1) + (cc[1] - lo[1])) *
-                                         (hi[2] - lo[2] + 1) + (cc[2] - lo[2]);
-        const bool own0 = lo[0] == cc[0], own1 = lo[1] == cc[1], own2 = lo[2] == cc[2];
-        const double qlx = qb.lo.x - dhat, qly = qb.lo.y - dhat, qlz = qb.lo.z - dhat;
-        const double qhx = qb.hi.x + dhat, qhy = qb.hi.y + dhat, qhz = qb.hi.z + dhat;
-        int64_t w = 0, wz = 0;
+        Box qb{};
+        int32_t q0 = 0, q1 = 0, qo = 0;
+        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        int64_t e, w = 0, wz = 0;
         if (EMIT) {
+            // the counting pass left the visit's entry; only the query's ids
+            // are needed
+            e = act ? evis[i] : 0;
+            q0 = q1 = (int32_t)q;
+            if (KIND == 1) {
+                const int4 qv = *reinterpret_cast<const int4*>(&qrec[q].v[0]);
+                q0 = qv.x;
+                q1 = qv.y;
+            }
             w = act ? eoff[e] : 0;
             wz = act ? eoff[e + 1] : 0;
             if (__ballot(w < wz) == 0) continue;
+        } else {
+            query_of<KIND>(q, X, vobj, qrec, qb, q0, q1, qo);
+            query_cells(qb, g, dhat, lo, hi);
+            e = qeoff[q] + ((int64_t)(cc[0] - lo[0]) * (hi[1] - lo[1] + 1) + (cc[1] - lo[1])) *
+                               (hi[2] - lo[2] + 1) + (cc[2] - lo[2]);
+            if (act) evis[i] = e;
         }
+        const bool own0 = lo[0] == cc[0], own1 = lo[1] == cc[1], own2 = lo[2] == cc[2];
+        const double qlx = qb.lo.x - dhat, qly = qb.lo.y - dhat, qlz = qb.lo.z - dhat;
+        const double qhx = qb.hi.x + dhat, qhy = qb.hi.y + dhat, qhz = qb.hi.z + dhat;
         int64_t t0 = ta;
         if (KIND == 1) {
             // the list is in increasing edge id: skip what no lane takes
@@ -365,18 +394,53 @@ __global__ void __launch_bounds__(kBlock) k_cell_pairs(const double* __restrict_
                 qmin = v < qmin ? v : qmin;
             }
             qmin = __builtin_amdgcn_readfirstlane((int)qmin);
-            while (t0 < tz && (int64_t)cent[t0] <= qmin) ++t0;
+            // (64 entries a step: they form a prefix of each window)
+            for (;;) {
+                const int64_t j = t0 + lane;
+                const unsigned long long m = __ballot(j < tz && (int64_t)cent[j] <= qmin);
+                t0 += __popcll(m);
+                if (m != ~0ull) break;
+            }
         }
         int32_t found = 0;
+        // this chunk's hit masks: slot (chunk of queries, record) of the cell
+        const int64_t bslot = boff[cell] + ((qb0 - qa) >> 6) * (tz - ta);
         for (int64_t tb0 = t0; tb0 < tz; tb0 += 64) {
             // this lane's record of the chunk
             const int64_t j = tb0 + lane;
             const int32_t id = cent[j < tz ? j : tb0];
+            const int nk = (int)(tz - tb0 < 64 ? tz - tb0 : 64);
+            if (EMIT) {
+                // replay the counting pass's masks, query by query (only
+                // the queries with a hit in this chunk): the hit records'
+                // lanes write the query's next candidates side by side
+                const int4 rv = *reinterpret_cast<const int4*>(&trec[id].v[0]);
+                const unsigned long long mine = lane < nk ? bal[bslot + (tb0 - ta) + lane] : 0ull;
+                unsigned long long any = mine;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) any |= __shfl_xor(any, o, 64);
+                any = read_lane_u64(any, 0);
+                const unsigned long long below = (1ull << lane) - 1ull;
+                while (any) {
+                    const int jq = __builtin_ctzll(any);
+                    any &= any - 1ull;
+                    const bool bit = (mine >> jq) & 1ull;
+                    const unsigned long long bm = __ballot(bit);
+                    const int64_t base = (int64_t)read_lane_u64((unsigned long long)w, jq);
+                    const int32_t a0 = __builtin_amdgcn_readlane(q0, jq), a1 = __builtin_amdgcn_readlane(q1, jq);
+                    if (bit)
+                        out[base + __popcll(bm & below)] =
+                            KIND == 0 ? make_int4(-(a0 + 1), rv.x, rv.y, rv.z) : make_int4(a0, a1, rv.x, rv.y);
+                    if (lane == jq) w += __popcll(bm);
+                }
+                if (__ballot(w < wz) == 0) break;
+                continue;
+            }
             const PrimRec r = trec[id];
             int tsel = 0;
             for (int d = 0; d < 3; ++d)
                 tsel |= (cell_of(r.lo[d], g.org[d], g.h[d], g.n[d]) == cc[d]) << d;
-            const int nk = (int)(tz - tb0 < 64 ? tz - tb0 : 64);
+            unsigned long long mine = 0;
             for (int k = 0; k < nk; ++k) {
                 const double lx = read_lane(r.lo[0], k), ly = read_lane(r.lo[1], k), lz = read_lane(r.lo[2], k);
                 const double hx = read_lane(r.hi[0], k), hy = read_lane(r.hi[1], k), hz = read_lane(r.hi[2], k);
@@ -392,15 +456,23 @@ __global__ void __launch_bounds__(kBlock) k_cell_pairs(const double* __restrict_
                 }
                 hit = hit && !(qlx > hx || lx > qhx || qly > hy || ly > qhy || qlz > hz || lz > qhz);
                 hit = hit && (own0 || (ts & 1)) && (own1 || (ts & 2)) && (own2 || (ts & 4));
-                if (hit) {
-                    if (EMIT) out[w++] = KIND == 0 ? make_int4(-(q0 + 1), v0, v1, v2) : make_int4(q0, q1, v0, v1);
-                    else ++found;
-                }
+                const unsigned long long m = __ballot(hit);
+                if (lane == k) mine = m;
+                found += hit;
             }
-            if (EMIT && __ballot(w < wz) == 0) break;
+            if (lane < nk) bal[bslot + (tb0 - ta) + lane] = mine;
         }
         if (!EMIT && act) cnt[e] = found;
     }
+}
+
+// per cell, the hit-mask slots of its pairs pass: one per chunk of 64
+// queries and primitive of the cell
+__global__ void __launch_bounds__(kBlock) k_cell_slots(int64_t ncell, const int64_t* __restrict__ qtoff,
+                                                       const int64_t* __restrict__ coff, int64_t* __restrict__ n) {
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= ncell) return;
+    n[c] = ((qtoff[c + 1] - qtoff[c] + 63) >> 6) * (coff[c + 1] - coff[c]);
 }
 
 unsigned grid1(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -492,10 +564,18 @@ hipError_t launch_qcells_fill(int kind, const double* x, int64_t nq, const void*
     return hipGetLastError();
 }
 
+hipError_t launch_cell_slots(const CandGrid& cg, const int64_t* qtoff, const int64_t* coff, int64_t* n,
+                             hipStream_t s) {
+    const int64_t ncell = (int64_t)cg.n[0] * cg.n[1] * cg.n[2];
+    k_cell_slots<<<grid1(ncell), kBlock, 0, s>>>(ncell, qtoff, coff, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_cell_pairs(int kind, bool emit, const double* x, const int32_t* vobj, const void* qrec,
                              const void* trec, const CandGrid& cg, double dhat, const int64_t* qtoff,
                              const int32_t* qent, const int64_t* qeoff, const int64_t* coff, const int32_t* cent,
-                             int32_t* cnt, const int64_t* eoff, int32_t* out, hipStream_t s) {
+                             int32_t* cnt, const int64_t* eoff, const int64_t* boff, uint64_t* bal,
+                             int64_t* evis, int32_t* out, hipStream_t s) {
     const Grid g = to_grid(cg);
     const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
     const unsigned nb = (unsigned)((ncell + kBlock / 64 - 1) / (kBlock / 64));
@@ -503,7 +583,8 @@ hipError_t launch_cell_pairs(int kind, bool emit, const double* x, const int32_t
     const PrimRec* qr = static_cast<const PrimRec*>(qrec);
     const PrimRec* tr = static_cast<const PrimRec*>(trec);
 #define GIPC_CELL_PAIRS(K, EM) \
-    k_cell_pairs<K, EM><<<nb, kBlock, 0, s>>>(x, vobj, qr, tr, g, dhat, ncell, qtoff, qent, qeoff, coff, cent, cnt, eoff, o)
+    k_cell_pairs<K, EM><<<nb, kBlock, 0, s>>>(x, vobj, qr, tr, g, dhat, ncell, qtoff, qent, qeoff, coff, cent, cnt, \
+                                              eoff, boff, reinterpret_cast<unsigned long long*>(bal), evis, o)
     if (kind == 0) {
         if (emit) GIPC_CELL_PAIRS(0, true);
         else GIPC_CELL_PAIRS(0, false);

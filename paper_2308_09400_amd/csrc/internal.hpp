@@ -167,7 +167,7 @@ struct gipc_ctx {
     // contact candidates: bounds partials, counters, cell tables (points
     // against triangles, edges against edges), per-query counts and offsets
     gipc::DevBuf cpart, ccnt, ccount, cfill, coff_t, cent_t, coff_e, cent_e, qcnt, qoff_p, qoff_e, crec_t, crec_e;
-    gipc::DevBuf qtoff_p, qtoff_e, qent_p, qent_e, ecnt_p, ecnt_e, eoff_p, eoff_e, craw;
+    gipc::DevBuf qtoff_p, qtoff_e, qent_p, qent_e, ecnt_p, ecnt_e, eoff_p, eoff_e, craw, bslot, boff_p, boff_e, bal_p, bal_e, evis_p, evis_e;
     uint64_t fric_gen = 0;
     double fric_sv = 0.0;
     uint64_t eval_gen = 0;   // bumped by every eval
@@ -360,14 +360,21 @@ hipError_t launch_qcells_count(int kind, const double* x, int64_t nq, const void
                                double dhat, int32_t* span, int32_t* count, hipStream_t s);
 hipError_t launch_qcells_fill(int kind, const double* x, int64_t nq, const void* qrec, const CandGrid& g,
                               double dhat, const int64_t* off, int32_t* fill, int32_t* ent, hipStream_t s);
+// n[cell] = hit-mask slots of the cell's pairs pass (chunks of 64 queries
+// times primitives)
+hipError_t launch_cell_slots(const CandGrid& g, const int64_t* qtoff, const int64_t* coff, int64_t* n,
+                             hipStream_t s);
 // per cell, its queries (qtoff/qent) against its primitives (coff/cent,
 // records trec): kind 0 points vs triangles, 1 edges vs edges of larger
 // index; per visit e = qeoff[q] + rank of the cell in q's walk, counts into
-// cnt[e] (emit = false) or int32 [4] tuples at out + 4 eoff[e] (emit = true)
+// cnt[e] and hit masks into bal + boff[cell] (emit = false), or int32 [4]
+// tuples at out + 4 eoff[e] from those masks (emit = true); evis (one per
+// query-table entry) carries each visit's e from the first to the second
 hipError_t launch_cell_pairs(int kind, bool emit, const double* x, const int32_t* vobj, const void* qrec,
                              const void* trec, const CandGrid& g, double dhat, const int64_t* qtoff,
                              const int32_t* qent, const int64_t* qeoff, const int64_t* coff, const int32_t* cent,
-                             int32_t* cnt, const int64_t* eoff, int32_t* out, hipStream_t s);
+                             int32_t* cnt, const int64_t* eoff, const int64_t* boff, uint64_t* bal,
+                             int64_t* evis, int32_t* out, hipStream_t s);
 
 // ---- accd.hip
 // additive CCD of P tuples moving by disp; counters [6] (see k_accd_reset)
