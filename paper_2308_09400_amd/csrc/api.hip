@@ -975,7 +975,7 @@ gipc_status gipc_candidates(gipc_ctx* ctx, const gipc_mesh* mesh, const gipc_top
     CK(ensure(ctx->bslot, sizeof(int64_t) * (size_t)ncell), "alloc candidates");
     for (int k = 0; k < 2; ++k) {
         CK(ensure(*boff[k], sizeof(int64_t) * (size_t)(ncell + 1)), "alloc candidates");
-        CK(launch_cell_slots(g, as<int64_t>(*qtoff[k]), as<int64_t>(*toff[k]), as<int64_t>(ctx->bslot), s),
+        CK(launch_cell_slots(k, g, as<int64_t>(*qtoff[k]), as<int64_t>(*toff[k]), as<int64_t>(ctx->bslot), s),
            "mask slots");
         CK((exclusive_scan<int64_t, int64_t>(as<int64_t>(ctx->bslot), ncell, as<int64_t>(*boff[k]), ctx, s)), "scan");
     }

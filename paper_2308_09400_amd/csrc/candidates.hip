@@ -305,15 +305,15 @@ __device__ __forceinline__ double read_lane(double v, int k) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// One wave per cell: its lanes take the queries covering the cell, 64 at a
-// time, and the cell's primitive list 64 records at a time, one record per
-// lane; each record is then handed to every lane from the lane holding it
-// (a lane read, no memory access), so the records are read once per 64
-// queries.  The query q's visit of the cell is entry e = qeoff[q] + j, j the
+// Edge-edge pairs, one wave per cell: its lanes take the edge queries
+// covering the cell, 64 at a time, and the cell's edge list 64 records at a
+// time, one record per lane; each record is then handed to every lane from
+// the lane holding it (a lane read, no memory access), so the records are
+// read once per 64 queries.  The query q's visit of the cell is entry e = qeoff[q] + j, j the
 // cell's rank in the query's walk (x slowest, z fastest): EMIT = false
 // stores the entry's candidate count in cnt[e], EMIT = true writes its
-// candidates at out + eoff[e], in list order.  KIND 1 takes only edges of
-// larger index than the query.  The counting pass also stores, per record
+// candidates at out + eoff[e], in list order.  Only edges of larger index
+// than the query are taken.  The counting pass also stores, per record
 // and chunk of queries, the 64-lane mask of the queries it pairs with
 // (bal, from boff[cell]); the emitting pass replays those masks instead of
 // testing again, reading only the records' vertex ids, and writes query by
@@ -328,10 +328,12 @@ __device__ __forceinline__ double read_lane(double v, int k) {
 // both are at most the current cell's (both boxes cover it): the pair is
 // this cell's when, along every axis, one of the two lower cells is this
 // cell's.
-template <int KIND, bool EMIT>
-// (seven waves per SIMD asked for: the compiler then keeps the counting
-// passes at 56 / 66 registers instead of 74 / 84, without spills)
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) k_cell_pairs(const double* __restrict__ X,
+//
+// (Seven waves per SIMD asked for: the compiler then keeps the counting
+// pass at 66 registers instead of 84, without spills; the point-triangle
+// pass below at 68.)
+template <bool EMIT>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) k_cell_pairs_ee(const double* __restrict__ X,
                                                        const int32_t* __restrict__ vobj,
                                                        const PrimRec* __restrict__ qrec,
                                                        const PrimRec* __restrict__ trec, Grid g, double dhat,
@@ -365,17 +367,14 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))
             // the counting pass left the visit's entry; only the query's ids
             // are needed
             e = act ? evis[i] : 0;
-            q0 = q1 = (int32_t)q;
-            if (KIND == 1) {
-                const int4 qv = *reinterpret_cast<const int4*>(&qrec[q].v[0]);
-                q0 = qv.x;
-                q1 = qv.y;
-            }
+            const int4 qv = *reinterpret_cast<const int4*>(&qrec[q].v[0]);
+            q0 = qv.x;
+            q1 = qv.y;
             w = act ? eoff[e] : 0;
             wz = act ? eoff[e + 1] : 0;
             if (__ballot(w < wz) == 0) continue;
         } else {
-            query_of<KIND>(q, X, vobj, qrec, qb, q0, q1, qo);
+            query_of<1>(q, X, vobj, qrec, qb, q0, q1, qo);
             query_cells(qb, g, dhat, lo, hi);
             e = qeoff[q] + ((int64_t)(cc[0] - lo[0]) * (hi[1] - lo[1] + 1) + (cc[1] - lo[1])) *
                                (hi[2] - lo[2] + 1) + (cc[2] - lo[2]);
@@ -385,22 +384,20 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))
         const double qlx = qb.lo.x - dhat, qly = qb.lo.y - dhat, qlz = qb.lo.z - dhat;
         const double qhx = qb.hi.x + dhat, qhy = qb.hi.y + dhat, qhz = qb.hi.z + dhat;
         int64_t t0 = ta;
-        if (KIND == 1) {
-            // the list is in increasing edge id: skip what no lane takes
-            int64_t qmin = act ? q : INT64_MAX;
+        // the list is in increasing edge id: skip what no lane takes
+        int64_t qmin = act ? q : INT64_MAX;
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                const int64_t v = __shfl_xor(qmin, o, 64);
-                qmin = v < qmin ? v : qmin;
-            }
-            qmin = __builtin_amdgcn_readfirstlane((int)qmin);
-            // (64 entries a step: they form a prefix of each window)
-            for (;;) {
-                const int64_t j = t0 + lane;
-                const unsigned long long m = __ballot(j < tz && (int64_t)cent[j] <= qmin);
-                t0 += __popcll(m);
-                if (m != ~0ull) break;
-            }
+        for (int o = 32; o > 0; o >>= 1) {
+            const int64_t v = __shfl_xor(qmin, o, 64);
+            qmin = v < qmin ? v : qmin;
+        }
+        qmin = __builtin_amdgcn_readfirstlane((int)qmin);
+        // (64 entries a step: they form a prefix of each window)
+        for (;;) {
+            const int64_t j = t0 + lane;
+            const unsigned long long m = __ballot(j < tz && (int64_t)cent[j] <= qmin);
+            t0 += __popcll(m);
+            if (m != ~0ull) break;
         }
         int32_t found = 0;
         // this chunk's hit masks: slot (chunk of queries, record) of the cell
@@ -430,7 +427,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))
                     const int32_t a0 = __builtin_amdgcn_readlane(q0, jq), a1 = __builtin_amdgcn_readlane(q1, jq);
                     if (bit)
                         out[base + __popcll(bm & below)] =
-                            KIND == 0 ? make_int4(-(a0 + 1), rv.x, rv.y, rv.z) : make_int4(a0, a1, rv.x, rv.y);
+                            make_int4(a0, a1, rv.x, rv.y);
                     if (lane == jq) w += __popcll(bm);
                 }
                 if (__ballot(w < wz) == 0) break;
@@ -445,15 +442,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))
                 const double lx = read_lane(r.lo[0], k), ly = read_lane(r.lo[1], k), lz = read_lane(r.lo[2], k);
                 const double hx = read_lane(r.hi[0], k), hy = read_lane(r.hi[1], k), hz = read_lane(r.hi[2], k);
                 const int32_t v0 = __builtin_amdgcn_readlane(r.v[0], k), v1 = __builtin_amdgcn_readlane(r.v[1], k);
-                const int32_t v2 = __builtin_amdgcn_readlane(r.v[2], k), ob = __builtin_amdgcn_readlane(r.obj, k);
+                const int32_t ob = __builtin_amdgcn_readlane(r.obj, k), tid = __builtin_amdgcn_readlane(id, k);
                 const int ts = __builtin_amdgcn_readlane(tsel, k);
-                bool hit = act && ob != qo;
-                if (KIND == 0) {
-                    hit = hit && v0 != q0 && v1 != q0 && v2 != q0;
-                } else {
-                    const int32_t tid = __builtin_amdgcn_readlane(id, k);
-                    hit = hit && (int64_t)tid > q && v0 != q0 && v0 != q1 && v1 != q0 && v1 != q1;
-                }
+                bool hit = act && ob != qo && (int64_t)tid > q && v0 != q0 && v0 != q1 && v1 != q0 && v1 != q1;
                 hit = hit && !(qlx > hx || lx > qhx || qly > hy || ly > qhy || qlz > hz || lz > qhz);
                 hit = hit && (own0 || (ts & 1)) && (own1 || (ts & 2)) && (own2 || (ts & 4));
                 const unsigned long long m = __ballot(hit);
@@ -466,13 +457,116 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))
     }
 }
 
+// Point-triangle pairs of a cell the other way round: the cell's triangles
+// in the lanes, 64 at a time, and its points (a cell holds tens of them,
+// fewer than triangles) handed to every lane by lane reads, so a wave step
+// tests one point against 64 triangles.  The points' setup (entry e,
+// reporting-cell flags) is done with the points in the lanes, 64 at a
+// time.  A pair is taken when the point and the triangle belong to
+// different objects, the point is none of the triangle's vertices, the
+// point's box inflated by dhat overlaps the triangle's box and the cell
+// reports it (as for the edges); the counting pass stores each point's
+// 64-bit mask over a chunk of triangles at bal + boff[cell] + (triangle
+// chunk) * (points of the cell) + (point's place in the cell's list), and
+// the emitting pass replays them, writing at out + eoff[e] in list order.
+template <bool EMIT>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7)))
+k_cell_pairs_pt(const double* __restrict__ X, const int32_t* __restrict__ vobj, const PrimRec* __restrict__ trec,
+                Grid g, double dhat, int64_t ncell, const int64_t* __restrict__ qtoff,
+                const int32_t* __restrict__ qent, const int64_t* __restrict__ qeoff,
+                const int64_t* __restrict__ coff, const int32_t* __restrict__ cent, int32_t* __restrict__ cnt,
+                const int64_t* __restrict__ eoff, const int64_t* __restrict__ boff,
+                unsigned long long* __restrict__ bal, int64_t* __restrict__ evis, int4* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t cell =
+        (int64_t)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (cell >= ncell) return;
+    const int64_t qa = qtoff[cell], qz = qtoff[cell + 1];
+    const int64_t ta = coff[cell], tz = coff[cell + 1];
+    if (qa == qz || (EMIT && ta == tz)) return;
+    const int cc[3] = {(int)(cell / ((int64_t)g.n[1] * g.n[2])), (int)((cell / g.n[2]) % g.n[1]),
+                       (int)(cell % g.n[2])};
+    const int64_t nq = qz - qa;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int64_t qb0 = qa; qb0 < qz; qb0 += 64) {
+        const int64_t i = qb0 + lane;
+        const bool act = i < qz;
+        const int32_t q = qent[act ? i : qa];
+        const int nqk = (int)(qz - qb0 < 64 ? qz - qb0 : 64);
+        d3 pq = mk(0.0, 0.0, 0.0);
+        int32_t qo = 0, own = 0;
+        int64_t e, w = 0, wz = 0;
+        if (EMIT) {
+            e = act ? evis[i] : 0;
+            w = act ? eoff[e] : 0;
+            wz = act ? eoff[e + 1] : 0;
+            if (__ballot(w < wz) == 0) continue;
+        } else {
+            Box qb;
+            int32_t q0, q1;
+            query_of<0>(q, X, vobj, nullptr, qb, q0, q1, qo);
+            pq = qb.lo;
+            int lo[3], hi[3];
+            query_cells(qb, g, dhat, lo, hi);
+            e = qeoff[q] + ((int64_t)(cc[0] - lo[0]) * (hi[1] - lo[1] + 1) + (cc[1] - lo[1])) *
+                               (hi[2] - lo[2] + 1) + (cc[2] - lo[2]);
+            if (act) evis[i] = e;
+            own = (lo[0] == cc[0]) | ((lo[1] == cc[1]) << 1) | ((lo[2] == cc[2]) << 2);
+        }
+        int32_t found = 0;
+        for (int64_t tb0 = ta; tb0 < tz; tb0 += 64) {
+            const int64_t j = tb0 + lane;
+            const bool tact = j < tz;
+            const int32_t id = cent[tact ? j : tb0];
+            const int64_t slot = boff[cell] + ((tb0 - ta) >> 6) * nq + (qb0 - qa);
+            if (EMIT) {
+                const int4 rv = *reinterpret_cast<const int4*>(&trec[id].v[0]);
+                const unsigned long long mq = lane < nqk ? bal[slot + lane] : 0ull;
+                for (int k = 0; k < nqk; ++k) {
+                    const unsigned long long m = read_lane_u64(mq, k);
+                    if (m == 0) continue;
+                    const int64_t base = (int64_t)read_lane_u64((unsigned long long)w, k);
+                    const int32_t a0 = __builtin_amdgcn_readlane(q, k);
+                    if ((m >> lane) & 1ull) out[base + __popcll(m & below)] = make_int4(-(a0 + 1), rv.x, rv.y, rv.z);
+                    if (lane == k) w += __popcll(m);
+                }
+                if (__ballot(w < wz) == 0) break;
+                continue;
+            }
+            const PrimRec r = trec[id];
+            int tsel = 0;
+            for (int d = 0; d < 3; ++d)
+                tsel |= (cell_of(r.lo[d], g.org[d], g.h[d], g.n[d]) == cc[d]) << d;
+            unsigned long long mine = 0;
+            for (int k = 0; k < nqk; ++k) {
+                const double px = read_lane(pq.x, k), py = read_lane(pq.y, k), pz = read_lane(pq.z, k);
+                const int32_t a0 = __builtin_amdgcn_readlane(q, k), ob = __builtin_amdgcn_readlane(qo, k);
+                const int ow = __builtin_amdgcn_readlane(own, k) | tsel;
+                bool hit = tact && r.obj != ob && r.v[0] != a0 && r.v[1] != a0 && r.v[2] != a0;
+                hit = hit && !(px - dhat > r.hi[0] || r.lo[0] > px + dhat || py - dhat > r.hi[1] ||
+                               r.lo[1] > py + dhat || pz - dhat > r.hi[2] || r.lo[2] > pz + dhat);
+                hit = hit && ow == 7;
+                const unsigned long long m = __ballot(hit);
+                if (lane == k) {
+                    mine = m;
+                    found += __popcll(m);
+                }
+            }
+            if (lane < nqk) bal[slot + lane] = mine;
+        }
+        if (!EMIT && act) cnt[e] = found;
+    }
+}
+
 // per cell, the hit-mask slots of its pairs pass: one per chunk of 64
-// queries and primitive of the cell
-__global__ void __launch_bounds__(kBlock) k_cell_slots(int64_t ncell, const int64_t* __restrict__ qtoff,
+// queries and primitive of the cell, or (by_points, the point-triangle
+// pass) one per chunk of 64 triangles and point of the cell
+__global__ void __launch_bounds__(kBlock) k_cell_slots(int64_t ncell, int by_points, const int64_t* __restrict__ qtoff,
                                                        const int64_t* __restrict__ coff, int64_t* __restrict__ n) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (c >= ncell) return;
-    n[c] = ((qtoff[c + 1] - qtoff[c] + 63) >> 6) * (coff[c + 1] - coff[c]);
+    const int64_t nq = qtoff[c + 1] - qtoff[c], nt = coff[c + 1] - coff[c];
+    n[c] = by_points ? ((nt + 63) >> 6) * nq : ((nq + 63) >> 6) * nt;
 }
 
 unsigned grid1(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -564,10 +658,10 @@ hipError_t launch_qcells_fill(int kind, const double* x, int64_t nq, const void*
     return hipGetLastError();
 }
 
-hipError_t launch_cell_slots(const CandGrid& cg, const int64_t* qtoff, const int64_t* coff, int64_t* n,
+hipError_t launch_cell_slots(int kind, const CandGrid& cg, const int64_t* qtoff, const int64_t* coff, int64_t* n,
                              hipStream_t s) {
     const int64_t ncell = (int64_t)cg.n[0] * cg.n[1] * cg.n[2];
-    k_cell_slots<<<grid1(ncell), kBlock, 0, s>>>(ncell, qtoff, coff, n);
+    k_cell_slots<<<grid1(ncell), kBlock, 0, s>>>(ncell, kind == 0, qtoff, coff, n);
     return hipGetLastError();
 }
 
@@ -582,17 +676,22 @@ hipError_t launch_cell_pairs(int kind, bool emit, const double* x, const int32_t
     int4* o = reinterpret_cast<int4*>(out);
     const PrimRec* qr = static_cast<const PrimRec*>(qrec);
     const PrimRec* tr = static_cast<const PrimRec*>(trec);
-#define GIPC_CELL_PAIRS(K, EM) \
-    k_cell_pairs<K, EM><<<nb, kBlock, 0, s>>>(x, vobj, qr, tr, g, dhat, ncell, qtoff, qent, qeoff, coff, cent, cnt, \
-                                              eoff, boff, reinterpret_cast<unsigned long long*>(bal), evis, o)
+    unsigned long long* b = reinterpret_cast<unsigned long long*>(bal);
     if (kind == 0) {
-        if (emit) GIPC_CELL_PAIRS(0, true);
-        else GIPC_CELL_PAIRS(0, false);
+        if (emit)
+            k_cell_pairs_pt<true><<<nb, kBlock, 0, s>>>(x, vobj, tr, g, dhat, ncell, qtoff, qent, qeoff, coff, cent,
+                                                        cnt, eoff, boff, b, evis, o);
+        else
+            k_cell_pairs_pt<false><<<nb, kBlock, 0, s>>>(x, vobj, tr, g, dhat, ncell, qtoff, qent, qeoff, coff, cent,
+                                                         cnt, eoff, boff, b, evis, o);
     } else {
-        if (emit) GIPC_CELL_PAIRS(1, true);
-        else GIPC_CELL_PAIRS(1, false);
+        if (emit)
+            k_cell_pairs_ee<true><<<nb, kBlock, 0, s>>>(x, vobj, qr, tr, g, dhat, ncell, qtoff, qent, qeoff, coff, cent,
+                                                        cnt, eoff, boff, b, evis, o);
+        else
+            k_cell_pairs_ee<false><<<nb, kBlock, 0, s>>>(x, vobj, qr, tr, g, dhat, ncell, qtoff, qent, qeoff, coff,
+                                                         cent, cnt, eoff, boff, b, evis, o);
     }
-#undef GIPC_CELL_PAIRS
     return hipGetLastError();
 }
 

@@ -360,9 +360,9 @@ hipError_t launch_qcells_count(int kind, const double* x, int64_t nq, const void
                                double dhat, int32_t* span, int32_t* count, hipStream_t s);
 hipError_t launch_qcells_fill(int kind, const double* x, int64_t nq, const void* qrec, const CandGrid& g,
                               double dhat, const int64_t* off, int32_t* fill, int32_t* ent, hipStream_t s);
-// n[cell] = hit-mask slots of the cell's pairs pass (chunks of 64 queries
-// times primitives)
-hipError_t launch_cell_slots(const CandGrid& g, const int64_t* qtoff, const int64_t* coff, int64_t* n,
+// n[cell] = hit-mask slots of the cell's pairs pass (kind 1: chunks of 64
+// queries times primitives; kind 0: chunks of 64 triangles times points)
+hipError_t launch_cell_slots(int kind, const CandGrid& g, const int64_t* qtoff, const int64_t* coff, int64_t* n,
                              hipStream_t s);
 // per cell, its queries (qtoff/qent) against its primitives (coff/cent,
 // records trec): kind 0 points vs triangles, 1 edges vs edges of larger
