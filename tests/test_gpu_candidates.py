@@ -130,6 +130,9 @@ def test_edge_cases_and_errors(gp):
     assert gp.candidates(ctx, x, vobj, none3, none2, 0.1).shape == (0, 4)
     only_pt = gp.candidates(ctx, x, vobj, tris, none2, 0.15).cpu().numpy()
     assert (only_pt[:, 0] < 0).all() and len(only_pt) > 0
+    only_ee = gp.candidates(ctx, x, vobj, none3, edges, 0.15).cpu().numpy()
+    ref_ee = oracle.candidates(s.x, s.vobj, np.zeros((0, 3), np.int32), s.edges, 0.15)
+    assert (only_ee[:, 0] >= 0).all() and len(only_ee) > 0 and _set(only_ee) == _set(ref_ee)
     x0 = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
     assert gp.candidates(ctx, x0, vobj[:0], none3, none2, 0.1).shape == (0, 4)
     bad = tris.clone()
