@@ -66,22 +66,53 @@ __device__ __forceinline__ bool overlap(const Box& a, double dhat, const Box& b)
              a.lo.z - dhat > b.hi.z || b.lo.z > a.hi.z + dhat);
 }
 
-// The item of a lane, -1 past the end.  SPREAD = false: consecutive lanes,
-// consecutive items.  SPREAD = true: a wave's lanes take items n/64 apart
-// (item = lane * waves + wave), so that a wave's per-cell atomics go to
-// cells far apart instead of the same few; measured faster for the point
-// queries only (a point's few cells are shared by all its neighbours).
-template <bool SPREAD>
+// the item of a lane, -1 past the end
 __device__ __forceinline__ int64_t item_of(int64_t n) {
-    if (!SPREAD) {
-        const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-        return i < n ? i : -1;
-    }
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t nw = (n + 63) / 64;
-    if ((i >> 6) >= nw) return -1;
-    const int64_t k = (i & 63) * nw + (i >> 6);
-    return k < n ? k : -1;
+    return i < n ? i : -1;
+}
+
+// A wave's visits of cells flattened: each lane's cells lo..hi (x slowest,
+// z fastest) are numbered after those of the lanes below it, and the wave
+// takes them 64 at a time, so that lanes covering few cells do not idle
+// while others walk up to 27.  f(cell, item) for every visit; the owner of
+// visit v is the last lane whose first number is at most v (a lane covering
+// no cell shares its first number with the next lane and is never last).
+template <typename C, typename F>
+__device__ __forceinline__ void wave_visits(const int lo[3], const int hi[3], bool valid, int32_t item, C vcell, F f) {
+    __shared__ int4 vbox[kBlock / 64][64];
+    __shared__ int2 vnum[kBlock / 64][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int sy = hi[1] - lo[1] + 1, sz = hi[2] - lo[2] + 1;
+    const int n = valid ? (hi[0] - lo[0] + 1) * sy * sz : 0;
+    int inc = n;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int v = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += v;
+    }
+    const int total = __builtin_amdgcn_readlane(inc, 63);
+    vbox[w][lane] = make_int4(lo[0], lo[1], lo[2], (sy << 8) | sz);
+    vnum[w][lane] = make_int2(inc - n, item);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int base = 0; base < total; base += 64) {
+        const int v = base + lane;
+        if (v < total) {
+            int l = 0;
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1)
+                if (vnum[w][l + step].x <= v) l += step;
+            const int4 b = vbox[w][l];
+            const int2 nm = vnum[w][l];
+            const int bz = b.w & 255, byz = (b.w >> 8) * bz;
+            const int j = v - nm.x;
+            const int da = j / byz, rem = j - da * byz;
+            const int dc = rem / bz, de = rem - dc * bz;
+            f(vcell(b.x + da, b.y + dc, b.z + de), nm.y);
+        }
+    }
 }
 
 // per block: min x,y,z, max x,y,z of the positions, largest primitive
@@ -146,17 +177,17 @@ template <int NPER>
 __global__ void __launch_bounds__(kBlock) k_cell_count_prims(const double* __restrict__ X,
                                                              const int32_t* __restrict__ prims, int64_t n, Grid g,
                                                              int32_t* __restrict__ count) {
-    const int64_t i = item_of<false>(n);
-    if (i < 0) return;
+    const int64_t i0 = item_of(n);
+    const bool valid = i0 >= 0;
+    const int64_t i = valid ? i0 : 0;
     const Box b = prim_box(X, prims + NPER * i, NPER);
     int lo[3], hi[3];
     for (int d = 0; d < 3; ++d) {
         lo[d] = cell_of(get(b.lo, d), g.org[d], g.h[d], g.n[d]);
         hi[d] = cell_of(get(b.hi, d), g.org[d], g.h[d], g.n[d]);
     }
-    for (int a = lo[0]; a <= hi[0]; ++a)
-        for (int c = lo[1]; c <= hi[1]; ++c)
-            for (int e = lo[2]; e <= hi[2]; ++e) atomicAdd(&count[((int64_t)a * g.n[1] + c) * g.n[2] + e], 1);
+    const auto vcell = [&](int a, int c, int e) { return ((int64_t)a * g.n[1] + c) * g.n[2] + e; };
+    wave_visits(lo, hi, valid, (int32_t)i, vcell, [&](int64_t cell, int32_t) { atomicAdd(&count[cell], 1); });
 }
 
 template <int NPER>
@@ -164,20 +195,19 @@ __global__ void __launch_bounds__(kBlock) k_cell_fill_prims(const double* __rest
                                                             const int32_t* __restrict__ prims, int64_t n, Grid g,
                                                             const int64_t* __restrict__ off,
                                                             int32_t* __restrict__ fill, int32_t* __restrict__ ent) {
-    const int64_t i = item_of<false>(n);
-    if (i < 0) return;
+    const int64_t i0 = item_of(n);
+    const bool valid = i0 >= 0;
+    const int64_t i = valid ? i0 : 0;
     const Box b = prim_box(X, prims + NPER * i, NPER);
     int lo[3], hi[3];
     for (int d = 0; d < 3; ++d) {
         lo[d] = cell_of(get(b.lo, d), g.org[d], g.h[d], g.n[d]);
         hi[d] = cell_of(get(b.hi, d), g.org[d], g.h[d], g.n[d]);
     }
-    for (int a = lo[0]; a <= hi[0]; ++a)
-        for (int c = lo[1]; c <= hi[1]; ++c)
-            for (int e = lo[2]; e <= hi[2]; ++e) {
-                const int64_t cell = ((int64_t)a * g.n[1] + c) * g.n[2] + e;
-                ent[off[cell] + atomicAdd(&fill[cell], 1)] = (int32_t)i;
-            }
+    const auto vcell = [&](int a, int c, int e) { return ((int64_t)a * g.n[1] + c) * g.n[2] + e; };
+    wave_visits(lo, hi, valid, (int32_t)i, vcell, [&](int64_t cell, int32_t item) {
+        ent[off[cell] + atomicAdd(&fill[cell], 1)] = item;
+    });
 }
 
 template <int NPER>
@@ -254,17 +284,17 @@ template <int KIND>
 __global__ void __launch_bounds__(kBlock) k_qcells_count(const double* __restrict__ X, int64_t nq,
                                                          const PrimRec* __restrict__ qrec, Grid g, double dhat,
                                                          int32_t* __restrict__ span, int32_t* __restrict__ count) {
-    const int64_t q = item_of<KIND == 0>(nq);
-    if (q < 0) return;
+    const int64_t qi = item_of(nq);
+    const bool valid = qi >= 0;
+    const int64_t q = valid ? qi : 0;
     Box qb;
     int32_t q0, q1, qo;
     query_of<KIND>(q, X, nullptr, qrec, qb, q0, q1, qo);
     int lo[3], hi[3];
     query_cells(qb, g, dhat, lo, hi);
-    span[q] = (hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1);
-    for (int a = lo[0]; a <= hi[0]; ++a)
-        for (int c = lo[1]; c <= hi[1]; ++c)
-            for (int e = lo[2]; e <= hi[2]; ++e) atomicAdd(&count[((int64_t)a * g.n[1] + c) * g.n[2] + e], 1);
+    if (valid) span[q] = (hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1);
+    const auto vcell = [&](int a, int c, int e) { return ((int64_t)a * g.n[1] + c) * g.n[2] + e; };
+    wave_visits(lo, hi, valid, (int32_t)q, vcell, [&](int64_t cell, int32_t) { atomicAdd(&count[cell], 1); });
 }
 
 // query table, filling: the queries covering each cell, in no particular
@@ -275,19 +305,18 @@ __global__ void __launch_bounds__(kBlock) k_qcells_fill(const double* __restrict
                                                         const PrimRec* __restrict__ qrec, Grid g, double dhat,
                                                         const int64_t* __restrict__ off, int32_t* __restrict__ fill,
                                                         int32_t* __restrict__ ent) {
-    const int64_t q = item_of<KIND == 0>(nq);
-    if (q < 0) return;
+    const int64_t qi = item_of(nq);
+    const bool valid = qi >= 0;
+    const int64_t q = valid ? qi : 0;
     Box qb;
     int32_t q0, q1, qo;
     query_of<KIND>(q, X, nullptr, qrec, qb, q0, q1, qo);
     int lo[3], hi[3];
     query_cells(qb, g, dhat, lo, hi);
-    for (int a = lo[0]; a <= hi[0]; ++a)
-        for (int c = lo[1]; c <= hi[1]; ++c)
-            for (int e = lo[2]; e <= hi[2]; ++e) {
-                const int64_t cell = ((int64_t)a * g.n[1] + c) * g.n[2] + e;
-                ent[off[cell] + atomicAdd(&fill[cell], 1)] = (int32_t)q;
-            }
+    const auto vcell = [&](int a, int c, int e) { return ((int64_t)a * g.n[1] + c) * g.n[2] + e; };
+    wave_visits(lo, hi, valid, (int32_t)q, vcell, [&](int64_t cell, int32_t item) {
+        ent[off[cell] + atomicAdd(&fill[cell], 1)] = item;
+    });
 }
 
 // a lane's 64-bit value, read by every lane (k wave-uniform)
