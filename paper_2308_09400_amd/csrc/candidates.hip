@@ -14,9 +14,12 @@
 //  2. per primitive kind, a cell table: counts (integer atomics), scan,
 //     fill, then each cell's list sorted by primitive id, so the table does
 //     not depend on the order of the atomics;
-//  3. one lane per query primitive (points against triangles, edges against
-//     edges of larger index), a counting pass, a scan, an emitting pass that
-//     walks the same cells in the same order.
+//  3. per query kind (points, edges), a cell table of the queries whose
+//     box inflated by dhat covers the cell, in any order;
+//  4. one wave per cell pairing its queries with its primitives (points
+//     against triangles, edges against edges of larger index): a counting
+//     pass that also keeps the hit masks, a scan over the queries' visits
+//     of cells, and an emitting pass that replays the masks.
 // The output is deterministic: point-triangle candidates grouped by point in
 // increasing order, then edge-edge candidates grouped by first edge, each
 // group in cell order and primitive order within a cell.
