@@ -111,6 +111,8 @@ def lib():
         L.orc_matfree.restype = ctypes.c_int
         L.orc_pcg.argtypes = [i32, i64, vp, vp, vp, vp, vp, d, ctypes.c_int, dp]
         L.orc_pcg.restype = ctypes.c_int
+        L.orc_pcg_delta.argtypes = [i32, i64, vp, vp, vp, vp, vp, d, ctypes.c_int, dp]
+        L.orc_pcg_delta.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -412,13 +414,18 @@ def matfree(V, tuples, pairH, x, diag=None):
     return y
 
 
-def pcg(V, rows, cols, vals, b, x0=None, rtol=1e-6, maxit=1000):
+def pcg(V, rows, cols, vals, b, x0=None, rtol=1e-6, maxit=1000, delta=False):
+    """Block-Jacobi PCG on the COO block matrix; stops when ||r|| <= rtol ||b||,
+    or with delta=True by the paper's termination r.z <= rtol r0.z0 (its
+    PCG in the implementation section, tolerance 1e-4 there).  Returns (x,
+    iterations, ||r||/||b||)."""
     b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
     x = np.zeros(3 * V) if x0 is None else np.ascontiguousarray(x0, dtype=np.float64).reshape(-1).copy()
     vals = np.ascontiguousarray(vals, dtype=np.float64)
     rows = np.ascontiguousarray(rows, dtype=np.int32)
     cols = np.ascontiguousarray(cols, dtype=np.int32)
     rr = ctypes.c_double()
-    it = lib().orc_pcg(V, rows.shape[0], rows.ctypes.data, cols.ctypes.data, vals.ctypes.data, b.ctypes.data,
-                       x.ctypes.data, float(rtol), int(maxit), ctypes.byref(rr))
+    f = lib().orc_pcg_delta if delta else lib().orc_pcg
+    it = f(V, rows.shape[0], rows.ctypes.data, cols.ctypes.data, vals.ctypes.data, b.ctypes.data,
+           x.ctypes.data, float(rtol), int(maxit), ctypes.byref(rr))
     return x, it, rr.value

@@ -1365,9 +1365,12 @@ static double vdot(int64_t n, const double* a, const double* b) {
 
 /* Preconditioned conjugate gradients (Saad, "Iterative Methods for Sparse
  * Linear Systems", Alg. 9.1) with the 3x3 block diagonal as preconditioner,
- * the paper's simple block preconditioner (Sec. 7.2). */
-int orc_pcg(int32_t V, int64_t nb, const int32_t* rows, const int32_t* cols, const double* vals,
-            const double* b, double* x, double rtol, int maxit, double* relres) {
+ * the paper's simple block preconditioner (Sec. 7.2).  Stopping test at the
+ * top of each iteration: delta = 0, ||r|| <= tol ||b||; delta = 1, the
+ * paper's termination (its PCG in the implementation section), r.z <= tol
+ * r0.z0 with z = M^-1 r. */
+static int pcg_core(int32_t V, int64_t nb, const int32_t* rows, const int32_t* cols, const double* vals,
+                    const double* b, double* x, double tol, int maxit, double* relres, int delta) {
     const int64_t n = 3 * (int64_t)V;
     double* Minv = (double*)calloc((size_t)V * 9, sizeof(double));
     for (int32_t v = 0; v < V; ++v) { Minv[9 * v] = Minv[9 * v + 4] = Minv[9 * v + 8] = 1.0; }
@@ -1387,10 +1390,15 @@ int orc_pcg(int32_t V, int64_t nb, const int32_t* rows, const int32_t* cols, con
         }
     memcpy(p, z, sizeof(double) * n);
     double rz = vdot(n, r, z);
+    const double rz0 = rz;
     int it = 0;
     for (; it < maxit; ++it) {
-        double rn = sqrt(vdot(n, r, r));
-        if (rn <= rtol * bn) break;
+        if (delta) {
+            if (rz <= tol * rz0) break;
+        } else {
+            double rn = sqrt(vdot(n, r, r));
+            if (rn <= tol * bn) break;
+        }
         orc_spmv(V, nb, rows, cols, vals, p, q);
         double pq = vdot(n, p, q);
         double alpha = rz / pq;
@@ -1408,4 +1416,14 @@ int orc_pcg(int32_t V, int64_t nb, const int32_t* rows, const int32_t* cols, con
     *relres = bn > 0.0 ? sqrt(vdot(n, r, r)) / bn : 0.0;
     free(Minv); free(r); free(z); free(p); free(q);
     return it;
+}
+
+int orc_pcg(int32_t V, int64_t nb, const int32_t* rows, const int32_t* cols, const double* vals,
+            const double* b, double* x, double rtol, int maxit, double* relres) {
+    return pcg_core(V, nb, rows, cols, vals, b, x, rtol, maxit, relres, 0);
+}
+
+int orc_pcg_delta(int32_t V, int64_t nb, const int32_t* rows, const int32_t* cols, const double* vals,
+                  const double* b, double* x, double eps, int maxit, double* relres) {
+    return pcg_core(V, nb, rows, cols, vals, b, x, eps, maxit, relres, 1);
 }

@@ -189,6 +189,10 @@ void orc_spmv(int32_t V, int64_t nb, const int32_t* rows, const int32_t* cols, c
  */
 int orc_pcg(int32_t V, int64_t nb, const int32_t* rows, const int32_t* cols, const double* vals,
             const double* b, double* x, double rtol, int maxit, double* relres);
+/* the same PCG stopped by the paper's termination: r.z <= eps r0.z0 (z the
+ * preconditioned residual), checked before each iteration */
+int orc_pcg_delta(int32_t V, int64_t nb, const int32_t* rows, const int32_t* cols, const double* vals,
+                  const double* b, double* x, double eps, int maxit, double* relres);
 
 #ifdef __cplusplus
 }

@@ -8,7 +8,10 @@
 * SpMV against scipy's BSR product.
 * Matrix-free mat-vec (sum of local products, no global matrix) against the
   hand-built two-spring product and the dense matrix of a small scene.
-* PCG against numpy.linalg.solve.
+* PCG against numpy.linalg.solve; the paper's termination (r.z <= eps
+  r0.z0) pinned by r.z recomputed with numpy from the returned solutions:
+  met after the reported iterations, not one iteration earlier; a block
+  diagonal system (the preconditioner is its inverse) stops after one.
 * Scene level: energy and gradient of a list equal the sums of the per-pair
   values; a duplicated tuple counts twice (contact multiplicity); the
   gradient of the whole scene is translation invariant.
@@ -125,6 +128,37 @@ def test_pcg_matches_direct_solve():
     # x0 = exact solution: zero iterations
     x2, it2, _ = oracle.pcg(s.V, rows, cols, vals, b, x0=ref, rtol=1e-6, maxit=10)
     assert it2 == 0
+
+
+def _delta(V, A, rows, cols, vals, b, x):
+    """r.z at x, z = (block diagonal of A)^-1 r, with numpy"""
+    r = b - A @ x
+    z = np.zeros_like(r)
+    for v in range(V):
+        D = A[3 * v:3 * v + 3, 3 * v:3 * v + 3]
+        z[3 * v:3 * v + 3] = np.linalg.solve(D, r[3 * v:3 * v + 3])
+    return float(r @ z)
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-4, 1e-8])
+def test_pcg_delta_termination(eps):
+    s, prm = _tiny_scene()
+    out = oracle.eval_scene(s.x, s.tuples, prm, x_rest=s.x_rest, per_pair=True)
+    diag = np.full(s.V, 10.0)
+    rows, cols, vals = oracle.assemble(s.V, s.tuples, out["pairH"], diag)
+    A = _dense(s.V, rows, cols, vals)
+    b = -out["grad"].reshape(-1)
+    d0 = _delta(s.V, A, rows, cols, vals, b, np.zeros_like(b))
+    x, it, rr = oracle.pcg(s.V, rows, cols, vals, b, rtol=eps, maxit=500, delta=True)
+    assert 0 < it < 500
+    assert _delta(s.V, A, rows, cols, vals, b, x) <= eps * d0 * (1 + 1e-9)
+    xm, itm, _ = oracle.pcg(s.V, rows, cols, vals, b, rtol=eps, maxit=it - 1, delta=True)
+    assert itm == it - 1 and _delta(s.V, A, rows, cols, vals, b, xm) > eps * d0 * (1 - 1e-9)
+    assert rr == pytest.approx(np.linalg.norm(b - A @ x) / np.linalg.norm(b), rel=1e-9)
+    # block diagonal system: one iteration to the exact solution
+    keep = rows == cols
+    xd, itd, rrd = oracle.pcg(s.V, rows[keep], cols[keep], vals[keep], b, rtol=eps, maxit=50, delta=True)
+    assert itd == 1 and rrd <= 1e-14
 
 
 def test_scene_sums_and_multiplicity():
