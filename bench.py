@@ -69,7 +69,7 @@ MEASURED_TRAFFIC = {
     "source": "profiles/sheets10_path.md (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 per dispatch, "
               "calibrated on the library's 2 GiB copy in the same run)",
     "file": "paper_2308_09400_amd/csrc/solve.hip",
-    "sha256": "f540f23320b00d1eeccfd47ee47dd086ba3e741fb28debb5a965bff5e6c71a37",
+    "sha256": "c6291caeb05ad8fcec59206c3ce7ac75e8bd7a46e7f4f484bed6b3e3c729ff19",
 }
 
 

@@ -299,6 +299,19 @@ gipc_status gipc_pcg(gipc_ctx* ctx, const gipc_bsr* A, const double* b, double* 
                      int32_t* iters, double* relres, void* stream);
 
 /*
+ * gipc_pcg stopped by the paper's own termination (its PCG in the
+ * implementation section, tolerance 1e-4 there): after iteration k when
+ * r_k . z_k <= eps r_0 . z_0, z = M^-1 r the preconditioned residual
+ * (checked before the first iteration too), or after maxit iterations.
+ * Same arguments, layouts, kernels and synchronisation as gipc_pcg;
+ * *relres still receives ||r||/||b||.  Returns OK when the test held,
+ * WARN_NOT_CONVERGED when eps > 0 and maxit came first, BREAKDOWN,
+ * INVALID_ARG (eps < 0, maxit < 0, bad matrix) or HIP.
+ */
+gipc_status gipc_pcg_delta(gipc_ctx* ctx, const gipc_bsr* A, const double* b, double* x, double eps,
+                           int32_t maxit, int32_t* iters, double* relres, void* stream);
+
+/*
  * gipc_pcg for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same solve, kernels and launch sequence as gipc_pcg, with its work

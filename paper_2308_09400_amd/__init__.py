@@ -26,7 +26,7 @@ SUBTYPES = {1: "PT", 2: "PE", 3: "PP", 4: "EE", 5: "EE_moll", 6: "PE_moll", 7: "
 EXPORTS = [
     "gipc_status_string", "gipc_ctx_create", "gipc_ctx_create_with_allocator", "gipc_ctx_destroy", "gipc_ctx_last_error", "gipc_pairs_build",
     "gipc_get_info", "gipc_bsr_pattern", "gipc_barrier_eval", "gipc_assemble_bsr", "gipc_eval_assemble",
-    "gipc_bsr_spmv", "gipc_pcg", "gipc_pair_inspect", "gipc_copy", "gipc_get_tune", "gipc_set_tune",
+    "gipc_bsr_spmv", "gipc_pcg", "gipc_pcg_delta", "gipc_pair_inspect", "gipc_copy", "gipc_get_tune", "gipc_set_tune",
     "gipc_autotune", "gipc_graph_create", "gipc_graph_launch", "gipc_graph_destroy", "gipc_mf_apply",
     "gipc_pcg_mf", "gipc_proxy_dense", "gipc_friction_lag", "gipc_friction_eval", "gipc_candidates",
     "gipc_read", "gipc_pairs_check", "gipc_pcg_static", "gipc_accd", "gipc_dense_apply", "gipc_pcg_dense",
@@ -137,6 +137,8 @@ def lib():
                                         ctypes.POINTER(Bsr), vp]),
             "gipc_bsr_spmv": (st, [ctypes.POINTER(Bsr), vp, vp, vp]),
             "gipc_pcg": (st, [vp, ctypes.POINTER(Bsr), vp, vp, d, i32, ctypes.POINTER(i32), ctypes.POINTER(d), vp]),
+            "gipc_pcg_delta": (st, [vp, ctypes.POINTER(Bsr), vp, vp, d, i32, ctypes.POINTER(i32), ctypes.POINTER(d),
+                                    vp]),
             "gipc_accd": (st, [vp, ctypes.POINTER(Mesh), vp, ctypes.POINTER(Pairs), d, d, i32, vp,
                                ctypes.POINTER(AccdInfo), vp]),
             "gipc_pcg_static": (st, [ctypes.POINTER(Bsr), vp, vp, d, i32, ctypes.POINTER(i32), ctypes.POINTER(d),
@@ -441,17 +443,22 @@ def bsr_spmv(A: BsrMatrix, x, y=None, stream=None, by_rows=False):
     return y
 
 
-def pcg(ctx: Context, A: BsrMatrix, b, x=None, rtol=1e-6, maxit=1000, stream=None, by_rows=False):
+def pcg(ctx: Context, A: BsrMatrix, b, x=None, rtol=1e-6, maxit=1000, stream=None, by_rows=False, stop="residual"):
     """Block-Jacobi PCG (synchronises).  Returns (x, iterations, relres, status).
-    by_rows=True drops the row-start map (row-by-row products)."""
+    by_rows=True drops the row-start map (row-by-row products).  stop =
+    "residual": ||r|| <= rtol ||b|| (gipc_pcg); "delta": the paper's
+    termination r.z <= rtol r0.z0 (gipc_pcg_delta)."""
     _need(b, torch.float64, 3, "b")
+    if stop not in ("residual", "delta"):
+        raise ValueError("stop must be 'residual' or 'delta'")
     x = torch.zeros_like(b) if x is None else x
     it = ctypes.c_int32()
     rr = ctypes.c_double()
     desc = A.row_descriptor() if by_rows else A.desc
-    s = lib().gipc_pcg(ctx.h, ctypes.byref(desc), _ptr(b), _ptr(x), float(rtol), int(maxit), ctypes.byref(it),
-                       ctypes.byref(rr), _stream(stream))
-    ctx._check(s, "gipc_pcg")
+    f = lib().gipc_pcg_delta if stop == "delta" else lib().gipc_pcg
+    s = f(ctx.h, ctypes.byref(desc), _ptr(b), _ptr(x), float(rtol), int(maxit), ctypes.byref(it), ctypes.byref(rr),
+          _stream(stream))
+    ctx._check(s, "gipc_pcg_delta" if stop == "delta" else "gipc_pcg")
     return x, int(it.value), float(rr.value), int(s)
 
 

@@ -709,6 +709,29 @@ gipc_status gipc_pcg(gipc_ctx* ctx, const gipc_bsr* A, const double* b, double* 
     return GIPC_OK;
 }
 
+gipc_status gipc_pcg_delta(gipc_ctx* ctx, const gipc_bsr* A, const double* b, double* x, double eps,
+                           int32_t maxit, int32_t* iters, double* relres, void* stream) {
+    if (!ctx) return GIPC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    gipc_status st;
+    if ((st = check_device(ctx)) != GIPC_OK) return st;
+    if (!A || A->nbrows < 0 || A->nnzb < 0) return fail(ctx, GIPC_ERR_INVALID_ARG, "bad matrix");
+    if (A->dtype != GIPC_F64 && A->dtype != GIPC_F32) return fail(ctx, GIPC_ERR_INVALID_ARG, "bad dtype");
+    if (A->nbrows > 0 && (!A->row_ptr || !A->col_idx || !A->val || !b || !x))
+        return fail(ctx, GIPC_ERR_INVALID_ARG, "NULL matrix or vector");
+    if (!(eps >= 0.0) || maxit < 0) return fail(ctx, GIPC_ERR_INVALID_ARG, "eps must be >= 0 and maxit >= 0");
+    int32_t it = 0;
+    double rr = 0.0;
+    int brk = 0, conv = 1;
+    if (A->nbrows > 0)
+        CK(pcg_run(ctx, *A, b, x, eps, maxit, &it, &rr, &brk, S(stream), nullptr, 1, &conv), "pcg");
+    if (iters) *iters = it;
+    if (relres) *relres = rr;
+    if (brk) return fail(ctx, GIPC_ERR_BREAKDOWN, "p^T A p <= 0 at iteration %d", it);
+    if (eps > 0.0 && !conv) return GIPC_WARN_NOT_CONVERGED;
+    return GIPC_OK;
+}
+
 }  // extern "C"
 
 namespace {

@@ -119,8 +119,10 @@ __device__ __forceinline__ double block_sum(double v, double* lds /*[kBlock/64]*
 }
 
 struct PcgScalars {  // device-resident scalars of the PCG loop
-    double rz, pq, rr, bb, alpha, beta, rtol2;
+    double rz, pq, rr, bb, alpha, beta, rtol2, rz0;
     int iters, done, breakdown, maxit;
+    int delta;  // stopping test: 0 r.r <= rtol2 b.b, 1 r.z <= rtol2 r0.z0
+    int conv;   // the stopping test held
 };
 
 }  // namespace gipc
@@ -387,8 +389,11 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s)
 // streaming read of bytes / 16 aligned 16-byte words (sink: device uint32, written only by chance)
 hipError_t launch_read(const void* src, int64_t bytes, uint32_t* sink, hipStream_t s);
 // with mf set, the operator is matrix-free (A is not read)
+// delta = 1: stop when r.z <= rtol r0.z0 instead of ||r|| <= rtol ||b||;
+// *conv (nullable) receives whether the stopping test held
 hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x, double rtol, int32_t maxit,
-                   int32_t* iters, double* relres, int* breakdown, hipStream_t s, const MfView* mf = nullptr);
+                   int32_t* iters, double* relres, int* breakdown, hipStream_t s, const MfView* mf = nullptr,
+                   int delta = 0, int* conv = nullptr);
 // the same on buffers carved from one device range ws of at least
 // pcg_workspace_bytes(A, mf) bytes (no allocation)
 size_t pcg_workspace_bytes(const gipc_bsr& A, const MfView* mf);

@@ -416,24 +416,28 @@ __global__ void k_pcg_reset(PcgScalars* sc) {
 }
 
 // first: initial scalars; otherwise beta, the new r.z and the stopping test
+// (delta = 0: r.r <= rtol2 b.b; delta = 1: r.z <= rtol2 r0.z0, the paper's
+// termination, rtol2 then holding its tolerance unsquared)
 __global__ void __launch_bounds__(kRed) k_pcg_beta(int first, const double* __restrict__ part, int64_t nb,
-                                                     PcgScalars* sc, double rtol2, int maxit) {
+                                                     PcgScalars* sc, double rtol2, int maxit, int delta) {
     if (!first && sc->done) return;
     __shared__ double lds[kRed / 64];
     const double RZ = sum_parts(part, nb, lds), RR = sum_parts(part + nb, nb, lds);
     const double BB = first ? sum_parts(part + 2 * nb, nb, lds) : 0.0;
     if (threadIdx.x != 0) return;
     if (first) {
-        sc->rz = RZ; sc->rr = RR; sc->bb = BB; sc->rtol2 = rtol2;
+        sc->rz = RZ; sc->rr = RR; sc->bb = BB; sc->rtol2 = rtol2; sc->rz0 = RZ;
         sc->pq = 0; sc->alpha = 0; sc->beta = 0;
-        sc->iters = 0; sc->breakdown = 0; sc->maxit = maxit;
-        sc->done = (RR <= rtol2 * BB) || maxit <= 0;
+        sc->iters = 0; sc->breakdown = 0; sc->maxit = maxit; sc->delta = delta;
+        sc->conv = delta ? (RZ <= rtol2 * RZ) : (RR <= rtol2 * BB);
+        sc->done = sc->conv || maxit <= 0;
     } else {
         sc->beta = RZ / sc->rz;
         sc->rz = RZ;
         sc->rr = RR;
         sc->iters += 1;
-        sc->done = (RR <= sc->rtol2 * sc->bb) || sc->iters >= sc->maxit;
+        sc->conv = sc->delta ? (RZ <= sc->rtol2 * sc->rz0) : (RR <= sc->rtol2 * sc->bb);
+        sc->done = sc->conv || sc->iters >= sc->maxit;
     }
 }
 
@@ -539,7 +543,7 @@ size_t pcg_workspace_bytes(const gipc_bsr& A, const MfView* mf) {
 
 static hipError_t pcg_exec(const gipc_bsr& A, const double* b, double* x, double rtol, int32_t maxit,
                            int32_t* iters, double* relres, int* breakdown, hipStream_t s, const MfView* mf,
-                           const PcgWork& w);
+                           const PcgWork& w, int delta, int* conv);
 
 // the buffers carved out of one device range of pcg_workspace_bytes bytes
 hipError_t pcg_run_in(void* ws, const gipc_bsr& A, const double* b, double* x, double rtol, int32_t maxit,
@@ -562,11 +566,12 @@ hipError_t pcg_run_in(void* ws, const gipc_bsr& A, const double* b, double* x, d
     w.part = reinterpret_cast<double*>(take(sizeof(double) * 3 * (size_t)pcg_num_parts(A, mf)));
     w.sc = reinterpret_cast<PcgScalars*>(take(sizeof(PcgScalars)));
     w.p32 = f32 ? reinterpret_cast<float*>(take(sizeof(float) * n3)) : nullptr;
-    return pcg_exec(A, b, x, rtol, maxit, iters, relres, breakdown, s, mf, w);
+    return pcg_exec(A, b, x, rtol, maxit, iters, relres, breakdown, s, mf, w, 0, nullptr);
 }
 
 hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x, double rtol, int32_t maxit,
-                   int32_t* iters, double* relres, int* breakdown, hipStream_t s, const MfView* mf) {
+                   int32_t* iters, double* relres, int* breakdown, hipStream_t s, const MfView* mf, int delta,
+                   int* conv) {
     const int32_t V = mf ? mf->V : A.nbrows;
     const size_t n3 = 3 * (size_t)V;
     hipError_t e;
@@ -587,12 +592,12 @@ hipError_t pcg_run(gipc_ctx* ctx, const gipc_bsr& A, const double* b, double* x,
     PcgWork w{as<double>(ctx->r), as<double>(ctx->z), as<double>(ctx->p), as<double>(ctx->q),
               as<double>(ctx->minv), as<double>(ctx->part), f32 ? as<float>(ctx->p32) : nullptr,
               as<PcgScalars>(ctx->scal)};
-    return pcg_exec(A, b, x, rtol, maxit, iters, relres, breakdown, s, mf, w);
+    return pcg_exec(A, b, x, rtol, maxit, iters, relres, breakdown, s, mf, w, delta, conv);
 }
 
 static hipError_t pcg_exec(const gipc_bsr& A, const double* b, double* x, double rtol, int32_t maxit,
                            int32_t* iters, double* relres, int* breakdown, hipStream_t s, const MfView* mf,
-                           const PcgWork& w) {
+                           const PcgWork& w, int delta, int* conv) {
     const int32_t V = mf ? mf->V : A.nbrows;
     const int64_t n3 = 3 * (int64_t)V;
     const int64_t nbv = (V + kBlock - 1) / kBlock;  // row-parallel kernels
@@ -628,7 +633,7 @@ static hipError_t pcg_exec(const gipc_bsr& A, const double* b, double* x, double
         GIPC_TRY(launch_spmv(A, x, q, s));
     }
     k_pcg_update<<<(unsigned)nbv, kBlock, 0, s>>>(1, V, b, x, r, z, p, q, minv, part, sc);
-    k_pcg_beta<<<1, kRed, 0, s>>>(1, part, nbv, sc, rtol * rtol, maxit);
+    k_pcg_beta<<<1, kRed, 0, s>>>(1, part, nbv, sc, delta ? rtol : rtol * rtol, maxit, delta);
     if (f32) k_pupdate<<<nbn, kBlock, 0, s>>>(n3, z, p, p32, sc, 1);  // FP32 copy of p0
     GIPC_TRY(hipGetLastError());
 
@@ -659,7 +664,7 @@ static hipError_t pcg_exec(const gipc_bsr& A, const double* b, double* x, double
             }
             k_pcg_alpha<<<1, kRed, 0, s>>>(part, nbs, sc);
             k_pcg_update<<<(unsigned)nbv, kBlock, 0, s>>>(0, V, b, x, r, z, p, q, minv, part, sc);
-            k_pcg_beta<<<1, kRed, 0, s>>>(0, part, nbv, sc, 0.0, 0);
+            k_pcg_beta<<<1, kRed, 0, s>>>(0, part, nbv, sc, 0.0, 0, 0);
             k_pupdate<<<nbn, kBlock, 0, s>>>(n3, z, p, p32, sc, 0);
         }
         GIPC_TRY(hipGetLastError());
@@ -677,6 +682,7 @@ static hipError_t pcg_exec(const gipc_bsr& A, const double* b, double* x, double
     if (iters) *iters = hs.iters;
     if (relres) *relres = hs.bb > 0.0 ? sqrt(hs.rr / hs.bb) : 0.0;
     if (breakdown) *breakdown = hs.breakdown;
+    if (conv) *conv = hs.conv;
     return hipSuccess;
 }
 
